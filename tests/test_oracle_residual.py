@@ -1,0 +1,177 @@
+"""Pins of the oracle's FR residual: freestream preservation, discrete
+conservation, convergence to the analytic -div f of a manufactured smooth
+field (textbook fluxes in primitive variables), and axis-permutation
+symmetry."""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as npleg
+
+from paper_2202_09733_amd import workloads as W
+
+GAM = 1.4
+
+
+def _level(orc, dim, n, p, h=None, Ma=0.3, mu=1e-2, u_dir=(1.0, 0.0, 0.0)):
+    qinf, _ = W.reference_state(dim, Ma, u_dir=u_dir)
+    if h is None:
+        h = [np.full(n[a], 1.0 / n[a]) for a in range(dim)]
+    return orc.Level(dim=dim, n=n, h=h, p=p, gamma=GAM, mu=mu, Pr=0.72, tau=0.1, qinf=qinf)
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, (4, 6), 1), (2, (4, 4), 4), (3, (2, 4, 2), 2), (3, (2, 2, 2), 3)])
+def test_freestream_is_exact_zero(orc, dim, n, p):
+    h = [np.geomspace(0.01, 0.2, n[a]) for a in range(dim)]
+    L = _level(orc, dim, n, p, h=h, Ma=1e-3)
+    r = L.residual(np.zeros(L.shape))
+    assert np.all(r == 0.0)
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, (4, 4), 2), (3, (2, 2, 4), 2)])
+def test_other_uniform_state_is_steady(orc, dim, n, p):
+    L = _level(orc, dim, n, p, Ma=0.2)
+    dq = np.zeros(L.shape)
+    dq[0] = 0.05
+    dq[1] = -0.1
+    dq[dim + 1] = 3.0
+    r = L.residual(dq)
+    assert np.abs(r).max() < 1e-11 * 100.0
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, (6, 4), 2), (2, (4, 4), 4), (3, (2, 4, 2), 3)])
+def test_discrete_conservation(orc, dim, n, p):
+    """sum_e sum_i w_i |J_e| R = 0 per variable on a periodic mesh."""
+    rng = np.random.default_rng(0)
+    h = [rng.uniform(0.05, 0.2, n[a]) for a in range(dim)]
+    L = _level(orc, dim, n, p, h=h, Ma=0.1)
+    dq = W.random_state(L.shape, rng, L.qinf, amp=0.05)
+    r = L.residual(dq)
+    _, w = npleg.leggauss(p + 1)
+    wd = w
+    for _ in range(dim - 1):
+        wd = np.kron(w, wd)
+    jac = np.ones(L.Ne)
+    e = np.arange(L.Ne)
+    ec = [e % n[0], (e // n[0]) % n[1]] + ([e // (n[0] * n[1])] if dim == 3 else [])
+    for a in range(dim):
+        jac = jac * h[a][ec[a]] / 2
+    tot = np.einsum("vik,i,k->v", r, wd, jac)
+    scale = np.abs(r).max() * float(np.sum(jac)) * 4
+    assert np.all(np.abs(tot) < 1e-14 * scale)
+
+
+# ---------------------------------------------------------------------------
+# manufactured solution
+# ---------------------------------------------------------------------------
+
+def _prim(x, y):
+    """Smooth periodic primitive field on the unit square and its gradient."""
+    k = 2 * math.pi
+    rho = 1 + 0.1 * np.sin(k * x) * np.cos(k * y)
+    u = 1 + 0.1 * np.cos(k * x) * np.sin(k * y)
+    v = 0.05 * np.sin(k * (x + y))
+    pinf = 1.0 / (GAM * 0.3 ** 2)
+    p = pinf * (1 + 0.05 * np.cos(k * (x - y)))
+    g = {
+        "rho": (0.1 * k * np.cos(k * x) * np.cos(k * y), -0.1 * k * np.sin(k * x) * np.sin(k * y)),
+        "u": (-0.1 * k * np.sin(k * x) * np.sin(k * y), 0.1 * k * np.cos(k * x) * np.cos(k * y)),
+        "v": (0.05 * k * np.cos(k * (x + y)), 0.05 * k * np.cos(k * (x + y))),
+        "p": (-pinf * 0.05 * k * np.sin(k * (x - y)), pinf * 0.05 * k * np.sin(k * (x - y))),
+    }
+    return rho, u, v, p, g
+
+
+def _textbook_total_flux(x, y, a, mu, Pr):
+    rho, u, v, p, g = _prim(x, y)
+    E = p / (GAM - 1) + 0.5 * rho * (u * u + v * v)
+    vel = [u, v]
+    fI = [rho * vel[a], rho * vel[a] * u + (p if a == 0 else 0), rho * vel[a] * v + (p if a == 1 else 0),
+          vel[a] * (E + p)]
+    gu = [[g["u"][0], g["u"][1]], [g["v"][0], g["v"][1]]]    # gu[b][c]
+    div = gu[0][0] + gu[1][1]
+    tau = [mu * (gu[a][b] + gu[b][a]) - (2 / 3 * mu * div if a == b else 0) for b in range(2)]
+    T = p / rho
+    gT = (g["p"][a] - T * g["rho"][a]) / rho
+    cp = GAM / (GAM - 1)
+    fV = [0 * x, tau[0], tau[1], u * tau[0] + v * tau[1] + mu * cp / Pr * gT]
+    return [fI[i] - fV[i] for i in range(4)]
+
+
+def _exact_rhs(x, y, mu, Pr, d=1e-3):
+    """-div f by 4th-order central differences of the analytic flux."""
+    out = np.zeros((4,) + x.shape)
+    for a in range(2):
+        ex = (d, 0) if a == 0 else (0, d)
+        fp1 = _textbook_total_flux(x + ex[0], y + ex[1], a, mu, Pr)
+        fm1 = _textbook_total_flux(x - ex[0], y - ex[1], a, mu, Pr)
+        fp2 = _textbook_total_flux(x + 2 * ex[0], y + 2 * ex[1], a, mu, Pr)
+        fm2 = _textbook_total_flux(x - 2 * ex[0], y - 2 * ex[1], a, mu, Pr)
+        for i in range(4):
+            out[i] -= (-fp2[i] + 8 * fp1[i] - 8 * fm1[i] + fm2[i]) / (12 * d)
+    return out
+
+
+@pytest.mark.parametrize("p,mu,order", [(2, 0.0, 2), (3, 0.0, 3), (4, 0.0, 4), (2, 1.0, 1), (3, 1.0, 2)])
+def test_manufactured_solution_convergence(orc, p, mu, order):
+    """Pointwise error of R against the analytic -div f.  Inviscid terms
+    converge at O(h^p); the LDG second-derivative terms at O(h^(p-1)), the
+    pointwise truncation order of the viscous discretisation."""
+    Pr = 0.72
+    errs = []
+    ns = [4, 8, 16]
+    for nn in ns:
+        L = _level(orc, 2, (nn, nn), p, Ma=0.3, mu=mu)
+        h = [np.full(nn, 1.0 / nn)] * 2
+        X, Y = W.point_coords((nn, nn), h, p, 2)
+        rho, u, v, pr, _ = _prim(X, Y)
+        pinf = 1.0 / (GAM * 0.3 ** 2)
+        dq = W.deviation_from_primitives(L.qinf, pinf, rho, [u, v], pr)
+        r = L.residual(dq)
+        ex = _exact_rhs(X, Y, mu, Pr)
+        errs.append(np.linalg.norm(r - ex) / np.linalg.norm(ex))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(orders) > order - 0.25, (errs, orders)
+
+
+def _swap_xy(dq, P, n):
+    """Transpose a 2D state: (x, y) -> (y, x), (rho u, rho v) -> (rho v, rho u)."""
+    nv, Np, Ne = dq.shape
+    a = dq.reshape(nv, P, P, n, n)           # [v][i1][i0][iy][ix]
+    a = a.transpose(0, 2, 1, 4, 3)
+    a = a[[0, 2, 1, 3]]
+    return np.ascontiguousarray(a.reshape(nv, Np, Ne))
+
+
+def test_axis_swap_symmetry(orc):
+    nn, p = 4, 3
+    P = p + 1
+    Lx = _level(orc, 2, (nn, nn), p, Ma=0.2, u_dir=(0.6, 0.8, 0.0))
+    Ly = _level(orc, 2, (nn, nn), p, Ma=0.2, u_dir=(0.8, 0.6, 0.0))
+    rng = np.random.default_rng(9)
+    dq = W.random_state(Lx.shape, rng, Lx.qinf, amp=0.05)
+    r = Lx.residual(dq)
+    r2 = Ly.residual(_swap_xy(dq, P, nn))
+    assert np.allclose(r2, _swap_xy(r, P, nn), rtol=0, atol=1e-12 * np.abs(r).max())
+
+
+def _cycle_xyz(dq, P, n):
+    """(x, y, z) -> (y, z, x) for a 3D state on an n^3 mesh."""
+    nv, Np, Ne = dq.shape
+    a = dq.reshape(nv, P, P, P, n, n, n)     # [v][i2][i1][i0][iz][iy][ix]
+    # new coordinate x' = y, y' = z, z' = x: new array indexed [i2'=i0][i1'=i2][i0'=i1]
+    a = a.transpose(0, 3, 1, 2, 6, 4, 5)
+    a = a[[0, 2, 3, 1, 4]]
+    return np.ascontiguousarray(a.reshape(nv, Np, Ne))
+
+
+def test_axis_cycle_symmetry_3d(orc):
+    nn, p = 2, 2
+    P = p + 1
+    La = _level(orc, 3, (nn, nn, nn), p, Ma=0.2, u_dir=(0.48, 0.6, 0.64))
+    Lb = _level(orc, 3, (nn, nn, nn), p, Ma=0.2, u_dir=(0.6, 0.64, 0.48))
+    rng = np.random.default_rng(10)
+    dq = W.random_state(La.shape, rng, La.qinf, amp=0.05)
+    r = La.residual(dq)
+    r2 = Lb.residual(_cycle_xyz(dq, P, nn))
+    assert np.allclose(r2, _cycle_xyz(r, P, nn), rtol=0, atol=1e-12 * np.abs(r).max())
