@@ -1,0 +1,227 @@
+"""Benchmark: DOF/s of one implicit stage solve to 1e-8 relative nonlinear
+residual on one MI355X, plus the residual/JVP/EJ kernel rates.
+
+Workload (default): 2D Navier-Stokes FR on the 64x64 y-stretched periodic
+mesh (aspect ratio 1-100), p = 4 (409,600 DOF), Ma 1e-3, one ESDIRK3 stage at
+dt = 1000 dt_exp solved by PTC + JFNK + FGMRES(30) with the nonlinear pMG
+p{4-2} preconditioner (n{2-2}, EJ smoothing on both levels), FP64.
+One step = one full stage solve, including the per-time-step preconditioner
+set-up (EJ formation and inversion on both levels) at the start.
+
+Prints ONE JSON line (see the fields in main()).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _events_time(fn, reps):
+    """Average duration (s) of fn() over reps calls, HIP events on the current stream."""
+    import torch
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def kernel_rates(fr, wl, dq_dev, reps=50):
+    """Live per-launch durations of the hot kernels at the workload's size."""
+    import torch
+    from paper_2202_09733_amd import capi
+    N = wl.dof()
+    nb = wl.nv * (wl.p0 + 1) ** wl.dim
+    out = {}
+    rq = fr.residual(0, dq_dev)
+    r_out = fr.empty(0)
+    t_r = _events_time(lambda: fr.residual(0, dq_dev, out=r_out), reps)
+    out["residual"] = dict(s_per_call=t_r, alg_bytes=16.0 * N, launches=3)
+    v = torch.randn_like(dq_dev)
+    v /= torch.linalg.norm(v)
+    w = fr.empty(0)
+    sig = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
+    t_j = _events_time(lambda: fr.jvp(0, dq_dev, rq, v, sig, out=w), reps)
+    out["jvp"] = dict(s_per_call=t_j, alg_bytes=32.0 * N, launches=6)
+    # EJ apply on the fine level (factors of the last stage solve)
+    y = fr.empty(0)
+    t_e = _events_time(lambda: fr.ej_solve(0, v, out=y), reps)
+    fac_bytes = wl.Ne * nb * nb * (8 if fr_prec(fr) == capi.PREC_FP64 else 4)
+    out["ej_apply_fine"] = dict(s_per_call=t_e, alg_bytes=float(fac_bytes + 16 * N), launches=1,
+                                kernel="k_ej_apply")
+    for k, d in out.items():
+        d["GBps"] = d["alg_bytes"] / d["s_per_call"] / 1e9
+    return out
+
+
+def fr_prec(fr):
+    return getattr(fr, "_last_prec", 0)
+
+
+def cpu_baseline(wl, st, max_seconds=25.0):
+    """Oracle (plain FP64 C + numpy, one thread) cost of the same stage:
+    unit costs measured on the workload's own state -- fine and coarse
+    residual, block LU factor and solve, a JVP -- multiplied by the GPU
+    stage's operation counts (R evaluations per level, EJ solves per level,
+    one factorisation per block, Krylov vectors).  Extrapolated, not a full
+    oracle stage solve."""
+    import oracle
+    t_begin = time.perf_counter()
+    L0 = oracle.Level(**wl.level_kwargs(wl.p0))
+    L1 = oracle.Level(**wl.level_kwargs(wl.p1))
+    q1 = oracle.restrict(wl.dq, wl.dim, wl.p0 + 1, wl.p1 + 1)
+
+    def timeit(f, n):
+        t = time.perf_counter()
+        for _ in range(n):
+            f()
+        return (time.perf_counter() - t) / n
+    tR0 = timeit(lambda: L0.residual(wl.dq), 3)
+    tR1 = timeit(lambda: L1.residual(q1), 3)
+    # LU cost depends on sizes only: stand-in well-conditioned blocks
+    rng = np.random.default_rng(0)
+    nsamp = 256
+    Bs0 = np.eye(L0.nb)[None] * 4.0 + 0.01 * rng.standard_normal((nsamp, L0.nb, L0.nb))
+    Bs1 = np.eye(L1.nb)[None] * 4.0 + 0.01 * rng.standard_normal((nsamp, L1.nb, L1.nb))
+    tF0 = timeit(lambda: oracle.lu_factor(Bs0), 1) / nsamp
+    tF1 = timeit(lambda: oracle.lu_factor(Bs1), 1) / nsamp
+    fac0 = oracle.lu_factor(np.tile(Bs0[:1], (L0.Ne, 1, 1)))
+    fac1 = oracle.lu_factor(np.tile(Bs1[:1], (L1.Ne, 1, 1)))
+    x0 = rng.standard_normal(L0.shape)
+    x1 = rng.standard_normal(L1.shape)
+    tS0 = timeit(lambda: oracle.lu_solve(fac0, x0), 3)
+    tS1 = timeit(lambda: oracle.lu_solve(fac1, x1), 3)
+    # Krylov vector work per FGMRES iteration (CGS2 over ~m/2 vectors on average)
+    m = 15
+    V = rng.standard_normal((m, L0.N))
+    wv = rng.standard_normal(L0.N)
+
+    def cgs2():
+        for _ in range(2):
+            h = V @ wv
+            _ = wv - V.T @ h
+    tK = timeit(cgs2, 2)
+    n_factor_blocks0 = L0.Ne
+    n_factor_blocks1 = L1.Ne if st["n_R_coarse"] > 0 else 0
+    total = (st["n_R_fine"] * tR0 + st["n_R_coarse"] * tR1 + st["n_ej_fine"] * tS0 + st["n_ej_coarse"] * tS1
+             + n_factor_blocks0 * tF0 + n_factor_blocks1 * tF1 + st["gmres_iters"] * tK)
+    dof = wl.dof()
+    return dict(value=dof / total, unit="DOF/s", cores=1, kind="oracle",
+                sample=("extrapolated: oracle unit costs on the config-2 state (fine R %.3fs, coarse R %.3fs, "
+                        "fine/coarse block LU solve %.3fs/%.3fs, block factor %.2e/%.2e s per block, CGS2 step "
+                        "%.3fs) x the GPU stage's counts (%d fine R, %d coarse R, %d fine + %d coarse EJ solves, "
+                        "%d FGMRES iterations) = %.1f s of oracle time; measuring took %.1f s")
+                % (tR0, tR1, tS0, tS1, tF0, tF1, tK, st["n_R_fine"], st["n_R_coarse"], st["n_ej_fine"],
+                   st["n_ej_coarse"], st["gmres_iters"], total, time.perf_counter() - t_begin),
+                seconds_extrapolated=total)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the EJ-only comparison and kernel rates")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this path has no multi-GPU mode (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+
+    wl = W.config2()
+    fr = capi.FR.from_workload(wl)
+    prec = capi.PREC_FP64 if args.precision == "fp64" else capi.PREC_FP32
+    fr._last_prec = prec
+    dq = fr.to_dev(wl.dq)
+    cfg = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=prec)
+    out = fr.empty(0)
+    print("[bench] warmup %d stage solve(s)" % args.warmup, file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        _, st = fr.solve_stage(cfg, dq, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        _, st = fr.solve_stage(cfg, dq, out=out)
+        stats.append(st)
+        print("[bench] step %d: %.3f s (setup %.3f s), %d PTC, %d FGMRES, rel. residual %.2e"
+              % (i, st["t_total"], st["t_setup"], st["ptc_iters"], st["gmres_iters"], st["rel_res"]),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dof = wl.dof()
+    elapsed = t1 - t0
+    st = stats[-1]
+    solve_only = float(np.mean([s["t_solve"] for s in stats]))
+    setup = float(np.mean([s["t_setup"] for s in stats]))
+    result = {
+        "metric": "DOF/s per ESDIRK/ROW stage solve to 1e-8 rel residual",
+        "value": dof * args.steps / elapsed,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == capi.PREC_FP64 else "f64 (EJ factors f32)",
+        "data": "synthetic",
+        "config": {
+            "workload": "config2: 2D NS FR 64x64 y-stretched (AR 1-100), p=4 (409,600 DOF), Ma 1e-3, ESDIRK3 "
+                        "stage at dt=1000 dt_exp, PTC+JFNK+FGMRES(30), pMG p{4-2} n{2-2} EJ smoothers",
+            "dof": dof, "setup_included": True,
+        },
+        "stage": {
+            "dof_per_s_without_setup": dof / solve_only, "t_setup_s": setup, "t_solve_s": solve_only,
+            "ptc_iters": st["ptc_iters"], "gmres_iters": st["gmres_iters"],
+            "gmres_per_newton": st["gmres_per_newton"], "rel_res": st["rel_res"],
+            "n_R_fine": st["n_R_fine"], "n_R_coarse": st["n_R_coarse"],
+            "n_ej_fine": st["n_ej_fine"], "n_ej_coarse": st["n_ej_coarse"],
+        },
+    }
+    if not args.no_extras:
+        print("[bench] plain-EJ comparison stage", file=sys.stderr, flush=True)
+        cfg_ej = capi.stage_config_for(wl, precond=capi.PRECOND_EJ, precision=prec)
+        _, st_ej = fr.solve_stage(cfg_ej, dq, out=fr.empty(0), raise_on_noconv=False)
+        result["plain_ej"] = {k: st_ej[k] for k in ("ptc_iters", "gmres_iters", "rel_res", "t_total", "t_setup",
+                                                      "converged")}
+        result["plain_ej"]["dof_per_s"] = dof / st_ej["t_total"]
+        # re-create the pMG factors for the kernel-rate measurements
+        fr.solve_stage(cfg, dq, out=out)
+        print("[bench] kernel rates", file=sys.stderr, flush=True)
+        rates = kernel_rates(fr, wl, dq)
+        result["kernels"] = rates
+        dom = rates["ej_apply_fine"]
+        result["roofline"] = {
+            "kernel": "k_ej_apply (fine level, n_b=100, FP64 inverse blocks)",
+            "bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None,
+        }
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(wl, st)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

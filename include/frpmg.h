@@ -1,0 +1,222 @@
+/*
+ * frpmg.h -- C ABI of the MI355X (gfx950) implementation of the nonlinear
+ * p-multigrid preconditioned Jacobian-free Newton-Krylov stage solve for the
+ * flux-reconstruction (FR) discretisation of the compressible Navier-Stokes
+ * equations.
+ *
+ * Paper: L. Wang, W. Trojak, F. Witherden, A. Jameson, "Nonlinear p-multigrid
+ * preconditioner for implicit time integration of compressible Navier-Stokes
+ * equations", arXiv 2202.09733.  Section numbers below refer to it.
+ *
+ * Conventions (all entry points):
+ *  - Array arguments are DEVICE pointers owned by the caller, contiguous,
+ *    FP64, unless stated otherwise.  The library owns only its internal
+ *    workspaces (EJ factors, Krylov basis, multigrid buffers), allocated at
+ *    fr_create, at the first ej_factor of a level, or at the first
+ *    gmres_solve_stage; no other call allocates.
+ *  - State arrays hold the DEVIATION dq = q - q_inf of the conservative
+ *    variables (rho, rho u, rho v, [rho w], E) from the reference state q_inf
+ *    given at creation, in the layout [nvar][npts][nelem]: element index
+ *    fastest, element e = ix + nx (iy + ny iz), local point
+ *    i = a + P (b + P c) with P = p + 1 Gauss-Legendre points per direction.
+ *    R(0) = 0 exactly.  Carrying the deviation keeps FP64 meaningful at low
+ *    Mach number, where E ~ p_inf/(gamma-1) would otherwise swamp the
+ *    perturbations.
+ *  - An element-Jacobi block of element k uses the local DOF index
+ *    j = v Np + i (Np = P^dim).
+ *  - Calls are asynchronous on the given stream (a hipStream_t, NULL = the
+ *    default stream), except gmres_solve_stage, which synchronises.
+ *  - Every call returns an fr_status; fr_last_error() describes the last
+ *    failure of a context.  A context is used by one host thread at a time.
+ *  - Periodic axis-aligned meshes only; element widths may vary per axis
+ *    index (stretched meshes).
+ */
+#ifndef FRPMG_H
+#define FRPMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int fr_status;
+#define FR_OK 0
+#define FR_EINVAL (-1)      /* invalid argument */
+#define FR_ENOMEM (-2)      /* device allocation failed */
+#define FR_EDEVICE (-3)     /* HIP runtime error */
+#define FR_ESINGULAR (-4)   /* exact zero pivot in an EJ block */
+#define FR_ENOCONV (-5)     /* iteration cap reached before the tolerance */
+#define FR_EBREAKDOWN (-6)  /* Arnoldi breakdown without convergence */
+#define FR_ENONFINITE (-7)  /* NaN or Inf in a norm */
+
+typedef struct frpmg_ctx frpmg_ctx;
+typedef void *fr_stream; /* hipStream_t */
+
+#define FR_MAX_LEVELS 4
+
+/* Mesh, polynomial levels and physics.  h[a] points to n[a] HOST doubles
+ * (element widths along axis a); the library copies them.  p[0] is the
+ * finest degree; levels 1.. are the coarser p-multigrid levels
+ * (Sec. 3.1, hierarchy p{p0-p1}).  Constant viscosity mu, Prandtl number Pr,
+ * LDG penalty tau; qinf = reference conservative state (dim + 2 values). */
+typedef struct {
+    int dim;              /* 2 or 3 */
+    int n[3];             /* elements per axis (n[2] ignored for dim = 2) */
+    const double *h[3];   /* host arrays of element widths */
+    int nlevels;          /* 1 .. FR_MAX_LEVELS */
+    int p[FR_MAX_LEVELS]; /* polynomial degree per level, 1 <= p <= 4, dim 3: p <= 3 */
+    double gamma, mu, Pr, tau;
+    double qinf[5];
+} fr_mesh_desc;
+
+/* Create a context on the current HIP device.  Builds the 1D operators
+ * (Gauss-Legendre points, differentiation, DG-recovering correction
+ * derivatives, L2-projection transfers) and the residual workspaces. */
+fr_status fr_create(const fr_mesh_desc *desc, frpmg_ctx **out);
+void fr_destroy(frpmg_ctx *ctx);
+const char *fr_last_error(const frpmg_ctx *ctx);
+
+/* Number of doubles in a state vector of a level: (dim+2) (p+1)^dim nelem. */
+size_t fr_level_size(const frpmg_ctx *ctx, int level);
+
+/* r = R_level(dq): FR right-hand side of dq/dt = -div f (Sec. 2.1, Eq. (1)):
+ * Gauss-Legendre solution points, Huynh's DG-recovering corrections, flux-
+ * polynomial traces, original Roe flux without entropy fix (Sec. 4.2.1),
+ * LDG viscous flux.  dq and r: fr_level_size(level) doubles, must not alias. */
+fr_status fr_residual(frpmg_ctx *ctx, int level, const double *dq, double *r, fr_stream stream);
+
+#define FR_EPS_ABSOLUTE 0   /* h = eps */
+#define FR_EPS_NORMALIZED 1 /* h = eps / ||v||_2 (unit-norm perturbation) */
+
+/* Finite-difference shifted Jacobian-vector product (Sec. 2.2, the matrix-
+ * free product with fixed eps = 1e-6):
+ *   w = shift v - (R(dq + h v) - rq) / h,
+ * rq = R(dq) supplied by the caller.  All arrays of the level's size; w must
+ * not alias the inputs. */
+fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const double *v,
+                 double shift, double eps, int eps_mode, double *w, fr_stream stream);
+
+#define FR_PREC_FP64 0      /* FP64 factor, FP64 storage */
+#define FR_PREC_FP32 1      /* FP32 elimination from the FP64 block, FP32 storage */
+#define FR_PREC_FP32_BF16 2 /* FP32 storage; trailing updates on BF16-input MFMA, FP32 accumulate */
+
+/* Element-Jacobi setup (Sec. 2.2, element-Jacobi preconditioner; the
+ * preconditioner matrix is evaluated once per physical time step):
+ * forms B_k = sigma I - dR_k/dq_k at dq_lin for every element by one-sided
+ * finite differences per block column (step 1e-7 max(1, |q_j|), taken as
+ * the representable difference), then inverts every block by Gauss-Jordan
+ * elimination with partial pivoting and stores the inverse in the requested
+ * precision.  Needs an even element count per axis (parity colouring).
+ * Returns FR_ESINGULAR if a block has an exact zero pivot.  Synchronises the
+ * stream at the end (to report the pivot status). */
+fr_status ej_factor(frpmg_ctx *ctx, int level, const double *dq_lin, double sigma, int precision,
+                    fr_stream stream);
+
+/* y = blockdiag(B)^{-1} r with the factors of the last ej_factor of the
+ * level (FP64 in and out; internal casting per the factor precision). */
+fr_status ej_solve(frpmg_ctx *ctx, int level, const double *r, double *y, fr_stream stream);
+
+/* Copy the stored inverse blocks of a level to a host buffer of
+ * nelem nb nb doubles, block k column-major (entry (row, col) at
+ * k nb nb + col nb + row), converted to FP64.  Synchronous. */
+fr_status ej_get_inverse(frpmg_ctx *ctx, int level, double *host_out);
+
+/* Restriction Gamma (L2 projection, Sec. 3.1 Eq. (projection)) from level
+ * `from` to the coarser level `to` = from + 1, and prolongation Pi
+ * (Eq. (prolongation)) from level `from` to the finer level `to` = from - 1,
+ * per element and variable as tensor products of the 1D operators. */
+fr_status pmg_restrict(frpmg_ctx *ctx, int from, int to, const double *x, double *y, fr_stream stream);
+fr_status pmg_prolong(frpmg_ctx *ctx, int from, int to, const double *x, double *y, fr_stream stream);
+
+#define FR_COARSE_NONE 0    /* fine-level smoothing only (n0 pre-sweeps) */
+#define FR_COARSE_EJ 1      /* two-level V-cycle with EJ smoothing on level 1 */
+#define FR_COARSE_LEARNED 2 /* coarse sweeps replaced by the learned correction */
+
+#define FR_SCALE_LITERAL 0    /* s = 1 */
+#define FR_SCALE_NORMALIZED 1 /* s = eps_p sigma_D / ||X||_2 */
+
+/* Nonlinear pMG preconditioner parameters (Sec. 3.2). */
+typedef struct {
+    double sigma_D;   /* 1/dtau + 1/(a_ii dt) (ESDIRK) or 1/(a_ii dt) (ROW) */
+    int n0, n1;       /* smoothing n{n0-n1} (Sec. 3.1) */
+    int coarse_mode;  /* FR_COARSE_* */
+    int scale_mode;   /* FR_SCALE_* */
+    double eps_p;     /* scale for FR_SCALE_NORMALIZED */
+} pmg_params;
+
+/* Set the linearisation point of the preconditioner: dq (level 0 state) and
+ * rq = R_0(dq).  Restricts dq to level 1 and evaluates R_1 there.  The
+ * pointers must stay valid until the next pmg_set_point. */
+fr_status pmg_set_point(frpmg_ctx *ctx, const double *dq, const double *rq, fr_stream stream);
+
+/* y ~ A^{-1} x by one two-level FAS V-cycle on
+ *   0 = X + R(q + Y) - R(q) - sigma_D Y       (Sec. 3.2, with q_hat = q + Y)
+ * smoothed by the element-Jacobi linearised pseudo-time step
+ * Y <- Y - B^{-1} G(Y), G(Y) = sigma_D Y - [R(q+Y) - R(q)] - X, with the
+ * factors of ej_factor on each level (their sigma is sigma_S = 1/dtau* +
+ * sigma_D).  x and y are level-0 vectors and must not alias. */
+fr_status pmg_precond_apply(frpmg_ctx *ctx, const pmg_params *prm, const double *x, double *y,
+                            fr_stream stream);
+
+#define FR_SCHEME_ESDIRK 0
+#define FR_SCHEME_ROW 1
+#define FR_PRECOND_EJ 0
+#define FR_PRECOND_PMG 1
+#define FR_PRECOND_PMG_LEARNED 2
+
+typedef struct {
+    int scheme;        /* FR_SCHEME_* */
+    double a_ii;       /* diagonal coefficient of the stage */
+    double a_i1;       /* ESDIRK: coefficient of R(q^n) in the stage (explicit first stage) */
+    double dt;         /* physical time step */
+    double dtau;       /* pseudo-time step of the outer PTC (ESDIRK); also dtau* of the smoother */
+    int m;             /* Krylov dimension K_dim */
+    int max_restarts;  /* FGMRES restarts per linear solve */
+    double eta;        /* ESDIRK: relative tolerance of each inexact Newton solve */
+    double tol;        /* stage tolerance: ||F|| <= tol ||F(q^n)|| (ESDIRK), Krylov tol (ROW) */
+    int max_ptc;       /* cap on pseudo-time iterations (ESDIRK) */
+    int precond;       /* FR_PRECOND_* */
+    int precision;     /* FR_PREC_* of the EJ factors */
+    int n0, n1;        /* pMG smoothing */
+    double eps;        /* FD step of the JVP */
+    int eps_mode;      /* FR_EPS_* */
+    int scale_mode;    /* FR_SCALE_* of the preconditioner */
+    double eps_p;      /* preconditioner scale */
+    int skip_setup;    /* 1: reuse the EJ factors already in the context */
+} stage_params;
+
+#define FR_MAX_NEWTON_LOG 128
+typedef struct {
+    int ptc_iters;
+    int gmres_iters;
+    int restarts;
+    int converged;
+    int status;
+    double res0, res, rel_res;       /* ||F(q^n)||, final ||F||, ratio (ESDIRK); ROW: Krylov estimate */
+    double true_rel_res;             /* ROW: ||R - A_h Y|| / ||R|| recomputed at the end */
+    double t_total, t_setup, t_solve; /* seconds, host wall clock around synchronised phases */
+    long n_R_fine, n_R_coarse, n_ej_fine, n_ej_coarse;
+    int fallbacks;
+    int gmres_per_newton[FR_MAX_NEWTON_LOG];
+} stage_stats;
+
+/* One implicit stage (synchronous).
+ * ESDIRK (Sec. 2.1 Eq. (ESDIRK2), second stage, explicit first stage):
+ *   q_i = q^n + dt (a_i1 R(q^n) + a_ii R(q_i)), solved by pseudo-transient
+ *   continuation with inexact Newton (Sec. 2.2): each step solves
+ *   (I/dtau + I/(a_ii dt) - dR/dq) dq = -F by FGMRES(m) to relative
+ *   tolerance eta, until ||F|| <= tol ||F(q^n)||.  out = q_i (deviation).
+ * ROW (Sec. 2.1 Eq. (Rosenbrock_General), first stage):
+ *   (I/(a_ii dt) - dR/dq(q^n)) Y = R(q^n) by FGMRES(m) to tol.  out = Y.
+ * The EJ factors are formed at q^n (skip_setup = 0).  Returns FR_ENOCONV
+ * when the caps are reached, FR_ENONFINITE on a NaN/Inf norm. */
+fr_status gmres_solve_stage(frpmg_ctx *ctx, const stage_params *prm, const double *dq_n, double *out,
+                            stage_stats *stats, fr_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRPMG_H */

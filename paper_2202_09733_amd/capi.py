@@ -1,0 +1,295 @@
+"""ctypes binding of libfrpmg.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts torch
+tensors to device pointers, Python parameters to the C structs declared in
+``include/frpmg.h`` and status codes to exceptions.  There is no fallback:
+if the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfrpmg.so")
+
+FR_OK, FR_EINVAL, FR_ENOMEM, FR_EDEVICE = 0, -1, -2, -3
+FR_ESINGULAR, FR_ENOCONV, FR_EBREAKDOWN, FR_ENONFINITE = -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGULAR", -5: "ENOCONV",
+                -6: "EBREAKDOWN", -7: "ENONFINITE"}
+EPS_ABSOLUTE, EPS_NORMALIZED = 0, 1
+PREC_FP64, PREC_FP32, PREC_FP32_BF16 = 0, 1, 2
+COARSE_NONE, COARSE_EJ, COARSE_LEARNED = 0, 1, 2
+SCALE_LITERAL, SCALE_NORMALIZED = 0, 1
+SCHEME_ESDIRK, SCHEME_ROW = 0, 1
+PRECOND_EJ, PRECOND_PMG, PRECOND_PMG_LEARNED = 0, 1, 2
+MAX_LEVELS = 4
+MAX_NEWTON_LOG = 128
+
+EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_residual", "fr_jvp", "ej_factor",
+           "ej_solve", "ej_get_inverse", "pmg_restrict", "pmg_prolong", "pmg_set_point", "pmg_precond_apply",
+           "gmres_solve_stage"]
+
+
+class FRError(RuntimeError):
+    def __init__(self, func, code, msg):
+        super().__init__("%s failed: %s (%d): %s" % (func, STATUS_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.POINTER(ctypes.c_double) * 3),
+                ("nlevels", ctypes.c_int), ("p", ctypes.c_int * MAX_LEVELS),
+                ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("Pr", ctypes.c_double),
+                ("tau", ctypes.c_double), ("qinf", ctypes.c_double * 5)]
+
+
+class PmgParams(ctypes.Structure):
+    _fields_ = [("sigma_D", ctypes.c_double), ("n0", ctypes.c_int), ("n1", ctypes.c_int),
+                ("coarse_mode", ctypes.c_int), ("scale_mode", ctypes.c_int), ("eps_p", ctypes.c_double)]
+
+
+class StageParams(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("a_ii", ctypes.c_double), ("a_i1", ctypes.c_double),
+                ("dt", ctypes.c_double), ("dtau", ctypes.c_double), ("m", ctypes.c_int),
+                ("max_restarts", ctypes.c_int), ("eta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_ptc", ctypes.c_int), ("precond", ctypes.c_int), ("precision", ctypes.c_int),
+                ("n0", ctypes.c_int), ("n1", ctypes.c_int), ("eps", ctypes.c_double),
+                ("eps_mode", ctypes.c_int), ("scale_mode", ctypes.c_int), ("eps_p", ctypes.c_double),
+                ("skip_setup", ctypes.c_int)]
+
+
+class StageStats(ctypes.Structure):
+    _fields_ = [("ptc_iters", ctypes.c_int), ("gmres_iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("converged", ctypes.c_int), ("status", ctypes.c_int),
+                ("res0", ctypes.c_double), ("res", ctypes.c_double), ("rel_res", ctypes.c_double),
+                ("true_rel_res", ctypes.c_double),
+                ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double),
+                ("n_R_fine", ctypes.c_long), ("n_R_coarse", ctypes.c_long),
+                ("n_ej_fine", ctypes.c_long), ("n_ej_coarse", ctypes.c_long),
+                ("fallbacks", ctypes.c_int), ("gmres_per_newton", ctypes.c_int * MAX_NEWTON_LOG)]
+
+    def as_dict(self):
+        d = {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "gmres_per_newton"}
+        n = self.ptc_iters if self.ptc_iters > 0 else 1
+        d["gmres_per_newton"] = list(self.gmres_per_newton)[:min(n, MAX_NEWTON_LOG)]
+        return d
+
+
+_lib = None
+
+
+def load():
+    """Load libfrpmg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfrpmg.so is not built (run __graft_entry__.build() or "
+                           "python -m paper_2202_09733_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp = ctypes.c_void_p, ctypes.c_double
+    L.fr_create.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_void_p)]
+    L.fr_destroy.argtypes = [vp]
+    L.fr_destroy.restype = None
+    L.fr_last_error.argtypes = [vp]
+    L.fr_last_error.restype = ctypes.c_char_p
+    L.fr_level_size.argtypes = [vp, ctypes.c_int]
+    L.fr_level_size.restype = ctypes.c_size_t
+    L.fr_residual.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.fr_jvp.argtypes = [vp, ctypes.c_int, vp, vp, vp, dp, dp, ctypes.c_int, vp, vp]
+    L.ej_factor.argtypes = [vp, ctypes.c_int, vp, dp, ctypes.c_int, vp]
+    L.ej_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.ej_get_inverse.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    L.pmg_restrict.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    L.pmg_prolong.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    L.pmg_set_point.argtypes = [vp, vp, vp, vp]
+    L.pmg_precond_apply.argtypes = [vp, ctypes.POINTER(PmgParams), vp, vp, vp]
+    L.gmres_solve_stage.argtypes = [vp, ctypes.POINTER(StageParams), vp, vp, ctypes.POINTER(StageStats), vp]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("fr_destroy", "fr_last_error", "fr_level_size"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), \
+        "expected a contiguous float64 CUDA tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class StageConfig:
+    scheme: int = SCHEME_ESDIRK
+    a_ii: float = 0.43586652150845899942
+    a_i1: float = 0.43586652150845899942
+    dt: float = 1e-3
+    dtau: float = 0.0
+    m: int = 30
+    max_restarts: int = 20
+    eta: float = 0.1
+    tol: float = 1e-8
+    max_ptc: int = 100
+    precond: int = PRECOND_PMG
+    precision: int = PREC_FP64
+    n0: int = 2
+    n1: int = 2
+    eps: float = 1e-6
+    eps_mode: int = EPS_NORMALIZED
+    scale_mode: int = SCALE_NORMALIZED
+    eps_p: float = 1e-6
+    skip_setup: int = 0
+
+    def to_c(self):
+        return StageParams(**{f[0]: getattr(self, f[0]) for f in StageParams._fields_})
+
+
+class FR:
+    """One library context: a periodic mesh with a hierarchy of degrees."""
+
+    def __init__(self, dim, n, h, levels, gamma, mu, Pr, tau, qinf, device="cuda:0"):
+        import torch
+        self.lib = load()
+        self.device = torch.device(device)
+        self.dim = int(dim)
+        self.n = tuple(int(x) for x in n)
+        self.levels = [int(p) for p in levels]
+        self.nv = self.dim + 2
+        self.Ne = int(np.prod(self.n))
+        d = MeshDesc()
+        d.dim = self.dim
+        self._h = [np.ascontiguousarray(np.asarray(h[a], dtype=np.float64)) for a in range(self.dim)]
+        for a in range(3):
+            d.n[a] = self.n[a] if a < self.dim else 1
+        for a in range(self.dim):
+            d.h[a] = self._h[a].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.nlevels = len(self.levels)
+        for i, p in enumerate(self.levels):
+            d.p[i] = p
+        d.gamma, d.mu, d.Pr, d.tau = gamma, mu, Pr, tau
+        for v in range(self.nv):
+            d.qinf[v] = float(qinf[v])
+        h_ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.fr_create(ctypes.byref(d), ctypes.byref(h_ctx))
+        if rc != FR_OK:
+            raise FRError("fr_create", rc, "see stderr")
+        self.ctx = h_ctx
+
+    @classmethod
+    def from_workload(cls, wl, levels=None, device="cuda:0"):
+        levels = [wl.p0, wl.p1] if levels is None else levels
+        return cls(wl.dim, wl.n, wl.h, levels, wl.gamma, wl.mu, wl.Pr, wl.tau, wl.qinf, device=device)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.lib.fr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------
+    def _check(self, name, rc):
+        if rc != FR_OK:
+            raise FRError(name, rc, self.lib.fr_last_error(self.ctx).decode())
+
+    def shape(self, level=0):
+        P = self.levels[level] + 1
+        return (self.nv, P ** self.dim, self.Ne)
+
+    def empty(self, level=0):
+        import torch
+        return torch.empty(self.shape(level), dtype=torch.float64, device=self.device)
+
+    def to_dev(self, a):
+        import torch
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=self.device).contiguous()
+
+    # -- ABI calls ------------------------------------------------------------
+    def residual(self, level, dq, out=None):
+        out = self.empty(level) if out is None else out
+        self._check("fr_residual", self.lib.fr_residual(self.ctx, level, _ptr(dq), _ptr(out), _stream()))
+        return out
+
+    def jvp(self, level, dq, rq, v, shift, eps=1e-6, eps_mode=EPS_NORMALIZED, out=None):
+        out = self.empty(level) if out is None else out
+        self._check("fr_jvp", self.lib.fr_jvp(self.ctx, level, _ptr(dq), _ptr(rq), _ptr(v), float(shift),
+                                              float(eps), int(eps_mode), _ptr(out), _stream()))
+        return out
+
+    def ej_factor(self, level, dq_lin, sigma, precision=PREC_FP64):
+        self._check("ej_factor", self.lib.ej_factor(self.ctx, level, _ptr(dq_lin), float(sigma),
+                                                    int(precision), _stream()))
+
+    def ej_solve(self, level, r, out=None):
+        out = self.empty(level) if out is None else out
+        self._check("ej_solve", self.lib.ej_solve(self.ctx, level, _ptr(r), _ptr(out), _stream()))
+        return out
+
+    def ej_inverse(self, level):
+        """Stored inverse blocks as [Ne][nb][nb] row-major numpy (FP64)."""
+        nb = self.nv * (self.levels[level] + 1) ** self.dim
+        buf = np.empty(self.Ne * nb * nb)
+        self._check("ej_get_inverse", self.lib.ej_get_inverse(
+            self.ctx, level, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return buf.reshape(self.Ne, nb, nb).transpose(0, 2, 1).copy()
+
+    def restrict(self, frm, x, out=None):
+        out = self.empty(frm + 1) if out is None else out
+        self._check("pmg_restrict", self.lib.pmg_restrict(self.ctx, frm, frm + 1, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def prolong(self, frm, x, out=None):
+        out = self.empty(frm - 1) if out is None else out
+        self._check("pmg_prolong", self.lib.pmg_prolong(self.ctx, frm, frm - 1, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def pmg_set_point(self, dq, rq):
+        self._keep_point = (dq, rq)
+        self._check("pmg_set_point", self.lib.pmg_set_point(self.ctx, _ptr(dq), _ptr(rq), _stream()))
+
+    def pmg_apply(self, x, sigma_D, n0=2, n1=2, coarse_mode=COARSE_EJ, scale_mode=SCALE_NORMALIZED, eps_p=1e-6,
+                  out=None):
+        out = self.empty(0) if out is None else out
+        prm = PmgParams(float(sigma_D), int(n0), int(n1), int(coarse_mode), int(scale_mode), float(eps_p))
+        self._check("pmg_precond_apply", self.lib.pmg_precond_apply(self.ctx, ctypes.byref(prm), _ptr(x),
+                                                                    _ptr(out), _stream()))
+        return out
+
+    def solve_stage(self, cfg: StageConfig, dq_n, out=None, raise_on_noconv=True):
+        out = self.empty(0) if out is None else out
+        st = StageStats()
+        prm = cfg.to_c()
+        rc = self.lib.gmres_solve_stage(self.ctx, ctypes.byref(prm), _ptr(dq_n), _ptr(out), ctypes.byref(st),
+                                        _stream())
+        if rc != FR_OK and (raise_on_noconv or rc != FR_ENOCONV):
+            self._check("gmres_solve_stage", rc)
+        d = st.as_dict()
+        d["rc"] = rc
+        return out, d
+
+
+def stage_config_for(wl, precond=PRECOND_PMG, precision=PREC_FP64, **kw):
+    """Stage parameters of a workload (ESDIRK: second stage, a_21 = a_22)."""
+    scheme = SCHEME_ESDIRK if wl.scheme == "esdirk" else SCHEME_ROW
+    eta = 0.1 if precond != PRECOND_EJ else 0.01
+    cfg = StageConfig(scheme=scheme, a_ii=wl.a_ii, a_i1=wl.a_ii, dt=wl.dt, dtau=wl.dt, precond=precond,
+                      precision=precision, eta=eta)
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    return cfg

@@ -1,0 +1,758 @@
+// Host orchestration of the frpmg library: context set-up, the C ABI entry
+// points, the nonlinear p-multigrid V-cycle (Sec. 3.1 applied as the
+// preconditioner of Sec. 3.2), flexible GMRES with classical Gram-Schmidt
+// and one re-orthogonalisation, and the ESDIRK / ROW stage drivers
+// (Sec. 2.1, 2.2).  All vector work runs in the HIP kernels of residual.hip,
+// vec.hip and ej.hip; the host only sequences launches and runs the small
+// Hessenberg least-squares problem.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+using namespace frpmg;
+
+namespace {
+
+struct Fail {
+    fr_status code;
+};
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                     \
+            throw Fail{e_ == hipErrorOutOfMemory ? FR_ENOMEM : FR_EDEVICE};                   \
+        }                                                                                     \
+    } while (0)
+
+#define REQUIRE(cond, msg)              \
+    do {                                \
+        if (!(cond)) {                  \
+            ctx->err = (msg);           \
+            throw Fail{FR_EINVAL};      \
+        }                               \
+    } while (0)
+
+template <typename F>
+fr_status guarded(frpmg_ctx *ctx, F &&f) {
+    if (!ctx) return FR_EINVAL;
+    try {
+        f();
+        return FR_OK;
+    } catch (const Fail &x) {
+        return x.code;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return FR_ENOMEM;
+    }
+}
+
+double *dalloc(frpmg_ctx *ctx, size_t n) {
+    void *p = nullptr;
+    HIPCHK(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(double)));
+    return (double *)p;
+}
+
+void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+hipStream_t S(fr_stream s) { return (hipStream_t)s; }
+
+int ipow(int b, int e) {
+    int r = 1;
+    while (e--) r *= b;
+    return r;
+}
+
+// ---- device scalars (slots of ctx->scal) ----
+enum { SC_JVP_H = 0, SC_JVP_N2 = 1, SC_PMG_S = 2, SC_PMG_INV = 3, SC_PMG_N2 = 4, SC_ONE = 5 };
+// ---- reduction outputs (slots of ctx->red_out) ----
+constexpr int RO_H1 = 0, RO_H2 = 64, RO_Y = 128, RO_N2 = 192, RO_SIZE = 256;
+
+double host_norm(frpmg_ctx *ctx, size_t n, const double *x, hipStream_t s) {
+    HIPCHK(vec_dot(ctx, n, x, x, ctx->red_out + RO_N2, s));
+    HIPCHK(hipMemcpyAsync(ctx->host_pinned, ctx->red_out + RO_N2, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return std::sqrt(ctx->host_pinned[0]);
+}
+
+void residual(frpmg_ctx *ctx, int level, const double *dq, double *r, hipStream_t s) {
+    ResidualArgs a;
+    a.src = SRC_PLAIN;
+    a.dq = dq;
+    a.out = OUT_R;
+    a.r = r;
+    HIPCHK(launch_residual(ctx, level, a, s));
+}
+
+// out = sigma v - (R(dq + alpha v) - r0) / alpha - x   (x optional)
+void residual_lin(frpmg_ctx *ctx, int level, const double *dq, const double *v, Scal alpha, const double *r0,
+                  double sigma, const double *x, double *out, hipStream_t s) {
+    ResidualArgs a;
+    a.src = SRC_AXPY;
+    a.dq = dq;
+    a.v = v;
+    a.alpha = alpha;
+    a.out = OUT_LIN;
+    a.r = out;
+    a.r0 = r0;
+    a.x = x;
+    a.sigma = sigma;
+    HIPCHK(launch_residual(ctx, level, a, s));
+}
+
+// w = shift v - (R(dq + h v) - rq) / h
+void jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const double *v, double shift,
+         double eps, int mode, double *w, hipStream_t s) {
+    Scal h{eps, nullptr};
+    if (mode == FR_EPS_NORMALIZED) {
+        HIPCHK(vec_dot(ctx, ctx->lv[level].N, v, v, ctx->scal + SC_JVP_N2, s));
+        HIPCHK(scal_fd_step(ctx->scal + SC_JVP_N2, eps, ctx->scal + SC_JVP_H, s));
+        h = Scal{0.0, ctx->scal + SC_JVP_H};
+    }
+    residual_lin(ctx, level, dq, v, h, rq, shift, nullptr, w, s);
+}
+
+void check_even(frpmg_ctx *ctx) {
+    for (int a = 0; a < ctx->dim; ++a)
+        REQUIRE(ctx->mesh.n[a] % 2 == 0, "EJ formation needs an even element count per axis");
+}
+
+void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, int precision, hipStream_t s) {
+    REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
+    REQUIRE(precision >= FR_PREC_FP64 && precision <= FR_PREC_FP32_BF16, "bad precision");
+    check_even(ctx);
+    Level &L = ctx->lv[level];
+    REQUIRE(L.nb <= 140, "EJ block too large for this build (n_b > 140)");
+    const size_t nblk = (size_t)ctx->mesh.Ne * L.nb * L.nb;
+    if (!L.blk64) L.blk64 = dalloc(ctx, nblk);
+    if (precision != FR_PREC_FP64 && !L.inv32) {
+        void *p = nullptr;
+        HIPCHK(hipMalloc(&p, nblk * sizeof(float)));
+        L.inv32 = (float *)p;
+    }
+    HIPCHK(hipMemsetAsync(L.dstatus, 0, sizeof(int), s));
+    residual(ctx, level, dq, L.r0, s);
+    const int ncol = 1 << ctx->dim;
+    for (int colour = 0; colour < ncol; ++colour)
+        for (int col = 0; col < L.nb; ++col) {
+            ResidualArgs a;
+            a.src = SRC_FDCOL;
+            a.dq = dq;
+            a.colour = colour;
+            a.col = col;
+            a.out = OUT_EJCOL;
+            a.r0 = L.r0;
+            a.sigma = sigma;
+            a.blocks = L.blk64;
+            HIPCHK(launch_residual(ctx, level, a, s));
+        }
+    HIPCHK(ej_invert(ctx, level, precision, s));
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(ctx->host_pinned, L.dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(&flag, ctx->host_pinned, sizeof(int));
+    if (flag) {
+        ctx->err = "zero pivot in an element-Jacobi block";
+        throw Fail{FR_ESINGULAR};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// nonlinear p-multigrid preconditioner
+// ---------------------------------------------------------------------------
+
+struct Counters {
+    long R0 = 0, R1 = 0, E0 = 0, E1 = 0;
+};
+
+void pmg_point(frpmg_ctx *ctx, const double *dq, const double *rq, hipStream_t s) {
+    ctx->pt_q = dq;
+    ctx->pt_rq = rq;
+    if (ctx->nlevels > 1) {
+        HIPCHK(transfer_apply(ctx, 0, true, dq, ctx->q1, s));
+        residual(ctx, 1, ctx->q1, ctx->r1, s);
+    }
+}
+
+void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double *y, hipStream_t s,
+                    Counters *cnt) {
+    REQUIRE(ctx->pt_q && ctx->pt_rq, "pmg_set_point has not been called");
+    REQUIRE(p.n0 >= 1, "n0 must be >= 1");
+    const Level &L0 = ctx->lv[0];
+    REQUIRE(L0.inv_prec >= 0, "level 0 has no EJ factors");
+    const size_t N0 = L0.N;
+    const bool coarse = p.coarse_mode != FR_COARSE_NONE;
+    if (coarse) {
+        REQUIRE(ctx->nlevels > 1 && ctx->lv[1].inv_prec >= 0, "level 1 has no EJ factors");
+        REQUIRE(p.n1 >= 1, "n1 must be >= 1");
+        REQUIRE(p.coarse_mode == FR_COARSE_EJ, "coarse mode not available in this build");
+    }
+    const Scal one{1.0, nullptr};
+    const double *Xs = x;
+    Scal inv_s{1.0, nullptr};
+    if (p.scale_mode == FR_SCALE_NORMALIZED) {
+        HIPCHK(vec_dot(ctx, N0, x, x, ctx->scal + SC_PMG_N2, s));
+        HIPCHK(scal_pmg_scale(ctx->scal + SC_PMG_N2, p.eps_p, p.sigma_D, ctx->scal + SC_PMG_S,
+                              ctx->scal + SC_PMG_INV, s));
+        HIPCHK(vec_scale_copy(N0, Scal{0.0, ctx->scal + SC_PMG_S}, x, ctx->wXs, s));
+        Xs = ctx->wXs;
+        inv_s = Scal{0.0, ctx->scal + SC_PMG_INV};
+    }
+    double *Y = ctx->wY, *G = ctx->wG;
+    // pre-smoothing: the first sweep starts at Y = 0, where G = -X
+    HIPCHK(ej_apply(ctx, 0, Xs, 1.0, 0.0, Y, s));
+    cnt->E0++;
+    for (int it = 1; it < p.n0; ++it) {
+        residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
+        cnt->R0++;
+        HIPCHK(ej_apply(ctx, 0, G, -1.0, 1.0, Y, s));
+        cnt->E0++;
+    }
+    if (coarse) {
+        const size_t N1 = ctx->lv[1].N;
+        // defect d = -G(Y); restrict Y and G
+        residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
+        cnt->R0++;
+        HIPCHK(transfer_apply(ctx, 0, true, Y, ctx->cZ0, s));
+        HIPCHK(transfer_apply(ctx, 0, true, G, ctx->cd, s));  // cd = Gamma G = -Gamma d
+        // FAS forcing S1 = G1(Z0) + Gamma d  with G1(Z) = sigma Z - (R1(q1 + Z) - R1(q1))
+        residual_lin(ctx, 1, ctx->q1, ctx->cZ0, one, ctx->r1, p.sigma_D, ctx->cd, ctx->cS, s);
+        cnt->R1++;
+        // coarse sweeps; the first uses G1(Z0) - S1 = -Gamma d = cd
+        HIPCHK(hipMemcpyAsync(ctx->cZ, ctx->cZ0, N1 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(ej_apply(ctx, 1, ctx->cd, -1.0, 1.0, ctx->cZ, s));
+        cnt->E1++;
+        for (int it = 1; it < p.n1; ++it) {
+            residual_lin(ctx, 1, ctx->q1, ctx->cZ, one, ctx->r1, p.sigma_D, ctx->cS, ctx->cG, s);
+            cnt->R1++;
+            HIPCHK(ej_apply(ctx, 1, ctx->cG, -1.0, 1.0, ctx->cZ, s));
+            cnt->E1++;
+        }
+        // Y += Pi (Z - Z0)
+        HIPCHK(vec_axpby(N1, Scal{-1.0, nullptr}, ctx->cZ0, one, ctx->cZ, s));
+        HIPCHK(transfer_apply(ctx, 0, false, ctx->cZ, G, s));
+        HIPCHK(vec_axpby(N0, one, G, one, Y, s));
+        // post-smoothing
+        for (int it = 0; it < p.n0; ++it) {
+            residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
+            cnt->R0++;
+            HIPCHK(ej_apply(ctx, 0, G, -1.0, 1.0, Y, s));
+            cnt->E0++;
+        }
+    }
+    HIPCHK(vec_scale_copy(N0, inv_s, Y, y, s));
+}
+
+// ---------------------------------------------------------------------------
+// flexible GMRES(m)
+// ---------------------------------------------------------------------------
+
+struct KrylovResult {
+    int iters = 0, restarts = 0;
+    bool converged = false, breakdown = false, nonfinite = false;
+    double res_est = 0.0, bnorm = 0.0;
+};
+
+template <typename MatVec, typename Prec>
+KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m, double tol, int max_restarts,
+                    MatVec &&A, Prec &&M, hipStream_t s) {
+    KrylovResult kr;
+    double *V = ctx->V, *Z = ctx->Zk, *w = ctx->kw;
+    const size_t ld = N;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv(m);
+    auto Hc = [&](int i, int j) -> double & { return H[(size_t)j * (m + 1) + i]; };
+    HIPCHK(vec_fill(N, 0.0, x, s));
+    const double bnorm = host_norm(ctx, N, b, s);
+    kr.bnorm = bnorm;
+    if (!std::isfinite(bnorm)) {
+        kr.nonfinite = true;
+        return kr;
+    }
+    if (bnorm == 0.0) {
+        kr.converged = true;
+        return kr;
+    }
+    const double target = tol * bnorm;
+    double beta = bnorm;
+    HIPCHK(vec_scale_copy(N, Scal{1.0 / beta, nullptr}, b, V, s));
+    for (;;) {
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jend = 0;
+        for (int j = 0; j < m; ++j) {
+            double *vj = V + (size_t)j * ld;
+            double *zj = Z + (size_t)j * ld;
+            M(vj, zj);
+            A(zj, w);
+            // CGS2
+            HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H1, s));
+            HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H1, w, s));
+            HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H2, s));
+            HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H2, w, s));
+            HIPCHK(vec_dot(ctx, N, w, w, ctx->red_out + RO_N2, s));
+            HIPCHK(hipMemcpyAsync(ctx->host_pinned, ctx->red_out, RO_SIZE * sizeof(double), hipMemcpyDeviceToHost,
+                                  s));
+            HIPCHK(hipStreamSynchronize(s));
+            const double *hp = ctx->host_pinned;
+            for (int i = 0; i <= j; ++i) Hc(i, j) = hp[RO_H1 + i] + hp[RO_H2 + i];
+            const double hn = std::sqrt(hp[RO_N2]);
+            Hc(j + 1, j) = hn;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
+                Hc(i + 1, j) = -sn[i] * Hc(i, j) + cs[i] * Hc(i + 1, j);
+                Hc(i, j) = t;
+            }
+            const double den = std::hypot(Hc(j, j), Hc(j + 1, j));
+            cs[j] = Hc(j, j) / den;
+            sn[j] = Hc(j + 1, j) / den;
+            Hc(j, j) = den;
+            Hc(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            kr.iters++;
+            jend = j + 1;
+            kr.res_est = std::fabs(g[j + 1]);
+            if (!std::isfinite(kr.res_est) || !std::isfinite(hn)) {
+                kr.nonfinite = true;
+                return kr;
+            }
+            if (hn == 0.0) {
+                kr.breakdown = true;
+                break;
+            }
+            HIPCHK(vec_scale_copy(N, Scal{1.0 / hn, nullptr}, w, V + (size_t)(j + 1) * ld, s));
+            if (kr.res_est <= target) break;
+        }
+        // back substitution with the triangular Hessenberg factor
+        for (int i = jend - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int k = i + 1; k < jend; ++k) t -= Hc(i, k) * yv[k];
+            yv[i] = t / Hc(i, i);
+        }
+        std::memcpy(ctx->host_pinned + RO_Y, yv.data(), jend * sizeof(double));
+        HIPCHK(hipMemcpyAsync(ctx->red_out + RO_Y, ctx->host_pinned + RO_Y, jend * sizeof(double),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(vec_combine(N, jend, Z, ld, ctx->red_out + RO_Y, x, s));
+        HIPCHK(hipStreamSynchronize(s));  // the pinned staging is reused below
+        if (kr.res_est <= target || kr.breakdown) {
+            kr.converged = true;
+            return kr;
+        }
+        if (kr.restarts >= max_restarts) return kr;
+        kr.restarts++;
+        // true residual r = b - A x
+        A(x, w);
+        HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, b, Scal{-1.0, nullptr}, w, s));
+        beta = host_norm(ctx, N, w, s);
+        kr.res_est = beta;
+        if (!std::isfinite(beta)) {
+            kr.nonfinite = true;
+            return kr;
+        }
+        if (beta <= target) {
+            kr.converged = true;
+            return kr;
+        }
+        HIPCHK(vec_scale_copy(N, Scal{1.0 / beta, nullptr}, w, V, s));
+    }
+}
+
+void ensure_krylov(frpmg_ctx *ctx, int m) {
+    const size_t N = ctx->lv[0].N;
+    if (ctx->kdim >= m && ctx->V) return;
+    dfree(ctx->V);
+    dfree(ctx->Zk);
+    ctx->V = nullptr;
+    ctx->Zk = nullptr;
+    ctx->V = dalloc(ctx, (size_t)(m + 1) * N);
+    ctx->Zk = dalloc(ctx, (size_t)m * N);
+    ctx->kdim = m;
+    if (!ctx->kw) ctx->kw = dalloc(ctx, N);
+    if (!ctx->sq) ctx->sq = dalloc(ctx, N);
+    if (!ctx->srq) ctx->srq = dalloc(ctx, N);
+    if (!ctx->sF) ctx->sF = dalloc(ctx, N);
+    if (!ctx->sb) ctx->sb = dalloc(ctx, N);
+    if (!ctx->sdx) ctx->sdx = dalloc(ctx, N);
+}
+
+double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, double *out, stage_stats *st,
+                hipStream_t s) {
+    REQUIRE(P.scheme == FR_SCHEME_ESDIRK || P.scheme == FR_SCHEME_ROW, "bad scheme");
+    REQUIRE(P.m >= 1 && P.m <= 60, "Krylov dimension must be in 1..60");
+    REQUIRE(P.dt > 0 && P.a_ii > 0, "dt and a_ii must be positive");
+    REQUIRE(P.precond == FR_PRECOND_EJ || P.precond == FR_PRECOND_PMG, "preconditioner not available");
+    const bool pmg = P.precond == FR_PRECOND_PMG;
+    REQUIRE(!pmg || ctx->nlevels > 1, "pMG needs two levels");
+    std::memset(st, 0, sizeof(*st));
+    const size_t N = ctx->lv[0].N;
+    ensure_krylov(ctx, P.m);
+    Counters cnt;
+    HIPCHK(hipStreamSynchronize(s));
+    const double t0 = now();
+    const bool esdirk = P.scheme == FR_SCHEME_ESDIRK;
+    const double dtau = (P.dtau > 0) ? P.dtau : P.dt;
+    // shifts: sigma_A of the outer operator, sigma_S of the smoother blocks
+    const double sigma_A = esdirk ? 1.0 / dtau + 1.0 / (P.a_ii * P.dt) : 1.0 / (P.a_ii * P.dt);
+    const double sigma_S = 1.0 / dtau + sigma_A;
+    if (!P.skip_setup) {
+        if (pmg) {
+            ej_factor_impl(ctx, 0, dq_n, sigma_S, P.precision, s);
+            // the coarse blocks are linearised at Gamma q^n
+            HIPCHK(transfer_apply(ctx, 0, true, dq_n, ctx->q1, s));
+            ej_factor_impl(ctx, 1, ctx->q1, sigma_S, P.precision, s);
+        } else {
+            ej_factor_impl(ctx, 0, dq_n, sigma_A, P.precision, s);
+        }
+        cnt.R0 += 1 + (1 << ctx->dim) * ctx->lv[0].nb;
+        if (pmg) cnt.R1 += 1 + (1 << ctx->dim) * ctx->lv[1].nb;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const double t1 = now();
+    pmg_params pp{sigma_A, P.n0, P.n1, FR_COARSE_EJ, P.scale_mode, P.eps_p};
+    auto prec = [&](const double *v, double *z) {
+        if (pmg) {
+            pmg_apply_impl(ctx, pp, v, z, s, &cnt);
+        } else {
+            HIPCHK(ej_apply(ctx, 0, v, 1.0, 0.0, z, s));
+            cnt.E0++;
+        }
+    };
+    fr_status status = FR_OK;
+    if (esdirk) {
+        double *q = ctx->sq, *rq = ctx->srq, *F = ctx->sF, *b = ctx->sb, *dx = ctx->sdx;
+        residual(ctx, 0, dq_n, rq, s);
+        cnt.R0++;
+        HIPCHK(hipMemcpyAsync(b, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(vec_axpby(N, Scal{P.a_i1 * P.dt, nullptr}, rq, Scal{1.0, nullptr}, b, s));
+        HIPCHK(hipMemcpyAsync(q, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        const double c = 1.0 / (P.a_ii * P.dt);
+        HIPCHK(vec_stage_F(N, q, b, c, rq, F, s));
+        const double f0 = host_norm(ctx, N, F, s);
+        st->res0 = f0;
+        double fn = f0;
+        if (!std::isfinite(f0)) status = FR_ENONFINITE;
+        while (status == FR_OK && fn > P.tol * f0 && st->ptc_iters < P.max_ptc) {
+            if (pmg) {
+                pmg_point(ctx, q, rq, s);
+                cnt.R1++;
+            }
+            HIPCHK(vec_axpby(N, Scal{0.0, nullptr}, nullptr, Scal{-1.0, nullptr}, F, s));  // F <- -F
+            auto A = [&](const double *z, double *w) {
+                jvp(ctx, 0, q, rq, z, sigma_A, P.eps, P.eps_mode, w, s);
+                cnt.R0++;
+            };
+            KrylovResult kr = fgmres(ctx, N, F, dx, P.m, P.eta, P.max_restarts, A, prec, s);
+            if (st->ptc_iters < FR_MAX_NEWTON_LOG) st->gmres_per_newton[st->ptc_iters] = kr.iters;
+            st->gmres_iters += kr.iters;
+            st->restarts += kr.restarts;
+            if (kr.nonfinite) {
+                status = FR_ENONFINITE;
+                break;
+            }
+            HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, dx, Scal{1.0, nullptr}, q, s));
+            residual(ctx, 0, q, rq, s);
+            cnt.R0++;
+            HIPCHK(vec_stage_F(N, q, b, c, rq, F, s));
+            fn = host_norm(ctx, N, F, s);
+            st->ptc_iters++;
+            if (!std::isfinite(fn)) status = FR_ENONFINITE;
+        }
+        st->res = fn;
+        st->rel_res = f0 > 0 ? fn / f0 : 0.0;
+        st->converged = (fn <= P.tol * f0) ? 1 : 0;
+        if (status == FR_OK && !st->converged) status = FR_ENOCONV;
+        HIPCHK(hipMemcpyAsync(out, q, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+        double *R0 = ctx->srq, *w = ctx->sF;
+        residual(ctx, 0, dq_n, R0, s);
+        cnt.R0++;
+        if (pmg) {
+            pmg_point(ctx, dq_n, R0, s);
+            cnt.R1++;
+        }
+        auto A = [&](const double *z, double *wout) {
+            jvp(ctx, 0, dq_n, R0, z, sigma_A, P.eps, P.eps_mode, wout, s);
+            cnt.R0++;
+        };
+        KrylovResult kr = fgmres(ctx, N, R0, out, P.m, P.tol, P.max_restarts, A, prec, s);
+        st->gmres_iters = kr.iters;
+        st->restarts = kr.restarts;
+        st->gmres_per_newton[0] = kr.iters;
+        st->res0 = kr.bnorm;
+        st->res = kr.res_est;
+        st->rel_res = kr.bnorm > 0 ? kr.res_est / kr.bnorm : 0.0;
+        st->converged = kr.converged ? 1 : 0;
+        if (kr.nonfinite) status = FR_ENONFINITE;
+        else if (!kr.converged) status = FR_ENOCONV;
+        // true residual of the FD operator at the solution
+        A(out, w);
+        HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, R0, Scal{-1.0, nullptr}, w, s));
+        const double tr = host_norm(ctx, N, w, s);
+        st->true_rel_res = kr.bnorm > 0 ? tr / kr.bnorm : 0.0;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const double t2 = now();
+    st->t_setup = t1 - t0;
+    st->t_solve = t2 - t1;
+    st->t_total = t2 - t0;
+    st->n_R_fine = cnt.R0;
+    st->n_R_coarse = cnt.R1;
+    st->n_ej_fine = cnt.E0;
+    st->n_ej_coarse = cnt.E1;
+    st->status = status;
+    if (status != FR_OK) {
+        ctx->err = status == FR_ENONFINITE ? "non-finite norm in the stage solve" : "stage solve did not converge";
+        throw Fail{status};
+    }
+}
+
+void destroy_all(frpmg_ctx *ctx) {
+    for (int l = 0; l < FR_MAX_LEVELS; ++l) {
+        Level &L = ctx->lv[l];
+        dfree(L.Tm);
+        dfree(L.Fs);
+        dfree(L.blk64);
+        dfree(L.inv32);
+        dfree(L.dstatus);
+        dfree(L.r0);
+    }
+    for (int a = 0; a < 3; ++a) dfree(ctx->inv2h[a]);
+    dfree(ctx->red_partial);
+    dfree(ctx->red_out);
+    dfree(ctx->scal);
+    if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+    double *bufs[] = {ctx->q1, ctx->r1, ctx->wY, ctx->wG, ctx->wXs, ctx->cZ0, ctx->cZ, ctx->cS, ctx->cG, ctx->cd,
+                      ctx->V, ctx->Zk, ctx->kw, ctx->sq, ctx->srq, ctx->sF, ctx->sb, ctx->sdx};
+    for (double *b : bufs) dfree(b);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+fr_status fr_create(const fr_mesh_desc *d, frpmg_ctx **out) {
+    if (!d || !out) return FR_EINVAL;
+    *out = nullptr;
+    frpmg_ctx *ctx = new (std::nothrow) frpmg_ctx();
+    if (!ctx) return FR_ENOMEM;
+    fr_status st = guarded(ctx, [&] {
+        REQUIRE(d->dim == 2 || d->dim == 3, "dim must be 2 or 3");
+        REQUIRE(d->nlevels >= 1 && d->nlevels <= FR_MAX_LEVELS, "nlevels out of range");
+        ctx->dim = d->dim;
+        ctx->nv = d->dim + 2;
+        ctx->nlevels = d->nlevels;
+        MeshK &m = ctx->mesh;
+        m.dim = d->dim;
+        m.n[2] = 1;
+        long ne = 1;
+        for (int a = 0; a < d->dim; ++a) {
+            REQUIRE(d->n[a] >= 1, "element counts must be >= 1");
+            REQUIRE(d->h[a] != nullptr, "element widths missing");
+            m.n[a] = d->n[a];
+            ne *= d->n[a];
+        }
+        REQUIRE(ne < (1L << 30), "too many elements");
+        m.Ne = (int)ne;
+        for (int a = 0; a < d->dim; ++a) {
+            std::vector<double> ih(d->n[a]);
+            for (int i = 0; i < d->n[a]; ++i) {
+                REQUIRE(d->h[a][i] > 0.0, "element widths must be positive");
+                ih[i] = 2.0 / d->h[a][i];
+            }
+            ctx->inv2h[a] = dalloc(ctx, d->n[a]);
+            HIPCHK(hipMemcpy(ctx->inv2h[a], ih.data(), d->n[a] * sizeof(double), hipMemcpyHostToDevice));
+            m.inv2h[a] = ctx->inv2h[a];
+        }
+        for (int a = d->dim; a < 3; ++a) m.inv2h[a] = nullptr;
+        Phys &ph = ctx->phys;
+        ph.gam = d->gamma;
+        ph.mu = d->mu;
+        ph.Pr = d->Pr;
+        ph.tau = d->tau;
+        REQUIRE(d->qinf[0] > 0.0, "reference density must be positive");
+        double kin = 0.0;
+        for (int v = 0; v < 5; ++v) ph.qinf[v] = (v < ctx->nv) ? d->qinf[v] : 0.0;
+        for (int b = 0; b < 3; ++b) ph.uinf[b] = (b < d->dim) ? d->qinf[1 + b] / d->qinf[0] : 0.0;
+        for (int b = 0; b < d->dim; ++b) kin += d->qinf[1 + b] * ph.uinf[b];
+        ph.pinf = (d->gamma - 1.0) * (d->qinf[d->dim + 1] - 0.5 * kin);
+        REQUIRE(ph.pinf > 0.0, "reference pressure must be positive");
+        for (int l = 0; l < d->nlevels; ++l) {
+            const int p = d->p[l];
+            REQUIRE(p >= 1 && p <= (d->dim == 2 ? 4 : 3), "polynomial degree out of range");
+            if (l > 0) REQUIRE(p < d->p[l - 1], "levels must have decreasing degree");
+            Level &L = ctx->lv[l];
+            L.p = p;
+            L.P = p + 1;
+            L.Np = ipow(L.P, d->dim);
+            L.NF = ipow(L.P, d->dim - 1);
+            L.nb = ctx->nv * L.Np;
+            L.N = (size_t)L.nb * m.Ne;
+            build_ops1d(L.P, L.ops);
+            const size_t ntr = (size_t)d->dim * ctx->nv * L.NF * m.Ne;
+            L.Tm = dalloc(ctx, ntr);
+            L.Fs = dalloc(ctx, ntr);
+            L.r0 = dalloc(ctx, L.N);
+            void *p2 = nullptr;
+            HIPCHK(hipMalloc(&p2, sizeof(int)));
+            L.dstatus = (int *)p2;
+            if (l > 0) build_transfer(ctx->lv[l - 1].P, L.P, ctx->tr[l - 1]);
+        }
+        ctx->red_partial = dalloc(ctx, (size_t)64 * kRedBlocks);
+        ctx->red_out = dalloc(ctx, RO_SIZE);
+        ctx->scal = dalloc(ctx, 16);
+        void *hp = nullptr;
+        HIPCHK(hipHostMalloc(&hp, RO_SIZE * sizeof(double), hipHostMallocDefault));
+        ctx->host_pinned = (double *)hp;
+        const size_t N0 = ctx->lv[0].N;
+        ctx->wY = dalloc(ctx, N0);
+        ctx->wG = dalloc(ctx, N0);
+        ctx->wXs = dalloc(ctx, N0);
+        if (d->nlevels > 1) {
+            const size_t N1 = ctx->lv[1].N;
+            ctx->q1 = dalloc(ctx, N1);
+            ctx->r1 = dalloc(ctx, N1);
+            ctx->cZ0 = dalloc(ctx, N1);
+            ctx->cZ = dalloc(ctx, N1);
+            ctx->cS = dalloc(ctx, N1);
+            ctx->cG = dalloc(ctx, N1);
+            ctx->cd = dalloc(ctx, N1);
+        }
+        HIPCHK(hipDeviceSynchronize());
+    });
+    if (st != FR_OK) {
+        std::fprintf(stderr, "fr_create: %s\n", ctx->err.c_str());
+        destroy_all(ctx);
+        delete ctx;
+        return st;
+    }
+    *out = ctx;
+    return FR_OK;
+}
+
+void fr_destroy(frpmg_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    destroy_all(ctx);
+    delete ctx;
+}
+
+const char *fr_last_error(const frpmg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+size_t fr_level_size(const frpmg_ctx *ctx, int level) {
+    if (!ctx || level < 0 || level >= ctx->nlevels) return 0;
+    return ctx->lv[level].N;
+}
+
+fr_status fr_residual(frpmg_ctx *ctx, int level, const double *dq, double *r, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
+        REQUIRE(dq && r && dq != r, "bad pointers");
+        residual(ctx, level, dq, r, S(stream));
+    });
+}
+
+fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const double *v, double shift,
+                 double eps, int eps_mode, double *w, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
+        REQUIRE(dq && rq && v && w, "null pointer");
+        REQUIRE(w != dq && w != rq && w != v, "w must not alias the inputs");
+        REQUIRE(eps > 0.0, "eps must be positive");
+        REQUIRE(eps_mode == FR_EPS_ABSOLUTE || eps_mode == FR_EPS_NORMALIZED, "bad eps_mode");
+        jvp(ctx, level, dq, rq, v, shift, eps, eps_mode, w, S(stream));
+    });
+}
+
+fr_status ej_factor(frpmg_ctx *ctx, int level, const double *dq_lin, double sigma, int precision,
+                    fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(dq_lin, "null pointer");
+        ej_factor_impl(ctx, level, dq_lin, sigma, precision, S(stream));
+    });
+}
+
+fr_status ej_solve(frpmg_ctx *ctx, int level, const double *r, double *y, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
+        REQUIRE(ctx->lv[level].inv_prec >= 0, "level has no EJ factors");
+        REQUIRE(r && y, "null pointer");
+        HIPCHK(ej_apply(ctx, level, r, 1.0, 0.0, y, S(stream)));
+    });
+}
+
+fr_status ej_get_inverse(frpmg_ctx *ctx, int level, double *host_out) {
+    return guarded(ctx, [&] {
+        REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
+        const Level &L = ctx->lv[level];
+        REQUIRE(L.inv_prec >= 0, "level has no EJ factors");
+        REQUIRE(host_out, "null pointer");
+        const size_t n = (size_t)ctx->mesh.Ne * L.nb * L.nb;
+        HIPCHK(hipDeviceSynchronize());
+        if (L.inv_prec == FR_PREC_FP64) {
+            HIPCHK(hipMemcpy(host_out, L.inv, n * sizeof(double), hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> tmp(n);
+            HIPCHK(hipMemcpy(tmp.data(), L.inv, n * sizeof(float), hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < n; ++i) host_out[i] = tmp[i];
+        }
+    });
+}
+
+fr_status pmg_restrict(frpmg_ctx *ctx, int from, int to, const double *x, double *y, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(from >= 0 && to == from + 1 && to < ctx->nlevels, "restriction goes from level l to l + 1");
+        REQUIRE(x && y && x != y, "bad pointers");
+        HIPCHK(transfer_apply(ctx, from, true, x, y, S(stream)));
+    });
+}
+
+fr_status pmg_prolong(frpmg_ctx *ctx, int from, int to, const double *x, double *y, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(to >= 0 && from == to + 1 && from < ctx->nlevels, "prolongation goes from level l + 1 to l");
+        REQUIRE(x && y && x != y, "bad pointers");
+        HIPCHK(transfer_apply(ctx, to, false, x, y, S(stream)));
+    });
+}
+
+fr_status pmg_set_point(frpmg_ctx *ctx, const double *dq, const double *rq, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(dq && rq, "null pointer");
+        pmg_point(ctx, dq, rq, S(stream));
+    });
+}
+
+fr_status pmg_precond_apply(frpmg_ctx *ctx, const pmg_params *prm, const double *x, double *y, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(prm && x && y && x != y, "bad arguments");
+        Counters c;
+        pmg_apply_impl(ctx, *prm, x, y, S(stream), &c);
+    });
+}
+
+fr_status gmres_solve_stage(frpmg_ctx *ctx, const stage_params *prm, const double *dq_n, double *out,
+                            stage_stats *stats, fr_stream stream) {
+    stage_stats local;
+    stage_stats *st = stats ? stats : &local;
+    return guarded(ctx, [&] {
+        REQUIRE(prm && dq_n && out && dq_n != out, "bad arguments");
+        stage_impl(ctx, *prm, dq_n, out, st, S(stream));
+    });
+}
+
+}  // extern "C"

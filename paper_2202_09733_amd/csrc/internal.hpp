@@ -1,0 +1,163 @@
+// Internal declarations of the frpmg library (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/frpmg.h"
+
+namespace frpmg {
+
+constexpr int kMaxP = 5;  // points per direction (p <= 4)
+
+// 1D operators on [-1, 1] for one number of Gauss-Legendre points.
+struct Ops1D {
+    double D[kMaxP][kMaxP];  // D[i][j] = l_j'(xi_i)
+    double bm[kMaxP];        // l_j(-1)
+    double bp[kMaxP];        // l_j(+1)
+    double gLd[kMaxP];       // derivative of the left correction at xi_i
+    double gRd[kMaxP];       // derivative of the right correction at xi_i
+};
+
+// 1D transfer operators between two levels (fine P0, coarse P1 points).
+struct Transfer1D {
+    int P0, P1;
+    double G[kMaxP][kMaxP];   // restriction, P1 x P0
+    double Pi[kMaxP][kMaxP];  // prolongation, P0 x P1
+};
+
+struct Phys {
+    double gam, mu, Pr, tau;
+    double qinf[5];
+    double uinf[3];
+    double pinf;
+};
+
+struct MeshK {
+    int dim;
+    int n[3];
+    int Ne;
+    const double *inv2h[3];  // device: 2 / h per axis index
+};
+
+// Scalar that lives either on the host (p == nullptr) or in device memory.
+struct Scal {
+    double v;
+    const double *p;
+};
+
+// How a residual launch forms the state it evaluates R at.
+enum SrcMode { SRC_PLAIN = 0, SRC_AXPY = 1, SRC_FDCOL = 2 };
+// What a residual launch writes.
+enum OutMode { OUT_R = 0, OUT_LIN = 1, OUT_EJCOL = 2 };
+
+struct ResidualArgs {
+    SrcMode src = SRC_PLAIN;
+    const double *dq = nullptr;   // base state deviation
+    const double *v = nullptr;    // direction (SRC_AXPY)
+    Scal alpha{1.0, nullptr};     // state = dq + alpha v
+    int colour = 0, col = 0;      // SRC_FDCOL: perturbed colour and block column
+    OutMode out = OUT_R;
+    double *r = nullptr;          // OUT_R / OUT_LIN destination
+    const double *r0 = nullptr;   // OUT_LIN / OUT_EJCOL: R at the base state
+    const double *x = nullptr;    // OUT_LIN: optional subtrahend
+    double sigma = 0.0;           // OUT_LIN / OUT_EJCOL shift
+    double *blocks = nullptr;     // OUT_EJCOL: [Ne][nb][nb] column-major blocks
+};
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+};
+
+struct Level {
+    int p = 0, P = 0, Np = 0, NF = 0, nb = 0;
+    size_t N = 0;  // state length
+    Ops1D ops{};
+    double *Tm = nullptr;  // minus traces [dim][nv][NF][Ne]
+    double *Fs = nullptr;  // common fluxes on + faces [dim][nv][NF][Ne]
+    // element-Jacobi storage: FP64 work blocks and the inverse
+    double *blk64 = nullptr;  // [Ne][nb][nb], column-major per block
+    void *inv = nullptr;      // inverse: points to blk64 (FP64) or inv32
+    float *inv32 = nullptr;
+    int inv_prec = -1;
+    int *dstatus = nullptr;   // device flag: 1 = zero pivot seen
+    double *r0 = nullptr;     // scratch: R at the EJ linearisation point
+};
+
+// Reduction scratch: partial sums per block and per vector.
+constexpr int kRedBlocks = 512;
+
+}  // namespace frpmg
+
+struct frpmg_ctx {
+    int dim = 0, nv = 0, nlevels = 0;
+    frpmg::MeshK mesh{};
+    frpmg::Phys phys{};
+    frpmg::Level lv[FR_MAX_LEVELS];
+    frpmg::Transfer1D tr[FR_MAX_LEVELS];  // tr[l]: between level l and l + 1
+    double *inv2h[3] = {nullptr, nullptr, nullptr};
+    std::string err;
+    double *red_partial = nullptr;  // [64][kRedBlocks]
+    double *red_out = nullptr;      // [64]
+    double *scal = nullptr;         // device scalars [16]
+    double *host_pinned = nullptr;  // pinned host staging [64]
+    // preconditioner workspaces (allocated at creation)
+    double *pq = nullptr, *prq = nullptr;    // linearisation point (borrowed pointers)
+    double *q1 = nullptr, *r1 = nullptr;     // restricted point and R_1 there
+    double *wY = nullptr, *wG = nullptr, *wXs = nullptr;
+    double *cZ0 = nullptr, *cZ = nullptr, *cS = nullptr, *cG = nullptr, *cd = nullptr;
+    const double *pt_q = nullptr, *pt_rq = nullptr;
+    // Krylov workspaces (allocated at the first stage solve)
+    int kdim = 0;
+    double *V = nullptr, *Zk = nullptr, *kw = nullptr;
+    double *sq = nullptr, *srq = nullptr, *sF = nullptr, *sb = nullptr, *sdx = nullptr;
+};
+
+namespace frpmg {
+
+// ops1d.cpp
+void build_ops1d(int P, Ops1D &o);
+void build_transfer(int P0, int P1, Transfer1D &t);
+void gauss_legendre(int P, double *x, double *w);
+
+// residual.hip
+hipError_t launch_residual(const frpmg_ctx *ctx, int level, const ResidualArgs &a, hipStream_t s);
+
+// vec.hip
+hipError_t vec_dot(frpmg_ctx *ctx, size_t n, const double *x, const double *y, double *dout, hipStream_t s);
+hipError_t vec_mdot(frpmg_ctx *ctx, size_t n, int nvec, const double *V, size_t ldv, const double *w,
+                    double *dout, hipStream_t s);
+hipError_t vec_gemv_sub(size_t n, int nvec, const double *V, size_t ldv, const double *h, double *w,
+                        hipStream_t s);
+// y = a x + b y (a, b host or device scalars); x may be null (then y = b y)
+hipError_t vec_axpby(size_t n, Scal a, const double *x, Scal b, double *y, hipStream_t s);
+// y = a x
+hipError_t vec_scale_copy(size_t n, Scal a, const double *x, double *y, hipStream_t s);
+// y = x0 + sum_i c[i] Z_i  with host coefficients
+hipError_t vec_combine(size_t n, int nvec, const double *Z, size_t ldz, const double *c_dev, double *y,
+                       hipStream_t s);
+hipError_t vec_fill(size_t n, double v, double *y, hipStream_t s);
+// out = (x - b) * c - r   (stage function)
+hipError_t vec_stage_F(size_t n, const double *x, const double *b, double c, const double *r, double *out,
+                       hipStream_t s);
+// d_out[k] = eps / sqrt(d_in[k]) if d_in[k] > 0 else eps  (FD step from a squared norm)
+hipError_t scal_fd_step(const double *sumsq, double eps, double *hout, hipStream_t s);
+// d_out = num * sigma / sqrt(sumsq) and its inverse (preconditioner scaling)
+hipError_t scal_pmg_scale(const double *sumsq, double eps_p, double sigma, double *s_out, double *inv_out,
+                          hipStream_t s);
+hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_dir, const double *x,
+                          double *y, hipStream_t s);
+
+// ej.hip
+hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s);
+// y = beta y + alpha B^{-1} r
+hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta, double *y,
+                    hipStream_t s);
+
+}  // namespace frpmg
