@@ -24,6 +24,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic():
+    """HBM bytes per fine-level FP64 k_ej_apply launch from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_ej_apply_config2.md")
+    src = os.path.join(ROOT, "paper_2202_09733_amd", "csrc", "ej.hip")
+    try:
+        txt = open(path).read()
+        want = re.search(r"ej.hip sha256: (\w+)", txt).group(1)
+        val = float(re.search(r"fp64 traffic bytes per launch: (\d+)", txt).group(1))
+    except (OSError, AttributeError):
+        return None
+    have = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return val if have == want else None
+
+
 def _events_time(fn, reps):
     """Average duration (s) of fn() over reps calls, HIP events on the current stream."""
     import torch
@@ -62,6 +80,11 @@ def kernel_rates(fr, wl, dq_dev, reps=50):
     fac_bytes = wl.Ne * nb * nb * (8 if fr_prec(fr) == capi.PREC_FP64 else 4)
     out["ej_apply_fine"] = dict(s_per_call=t_e, alg_bytes=float(fac_bytes + 16 * N), launches=1,
                                 kernel="k_ej_apply")
+    # reference: a plain device copy of 512 MiB (256 MiB read + 256 MiB written)
+    a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dq_dev.device).normal_()
+    b = torch.empty_like(a)
+    t_c = _events_time(lambda: b.copy_(a), 20)
+    out["device_copy_512MiB"] = dict(s_per_call=t_c, alg_bytes=float(2 * a.numel() * 8), launches=1)
     for k, d in out.items():
         d["GBps"] = d["alg_bytes"] / d["s_per_call"] / 1e9
     return out
@@ -129,6 +152,32 @@ def cpu_baseline(wl, st, max_seconds=25.0):
                 seconds_extrapolated=total)
 
 
+def only_kernel(fr, wl, dq, args, prec):
+    import torch
+    sig = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
+    x = torch.randn_like(dq)
+    y = fr.empty(0)
+    if args.only_kernel == "ej_apply":
+        fr.ej_factor(0, dq, sig, prec)
+    rq = fr.residual(0, dq)
+    torch.cuda.synchronize()
+    for _ in range(args.reps):
+        if args.only_kernel == "ej_apply":
+            fr.ej_solve(0, x, out=y)
+        elif args.only_kernel == "residual":
+            fr.residual(0, dq, out=y)
+        else:
+            fr.jvp(0, dq, rq, x, sig, out=y)
+    torch.cuda.synchronize()
+    # calibration: a plain device copy of exactly 256 MiB read + 256 MiB written
+    a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dq.device).normal_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("[bench] only-kernel %s x%d done" % (args.only_kernel, args.reps), file=sys.stderr)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,9 +186,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the EJ-only comparison and kernel rates")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "residual", "jvp"],
+                    help="profiling driver: set up the config-2 state, launch one kernel family --reps times "
+                         "and a 256 MiB device copy (counter calibration), print nothing else")
+    ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this path has no multi-GPU mode (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU only: this build has no multi-GPU path (N > 1 is not supported)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -154,6 +207,9 @@ def main():
     dq = fr.to_dev(wl.dq)
     cfg = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=prec)
     out = fr.empty(0)
+    if args.only_kernel:
+        only_kernel(fr, wl, dq, args, prec)
+        return
     print("[bench] warmup %d stage solve(s)" % args.warmup, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         _, st = fr.solve_stage(cfg, dq, out=out)
@@ -206,6 +262,22 @@ def main():
         result["plain_ej"] = {k: st_ej[k] for k in ("ptc_iters", "gmres_iters", "rel_res", "t_total", "t_setup",
                                                       "converged")}
         result["plain_ej"]["dof_per_s"] = dof / st_ej["t_total"]
+        if prec == capi.PREC_FP64:
+            print("[bench] FP32-storage preconditioner variant", file=sys.stderr, flush=True)
+            cfg32 = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=capi.PREC_FP32)
+            fr.solve_stage(cfg32, dq, out=fr.empty(0))
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            st32 = None
+            for _ in range(args.steps):
+                _, st32 = fr.solve_stage(cfg32, dq, out=fr.empty(0))
+            torch.cuda.synchronize()
+            v32 = dof * args.steps / (time.perf_counter() - ta)
+            result["precision_fp32_factors"] = {
+                "value": v32, "speedup_vs_fp64": v32 / result["value"],
+                "dof_per_s_without_setup": dof / st32["t_solve"], "ptc_iters": st32["ptc_iters"],
+                "gmres_iters": st32["gmres_iters"], "rel_res": st32["rel_res"],
+                "note": "EJ inverses stored FP32 on both levels; R, JVP, FGMRES and the stage update FP64"}
         # re-create the pMG factors for the kernel-rate measurements
         fr.solve_stage(cfg, dq, out=out)
         print("[bench] kernel rates", file=sys.stderr, flush=True)
@@ -215,7 +287,7 @@ def main():
         result["roofline"] = {
             "kernel": "k_ej_apply (fine level, n_b=100, FP64 inverse blocks)",
             "bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None,
+            "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(),
         }
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)

@@ -107,8 +107,40 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
 
 constexpr int kApplyThreads = 256;
 
+template <typename T, int R>
+struct VecLoad;
+template <>
+struct VecLoad<double, 1> {
+    __device__ static void get(const double *p, double *o) { o[0] = p[0]; }
+};
+template <>
+struct VecLoad<double, 2> {
+    __device__ static void get(const double *p, double *o) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <>
+struct VecLoad<float, 1> {
+    __device__ static void get(const float *p, double *o) { o[0] = p[0]; }
+};
+template <>
+struct VecLoad<float, 4> {
+    __device__ static void get(const float *p, double *o) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+
 // y[row][k] = beta y + alpha sum_j Binv_k[row][j] r[j][k], Binv column-major.
-template <typename T>
+// Each lane owns R consecutive rows of one block and streams the block
+// column by column with one 16-byte load per column (R = 2 for FP64, 4 for
+// FP32 storage), so a wavefront reads whole contiguous column segments.
+template <typename T, int R>
 __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int epb, const T *__restrict__ inv,
                                                             const double *__restrict__ r, double alpha,
                                                             double beta, double *__restrict__ y) {
@@ -120,26 +152,53 @@ __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int 
         s_r[t] = (e < ne) ? r[(size_t)j * Ne + k0 + e] : 0.0;
     }
     __syncthreads();
-    const int span = epb * nb;
-    for (int t = threadIdx.x; t < span; t += blockDim.x) {
-        const int e = t / nb, row = t - e * nb;
-        if (e >= ne) continue;
-        const int k = k0 + e;
-        const T *col = inv + (size_t)k * nb * nb + row;
-        const double *rv = s_r + e * nb;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int j = 0;
-        for (; j + 4 <= nb; j += 4) {
-            a0 += (double)col[(size_t)j * nb] * rv[j];
-            a1 += (double)col[(size_t)(j + 1) * nb] * rv[j + 1];
-            a2 += (double)col[(size_t)(j + 2) * nb] * rv[j + 2];
-            a3 += (double)col[(size_t)(j + 3) * nb] * rv[j + 3];
-        }
-        for (; j < nb; ++j) a0 += (double)col[(size_t)j * nb] * rv[j];
-        const double acc = (a0 + a1) + (a2 + a3);
-        const size_t idx = (size_t)row * Ne + k;
-        y[idx] = (beta == 0.0) ? alpha * acc : beta * y[idx] + alpha * acc;
+    const int tpe = nb / R;  // lanes per block
+    const int e = threadIdx.x / tpe;
+    const int row = (threadIdx.x - e * tpe) * R;
+    if (e >= ne) return;
+    const int k = k0 + e;
+    const T *col = inv + (size_t)k * nb * nb + row;
+    const double *rv = s_r + e * nb;
+    double acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0.0;
+    int j = 0;
+    for (; j + 4 <= nb; j += 4) {
+        double v0[R], v1[R], v2[R], v3[R];
+        VecLoad<T, R>::get(col + (size_t)j * nb, v0);
+        VecLoad<T, R>::get(col + (size_t)(j + 1) * nb, v1);
+        VecLoad<T, R>::get(col + (size_t)(j + 2) * nb, v2);
+        VecLoad<T, R>::get(col + (size_t)(j + 3) * nb, v3);
+        const double x0 = rv[j], x1 = rv[j + 1], x2 = rv[j + 2], x3 = rv[j + 3];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += (v0[q] * x0 + v1[q] * x1) + (v2[q] * x2 + v3[q] * x3);
     }
+    for (; j < nb; ++j) {
+        double v0[R];
+        VecLoad<T, R>::get(col + (size_t)j * nb, v0);
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += v0[q] * rv[j];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const size_t idx = (size_t)(row + q) * Ne + k;
+        y[idx] = (beta == 0.0) ? alpha * acc[q] : beta * y[idx] + alpha * acc[q];
+    }
+}
+
+template <typename T, int R>
+hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, double beta, double *y,
+                        hipStream_t s) {
+    const int nb = L.nb;
+    const int tpe = nb / R;
+    if (tpe > kApplyThreads) return hipErrorInvalidValue;
+    const int epb = (tpe >= kApplyThreads) ? 1 : kApplyThreads / tpe;
+    const size_t lds = (size_t)epb * nb * sizeof(double);
+    dim3 grid((Ne + epb - 1) / epb);
+    dim3 block(tpe >= kApplyThreads ? tpe : kApplyThreads);
+    hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, (const T *)L.inv, r, alpha, beta,
+                       y);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -173,18 +232,13 @@ hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alp
                     hipStream_t s) {
     const Level &L = ctx->lv[level];
     const int nb = L.nb, Ne = ctx->mesh.Ne;
-    const int epb = (nb >= kApplyThreads) ? 1 : kApplyThreads / nb;
-    const size_t lds = (size_t)epb * nb * sizeof(double);
-    dim3 grid((Ne + epb - 1) / epb);
     if (L.inv_prec == FR_PREC_FP64)
-        hipLaunchKernelGGL(k_ej_apply<double>, grid, dim3(kApplyThreads), lds, s, nb, Ne, epb,
-                           (const double *)L.inv, r, alpha, beta, y);
-    else if (L.inv_prec >= 0)
-        hipLaunchKernelGGL(k_ej_apply<float>, grid, dim3(kApplyThreads), lds, s, nb, Ne, epb,
-                           (const float *)L.inv, r, alpha, beta, y);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+        return (nb % 2 == 0) ? launch_apply<double, 2>(L, Ne, r, alpha, beta, y, s)
+                             : launch_apply<double, 1>(L, Ne, r, alpha, beta, y, s);
+    if (L.inv_prec >= 0)
+        return (nb % 4 == 0) ? launch_apply<float, 4>(L, Ne, r, alpha, beta, y, s)
+                             : launch_apply<float, 1>(L, Ne, r, alpha, beta, y, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace frpmg
