@@ -88,7 +88,8 @@ size_t fr_level_size(const frpmg_ctx *ctx, int level);
 fr_status fr_residual(frpmg_ctx *ctx, int level, const double *dq, double *r, fr_stream stream);
 
 #define FR_EPS_ABSOLUTE 0   /* h = eps */
-#define FR_EPS_NORMALIZED 1 /* h = eps / ||v||_2 (unit-norm perturbation) */
+#define FR_EPS_NORMALIZED 1 /* h = eps / ||v||_2 (perturbation of norm eps) */
+#define FR_EPS_SCALED 2     /* h = eps (1 + ||dq||_2) / ||v||_2 (Knoll-Keyes scaling) */
 
 /* Finite-difference shifted Jacobian-vector product (Sec. 2.2, the matrix-
  * free product with fixed eps = 1e-6):
@@ -99,7 +100,7 @@ fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, 
                  double shift, double eps, int eps_mode, double *w, fr_stream stream);
 
 #define FR_PREC_FP64 0      /* FP64 factor, FP64 storage */
-#define FR_PREC_FP32 1      /* FP32 elimination from the FP64 block, FP32 storage */
+#define FR_PREC_FP32 1      /* FP64 elimination, inverse stored in FP32 */
 #define FR_PREC_FP32_BF16 2 /* FP32 storage; trailing updates on BF16-input MFMA, FP32 accumulate */
 
 /* Element-Jacobi setup (Sec. 2.2, element-Jacobi preconditioner; the
@@ -136,6 +137,7 @@ fr_status pmg_prolong(frpmg_ctx *ctx, int from, int to, const double *x, double 
 
 #define FR_SCALE_LITERAL 0    /* s = 1 */
 #define FR_SCALE_NORMALIZED 1 /* s = eps_p sigma_D / ||X||_2 */
+#define FR_SCALE_SCALED 2     /* s = eps_p sigma_D (1 + ||dq||_2) / ||X||_2, dq = the set point */
 
 /* Nonlinear pMG preconditioner parameters (Sec. 3.2). */
 typedef struct {

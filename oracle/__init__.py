@@ -220,21 +220,27 @@ def lu_solve(fac, x: np.ndarray) -> np.ndarray:
 # Finite-difference Jacobian-vector product (Sec. 2.2)
 # ---------------------------------------------------------------------------
 
-EPS_ABSOLUTE, EPS_NORMALIZED = 0, 1
+EPS_ABSOLUTE, EPS_NORMALIZED, EPS_SCALED = 0, 1, 2
 
 
-def fd_step(v: np.ndarray, eps: float, mode: int) -> float:
+def fd_step(v: np.ndarray, eps: float, mode: int, dq: np.ndarray | None = None) -> float:
     """Step h of the FD matvec: ABSOLUTE h = eps; NORMALIZED h = eps / ||v||_2
-    (the paper's fixed eps applied to the unit direction)."""
+    (the paper's fixed eps applied to the unit direction); SCALED
+    h = eps (1 + ||dq||_2) / ||v||_2 (the paper's eps with Knoll-Keyes
+    scaling by the size of the state deviation)."""
     if mode == EPS_ABSOLUTE:
         return eps
     nv = float(np.linalg.norm(v))
-    return eps / nv if nv > 0 else eps
+    if nv == 0.0:
+        return eps
+    if mode == EPS_SCALED:
+        return eps * (1.0 + float(np.linalg.norm(dq))) / nv
+    return eps / nv
 
 
-def jvp(level: Level, dq, rq, v, shift, eps=1e-6, mode=EPS_NORMALIZED):
+def jvp(level: Level, dq, rq, v, shift, eps=1e-6, mode=EPS_SCALED):
     """w = shift v - (R(q + h v) - R(q)) / h  (Sec. 2.2, matrix-free product)."""
-    h = fd_step(v, eps, mode)
+    h = fd_step(v, eps, mode, dq)
     return shift * v - (level.residual(dq + h * v) - rq) / h
 
 
@@ -344,7 +350,7 @@ def fgmres(A, M, b, m=30, tol=1e-8, max_restarts=20, max_iters=None):
 # Nonlinear p-multigrid preconditioner (Sec. 3.1 applied to Sec. 3.2)
 # ---------------------------------------------------------------------------
 
-SCALE_LITERAL, SCALE_NORMALIZED = 0, 1
+SCALE_LITERAL, SCALE_NORMALIZED, SCALE_SCALED = 0, 1, 2
 
 
 @dataclass
@@ -352,7 +358,7 @@ class PMGParams:
     sigma_D: float          # 1/dtau + 1/(a_ii dt) (ESDIRK) or 1/(a_ii dt) (ROW)
     n0: int = 2             # pre- and post-sweeps on p0
     n1: int = 2             # sweeps on p1
-    scale_mode: int = SCALE_NORMALIZED
+    scale_mode: int = SCALE_SCALED
     eps_p: float = 1e-6
     coarse: bool = True     # False: fine-level smoothing only (no coarse correction, no post-sweeps)
 
@@ -366,7 +372,10 @@ class PMG:
     Y <- Y - B^{-1} G(Y), where G(Y) = sigma_D Y - [R(q+Y) - R(q)] - X and
     B = sigma_S I - dR_k/dq_k holds the blocks with sigma_S = 1/dtau* + sigma_D
     (the pseudo-time backward-Euler step, alpha = 1), frozen at the start of
-    the time step (Sec. 2.2).
+    the time step (Sec. 2.2).  X is scaled by s before the cycle and Y by
+    1/s after: LITERAL s = 1; NORMALIZED s = eps_p sigma_D / ||X||;
+    SCALED s = eps_p sigma_D (1 + ||q||) / ||X||, so that Y is a small
+    perturbation of the state in the same sense as the FD matvec step.
 
     fine/coarse: Level objects; fac0/fac1: LU factors of B on each level.
     """
@@ -393,9 +402,10 @@ class PMG:
     def apply(self, X: np.ndarray) -> np.ndarray:
         p = self.prm
         s = 1.0
-        if p.scale_mode == SCALE_NORMALIZED:
+        if p.scale_mode in (SCALE_NORMALIZED, SCALE_SCALED):
             xn = float(np.linalg.norm(X))
-            s = p.eps_p * p.sigma_D / xn if xn > 0 else 1.0
+            size = 1.0 + float(np.linalg.norm(self.q)) if p.scale_mode == SCALE_SCALED else 1.0
+            s = p.eps_p * p.sigma_D * size / xn if xn > 0 else 1.0
         Xs = s * X
         dim, P0 = self.fine.dim, self.fine.P
         # pre-smoothing (the first sweep starts from Y = 0 where G = -X)
@@ -455,7 +465,7 @@ def _setup_precond(fine, coarse, dq_lin, kind, sigma_EJ, sigma_D, sigma_S, pmg_k
 
 def esdirk_stage(fine: Level, coarse: Level | None, dq_n, dt, a_ii, a_i1=None, precond="pmg",
                  eta=0.1, m=30, max_restarts=20, tol=1e-8, max_ptc=100, eps=1e-6,
-                 eps_mode=EPS_NORMALIZED, dtau=None, pmg_kw=None):
+                 eps_mode=EPS_SCALED, dtau=None, pmg_kw=None):
     """Second stage of an ESDIRK scheme with explicit first stage
     (Sec. 2.1 Eq. (ESDIRK2)): q_2 = q^n + dt (a_21 R(q^n) + a_22 R(q_2)),
     solved by pseudo-transient continuation with inexact Newton
@@ -501,7 +511,7 @@ def esdirk_stage(fine: Level, coarse: Level | None, dq_n, dt, a_ii, a_i1=None, p
 
 
 def row_stage(fine: Level, coarse: Level | None, dq_n, dt, a_ii, precond="pmg", m=30,
-              max_restarts=50, tol=1e-8, eps=1e-6, eps_mode=EPS_NORMALIZED, pmg_kw=None):
+              max_restarts=50, tol=1e-8, eps=1e-6, eps_mode=EPS_SCALED, pmg_kw=None):
     """First stage of a Rosenbrock-Wanner scheme (Sec. 2.1 Eq.
     (Rosenbrock_General) with i = 1): (I/(a_ii dt) - dR/dq(q^n)) Y = R(q^n),
     solved by FGMRES with the FD matvec to ||R(q^n) - A_h Y|| <= tol ||R(q^n)||.

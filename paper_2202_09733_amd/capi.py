@@ -20,10 +20,10 @@ FR_OK, FR_EINVAL, FR_ENOMEM, FR_EDEVICE = 0, -1, -2, -3
 FR_ESINGULAR, FR_ENOCONV, FR_EBREAKDOWN, FR_ENONFINITE = -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGULAR", -5: "ENOCONV",
                 -6: "EBREAKDOWN", -7: "ENONFINITE"}
-EPS_ABSOLUTE, EPS_NORMALIZED = 0, 1
+EPS_ABSOLUTE, EPS_NORMALIZED, EPS_SCALED = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_FP32_BF16 = 0, 1, 2
 COARSE_NONE, COARSE_EJ, COARSE_LEARNED = 0, 1, 2
-SCALE_LITERAL, SCALE_NORMALIZED = 0, 1
+SCALE_LITERAL, SCALE_NORMALIZED, SCALE_SCALED = 0, 1, 2
 SCHEME_ESDIRK, SCHEME_ROW = 0, 1
 PRECOND_EJ, PRECOND_PMG, PRECOND_PMG_LEARNED = 0, 1, 2
 MAX_LEVELS = 4
@@ -146,8 +146,8 @@ class StageConfig:
     n0: int = 2
     n1: int = 2
     eps: float = 1e-6
-    eps_mode: int = EPS_NORMALIZED
-    scale_mode: int = SCALE_NORMALIZED
+    eps_mode: int = EPS_SCALED
+    scale_mode: int = SCALE_SCALED
     eps_p: float = 1e-6
     skip_setup: int = 0
 
@@ -226,7 +226,7 @@ class FR:
         self._check("fr_residual", self.lib.fr_residual(self.ctx, level, _ptr(dq), _ptr(out), _stream()))
         return out
 
-    def jvp(self, level, dq, rq, v, shift, eps=1e-6, eps_mode=EPS_NORMALIZED, out=None):
+    def jvp(self, level, dq, rq, v, shift, eps=1e-6, eps_mode=EPS_SCALED, out=None):
         out = self.empty(level) if out is None else out
         self._check("fr_jvp", self.lib.fr_jvp(self.ctx, level, _ptr(dq), _ptr(rq), _ptr(v), float(shift),
                                               float(eps), int(eps_mode), _ptr(out), _stream()))
@@ -263,7 +263,7 @@ class FR:
         self._keep_point = (dq, rq)
         self._check("pmg_set_point", self.lib.pmg_set_point(self.ctx, _ptr(dq), _ptr(rq), _stream()))
 
-    def pmg_apply(self, x, sigma_D, n0=2, n1=2, coarse_mode=COARSE_EJ, scale_mode=SCALE_NORMALIZED, eps_p=1e-6,
+    def pmg_apply(self, x, sigma_D, n0=2, n1=2, coarse_mode=COARSE_EJ, scale_mode=SCALE_SCALED, eps_p=1e-6,
                   out=None):
         out = self.empty(0) if out is None else out
         prm = PmgParams(float(sigma_D), int(n0), int(n1), int(coarse_mode), int(scale_mode), float(eps_p))

@@ -105,6 +105,183 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
     if (singular && tid == 0) status[0] = 1;
 }
 
+// ---------------------------------------------------------------------------
+// Blocked in-place Gauss-Jordan for blocks too large for LDS (n_b > 140, e.g.
+// 320 x 320 in 3D at p = 3).  Panels of kPanel columns are eliminated in LDS
+// (pivot search over the full column, row swaps recorded); the product of the
+// panel's elementary transforms T = (I + W S^T) P (S = the panel's pivot rows)
+// is then applied to every other column at once as a GEMM:
+//     x <- (P x with the pivot rows zeroed) + T_panel (P x)_S,
+// where T_panel = the panel columns just written back.  After the last panel
+// the row interchanges are undone as column interchanges, last first.
+// ---------------------------------------------------------------------------
+constexpr int kPanel = 32;
+
+template <int dummy = 0>
+__global__ void __launch_bounds__(kGJThreads) k_gj_panel(int nb, int c0, int bw, double *__restrict__ A,
+                                                         int *__restrict__ perm, int *__restrict__ status) {
+    extern __shared__ double Pn[];  // [bw][nb] column-major panel
+    double *colk = Pn + (size_t)bw * nb;
+    __shared__ double s_v[kGJThreads / 64];
+    __shared__ int s_i[kGJThreads / 64];
+    __shared__ int s_piv;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double *Ak = A + (size_t)blockIdx.x * nb * nb;
+    for (int t = tid; t < bw * nb; t += nt) Pn[t] = Ak[(size_t)c0 * nb + t];
+    __syncthreads();
+    bool singular = false;
+    for (int cc = 0; cc < bw; ++cc) {
+        const int c = c0 + cc;
+        double best = -1.0;
+        int bi = 0x7fffffff;
+        for (int r = c + tid; r < nb; r += nt) argmax_combine(best, bi, fabs(Pn[cc * nb + r]), r);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double v2 = __shfl_down(best, off, 64);
+            const int i2 = __shfl_down(bi, off, 64);
+            argmax_combine(best, bi, v2, i2);
+        }
+        if ((tid & 63) == 0) {
+            s_v[tid >> 6] = best;
+            s_i[tid >> 6] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double bv = s_v[0];
+            int ii = s_i[0];
+            for (int w = 1; w < nt / 64; ++w) argmax_combine(bv, ii, s_v[w], s_i[w]);
+            s_piv = ii;
+            perm[(size_t)blockIdx.x * nb + c] = ii;
+        }
+        __syncthreads();
+        const int p = s_piv;
+        if (p != c) {
+            for (int j = tid; j < bw; j += nt) {
+                const double t0 = Pn[j * nb + c];
+                Pn[j * nb + c] = Pn[j * nb + p];
+                Pn[j * nb + p] = t0;
+            }
+        }
+        __syncthreads();
+        double d = Pn[cc * nb + c];
+        if (d == 0.0) {
+            singular = true;
+            d = 1.0;
+        }
+        const double inv = 1.0 / d;
+        for (int r = tid; r < nb; r += nt) colk[r] = Pn[cc * nb + r];
+        __syncthreads();
+        for (int j = tid; j < bw; j += nt) Pn[j * nb + c] = (j == cc ? 1.0 : Pn[j * nb + c]) * inv;
+        __syncthreads();
+        for (int t = tid; t < bw * nb; t += nt) {
+            const int j = t / nb, r = t - j * nb;
+            if (r == c) continue;
+            const double cur = (j == cc) ? 0.0 : Pn[t];
+            Pn[t] = cur - colk[r] * Pn[j * nb + c];
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < bw * nb; t += nt) Ak[(size_t)c0 * nb + t] = Pn[t];
+    if (singular && tid == 0) status[0] = 1;
+}
+
+constexpr int kUpdCols = 64;  // columns per update workgroup
+constexpr int kUpdRows = 64;  // rows per LDS chunk of T_panel
+
+// Apply the panel transform to the kUpdCols columns (outside the panel) of
+// one block: 256 lanes, each owns a 4 x 4 register tile of the output chunk.
+__global__ void __launch_bounds__(256) k_gj_update(int nb, int c0, int bw, double *__restrict__ A,
+                                                   const int *__restrict__ perm) {
+    __shared__ double xs[kPanel][kUpdCols];    // (P x)_S for the tile's columns
+    __shared__ double tp[kPanel][kUpdRows];    // T_panel rows chunk
+    const int tid = threadIdx.x;
+    const int k = blockIdx.x;
+    double *Ak = A + (size_t)k * nb * nb;
+    const int nrest = nb - bw;
+    const int ri = blockIdx.y * kUpdCols + (tid % kUpdCols);  // rest-column index of this lane (phase 1)
+    // phase 1: row interchanges on the tile's columns, then gather (P x)_S
+    if (tid < kUpdCols) {
+        if (ri < nrest) {
+            const int j = (ri < c0) ? ri : ri + bw;
+            double *x = Ak + (size_t)j * nb;
+            for (int cc = 0; cc < bw; ++cc) {
+                const int c = c0 + cc, p = perm[(size_t)k * nb + c];
+                if (p != c) {
+                    const double t0 = x[c];
+                    x[c] = x[p];
+                    x[p] = t0;
+                }
+            }
+            for (int cc = 0; cc < bw; ++cc) xs[cc][tid] = x[c0 + cc];
+        } else {
+            for (int cc = 0; cc < bw; ++cc) xs[cc][tid] = 0.0;
+        }
+    }
+    __syncthreads();
+    // phase 2: out[r][j] = (r in S ? 0 : x[r]) + sum_cc T[r][cc] xs[cc][j]
+    const int tr = (tid % 16) * 4;  // 4 rows
+    const int tc = (tid / 16) * 4;  // 4 columns
+    for (int r0 = 0; r0 < nb; r0 += kUpdRows) {
+        for (int t = tid; t < bw * kUpdRows; t += 256) {
+            const int cc = t / kUpdRows, rr = t % kUpdRows;
+            tp[cc][rr] = (r0 + rr < nb) ? Ak[(size_t)(c0 + cc) * nb + r0 + rr] : 0.0;
+        }
+        __syncthreads();
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int cc = 0; cc < bw; ++cc) {
+            double tv[4], xv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) tv[a] = tp[cc][tr + a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) xv[b] = xs[cc][tc + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += tv[a] * xv[b];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int rib = blockIdx.y * kUpdCols + tc + b;
+            if (rib >= nrest) continue;
+            const int j = (rib < c0) ? rib : rib + bw;
+            double *x = Ak + (size_t)j * nb;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int r = r0 + tr + a;
+                if (r >= nb) continue;
+                const bool inS = (r >= c0 && r < c0 + bw);
+                x[r] = (inS ? 0.0 : x[r]) + acc[a][b];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Undo the row interchanges as column interchanges, last first.
+__global__ void __launch_bounds__(256) k_gj_unscramble(int nb, double *__restrict__ A, const int *__restrict__ perm) {
+    double *Ak = A + (size_t)blockIdx.x * nb * nb;
+    for (int c = nb - 1; c >= 0; --c) {
+        const int p = perm[(size_t)blockIdx.x * nb + c];
+        if (p != c) {
+            for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+                const double t0 = Ak[(size_t)c * nb + r];
+                Ak[(size_t)c * nb + r] = Ak[(size_t)p * nb + r];
+                Ak[(size_t)p * nb + r] = t0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_to_float(size_t n, const double *__restrict__ a, float *__restrict__ b) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
+}
+
 constexpr int kApplyThreads = 256;
 
 template <typename T, int R>
@@ -206,7 +383,32 @@ hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, d
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
     Level &L = ctx->lv[level];
     const int nb = L.nb, Ne = ctx->mesh.Ne;
-    if (nb > kMaxLdsBlock) return hipErrorInvalidValue;
+    if (nb > kMaxLdsBlock) {
+        if (nb > 512 || !L.perm) return hipErrorInvalidValue;
+        const size_t lds_p = ((size_t)kPanel * nb + nb) * sizeof(double);
+        hipError_t e = hipFuncSetAttribute((const void *)k_gj_panel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_p);
+        if (e != hipSuccess) return e;
+        for (int c0 = 0; c0 < nb; c0 += kPanel) {
+            const int bw = min(kPanel, nb - c0);
+            hipLaunchKernelGGL(k_gj_panel<0>, dim3(Ne), dim3(kGJThreads), lds_p, s, nb, c0, bw, L.blk64, L.perm,
+                               L.dstatus);
+            const int nrest = nb - bw;
+            if (nrest > 0)
+                hipLaunchKernelGGL(k_gj_update, dim3(Ne, (nrest + kUpdCols - 1) / kUpdCols), dim3(256), 0, s, nb, c0,
+                                   bw, L.blk64, L.perm);
+        }
+        hipLaunchKernelGGL(k_gj_unscramble, dim3(Ne), dim3(256), 0, s, nb, L.blk64, L.perm);
+        if (precision == FR_PREC_FP64) {
+            L.inv = L.blk64;
+        } else {
+            const size_t n = (size_t)Ne * nb * nb;
+            hipLaunchKernelGGL(k_to_float, dim3(4096), dim3(256), 0, s, n, L.blk64, L.inv32);
+            L.inv = L.inv32;
+        }
+        L.inv_prec = precision;
+        return hipGetLastError();
+    }
     const size_t lds = ((size_t)nb * nb + nb) * sizeof(double);
     hipError_t e;
     if (precision == FR_PREC_FP64) {

@@ -72,7 +72,7 @@ int ipow(int b, int e) {
 }
 
 // ---- device scalars (slots of ctx->scal) ----
-enum { SC_JVP_H = 0, SC_JVP_N2 = 1, SC_PMG_S = 2, SC_PMG_INV = 3, SC_PMG_N2 = 4, SC_ONE = 5 };
+enum { SC_JVP_H = 0, SC_JVP_N2 = 1, SC_PMG_S = 2, SC_PMG_INV = 3, SC_PMG_N2 = 4, SC_DQ_N2 = 5, SC_PT_N2 = 6 };
 // ---- reduction outputs (slots of ctx->red_out) ----
 constexpr int RO_H1 = 0, RO_H2 = 64, RO_Y = 128, RO_N2 = 192, RO_SIZE = 256;
 
@@ -108,13 +108,23 @@ void residual_lin(frpmg_ctx *ctx, int level, const double *dq, const double *v, 
     HIPCHK(launch_residual(ctx, level, a, s));
 }
 
-// w = shift v - (R(dq + h v) - rq) / h
+// w = shift v - (R(dq + h v) - rq) / h.  dqn2: device ||dq||^2 for the
+// SCALED step (computed here when null).
 void jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const double *v, double shift,
-         double eps, int mode, double *w, hipStream_t s) {
+         double eps, int mode, double *w, hipStream_t s, const double *dqn2 = nullptr) {
     Scal h{eps, nullptr};
-    if (mode == FR_EPS_NORMALIZED) {
-        HIPCHK(vec_dot(ctx, ctx->lv[level].N, v, v, ctx->scal + SC_JVP_N2, s));
-        HIPCHK(scal_fd_step(ctx->scal + SC_JVP_N2, eps, ctx->scal + SC_JVP_H, s));
+    const size_t N = ctx->lv[level].N;
+    if (mode == FR_EPS_NORMALIZED || mode == FR_EPS_SCALED) {
+        HIPCHK(vec_dot(ctx, N, v, v, ctx->scal + SC_JVP_N2, s));
+        const double *size = nullptr;
+        if (mode == FR_EPS_SCALED) {
+            if (!dqn2) {
+                HIPCHK(vec_dot(ctx, N, dq, dq, ctx->scal + SC_DQ_N2, s));
+                dqn2 = ctx->scal + SC_DQ_N2;
+            }
+            size = dqn2;
+        }
+        HIPCHK(scal_fd_step(ctx->scal + SC_JVP_N2, size, eps, ctx->scal + SC_JVP_H, s));
         h = Scal{0.0, ctx->scal + SC_JVP_H};
     }
     residual_lin(ctx, level, dq, v, h, rq, shift, nullptr, w, s);
@@ -130,9 +140,14 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
     REQUIRE(precision >= FR_PREC_FP64 && precision <= FR_PREC_FP32_BF16, "bad precision");
     check_even(ctx);
     Level &L = ctx->lv[level];
-    REQUIRE(L.nb <= 140, "EJ block too large for this build (n_b > 140)");
+    REQUIRE(L.nb <= 512, "EJ block too large (n_b > 512)");
     const size_t nblk = (size_t)ctx->mesh.Ne * L.nb * L.nb;
     if (!L.blk64) L.blk64 = dalloc(ctx, nblk);
+    if (L.nb > 140 && !L.perm) {
+        void *p = nullptr;
+        HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * L.nb * sizeof(int)));
+        L.perm = (int *)p;
+    }
     if (precision != FR_PREC_FP64 && !L.inv32) {
         void *p = nullptr;
         HIPCHK(hipMalloc(&p, nblk * sizeof(float)));
@@ -176,6 +191,7 @@ struct Counters {
 void pmg_point(frpmg_ctx *ctx, const double *dq, const double *rq, hipStream_t s) {
     ctx->pt_q = dq;
     ctx->pt_rq = rq;
+    HIPCHK(vec_dot(ctx, ctx->lv[0].N, dq, dq, ctx->scal + SC_PT_N2, s));
     if (ctx->nlevels > 1) {
         HIPCHK(transfer_apply(ctx, 0, true, dq, ctx->q1, s));
         residual(ctx, 1, ctx->q1, ctx->r1, s);
@@ -198,10 +214,10 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
     const Scal one{1.0, nullptr};
     const double *Xs = x;
     Scal inv_s{1.0, nullptr};
-    if (p.scale_mode == FR_SCALE_NORMALIZED) {
+    if (p.scale_mode == FR_SCALE_NORMALIZED || p.scale_mode == FR_SCALE_SCALED) {
         HIPCHK(vec_dot(ctx, N0, x, x, ctx->scal + SC_PMG_N2, s));
-        HIPCHK(scal_pmg_scale(ctx->scal + SC_PMG_N2, p.eps_p, p.sigma_D, ctx->scal + SC_PMG_S,
-                              ctx->scal + SC_PMG_INV, s));
+        HIPCHK(scal_pmg_scale(ctx->scal + SC_PMG_N2, p.scale_mode == FR_SCALE_SCALED ? ctx->scal + SC_PT_N2 : nullptr,
+                              p.eps_p, p.sigma_D, ctx->scal + SC_PMG_S, ctx->scal + SC_PMG_INV, s));
         HIPCHK(vec_scale_copy(N0, Scal{0.0, ctx->scal + SC_PMG_S}, x, ctx->wXs, s));
         Xs = ctx->wXs;
         inv_s = Scal{0.0, ctx->scal + SC_PMG_INV};
@@ -449,8 +465,9 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
                 cnt.R1++;
             }
             HIPCHK(vec_axpby(N, Scal{0.0, nullptr}, nullptr, Scal{-1.0, nullptr}, F, s));  // F <- -F
+            HIPCHK(vec_dot(ctx, N, q, q, ctx->scal + SC_DQ_N2, s));
             auto A = [&](const double *z, double *w) {
-                jvp(ctx, 0, q, rq, z, sigma_A, P.eps, P.eps_mode, w, s);
+                jvp(ctx, 0, q, rq, z, sigma_A, P.eps, P.eps_mode, w, s, ctx->scal + SC_DQ_N2);
                 cnt.R0++;
             };
             KrylovResult kr = fgmres(ctx, N, F, dx, P.m, P.eta, P.max_restarts, A, prec, s);
@@ -482,8 +499,9 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
             pmg_point(ctx, dq_n, R0, s);
             cnt.R1++;
         }
+        HIPCHK(vec_dot(ctx, N, dq_n, dq_n, ctx->scal + SC_DQ_N2, s));
         auto A = [&](const double *z, double *wout) {
-            jvp(ctx, 0, dq_n, R0, z, sigma_A, P.eps, P.eps_mode, wout, s);
+            jvp(ctx, 0, dq_n, R0, z, sigma_A, P.eps, P.eps_mode, wout, s, ctx->scal + SC_DQ_N2);
             cnt.R0++;
         };
         KrylovResult kr = fgmres(ctx, N, R0, out, P.m, P.tol, P.max_restarts, A, prec, s);
@@ -526,6 +544,7 @@ void destroy_all(frpmg_ctx *ctx) {
         dfree(L.blk64);
         dfree(L.inv32);
         dfree(L.dstatus);
+        dfree(L.perm);
         dfree(L.r0);
     }
     for (int a = 0; a < 3; ++a) dfree(ctx->inv2h[a]);
@@ -674,7 +693,7 @@ fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, 
         REQUIRE(dq && rq && v && w, "null pointer");
         REQUIRE(w != dq && w != rq && w != v, "w must not alias the inputs");
         REQUIRE(eps > 0.0, "eps must be positive");
-        REQUIRE(eps_mode == FR_EPS_ABSOLUTE || eps_mode == FR_EPS_NORMALIZED, "bad eps_mode");
+        REQUIRE(eps_mode >= FR_EPS_ABSOLUTE && eps_mode <= FR_EPS_SCALED, "bad eps_mode");
         jvp(ctx, level, dq, rq, v, shift, eps, eps_mode, w, S(stream));
     });
 }

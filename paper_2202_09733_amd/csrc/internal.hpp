@@ -87,6 +87,7 @@ struct Level {
     float *inv32 = nullptr;
     int inv_prec = -1;
     int *dstatus = nullptr;   // device flag: 1 = zero pivot seen
+    int *perm = nullptr;      // pivot rows of the blocked inversion [Ne][nb]
     double *r0 = nullptr;     // scratch: R at the EJ linearisation point
 };
 
@@ -146,11 +147,12 @@ hipError_t vec_fill(size_t n, double v, double *y, hipStream_t s);
 // out = (x - b) * c - r   (stage function)
 hipError_t vec_stage_F(size_t n, const double *x, const double *b, double c, const double *r, double *out,
                        hipStream_t s);
-// d_out[k] = eps / sqrt(d_in[k]) if d_in[k] > 0 else eps  (FD step from a squared norm)
-hipError_t scal_fd_step(const double *sumsq, double eps, double *hout, hipStream_t s);
-// d_out = num * sigma / sqrt(sumsq) and its inverse (preconditioner scaling)
-hipError_t scal_pmg_scale(const double *sumsq, double eps_p, double sigma, double *s_out, double *inv_out,
-                          hipStream_t s);
+// FD step h = eps (1 + ||dq||) / ||v|| from squared norms on the device
+// (dqn2 = null drops the state size)
+hipError_t scal_fd_step(const double *vn2, const double *dqn2, double eps, double *hout, hipStream_t s);
+// preconditioner scale s = eps_p sigma (1 + ||q||) / ||X|| and 1/s (qn2 = null drops the state size)
+hipError_t scal_pmg_scale(const double *xn2, const double *qn2, double eps_p, double sigma, double *s_out,
+                          double *inv_out, hipStream_t s);
 hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_dir, const double *x,
                           double *y, hipStream_t s);
 

@@ -109,14 +109,19 @@ __global__ void __launch_bounds__(kThreads) k_stage_F(size_t n, const double *__
         out[i] = (x[i] - b[i]) * c - r[i];
 }
 
-__global__ void k_fd_step(const double *sumsq, double eps, double *hout) {
-    const double s = *sumsq;
-    *hout = (s > 0.0) ? eps / sqrt(s) : eps;
+// h = eps (1 + ||dq||) / ||v||  (dqn2 = null: h = eps / ||v||)
+__global__ void k_fd_step(const double *vn2, const double *dqn2, double eps, double *hout) {
+    const double s = *vn2;
+    const double size = dqn2 ? 1.0 + sqrt(*dqn2) : 1.0;
+    *hout = (s > 0.0) ? eps * size / sqrt(s) : eps;
 }
 
-__global__ void k_pmg_scale(const double *sumsq, double eps_p, double sigma, double *s_out, double *inv_out) {
-    const double nrm = sqrt(*sumsq);
-    const double s = (nrm > 0.0) ? eps_p * sigma / nrm : 1.0;
+// s = eps_p sigma (1 + ||q||) / ||X||  (qn2 = null: without the state size)
+__global__ void k_pmg_scale(const double *xn2, const double *qn2, double eps_p, double sigma, double *s_out,
+                            double *inv_out) {
+    const double nrm = sqrt(*xn2);
+    const double size = qn2 ? 1.0 + sqrt(*qn2) : 1.0;
+    const double s = (nrm > 0.0) ? eps_p * sigma * size / nrm : 1.0;
     *s_out = s;
     *inv_out = 1.0 / s;
 }
@@ -209,14 +214,14 @@ hipError_t vec_stage_F(size_t n, const double *x, const double *b, double c, con
     return hipGetLastError();
 }
 
-hipError_t scal_fd_step(const double *sumsq, double eps, double *hout, hipStream_t s) {
-    hipLaunchKernelGGL(k_fd_step, dim3(1), dim3(1), 0, s, sumsq, eps, hout);
+hipError_t scal_fd_step(const double *vn2, const double *dqn2, double eps, double *hout, hipStream_t s) {
+    hipLaunchKernelGGL(k_fd_step, dim3(1), dim3(1), 0, s, vn2, dqn2, eps, hout);
     return hipGetLastError();
 }
 
-hipError_t scal_pmg_scale(const double *sumsq, double eps_p, double sigma, double *s_out, double *inv_out,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_pmg_scale, dim3(1), dim3(1), 0, s, sumsq, eps_p, sigma, s_out, inv_out);
+hipError_t scal_pmg_scale(const double *xn2, const double *qn2, double eps_p, double sigma, double *s_out,
+                          double *inv_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pmg_scale, dim3(1), dim3(1), 0, s, xn2, qn2, eps_p, sigma, s_out, inv_out);
     return hipGetLastError();
 }
 
