@@ -187,6 +187,9 @@ typedef struct {
     int scale_mode;    /* FR_SCALE_* of the preconditioner */
     double eps_p;      /* preconditioner scale */
     int skip_setup;    /* 1: reuse the EJ factors already in the context */
+    int stall_window;  /* FR_PRECOND_PMG_LEARNED: fall back to plain pMG when the FGMRES residual */
+    double stall_ratio; /*   estimate exceeds stall_ratio x its value stall_window iterations earlier
+                             (0: defaults 5 and 0.7); the fallback holds for the rest of the stage */
 } stage_params;
 
 #define FR_MAX_NEWTON_LOG 128
@@ -216,6 +219,81 @@ typedef struct {
  * when the caps are reached, FR_ENONFINITE on a NaN/Inf norm. */
 fr_status gmres_solve_stage(frpmg_ctx *ctx, const stage_params *prm, const double *dq_n, double *out,
                             stage_stats *stats, fr_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Learned coarse correction (not in the paper): an element-local, bias-free
+ * ReLU network in -> 256 -> 256 -> out refines the element-local coarse EJ
+ * step.  With C1 = B1^{-1} Gamma d (one coarse EJ application to the
+ * restricted defect), the input row of an element is C1 on the element plus
+ * the traces of C1 of its 2 dim face neighbours (standardised per variable,
+ * divided by the row norm s) followed by dim geometry entries
+ * ln(h_a / max h_a); the coarse correction is
+ *   C = C1 + tau s (N(x, g) - N(-x, g)) / 2,
+ * exactly positive-homogeneous and odd in the defect.  It replaces the coarse
+ * smoothing sweeps of the V-cycle (FR_COARSE_LEARNED); the training target is
+ * what target_sweeps coarse EJ sweeps add to C1.  Products run on BF16 MFMA
+ * with FP32 accumulation; FP32 master weights, Adam.
+ * Feature row layout: [own (nv Np1, index v Np1 + i) | for each axis a:
+ * the -a neighbour's trace at its + end, then the +a neighbour's trace at its
+ * - end (nv NF1 each, index v NF1 + f) | geometry (dim)], zero padded to
+ * nin_pad.
+ * Weight layout (FP32, row-major): W1 [256 x nin_pad] | W2 [256 x 256] |
+ * W3 [nout_pad x 256].
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int enable;         /* 1: record pairs in every FR_COARSE_EJ V-cycle; 0: stop */
+    int max_pairs;      /* harvest buffer rows (allocated at the first enable) */
+    int stride;         /* record every stride-th element of a V-cycle; the offset rotates per cycle */
+    int target_sweeps;  /* coarse EJ sweeps that define the target correction (>= n1) */
+    int reset;          /* 1: discard pairs harvested so far (and the input/output scales) */
+} lcc_harvest_params;
+
+/* Turn harvesting on or off.  Pairs: (features of C1, Ct - C1) with Ct the
+ * coarse correction after target_sweeps EJ sweeps on the coarse FAS equation
+ * (the V-cycle itself keeps using n1 sweeps).  The first harvested V-cycle
+ * fixes the per-variable input and output scales (RMS over the mesh). */
+fr_status lcc_harvest(frpmg_ctx *ctx, const lcc_harvest_params *prm);
+int lcc_harvest_count(const frpmg_ctx *ctx);
+
+typedef struct {
+    int epochs;
+    int batch;        /* multiple of 32 */
+    double lr;        /* Adam step size */
+    uint64_t seed;    /* shuffling (and re-initialisation) */
+    double holdout;   /* fraction of the harvested rows kept out of training (the last ones) */
+    int reinit;       /* 1: re-initialise the weights from seed before training */
+} lcc_train_params;
+
+typedef struct {
+    int steps;
+    double loss_first, loss_last, val_loss, val_loss_init, t_train;
+} lcc_train_stats;
+
+/* Train on the harvested pairs (loss 0.5 ||N(x) - t||^2 averaged over the
+ * batch), synchronous. */
+fr_status lcc_train(frpmg_ctx *ctx, const lcc_train_params *prm, lcc_train_stats *st, fr_stream stream);
+
+/* Dimensions (allocates the network on first use). */
+fr_status lcc_dims(frpmg_ctx *ctx, int *nin, int *nin_pad, int *nh, int *nout, int *nout_pad);
+size_t lcc_num_weights(frpmg_ctx *ctx);
+/* Host copies of the FP32 master weights (n = lcc_num_weights); setting them
+ * also refreshes the BF16 copies and resets the Adam moments. */
+fr_status lcc_get_weights(frpmg_ctx *ctx, float *host, size_t n);
+fr_status lcc_set_weights(frpmg_ctx *ctx, const float *host, size_t n);
+/* Per-variable input and output scales (dim + 2 floats each, host). */
+fr_status lcc_get_scales(frpmg_ctx *ctx, float *in_scale, float *out_scale);
+fr_status lcc_set_scales(frpmg_ctx *ctx, const float *in_scale, const float *out_scale);
+
+/* Test hooks (device pointers).  Y = N(X) for rows (multiple of 32) of
+ * normalised inputs X [rows x nin_pad] -> Y [rows x nout_pad]; loss and
+ * gradient (layout as the weights) of a batch (X, T [rows x nout_pad]); the
+ * feature rows [Ne x nin_pad] and norms s [Ne] of a level-1 field d1 (the
+ * field itself stands in for C1). */
+fr_status lcc_forward(frpmg_ctx *ctx, const float *X, int rows, float *Y, fr_stream stream);
+fr_status lcc_loss_grad(frpmg_ctx *ctx, const float *X, const float *T, int rows, double *loss, float *grad,
+                        fr_stream stream);
+fr_status lcc_features_of(frpmg_ctx *ctx, const double *d1, float *rows_out, float *s_out, fr_stream stream);
 
 #ifdef __cplusplus
 }

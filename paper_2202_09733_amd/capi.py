@@ -31,7 +31,9 @@ MAX_NEWTON_LOG = 128
 
 EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_residual", "fr_jvp", "ej_factor",
            "ej_solve", "ej_get_inverse", "pmg_restrict", "pmg_prolong", "pmg_set_point", "pmg_precond_apply",
-           "gmres_solve_stage"]
+           "gmres_solve_stage", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
+           "lcc_get_weights", "lcc_set_weights", "lcc_get_scales", "lcc_set_scales", "lcc_forward",
+           "lcc_loss_grad", "lcc_features_of"]
 
 
 class FRError(RuntimeError):
@@ -59,7 +61,22 @@ class StageParams(ctypes.Structure):
                 ("max_ptc", ctypes.c_int), ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("n0", ctypes.c_int), ("n1", ctypes.c_int), ("eps", ctypes.c_double),
                 ("eps_mode", ctypes.c_int), ("scale_mode", ctypes.c_int), ("eps_p", ctypes.c_double),
-                ("skip_setup", ctypes.c_int)]
+                ("skip_setup", ctypes.c_int), ("stall_window", ctypes.c_int), ("stall_ratio", ctypes.c_double)]
+
+
+class LccHarvestParams(ctypes.Structure):
+    _fields_ = [("enable", ctypes.c_int), ("max_pairs", ctypes.c_int), ("stride", ctypes.c_int),
+                ("target_sweeps", ctypes.c_int), ("reset", ctypes.c_int)]
+
+
+class LccTrainParams(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("holdout", ctypes.c_double), ("reinit", ctypes.c_int)]
+
+
+class LccTrainStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("val_loss", ctypes.c_double), ("val_loss_init", ctypes.c_double), ("t_train", ctypes.c_double)]
 
 
 class StageStats(ctypes.Structure):
@@ -109,9 +126,24 @@ def load():
     L.pmg_set_point.argtypes = [vp, vp, vp, vp]
     L.pmg_precond_apply.argtypes = [vp, ctypes.POINTER(PmgParams), vp, vp, vp]
     L.gmres_solve_stage.argtypes = [vp, ctypes.POINTER(StageParams), vp, vp, ctypes.POINTER(StageStats), vp]
+    ip = ctypes.POINTER(ctypes.c_int)
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.lcc_harvest.argtypes = [vp, ctypes.POINTER(LccHarvestParams)]
+    L.lcc_harvest_count.argtypes = [vp]
+    L.lcc_train.argtypes = [vp, ctypes.POINTER(LccTrainParams), ctypes.POINTER(LccTrainStats), vp]
+    L.lcc_dims.argtypes = [vp, ip, ip, ip, ip, ip]
+    L.lcc_num_weights.argtypes = [vp]
+    L.lcc_num_weights.restype = ctypes.c_size_t
+    L.lcc_get_weights.argtypes = [vp, fp, ctypes.c_size_t]
+    L.lcc_set_weights.argtypes = [vp, fp, ctypes.c_size_t]
+    L.lcc_get_scales.argtypes = [vp, fp, fp]
+    L.lcc_set_scales.argtypes = [vp, fp, fp]
+    L.lcc_forward.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+    L.lcc_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp, vp]
+    L.lcc_features_of.argtypes = [vp, vp, vp, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("fr_destroy", "fr_last_error", "fr_level_size"):
+        if name not in ("fr_destroy", "fr_last_error", "fr_level_size", "lcc_num_weights"):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -126,6 +158,13 @@ def _ptr(t):
     import torch
     assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), \
         "expected a contiguous float64 CUDA tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _fptr(t):
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), \
+        "expected a contiguous float32 CUDA tensor"
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -150,6 +189,8 @@ class StageConfig:
     scale_mode: int = SCALE_SCALED
     eps_p: float = 1e-6
     skip_setup: int = 0
+    stall_window: int = 0
+    stall_ratio: float = 0.0
 
     def to_c(self):
         return StageParams(**{f[0]: getattr(self, f[0]) for f in StageParams._fields_})
@@ -270,6 +311,93 @@ class FR:
         self._check("pmg_precond_apply", self.lib.pmg_precond_apply(self.ctx, ctypes.byref(prm), _ptr(x),
                                                                     _ptr(out), _stream()))
         return out
+
+    # -- learned coarse correction ---------------------------------------------
+    def lcc_dims(self):
+        v = [ctypes.c_int() for _ in range(5)]
+        self._check("lcc_dims", self.lib.lcc_dims(self.ctx, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["nin", "nin_pad", "nh", "nout", "nout_pad"], [x.value for x in v]))
+
+    def lcc_harvest(self, enable=1, max_pairs=100000, stride=8, target_sweeps=8, reset=0):
+        prm = LccHarvestParams(int(enable), int(max_pairs), int(stride), int(target_sweeps), int(reset))
+        self._check("lcc_harvest", self.lib.lcc_harvest(self.ctx, ctypes.byref(prm)))
+
+    def lcc_count(self):
+        return int(self.lib.lcc_harvest_count(self.ctx))
+
+    def lcc_train(self, epochs=20, batch=256, lr=1e-3, seed=7, holdout=0.1, reinit=0):
+        prm = LccTrainParams(int(epochs), int(batch), float(lr), int(seed), float(holdout), int(reinit))
+        st = LccTrainStats()
+        self._check("lcc_train", self.lib.lcc_train(self.ctx, ctypes.byref(prm), ctypes.byref(st), _stream()))
+        return {f[0]: getattr(st, f[0]) for f in LccTrainStats._fields_}
+
+    def _wshapes(self):
+        d = self.lcc_dims()
+        return [(d["nh"], d["nin_pad"]), (d["nh"], d["nh"]), (d["nout_pad"], d["nh"])]
+
+    def lcc_get_weights(self):
+        n = int(self.lib.lcc_num_weights(self.ctx))
+        buf = np.empty(n, dtype=np.float32)
+        self._check("lcc_get_weights", self.lib.lcc_get_weights(
+            self.ctx, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n))
+        out, off = [], 0
+        for r, c in self._wshapes():
+            out.append(buf[off:off + r * c].reshape(r, c).copy())
+            off += r * c
+        return out
+
+    def lcc_set_weights(self, Ws):
+        buf = np.ascontiguousarray(np.concatenate([np.asarray(w, dtype=np.float32).reshape(-1) for w in Ws]))
+        self._check("lcc_set_weights", self.lib.lcc_set_weights(
+            self.ctx, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), buf.size))
+
+    def lcc_get_scales(self):
+        a = np.zeros(self.nv, dtype=np.float32)
+        b = np.zeros(self.nv, dtype=np.float32)
+        self._check("lcc_get_scales", self.lib.lcc_get_scales(
+            self.ctx, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            b.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return a, b
+
+    def lcc_set_scales(self, in_scale, out_scale):
+        a = np.ascontiguousarray(in_scale, dtype=np.float32)
+        b = np.ascontiguousarray(out_scale, dtype=np.float32)
+        self._check("lcc_set_scales", self.lib.lcc_set_scales(
+            self.ctx, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            b.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def lcc_forward(self, X):
+        import torch
+        d = self.lcc_dims()
+        Xd = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float32), device=self.device).contiguous()
+        Y = torch.empty((X.shape[0], d["nout_pad"]), dtype=torch.float32, device=self.device)
+        self._check("lcc_forward", self.lib.lcc_forward(self.ctx, _fptr(Xd), int(X.shape[0]), _fptr(Y), _stream()))
+        return Y.cpu().numpy()
+
+    def lcc_loss_grad(self, X, T):
+        import torch
+        Xd = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float32), device=self.device).contiguous()
+        Td = torch.as_tensor(np.ascontiguousarray(T, dtype=np.float32), device=self.device).contiguous()
+        n = int(self.lib.lcc_num_weights(self.ctx))
+        g = torch.empty(n, dtype=torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        self._check("lcc_loss_grad", self.lib.lcc_loss_grad(self.ctx, _fptr(Xd), _fptr(Td), int(X.shape[0]),
+                                                            ctypes.byref(loss), _fptr(g), _stream()))
+        gh = g.cpu().numpy()
+        out, off = [], 0
+        for r, c in self._wshapes():
+            out.append(gh[off:off + r * c].reshape(r, c).copy())
+            off += r * c
+        return loss.value, out
+
+    def lcc_features_of(self, d1):
+        import torch
+        d = self.lcc_dims()
+        rows = torch.empty((self.Ne, d["nin_pad"]), dtype=torch.float32, device=self.device)
+        s = torch.empty(self.Ne, dtype=torch.float32, device=self.device)
+        self._check("lcc_features_of", self.lib.lcc_features_of(self.ctx, _ptr(d1), _fptr(rows), _fptr(s),
+                                                                _stream()))
+        return rows.cpu().numpy(), s.cpu().numpy()
 
     def solve_stage(self, cfg: StageConfig, dq_n, out=None, raise_on_noconv=True):
         out = self.empty(0) if out is None else out

@@ -11,8 +11,11 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <functional>
+#include <random>
 
 #include "internal.hpp"
+#include "lcc.hpp"
 
 using namespace frpmg;
 
@@ -180,6 +183,181 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// learned coarse correction: buffers, forward pass, training step
+// ---------------------------------------------------------------------------
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+template <typename T>
+T *talloc(frpmg_ctx *ctx, size_t n) {
+    void *p = nullptr;
+    HIPCHK(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)));
+    return (T *)p;
+}
+
+void lcc_init_weights(frpmg_ctx *ctx, uint64_t seed) {
+    Lcc &L = *ctx->lcc;
+    std::mt19937_64 rng(seed);
+    for (int l = 0; l < 3; ++l) {
+        const int rows = L.wrows[l], cols = L.wcols[l];
+        const int fan_in = (l == 0) ? L.nin : L.nh;
+        const int live_rows = (l == 2) ? L.nout : rows;
+        const int live_cols = (l == 0) ? L.nin : cols;
+        const double sd = std::sqrt(2.0 / fan_in) * (l == 2 ? 0.5 : 1.0);
+        std::normal_distribution<double> nd(0.0, sd);
+        std::vector<float> w((size_t)rows * cols, 0.f);
+        for (int r = 0; r < live_rows; ++r)
+            for (int q = 0; q < live_cols; ++q) w[(size_t)r * cols + q] = (float)nd(rng);
+        HIPCHK(hipMemcpy(L.W[l], w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(hipMemset(L.Mo[l], 0, w.size() * sizeof(float)));
+        HIPCHK(hipMemset(L.Vo[l], 0, w.size() * sizeof(float)));
+        HIPCHK(lcc_to_bf(w.size(), L.W[l], L.Wb[l], nullptr));
+    }
+    L.adam_step = 0;
+    HIPCHK(hipDeviceSynchronize());
+}
+
+void lcc_alloc(frpmg_ctx *ctx) {
+    if (ctx->lcc) return;
+    REQUIRE(ctx->nlevels > 1, "the learned correction needs two levels");
+    Lcc *Lp = new Lcc();
+    ctx->lcc = Lp;
+    Lcc &L = *Lp;
+    const Level &C = ctx->lv[1];
+    L.ngeo = ctx->dim;
+    L.nin = C.nb + 2 * ctx->dim * ctx->nv * C.NF + L.ngeo;
+    L.nin_pad = round_up(L.nin, 32);
+    L.nout = C.nb;
+    L.nout_pad = round_up(L.nout, 32);
+    L.wrows[0] = L.nh; L.wcols[0] = L.nin_pad;
+    L.wrows[1] = L.nh; L.wcols[1] = L.nh;
+    L.wrows[2] = L.nout_pad; L.wcols[2] = L.nh;
+    for (int l = 0; l < 3; ++l) {
+        const size_t n = (size_t)L.wrows[l] * L.wcols[l];
+        L.W[l] = talloc<float>(ctx, n);
+        L.G[l] = talloc<float>(ctx, n);
+        L.Mo[l] = talloc<float>(ctx, n);
+        L.Vo[l] = talloc<float>(ctx, n);
+        L.Wb[l] = talloc<__bf16>(ctx, n);
+        L.WbT[l] = talloc<__bf16>(ctx, n);
+    }
+    for (int a = 0; a < ctx->dim; ++a) {
+        std::vector<double> ih(ctx->mesh.n[a]);
+        HIPCHK(hipMemcpy(ih.data(), ctx->inv2h[a], ih.size() * sizeof(double), hipMemcpyDeviceToHost));
+        double hm = 0.0;
+        for (double x : ih) hm = std::max(hm, 2.0 / x);
+        L.hmax[a] = hm;
+    }
+    L.in_scale = talloc<float>(ctx, 8);
+    L.out_scale = talloc<float>(ctx, 8);
+    const int Ne = ctx->mesh.Ne;
+    L.Mpad = round_up(2 * Ne, 32);
+    L.Xf = talloc<float>(ctx, (size_t)Ne * L.nin_pad);
+    L.Tf = talloc<float>(ctx, (size_t)Ne * L.nout_pad);
+    L.srow = talloc<float>(ctx, Ne);
+    L.Xb = talloc<__bf16>(ctx, (size_t)L.Mpad * L.nin_pad);
+    HIPCHK(hipMemset(L.Xb, 0, (size_t)L.Mpad * L.nin_pad * sizeof(__bf16)));
+    L.H1 = talloc<__bf16>(ctx, (size_t)L.Mpad * L.nh);
+    L.H2 = talloc<__bf16>(ctx, (size_t)L.Mpad * L.nh);
+    L.Y = talloc<float>(ctx, (size_t)L.Mpad * L.nout_pad);
+    L.dtmp = dalloc(ctx, C.N);
+    L.Cuse = dalloc(ctx, C.N);
+    L.lpart = dalloc(ctx, 64);
+    L.lval = dalloc(ctx, 8);
+    lcc_init_weights(ctx, 0x5eed1234ULL);
+}
+
+void lcc_free(frpmg_ctx *ctx) {
+    if (!ctx->lcc) return;
+    Lcc &L = *ctx->lcc;
+    for (int l = 0; l < 3; ++l) {
+        dfree(L.W[l]); dfree(L.G[l]); dfree(L.Mo[l]); dfree(L.Vo[l]); dfree(L.Wb[l]); dfree(L.WbT[l]);
+    }
+    void *bufs[] = {L.in_scale, L.out_scale, L.HX, L.HT, L.Xf, L.Tf, L.srow, L.Y, L.Xb, L.H1, L.H2, L.dtmp, L.Cuse,
+                    L.bX, L.bXT, L.bH1, L.bH1T, L.bH2, L.bH2T, L.bdY, L.bdYT, L.bdH2, L.bdH2T, L.bdH1, L.bdH1T,
+                    L.bY, L.bT, L.perm, L.lpart, L.lval};
+    for (void *b : bufs) dfree(b);
+    delete ctx->lcc;
+    ctx->lcc = nullptr;
+}
+
+void lcc_train_buffers(frpmg_ctx *ctx, int B) {
+    Lcc &L = *ctx->lcc;
+    if (L.B == B) return;
+    void *bufs[] = {L.bX, L.bXT, L.bH1, L.bH1T, L.bH2, L.bH2T, L.bdY, L.bdYT, L.bdH2, L.bdH2T, L.bdH1, L.bdH1T,
+                    L.bY, L.bT};
+    for (void *b : bufs) dfree(b);
+    L.B = B;
+    L.bX = talloc<__bf16>(ctx, (size_t)B * L.nin_pad);
+    L.bXT = talloc<__bf16>(ctx, (size_t)B * L.nin_pad);
+    L.bH1 = talloc<__bf16>(ctx, (size_t)B * L.nh);
+    L.bH1T = talloc<__bf16>(ctx, (size_t)B * L.nh);
+    L.bH2 = talloc<__bf16>(ctx, (size_t)B * L.nh);
+    L.bH2T = talloc<__bf16>(ctx, (size_t)B * L.nh);
+    L.bdY = talloc<__bf16>(ctx, (size_t)B * L.nout_pad);
+    L.bdYT = talloc<__bf16>(ctx, (size_t)B * L.nout_pad);
+    L.bdH2 = talloc<__bf16>(ctx, (size_t)B * L.nh);
+    L.bdH2T = talloc<__bf16>(ctx, (size_t)B * L.nh);
+    L.bdH1 = talloc<__bf16>(ctx, (size_t)B * L.nh);
+    L.bdH1T = talloc<__bf16>(ctx, (size_t)B * L.nh);
+    L.bY = talloc<float>(ctx, (size_t)B * L.nout_pad);
+    L.bT = talloc<float>(ctx, (size_t)B * L.nout_pad);
+}
+
+// H1 = relu(X W1^T), H2 = relu(H1 W2^T), Y = H2 W3^T for M rows
+void lcc_forward_rows(frpmg_ctx *ctx, int M, const __bf16 *X, __bf16 *H1, __bf16 *H2, float *Y, hipStream_t s) {
+    Lcc &L = *ctx->lcc;
+    HIPCHK(lcc_gemm(LCC_EP_RELU, M, L.nh, L.nin_pad, X, L.nin_pad, L.Wb[0], L.nin_pad, nullptr, H1, L.nh, nullptr,
+                    1.f, s));
+    HIPCHK(lcc_gemm(LCC_EP_RELU, M, L.nh, L.nh, H1, L.nh, L.Wb[1], L.nh, nullptr, H2, L.nh, nullptr, 1.f, s));
+    HIPCHK(lcc_gemm(LCC_EP_F32, M, L.nout_pad, L.nh, H2, L.nh, L.Wb[2], L.nh, Y, nullptr, L.nout_pad, nullptr, 1.f,
+                    s));
+}
+
+// loss and gradients of one batch already in L.bX / L.bT (B rows)
+void lcc_batch_grad(frpmg_ctx *ctx, hipStream_t s) {
+    Lcc &L = *ctx->lcc;
+    const int B = L.B;
+    lcc_forward_rows(ctx, B, L.bX, L.bH1, L.bH2, L.bY, s);
+    HIPCHK(lcc_loss_grad(B, L.nout_pad, L.nout, L.bY, L.bT, L.bdY, L.lpart, L.lval, s));
+    // dW3 = dY^T H2
+    HIPCHK(lcc_transpose(B, L.nout_pad, L.bdY, L.nout_pad, L.bdYT, B, s));
+    HIPCHK(lcc_transpose(B, L.nh, L.bH2, L.nh, L.bH2T, B, s));
+    HIPCHK(lcc_gemm(LCC_EP_F32, L.nout_pad, L.nh, B, L.bdYT, B, L.bH2T, B, L.G[2], nullptr, L.nh, nullptr, 1.f, s));
+    // dH2 = (dY W3) * [H2 > 0]
+    HIPCHK(lcc_transpose(L.nout_pad, L.nh, L.Wb[2], L.nh, L.WbT[2], L.nout_pad, s));
+    HIPCHK(lcc_gemm(LCC_EP_MASK, B, L.nh, L.nout_pad, L.bdY, L.nout_pad, L.WbT[2], L.nout_pad, nullptr, L.bdH2, L.nh,
+                    L.bH2, 1.f, s));
+    // dW2 = dH2^T H1
+    HIPCHK(lcc_transpose(B, L.nh, L.bdH2, L.nh, L.bdH2T, B, s));
+    HIPCHK(lcc_transpose(B, L.nh, L.bH1, L.nh, L.bH1T, B, s));
+    HIPCHK(lcc_gemm(LCC_EP_F32, L.nh, L.nh, B, L.bdH2T, B, L.bH1T, B, L.G[1], nullptr, L.nh, nullptr, 1.f, s));
+    // dH1 = (dH2 W2) * [H1 > 0]
+    HIPCHK(lcc_transpose(L.nh, L.nh, L.Wb[1], L.nh, L.WbT[1], L.nh, s));
+    HIPCHK(lcc_gemm(LCC_EP_MASK, B, L.nh, L.nh, L.bdH2, L.nh, L.WbT[1], L.nh, nullptr, L.bdH1, L.nh, L.bH1, 1.f, s));
+    // dW1 = dH1^T X
+    HIPCHK(lcc_transpose(B, L.nh, L.bdH1, L.nh, L.bdH1T, B, s));
+    HIPCHK(lcc_transpose(B, L.nin_pad, L.bX, L.nin_pad, L.bXT, B, s));
+    HIPCHK(lcc_gemm(LCC_EP_F32, L.nh, L.nin_pad, B, L.bdH1T, B, L.bXT, B, L.G[0], nullptr, L.nin_pad, nullptr, 1.f,
+                    s));
+}
+
+// per-variable RMS of a level-1 field (host), 1 where the field vanishes
+void lcc_rms(frpmg_ctx *ctx, const double *d, float *out) {
+    const Level &C = ctx->lv[1];
+    std::vector<double> h(C.N);
+    HIPCHK(hipMemcpy(h.data(), d, C.N * sizeof(double), hipMemcpyDeviceToHost));
+    const size_t per = (size_t)C.Np * ctx->mesh.Ne;
+    for (int v = 0; v < ctx->nv; ++v) {
+        double ss = 0.0;
+        for (size_t i = 0; i < per; ++i) ss += h[v * per + i] * h[v * per + i];
+        const double r = std::sqrt(ss / per);
+        out[v] = (r > 0.0 && std::isfinite(r)) ? (float)r : 1.f;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // nonlinear p-multigrid preconditioner
 // ---------------------------------------------------------------------------
@@ -206,10 +384,16 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
     REQUIRE(L0.inv_prec >= 0, "level 0 has no EJ factors");
     const size_t N0 = L0.N;
     const bool coarse = p.coarse_mode != FR_COARSE_NONE;
+    const bool learned = p.coarse_mode == FR_COARSE_LEARNED;
     if (coarse) {
-        REQUIRE(ctx->nlevels > 1 && ctx->lv[1].inv_prec >= 0, "level 1 has no EJ factors");
-        REQUIRE(p.n1 >= 1, "n1 must be >= 1");
-        REQUIRE(p.coarse_mode == FR_COARSE_EJ, "coarse mode not available in this build");
+        REQUIRE(ctx->nlevels > 1, "pMG needs two levels");
+        if (learned) {
+            REQUIRE(ctx->lcc && ctx->lcc->scales_set, "the learned correction has no trained network");
+        } else {
+            REQUIRE(ctx->lv[1].inv_prec >= 0, "level 1 has no EJ factors");
+            REQUIRE(p.n1 >= 1, "n1 must be >= 1");
+            REQUIRE(p.coarse_mode == FR_COARSE_EJ, "unknown coarse mode");
+        }
     }
     const Scal one{1.0, nullptr};
     const double *Xs = x;
@@ -232,7 +416,29 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
         HIPCHK(ej_apply(ctx, 0, G, -1.0, 1.0, Y, s));
         cnt->E0++;
     }
-    if (coarse) {
+    if (coarse && learned) {
+        // defect d = -G(Y), restricted; the network maps Gamma d to the coarse correction
+        Lcc &Lc = *ctx->lcc;
+        const size_t N1 = ctx->lv[1].N;
+        residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
+        cnt->R0++;
+        HIPCHK(transfer_apply(ctx, 0, true, G, ctx->cd, s));
+        // base: the element-local coarse EJ step C1 = B1^{-1} Gamma d
+        HIPCHK(ej_apply(ctx, 1, ctx->cd, -1.0, 0.0, Lc.dtmp, s));
+        cnt->E1++;
+        HIPCHK(lcc_features(ctx, Lc.dtmp, Lc, Lc.Xf, Lc.Xb, Lc.srow, 1, s));
+        lcc_forward_rows(ctx, Lc.Mpad, Lc.Xb, Lc.H1, Lc.H2, Lc.Y, s);
+        HIPCHK(lcc_output(ctx, Lc, Lc.Y, Lc.srow, ctx->cZ, s));
+        HIPCHK(vec_axpby(N1, one, Lc.dtmp, one, ctx->cZ, s));  // C = C1 + network refinement
+        HIPCHK(transfer_apply(ctx, 0, false, ctx->cZ, G, s));
+        HIPCHK(vec_axpby(N0, one, G, one, Y, s));
+        for (int it = 0; it < p.n0; ++it) {
+            residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
+            cnt->R0++;
+            HIPCHK(ej_apply(ctx, 0, G, -1.0, 1.0, Y, s));
+            cnt->E0++;
+        }
+    } else if (coarse) {
         const size_t N1 = ctx->lv[1].N;
         // defect d = -G(Y); restrict Y and G
         residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
@@ -251,6 +457,37 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
             cnt->R1++;
             HIPCHK(ej_apply(ctx, 1, ctx->cG, -1.0, 1.0, ctx->cZ, s));
             cnt->E1++;
+        }
+        if (ctx->lcc && ctx->lcc->harvesting && ctx->lcc->count < ctx->lcc->cap) {
+            // record (Gamma d, correction after target_sweeps coarse sweeps) for a rotating subset
+            Lcc &Lc = *ctx->lcc;
+            HIPCHK(hipMemcpyAsync(Lc.Cuse, ctx->cZ, N1 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            for (int it = p.n1; it < Lc.target_sweeps; ++it) {
+                residual_lin(ctx, 1, ctx->q1, ctx->cZ, one, ctx->r1, p.sigma_D, ctx->cS, ctx->cG, s);
+                HIPCHK(ej_apply(ctx, 1, ctx->cG, -1.0, 1.0, ctx->cZ, s));
+            }
+            HIPCHK(vec_axpby(N1, Scal{-1.0, nullptr}, ctx->cZ0, Scal{1.0, nullptr}, ctx->cZ, s));  // target C
+            // network input: the element-local first sweep C1 = B1^{-1} Gamma d;
+            // network target: what the deeper coarse solve adds to it
+            HIPCHK(ej_apply(ctx, 1, ctx->cd, -1.0, 0.0, Lc.dtmp, s));
+            HIPCHK(vec_axpby(N1, Scal{-1.0, nullptr}, Lc.dtmp, Scal{1.0, nullptr}, ctx->cZ, s));
+            if (!Lc.scales_set) {
+                HIPCHK(hipStreamSynchronize(s));
+                lcc_rms(ctx, Lc.dtmp, Lc.h_in_scale);
+                lcc_rms(ctx, ctx->cZ, Lc.h_out_scale);
+                HIPCHK(hipMemcpy(Lc.in_scale, Lc.h_in_scale, 5 * sizeof(float), hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(Lc.out_scale, Lc.h_out_scale, 5 * sizeof(float), hipMemcpyHostToDevice));
+                Lc.scales_set = 1;
+            }
+            HIPCHK(lcc_features(ctx, Lc.dtmp, Lc, Lc.Xf, Lc.Xb, Lc.srow, 0, s));
+            HIPCHK(lcc_targets(ctx, ctx->cZ, Lc, Lc.srow, Lc.Tf, s));
+            const int Ne = ctx->mesh.Ne;
+            const int offset = Lc.cycle % Lc.stride;
+            const int nsel = (Ne - offset + Lc.stride - 1) / Lc.stride;
+            HIPCHK(lcc_harvest_rows(Lc, Ne, Lc.stride, offset, Lc.count, Lc.Xf, Lc.Tf, s));
+            Lc.count = std::min(Lc.cap, Lc.count + nsel);
+            Lc.cycle++;
+            HIPCHK(hipMemcpyAsync(ctx->cZ, Lc.Cuse, N1 * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
         // Y += Pi (Z - Z0)
         HIPCHK(vec_axpby(N1, Scal{-1.0, nullptr}, ctx->cZ0, one, ctx->cZ, s));
@@ -273,13 +510,23 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
 
 struct KrylovResult {
     int iters = 0, restarts = 0;
-    bool converged = false, breakdown = false, nonfinite = false;
+    bool converged = false, breakdown = false, nonfinite = false, restarted_nonfinite = false;
     double res_est = 0.0, bnorm = 0.0;
+};
+
+// Stall monitor: when the residual estimate fails to drop below ratio times
+// its value window iterations earlier, on_stall() is called once.
+struct Stall {
+    bool active = false;
+    int window = 5;
+    double ratio = 0.7;
+    std::vector<double> hist;
+    std::function<void()> on_stall;
 };
 
 template <typename MatVec, typename Prec>
 KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m, double tol, int max_restarts,
-                    MatVec &&A, Prec &&M, hipStream_t s) {
+                    MatVec &&A, Prec &&M, hipStream_t s, Stall *stall = nullptr) {
     KrylovResult kr;
     double *V = ctx->V, *Z = ctx->Zk, *w = ctx->kw;
     const size_t ld = N;
@@ -298,6 +545,10 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
     }
     const double target = tol * bnorm;
     double beta = bnorm;
+    if (stall) {
+        stall->hist.clear();
+        stall->hist.push_back(bnorm);
+    }
     HIPCHK(vec_scale_copy(N, Scal{1.0 / beta, nullptr}, b, V, s));
     for (;;) {
         std::fill(g.begin(), g.end(), 0.0);
@@ -337,8 +588,25 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
             jend = j + 1;
             kr.res_est = std::fabs(g[j + 1]);
             if (!std::isfinite(kr.res_est) || !std::isfinite(hn)) {
+                if (stall && stall->active) {
+                    // the learned preconditioner produced a non-finite direction:
+                    // fall back and restart the cycle from the last iterate
+                    stall->active = false;
+                    stall->on_stall();
+                    jend = 0;
+                    kr.restarted_nonfinite = true;
+                    break;
+                }
                 kr.nonfinite = true;
                 return kr;
+            }
+            if (stall && stall->active) {
+                stall->hist.push_back(kr.res_est);
+                const size_t n = stall->hist.size();
+                if ((int)n > stall->window && kr.res_est > stall->ratio * stall->hist[n - 1 - stall->window]) {
+                    stall->active = false;
+                    stall->on_stall();
+                }
             }
             if (hn == 0.0) {
                 kr.breakdown = true;
@@ -346,6 +614,25 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
             }
             HIPCHK(vec_scale_copy(N, Scal{1.0 / hn, nullptr}, w, V + (size_t)(j + 1) * ld, s));
             if (kr.res_est <= target) break;
+        }
+        if (kr.restarted_nonfinite) {
+            // discard the cycle; restart from x with the true residual
+            kr.restarted_nonfinite = false;
+            kr.restarts++;
+            A(x, w);
+            HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, b, Scal{-1.0, nullptr}, w, s));
+            beta = host_norm(ctx, N, w, s);
+            if (!std::isfinite(beta)) {
+                kr.nonfinite = true;
+                return kr;
+            }
+            kr.res_est = beta;
+            if (beta <= target) {
+                kr.converged = true;
+                return kr;
+            }
+            HIPCHK(vec_scale_copy(N, Scal{1.0 / beta, nullptr}, w, V, s));
+            continue;
         }
         // back substitution with the triangular Hessenberg factor
         for (int i = jend - 1; i >= 0; --i) {
@@ -408,8 +695,10 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
     REQUIRE(P.scheme == FR_SCHEME_ESDIRK || P.scheme == FR_SCHEME_ROW, "bad scheme");
     REQUIRE(P.m >= 1 && P.m <= 60, "Krylov dimension must be in 1..60");
     REQUIRE(P.dt > 0 && P.a_ii > 0, "dt and a_ii must be positive");
-    REQUIRE(P.precond == FR_PRECOND_EJ || P.precond == FR_PRECOND_PMG, "preconditioner not available");
-    const bool pmg = P.precond == FR_PRECOND_PMG;
+    REQUIRE(P.precond >= FR_PRECOND_EJ && P.precond <= FR_PRECOND_PMG_LEARNED, "unknown preconditioner");
+    const bool pmg = P.precond != FR_PRECOND_EJ;
+    const bool learned = P.precond == FR_PRECOND_PMG_LEARNED;
+    if (learned) REQUIRE(ctx->lcc && ctx->lcc->scales_set, "the learned correction has no trained network");
     REQUIRE(!pmg || ctx->nlevels > 1, "pMG needs two levels");
     std::memset(st, 0, sizeof(*st));
     const size_t N = ctx->lv[0].N;
@@ -436,7 +725,15 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
     }
     HIPCHK(hipStreamSynchronize(s));
     const double t1 = now();
-    pmg_params pp{sigma_A, P.n0, P.n1, FR_COARSE_EJ, P.scale_mode, P.eps_p};
+    pmg_params pp{sigma_A, P.n0, P.n1, learned ? FR_COARSE_LEARNED : FR_COARSE_EJ, P.scale_mode, P.eps_p};
+    Stall stall;
+    stall.active = learned;
+    if (P.stall_window > 0) stall.window = P.stall_window;
+    if (P.stall_ratio > 0) stall.ratio = P.stall_ratio;
+    stall.on_stall = [&] {
+        pp.coarse_mode = FR_COARSE_EJ;  // plain pMG for the rest of the stage
+        st->fallbacks++;
+    };
     auto prec = [&](const double *v, double *z) {
         if (pmg) {
             pmg_apply_impl(ctx, pp, v, z, s, &cnt);
@@ -470,7 +767,7 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
                 jvp(ctx, 0, q, rq, z, sigma_A, P.eps, P.eps_mode, w, s, ctx->scal + SC_DQ_N2);
                 cnt.R0++;
             };
-            KrylovResult kr = fgmres(ctx, N, F, dx, P.m, P.eta, P.max_restarts, A, prec, s);
+            KrylovResult kr = fgmres(ctx, N, F, dx, P.m, P.eta, P.max_restarts, A, prec, s, &stall);
             if (st->ptc_iters < FR_MAX_NEWTON_LOG) st->gmres_per_newton[st->ptc_iters] = kr.iters;
             st->gmres_iters += kr.iters;
             st->restarts += kr.restarts;
@@ -504,7 +801,7 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
             jvp(ctx, 0, dq_n, R0, z, sigma_A, P.eps, P.eps_mode, wout, s, ctx->scal + SC_DQ_N2);
             cnt.R0++;
         };
-        KrylovResult kr = fgmres(ctx, N, R0, out, P.m, P.tol, P.max_restarts, A, prec, s);
+        KrylovResult kr = fgmres(ctx, N, R0, out, P.m, P.tol, P.max_restarts, A, prec, s, &stall);
         st->gmres_iters = kr.iters;
         st->restarts = kr.restarts;
         st->gmres_per_newton[0] = kr.iters;
@@ -537,6 +834,7 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
 }
 
 void destroy_all(frpmg_ctx *ctx) {
+    lcc_free(ctx);
     for (int l = 0; l < FR_MAX_LEVELS; ++l) {
         Level &L = ctx->lv[l];
         dfree(L.Tm);
@@ -771,6 +1069,233 @@ fr_status gmres_solve_stage(frpmg_ctx *ctx, const stage_params *prm, const doubl
     return guarded(ctx, [&] {
         REQUIRE(prm && dq_n && out && dq_n != out, "bad arguments");
         stage_impl(ctx, *prm, dq_n, out, st, S(stream));
+    });
+}
+
+fr_status lcc_harvest(frpmg_ctx *ctx, const lcc_harvest_params *prm) {
+    return guarded(ctx, [&] {
+        REQUIRE(prm, "null parameters");
+        lcc_alloc(ctx);
+        Lcc &L = *ctx->lcc;
+        if (prm->reset) {
+            L.count = 0;
+            L.cycle = 0;
+            L.scales_set = 0;
+        }
+        if (prm->enable) {
+            REQUIRE(prm->max_pairs > 0 && prm->stride >= 1 && prm->target_sweeps >= 1, "bad harvest parameters");
+            if (!L.HX || prm->max_pairs != L.cap) {
+                dfree(L.HX);
+                dfree(L.HT);
+                L.HX = talloc<float>(ctx, (size_t)prm->max_pairs * L.nin_pad);
+                L.HT = talloc<float>(ctx, (size_t)prm->max_pairs * L.nout_pad);
+                L.cap = prm->max_pairs;
+                L.count = std::min(L.count, L.cap);
+            }
+            L.stride = prm->stride;
+            L.target_sweeps = prm->target_sweeps;
+        }
+        L.harvesting = prm->enable ? 1 : 0;
+    });
+}
+
+int lcc_harvest_count(const frpmg_ctx *ctx) { return (ctx && ctx->lcc) ? ctx->lcc->count : 0; }
+
+fr_status lcc_dims(frpmg_ctx *ctx, int *nin, int *nin_pad, int *nh, int *nout, int *nout_pad) {
+    return guarded(ctx, [&] {
+        lcc_alloc(ctx);
+        const Lcc &L = *ctx->lcc;
+        if (nin) *nin = L.nin;
+        if (nin_pad) *nin_pad = L.nin_pad;
+        if (nh) *nh = L.nh;
+        if (nout) *nout = L.nout;
+        if (nout_pad) *nout_pad = L.nout_pad;
+    });
+}
+
+size_t lcc_num_weights(frpmg_ctx *ctx) {
+    if (!ctx || lcc_dims(ctx, nullptr, nullptr, nullptr, nullptr, nullptr) != FR_OK) return 0;
+    const Lcc &L = *ctx->lcc;
+    size_t n = 0;
+    for (int l = 0; l < 3; ++l) n += (size_t)L.wrows[l] * L.wcols[l];
+    return n;
+}
+
+fr_status lcc_get_weights(frpmg_ctx *ctx, float *host, size_t n) {
+    return guarded(ctx, [&] {
+        REQUIRE(host && n == lcc_num_weights(ctx), "weight buffer size mismatch");
+        Lcc &L = *ctx->lcc;
+        HIPCHK(hipDeviceSynchronize());
+        size_t off = 0;
+        for (int l = 0; l < 3; ++l) {
+            const size_t m = (size_t)L.wrows[l] * L.wcols[l];
+            HIPCHK(hipMemcpy(host + off, L.W[l], m * sizeof(float), hipMemcpyDeviceToHost));
+            off += m;
+        }
+    });
+}
+
+fr_status lcc_set_weights(frpmg_ctx *ctx, const float *host, size_t n) {
+    return guarded(ctx, [&] {
+        REQUIRE(host && n == lcc_num_weights(ctx), "weight buffer size mismatch");
+        Lcc &L = *ctx->lcc;
+        HIPCHK(hipDeviceSynchronize());
+        size_t off = 0;
+        for (int l = 0; l < 3; ++l) {
+            const size_t m = (size_t)L.wrows[l] * L.wcols[l];
+            HIPCHK(hipMemcpy(L.W[l], host + off, m * sizeof(float), hipMemcpyHostToDevice));
+            HIPCHK(hipMemset(L.Mo[l], 0, m * sizeof(float)));
+            HIPCHK(hipMemset(L.Vo[l], 0, m * sizeof(float)));
+            HIPCHK(lcc_to_bf(m, L.W[l], L.Wb[l], nullptr));
+            off += m;
+        }
+        L.adam_step = 0;
+        HIPCHK(hipDeviceSynchronize());
+    });
+}
+
+fr_status lcc_get_scales(frpmg_ctx *ctx, float *in_scale, float *out_scale) {
+    return guarded(ctx, [&] {
+        lcc_alloc(ctx);
+        REQUIRE(ctx->lcc->scales_set, "scales not set");
+        for (int v = 0; v < ctx->nv; ++v) {
+            if (in_scale) in_scale[v] = ctx->lcc->h_in_scale[v];
+            if (out_scale) out_scale[v] = ctx->lcc->h_out_scale[v];
+        }
+    });
+}
+
+fr_status lcc_set_scales(frpmg_ctx *ctx, const float *in_scale, const float *out_scale) {
+    return guarded(ctx, [&] {
+        REQUIRE(in_scale && out_scale, "null scales");
+        lcc_alloc(ctx);
+        Lcc &L = *ctx->lcc;
+        for (int v = 0; v < ctx->nv; ++v) {
+            REQUIRE(in_scale[v] > 0.f && out_scale[v] > 0.f, "scales must be positive");
+            L.h_in_scale[v] = in_scale[v];
+            L.h_out_scale[v] = out_scale[v];
+        }
+        HIPCHK(hipMemcpy(L.in_scale, L.h_in_scale, 5 * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(L.out_scale, L.h_out_scale, 5 * sizeof(float), hipMemcpyHostToDevice));
+        L.scales_set = 1;
+    });
+}
+
+fr_status lcc_forward(frpmg_ctx *ctx, const float *X, int rows, float *Y, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(X && Y && rows > 0 && rows % 32 == 0, "rows must be a positive multiple of 32");
+        lcc_alloc(ctx);
+        lcc_train_buffers(ctx, rows);
+        Lcc &L = *ctx->lcc;
+        hipStream_t s = S(stream);
+        HIPCHK(lcc_to_bf((size_t)rows * L.nin_pad, X, L.bX, s));
+        lcc_forward_rows(ctx, rows, L.bX, L.bH1, L.bH2, L.bY, s);
+        HIPCHK(hipMemcpyAsync(Y, L.bY, (size_t)rows * L.nout_pad * sizeof(float), hipMemcpyDeviceToDevice, s));
+    });
+}
+
+fr_status lcc_loss_grad(frpmg_ctx *ctx, const float *X, const float *T, int rows, double *loss, float *grad,
+                        fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(X && T && grad && loss && rows > 0 && rows % 32 == 0, "bad arguments");
+        lcc_alloc(ctx);
+        lcc_train_buffers(ctx, rows);
+        Lcc &L = *ctx->lcc;
+        hipStream_t s = S(stream);
+        HIPCHK(lcc_to_bf((size_t)rows * L.nin_pad, X, L.bX, s));
+        HIPCHK(hipMemcpyAsync(L.bT, T, (size_t)rows * L.nout_pad * sizeof(float), hipMemcpyDeviceToDevice, s));
+        lcc_batch_grad(ctx, s);
+        size_t off = 0;
+        for (int l = 0; l < 3; ++l) {
+            const size_t m = (size_t)L.wrows[l] * L.wcols[l];
+            HIPCHK(hipMemcpyAsync(grad + off, L.G[l], m * sizeof(float), hipMemcpyDeviceToDevice, s));
+            off += m;
+        }
+        HIPCHK(hipMemcpyAsync(ctx->host_pinned, L.lval, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *loss = ctx->host_pinned[0];
+    });
+}
+
+fr_status lcc_features_of(frpmg_ctx *ctx, const double *d1, float *rows_out, float *s_out, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(d1 && rows_out && s_out, "null pointer");
+        lcc_alloc(ctx);
+        Lcc &L = *ctx->lcc;
+        REQUIRE(L.scales_set, "scales not set");
+        hipStream_t s = S(stream);
+        HIPCHK(lcc_features(ctx, d1, L, L.Xf, L.Xb, L.srow, 0, s));
+        HIPCHK(hipMemcpyAsync(rows_out, L.Xf, (size_t)ctx->mesh.Ne * L.nin_pad * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(s_out, L.srow, (size_t)ctx->mesh.Ne * sizeof(float), hipMemcpyDeviceToDevice, s));
+    });
+}
+
+fr_status lcc_train(frpmg_ctx *ctx, const lcc_train_params *prm, lcc_train_stats *st, fr_stream stream) {
+    lcc_train_stats local;
+    lcc_train_stats *out = st ? st : &local;
+    return guarded(ctx, [&] {
+        REQUIRE(prm && prm->batch > 0 && prm->batch % 32 == 0, "batch must be a positive multiple of 32");
+        REQUIRE(prm->epochs >= 1 && prm->lr > 0.0, "bad training parameters");
+        REQUIRE(ctx->lcc && ctx->lcc->count >= 2 * prm->batch, "not enough harvested pairs");
+        Lcc &L = *ctx->lcc;
+        hipStream_t s = S(stream);
+        std::memset(out, 0, sizeof(*out));
+        HIPCHK(hipStreamSynchronize(s));
+        const double t0 = now();
+        if (prm->reinit) lcc_init_weights(ctx, prm->seed);
+        const int B = prm->batch;
+        lcc_train_buffers(ctx, B);
+        const int nval = std::min(L.count - B, std::max(0, (int)(L.count * prm->holdout)));
+        const int ntrain = L.count - nval;
+        const int spe = ntrain / B;
+        if (!L.perm) L.perm = talloc<int>(ctx, (size_t)L.cap + B);
+        auto val_loss = [&]() {
+            const int nb = nval / B;
+            if (nb == 0) return 0.0;
+            std::vector<int> idx(nval);
+            for (int i = 0; i < nval; ++i) idx[i] = ntrain + i;
+            HIPCHK(hipMemcpy(L.perm, idx.data(), nval * sizeof(int), hipMemcpyHostToDevice));
+            double acc = 0.0;
+            for (int b = 0; b < nb; ++b) {
+                HIPCHK(lcc_gather_batch(L, B, L.perm + (size_t)b * B, L.bX, L.bT, 0, s));
+                lcc_forward_rows(ctx, B, L.bX, L.bH1, L.bH2, L.bY, s);
+                HIPCHK(lcc_loss_grad(B, L.nout_pad, L.nout, L.bY, L.bT, L.bdY, L.lpart, L.lval, s));
+                HIPCHK(hipMemcpyAsync(ctx->host_pinned, L.lval, sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                acc += ctx->host_pinned[0];
+            }
+            return acc / nb;
+        };
+        out->val_loss_init = val_loss();
+        std::mt19937_64 rng(prm->seed);
+        std::vector<int> idx(ntrain);
+        for (int i = 0; i < ntrain; ++i) idx[i] = i;
+        for (int e = 0; e < prm->epochs; ++e) {
+            std::shuffle(idx.begin(), idx.end(), rng);
+            HIPCHK(hipMemcpy(L.perm, idx.data(), ntrain * sizeof(int), hipMemcpyHostToDevice));
+            for (int b = 0; b < spe; ++b) {
+                HIPCHK(lcc_gather_batch(L, B, L.perm + (size_t)b * B, L.bX, L.bT, 1, s));
+                lcc_batch_grad(ctx, s);
+                L.adam_step++;
+                for (int l = 0; l < 3; ++l)
+                    HIPCHK(lcc_adam((size_t)L.wrows[l] * L.wcols[l], L.W[l], L.G[l], L.Mo[l], L.Vo[l], L.Wb[l],
+                                    (float)prm->lr, 0.9f, 0.999f, 1e-8f, L.adam_step, s));
+                out->steps++;
+                if (e == 0 && b == 0) {
+                    HIPCHK(hipMemcpyAsync(ctx->host_pinned, L.lval, sizeof(double), hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipStreamSynchronize(s));
+                    out->loss_first = ctx->host_pinned[0];
+                }
+            }
+        }
+        HIPCHK(hipMemcpyAsync(ctx->host_pinned, L.lval, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        out->loss_last = ctx->host_pinned[0];
+        out->val_loss = val_loss();
+        L.weights_set = 1;
+        HIPCHK(hipStreamSynchronize(s));
+        out->t_train = now() - t0;
     });
 }
 

@@ -12,6 +12,7 @@
 
 namespace frpmg {
 
+struct Lcc;
 constexpr int kMaxP = 5;  // points per direction (p <= 4)
 
 // 1D operators on [-1, 1] for one number of Gauss-Legendre points.
@@ -118,6 +119,8 @@ struct frpmg_ctx {
     int kdim = 0;
     double *V = nullptr, *Zk = nullptr, *kw = nullptr;
     double *sq = nullptr, *srq = nullptr, *sF = nullptr, *sb = nullptr, *sdx = nullptr;
+    // learned coarse correction (allocated on first use)
+    frpmg::Lcc *lcc = nullptr;
 };
 
 namespace frpmg {

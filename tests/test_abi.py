@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     txt = open(os.path.join(ROOT, "include", "frpmg.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:fr_status|void|const char \*|size_t)\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)
+    names = re.findall(r"^\s*(?:fr_status|void|const char \*|size_t|int)\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 
