@@ -263,21 +263,27 @@ def main():
                                                       "converged")}
         result["plain_ej"]["dof_per_s"] = dof / st_ej["t_total"]
         if prec == capi.PREC_FP64:
-            print("[bench] FP32-storage preconditioner variant", file=sys.stderr, flush=True)
-            cfg32 = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=capi.PREC_FP32)
-            fr.solve_stage(cfg32, dq, out=fr.empty(0))
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            st32 = None
-            for _ in range(args.steps):
-                _, st32 = fr.solve_stage(cfg32, dq, out=fr.empty(0))
-            torch.cuda.synchronize()
-            v32 = dof * args.steps / (time.perf_counter() - ta)
-            result["precision_fp32_factors"] = {
-                "value": v32, "speedup_vs_fp64": v32 / result["value"],
-                "dof_per_s_without_setup": dof / st32["t_solve"], "ptc_iters": st32["ptc_iters"],
-                "gmres_iters": st32["gmres_iters"], "rel_res": st32["rel_res"],
-                "note": "EJ inverses stored FP32 on both levels; R, JVP, FGMRES and the stage update FP64"}
+            for key, pv, note in [
+                    ("precision_fp32_factors", capi.PREC_FP32,
+                     "EJ inverses: FP64 Gauss-Jordan, stored FP32 on both levels; R, JVP, FGMRES, stage update FP64"),
+                    ("precision_bf16_mfma_factors", capi.PREC_FP32_BF16,
+                     "EJ inverses: blocked Gauss-Jordan with BF16-MFMA (hi/lo, FP32 accumulate) panel updates, "
+                     "stored FP32; R, JVP, FGMRES, stage update FP64")]:
+                print("[bench] preconditioner variant " + key, file=sys.stderr, flush=True)
+                cfgv = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=pv)
+                fr.solve_stage(cfgv, dq, out=fr.empty(0))
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                stv = None
+                for _ in range(args.steps):
+                    _, stv = fr.solve_stage(cfgv, dq, out=fr.empty(0))
+                torch.cuda.synchronize()
+                vv = dof * args.steps / (time.perf_counter() - ta)
+                result[key] = {
+                    "value": vv, "speedup_vs_fp64": vv / result["value"],
+                    "dof_per_s_without_setup": dof / stv["t_solve"], "t_setup_s": stv["t_setup"],
+                    "ptc_iters": stv["ptc_iters"], "gmres_iters": stv["gmres_iters"], "rel_res": stv["rel_res"],
+                    "note": note}
         # re-create the pMG factors for the kernel-rate measurements
         fr.solve_stage(cfg, dq, out=out)
         print("[bench] kernel rates", file=sys.stderr, flush=True)

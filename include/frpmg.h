@@ -101,7 +101,8 @@ fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, 
 
 #define FR_PREC_FP64 0      /* FP64 factor, FP64 storage */
 #define FR_PREC_FP32 1      /* FP64 elimination, inverse stored in FP32 */
-#define FR_PREC_FP32_BF16 2 /* FP32 storage; trailing updates on BF16-input MFMA, FP32 accumulate */
+#define FR_PREC_FP32_BF16 2 /* blocked Gauss-Jordan: FP64 panels, panel updates on BF16-input MFMA (hi/lo
+                                split, FP32 accumulate), inverse stored in FP32 */
 
 /* Element-Jacobi setup (Sec. 2.2, element-Jacobi preconditioner; the
  * preconditioner matrix is evaluated once per physical time step):

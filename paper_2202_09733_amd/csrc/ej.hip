@@ -5,7 +5,8 @@
 // Inversion: one workgroup per block, the whole FP64 block resident in LDS
 // (n_b <= 140 fits in the 160 KB of a CU), Gauss-Jordan elimination with
 // partial pivoting (largest |a|, first row on ties), the inverse written
-// back column-major in the requested storage precision.  Storing the inverse
+// back column-major in the requested storage precision.  Larger blocks, and
+// the BF16-MFMA precision form at any size, use the blocked variant below.  Storing the inverse
 // turns every apply into a batched GEMV that streams the blocks once from
 // HBM with coalesced column reads, with no sequential triangular sweeps.
 #include "internal.hpp"
@@ -261,6 +262,93 @@ __global__ void __launch_bounds__(256) k_gj_update(int nb, int c0, int bw, doubl
     }
 }
 
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// The same panel update on BF16-input MFMA with FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16, K = the 32-column panel): each FP32 operand is
+// split into hi + lo BF16 parts and the product taken as hi*hi + hi*lo +
+// lo*hi (three MFMAs), ~16 mantissa bits.  Operands are staged k-contiguous
+// in LDS; wave w owns 16 output rows of the 64-row chunk and the four 16-column
+// blocks of the workgroup's 64 columns.
+__global__ void __launch_bounds__(256) k_gj_update_mfma(int nb, int c0, int bw, double *__restrict__ A,
+                                                        const int *__restrict__ perm) {
+    __shared__ __attribute__((aligned(16))) __bf16 xs_h[kUpdCols][kPanel];
+    __shared__ __attribute__((aligned(16))) __bf16 xs_l[kUpdCols][kPanel];
+    __shared__ __attribute__((aligned(16))) __bf16 tp_h[kUpdRows][kPanel];
+    __shared__ __attribute__((aligned(16))) __bf16 tp_l[kUpdRows][kPanel];
+    const int tid = threadIdx.x;
+    const int k = blockIdx.x;
+    double *Ak = A + (size_t)k * nb * nb;
+    const int nrest = nb - bw;
+    // phase 1: row interchanges on this tile's columns, gather (P x)_S split in hi/lo
+    if (tid < kUpdCols) {
+        const int ri = blockIdx.y * kUpdCols + tid;
+        if (ri < nrest) {
+            const int j = (ri < c0) ? ri : ri + bw;
+            double *x = Ak + (size_t)j * nb;
+            for (int cc = 0; cc < bw; ++cc) {
+                const int c = c0 + cc, p = perm[(size_t)k * nb + c];
+                if (p != c) {
+                    const double t0 = x[c];
+                    x[c] = x[p];
+                    x[p] = t0;
+                }
+            }
+            for (int cc = 0; cc < kPanel; ++cc) {
+                const float v = (cc < bw) ? (float)x[c0 + cc] : 0.f;
+                const __bf16 h = (__bf16)v;
+                xs_h[tid][cc] = h;
+                xs_l[tid][cc] = (__bf16)(v - (float)h);
+            }
+        } else {
+            for (int cc = 0; cc < kPanel; ++cc) {
+                xs_h[tid][cc] = (__bf16)0.f;
+                xs_l[tid][cc] = (__bf16)0.f;
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    for (int r0 = 0; r0 < nb; r0 += kUpdRows) {
+        for (int t = tid; t < kPanel * kUpdRows; t += 256) {
+            const int cc = t / kUpdRows, rr = t % kUpdRows;
+            const float v = (cc < bw && r0 + rr < nb) ? (float)Ak[(size_t)(c0 + cc) * nb + r0 + rr] : 0.f;
+            const __bf16 h = (__bf16)v;
+            tp_h[rr][cc] = h;
+            tp_l[rr][cc] = (__bf16)(v - (float)h);
+        }
+        __syncthreads();
+        const int arow = wave * 16 + r16;
+        const bf16x8_t ah = *reinterpret_cast<const bf16x8_t *>(&tp_h[arow][8 * g]);
+        const bf16x8_t al = *reinterpret_cast<const bf16x8_t *>(&tp_l[arow][8 * g]);
+#pragma unroll
+        for (int cb = 0; cb < kUpdCols / 16; ++cb) {
+            const int bcol = cb * 16 + r16;
+            const bf16x8_t bh = *reinterpret_cast<const bf16x8_t *>(&xs_h[bcol][8 * g]);
+            const bf16x8_t bl = *reinterpret_cast<const bf16x8_t *>(&xs_l[bcol][8 * g]);
+            f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+            const int rib = blockIdx.y * kUpdCols + bcol;
+            if (rib < nrest) {
+                const int j = (rib < c0) ? rib : rib + bw;
+                double *x = Ak + (size_t)j * nb;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = r0 + wave * 16 + 4 * g + i;
+                    if (r >= nb) continue;
+                    const bool inS = (r >= c0 && r < c0 + bw);
+                    x[r] = (inS ? 0.0 : x[r]) + (double)acc[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Undo the row interchanges as column interchanges, last first.
 __global__ void __launch_bounds__(256) k_gj_unscramble(int nb, double *__restrict__ A, const int *__restrict__ perm) {
     double *Ak = A + (size_t)blockIdx.x * nb * nb;
@@ -383,8 +471,9 @@ hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, d
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
     Level &L = ctx->lv[level];
     const int nb = L.nb, Ne = ctx->mesh.Ne;
-    if (nb > kMaxLdsBlock) {
+    if (nb > kMaxLdsBlock || precision == FR_PREC_FP32_BF16) {
         if (nb > 512 || !L.perm) return hipErrorInvalidValue;
+        const bool mfma = precision == FR_PREC_FP32_BF16;
         const size_t lds_p = ((size_t)kPanel * nb + nb) * sizeof(double);
         hipError_t e = hipFuncSetAttribute((const void *)k_gj_panel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_p);
@@ -394,9 +483,13 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
             hipLaunchKernelGGL(k_gj_panel<0>, dim3(Ne), dim3(kGJThreads), lds_p, s, nb, c0, bw, L.blk64, L.perm,
                                L.dstatus);
             const int nrest = nb - bw;
-            if (nrest > 0)
-                hipLaunchKernelGGL(k_gj_update, dim3(Ne, (nrest + kUpdCols - 1) / kUpdCols), dim3(256), 0, s, nb, c0,
-                                   bw, L.blk64, L.perm);
+            if (nrest > 0) {
+                const dim3 gu(Ne, (nrest + kUpdCols - 1) / kUpdCols);
+                if (mfma)
+                    hipLaunchKernelGGL(k_gj_update_mfma, gu, dim3(256), 0, s, nb, c0, bw, L.blk64, L.perm);
+                else
+                    hipLaunchKernelGGL(k_gj_update, gu, dim3(256), 0, s, nb, c0, bw, L.blk64, L.perm);
+            }
         }
         hipLaunchKernelGGL(k_gj_unscramble, dim3(Ne), dim3(256), 0, s, nb, L.blk64, L.perm);
         if (precision == FR_PREC_FP64) {

@@ -146,7 +146,7 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
     REQUIRE(L.nb <= 512, "EJ block too large (n_b > 512)");
     const size_t nblk = (size_t)ctx->mesh.Ne * L.nb * L.nb;
     if (!L.blk64) L.blk64 = dalloc(ctx, nblk);
-    if (L.nb > 140 && !L.perm) {
+    if ((L.nb > 140 || precision == FR_PREC_FP32_BF16) && !L.perm) {
         void *p = nullptr;
         HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * L.nb * sizeof(int)));
         L.perm = (int *)p;

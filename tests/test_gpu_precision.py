@@ -55,3 +55,44 @@ def test_fp32_stage_converges_config2_full(orc):
     print("fp32 vs fp64 stage: iterations %d/%d vs %d/%d; state difference %.2e of the stage update"
           % (s32["ptc_iters"], s32["gmres_iters"], s64["ptc_iters"], s64["gmres_iters"], e_state))
     assert e_state <= 1e-5
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_bf16_mfma_factor_error(orc, dim):
+    """Blocked Gauss-Jordan with the panel updates on BF16 MFMA (hi/lo split,
+    FP32 accumulation): the inverse against the FP64 inverse of the same
+    blocks; the error is stated and bounded by the 16-bit effective mantissa
+    times the block condition number."""
+    require_gpu()
+    announce("bf16-mfma EJ factor error dim=%d" % dim)
+    if dim == 2:
+        wl = W.make_vortical_workload(n=(8, 8), dt_factor=1000.0)
+    else:
+        wl = W.make_tgv_workload(n=(2, 2, 2))
+    fr = capi.FR.from_workload(wl)
+    sig = 2.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
+    dq = fr.to_dev(wl.dq)
+    fr.ej_factor(0, dq, sig, capi.PREC_FP64)
+    inv64 = fr.ej_inverse(0)
+    fr.ej_factor(0, dq, sig, capi.PREC_FP32_BF16)
+    invb = fr.ej_inverse(0)
+    cond = max(np.linalg.cond(np.linalg.inv(inv64[k])) for k in range(0, inv64.shape[0], max(1, inv64.shape[0] // 8)))
+    e = rel(invb, inv64)
+    print("bf16x3-MFMA inverse: rel err %.2e (block cond up to %.1e)" % (e, cond))
+    assert e <= 2.0 ** -15 * cond
+
+
+def test_bf16_mfma_stage_converges_config2(orc):
+    require_gpu()
+    announce("stage config2 with BF16-MFMA EJ factors")
+    wl = W.config2()
+    fr = capi.FR.from_workload(wl)
+    q, st = fr.solve_stage(capi.stage_config_for(wl, precision=capi.PREC_FP32_BF16), fr.to_dev(wl.dq))
+    assert st["converged"] == 1
+    L0 = orc.Level(**wl.level_kwargs(wl.p0))
+    R0 = L0.residual(wl.dq)
+    b = wl.dq + wl.a_ii * wl.dt * R0
+    qh = q.cpu().numpy()
+    F = (qh - b) / (wl.a_ii * wl.dt) - L0.residual(qh)
+    print("bf16-mfma factors: %d PTC / %d FGMRES, setup %.4f s" % (st["ptc_iters"], st["gmres_iters"], st["t_setup"]))
+    assert np.linalg.norm(F) / np.linalg.norm(2 * R0) <= 1.5e-8
