@@ -268,7 +268,10 @@ def main():
                      "EJ inverses: FP64 Gauss-Jordan, stored FP32 on both levels; R, JVP, FGMRES, stage update FP64"),
                     ("precision_bf16_mfma_factors", capi.PREC_FP32_BF16,
                      "EJ inverses: blocked Gauss-Jordan with BF16-MFMA (hi/lo, FP32 accumulate) panel updates, "
-                     "stored FP32; R, JVP, FGMRES, stage update FP64")]:
+                     "stored FP32; R, JVP, FGMRES, stage update FP64"),
+                    ("precision_bf16_storage", capi.PREC_BF16_STORE,
+                     "EJ inverses: as precision_bf16_mfma_factors, stored BF16 (FP64 accumulation in the apply); "
+                     "R, JVP, FGMRES, stage update FP64")]:
                 print("[bench] preconditioner variant " + key, file=sys.stderr, flush=True)
                 cfgv = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=pv)
                 fr.solve_stage(cfgv, dq, out=fr.empty(0))

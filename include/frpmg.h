@@ -103,6 +103,7 @@ fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, 
 #define FR_PREC_FP32 1      /* FP64 elimination, inverse stored in FP32 */
 #define FR_PREC_FP32_BF16 2 /* blocked Gauss-Jordan: FP64 panels, panel updates on BF16-input MFMA (hi/lo
                                 split, FP32 accumulate), inverse stored in FP32 */
+#define FR_PREC_BF16_STORE 3 /* as FR_PREC_FP32_BF16, inverse stored in BF16 (applied with FP64 accumulation) */
 
 /* Element-Jacobi setup (Sec. 2.2, element-Jacobi preconditioner; the
  * preconditioner matrix is evaluated once per physical time step):

@@ -21,7 +21,7 @@ FR_ESINGULAR, FR_ENOCONV, FR_EBREAKDOWN, FR_ENONFINITE = -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGULAR", -5: "ENOCONV",
                 -6: "EBREAKDOWN", -7: "ENONFINITE"}
 EPS_ABSOLUTE, EPS_NORMALIZED, EPS_SCALED = 0, 1, 2
-PREC_FP64, PREC_FP32, PREC_FP32_BF16 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_FP32_BF16, PREC_BF16_STORE = 0, 1, 2, 3
 COARSE_NONE, COARSE_EJ, COARSE_LEARNED = 0, 1, 2
 SCALE_LITERAL, SCALE_NORMALIZED, SCALE_SCALED = 0, 1, 2
 SCHEME_ESDIRK, SCHEME_ROW = 0, 1

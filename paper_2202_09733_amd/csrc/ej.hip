@@ -370,6 +370,11 @@ __global__ void k_to_float(size_t n, const double *__restrict__ a, float *__rest
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
 }
 
+__global__ void k_to_bf16(size_t n, const double *__restrict__ a, __bf16 *__restrict__ b) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (__bf16)(float)a[i];
+}
+
 constexpr int kApplyThreads = 256;
 
 template <typename T, int R>
@@ -401,10 +406,26 @@ struct VecLoad<float, 4> {
     }
 };
 
+template <>
+struct VecLoad<__bf16, 1> {
+    __device__ static void get(const __bf16 *p, double *o) { o[0] = (float)p[0]; }
+};
+template <>
+struct VecLoad<__bf16, 4> {
+    __device__ static void get(const __bf16 *p, double *o) {
+        typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+        const b4 v = *reinterpret_cast<const b4 *>(p);
+        o[0] = (float)v.x;
+        o[1] = (float)v.y;
+        o[2] = (float)v.z;
+        o[3] = (float)v.w;
+    }
+};
+
 // y[row][k] = beta y + alpha sum_j Binv_k[row][j] r[j][k], Binv column-major.
 // Each lane owns R consecutive rows of one block and streams the block
-// column by column with one 16-byte load per column (R = 2 for FP64, 4 for
-// FP32 storage), so a wavefront reads whole contiguous column segments.
+// column by column with one wide load per column (R = 2 for FP64, 4 for FP32
+// and BF16 storage), so a wavefront reads whole contiguous column segments.
 template <typename T, int R>
 __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int epb, const T *__restrict__ inv,
                                                             const double *__restrict__ r, double alpha,
@@ -471,9 +492,9 @@ hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, d
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
     Level &L = ctx->lv[level];
     const int nb = L.nb, Ne = ctx->mesh.Ne;
-    if (nb > kMaxLdsBlock || precision == FR_PREC_FP32_BF16) {
+    if (nb > kMaxLdsBlock || precision == FR_PREC_FP32_BF16 || precision == FR_PREC_BF16_STORE) {
         if (nb > 512 || !L.perm) return hipErrorInvalidValue;
-        const bool mfma = precision == FR_PREC_FP32_BF16;
+        const bool mfma = precision != FR_PREC_FP64;
         const size_t lds_p = ((size_t)kPanel * nb + nb) * sizeof(double);
         hipError_t e = hipFuncSetAttribute((const void *)k_gj_panel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_p);
@@ -492,10 +513,13 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
             }
         }
         hipLaunchKernelGGL(k_gj_unscramble, dim3(Ne), dim3(256), 0, s, nb, L.blk64, L.perm);
+        const size_t n = (size_t)Ne * nb * nb;
         if (precision == FR_PREC_FP64) {
             L.inv = L.blk64;
+        } else if (precision == FR_PREC_BF16_STORE) {
+            hipLaunchKernelGGL(k_to_bf16, dim3(4096), dim3(256), 0, s, n, L.blk64, L.inv16);
+            L.inv = L.inv16;
         } else {
-            const size_t n = (size_t)Ne * nb * nb;
             hipLaunchKernelGGL(k_to_float, dim3(4096), dim3(256), 0, s, n, L.blk64, L.inv32);
             L.inv = L.inv32;
         }
@@ -530,6 +554,9 @@ hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alp
     if (L.inv_prec == FR_PREC_FP64)
         return (nb % 2 == 0) ? launch_apply<double, 2>(L, Ne, r, alpha, beta, y, s)
                              : launch_apply<double, 1>(L, Ne, r, alpha, beta, y, s);
+    if (L.inv_prec == FR_PREC_BF16_STORE)
+        return (nb % 4 == 0) ? launch_apply<__bf16, 4>(L, Ne, r, alpha, beta, y, s)
+                             : launch_apply<__bf16, 1>(L, Ne, r, alpha, beta, y, s);
     if (L.inv_prec >= 0)
         return (nb % 4 == 0) ? launch_apply<float, 4>(L, Ne, r, alpha, beta, y, s)
                              : launch_apply<float, 1>(L, Ne, r, alpha, beta, y, s);

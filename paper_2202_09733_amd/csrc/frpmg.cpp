@@ -140,21 +140,26 @@ void check_even(frpmg_ctx *ctx) {
 
 void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, int precision, hipStream_t s) {
     REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
-    REQUIRE(precision >= FR_PREC_FP64 && precision <= FR_PREC_FP32_BF16, "bad precision");
+    REQUIRE(precision >= FR_PREC_FP64 && precision <= FR_PREC_BF16_STORE, "bad precision");
     check_even(ctx);
     Level &L = ctx->lv[level];
     REQUIRE(L.nb <= 512, "EJ block too large (n_b > 512)");
     const size_t nblk = (size_t)ctx->mesh.Ne * L.nb * L.nb;
     if (!L.blk64) L.blk64 = dalloc(ctx, nblk);
-    if ((L.nb > 140 || precision == FR_PREC_FP32_BF16) && !L.perm) {
+    if ((L.nb > 140 || precision != FR_PREC_FP64) && !L.perm) {
         void *p = nullptr;
         HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * L.nb * sizeof(int)));
         L.perm = (int *)p;
     }
-    if (precision != FR_PREC_FP64 && !L.inv32) {
+    if ((precision == FR_PREC_FP32 || precision == FR_PREC_FP32_BF16) && !L.inv32) {
         void *p = nullptr;
         HIPCHK(hipMalloc(&p, nblk * sizeof(float)));
         L.inv32 = (float *)p;
+    }
+    if (precision == FR_PREC_BF16_STORE && !L.inv16) {
+        void *p = nullptr;
+        HIPCHK(hipMalloc(&p, nblk * sizeof(__bf16)));
+        L.inv16 = (__bf16 *)p;
     }
     HIPCHK(hipMemsetAsync(L.dstatus, 0, sizeof(int), s));
     residual(ctx, level, dq, L.r0, s);
@@ -841,6 +846,7 @@ void destroy_all(frpmg_ctx *ctx) {
         dfree(L.Fs);
         dfree(L.blk64);
         dfree(L.inv32);
+        dfree(L.inv16);
         dfree(L.dstatus);
         dfree(L.perm);
         dfree(L.r0);
@@ -1023,6 +1029,15 @@ fr_status ej_get_inverse(frpmg_ctx *ctx, int level, double *host_out) {
         HIPCHK(hipDeviceSynchronize());
         if (L.inv_prec == FR_PREC_FP64) {
             HIPCHK(hipMemcpy(host_out, L.inv, n * sizeof(double), hipMemcpyDeviceToHost));
+        } else if (L.inv_prec == FR_PREC_BF16_STORE) {
+            std::vector<uint16_t> tmp(n);
+            HIPCHK(hipMemcpy(tmp.data(), L.inv, n * sizeof(uint16_t), hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < n; ++i) {
+                const uint32_t bits = (uint32_t)tmp[i] << 16;
+                float f;
+                std::memcpy(&f, &bits, sizeof(f));
+                host_out[i] = f;
+            }
         } else {
             std::vector<float> tmp(n);
             HIPCHK(hipMemcpy(tmp.data(), L.inv, n * sizeof(float), hipMemcpyDeviceToHost));

@@ -86,6 +86,7 @@ struct Level {
     double *blk64 = nullptr;  // [Ne][nb][nb], column-major per block
     void *inv = nullptr;      // inverse: points to blk64 (FP64) or inv32
     float *inv32 = nullptr;
+    __bf16 *inv16 = nullptr;
     int inv_prec = -1;
     int *dstatus = nullptr;   // device flag: 1 = zero pivot seen
     int *perm = nullptr;      // pivot rows of the blocked inversion [Ne][nb]

@@ -421,7 +421,9 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK sr
     __syncthreads();
     const int t = threadIdx.x;
     const int e = t % EB, i = t / EB;
-    const bool active = (t < NP * EB) && (e < ne);
+    // EJ columns: only elements of the perturbed colour produce output, and
+    // their residual needs no other element's pointwise fluxes
+    const bool active = (t < NP * EB) && (e < ne) && (OUT != OUT_EJCOL || colour_of(m, k0 + e) == src.colour);
     double g[DIM][DIM + 2];
     if (active) gradient_point<DIM, P>(ops, s_u, s_t, s_ih, e, i, g);
     // the gradient stays in registers; s_g now receives the pointwise fluxes

@@ -133,37 +133,85 @@ unsigned grid_for(size_t n) {
     return (unsigned)b;
 }
 
-// Restriction / prolongation: y[v][i][k] = sum_j (M (x) M (x) M)[i][j] x[v][j][k]
-// with the 1D operator M of the direction (tensor product over dim axes).
-template <int DIM>
-__global__ void __launch_bounds__(kThreads) k_transfer(int Ne, int Pin, int Pout, Transfer1D t, bool restr,
-                                                       const double *__restrict__ x, double *__restrict__ y,
-                                                       int nv) {
-    const int Npo = (DIM == 2) ? Pout * Pout : Pout * Pout * Pout;
-    const int Npi = (DIM == 2) ? Pin * Pin : Pin * Pin * Pin;
-    const size_t total = (size_t)nv * Npo * Ne;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-        const int k = (int)(idx % Ne);
-        const size_t vi = idx / Ne;
-        const int i = (int)(vi % Npo);
-        const int v = (int)(vi / Npo);
-        const int i0 = i % Pout, i1 = (i / Pout) % Pout, i2 = (DIM == 3) ? i / (Pout * Pout) : 0;
-        double acc = 0.0;
-        for (int j = 0; j < Npi; ++j) {
-            const int j0 = j % Pin, j1 = (j / Pin) % Pin, j2 = (DIM == 3) ? j / (Pin * Pin) : 0;
-            double w;
-            if (restr) {
-                w = t.G[i0][j0] * t.G[i1][j1];
-                if (DIM == 3) w *= t.G[i2][j2];
-            } else {
-                w = t.Pi[i0][j0] * t.Pi[i1][j1];
-                if (DIM == 3) w *= t.Pi[i2][j2];
+// Restriction / prolongation, sum-factorised: one lane per (variable,
+// element) applies the 1D operator M (PO x PI) along x, then y (then z), all
+// in registers.  Compile-time sizes let the operator entries come from the
+// kernel-argument segment with uniform indices.
+struct Mat1D {
+    double m[kMaxP][kMaxP];
+};
+
+template <int DIM, int PI, int PO>
+__global__ void __launch_bounds__(kThreads) k_transfer_sf(int Ne, int nv, Mat1D M, const double *__restrict__ x,
+                                                          double *__restrict__ y) {
+    constexpr int NI = (DIM == 2) ? PI * PI : PI * PI * PI;
+    constexpr int NO = (DIM == 2) ? PO * PO : PO * PO * PO;
+    constexpr int PZI = (DIM == 2) ? 1 : PI;
+    constexpr int PZO = (DIM == 2) ? 1 : PO;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nv * Ne) return;
+    const int k = idx % Ne, v = idx / Ne;
+    double a[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) a[j] = x[((size_t)v * NI + j) * Ne + k];
+    double b[PZI * PI * PO];  // [z][y][x_out]
+#pragma unroll
+    for (int z = 0; z < PZI; ++z)
+#pragma unroll
+        for (int yy = 0; yy < PI; ++yy)
+#pragma unroll
+            for (int o = 0; o < PO; ++o) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < PI; ++j) s += M.m[o][j] * a[(z * PI + yy) * PI + j];
+                b[(z * PI + yy) * PO + o] = s;
             }
-            acc += w * x[((size_t)v * Npi + j) * Ne + k];
-        }
-        y[idx] = acc;
+    double c[PZI * PO * PO];  // [z][y_out][x_out]
+#pragma unroll
+    for (int z = 0; z < PZI; ++z)
+#pragma unroll
+        for (int o1 = 0; o1 < PO; ++o1)
+#pragma unroll
+            for (int o0 = 0; o0 < PO; ++o0) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < PI; ++j) s += M.m[o1][j] * b[(z * PI + j) * PO + o0];
+                c[(z * PO + o1) * PO + o0] = s;
+            }
+    if (DIM == 2) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) y[((size_t)v * NO + o) * Ne + k] = c[o];
+    } else {
+#pragma unroll
+        for (int o2 = 0; o2 < PZO; ++o2)
+#pragma unroll
+            for (int o = 0; o < PO * PO; ++o) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < PZI; ++j) s += M.m[o2][j] * c[j * PO * PO + o];
+                y[((size_t)v * NO + o2 * PO * PO + o) * Ne + k] = s;
+            }
     }
+}
+
+template <int DIM, int PI, int PO>
+void launch_sf(int Ne, int nv, const Mat1D &M, const double *x, double *y, hipStream_t s) {
+    const int n = nv * Ne;
+    hipLaunchKernelGGL((k_transfer_sf<DIM, PI, PO>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, Ne,
+                       nv, M, x, y);
+}
+
+template <int DIM>
+bool dispatch_sf(int PI, int PO, int Ne, int nv, const Mat1D &M, const double *x, double *y, hipStream_t s) {
+#define FR_SF(a, b) \
+    if (PI == a && PO == b) { launch_sf<DIM, a, b>(Ne, nv, M, x, y, s); return true; }
+    FR_SF(2, 3) FR_SF(2, 4) FR_SF(3, 2) FR_SF(3, 4) FR_SF(4, 2) FR_SF(4, 3) FR_SF(2, 1) FR_SF(1, 2)
+    FR_SF(3, 1) FR_SF(1, 3) FR_SF(4, 1) FR_SF(1, 4)
+    if (DIM == 2) {
+        FR_SF(5, 2) FR_SF(2, 5) FR_SF(5, 3) FR_SF(3, 5) FR_SF(5, 4) FR_SF(4, 5) FR_SF(5, 1) FR_SF(1, 5)
+    }
+#undef FR_SF
+    return false;
 }
 
 }  // namespace
@@ -231,13 +279,12 @@ hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_di
     const int Pin = restrict_dir ? t.P0 : t.P1;
     const int Pout = restrict_dir ? t.P1 : t.P0;
     const int Ne = ctx->mesh.Ne;
-    const size_t total = (size_t)ctx->nv * ctx->lv[restrict_dir ? fine_level + 1 : fine_level].Np * Ne;
-    if (ctx->dim == 2)
-        hipLaunchKernelGGL(k_transfer<2>, dim3(grid_for(total)), dim3(kThreads), 0, s, Ne, Pin, Pout, t,
-                           restrict_dir, x, y, ctx->nv);
-    else
-        hipLaunchKernelGGL(k_transfer<3>, dim3(grid_for(total)), dim3(kThreads), 0, s, Ne, Pin, Pout, t,
-                           restrict_dir, x, y, ctx->nv);
+    Mat1D M{};
+    for (int o = 0; o < Pout; ++o)
+        for (int j = 0; j < Pin; ++j) M.m[o][j] = restrict_dir ? t.G[o][j] : t.Pi[o][j];
+    const bool ok = (ctx->dim == 2) ? dispatch_sf<2>(Pin, Pout, Ne, ctx->nv, M, x, y, s)
+                                    : dispatch_sf<3>(Pin, Pout, Ne, ctx->nv, M, x, y, s);
+    if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

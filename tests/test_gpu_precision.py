@@ -96,3 +96,27 @@ def test_bf16_mfma_stage_converges_config2(orc):
     F = (qh - b) / (wl.a_ii * wl.dt) - L0.residual(qh)
     print("bf16-mfma factors: %d PTC / %d FGMRES, setup %.4f s" % (st["ptc_iters"], st["gmres_iters"], st["t_setup"]))
     assert np.linalg.norm(F) / np.linalg.norm(2 * R0) <= 1.5e-8
+
+
+def test_bf16_storage_stage_converges_config2(orc):
+    """EJ inverses stored in BF16 (applied with FP64 accumulation): the stage
+    still reaches 1e-8 in the oracle's FP64 F; iteration counts stated."""
+    require_gpu()
+    announce("stage config2 with BF16-stored EJ inverses")
+    wl = W.config2()
+    fr = capi.FR.from_workload(wl)
+    dq = fr.to_dev(wl.dq)
+    sig = 2.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
+    fr.ej_factor(0, dq, sig, capi.PREC_FP64)
+    inv64 = fr.ej_inverse(0)
+    fr.ej_factor(0, dq, sig, capi.PREC_BF16_STORE)
+    e = rel(fr.ej_inverse(0), inv64)
+    q, st = fr.solve_stage(capi.stage_config_for(wl, precision=capi.PREC_BF16_STORE), dq)
+    L0 = orc.Level(**wl.level_kwargs(wl.p0))
+    R0 = L0.residual(wl.dq)
+    b = wl.dq + wl.a_ii * wl.dt * R0
+    qh = q.cpu().numpy()
+    F = (qh - b) / (wl.a_ii * wl.dt) - L0.residual(qh)
+    print("bf16 storage: inverse rel err %.2e; %d PTC / %d FGMRES" % (e, st["ptc_iters"], st["gmres_iters"]))
+    assert e <= 2.0 ** -8
+    assert st["converged"] == 1 and np.linalg.norm(F) / np.linalg.norm(2 * R0) <= 1.5e-8
