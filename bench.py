@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# precision forms of the preconditioner (values of the library's FR_PREC_* codes)
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16s": 3}
 
 
 def measured_traffic():
@@ -90,6 +92,51 @@ def kernel_rates(fr, wl, dq_dev, reps=50):
     return out
 
 
+def kernel_rates_3d(reps=20, nsets=4):
+    """R and JVP at the 3D workload (32^3 hexes, p = 3, 10,485,760 DOF, 84 MB
+    per vector), rotating over nsets independent buffer sets (> 1 GB in all)
+    so that the 256 MB last-level cache cannot serve them from one launch to
+    the next."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    wl = W.config4()
+    fr = capi.FR.from_workload(wl, levels=[wl.p0])
+    N = wl.dof()
+    base = fr.to_dev(wl.dq)
+    sets = []
+    for i in range(nsets):
+        dq = base + 1e-4 * torch.randn_like(base) if i else base
+        v = torch.randn_like(base)
+        v /= torch.linalg.norm(v)
+        sets.append(dict(dq=dq, rq=fr.residual(0, dq), v=v, out=fr.empty(0)))
+    sig = 1.0 / (wl.a_ii * wl.dt)
+    it = {"i": 0}
+
+    def nxt():
+        it["i"] = (it["i"] + 1) % nsets
+        return sets[it["i"]]
+
+    def r_call():
+        b = nxt()
+        fr.residual(0, b["dq"], out=b["out"])
+
+    def j_call():
+        b = nxt()
+        fr.jvp(0, b["dq"], b["rq"], b["v"], sig, out=b["out"])
+    out = {
+        "residual_3d": dict(s_per_call=_events_time(r_call, reps), alg_bytes=16.0 * N, launches=3),
+        "jvp_3d": dict(s_per_call=_events_time(j_call, reps), alg_bytes=32.0 * N, launches=6),
+    }
+    for d in out.values():
+        d["GBps"] = d["alg_bytes"] / d["s_per_call"] / 1e9
+        d["frac_hbm"] = d["GBps"] / HBM_PEAK_GBS
+    fr.close()
+    del sets, base
+    torch.cuda.empty_cache()
+    return out
+
+
 def fr_prec(fr):
     return getattr(fr, "_last_prec", 0)
 
@@ -152,8 +199,17 @@ def cpu_baseline(wl, st, max_seconds=25.0):
                 seconds_extrapolated=total)
 
 
-def only_kernel(fr, wl, dq, args, prec):
+def only_kernel(args):
+    """Profiling driver: build the chosen workload's state, launch one kernel
+    family --reps times, then a plain 256 MiB device copy whose counter
+    readings calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    wl = W.config2() if args.workload == "config2" else W.config4()
+    fr = capi.FR.from_workload(wl)
+    prec = PRECISIONS[args.precision]
+    dq = fr.to_dev(wl.dq)
     sig = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
     x = torch.randn_like(dq)
     y = fr.empty(0)
@@ -161,15 +217,18 @@ def only_kernel(fr, wl, dq, args, prec):
         fr.ej_factor(0, dq, sig, prec)
     rq = fr.residual(0, dq)
     torch.cuda.synchronize()
+    print("[bench] only-kernel %s on %s, precision %s" % (args.only_kernel, args.workload, args.precision),
+          file=sys.stderr, flush=True)
     for _ in range(args.reps):
         if args.only_kernel == "ej_apply":
             fr.ej_solve(0, x, out=y)
+        elif args.only_kernel == "ej_factor":
+            fr.ej_factor(0, dq, sig, prec)
         elif args.only_kernel == "residual":
             fr.residual(0, dq, out=y)
         else:
             fr.jvp(0, dq, rq, x, sig, out=y)
     torch.cuda.synchronize()
-    # calibration: a plain device copy of exactly 256 MiB read + 256 MiB written
     a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dq.device).normal_()
     b = torch.empty_like(a)
     for _ in range(3):
@@ -185,10 +244,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the EJ-only comparison and kernel rates")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "residual", "jvp"],
-                    help="profiling driver: set up the config-2 state, launch one kernel family --reps times "
+    ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
+    ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "ej_factor", "residual", "jvp"],
+                    help="profiling driver: set up the workload's state, launch one kernel family --reps times "
                          "and a 256 MiB device copy (counter calibration), print nothing else")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config4"],
+                    help="workload of the --only-kernel driver")
     ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -200,16 +261,16 @@ def main():
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
 
+    if args.only_kernel:
+        only_kernel(args)
+        return
     wl = W.config2()
     fr = capi.FR.from_workload(wl)
-    prec = capi.PREC_FP64 if args.precision == "fp64" else capi.PREC_FP32
+    prec = PRECISIONS[args.precision]
     fr._last_prec = prec
     dq = fr.to_dev(wl.dq)
     cfg = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=prec)
     out = fr.empty(0)
-    if args.only_kernel:
-        only_kernel(fr, wl, dq, args, prec)
-        return
     print("[bench] warmup %d stage solve(s)" % args.warmup, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         _, st = fr.solve_stage(cfg, dq, out=out)
@@ -240,7 +301,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == capi.PREC_FP64 else "f64 (EJ factors f32)",
+        "dtype": "f64" if prec == capi.PREC_FP64 else "f64 (EJ factors %s)" % args.precision,
         "data": "synthetic",
         "config": {
             "workload": "config2: 2D NS FR 64x64 y-stretched (AR 1-100), p=4 (409,600 DOF), Ma 1e-3, ESDIRK3 "
@@ -291,6 +352,8 @@ def main():
         fr.solve_stage(cfg, dq, out=out)
         print("[bench] kernel rates", file=sys.stderr, flush=True)
         rates = kernel_rates(fr, wl, dq)
+        print("[bench] kernel rates, 3D workload", file=sys.stderr, flush=True)
+        rates.update(kernel_rates_3d())
         result["kernels"] = rates
         dom = rates["ej_apply_fine"]
         result["roofline"] = {
