@@ -108,10 +108,11 @@ fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, 
 /* Element-Jacobi setup (Sec. 2.2, element-Jacobi preconditioner; the
  * preconditioner matrix is evaluated once per physical time step):
  * forms B_k = sigma I - dR_k/dq_k at dq_lin for every element by one-sided
- * finite differences per block column (step 1e-7 max(1, |q_j|), taken as
- * the representable difference), then inverts every block by Gauss-Jordan
- * elimination with partial pivoting and stores the inverse in the requested
- * precision.  Needs an even element count per axis (parity colouring).
+ * finite differences per block column with element k alone perturbed (step
+ * 1e-7 max(1, |q_j|), taken as the representable difference), then inverts
+ * every block by Gauss-Jordan elimination with partial pivoting and stores
+ * the inverse in the requested precision.  Needs at least two elements per
+ * axis (FR_EINVAL otherwise).
  * Returns FR_ESINGULAR if a block has an exact zero pivot.  Synchronises the
  * stream at the end (to report the pivot status). */
 fr_status ej_factor(frpmg_ctx *ctx, int level, const double *dq_lin, double sigma, int precision,

@@ -133,15 +133,17 @@ void jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const do
     residual_lin(ctx, level, dq, v, h, rq, shift, nullptr, w, s);
 }
 
-void check_even(frpmg_ctx *ctx) {
+// The element-local block formation takes the face neighbours as
+// unperturbed: each must differ from the element itself.
+void check_neighbours(frpmg_ctx *ctx) {
     for (int a = 0; a < ctx->dim; ++a)
-        REQUIRE(ctx->mesh.n[a] % 2 == 0, "EJ formation needs an even element count per axis");
+        REQUIRE(ctx->mesh.n[a] >= 2, "EJ formation needs at least two elements per axis");
 }
 
 void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, int precision, hipStream_t s) {
     REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
     REQUIRE(precision >= FR_PREC_FP64 && precision <= FR_PREC_BF16_STORE, "bad precision");
-    check_even(ctx);
+    check_neighbours(ctx);
     Level &L = ctx->lv[level];
     REQUIRE(L.nb <= 512, "EJ block too large (n_b > 512)");
     const size_t nblk = (size_t)ctx->mesh.Ne * L.nb * L.nb;
@@ -161,22 +163,14 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
         HIPCHK(hipMalloc(&p, nblk * sizeof(__bf16)));
         L.inv16 = (__bf16 *)p;
     }
+    if (!L.fQp) {
+        const size_t nface = (size_t)ctx->dim * ctx->nv * L.NF * ctx->mesh.Ne;
+        L.fQp = dalloc(ctx, nface);
+        L.fSn = dalloc(ctx, nface);
+        L.fGt = dalloc(ctx, nface * (ctx->dim - 1));
+    }
     HIPCHK(hipMemsetAsync(L.dstatus, 0, sizeof(int), s));
-    residual(ctx, level, dq, L.r0, s);
-    const int ncol = 1 << ctx->dim;
-    for (int colour = 0; colour < ncol; ++colour)
-        for (int col = 0; col < L.nb; ++col) {
-            ResidualArgs a;
-            a.src = SRC_FDCOL;
-            a.dq = dq;
-            a.colour = colour;
-            a.col = col;
-            a.out = OUT_EJCOL;
-            a.r0 = L.r0;
-            a.sigma = sigma;
-            a.blocks = L.blk64;
-            HIPCHK(launch_residual(ctx, level, a, s));
-        }
+    HIPCHK(launch_ej_form(ctx, level, dq, sigma, s));
     HIPCHK(ej_invert(ctx, level, precision, s));
     int flag = 0;
     HIPCHK(hipMemcpyAsync(ctx->host_pinned, L.dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -844,6 +838,9 @@ void destroy_all(frpmg_ctx *ctx) {
         Level &L = ctx->lv[l];
         dfree(L.Tm);
         dfree(L.Fs);
+        dfree(L.fQp);
+        dfree(L.fSn);
+        dfree(L.fGt);
         dfree(L.blk64);
         dfree(L.inv32);
         dfree(L.inv16);

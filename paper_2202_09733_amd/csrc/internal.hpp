@@ -22,6 +22,8 @@ struct Ops1D {
     double bp[kMaxP];        // l_j(+1)
     double gLd[kMaxP];       // derivative of the left correction at xi_i
     double gRd[kMaxP];       // derivative of the right correction at xi_i
+    double dnp[kMaxP];       // sum_i l_i(+1) D[i][j]: derivative values interpolated to +1
+    double cgp;              // sum_i l_i(+1) gRd[i]: right-correction derivative interpolated to +1
 };
 
 // 1D transfer operators between two levels (fine P0, coarse P1 points).
@@ -52,22 +54,20 @@ struct Scal {
 };
 
 // How a residual launch forms the state it evaluates R at.
-enum SrcMode { SRC_PLAIN = 0, SRC_AXPY = 1, SRC_FDCOL = 2 };
+enum SrcMode { SRC_PLAIN = 0, SRC_AXPY = 1 };
 // What a residual launch writes.
-enum OutMode { OUT_R = 0, OUT_LIN = 1, OUT_EJCOL = 2 };
+enum OutMode { OUT_R = 0, OUT_LIN = 1 };
 
 struct ResidualArgs {
     SrcMode src = SRC_PLAIN;
     const double *dq = nullptr;   // base state deviation
     const double *v = nullptr;    // direction (SRC_AXPY)
     Scal alpha{1.0, nullptr};     // state = dq + alpha v
-    int colour = 0, col = 0;      // SRC_FDCOL: perturbed colour and block column
     OutMode out = OUT_R;
     double *r = nullptr;          // OUT_R / OUT_LIN destination
-    const double *r0 = nullptr;   // OUT_LIN / OUT_EJCOL: R at the base state
+    const double *r0 = nullptr;   // OUT_LIN: R at the base state
     const double *x = nullptr;    // OUT_LIN: optional subtrahend
-    double sigma = 0.0;           // OUT_LIN / OUT_EJCOL shift
-    double *blocks = nullptr;     // OUT_EJCOL: [Ne][nb][nb] column-major blocks
+    double sigma = 0.0;           // OUT_LIN shift
 };
 
 template <typename T>
@@ -82,6 +82,10 @@ struct Level {
     Ops1D ops{};
     double *Tm = nullptr;  // minus traces [dim][nv][NF][Ne]
     double *Fs = nullptr;  // common fluxes on + faces [dim][nv][NF][Ne]
+    // face data of the EJ linearisation point (allocated at the first factorisation)
+    double *fQp = nullptr;  // + traces [dim][nv][NF][Ne]
+    double *fSn = nullptr;  // D part of the normal gradient at + faces [dim][nv][NF][Ne]
+    double *fGt = nullptr;  // tangential gradients at + faces [dim][dim-1][nv][NF][Ne]
     // element-Jacobi storage: FP64 work blocks and the inverse
     double *blk64 = nullptr;  // [Ne][nb][nb], column-major per block
     void *inv = nullptr;      // inverse: points to blk64 (FP64) or inv32
@@ -133,6 +137,8 @@ void gauss_legendre(int P, double *x, double *w);
 
 // residual.hip
 hipError_t launch_residual(const frpmg_ctx *ctx, int level, const ResidualArgs &a, hipStream_t s);
+// r0 = R(dq) and the FP64 blocks sigma I - dR_k/dq_k of every element into L.blk64
+hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s);
 
 // vec.hip
 hipError_t vec_dot(frpmg_ctx *ctx, size_t n, const double *x, const double *y, double *dout, hipStream_t s);

@@ -99,6 +99,14 @@ void build_ops1d(int P, Ops1D &o) {
         o.gLd[i] = 0.5 * sgn * (dLp - dLq);
         o.gRd[i] = 0.5 * (dLp + dLq);
     }
+    // the + end value of the nodal interpolant of D q and of gRd
+    o.cgp = 0.0;
+    for (int j = 0; j < P; ++j) {
+        double sdn = 0.0;
+        for (int i = 0; i < P; ++i) sdn += o.bp[i] * o.D[i][j];
+        o.dnp[j] = sdn;
+        o.cgp += o.bp[j] * o.gRd[j];
+    }
 }
 
 void build_transfer(int P0, int P1, Transfer1D &t) {

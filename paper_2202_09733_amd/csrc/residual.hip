@@ -9,33 +9,50 @@
 // penalty tau (q_R - q_L)).
 //
 // Three launches per evaluation, exchanging face data through L2/HBM:
-//   1. k_traces : minus-end traces of the state along every axis      [dim][nv][NF][Ne]
-//   2. k_faces  : corrected gradient per element, then the common flux on
-//                 each element's + faces (Roe - LDG viscous)           [dim][nv][NF][Ne]
-//   3. k_volume : corrected gradient again, pointwise fluxes, flux traces,
-//                 divergence plus FR corrections -> R (or a fused output)
+//   1. k_traces : minus-end traces of the state along every axis, from one
+//                 LDS-staged pass over the state                       [dim][nv][NF][Ne]
+//   2. k_faces  : the common flux on each element's + faces.  The corrected
+//                 gradient is needed there only as a + face trace, which is
+//                 formed by sum factorisation from the state's face traces
+//                 (normal part: a 1D row operator; tangential parts: D along
+//                 the face plus the + end value of the neighbouring faces'
+//                 jumps), so no volume gradient is formed.   [dim][nv][NF][Ne]
+//   3. k_volume : corrected gradient (registers), pointwise fluxes one
+//                 direction at a time through LDS, divergence plus FR
+//                 corrections -> R (or a fused output).
+// Face quantities that every solution point on a line needs (state jumps
+// q* - q+, flux jumps F* - f-/+) are formed once per face point.
 // Elements are processed EB at a time per workgroup, staged in LDS as
 // [var][point][element] so that consecutive lanes touch consecutive elements
 // (the HBM layout has the element index fastest, so global loads coalesce).
 //
 // State convention: every kernel evaluates at the deviation dq from the
-// reference state, possibly plus a perturbation (SRC_AXPY: dq + alpha v;
-// SRC_FDCOL: one block column perturbed in all elements of one parity
-// colour).  Fluxes are formed as f(q) - f(q_inf) through identities exact in
-// real arithmetic, so R(0) = 0 exactly.
+// reference state, possibly plus a direction (SRC_AXPY: dq + alpha v).
+// Fluxes are formed as f(q) - f(q_inf) through identities exact in real
+// arithmetic, so R(0) = 0 exactly.
+//
+// The element-Jacobi blocks are formed element-locally (k_ej_form, below).
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace frpmg {
 
 namespace {
 
+constexpr int round64(int n) { return ((n + 63) / 64) * 64; }
+
 template <int DIM, int P>
 struct Shape {
     static constexpr int NV = DIM + 2;
     static constexpr int NP = (DIM == 2) ? P * P : P * P * P;
     static constexpr int NF = (DIM == 2) ? P : P * P;
-    static constexpr int EB = (256 / NP) > 0 ? (256 / NP) : 1;  // elements per workgroup
-    static constexpr int NT = ((NP * EB + 63) / 64) * 64;      // threads per workgroup
+    // volume kernel: one lane per (element, point)
+    static constexpr int EB = (256 / NP) > 0 ? (256 / NP) : 1;
+    static constexpr int NT = round64(NP * EB);
+    // face kernel: one lane per (element, + face point)
+    static constexpr int EBF = (256 / (DIM * NF)) > 0 ? (256 / (DIM * NF)) : 1;
+    static constexpr int NTF = round64(DIM * NF * EBF);
 
     // local point on the line along axis a through face point f, position j
     __device__ __forceinline__ static int line(int a, int f, int j) {
@@ -60,6 +77,29 @@ struct Shape {
             f = i % (P * P);
         }
     }
+    // index on the face normal to axis a of the point with coordinates x
+    // (the remaining coordinates in increasing axis order, first fastest)
+    __device__ __forceinline__ static int face_index(int a, const int (&x)[3]) {
+        if (DIM == 2) return a == 0 ? x[1] : x[0];
+        if (a == 0) return x[1] + P * x[2];
+        if (a == 1) return x[0] + P * x[2];
+        return x[0] + P * x[1];
+    }
+    __device__ __forceinline__ static void face_coords(int a, int f, int (&x)[3]) {
+        x[0] = x[1] = x[2] = 0;
+        if (DIM == 2) {
+            x[a == 0 ? 1 : 0] = f;
+        } else if (a == 0) {
+            x[1] = f % P;
+            x[2] = f / P;
+        } else if (a == 1) {
+            x[0] = f % P;
+            x[2] = f / P;
+        } else {
+            x[0] = f % P;
+            x[1] = f / P;
+        }
+    }
 };
 
 __device__ __forceinline__ void coords(const MeshK &m, int k, int c[3]) {
@@ -79,10 +119,17 @@ __device__ __forceinline__ int neighbour(const MeshK &m, int k, int a, int s) {
     return c[0] + m.n[0] * (c[1] + m.n[1] * c[2]);
 }
 
-__device__ __forceinline__ int colour_of(const MeshK &m, int k) {
-    int c[3];
-    coords(m, k, c);
-    return (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  Remap the hardware workgroup index so that every XCD
+// processes one contiguous range of logical workgroups: neighbouring
+// elements then share their 128-byte lines and face data through one L2
+// instead of each XCD fetching the same lines again.  A bijection on
+// [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int NX = 8;
+    const int x = b % NX, j = b / NX;
+    const int q = nb / NX, r = nb % NX;
+    return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
 __device__ __forceinline__ double sval(const Scal &s) { return s.p ? *s.p : s.v; }
@@ -91,7 +138,7 @@ struct SrcK {
     const double *dq;
     const double *v;
     Scal alpha;
-    int colour, col, Np;
+    int Np;
 };
 
 // Finite-difference step of one perturbed entry: 1e-7 max(1, |q_inf + dq|).
@@ -100,14 +147,10 @@ __device__ __forceinline__ double fd_step(double qinf_v, double dqv) {
 }
 
 template <int MODE>
-__device__ __forceinline__ double load_state(const SrcK &s, const MeshK &m, const Phys &ph, int v, int i,
-                                             int k, double alpha) {
+__device__ __forceinline__ double load_state(const SrcK &s, const MeshK &m, int v, int i, int k, double alpha) {
     const size_t idx = ((size_t)v * s.Np + i) * m.Ne + k;
     double u = s.dq[idx];
     if (MODE == SRC_AXPY) u = fma(alpha, s.v[idx], u);
-    if (MODE == SRC_FDCOL) {
-        if (v * s.Np + i == s.col && colour_of(m, k) == s.colour) u = u + fd_step(ph.qinf[v], u);
-    }
     return u;
 }
 
@@ -147,38 +190,6 @@ __device__ __forceinline__ void inviscid_dev(const Phys &ph, int a, const PState
 #pragma unroll
     for (int b = 0; b < D; ++b) F[1 + b] = s.dm[a] * s.u[b] + ph.qinf[1 + a] * s.du[b] + (a == b ? s.dp : 0.0);
     F[D + 1] = s.du[a] * (s.E + s.p) + ph.uinf[a] * (s.dE + s.dp);
-}
-
-// viscous flux along a from conservative gradients g[c][v]
-template <int D>
-__device__ __forceinline__ void viscous(const Phys &ph, int a, const PState<D> &s, const double (&g)[D][D + 2],
-                                        double *F) {
-    double gu[D][D];  // gu[b][c] = d u_b / d x_c
-    double ge[D];
-    const double et = s.E * s.irho;
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-        double kin = 0.0;
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-            gu[b][c] = (g[c][1 + b] - s.u[b] * g[c][0]) * s.irho;
-            kin += s.u[b] * gu[b][c];
-        }
-        ge[c] = (g[c][D + 1] - et * g[c][0]) * s.irho - kin;
-    }
-    double div = 0.0;
-#pragma unroll
-    for (int b = 0; b < D; ++b) div += gu[b][b];
-    F[0] = 0.0;
-    double work = 0.0;
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-        double t = ph.mu * (gu[a][b] + gu[b][a]);
-        if (a == b) t -= (2.0 / 3.0) * ph.mu * div;
-        F[1 + b] = t;
-        work += s.u[b] * t;
-    }
-    F[D + 1] = work + (ph.mu * ph.gam / ph.Pr) * ge[a];
 }
 
 // Roe flux along a, deviation form, no entropy fix.
@@ -228,51 +239,117 @@ __device__ __forceinline__ void roe(const Phys &ph, int a, const double *qL, con
     for (int v = 0; v < D + 2; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * dis[v];
 }
 
+
+// Gradients of the primitive variables at one point from the conservative
+// gradients g[c][v]: gu[b][c] = d u_b / d x_c, ge[c] = d e / d x_c (e the
+// specific internal energy), div = div u.  Shared by every flux direction.
+template <int D>
+struct VGrad {
+    double gu[D][D];
+    double ge[D];
+    double div;
+};
+
+template <int D>
+__device__ __forceinline__ void vgrad(const PState<D> &s, const double (&g)[D][D + 2], VGrad<D> &w) {
+    const double et = s.E * s.irho;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        double kin = 0.0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            w.gu[b][c] = (g[c][1 + b] - s.u[b] * g[c][0]) * s.irho;
+            kin += s.u[b] * w.gu[b][c];
+        }
+        w.ge[c] = (g[c][D + 1] - et * g[c][0]) * s.irho - kin;
+    }
+    double div = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) div += w.gu[b][b];
+    w.div = div;
+}
+
+// viscous flux along a (constant mu, Stokes hypothesis, Fourier heat flux)
+template <int D>
+__device__ __forceinline__ void viscous_dir(const Phys &ph, int a, const PState<D> &s, const VGrad<D> &w,
+                                            double *F) {
+    F[0] = 0.0;
+    double work = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        double t = ph.mu * (w.gu[a][b] + w.gu[b][a]);
+        if (a == b) t -= (2.0 / 3.0) * ph.mu * w.div;
+        F[1 + b] = t;
+        work += s.u[b] * t;
+    }
+    F[D + 1] = work + (ph.mu * ph.gam / ph.Pr) * w.ge[a];
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 
+// Index into an LDS array whose trailing dimension is the workgroup slot
+// with stride SL (SL = 0: one copy shared by every slot).
+template <int SL>
+__device__ __forceinline__ int sidx(int base, int e) {
+    return SL ? base * SL + e : base;
+}
+
+// Minus-end traces along every axis of TE elements per workgroup: the state
+// is staged once in LDS (one coalesced pass over q), then every (axis,
+// variable, face point, element) trace is formed from it.
+template <int DIM, int P>
+struct TraceShape {
+    static constexpr int NP = Shape<DIM, P>::NP;
+    static constexpr int NV = DIM + 2;
+    static constexpr int TE = (NV * NP * 16 * 8 <= 48 * 1024) ? 16 : 8;  // elements per workgroup
+};
+
 template <int DIM, int P, int MODE>
-__global__ void __launch_bounds__(256) k_traces(MeshK m, SrcK src, Ops1D ops, Phys ph, double *__restrict__ Tm) {
+__global__ void __launch_bounds__(256) k_traces(MeshK m, SrcK src, Ops1D ops_in, double *__restrict__ Tm) {
     using S = Shape<DIM, P>;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m.Ne) return;
-    const int a = blockIdx.y / S::NF;
-    const int f = blockIdx.y % S::NF;
+    constexpr int TE = TraceShape<DIM, P>::TE, NV = S::NV, NP = S::NP, NF = S::NF;
+    __shared__ Ops1D ops;
+    __shared__ double s_u[NV * NP * TE];
+    if (threadIdx.x == 0) ops = ops_in;
+    const int k0 = xcd_block(blockIdx.x, gridDim.x) * TE;
+    const int ne = min(TE, m.Ne - k0);
     const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
-#pragma unroll
-    for (int v = 0; v < S::NV; ++v) {
+    for (int t = threadIdx.x; t < NV * NP * TE; t += blockDim.x) {
+        const int e = t % TE, vi = t / TE;
+        s_u[t] = (e < ne) ? load_state<MODE>(src, m, vi / NP, vi % NP, k0 + e, alpha) : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < DIM * NV * NF * TE; t += blockDim.x) {
+        const int e = t % TE;
+        const int r = t / TE;  // (a * NV + v) * NF + f
+        const int f = r % NF;
+        const int v = (r / NF) % NV, a = r / (NF * NV);
+        if (e >= ne) continue;
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < P; ++j) s += ops.bm[j] * load_state<MODE>(src, m, ph, v, S::line(a, f, j), k, alpha);
-        Tm[((size_t)(a * S::NV + v) * S::NF + f) * m.Ne + k] = s;
+        for (int j = 0; j < P; ++j) s += ops.bm[j] * s_u[(v * NP + S::line(a, f, j)) * TE + e];
+        Tm[(size_t)r * m.Ne + k0 + e] = s;
     }
 }
 
-// Shared staging of a workgroup's elements: state, neighbour traces, 2/h.
-template <int DIM, int P, int MODE>
-__device__ __forceinline__ void stage_elements(const MeshK &m, const SrcK &src, const Phys &ph,
-                                               const double *__restrict__ Tm, int k0, int ne, double *s_u,
-                                               double *s_t, double *s_ih, double alpha) {
+// Stage the EB elements k0 .. k0 + ne - 1: the state [v][i][e], the
+// + neighbours' minus traces [a][v][f][e] and 2/h per axis [a][e].
+template <int DIM, int P, int MODE, int EB>
+__device__ __forceinline__ void stage_state(const MeshK &m, const SrcK &src, const double *__restrict__ Tm,
+                                            int k0, int ne, double *s_u, double *s_t, double *s_ih,
+                                            double alpha) {
     using S = Shape<DIM, P>;
-    constexpr int EB = S::EB;
     for (int t = threadIdx.x; t < S::NV * S::NP * EB; t += blockDim.x) {
         const int e = t % EB, vi = t / EB;
-        const int v = vi / S::NP, i = vi % S::NP;
-        s_u[t] = (e < ne) ? load_state<MODE>(src, m, ph, v, i, k0 + e, alpha) : 0.0;
+        s_u[t] = (e < ne) ? load_state<MODE>(src, m, vi / S::NP, vi % S::NP, k0 + e, alpha) : 0.0;
     }
     for (int t = threadIdx.x; t < DIM * S::NV * S::NF * EB; t += blockDim.x) {
         const int e = t % EB;
-        int r = t / EB;
-        const int f = r % S::NF;
-        r /= S::NF;
-        const int v = r % S::NV, a = r / S::NV;
-        double val = 0.0;
-        if (e < ne) {
-            const int kn = neighbour(m, k0 + e, a, +1);
-            val = Tm[((size_t)(a * S::NV + v) * S::NF + f) * m.Ne + kn];
-        }
-        s_t[t] = val;
+        const int r = t / EB;  // (a * NV + v) * NF + f
+        const int a = r / (S::NV * S::NF);
+        s_t[t] = (e < ne) ? Tm[(size_t)r * m.Ne + neighbour(m, k0 + e, a, +1)] : 0.0;
     }
     for (int t = threadIdx.x; t < DIM * EB; t += blockDim.x) {
         const int e = t % EB, a = t / EB;
@@ -286,61 +363,147 @@ __device__ __forceinline__ void stage_elements(const MeshK &m, const SrcK &src, 
     }
 }
 
-// Corrected gradient at one point of one staged element (the common solution
-// is the +axis element's trace, so only the + end carries a correction).
-template <int DIM, int P>
-__device__ __forceinline__ void gradient_point(const Ops1D &ops, const double *s_u, const double *s_t,
-                                               const double *s_ih, int e, int i, double (&g)[DIM][DIM + 2]) {
+// State and gradient traces at one point of the + face normal to A of slot
+// e.  s_u [v][i][slot], s_qp = own + traces [a][v][f][slot]; s_t = q* on the
+// + faces and s_ih = 2/h [a], both with slot stride TS (0: shared).  The
+// gradient trace is formed by sum factorisation: the normal component from
+// the row operator dnp = l(+1)^T D and the + end value cgp of the right
+// correction; each tangential component from D along the face applied to
+// the + traces plus the + end value of the jumps on the neighbouring face.
+// Sn receives the normal component's D part before the correction.
+template <int DIM, int P, int A, int EB, int TS>
+__device__ __forceinline__ void plus_face_state(const Ops1D &ops, const double *s_u, const double *s_t,
+                                                const double *s_qp, const double *s_ih, int e, int f,
+                                                double (&qL)[DIM + 2], double (&qR)[DIM + 2],
+                                                double (&g)[DIM][DIM + 2], double (&Sn)[DIM + 2]) {
     using S = Shape<DIM, P>;
-    constexpr int EB = S::EB;
+    constexpr int NV = S::NV, NP = S::NP, NF = S::NF;
+    int x[3];
+    S::face_coords(A, f, x);
+    const double ihA = s_ih[sidx<TS>(A, e)];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int fb = (A * NV + v) * NF + f;
+        qL[v] = s_qp[fb * EB + e];
+        qR[v] = s_t[sidx<TS>(fb, e)];
+        double d = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) d += ops.dnp[j] * s_u[(v * NP + S::line(A, f, j)) * EB + e];
+        Sn[v] = d;
+        d += (qR[v] - qL[v]) * ops.cgp;
+        g[A][v] = ihA * d;
+    }
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        int f, ic;
-        S::split(i, c, f, ic);
-        const double ih = s_ih[c * EB + e];
+        if (c == A) continue;
+        const int ic = x[c];
+        const double ihc = s_ih[sidx<TS>(c, e)];
 #pragma unroll
-        for (int v = 0; v < S::NV; ++v) {
-            double d = 0.0, tp = 0.0;
+        for (int v = 0; v < NV; ++v) {
+            double d = 0.0;
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const double q = s_u[(v * S::NP + S::line(c, f, j)) * EB + e];
-                d += ops.D[ic][j] * q;
-                tp += ops.bp[j] * q;
+            for (int l = 0; l < P; ++l) {
+                int y[3] = {x[0], x[1], x[2]};
+                y[c] = l;
+                d += ops.D[ic][l] * s_qp[((A * NV + v) * NF + S::face_index(A, y)) * EB + e];
             }
-            d += (s_t[((c * S::NV + v) * S::NF + f) * EB + e] - tp) * ops.gRd[ic];
-            g[c][v] = ih * d;
+            double jt = 0.0;
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                int y[3] = {x[0], x[1], x[2]};
+                y[A] = i;
+                const int fj = (c * NV + v) * NF + S::face_index(c, y);
+                jt += ops.bp[i] * (s_t[sidx<TS>(fj, e)] - s_qp[fj * EB + e]);
+            }
+            d += jt * ops.gRd[ic];
+            g[c][v] = ihc * d;
         }
     }
 }
 
-template <int DIM, int P, int MODE>
-__global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_faces(MeshK m, SrcK src, Ops1D ops_in, Phys ph,
-                                                            const double *__restrict__ Tm,
-                                                            double *__restrict__ Fs) {
+// Common flux along A from the two states and the -axis side's gradient:
+// F* = Roe(qL, qR) - (f^V(qL, g) + tau (qR - qL)).
+template <int DIM, int A>
+__device__ __forceinline__ void common_flux(const Phys &ph, const double (&qL)[DIM + 2], const double (&qR)[DIM + 2],
+                                            const double (&g)[DIM][DIM + 2], double (&F)[DIM + 2]) {
+    constexpr int NV = DIM + 2;
+    double Fv[NV], Fr[NV];
+    {
+        PState<DIM> sL;
+        pstate<DIM>(ph, qL, sL);
+        VGrad<DIM> w;
+        vgrad<DIM>(sL, g, w);
+        viscous_dir<DIM>(ph, A, sL, w, Fv);
+    }
+    roe<DIM>(ph, A, qL, qR, Fr);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = Fr[v] - (Fv[v] + ph.tau * (qR[v] - qL[v]));
+}
+
+// Face data of the linearisation point kept for the element-local EJ
+// formation: per + face of its owner, the owner's + trace, the D part of the
+// normal gradient and the tangential gradient components.
+struct FaceSave {
+    double *Qp;  // [a][v][f][Ne]
+    double *Sn;  // [a][v][f][Ne]
+    double *Gt;  // [a][c'][v][f][Ne], c' over the axes other than a in increasing order
+};
+
+template <int DIM, int P, int A, int EB, bool SAVE>
+__device__ __forceinline__ void face_flux(const MeshK &m, const Ops1D &ops, const Phys &ph, const double *s_u,
+                                          const double *s_t, const double *s_qp, const double *s_ih, int e,
+                                          int f, int k, double *__restrict__ Fs, const FaceSave &sv) {
     using S = Shape<DIM, P>;
-    constexpr int EB = S::EB, NV = S::NV, NP = S::NP, NF = S::NF;
+    constexpr int NV = S::NV, NF = S::NF;
+    double qL[NV], qR[NV], g[DIM][NV], Sn[NV], F[NV];
+    plus_face_state<DIM, P, A, EB, EB>(ops, s_u, s_t, s_qp, s_ih, e, f, qL, qR, g, Sn);
+    if (SAVE) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t o = ((size_t)(A * NV + v) * NF + f) * m.Ne + k;
+            sv.Qp[o] = qL[v];
+            sv.Sn[o] = Sn[v];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                if (c == A) continue;
+                const int cc = c < A ? c : c - 1;
+                sv.Gt[((size_t)((A * (DIM - 1) + cc) * NV + v) * NF + f) * m.Ne + k] = g[c][v];
+            }
+        }
+    }
+    common_flux<DIM, A>(ph, qL, qR, g, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fs[((size_t)(A * NV + v) * NF + f) * m.Ne + k] = F[v];
+}
+
+template <int DIM, int P, int MODE, bool SAVE>
+__global__ void __launch_bounds__((Shape<DIM, P>::NTF)) k_faces(MeshK m, SrcK src, Ops1D ops_in, Phys ph,
+                                                             const double *__restrict__ Tm,
+                                                             double *__restrict__ Fs, FaceSave sv) {
+    using S = Shape<DIM, P>;
+    constexpr int EB = S::EBF, NV = S::NV, NP = S::NP, NF = S::NF;
+    constexpr int NFACE = DIM * NV * NF * EB;
     __shared__ Ops1D ops;
     __shared__ double s_u[NV * NP * EB];
-    __shared__ double s_t[DIM * NV * NF * EB];
-    __shared__ double s_g[DIM * NV * NP * EB];
+    __shared__ double s_t[NFACE];   // q* on the + faces (the + neighbour's minus trace)
+    __shared__ double s_qp[NFACE];  // q+ (own plus trace)
     __shared__ double s_ih[DIM * EB];
     if (threadIdx.x == 0) ops = ops_in;
-    const int k0 = blockIdx.x * EB;
+    const int k0 = xcd_block(blockIdx.x, gridDim.x) * EB;
     const int ne = min(EB, m.Ne - k0);
     const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
-    stage_elements<DIM, P, MODE>(m, src, ph, Tm, k0, ne, s_u, s_t, s_ih, alpha);
+    stage_state<DIM, P, MODE, EB>(m, src, Tm, k0, ne, s_u, s_t, s_ih, alpha);
     __syncthreads();
-    {
-        const int t = threadIdx.x;
-        const int e = t % EB, i = t / EB;
-        if (t < NP * EB && e < ne) {
-            double g[DIM][DIM + 2];
-            gradient_point<DIM, P>(ops, s_u, s_t, s_ih, e, i, g);
+    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
+        const int e = t % EB;
+        int r = t / EB;
+        const int f = r % NF;
+        r /= NF;
+        const int v = r % NV, a = r / NV;
+        double s = 0.0;
 #pragma unroll
-            for (int c = 0; c < DIM; ++c)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) s_g[((c * NV + v) * NP + i) * EB + e] = g[c][v];
-        }
+        for (int j = 0; j < P; ++j) s += ops.bp[j] * s_u[(v * NP + S::line(a, f, j)) * EB + e];
+        s_qp[t] = s;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < DIM * NF * EB; t += blockDim.x) {
@@ -348,32 +511,102 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_faces(MeshK m, SrcK src
         const int r = t / EB;
         const int f = r % NF, a = r / NF;
         if (e >= ne) continue;
-        double qL[NV], qR[NV], gL[DIM][DIM + 2];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < P; ++j) s += ops.bp[j] * s_u[(v * NP + S::line(a, f, j)) * EB + e];
-            qL[v] = s;
-            qR[v] = s_t[((a * NV + v) * NF + f) * EB + e];
+        if (a == 0) {
+            face_flux<DIM, P, 0, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, sv);
+        } else if (a == 1) {
+            face_flux<DIM, P, 1, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, sv);
+        } else {
+            if constexpr (DIM == 3) face_flux<DIM, P, 2, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, sv);
         }
+    }
+}
+
+// Divergence part of R at solution point i of slot e (lane active), for EB
+// slots staged as: s_u the state [v][i][slot] (overwritten by the fluxes,
+// one direction at a time), s_t the state jumps q* - q+ on the + faces
+// [a][v][f][slot], s_fm / s_fp the common fluxes on the - / + faces
+// [a][v][f][slot] (overwritten by the flux jumps F* - f-/+), s_ih = 2/h with
+// slot stride IHS.  Every lane of the workgroup calls it (it holds barriers);
+// acc receives sum_a (2/h_a)[D f_a + (F*- - f-) gL' + (F*+ - f+) gR'] = -R.
+template <int DIM, int P, int EB, int IHS>
+__device__ __forceinline__ void divergence(const Ops1D &ops, const Phys &ph, double *s_u, const double *s_t,
+                                           double *s_fm, double *s_fp, const double *s_ih, bool active, int e,
+                                           int i, double (&acc)[DIM + 2]) {
+    using S = Shape<DIM, P>;
+    constexpr int NV = S::NV, NP = S::NP, NF = S::NF;
+    PState<DIM> st;
+    VGrad<DIM> vg;
+    if (active) {
+        double g[DIM][NV];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c)
+        for (int c = 0; c < DIM; ++c) {
+            int f, ic;
+            S::split(i, c, f, ic);
+            const double ih = s_ih[sidx<IHS>(c, e)];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                double s = 0.0;
+                double d = 0.0;
 #pragma unroll
-                for (int j = 0; j < P; ++j) s += ops.bp[j] * s_g[((c * NV + v) * NP + S::line(a, f, j)) * EB + e];
-                gL[c][v] = s;
+                for (int j = 0; j < P; ++j) d += ops.D[ic][j] * s_u[(v * NP + S::line(c, f, j)) * EB + e];
+                d += s_t[((c * NV + v) * NF + f) * EB + e] * ops.gRd[ic];
+                g[c][v] = ih * d;
             }
-        double Fr[NV], Fv[NV];
-        roe<DIM>(ph, a, qL, qR, Fr);
-        PState<DIM> sL;
-        pstate<DIM>(ph, qL, sL);
-        viscous<DIM>(ph, a, sL, gL, Fv);
+        }
+        double q[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-            Fs[((size_t)(a * NV + v) * NF + f) * m.Ne + k0 + e] = Fr[v] - (Fv[v] + ph.tau * (qR[v] - qL[v]));
+        for (int v = 0; v < NV; ++v) q[v] = s_u[(v * NP + i) * EB + e];
+        pstate<DIM>(ph, q, st);
+        vgrad<DIM>(st, g, vg);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double F[NV];
+        if (active) {
+            double FI[NV], FV[NV];
+            inviscid_dev<DIM>(ph, a, st, FI);
+            viscous_dir<DIM>(ph, a, st, vg, FV);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[v] = FI[v] - FV[v];
+        }
+        __syncthreads();  // every read of s_u (state or previous flux) is done
+        if (active) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s_u[(v * NP + i) * EB + e] = F[v];
+        }
+        __syncthreads();
+        // flux jumps on both faces normal to a
+        for (int t2 = threadIdx.x; t2 < NV * NF * EB; t2 += blockDim.x) {
+            const int e2 = t2 % EB;
+            const int r = t2 / EB;
+            const int f = r % NF, v = r / NF;
+            double fm = 0.0, fp = 0.0;
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const double xv = s_u[(v * NP + S::line(a, f, j)) * EB + e2];
+                fm += ops.bm[j] * xv;
+                fp += ops.bp[j] * xv;
+            }
+            const int fi = ((a * NV + v) * NF + f) * EB + e2;
+            s_fm[fi] -= fm;
+            s_fp[fi] -= fp;
+        }
+        __syncthreads();
+        if (active) {
+            int f, ia;
+            S::split(i, a, f, ia);
+            const double ih = s_ih[sidx<IHS>(a, e)];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double d = 0.0;
+#pragma unroll
+                for (int j = 0; j < P; ++j) d += ops.D[ia][j] * s_u[(v * NP + S::line(a, f, j)) * EB + e];
+                const int fi = ((a * NV + v) * NF + f) * EB + e;
+                d += s_fm[fi] * ops.gLd[ia] + s_fp[fi] * ops.gRd[ia];
+                acc[v] += ih * d;
+            }
+        }
     }
 }
 
@@ -383,8 +616,6 @@ struct OutK {
     const double *x;
     const double *vdir;
     double sigma;
-    double *blocks;
-    int nb;
 };
 
 template <int DIM, int P, int MODE, int OUT>
@@ -393,21 +624,21 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK sr
                                                              const double *__restrict__ Fs, OutK o) {
     using S = Shape<DIM, P>;
     constexpr int EB = S::EB, NV = S::NV, NP = S::NP, NF = S::NF;
+    constexpr int NFACE = DIM * NV * NF * EB;
     __shared__ Ops1D ops;
-    __shared__ double s_u[NV * NP * EB];
-    __shared__ double s_t[DIM * NV * NF * EB];
-    __shared__ double s_g[DIM * NV * NP * EB];  // pointwise fluxes
-    __shared__ double s_fp[DIM * NV * NF * EB];
-    __shared__ double s_fm[DIM * NV * NF * EB];
+    __shared__ double s_u[NV * NP * EB];  // the state, then the flux of one direction
+    __shared__ double s_t[NFACE];         // q* on the + faces, then the jump q* - q+
+    __shared__ double s_fm[NFACE];        // F* on the - faces, then F* - f^-
+    __shared__ double s_fp[NFACE];        // F* on the + faces, then F* - f^+
     __shared__ double s_ih[DIM * EB];
     if (threadIdx.x == 0) ops = ops_in;
-    const int k0 = blockIdx.x * EB;
+    const int k0 = xcd_block(blockIdx.x, gridDim.x) * EB;
     const int ne = min(EB, m.Ne - k0);
     const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
-    stage_elements<DIM, P, MODE>(m, src, ph, Tm, k0, ne, s_u, s_t, s_ih, alpha);
-    for (int t = threadIdx.x; t < DIM * NV * NF * EB; t += blockDim.x) {
+    stage_state<DIM, P, MODE, EB>(m, src, Tm, k0, ne, s_u, s_t, s_ih, alpha);
+    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
         const int e = t % EB;
-        const int r = t / EB;  // (a*NV + v)*NF + f
+        const int r = t / EB;  // (a * NV + v) * NF + f
         const int a = r / (NV * NF);
         double vp = 0.0, vm = 0.0;
         if (e < ne) {
@@ -419,100 +650,255 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK sr
         s_fm[t] = vm;
     }
     __syncthreads();
-    const int t = threadIdx.x;
-    const int e = t % EB, i = t / EB;
-    // EJ columns: only elements of the perturbed colour produce output, and
-    // their residual needs no other element's pointwise fluxes
-    const bool active = (t < NP * EB) && (e < ne) && (OUT != OUT_EJCOL || colour_of(m, k0 + e) == src.colour);
-    double g[DIM][DIM + 2];
-    if (active) gradient_point<DIM, P>(ops, s_u, s_t, s_ih, e, i, g);
-    // the gradient stays in registers; s_g now receives the pointwise fluxes
-    if (active) {
-        double q[NV];
+    // state jumps on the + faces (the common solution is q*, so the - faces carry none)
+    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
+        const int e = t % EB;
+        int r = t / EB;
+        const int f = r % NF;
+        r /= NF;
+        const int v = r % NV, a = r / NV;
+        double s = 0.0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q[v] = s_u[(v * NP + i) * EB + e];
-        PState<DIM> st;
-        pstate<DIM>(ph, q, st);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            double FI[NV], FV[NV];
-            inviscid_dev<DIM>(ph, a, st, FI);
-            viscous<DIM>(ph, a, st, g, FV);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) s_g[((a * NV + v) * NP + i) * EB + e] = FI[v] - FV[v];
-        }
+        for (int j = 0; j < P; ++j) s += ops.bp[j] * s_u[(v * NP + S::line(a, f, j)) * EB + e];
+        s_t[t] -= s;
     }
     __syncthreads();
+    const int t = threadIdx.x;
+    const int e = t % EB, i = t / EB;
+    const bool active = (t < NP * EB) && (e < ne);
+    double acc[NV];
+    divergence<DIM, P, EB, EB>(ops, ph, s_u, s_t, s_fm, s_fp, s_ih, active, e, i, acc);
     if (!active) return;
     const int k = k0 + e;
-    double hact = 1.0;
-    bool write_col = true;
-    if (OUT == OUT_EJCOL) {
-        write_col = (colour_of(m, k) == src.colour);
-        const size_t jidx = (size_t)src.col * m.Ne + k;
-        const int jv = src.col / NP;
-        const double base = src.dq[jidx];
-        hact = (base + fd_step(ph.qinf[jv], base)) - base;
-        if (!write_col) return;
-    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        double acc = 0.0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            int f, ia;
-            S::split(i, a, f, ia);
-            double d = 0.0, fm = 0.0, fp = 0.0;
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const double x = s_g[((a * NV + v) * NP + S::line(a, f, j)) * EB + e];
-                d += ops.D[ia][j] * x;
-                fm += ops.bm[j] * x;
-                fp += ops.bp[j] * x;
-            }
-            const int fi = ((a * NV + v) * NF + f) * EB + e;
-            d += (s_fm[fi] - fm) * ops.gLd[ia] + (s_fp[fi] - fp) * ops.gRd[ia];
-            acc += s_ih[a * EB + e] * d;
-        }
-        const double R = -acc;
+        const double R = -acc[v];
         const size_t idx = ((size_t)v * NP + i) * m.Ne + k;
         if (OUT == OUT_R) {
             o.r[idx] = R;
-        } else if (OUT == OUT_LIN) {
+        } else {
             double val = o.sigma * o.vdir[idx] - (R - o.r0[idx]) / alpha;
             if (o.x) val -= o.x[idx];
             o.r[idx] = val;
-        } else {
-            const int row = v * NP + i;
-            double val = -(R - o.r0[idx]) / hact;
-            if (row == src.col) val += o.sigma;
-            o.blocks[(size_t)k * o.nb * o.nb + (size_t)src.col * o.nb + row] = val;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element-Jacobi blocks by element-local one-sided differences
+// ---------------------------------------------------------------------------
+//
+// Column j of B_k = sigma I - dR_k/dq_k is sigma e_j - (R_k(q + h e_j) - R_k(q)) / h
+// with only element k perturbed.  R_k depends on the states of k and of its
+// face neighbours; with k alone perturbed, the neighbours enter only through
+// face data of the unperturbed state: the + neighbours' minus traces (q* on
+// k's + faces) and, for each - face of k (owned by the - neighbour m), m's
+// + trace, the D part of m's normal gradient and m's tangential gradient
+// components there -- the normal gradient at that face changes with k
+// through q* only.  These are saved by one base evaluation; each workgroup
+// then evaluates R_k for EB columns of one element (the slots), with the same
+// arithmetic as a global evaluation.
+
+struct FormK {
+    const double *dq;  // linearisation point
+    const double *Tm;  // base minus traces
+    FaceSave sv;       // base face data
+    const double *r0;  // R at the linearisation point
+    double *blocks;    // [Ne][nb][nb], column-major per block
+    double sigma;
+    int nb;
+};
+
+template <int DIM, int P>
+__global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_ej_form(MeshK m, Ops1D ops_in, Phys ph, FormK fk) {
+    using S = Shape<DIM, P>;
+    constexpr int EB = S::EB, NV = S::NV, NP = S::NP, NF = S::NF;
+    constexpr int NFACE = DIM * NV * NF * EB;
+    constexpr int NSH = DIM * NV * NF;
+    __shared__ Ops1D ops;
+    __shared__ double s_u[NV * NP * EB];   // perturbed states, then the flux of one direction
+    __shared__ double s_qp[NFACE];         // own + traces, then the jumps q* - q+
+    __shared__ double s_qm[NFACE];         // own - traces (q* on the - faces)
+    __shared__ double s_fm[NFACE];         // F* on the - faces, then F* - f^-
+    __shared__ double s_fp[NFACE];         // F* on the + faces, then F* - f^+
+    __shared__ double s_tn[NSH];           // q* on the + faces
+    __shared__ double s_mq[NSH];           // - neighbours' + traces
+    __shared__ double s_ms[NSH];           // - neighbours' normal-gradient D parts
+    __shared__ double s_mg[DIM > 1 ? (DIM - 1) * NSH : 1];  // - neighbours' tangential gradients
+    __shared__ double s_ih[DIM], s_ihm[DIM];
+    if (threadIdx.x == 0) ops = ops_in;
+    const int nb = fk.nb;
+    const int ncb = (nb + EB - 1) / EB;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int k = b / ncb;
+    const int col0 = (b % ncb) * EB;
+    const int ncol = min(EB, nb - col0);
+    for (int t = threadIdx.x; t < NV * NP * EB; t += blockDim.x) {
+        const int e = t % EB, vi = t / EB;
+        const int v = vi / NP;
+        double u = fk.dq[(size_t)vi * m.Ne + k];
+        if (e < ncol && vi == col0 + e) u = u + fd_step(ph.qinf[v], u);
+        s_u[t] = u;
+    }
+    for (int t = threadIdx.x; t < NSH; t += blockDim.x) {
+        const int a = t / (NV * NF);
+        const int mm = neighbour(m, k, a, -1);
+        s_tn[t] = fk.Tm[(size_t)t * m.Ne + neighbour(m, k, a, +1)];
+        s_mq[t] = fk.sv.Qp[(size_t)t * m.Ne + mm];
+        s_ms[t] = fk.sv.Sn[(size_t)t * m.Ne + mm];
+    }
+    for (int t = threadIdx.x; t < (DIM - 1) * NSH; t += blockDim.x) {
+        const int a = t / ((DIM - 1) * NV * NF);
+        s_mg[t] = fk.sv.Gt[(size_t)t * m.Ne + neighbour(m, k, a, -1)];
+    }
+    if (threadIdx.x < DIM) {
+        const int a = threadIdx.x;
+        int c[3];
+        coords(m, k, c);
+        s_ih[a] = m.inv2h[a][c[a]];
+        s_ihm[a] = m.inv2h[a][c[a] > 0 ? c[a] - 1 : m.n[a] - 1];
+    }
+    __syncthreads();
+    // own traces of every slot
+    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
+        const int e = t % EB;
+        int r = t / EB;
+        const int f = r % NF;
+        r /= NF;
+        const int v = r % NV, a = r / NV;
+        double sp = 0.0, sm = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const double x = s_u[(v * NP + S::line(a, f, j)) * EB + e];
+            sp += ops.bp[j] * x;
+            sm += ops.bm[j] * x;
+        }
+        s_qp[t] = sp;
+        s_qm[t] = sm;
+    }
+    __syncthreads();
+    // common fluxes on the 2 DIM faces of every slot
+    for (int t = threadIdx.x; t < 2 * DIM * NF * EB; t += blockDim.x) {
+        const int e = t % EB;
+        int r = t / EB;
+        const int f = r % NF;
+        r /= NF;
+        const int a = r % DIM, side = r / DIM;
+        double qL[NV], qR[NV], g[DIM][NV], F[NV];
+        auto minus_face = [&](auto Ac) {
+            constexpr int A = decltype(Ac)::value;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int fb = (A * NV + v) * NF + f;
+                qL[v] = s_mq[fb];
+                qR[v] = s_qm[fb * EB + e];
+                double d = s_ms[fb];
+                d += (qR[v] - qL[v]) * ops.cgp;
+                g[A][v] = s_ihm[A] * d;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    if (c == A) continue;
+                    const int cc = c < A ? c : c - 1;
+                    g[c][v] = s_mg[((A * (DIM - 1) + cc) * NV + v) * NF + f];
+                }
+            }
+            common_flux<DIM, A>(ph, qL, qR, g, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s_fm[((A * NV + v) * NF + f) * EB + e] = F[v];
+        };
+        auto plus_face = [&](auto Ac) {
+            constexpr int A = decltype(Ac)::value;
+            double Sn[NV];
+            plus_face_state<DIM, P, A, EB, 0>(ops, s_u, s_tn, s_qp, s_ih, e, f, qL, qR, g, Sn);
+            common_flux<DIM, A>(ph, qL, qR, g, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s_fp[((A * NV + v) * NF + f) * EB + e] = F[v];
+        };
+        using A0 = std::integral_constant<int, 0>;
+        using A1 = std::integral_constant<int, 1>;
+        using A2 = std::integral_constant<int, (DIM == 3 ? 2 : 1)>;
+        if (side == 0) {
+            if (a == 0) plus_face(A0{});
+            else if (a == 1) plus_face(A1{});
+            else if constexpr (DIM == 3) plus_face(A2{});
+        } else {
+            if (a == 0) minus_face(A0{});
+            else if (a == 1) minus_face(A1{});
+            else if constexpr (DIM == 3) minus_face(A2{});
+        }
+    }
+    __syncthreads();
+    // state jumps q* - q+ on the + faces
+    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) s_qp[t] = s_tn[t / EB] - s_qp[t];
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int e = t % EB, i = t / EB;
+    const bool active = (t < NP * EB);
+    double acc[NV];
+    divergence<DIM, P, EB, 0>(ops, ph, s_u, s_qp, s_fm, s_fp, s_ih, active, e, i, acc);
+    if (!active || e >= ncol) return;
+    const int col = col0 + e;
+    const double base = fk.dq[(size_t)col * m.Ne + k];
+    const double hact = (base + fd_step(ph.qinf[col / NP], base)) - base;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double R = -acc[v];
+        const int row = v * NP + i;
+        double val = -(R - fk.r0[(size_t)row * m.Ne + k]) / hact;
+        if (row == col) val += fk.sigma;
+        fk.blocks[(size_t)k * nb * nb + (size_t)col * nb + row] = val;
     }
 }
 
 template <int DIM, int P, int MODE, int OUT>
-hipError_t run(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, hipStream_t s) {
+hipError_t run(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, const FaceSave *save, hipStream_t s) {
     using S = Shape<DIM, P>;
     const MeshK &m = ctx->mesh;
-    SrcK src{a.dq, a.v, a.alpha, a.colour, a.col, S::NP};
-    dim3 g0((m.Ne + 255) / 256, DIM * S::NF);
-    hipLaunchKernelGGL((k_traces<DIM, P, MODE>), g0, dim3(256), 0, s, m, src, L.ops, ctx->phys, L.Tm);
-    dim3 g1((m.Ne + S::EB - 1) / S::EB);
-    hipLaunchKernelGGL((k_faces<DIM, P, MODE>), g1, dim3(S::NT), 0, s, m, src, L.ops, ctx->phys, L.Tm, L.Fs);
-    OutK o{a.r, a.r0, a.x, a.v, a.sigma, a.blocks, L.nb};
-    hipLaunchKernelGGL((k_volume<DIM, P, MODE, OUT>), g1, dim3(S::NT), 0, s, m, src, L.ops, ctx->phys, L.Tm,
-                       L.Fs, o);
+    SrcK src{a.dq, a.v, a.alpha, S::NP};
+    constexpr int TE = TraceShape<DIM, P>::TE;
+    hipLaunchKernelGGL((k_traces<DIM, P, MODE>), dim3((m.Ne + TE - 1) / TE), dim3(256), 0, s, m, src, L.ops, L.Tm);
+    const dim3 g1((m.Ne + S::EBF - 1) / S::EBF);
+    if (save) {
+        hipLaunchKernelGGL((k_faces<DIM, P, MODE, true>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, L.Tm,
+                           L.Fs, *save);
+    } else {
+        hipLaunchKernelGGL((k_faces<DIM, P, MODE, false>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, L.Tm,
+                           L.Fs, FaceSave{nullptr, nullptr, nullptr});
+    }
+    OutK o{a.r, a.r0, a.x, a.v, a.sigma};
+    hipLaunchKernelGGL((k_volume<DIM, P, MODE, OUT>), dim3((m.Ne + S::EB - 1) / S::EB), dim3(S::NT), 0, s, m, src,
+                       L.ops, ctx->phys, L.Tm, L.Fs, o);
     return hipGetLastError();
 }
 
 template <int DIM, int P>
-hipError_t dispatch_modes(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, hipStream_t s) {
-    if (a.src == SRC_PLAIN && a.out == OUT_R) return run<DIM, P, SRC_PLAIN, OUT_R>(ctx, L, a, s);
-    if (a.src == SRC_AXPY && a.out == OUT_R) return run<DIM, P, SRC_AXPY, OUT_R>(ctx, L, a, s);
-    if (a.src == SRC_AXPY && a.out == OUT_LIN) return run<DIM, P, SRC_AXPY, OUT_LIN>(ctx, L, a, s);
-    if (a.src == SRC_FDCOL && a.out == OUT_EJCOL) return run<DIM, P, SRC_FDCOL, OUT_EJCOL>(ctx, L, a, s);
+hipError_t dispatch_modes(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, const FaceSave *save,
+                          hipStream_t s) {
+    if (a.src == SRC_PLAIN && a.out == OUT_R) return run<DIM, P, SRC_PLAIN, OUT_R>(ctx, L, a, save, s);
+    if (save) return hipErrorInvalidValue;
+    if (a.src == SRC_AXPY && a.out == OUT_R) return run<DIM, P, SRC_AXPY, OUT_R>(ctx, L, a, nullptr, s);
+    if (a.src == SRC_AXPY && a.out == OUT_LIN) return run<DIM, P, SRC_AXPY, OUT_LIN>(ctx, L, a, nullptr, s);
     return hipErrorInvalidValue;
+}
+
+template <int DIM, int P>
+hipError_t form(const frpmg_ctx *ctx, const Level &L, const double *dq, double sigma, hipStream_t s) {
+    using S = Shape<DIM, P>;
+    const MeshK &m = ctx->mesh;
+    const FaceSave sv{L.fQp, L.fSn, L.fGt};
+    ResidualArgs a;
+    a.src = SRC_PLAIN;
+    a.dq = dq;
+    a.out = OUT_R;
+    a.r = L.r0;
+    hipError_t err = run<DIM, P, SRC_PLAIN, OUT_R>(ctx, L, a, &sv, s);
+    if (err != hipSuccess) return err;
+    const int ncb = (L.nb + S::EB - 1) / S::EB;
+    const size_t nblk = (size_t)m.Ne * ncb;
+    if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    FormK fk{dq, L.Tm, sv, L.r0, L.blk64, sigma, L.nb};
+    hipLaunchKernelGGL((k_ej_form<DIM, P>), dim3((unsigned)nblk), dim3(S::NT), 0, s, m, L.ops, ctx->phys, fk);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -521,16 +907,36 @@ hipError_t launch_residual(const frpmg_ctx *ctx, int level, const ResidualArgs &
     const Level &L = ctx->lv[level];
     if (ctx->dim == 2) {
         switch (L.P) {
-            case 2: return dispatch_modes<2, 2>(ctx, L, a, s);
-            case 3: return dispatch_modes<2, 3>(ctx, L, a, s);
-            case 4: return dispatch_modes<2, 4>(ctx, L, a, s);
-            case 5: return dispatch_modes<2, 5>(ctx, L, a, s);
+            case 2: return dispatch_modes<2, 2>(ctx, L, a, nullptr, s);
+            case 3: return dispatch_modes<2, 3>(ctx, L, a, nullptr, s);
+            case 4: return dispatch_modes<2, 4>(ctx, L, a, nullptr, s);
+            case 5: return dispatch_modes<2, 5>(ctx, L, a, nullptr, s);
         }
     } else {
         switch (L.P) {
-            case 2: return dispatch_modes<3, 2>(ctx, L, a, s);
-            case 3: return dispatch_modes<3, 3>(ctx, L, a, s);
-            case 4: return dispatch_modes<3, 4>(ctx, L, a, s);
+            case 2: return dispatch_modes<3, 2>(ctx, L, a, nullptr, s);
+            case 3: return dispatch_modes<3, 3>(ctx, L, a, nullptr, s);
+            case 4: return dispatch_modes<3, 4>(ctx, L, a, nullptr, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s) {
+    const Level &L = ctx->lv[level];
+    if (!L.fQp || !L.fSn || !L.fGt || !L.blk64) return hipErrorInvalidValue;
+    if (ctx->dim == 2) {
+        switch (L.P) {
+            case 2: return form<2, 2>(ctx, L, dq, sigma, s);
+            case 3: return form<2, 3>(ctx, L, dq, sigma, s);
+            case 4: return form<2, 4>(ctx, L, dq, sigma, s);
+            case 5: return form<2, 5>(ctx, L, dq, sigma, s);
+        }
+    } else {
+        switch (L.P) {
+            case 2: return form<3, 2>(ctx, L, dq, sigma, s);
+            case 3: return form<3, 3>(ctx, L, dq, sigma, s);
+            case 4: return form<3, 4>(ctx, L, dq, sigma, s);
         }
     }
     return hipErrorInvalidValue;
