@@ -193,6 +193,11 @@ typedef struct {
     int stall_window;  /* FR_PRECOND_PMG_LEARNED: fall back to plain pMG when the FGMRES residual */
     double stall_ratio; /*   estimate exceeds stall_ratio x its value stall_window iterations earlier
                              (0: defaults 5 and 0.7); the fallback holds for the rest of the stage */
+    int graphs;        /* 1: each Arnoldi step (preconditioner, JVP, orthogonalisation, normalisation) is
+                          captured once as a HIP graph, cached in the context and replayed on the stream;
+                          0: every kernel is launched from the host.  Both give bitwise identical results
+                          (measured: no faster on MI355X).  Graphs are not used with the learned
+                          preconditioner or while harvesting. */
 } stage_params;
 
 #define FR_MAX_NEWTON_LOG 128

@@ -61,7 +61,8 @@ class StageParams(ctypes.Structure):
                 ("max_ptc", ctypes.c_int), ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("n0", ctypes.c_int), ("n1", ctypes.c_int), ("eps", ctypes.c_double),
                 ("eps_mode", ctypes.c_int), ("scale_mode", ctypes.c_int), ("eps_p", ctypes.c_double),
-                ("skip_setup", ctypes.c_int), ("stall_window", ctypes.c_int), ("stall_ratio", ctypes.c_double)]
+                ("skip_setup", ctypes.c_int), ("stall_window", ctypes.c_int), ("stall_ratio", ctypes.c_double),
+                ("graphs", ctypes.c_int)]
 
 
 class LccHarvestParams(ctypes.Structure):
@@ -191,6 +192,7 @@ class StageConfig:
     skip_setup: int = 0
     stall_window: int = 0
     stall_ratio: float = 0.0
+    graphs: int = 0
 
     def to_c(self):
         return StageParams(**{f[0]: getattr(self, f[0]) for f in StageParams._fields_})

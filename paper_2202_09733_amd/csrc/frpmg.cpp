@@ -79,6 +79,11 @@ enum { SC_JVP_H = 0, SC_JVP_N2 = 1, SC_PMG_S = 2, SC_PMG_INV = 3, SC_PMG_N2 = 4,
 // ---- reduction outputs (slots of ctx->red_out) ----
 constexpr int RO_H1 = 0, RO_H2 = 64, RO_Y = 128, RO_N2 = 192, RO_SIZE = 256;
 
+// operation counts of a stage solve (fine / coarse residuals, EJ applies)
+struct Counters {
+    long R0 = 0, R1 = 0, E0 = 0, E1 = 0;
+};
+
 double host_norm(frpmg_ctx *ctx, size_t n, const double *x, hipStream_t s) {
     HIPCHK(vec_dot(ctx, n, x, x, ctx->red_out + RO_N2, s));
     HIPCHK(hipMemcpyAsync(ctx->host_pinned, ctx->red_out + RO_N2, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -169,6 +174,7 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
         L.fSn = dalloc(ctx, nface);
         L.fGt = dalloc(ctx, nface * (ctx->dim - 1));
     }
+    ctx->graph_epoch++;  // captured steps bake in the factor buffers and precision
     HIPCHK(hipMemsetAsync(L.dstatus, 0, sizeof(int), s));
     HIPCHK(launch_ej_form(ctx, level, dq, sigma, s));
     HIPCHK(ej_invert(ctx, level, precision, s));
@@ -361,10 +367,6 @@ void lcc_rms(frpmg_ctx *ctx, const double *d, float *out) {
 // nonlinear p-multigrid preconditioner
 // ---------------------------------------------------------------------------
 
-struct Counters {
-    long R0 = 0, R1 = 0, E0 = 0, E1 = 0;
-};
-
 void pmg_point(frpmg_ctx *ctx, const double *dq, const double *rq, hipStream_t s) {
     ctx->pt_q = dq;
     ctx->pt_rq = rq;
@@ -448,7 +450,7 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
         residual_lin(ctx, 1, ctx->q1, ctx->cZ0, one, ctx->r1, p.sigma_D, ctx->cd, ctx->cS, s);
         cnt->R1++;
         // coarse sweeps; the first uses G1(Z0) - S1 = -Gamma d = cd
-        HIPCHK(hipMemcpyAsync(ctx->cZ, ctx->cZ0, N1 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(vec_scale_copy(N1, one, ctx->cZ0, ctx->cZ, s));
         HIPCHK(ej_apply(ctx, 1, ctx->cd, -1.0, 1.0, ctx->cZ, s));
         cnt->E1++;
         for (int it = 1; it < p.n1; ++it) {
@@ -523,9 +525,75 @@ struct Stall {
     std::function<void()> on_stall;
 };
 
+void clear_graphs(frpmg_ctx *ctx) {
+    for (auto &g : ctx->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+}
+
+// Launch the captured graph of `body` for this key on s, capturing and
+// instantiating it on first use (on the context's capture stream, so nothing
+// runs while it is recorded).  cnt receives the operation counts of one
+// replay.
+template <typename Body>
+void run_graph(frpmg_ctx *ctx, const std::vector<unsigned long long> &key, Counters *cnt, Body &&body,
+               hipStream_t s) {
+    for (const auto &g : ctx->graphs) {
+        if (g.key == key) {
+            HIPCHK(hipGraphLaunch(g.exec, s));
+            cnt->R0 += g.dR0;
+            cnt->R1 += g.dR1;
+            cnt->E0 += g.dE0;
+            cnt->E1 += g.dE1;
+            return;
+        }
+    }
+    if (ctx->graphs.size() >= 256) clear_graphs(ctx);
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    const Counters before = *cnt;
+    HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        body(ctx->cap_stream);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(ctx->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamEndCapture(ctx->cap_stream, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    StepGraph sg;
+    sg.key = key;
+    sg.exec = ex;
+    sg.dR0 = cnt->R0 - before.R0;
+    sg.dR1 = cnt->R1 - before.R1;
+    sg.dE0 = cnt->E0 - before.E0;
+    sg.dE1 = cnt->E1 - before.E1;
+    ctx->graphs.push_back(std::move(sg));
+    HIPCHK(hipGraphLaunch(ex, s));
+}
+
+// What a captured Arnoldi step depends on besides its index: null when the
+// steps are launched from the host.
+struct GraphUse {
+    std::vector<unsigned long long> key;
+    Counters *cnt = nullptr;
+};
+
+unsigned long long bits(double v) {
+    unsigned long long u;
+    std::memcpy(&u, &v, sizeof(u));
+    return u;
+}
+unsigned long long bits(const void *p) { return (unsigned long long)(uintptr_t)p; }
+
 template <typename MatVec, typename Prec>
 KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m, double tol, int max_restarts,
-                    MatVec &&A, Prec &&M, hipStream_t s, Stall *stall = nullptr) {
+                    MatVec &&A, Prec &&M, hipStream_t s, Stall *stall = nullptr, const GraphUse *gu = nullptr) {
     KrylovResult kr;
     double *V = ctx->V, *Z = ctx->Zk, *w = ctx->kw;
     const size_t ld = N;
@@ -554,16 +622,27 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
         g[0] = beta;
         int jend = 0;
         for (int j = 0; j < m; ++j) {
-            double *vj = V + (size_t)j * ld;
-            double *zj = Z + (size_t)j * ld;
-            M(vj, zj);
-            A(zj, w);
-            // CGS2
-            HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H1, s));
-            HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H1, w, s));
-            HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H2, s));
-            HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H2, w, s));
-            HIPCHK(vec_dot(ctx, N, w, w, ctx->red_out + RO_N2, s));
+            // one Arnoldi step: z_j = M v_j, w = A z_j, CGS2 against v_0..v_j,
+            // v_{j+1} = w / ||w|| (the norm stays on the device)
+            auto step = [&, j](hipStream_t st) {
+                double *vj = V + (size_t)j * ld;
+                double *zj = Z + (size_t)j * ld;
+                M(vj, zj, st);
+                A(zj, w, st);
+                HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H1, st));
+                HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H1, w, st));
+                HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H2, st));
+                HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H2, w, st));
+                HIPCHK(vec_dot(ctx, N, w, w, ctx->red_out + RO_N2, st));
+                HIPCHK(vec_normalize(N, ctx->red_out + RO_N2, w, V + (size_t)(j + 1) * ld, st));
+            };
+            if (gu) {
+                std::vector<unsigned long long> key = gu->key;
+                key.push_back((unsigned long long)j);
+                run_graph(ctx, key, gu->cnt, step, s);
+            } else {
+                step(s);
+            }
             HIPCHK(hipMemcpyAsync(ctx->host_pinned, ctx->red_out, RO_SIZE * sizeof(double), hipMemcpyDeviceToHost,
                                   s));
             HIPCHK(hipStreamSynchronize(s));
@@ -611,14 +690,13 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
                 kr.breakdown = true;
                 break;
             }
-            HIPCHK(vec_scale_copy(N, Scal{1.0 / hn, nullptr}, w, V + (size_t)(j + 1) * ld, s));
             if (kr.res_est <= target) break;
         }
         if (kr.restarted_nonfinite) {
             // discard the cycle; restart from x with the true residual
             kr.restarted_nonfinite = false;
             kr.restarts++;
-            A(x, w);
+            A(x, w, s);
             HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, b, Scal{-1.0, nullptr}, w, s));
             beta = host_norm(ctx, N, w, s);
             if (!std::isfinite(beta)) {
@@ -651,7 +729,7 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
         if (kr.restarts >= max_restarts) return kr;
         kr.restarts++;
         // true residual r = b - A x
-        A(x, w);
+        A(x, w, s);
         HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, b, Scal{-1.0, nullptr}, w, s));
         beta = host_norm(ctx, N, w, s);
         kr.res_est = beta;
@@ -719,8 +797,9 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
         } else {
             ej_factor_impl(ctx, 0, dq_n, sigma_A, P.precision, s);
         }
-        cnt.R0 += 1 + (1 << ctx->dim) * ctx->lv[0].nb;
-        if (pmg) cnt.R1 += 1 + (1 << ctx->dim) * ctx->lv[1].nb;
+        // one base evaluation plus the element-local columns (nb evaluations' worth)
+        cnt.R0 += 1 + ctx->lv[0].nb;
+        if (pmg) cnt.R1 += 1 + ctx->lv[1].nb;
     }
     HIPCHK(hipStreamSynchronize(s));
     const double t1 = now();
@@ -733,13 +812,24 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
         pp.coarse_mode = FR_COARSE_EJ;  // plain pMG for the rest of the stage
         st->fallbacks++;
     };
-    auto prec = [&](const double *v, double *z) {
+    auto prec = [&](const double *v, double *z, hipStream_t st) {
         if (pmg) {
-            pmg_apply_impl(ctx, pp, v, z, s, &cnt);
+            pmg_apply_impl(ctx, pp, v, z, st, &cnt);
         } else {
-            HIPCHK(ej_apply(ctx, 0, v, 1.0, 0.0, z, s));
+            HIPCHK(ej_apply(ctx, 0, v, 1.0, 0.0, z, st));
             cnt.E0++;
         }
+    };
+    // captured Arnoldi steps: everything a step bakes in goes into its key
+    const bool use_graphs = P.graphs && !learned && !(ctx->lcc && ctx->lcc->harvesting);
+    auto graph_use = [&](const double *q, const double *rq) {
+        GraphUse g;
+        g.cnt = &cnt;
+        g.key = {ctx->graph_epoch, (unsigned long long)P.scheme, (unsigned long long)P.precond, bits(sigma_A),
+                 bits(P.eps), (unsigned long long)P.eps_mode, (unsigned long long)P.n0, (unsigned long long)P.n1,
+                 (unsigned long long)P.scale_mode, bits(P.eps_p), bits(q), bits(rq), bits(ctx->V), bits(ctx->Zk),
+                 bits(ctx->kw), (unsigned long long)N};
+        return g;
     };
     fr_status status = FR_OK;
     if (esdirk) {
@@ -762,11 +852,13 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
             }
             HIPCHK(vec_axpby(N, Scal{0.0, nullptr}, nullptr, Scal{-1.0, nullptr}, F, s));  // F <- -F
             HIPCHK(vec_dot(ctx, N, q, q, ctx->scal + SC_DQ_N2, s));
-            auto A = [&](const double *z, double *w) {
-                jvp(ctx, 0, q, rq, z, sigma_A, P.eps, P.eps_mode, w, s, ctx->scal + SC_DQ_N2);
+            auto A = [&](const double *z, double *w, hipStream_t st) {
+                jvp(ctx, 0, q, rq, z, sigma_A, P.eps, P.eps_mode, w, st, ctx->scal + SC_DQ_N2);
                 cnt.R0++;
             };
-            KrylovResult kr = fgmres(ctx, N, F, dx, P.m, P.eta, P.max_restarts, A, prec, s, &stall);
+            const GraphUse gu = graph_use(q, rq);
+            KrylovResult kr = fgmres(ctx, N, F, dx, P.m, P.eta, P.max_restarts, A, prec, s, &stall,
+                                     use_graphs ? &gu : nullptr);
             if (st->ptc_iters < FR_MAX_NEWTON_LOG) st->gmres_per_newton[st->ptc_iters] = kr.iters;
             st->gmres_iters += kr.iters;
             st->restarts += kr.restarts;
@@ -796,11 +888,13 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
             cnt.R1++;
         }
         HIPCHK(vec_dot(ctx, N, dq_n, dq_n, ctx->scal + SC_DQ_N2, s));
-        auto A = [&](const double *z, double *wout) {
-            jvp(ctx, 0, dq_n, R0, z, sigma_A, P.eps, P.eps_mode, wout, s, ctx->scal + SC_DQ_N2);
+        auto A = [&](const double *z, double *wout, hipStream_t st) {
+            jvp(ctx, 0, dq_n, R0, z, sigma_A, P.eps, P.eps_mode, wout, st, ctx->scal + SC_DQ_N2);
             cnt.R0++;
         };
-        KrylovResult kr = fgmres(ctx, N, R0, out, P.m, P.tol, P.max_restarts, A, prec, s, &stall);
+        const GraphUse gu = graph_use(dq_n, R0);
+        KrylovResult kr = fgmres(ctx, N, R0, out, P.m, P.tol, P.max_restarts, A, prec, s, &stall,
+                                 use_graphs ? &gu : nullptr);
         st->gmres_iters = kr.iters;
         st->restarts = kr.restarts;
         st->gmres_per_newton[0] = kr.iters;
@@ -811,7 +905,7 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
         if (kr.nonfinite) status = FR_ENONFINITE;
         else if (!kr.converged) status = FR_ENOCONV;
         // true residual of the FD operator at the solution
-        A(out, w);
+        A(out, w, s);
         HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, R0, Scal{-1.0, nullptr}, w, s));
         const double tr = host_norm(ctx, N, w, s);
         st->true_rel_res = kr.bnorm > 0 ? tr / kr.bnorm : 0.0;
@@ -833,6 +927,9 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
 }
 
 void destroy_all(frpmg_ctx *ctx) {
+    clear_graphs(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    ctx->cap_stream = nullptr;
     lcc_free(ctx);
     for (int l = 0; l < FR_MAX_LEVELS; ++l) {
         Level &L = ctx->lv[l];

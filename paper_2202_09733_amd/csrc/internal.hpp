@@ -100,6 +100,14 @@ struct Level {
 // Reduction scratch: partial sums per block and per vector.
 constexpr int kRedBlocks = 512;
 
+// One captured Arnoldi step: the instantiated graph, the bit patterns of every
+// parameter and pointer it bakes in, and the operation counts of one replay.
+struct StepGraph {
+    std::vector<unsigned long long> key;
+    hipGraphExec_t exec = nullptr;
+    long dR0 = 0, dR1 = 0, dE0 = 0, dE1 = 0;
+};
+
 }  // namespace frpmg
 
 struct frpmg_ctx {
@@ -126,6 +134,10 @@ struct frpmg_ctx {
     double *sq = nullptr, *srq = nullptr, *sF = nullptr, *sb = nullptr, *sdx = nullptr;
     // learned coarse correction (allocated on first use)
     frpmg::Lcc *lcc = nullptr;
+    // captured Arnoldi steps, replayed on the caller's stream
+    hipStream_t cap_stream = nullptr;
+    std::vector<frpmg::StepGraph> graphs;
+    unsigned long long graph_epoch = 0;  // bumped whenever baked-in factors change
 };
 
 namespace frpmg {
@@ -154,6 +166,8 @@ hipError_t vec_scale_copy(size_t n, Scal a, const double *x, double *y, hipStrea
 hipError_t vec_combine(size_t n, int nvec, const double *Z, size_t ldz, const double *c_dev, double *y,
                        hipStream_t s);
 hipError_t vec_fill(size_t n, double v, double *y, hipStream_t s);
+// y = x / sqrt(n2) with the squared norm n2 on the device
+hipError_t vec_normalize(size_t n, const double *n2, const double *x, double *y, hipStream_t s);
 // out = (x - b) * c - r   (stage function)
 hipError_t vec_stage_F(size_t n, const double *x, const double *b, double c, const double *r, double *out,
                        hipStream_t s);

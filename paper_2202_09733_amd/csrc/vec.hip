@@ -96,6 +96,14 @@ __global__ void __launch_bounds__(kThreads) k_scale_copy(size_t n, Scal a, const
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = av * x[i];
 }
 
+// y = x / sqrt(n2): the reciprocal is formed as 1 / sqrt(n2), both correctly rounded
+__global__ void __launch_bounds__(kThreads) k_normalize(size_t n, const double *__restrict__ n2,
+                                                        const double *__restrict__ x, double *__restrict__ y) {
+    const double av = 1.0 / sqrt(*n2);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = av * x[i];
+}
+
 __global__ void __launch_bounds__(kThreads) k_fill(size_t n, double v, double *__restrict__ y) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = v;
@@ -243,6 +251,11 @@ hipError_t vec_combine(size_t n, int nvec, const double *Z, size_t ldz, const do
 
 hipError_t vec_axpby(size_t n, Scal a, const double *x, Scal b, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(kThreads), 0, s, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+hipError_t vec_normalize(size_t n, const double *n2, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_normalize, dim3(grid_for(n)), dim3(kThreads), 0, s, n, n2, x, y);
     return hipGetLastError();
 }
 
