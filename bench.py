@@ -141,68 +141,44 @@ def fr_prec(fr):
     return getattr(fr, "_last_prec", 0)
 
 
-def cpu_baseline(wl, st, max_seconds=25.0):
-    """Oracle (plain FP64 C + numpy, one thread) cost of the same stage:
-    unit costs measured on the workload's own state -- fine and coarse
-    residual, block LU factor and solve, a JVP -- multiplied by the GPU
-    stage's operation counts (R evaluations per level, EJ solves per level,
-    one factorisation per block, Krylov vectors).  Extrapolated, not a full
-    oracle stage solve."""
+def cpu_baseline(wl, st, n_sample_iters=3):
+    """The oracle (plain FP64 C + numpy, one thread) on a bounded sample of
+    the same stage: its preconditioner set-up run in full (EJ blocks of both
+    levels by parity-coloured differencing, block LU), then the first
+    n_sample_iters FGMRES iterations of the first pseudo-time step (nonlinear
+    pMG preconditioner + FD JVP + Gram-Schmidt), timed; extrapolated to the
+    GPU stage's PTC and FGMRES iteration counts."""
     import oracle
-    t_begin = time.perf_counter()
-    L0 = oracle.Level(**wl.level_kwargs(wl.p0))
-    L1 = oracle.Level(**wl.level_kwargs(wl.p1))
-    q1 = oracle.restrict(wl.dq, wl.dim, wl.p0 + 1, wl.p1 + 1)
-
-    def timeit(f, n):
-        t = time.perf_counter()
-        for _ in range(n):
-            f()
-        return (time.perf_counter() - t) / n
-    tR0 = timeit(lambda: L0.residual(wl.dq), 3)
-    tR1 = timeit(lambda: L1.residual(q1), 3)
-    # LU cost depends on sizes only: stand-in well-conditioned blocks
-    rng = np.random.default_rng(0)
-    nsamp = 256
-    Bs0 = np.eye(L0.nb)[None] * 4.0 + 0.01 * rng.standard_normal((nsamp, L0.nb, L0.nb))
-    Bs1 = np.eye(L1.nb)[None] * 4.0 + 0.01 * rng.standard_normal((nsamp, L1.nb, L1.nb))
-    tF0 = timeit(lambda: oracle.lu_factor(Bs0), 1) / nsamp
-    tF1 = timeit(lambda: oracle.lu_factor(Bs1), 1) / nsamp
-    fac0 = oracle.lu_factor(np.tile(Bs0[:1], (L0.Ne, 1, 1)))
-    fac1 = oracle.lu_factor(np.tile(Bs1[:1], (L1.Ne, 1, 1)))
-    x0 = rng.standard_normal(L0.shape)
-    x1 = rng.standard_normal(L1.shape)
-    tS0 = timeit(lambda: oracle.lu_solve(fac0, x0), 3)
-    tS1 = timeit(lambda: oracle.lu_solve(fac1, x1), 3)
-    # Krylov vector work per FGMRES iteration (CGS2 over ~m/2 vectors on average)
-    m = 15
-    V = rng.standard_normal((m, L0.N))
-    wv = rng.standard_normal(L0.N)
-
-    def cgs2():
-        for _ in range(2):
-            h = V @ wv
-            _ = wv - V.T @ h
-    tK = timeit(cgs2, 2)
-    n_factor_blocks0 = L0.Ne
-    n_factor_blocks1 = L1.Ne if st["n_R_coarse"] > 0 else 0
-    # the stage counts the set-up as 1 + nb residual evaluations per level; the
-    # oracle forms the blocks by parity colouring: 1 + 2^d nb evaluations
-    ncol = 1 << wl.dim
-    form0 = 1 + L0.nb
-    form1 = (1 + L1.nb) if n_factor_blocks1 else 0
-    oracle_R0 = st["n_R_fine"] - form0 + 1 + ncol * L0.nb
-    oracle_R1 = st["n_R_coarse"] - form1 + ((1 + ncol * L1.nb) if n_factor_blocks1 else 0)
-    total = (oracle_R0 * tR0 + oracle_R1 * tR1 + st["n_ej_fine"] * tS0 + st["n_ej_coarse"] * tS1
-             + n_factor_blocks0 * tF0 + n_factor_blocks1 * tF1 + st["gmres_iters"] * tK)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t_begin = time.perf_counter()
+        L0 = oracle.Level(**wl.level_kwargs(wl.p0))
+        L1 = oracle.Level(**wl.level_kwargs(wl.p1))
+        dq = wl.dq
+        sigma_A = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
+        sigma_S = 1.0 / wl.dt + sigma_A
+        t0 = time.perf_counter()
+        M, pm = oracle._setup_precond(L0, L1, dq, "pmg", sigma_A, sigma_A, sigma_S, {})
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rq = L0.residual(dq)
+        b = dq + (wl.a_ii * wl.dt) * rq
+        F = (dq - b) / (wl.a_ii * wl.dt) - rq
+        t_ptc = time.perf_counter() - t0  # one residual + stage function per pseudo-time step
+        pm.set_point(dq, rq)
+        A = lambda v: oracle.jvp(L0, dq, rq, v, sigma_A)
+        t0 = time.perf_counter()
+        _, ks = oracle.fgmres(A, M, -F, m=30, tol=1e-30, max_restarts=0, max_iters=n_sample_iters)
+        t_iter = (time.perf_counter() - t0) / max(1, ks.iters)
+    total = t_setup + st["ptc_iters"] * t_ptc + st["gmres_iters"] * t_iter
     dof = wl.dof()
     return dict(value=dof / total, unit="DOF/s", cores=1, kind="oracle",
-                sample=("extrapolated: oracle unit costs on the config-2 state (fine R %.3fs, coarse R %.3fs, "
-                        "fine/coarse block LU solve %.3fs/%.3fs, block factor %.2e/%.2e s per block, CGS2 step "
-                        "%.3fs) x the GPU stage's counts (%d fine R, %d coarse R, %d fine + %d coarse EJ solves, "
-                        "%d FGMRES iterations) = %.1f s of oracle time; measuring took %.1f s")
-                % (tR0, tR1, tS0, tS1, tF0, tF1, tK, oracle_R0, oracle_R1, st["n_ej_fine"],
-                   st["n_ej_coarse"], st["gmres_iters"], total, time.perf_counter() - t_begin),
+                sample=("oracle run on the config-2 stage: preconditioner set-up in full (coloured EJ formation "
+                        "and block LU on both levels, %.1f s) and the first %d preconditioned FGMRES iterations "
+                        "(%.3f s each), one thread; extrapolated to the GPU stage's %d PTC steps and %d FGMRES "
+                        "iterations = %.1f s of oracle time; measuring took %.1f s")
+                % (t_setup, ks.iters, t_iter, st["ptc_iters"], st["gmres_iters"], total,
+                   time.perf_counter() - t_begin),
                 seconds_extrapolated=total)
 
 
