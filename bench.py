@@ -33,10 +33,10 @@ def measured_traffic():
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "k_ej_apply_config2.md")
-    src = os.path.join(ROOT, "paper_2202_09733_amd", "csrc", "ej.hip")
+    src = os.path.join(ROOT, "paper_2202_09733_amd", "csrc", "ej_apply.hip")
     try:
         txt = open(path).read()
-        want = re.search(r"ej.hip sha256: (\w+)", txt).group(1)
+        want = re.search(r"ej_apply.hip sha256: (\w+)", txt).group(1)
         val = float(re.search(r"fp64 traffic bytes per launch: (\d+)", txt).group(1))
     except (OSError, AttributeError):
         return None
@@ -133,6 +133,39 @@ def kernel_rates_3d(reps=20, nsets=4):
         d["frac_hbm"] = d["GBps"] / HBM_PEAK_GBS
     fr.close()
     del sets, base
+    torch.cuda.empty_cache()
+    return out
+
+
+def stage_3d(steps=1):
+    """The first ROW stage of the 3D workload (32^3 hexes, p{3-2}, 10,485,760
+    DOF, fine EJ blocks 320 x 320) with the preconditioner in FP64 and in the
+    BF16-MFMA / BF16-storage form: DOF/s including the set-up, after one
+    warm-up stage each."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    wl = W.config4()
+    fr = capi.FR.from_workload(wl)
+    dq = fr.to_dev(wl.dq)
+    out = {}
+    for key, prec in (("fp64", capi.PREC_FP64), ("bf16_storage", capi.PREC_BF16_STORE)):
+        cfg = capi.stage_config_for(wl, precision=prec)
+        Y = fr.empty(0)
+        fr.solve_stage(cfg, dq, out=Y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st = fr.solve_stage(cfg, dq, out=Y)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        out[key] = {"dof_per_s": wl.dof() / el, "s_per_stage": el, "t_setup_s": st["t_setup"],
+                    "t_solve_s": st["t_solve"], "gmres_iters": st["gmres_iters"], "rel_res": st["rel_res"],
+                    "true_rel_res": st["true_rel_res"]}
+    out["bf16_storage"]["speedup_vs_fp64"] = out["bf16_storage"]["dof_per_s"] / out["fp64"]["dof_per_s"]
+    out["workload"] = ("config4: 3D NS FR periodic 32^3 p=3 (10,485,760 DOF) TGV, Ma 0.1, Re 1600, first ROW stage "
+                       "gamma 0.25 at dt = 100 dt_exp, FGMRES(30) to 1e-8, pMG p{3-2} n{2-2}, EJ blocks 320^2 / 135^2")
+    fr.close()
     torch.cuda.empty_cache()
     return out
 
@@ -350,6 +383,8 @@ def main():
         rates = kernel_rates(fr, wl, dq)
         print("[bench] kernel rates, 3D workload", file=sys.stderr, flush=True)
         rates.update(kernel_rates_3d())
+        print("[bench] 3D ROW stage", file=sys.stderr, flush=True)
+        result["stage_3d"] = stage_3d()
         result["kernels"] = rates
         dom = rates["ej_apply_fine"]
         result["roofline"] = {

@@ -1,6 +1,6 @@
-// Element-Jacobi blocks on gfx950: inversion of every block and the batched
-// block apply y = beta y + alpha B^{-1} r (Sec. 2.2, element-Jacobi
-// preconditioner; Sec. 3.2, EJ smoother).
+// Element-Jacobi blocks on gfx950: inversion of every block (Sec. 2.2,
+// element-Jacobi preconditioner; Sec. 3.2, EJ smoother).  The batched apply
+// with the stored inverses is in ej_apply.hip.
 //
 // Inversion: one workgroup per block, the whole FP64 block resident in LDS
 // (n_b <= 140 fits in the 160 KB of a CU), Gauss-Jordan elimination with
@@ -36,6 +36,10 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
     __shared__ int s_piv;
     const int tid = threadIdx.x, nt = blockDim.x;
     const size_t base = (size_t)blockIdx.x * nb * nb;
+    // elimination layout: lane = (row er, column group eg), rows padded to a
+    // multiple of 64 so that a wave never straddles two column groups
+    const int RT = min(nt, ((nb + 63) / 64) * 64);
+    const int er = tid % RT, eg = tid / RT, ng = nt / RT;
     for (int t = tid; t < nb * nb; t += nt) A[t] = B[base + t];
     __syncthreads();
     bool singular = false;
@@ -82,11 +86,28 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
         __syncthreads();
         for (int j = tid; j < nb; j += nt) A[j * nb + c] = (j == c ? 1.0 : A[j * nb + c]) * inv;
         __syncthreads();
-        for (int t = tid; t < nb * nb; t += nt) {
-            const int j = t / nb, r = t - j * nb;
-            if (r == c) continue;
-            const double cur = (j == c) ? 0.0 : A[t];
-            A[t] = cur - colk[r] * A[j * nb + c];
+        if (er < nb && er != c && eg < ng) {
+            // rows other than c never write the pivot row, so the pivot-row
+            // reads of four columns can be issued ahead of the updates
+            const double f = colk[er];
+            int j = eg;
+            for (; j + 3 * ng < nb; j += 4 * ng) {
+                double a[4], pv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = A[(j + u * ng) * nb + er];
+                    pv[u] = A[(j + u * ng) * nb + c];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double cur = (j + u * ng == c) ? 0.0 : a[u];
+                    A[(j + u * ng) * nb + er] = cur - f * pv[u];
+                }
+            }
+            for (; j < nb; j += ng) {
+                const double cur = (j == c) ? 0.0 : A[j * nb + er];
+                A[j * nb + er] = cur - f * A[j * nb + c];
+            }
         }
         __syncthreads();
     }
@@ -127,6 +148,8 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int nb, int c0, int bw,
     __shared__ int s_i[kGJThreads / 64];
     __shared__ int s_piv;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int RT = min(nt, ((nb + 63) / 64) * 64);
+    const int er = tid % RT, eg = tid / RT, ng = nt / RT;
     double *Ak = A + (size_t)blockIdx.x * nb * nb;
     for (int t = tid; t < bw * nb; t += nt) Pn[t] = Ak[(size_t)c0 * nb + t];
     __syncthreads();
@@ -174,11 +197,31 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int nb, int c0, int bw,
         __syncthreads();
         for (int j = tid; j < bw; j += nt) Pn[j * nb + c] = (j == cc ? 1.0 : Pn[j * nb + c]) * inv;
         __syncthreads();
-        for (int t = tid; t < bw * nb; t += nt) {
-            const int j = t / nb, r = t - j * nb;
-            if (r == c) continue;
-            const double cur = (j == cc) ? 0.0 : Pn[t];
-            Pn[t] = cur - colk[r] * Pn[j * nb + c];
+        // lane = (row er + k RT, column group eg): no division in the loop, and
+        // the pivot-row reads of four columns issue ahead of the updates
+        if (eg < ng) {
+            for (int r = er; r < nb; r += RT) {
+                if (r == c) continue;
+                const double f = colk[r];
+                int j = eg;
+                for (; j + 3 * ng < bw; j += 4 * ng) {
+                    double a[4], pv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a[u] = Pn[(j + u * ng) * nb + r];
+                        pv[u] = Pn[(j + u * ng) * nb + c];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double cur = (j + u * ng == cc) ? 0.0 : a[u];
+                        Pn[(j + u * ng) * nb + r] = cur - f * pv[u];
+                    }
+                }
+                for (; j < bw; j += ng) {
+                    const double cur = (j == cc) ? 0.0 : Pn[j * nb + r];
+                    Pn[j * nb + r] = cur - f * Pn[j * nb + c];
+                }
+            }
         }
         __syncthreads();
     }
@@ -375,118 +418,6 @@ __global__ void k_to_bf16(size_t n, const double *__restrict__ a, __bf16 *__rest
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (__bf16)(float)a[i];
 }
 
-constexpr int kApplyThreads = 256;
-
-template <typename T, int R>
-struct VecLoad;
-template <>
-struct VecLoad<double, 1> {
-    __device__ static void get(const double *p, double *o) { o[0] = p[0]; }
-};
-template <>
-struct VecLoad<double, 2> {
-    __device__ static void get(const double *p, double *o) {
-        const double2 v = *reinterpret_cast<const double2 *>(p);
-        o[0] = v.x;
-        o[1] = v.y;
-    }
-};
-template <>
-struct VecLoad<float, 1> {
-    __device__ static void get(const float *p, double *o) { o[0] = p[0]; }
-};
-template <>
-struct VecLoad<float, 4> {
-    __device__ static void get(const float *p, double *o) {
-        const float4 v = *reinterpret_cast<const float4 *>(p);
-        o[0] = v.x;
-        o[1] = v.y;
-        o[2] = v.z;
-        o[3] = v.w;
-    }
-};
-
-template <>
-struct VecLoad<__bf16, 1> {
-    __device__ static void get(const __bf16 *p, double *o) { o[0] = (float)p[0]; }
-};
-template <>
-struct VecLoad<__bf16, 4> {
-    __device__ static void get(const __bf16 *p, double *o) {
-        typedef __bf16 b4 __attribute__((ext_vector_type(4)));
-        const b4 v = *reinterpret_cast<const b4 *>(p);
-        o[0] = (float)v.x;
-        o[1] = (float)v.y;
-        o[2] = (float)v.z;
-        o[3] = (float)v.w;
-    }
-};
-
-// y[row][k] = beta y + alpha sum_j Binv_k[row][j] r[j][k], Binv column-major.
-// Each lane owns R consecutive rows of one block and streams the block
-// column by column with one wide load per column (R = 2 for FP64, 4 for FP32
-// and BF16 storage), so a wavefront reads whole contiguous column segments.
-template <typename T, int R>
-__global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int epb, const T *__restrict__ inv,
-                                                            const double *__restrict__ r, double alpha,
-                                                            double beta, double *__restrict__ y) {
-    extern __shared__ double s_r[];  // [epb][nb]
-    const int k0 = blockIdx.x * epb;
-    const int ne = min(epb, Ne - k0);
-    for (int t = threadIdx.x; t < epb * nb; t += blockDim.x) {
-        const int e = t / nb, j = t - e * nb;
-        s_r[t] = (e < ne) ? r[(size_t)j * Ne + k0 + e] : 0.0;
-    }
-    __syncthreads();
-    const int tpe = nb / R;  // lanes per block
-    const int e = threadIdx.x / tpe;
-    const int row = (threadIdx.x - e * tpe) * R;
-    if (e >= ne) return;
-    const int k = k0 + e;
-    const T *col = inv + (size_t)k * nb * nb + row;
-    const double *rv = s_r + e * nb;
-    double acc[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = 0.0;
-    int j = 0;
-    for (; j + 4 <= nb; j += 4) {
-        double v0[R], v1[R], v2[R], v3[R];
-        VecLoad<T, R>::get(col + (size_t)j * nb, v0);
-        VecLoad<T, R>::get(col + (size_t)(j + 1) * nb, v1);
-        VecLoad<T, R>::get(col + (size_t)(j + 2) * nb, v2);
-        VecLoad<T, R>::get(col + (size_t)(j + 3) * nb, v3);
-        const double x0 = rv[j], x1 = rv[j + 1], x2 = rv[j + 2], x3 = rv[j + 3];
-#pragma unroll
-        for (int q = 0; q < R; ++q) acc[q] += (v0[q] * x0 + v1[q] * x1) + (v2[q] * x2 + v3[q] * x3);
-    }
-    for (; j < nb; ++j) {
-        double v0[R];
-        VecLoad<T, R>::get(col + (size_t)j * nb, v0);
-#pragma unroll
-        for (int q = 0; q < R; ++q) acc[q] += v0[q] * rv[j];
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const size_t idx = (size_t)(row + q) * Ne + k;
-        y[idx] = (beta == 0.0) ? alpha * acc[q] : beta * y[idx] + alpha * acc[q];
-    }
-}
-
-template <typename T, int R>
-hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, double beta, double *y,
-                        hipStream_t s) {
-    const int nb = L.nb;
-    const int tpe = nb / R;
-    if (tpe > kApplyThreads) return hipErrorInvalidValue;
-    const int epb = (tpe >= kApplyThreads) ? 1 : kApplyThreads / tpe;
-    const size_t lds = (size_t)epb * nb * sizeof(double);
-    dim3 grid((Ne + epb - 1) / epb);
-    dim3 block(tpe >= kApplyThreads ? tpe : kApplyThreads);
-    hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, (const T *)L.inv, r, alpha, beta,
-                       y);
-    return hipGetLastError();
-}
-
 }  // namespace
 
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
@@ -545,22 +476,6 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
     }
     L.inv_prec = precision;
     return hipGetLastError();
-}
-
-hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta, double *y,
-                    hipStream_t s) {
-    const Level &L = ctx->lv[level];
-    const int nb = L.nb, Ne = ctx->mesh.Ne;
-    if (L.inv_prec == FR_PREC_FP64)
-        return (nb % 2 == 0) ? launch_apply<double, 2>(L, Ne, r, alpha, beta, y, s)
-                             : launch_apply<double, 1>(L, Ne, r, alpha, beta, y, s);
-    if (L.inv_prec == FR_PREC_BF16_STORE)
-        return (nb % 4 == 0) ? launch_apply<__bf16, 4>(L, Ne, r, alpha, beta, y, s)
-                             : launch_apply<__bf16, 1>(L, Ne, r, alpha, beta, y, s);
-    if (L.inv_prec >= 0)
-        return (nb % 4 == 0) ? launch_apply<float, 4>(L, Ne, r, alpha, beta, y, s)
-                             : launch_apply<float, 1>(L, Ne, r, alpha, beta, y, s);
-    return hipErrorInvalidValue;
 }
 
 }  // namespace frpmg

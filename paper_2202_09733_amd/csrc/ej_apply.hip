@@ -1,0 +1,144 @@
+// Element-Jacobi apply on gfx950: y = beta y + alpha B^{-1} r for every
+// element at once with the stored inverse blocks (Sec. 2.2, element-Jacobi
+// preconditioner; Sec. 3.2, EJ smoother).  A batched GEMV that streams the
+// inverses once from HBM: each lane owns R consecutive rows of one block and
+// reads them with one 16-byte load per block column (FP64 R = 2, FP32 and
+// BF16 R = 4), accumulating in FP64.  This is the HBM-bound kernel of the
+// preconditioner.
+#include "internal.hpp"
+
+namespace frpmg {
+
+namespace {
+
+constexpr int kApplyThreads = 256;
+
+template <typename T, int R>
+struct VecLoad;
+template <>
+struct VecLoad<double, 1> {
+    __device__ static void get(const double *p, double *o) { o[0] = p[0]; }
+};
+template <>
+struct VecLoad<double, 2> {
+    __device__ static void get(const double *p, double *o) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <>
+struct VecLoad<float, 1> {
+    __device__ static void get(const float *p, double *o) { o[0] = p[0]; }
+};
+template <>
+struct VecLoad<float, 4> {
+    __device__ static void get(const float *p, double *o) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+
+template <>
+struct VecLoad<__bf16, 1> {
+    __device__ static void get(const __bf16 *p, double *o) { o[0] = (float)p[0]; }
+};
+template <>
+struct VecLoad<__bf16, 4> {
+    __device__ static void get(const __bf16 *p, double *o) {
+        typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+        const b4 v = *reinterpret_cast<const b4 *>(p);
+        o[0] = (float)v.x;
+        o[1] = (float)v.y;
+        o[2] = (float)v.z;
+        o[3] = (float)v.w;
+    }
+};
+
+// y[row][k] = beta y + alpha sum_j Binv_k[row][j] r[j][k], Binv column-major.
+// Each lane owns R consecutive rows of one block and streams the block
+// column by column with one wide load per column (R = 2 for FP64, 4 for FP32
+// and BF16 storage), so a wavefront reads whole contiguous column segments.
+template <typename T, int R>
+__global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int epb, const T *__restrict__ inv,
+                                                            const double *__restrict__ r, double alpha,
+                                                            double beta, double *__restrict__ y) {
+    extern __shared__ double s_r[];  // [epb][nb]
+    const int k0 = blockIdx.x * epb;
+    const int ne = min(epb, Ne - k0);
+    for (int t = threadIdx.x; t < epb * nb; t += blockDim.x) {
+        const int e = t / nb, j = t - e * nb;
+        s_r[t] = (e < ne) ? r[(size_t)j * Ne + k0 + e] : 0.0;
+    }
+    __syncthreads();
+    const int tpe = nb / R;  // lanes per block
+    const int e = threadIdx.x / tpe;
+    const int row = (threadIdx.x - e * tpe) * R;
+    if (e >= ne) return;
+    const int k = k0 + e;
+    const T *col = inv + (size_t)k * nb * nb + row;
+    const double *rv = s_r + e * nb;
+    double acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0.0;
+    int j = 0;
+    for (; j + 4 <= nb; j += 4) {
+        double v0[R], v1[R], v2[R], v3[R];
+        VecLoad<T, R>::get(col + (size_t)j * nb, v0);
+        VecLoad<T, R>::get(col + (size_t)(j + 1) * nb, v1);
+        VecLoad<T, R>::get(col + (size_t)(j + 2) * nb, v2);
+        VecLoad<T, R>::get(col + (size_t)(j + 3) * nb, v3);
+        const double x0 = rv[j], x1 = rv[j + 1], x2 = rv[j + 2], x3 = rv[j + 3];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += (v0[q] * x0 + v1[q] * x1) + (v2[q] * x2 + v3[q] * x3);
+    }
+    for (; j < nb; ++j) {
+        double v0[R];
+        VecLoad<T, R>::get(col + (size_t)j * nb, v0);
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += v0[q] * rv[j];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const size_t idx = (size_t)(row + q) * Ne + k;
+        y[idx] = (beta == 0.0) ? alpha * acc[q] : beta * y[idx] + alpha * acc[q];
+    }
+}
+
+template <typename T, int R>
+hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, double beta, double *y,
+                        hipStream_t s) {
+    const int nb = L.nb;
+    const int tpe = nb / R;
+    if (tpe > kApplyThreads) return hipErrorInvalidValue;
+    const int epb = (tpe >= kApplyThreads) ? 1 : kApplyThreads / tpe;
+    const size_t lds = (size_t)epb * nb * sizeof(double);
+    dim3 grid((Ne + epb - 1) / epb);
+    dim3 block(tpe >= kApplyThreads ? tpe : kApplyThreads);
+    hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, (const T *)L.inv, r, alpha, beta,
+                       y);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta, double *y,
+                    hipStream_t s) {
+    const Level &L = ctx->lv[level];
+    const int nb = L.nb, Ne = ctx->mesh.Ne;
+    if (L.inv_prec == FR_PREC_FP64)
+        return (nb % 2 == 0) ? launch_apply<double, 2>(L, Ne, r, alpha, beta, y, s)
+                             : launch_apply<double, 1>(L, Ne, r, alpha, beta, y, s);
+    if (L.inv_prec == FR_PREC_BF16_STORE)
+        return (nb % 4 == 0) ? launch_apply<__bf16, 4>(L, Ne, r, alpha, beta, y, s)
+                             : launch_apply<__bf16, 1>(L, Ne, r, alpha, beta, y, s);
+    if (L.inv_prec >= 0)
+        return (nb % 4 == 0) ? launch_apply<float, 4>(L, Ne, r, alpha, beta, y, s)
+                             : launch_apply<float, 1>(L, Ne, r, alpha, beta, y, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace frpmg

@@ -476,8 +476,9 @@ __device__ __forceinline__ void face_flux(const MeshK &m, const Ops1D &ops, cons
     for (int v = 0; v < NV; ++v) Fs[((size_t)(A * NV + v) * NF + f) * m.Ne + k] = F[v];
 }
 
+// at most 128 VGPRs (four waves per SIMD): the 3D face flux otherwise takes ~131
 template <int DIM, int P, int MODE, bool SAVE>
-__global__ void __launch_bounds__((Shape<DIM, P>::NTF)) k_faces(MeshK m, SrcK src, Ops1D ops_in, Phys ph,
+__global__ void __launch_bounds__((Shape<DIM, P>::NTF)) __attribute__((amdgpu_waves_per_eu(4, 8))) k_faces(MeshK m, SrcK src, Ops1D ops_in, Phys ph,
                                                              const double *__restrict__ Tm,
                                                              double *__restrict__ Fs, FaceSave sv) {
     using S = Shape<DIM, P>;

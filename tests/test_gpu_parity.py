@@ -265,25 +265,33 @@ def test_row_stage_tiny_matches_oracle(orc):
     assert rel(Y.cpu().numpy(), Y_ref) <= 1e-7
 
 
-def test_row_stage_config4_full_size(orc):
+@pytest.fixture(scope="module")
+def config4_oracle_rhs(orc):
+    wl = W.config4()
+    L0 = orc.Level(**wl.level_kwargs(wl.p0))
+    return wl, L0, L0.residual(wl.dq)
+
+
+@pytest.mark.parametrize("precision", [capi.PREC_FP64, capi.PREC_FP32, capi.PREC_BF16_STORE])
+def test_row_stage_config4_full_size(orc, config4_oracle_rhs, precision):
     """3D 32^3 p=3 first ROW stage with pMG p{3-2} (fine blocks 320 x 320,
-    blocked Gauss-Jordan), FP32 EJ storage.  FGMRES stops on its residual
+    blocked Gauss-Jordan) with the EJ inverses in FP64, FP32, or from the
+    BF16-MFMA factorisation stored in BF16.  FGMRES stops on its residual
     estimate (1e-8).  The one-sided FD operator at the paper's eps = 1e-6 is
     itself accurate only to O(h) ~ 1e-7 relative here (per-entry step ~5e-7
     of O(1) velocities), so the residual of the re-applied FD operator, which
     the oracle recomputes at the GPU solution, is bounded by 1e-6 and must
     agree with the GPU's own recomputation."""
     require_gpu()
-    announce("row stage config4 full size")
-    wl = W.config4()
+    announce("row stage config4 full size, precision %d" % precision)
+    wl, L0, R0 = config4_oracle_rhs
     fr = capi.FR.from_workload(wl)
     dq = fr.to_dev(wl.dq)
-    Y, st = fr.solve_stage(capi.stage_config_for(wl, precision=capi.PREC_FP32), dq)
+    Y, st = fr.solve_stage(capi.stage_config_for(wl, precision=precision), dq)
     print({k: st[k] for k in ("gmres_iters", "restarts", "rel_res", "true_rel_res", "t_setup", "t_solve")})
     assert st["converged"] == 1 and st["rel_res"] <= 1e-8
     Y = Y.cpu().numpy()
-    L0 = orc.Level(**wl.level_kwargs(wl.p0))
-    R0 = L0.residual(wl.dq)
+    fr.close()
     sigma = 1.0 / (wl.a_ii * wl.dt)
     AY = orc.jvp(L0, wl.dq, R0, Y, sigma, eps=1e-6, mode=orc.EPS_SCALED)
     true_orc = np.linalg.norm(R0 - AY) / np.linalg.norm(R0)
