@@ -231,6 +231,72 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int nb, int c0, int bw,
 
 constexpr int kUpdCols = 64;  // columns per update workgroup
 constexpr int kUpdRows = 64;  // rows per LDS chunk of T_panel
+constexpr int kMaxNb = 512;   // largest block the update kernels take
+
+// The row interchanges of one panel, applied by gathering instead of swapping
+// in place.  LDS state of one workgroup: src[r] = the row whose value ends at
+// row r after the panel's interchanges (identity outside the touched rows),
+// upos[r] = index of row r in the list of touched rows U (-1 if untouched),
+// and stage[u][jj] = the old value at touched row U[u] of tile column jj.
+struct PanelPerm {
+    int src[kMaxNb];
+    int upos[kMaxNb];
+    int rows[2 * kPanel];
+    int nu;
+};
+
+// Fill a PanelPerm for block k (all lanes take part; ends with a barrier).
+__device__ __forceinline__ void panel_perm(PanelPerm &pp, int nb, int c0, int bw, const int *__restrict__ perm,
+                                           int k) {
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+        pp.src[r] = r;
+        pp.upos[r] = -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nu = 0;
+        for (int cc = 0; cc < bw; ++cc) {
+            const int c = c0 + cc, p = perm[(size_t)k * nb + c];
+            const int t = pp.src[c];
+            pp.src[c] = pp.src[p];
+            pp.src[p] = t;
+            if (pp.upos[c] < 0) {
+                pp.upos[c] = nu;
+                pp.rows[nu++] = c;
+            }
+            if (pp.upos[p] < 0) {
+                pp.upos[p] = nu;
+                pp.rows[nu++] = p;
+            }
+        }
+        pp.nu = nu;
+    }
+    __syncthreads();
+}
+
+// stage[u][jj] = old value of touched row U[u] in tile column jj (0 beyond
+// the block's columns); every lane takes part, ends with a barrier.
+__device__ __forceinline__ void stage_touched(const PanelPerm &pp, double (*stage)[kUpdCols], const double *Ak,
+                                              int nb, int c0, int bw, int tile) {
+    const int nrest = nb - bw;
+    for (int t = threadIdx.x; t < pp.nu * kUpdCols; t += blockDim.x) {
+        const int u = t / kUpdCols, jj = t % kUpdCols;
+        const int ri = tile * kUpdCols + jj;
+        double v = 0.0;
+        if (ri < nrest) {
+            const int j = (ri < c0) ? ri : ri + bw;
+            v = Ak[(size_t)j * nb + pp.rows[u]];
+        }
+        stage[u][jj] = v;
+    }
+    __syncthreads();
+}
+
+// (P x)[r] of tile column jj: from the stage for touched rows, else from x
+__device__ __forceinline__ double permuted(const PanelPerm &pp, const double (*stage)[kUpdCols], const double *x,
+                                           int r, int jj) {
+    return pp.upos[r] >= 0 ? stage[pp.upos[pp.src[r]]][jj] : x[r];
+}
 
 // Apply the panel transform to the kUpdCols columns (outside the panel) of
 // one block: 256 lanes, each owns a 4 x 4 register tile of the output chunk.
@@ -243,7 +309,9 @@ __global__ void __launch_bounds__(256) k_gj_update(int nb, int c0, int bw, doubl
     double *Ak = A + (size_t)k * nb * nb;
     const int nrest = nb - bw;
     const int ri = blockIdx.y * kUpdCols + (tid % kUpdCols);  // rest-column index of this lane (phase 1)
-    // phase 1: row interchanges on the tile's columns, then gather (P x)_S
+    // phase 1: row interchanges on the tile's columns in place (32 KB of LDS
+    // keeps five workgroups per CU, which beats the gather of the MFMA variant
+    // here), then gather (P x)_S
     if (tid < kUpdCols) {
         if (ri < nrest) {
             const int j = (ri < c0) ? ri : ri + bw;
@@ -320,36 +388,21 @@ __global__ void __launch_bounds__(256) k_gj_update_mfma(int nb, int c0, int bw, 
     __shared__ __attribute__((aligned(16))) __bf16 xs_l[kUpdCols][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 tp_h[kUpdRows][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 tp_l[kUpdRows][kPanel];
+    __shared__ double stage[2 * kPanel][kUpdCols];
+    __shared__ PanelPerm pp;
     const int tid = threadIdx.x;
     const int k = blockIdx.x;
     double *Ak = A + (size_t)k * nb * nb;
     const int nrest = nb - bw;
-    // phase 1: row interchanges on this tile's columns, gather (P x)_S split in hi/lo
-    if (tid < kUpdCols) {
-        const int ri = blockIdx.y * kUpdCols + tid;
-        if (ri < nrest) {
-            const int j = (ri < c0) ? ri : ri + bw;
-            double *x = Ak + (size_t)j * nb;
-            for (int cc = 0; cc < bw; ++cc) {
-                const int c = c0 + cc, p = perm[(size_t)k * nb + c];
-                if (p != c) {
-                    const double t0 = x[c];
-                    x[c] = x[p];
-                    x[p] = t0;
-                }
-            }
-            for (int cc = 0; cc < kPanel; ++cc) {
-                const float v = (cc < bw) ? (float)x[c0 + cc] : 0.f;
-                const __bf16 h = (__bf16)v;
-                xs_h[tid][cc] = h;
-                xs_l[tid][cc] = (__bf16)(v - (float)h);
-            }
-        } else {
-            for (int cc = 0; cc < kPanel; ++cc) {
-                xs_h[tid][cc] = (__bf16)0.f;
-                xs_l[tid][cc] = (__bf16)0.f;
-            }
-        }
+    // phase 1: the panel's row interchanges as a gather, (P x)_S split in hi/lo
+    panel_perm(pp, nb, c0, bw, perm, k);
+    stage_touched(pp, stage, Ak, nb, c0, bw, blockIdx.y);
+    for (int t = tid; t < kPanel * kUpdCols; t += 256) {
+        const int cc = t % kPanel, jj = t / kPanel;
+        const float v = (cc < bw) ? (float)stage[pp.upos[pp.src[c0 + cc]]][jj] : 0.f;
+        const __bf16 h = (__bf16)v;
+        xs_h[jj][cc] = h;
+        xs_l[jj][cc] = (__bf16)(v - (float)h);
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
@@ -384,7 +437,7 @@ __global__ void __launch_bounds__(256) k_gj_update_mfma(int nb, int c0, int bw, 
                     const int r = r0 + wave * 16 + 4 * g + i;
                     if (r >= nb) continue;
                     const bool inS = (r >= c0 && r < c0 + bw);
-                    x[r] = (inS ? 0.0 : x[r]) + (double)acc[i];
+                    x[r] = (inS ? 0.0 : permuted(pp, stage, x, r, bcol)) + (double)acc[i];
                 }
             }
         }
