@@ -170,6 +170,7 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
     }
     if (!L.fQp) {
         const size_t nface = (size_t)ctx->dim * ctx->nv * L.NF * ctx->mesh.Ne;
+        L.fQs = dalloc(ctx, nface);
         L.fQp = dalloc(ctx, nface);
         L.fSn = dalloc(ctx, nface);
         L.fGt = dalloc(ctx, nface * (ctx->dim - 1));
@@ -933,8 +934,9 @@ void destroy_all(frpmg_ctx *ctx) {
     lcc_free(ctx);
     for (int l = 0; l < FR_MAX_LEVELS; ++l) {
         Level &L = ctx->lv[l];
-        dfree(L.Tm);
+        dfree(L.Jp);
         dfree(L.Fs);
+        dfree(L.fQs);
         dfree(L.fQp);
         dfree(L.fSn);
         dfree(L.fGt);
@@ -1022,7 +1024,7 @@ fr_status fr_create(const fr_mesh_desc *d, frpmg_ctx **out) {
             L.N = (size_t)L.nb * m.Ne;
             build_ops1d(L.P, L.ops);
             const size_t ntr = (size_t)d->dim * ctx->nv * L.NF * m.Ne;
-            L.Tm = dalloc(ctx, ntr);
+            L.Jp = dalloc(ctx, ntr);
             L.Fs = dalloc(ctx, ntr);
             L.r0 = dalloc(ctx, L.N);
             void *p2 = nullptr;

@@ -80,9 +80,10 @@ struct Level {
     int p = 0, P = 0, Np = 0, NF = 0, nb = 0;
     size_t N = 0;  // state length
     Ops1D ops{};
-    double *Tm = nullptr;  // minus traces [dim][nv][NF][Ne]
+    double *Jp = nullptr;  // state jumps q* - q+ on + faces [dim][nv][NF][Ne]
     double *Fs = nullptr;  // common fluxes on + faces [dim][nv][NF][Ne]
     // face data of the EJ linearisation point (allocated at the first factorisation)
+    double *fQs = nullptr;  // q* on + faces [dim][nv][NF][Ne]
     double *fQp = nullptr;  // + traces [dim][nv][NF][Ne]
     double *fSn = nullptr;  // D part of the normal gradient at + faces [dim][nv][NF][Ne]
     double *fGt = nullptr;  // tangential gradients at + faces [dim][dim-1][nv][NF][Ne]

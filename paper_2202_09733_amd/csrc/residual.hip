@@ -8,16 +8,16 @@
 // the +axis element, common viscous flux from the -axis element plus a
 // penalty tau (q_R - q_L)).
 //
-// Three launches per evaluation, exchanging face data through L2/HBM:
-//   1. k_traces : minus-end traces of the state along every axis, from one
-//                 LDS-staged pass over the state                       [dim][nv][NF][Ne]
-//   2. k_faces  : the common flux on each element's + faces.  The corrected
+// Two launches per evaluation, exchanging face data through L2/HBM:
+//   1. k_faces  : the common flux on each element's + faces, and the state
+//                 jump q* - q+ there (q* = the + neighbour's minus-end trace,
+//                 formed from the neighbour's state while staging).  The corrected
 //                 gradient is needed there only as a + face trace, which is
 //                 formed by sum factorisation from the state's face traces
 //                 (normal part: a 1D row operator; tangential parts: D along
 //                 the face plus the + end value of the neighbouring faces'
-//                 jumps), so no volume gradient is formed.   [dim][nv][NF][Ne]
-//   3. k_volume : corrected gradient (registers), pointwise fluxes one
+//                 jumps), so no volume gradient is formed.   2 x [dim][nv][NF][Ne]
+//   2. k_volume : corrected gradient (registers), pointwise fluxes one
 //                 direction at a time through LDS, divergence plus FR
 //                 corrections -> R (or a fused output).
 // Face quantities that every solution point on a line needs (state jumps
@@ -296,50 +296,14 @@ __device__ __forceinline__ int sidx(int base, int e) {
     return SL ? base * SL + e : base;
 }
 
-// Minus-end traces along every axis of TE elements per workgroup: the state
-// is staged once in LDS (one coalesced pass over q), then every (axis,
-// variable, face point, element) trace is formed from it.
-template <int DIM, int P>
-struct TraceShape {
-    static constexpr int NP = Shape<DIM, P>::NP;
-    static constexpr int NV = DIM + 2;
-    static constexpr int TE = (NV * NP * 16 * 8 <= 48 * 1024) ? 16 : 8;  // elements per workgroup
-};
-
-template <int DIM, int P, int MODE>
-__global__ void __launch_bounds__(256) k_traces(MeshK m, SrcK src, Ops1D ops_in, double *__restrict__ Tm) {
-    using S = Shape<DIM, P>;
-    constexpr int TE = TraceShape<DIM, P>::TE, NV = S::NV, NP = S::NP, NF = S::NF;
-    __shared__ Ops1D ops;
-    __shared__ double s_u[NV * NP * TE];
-    if (threadIdx.x == 0) ops = ops_in;
-    const int k0 = xcd_block(blockIdx.x, gridDim.x) * TE;
-    const int ne = min(TE, m.Ne - k0);
-    const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
-    for (int t = threadIdx.x; t < NV * NP * TE; t += blockDim.x) {
-        const int e = t % TE, vi = t / TE;
-        s_u[t] = (e < ne) ? load_state<MODE>(src, m, vi / NP, vi % NP, k0 + e, alpha) : 0.0;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < DIM * NV * NF * TE; t += blockDim.x) {
-        const int e = t % TE;
-        const int r = t / TE;  // (a * NV + v) * NF + f
-        const int f = r % NF;
-        const int v = (r / NF) % NV, a = r / (NF * NV);
-        if (e >= ne) continue;
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < P; ++j) s += ops.bm[j] * s_u[(v * NP + S::line(a, f, j)) * TE + e];
-        Tm[(size_t)r * m.Ne + k0 + e] = s;
-    }
-}
-
-// Stage the EB elements k0 .. k0 + ne - 1: the state [v][i][e], the
-// + neighbours' minus traces [a][v][f][e] and 2/h per axis [a][e].
-template <int DIM, int P, int MODE, int EB>
-__device__ __forceinline__ void stage_state(const MeshK &m, const SrcK &src, const double *__restrict__ Tm,
-                                            int k0, int ne, double *s_u, double *s_t, double *s_ih,
-                                            double alpha) {
+// Stage the EB elements k0 .. k0 + ne - 1: the state [v][i][e], face data
+// on the + faces [a][v][f][e] and 2/h per axis [a][e].  TRACE: the face data
+// is q*, the + neighbour's minus-end trace, formed here from the neighbour's
+// state; otherwise it is read from Fd ([a][v][f][Ne], written by k_faces).
+template <int DIM, int P, int MODE, int EB, bool TRACE>
+__device__ __forceinline__ void stage_state(const MeshK &m, const SrcK &src, const Ops1D &ops,
+                                            const double *__restrict__ Fd, int k0, int ne, double *s_u,
+                                            double *s_t, double *s_ih, double alpha) {
     using S = Shape<DIM, P>;
     for (int t = threadIdx.x; t < S::NV * S::NP * EB; t += blockDim.x) {
         const int e = t % EB, vi = t / EB;
@@ -348,8 +312,19 @@ __device__ __forceinline__ void stage_state(const MeshK &m, const SrcK &src, con
     for (int t = threadIdx.x; t < DIM * S::NV * S::NF * EB; t += blockDim.x) {
         const int e = t % EB;
         const int r = t / EB;  // (a * NV + v) * NF + f
-        const int a = r / (S::NV * S::NF);
-        s_t[t] = (e < ne) ? Tm[(size_t)r * m.Ne + neighbour(m, k0 + e, a, +1)] : 0.0;
+        double val = 0.0;
+        if (e < ne) {
+            if (TRACE) {
+                const int f = r % S::NF;
+                const int v = (r / S::NF) % S::NV, a = r / (S::NF * S::NV);
+                const int kn = neighbour(m, k0 + e, a, +1);
+#pragma unroll
+                for (int j = 0; j < P; ++j) val += ops.bm[j] * load_state<MODE>(src, m, v, S::line(a, f, j), kn, alpha);
+            } else {
+                val = Fd[(size_t)r * m.Ne + k0 + e];
+            }
+        }
+        s_t[t] = val;
     }
     for (int t = threadIdx.x; t < DIM * EB; t += blockDim.x) {
         const int e = t % EB, a = t / EB;
@@ -441,26 +416,33 @@ __device__ __forceinline__ void common_flux(const Phys &ph, const double (&qL)[D
 }
 
 // Face data of the linearisation point kept for the element-local EJ
-// formation: per + face of its owner, the owner's + trace, the D part of the
-// normal gradient and the tangential gradient components.
+// formation: per + face of its owner, q* there, the owner's + trace, the D
+// part of the normal gradient and the tangential gradient components.
 struct FaceSave {
+    double *Qs;  // q*, the + neighbour's minus trace [a][v][f][Ne]
     double *Qp;  // [a][v][f][Ne]
     double *Sn;  // [a][v][f][Ne]
     double *Gt;  // [a][c'][v][f][Ne], c' over the axes other than a in increasing order
 };
 
+// Common flux on one + face point; also writes the state jump q* - q+ there
+// (Jp), which the volume kernel needs, and the saved base data.
 template <int DIM, int P, int A, int EB, bool SAVE>
 __device__ __forceinline__ void face_flux(const MeshK &m, const Ops1D &ops, const Phys &ph, const double *s_u,
                                           const double *s_t, const double *s_qp, const double *s_ih, int e,
-                                          int f, int k, double *__restrict__ Fs, const FaceSave &sv) {
+                                          int f, int k, double *__restrict__ Fs, double *__restrict__ Jp,
+                                          const FaceSave &sv) {
     using S = Shape<DIM, P>;
     constexpr int NV = S::NV, NF = S::NF;
     double qL[NV], qR[NV], g[DIM][NV], Sn[NV], F[NV];
     plus_face_state<DIM, P, A, EB, EB>(ops, s_u, s_t, s_qp, s_ih, e, f, qL, qR, g, Sn);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Jp[((size_t)(A * NV + v) * NF + f) * m.Ne + k] = qR[v] - qL[v];
     if (SAVE) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const size_t o = ((size_t)(A * NV + v) * NF + f) * m.Ne + k;
+            sv.Qs[o] = qR[v];
             sv.Qp[o] = qL[v];
             sv.Sn[o] = Sn[v];
 #pragma unroll
@@ -479,7 +461,7 @@ __device__ __forceinline__ void face_flux(const MeshK &m, const Ops1D &ops, cons
 // at most 128 VGPRs (four waves per SIMD): the 3D face flux otherwise takes ~131
 template <int DIM, int P, int MODE, bool SAVE>
 __global__ void __launch_bounds__((Shape<DIM, P>::NTF)) __attribute__((amdgpu_waves_per_eu(4, 8))) k_faces(MeshK m, SrcK src, Ops1D ops_in, Phys ph,
-                                                             const double *__restrict__ Tm,
+                                                             double *__restrict__ Jp,
                                                              double *__restrict__ Fs, FaceSave sv) {
     using S = Shape<DIM, P>;
     constexpr int EB = S::EBF, NV = S::NV, NP = S::NP, NF = S::NF;
@@ -493,7 +475,7 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NTF)) __attribute__((amdgpu_wa
     const int k0 = xcd_block(blockIdx.x, gridDim.x) * EB;
     const int ne = min(EB, m.Ne - k0);
     const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
-    stage_state<DIM, P, MODE, EB>(m, src, Tm, k0, ne, s_u, s_t, s_ih, alpha);
+    stage_state<DIM, P, MODE, EB, true>(m, src, ops_in, nullptr, k0, ne, s_u, s_t, s_ih, alpha);
     __syncthreads();
     for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
         const int e = t % EB;
@@ -513,11 +495,11 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NTF)) __attribute__((amdgpu_wa
         const int f = r % NF, a = r / NF;
         if (e >= ne) continue;
         if (a == 0) {
-            face_flux<DIM, P, 0, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, sv);
+            face_flux<DIM, P, 0, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
         } else if (a == 1) {
-            face_flux<DIM, P, 1, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, sv);
+            face_flux<DIM, P, 1, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
         } else {
-            if constexpr (DIM == 3) face_flux<DIM, P, 2, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, sv);
+            if constexpr (DIM == 3) face_flux<DIM, P, 2, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
         }
     }
 }
@@ -621,14 +603,14 @@ struct OutK {
 
 template <int DIM, int P, int MODE, int OUT>
 __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph,
-                                                             const double *__restrict__ Tm,
+                                                             const double *__restrict__ Jp,
                                                              const double *__restrict__ Fs, OutK o) {
     using S = Shape<DIM, P>;
     constexpr int EB = S::EB, NV = S::NV, NP = S::NP, NF = S::NF;
     constexpr int NFACE = DIM * NV * NF * EB;
     __shared__ Ops1D ops;
     __shared__ double s_u[NV * NP * EB];  // the state, then the flux of one direction
-    __shared__ double s_t[NFACE];         // q* on the + faces, then the jump q* - q+
+    __shared__ double s_t[NFACE];         // state jumps q* - q+ on the + faces
     __shared__ double s_fm[NFACE];        // F* on the - faces, then F* - f^-
     __shared__ double s_fp[NFACE];        // F* on the + faces, then F* - f^+
     __shared__ double s_ih[DIM * EB];
@@ -636,7 +618,7 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK sr
     const int k0 = xcd_block(blockIdx.x, gridDim.x) * EB;
     const int ne = min(EB, m.Ne - k0);
     const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
-    stage_state<DIM, P, MODE, EB>(m, src, Tm, k0, ne, s_u, s_t, s_ih, alpha);
+    stage_state<DIM, P, MODE, EB, false>(m, src, ops_in, Jp, k0, ne, s_u, s_t, s_ih, alpha);
     for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
         const int e = t % EB;
         const int r = t / EB;  // (a * NV + v) * NF + f
@@ -649,19 +631,6 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK sr
         }
         s_fp[t] = vp;
         s_fm[t] = vm;
-    }
-    __syncthreads();
-    // state jumps on the + faces (the common solution is q*, so the - faces carry none)
-    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
-        const int e = t % EB;
-        int r = t / EB;
-        const int f = r % NF;
-        r /= NF;
-        const int v = r % NV, a = r / NV;
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < P; ++j) s += ops.bp[j] * s_u[(v * NP + S::line(a, f, j)) * EB + e];
-        s_t[t] -= s;
     }
     __syncthreads();
     const int t = threadIdx.x;
@@ -702,7 +671,6 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK sr
 
 struct FormK {
     const double *dq;  // linearisation point
-    const double *Tm;  // base minus traces
     FaceSave sv;       // base face data
     const double *r0;  // R at the linearisation point
     double *blocks;    // [Ne][nb][nb], column-major per block
@@ -744,7 +712,7 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_ej_form(MeshK m, Ops1D 
     for (int t = threadIdx.x; t < NSH; t += blockDim.x) {
         const int a = t / (NV * NF);
         const int mm = neighbour(m, k, a, -1);
-        s_tn[t] = fk.Tm[(size_t)t * m.Ne + neighbour(m, k, a, +1)];
+        s_tn[t] = fk.sv.Qs[(size_t)t * m.Ne + k];
         s_mq[t] = fk.sv.Qp[(size_t)t * m.Ne + mm];
         s_ms[t] = fk.sv.Sn[(size_t)t * m.Ne + mm];
     }
@@ -856,19 +824,17 @@ hipError_t run(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, cons
     using S = Shape<DIM, P>;
     const MeshK &m = ctx->mesh;
     SrcK src{a.dq, a.v, a.alpha, S::NP};
-    constexpr int TE = TraceShape<DIM, P>::TE;
-    hipLaunchKernelGGL((k_traces<DIM, P, MODE>), dim3((m.Ne + TE - 1) / TE), dim3(256), 0, s, m, src, L.ops, L.Tm);
     const dim3 g1((m.Ne + S::EBF - 1) / S::EBF);
     if (save) {
-        hipLaunchKernelGGL((k_faces<DIM, P, MODE, true>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, L.Tm,
+        hipLaunchKernelGGL((k_faces<DIM, P, MODE, true>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, L.Jp,
                            L.Fs, *save);
     } else {
-        hipLaunchKernelGGL((k_faces<DIM, P, MODE, false>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, L.Tm,
-                           L.Fs, FaceSave{nullptr, nullptr, nullptr});
+        hipLaunchKernelGGL((k_faces<DIM, P, MODE, false>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, L.Jp,
+                           L.Fs, FaceSave{nullptr, nullptr, nullptr, nullptr});
     }
     OutK o{a.r, a.r0, a.x, a.v, a.sigma};
     hipLaunchKernelGGL((k_volume<DIM, P, MODE, OUT>), dim3((m.Ne + S::EB - 1) / S::EB), dim3(S::NT), 0, s, m, src,
-                       L.ops, ctx->phys, L.Tm, L.Fs, o);
+                       L.ops, ctx->phys, L.Jp, L.Fs, o);
     return hipGetLastError();
 }
 
@@ -886,7 +852,7 @@ template <int DIM, int P>
 hipError_t form(const frpmg_ctx *ctx, const Level &L, const double *dq, double sigma, hipStream_t s) {
     using S = Shape<DIM, P>;
     const MeshK &m = ctx->mesh;
-    const FaceSave sv{L.fQp, L.fSn, L.fGt};
+    const FaceSave sv{L.fQs, L.fQp, L.fSn, L.fGt};
     ResidualArgs a;
     a.src = SRC_PLAIN;
     a.dq = dq;
@@ -897,7 +863,7 @@ hipError_t form(const frpmg_ctx *ctx, const Level &L, const double *dq, double s
     const int ncb = (L.nb + S::EB - 1) / S::EB;
     const size_t nblk = (size_t)m.Ne * ncb;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    FormK fk{dq, L.Tm, sv, L.r0, L.blk64, sigma, L.nb};
+    FormK fk{dq, sv, L.r0, L.blk64, sigma, L.nb};
     hipLaunchKernelGGL((k_ej_form<DIM, P>), dim3((unsigned)nblk), dim3(S::NT), 0, s, m, L.ops, ctx->phys, fk);
     return hipGetLastError();
 }
@@ -925,7 +891,7 @@ hipError_t launch_residual(const frpmg_ctx *ctx, int level, const ResidualArgs &
 
 hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s) {
     const Level &L = ctx->lv[level];
-    if (!L.fQp || !L.fSn || !L.fGt || !L.blk64) return hipErrorInvalidValue;
+    if (!L.fQs || !L.fQp || !L.fSn || !L.fGt || !L.blk64) return hipErrorInvalidValue;
     if (ctx->dim == 2) {
         switch (L.P) {
             case 2: return form<2, 2>(ctx, L, dq, sigma, s);
