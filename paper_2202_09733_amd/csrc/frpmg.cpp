@@ -123,7 +123,6 @@ void jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const do
     Scal h{eps, nullptr};
     const size_t N = ctx->lv[level].N;
     if (mode == FR_EPS_NORMALIZED || mode == FR_EPS_SCALED) {
-        HIPCHK(vec_dot(ctx, N, v, v, ctx->scal + SC_JVP_N2, s));
         const double *size = nullptr;
         if (mode == FR_EPS_SCALED) {
             if (!dqn2) {
@@ -132,7 +131,7 @@ void jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const do
             }
             size = dqn2;
         }
-        HIPCHK(scal_fd_step(ctx->scal + SC_JVP_N2, size, eps, ctx->scal + SC_JVP_H, s));
+        HIPCHK(vec_dot_fd_step(ctx, N, v, size, eps, ctx->scal + SC_JVP_N2, ctx->scal + SC_JVP_H, s));
         h = Scal{0.0, ctx->scal + SC_JVP_H};
     }
     residual_lin(ctx, level, dq, v, h, rq, shift, nullptr, w, s);
@@ -401,9 +400,9 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
     const double *Xs = x;
     Scal inv_s{1.0, nullptr};
     if (p.scale_mode == FR_SCALE_NORMALIZED || p.scale_mode == FR_SCALE_SCALED) {
-        HIPCHK(vec_dot(ctx, N0, x, x, ctx->scal + SC_PMG_N2, s));
-        HIPCHK(scal_pmg_scale(ctx->scal + SC_PMG_N2, p.scale_mode == FR_SCALE_SCALED ? ctx->scal + SC_PT_N2 : nullptr,
-                              p.eps_p, p.sigma_D, ctx->scal + SC_PMG_S, ctx->scal + SC_PMG_INV, s));
+        HIPCHK(vec_dot_pmg_scale(ctx, N0, x, p.scale_mode == FR_SCALE_SCALED ? ctx->scal + SC_PT_N2 : nullptr,
+                                 p.eps_p, p.sigma_D, ctx->scal + SC_PMG_N2, ctx->scal + SC_PMG_S,
+                                 ctx->scal + SC_PMG_INV, s));
         HIPCHK(vec_scale_copy(N0, Scal{0.0, ctx->scal + SC_PMG_S}, x, ctx->wXs, s));
         Xs = ctx->wXs;
         inv_s = Scal{0.0, ctx->scal + SC_PMG_INV};
@@ -432,8 +431,7 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
         lcc_forward_rows(ctx, Lc.Mpad, Lc.Xb, Lc.H1, Lc.H2, Lc.Y, s);
         HIPCHK(lcc_output(ctx, Lc, Lc.Y, Lc.srow, ctx->cZ, s));
         HIPCHK(vec_axpby(N1, one, Lc.dtmp, one, ctx->cZ, s));  // C = C1 + network refinement
-        HIPCHK(transfer_apply(ctx, 0, false, ctx->cZ, G, s));
-        HIPCHK(vec_axpby(N0, one, G, one, Y, s));
+        HIPCHK(transfer_apply(ctx, 0, false, ctx->cZ, Y, s, nullptr, true));  // Y += Pi C
         for (int it = 0; it < p.n0; ++it) {
             residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
             cnt->R0++;
@@ -491,10 +489,8 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
             Lc.cycle++;
             HIPCHK(hipMemcpyAsync(ctx->cZ, Lc.Cuse, N1 * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
-        // Y += Pi (Z - Z0)
-        HIPCHK(vec_axpby(N1, Scal{-1.0, nullptr}, ctx->cZ0, one, ctx->cZ, s));
-        HIPCHK(transfer_apply(ctx, 0, false, ctx->cZ, G, s));
-        HIPCHK(vec_axpby(N0, one, G, one, Y, s));
+        // Y += Pi (Z - Z0), one kernel
+        HIPCHK(transfer_apply(ctx, 0, false, ctx->cZ, Y, s, ctx->cZ0, true));
         // post-smoothing
         for (int it = 0; it < p.n0; ++it) {
             residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
@@ -634,8 +630,7 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
                 HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H1, w, st));
                 HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H2, st));
                 HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H2, w, st));
-                HIPCHK(vec_dot(ctx, N, w, w, ctx->red_out + RO_N2, st));
-                HIPCHK(vec_normalize(N, ctx->red_out + RO_N2, w, V + (size_t)(j + 1) * ld, st));
+                HIPCHK(vec_dot_normalize(ctx, N, w, ctx->red_out + RO_N2, V + (size_t)(j + 1) * ld, st));
             };
             if (gu) {
                 std::vector<unsigned long long> key = gu->key;

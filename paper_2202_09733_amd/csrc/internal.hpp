@@ -178,8 +178,17 @@ hipError_t scal_fd_step(const double *vn2, const double *dqn2, double eps, doubl
 // preconditioner scale s = eps_p sigma (1 + ||q||) / ||X|| and 1/s (qn2 = null drops the state size)
 hipError_t scal_pmg_scale(const double *xn2, const double *qn2, double eps_p, double sigma, double *s_out,
                           double *inv_out, hipStream_t s);
+// y = T x (or y += T (x - x0) with x0 / accumulate), T = restriction or prolongation
 hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_dir, const double *x,
-                          double *y, hipStream_t s);
+                          double *y, hipStream_t s, const double *x0 = nullptr, bool accumulate = false);
+// ||v||^2 -> n2out and the FD step h = eps (1 + ||dq||) / ||v|| -> hout, one reduction
+hipError_t vec_dot_fd_step(frpmg_ctx *ctx, size_t n, const double *v, const double *dqn2, double eps,
+                           double *n2out, double *hout, hipStream_t s);
+// ||x||^2 -> n2out and y = x / ||x||, one reduction
+hipError_t vec_dot_normalize(frpmg_ctx *ctx, size_t n, const double *x, double *n2out, double *y, hipStream_t s);
+// ||X||^2 -> n2out and the preconditioner scale s, 1/s, one reduction
+hipError_t vec_dot_pmg_scale(frpmg_ctx *ctx, size_t n, const double *x, const double *qn2, double eps_p,
+                             double sigma, double *n2out, double *s_out, double *inv_out, hipStream_t s);
 
 // ej.hip
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s);

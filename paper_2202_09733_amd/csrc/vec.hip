@@ -117,6 +117,62 @@ __global__ void __launch_bounds__(kThreads) k_stage_F(size_t n, const double *__
         out[i] = (x[i] - b[i]) * c - r[i];
 }
 
+// Sum of the dot-product partials of one vector, in the order of
+// k_sum_partials (so both give the same bits); every lane of block 0 calls it.
+__device__ __forceinline__ double sum_partials_0(int nblk, const double *__restrict__ partial, double *s_red) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += partial[b];
+    return block_sum(acc, s_red);
+}
+
+// y = x / ||x|| with ||x||^2 summed from the partials by every block (same
+// order as k_sum_partials, so every block sees the same bits); block 0
+// also stores ||x||^2.
+__global__ void __launch_bounds__(kThreads) k_sum_normalize(size_t n, int nblk, const double *__restrict__ partial,
+                                                            double *n2out, const double *__restrict__ x,
+                                                            double *__restrict__ y) {
+    __shared__ double s_red[kThreads / 64];
+    __shared__ double s_av;
+    const double n2 = sum_partials_0(nblk, partial, s_red);
+    if (threadIdx.x == 0) {
+        if (blockIdx.x == 0) *n2out = n2;
+        s_av = 1.0 / sqrt(n2);
+    }
+    __syncthreads();
+    const double av = s_av;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = av * x[i];
+}
+
+// ||v||^2 from the partials, then the FD step h = eps (1 + ||dq||) / ||v||
+__global__ void __launch_bounds__(kThreads) k_sum_fd_step(int nblk, const double *__restrict__ partial,
+                                                          const double *dqn2, double eps, double *n2out,
+                                                          double *hout) {
+    __shared__ double s_red[kThreads / 64];
+    const double n2 = sum_partials_0(nblk, partial, s_red);
+    if (threadIdx.x == 0) {
+        *n2out = n2;
+        const double size = dqn2 ? 1.0 + sqrt(*dqn2) : 1.0;
+        *hout = (n2 > 0.0) ? eps * size / sqrt(n2) : eps;
+    }
+}
+
+// ||X||^2 from the partials, then the preconditioner scale s and 1/s
+__global__ void __launch_bounds__(kThreads) k_sum_pmg_scale(int nblk, const double *__restrict__ partial,
+                                                            const double *qn2, double eps_p, double sigma,
+                                                            double *n2out, double *s_out, double *inv_out) {
+    __shared__ double s_red[kThreads / 64];
+    const double n2 = sum_partials_0(nblk, partial, s_red);
+    if (threadIdx.x == 0) {
+        *n2out = n2;
+        const double nrm = sqrt(n2);
+        const double size = qn2 ? 1.0 + sqrt(*qn2) : 1.0;
+        const double sc = (nrm > 0.0) ? eps_p * sigma * size / nrm : 1.0;
+        *s_out = sc;
+        *inv_out = 1.0 / sc;
+    }
+}
+
 // h = eps (1 + ||dq||) / ||v||  (dqn2 = null: h = eps / ||v||)
 __global__ void k_fd_step(const double *vn2, const double *dqn2, double eps, double *hout) {
     const double s = *vn2;
@@ -149,8 +205,10 @@ struct Mat1D {
     double m[kMaxP][kMaxP];
 };
 
+// input x (minus x0 when given); output written, or added to y (acc)
 template <int DIM, int PI, int PO>
 __global__ void __launch_bounds__(kThreads) k_transfer_sf(int Ne, int nv, Mat1D M, const double *__restrict__ x,
+                                                          const double *__restrict__ x0, int acc,
                                                           double *__restrict__ y) {
     constexpr int NI = (DIM == 2) ? PI * PI : PI * PI * PI;
     constexpr int NO = (DIM == 2) ? PO * PO : PO * PO * PO;
@@ -161,7 +219,10 @@ __global__ void __launch_bounds__(kThreads) k_transfer_sf(int Ne, int nv, Mat1D 
     const int k = idx % Ne, v = idx / Ne;
     double a[NI];
 #pragma unroll
-    for (int j = 0; j < NI; ++j) a[j] = x[((size_t)v * NI + j) * Ne + k];
+    for (int j = 0; j < NI; ++j) {
+        const size_t i = ((size_t)v * NI + j) * Ne + k;
+        a[j] = x0 ? x[i] - x0[i] : x[i];
+    }
     double b[PZI * PI * PO];  // [z][y][x_out]
 #pragma unroll
     for (int z = 0; z < PZI; ++z)
@@ -188,7 +249,10 @@ __global__ void __launch_bounds__(kThreads) k_transfer_sf(int Ne, int nv, Mat1D 
             }
     if (DIM == 2) {
 #pragma unroll
-        for (int o = 0; o < NO; ++o) y[((size_t)v * NO + o) * Ne + k] = c[o];
+        for (int o = 0; o < NO; ++o) {
+            const size_t i = ((size_t)v * NO + o) * Ne + k;
+            y[i] = acc ? y[i] + c[o] : c[o];
+        }
     } else {
 #pragma unroll
         for (int o2 = 0; o2 < PZO; ++o2)
@@ -197,22 +261,25 @@ __global__ void __launch_bounds__(kThreads) k_transfer_sf(int Ne, int nv, Mat1D 
                 double s = 0.0;
 #pragma unroll
                 for (int j = 0; j < PZI; ++j) s += M.m[o2][j] * c[j * PO * PO + o];
-                y[((size_t)v * NO + o2 * PO * PO + o) * Ne + k] = s;
+                const size_t i = ((size_t)v * NO + o2 * PO * PO + o) * Ne + k;
+                y[i] = acc ? y[i] + s : s;
             }
     }
 }
 
 template <int DIM, int PI, int PO>
-void launch_sf(int Ne, int nv, const Mat1D &M, const double *x, double *y, hipStream_t s) {
+void launch_sf(int Ne, int nv, const Mat1D &M, const double *x, const double *x0, int acc, double *y,
+               hipStream_t s) {
     const int n = nv * Ne;
     hipLaunchKernelGGL((k_transfer_sf<DIM, PI, PO>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, Ne,
-                       nv, M, x, y);
+                       nv, M, x, x0, acc, y);
 }
 
 template <int DIM>
-bool dispatch_sf(int PI, int PO, int Ne, int nv, const Mat1D &M, const double *x, double *y, hipStream_t s) {
+bool dispatch_sf(int PI, int PO, int Ne, int nv, const Mat1D &M, const double *x, const double *x0, int acc,
+                 double *y, hipStream_t s) {
 #define FR_SF(a, b) \
-    if (PI == a && PO == b) { launch_sf<DIM, a, b>(Ne, nv, M, x, y, s); return true; }
+    if (PI == a && PO == b) { launch_sf<DIM, a, b>(Ne, nv, M, x, x0, acc, y, s); return true; }
     FR_SF(2, 3) FR_SF(2, 4) FR_SF(3, 2) FR_SF(3, 4) FR_SF(4, 2) FR_SF(4, 3) FR_SF(2, 1) FR_SF(1, 2)
     FR_SF(3, 1) FR_SF(1, 3) FR_SF(4, 1) FR_SF(1, 4)
     if (DIM == 2) {
@@ -226,6 +293,35 @@ bool dispatch_sf(int PI, int PO, int Ne, int nv, const Mat1D &M, const double *x
 
 hipError_t vec_dot(frpmg_ctx *ctx, size_t n, const double *x, const double *y, double *dout, hipStream_t s) {
     return vec_mdot(ctx, n, 1, x, 0, y, dout, s);
+}
+
+hipError_t vec_dot_fd_step(frpmg_ctx *ctx, size_t n, const double *v, const double *dqn2, double eps,
+                           double *n2out, double *hout, hipStream_t s) {
+    unsigned nb = grid_for(n);
+    if (nb > (unsigned)kRedBlocks) nb = kRedBlocks;
+    hipLaunchKernelGGL(k_mdot_partial, dim3(nb), dim3(kThreads), 0, s, n, 1, v, (size_t)0, v, ctx->red_partial);
+    hipLaunchKernelGGL(k_sum_fd_step, dim3(1), dim3(kThreads), 0, s, (int)nb, ctx->red_partial, dqn2, eps, n2out,
+                       hout);
+    return hipGetLastError();
+}
+
+hipError_t vec_dot_normalize(frpmg_ctx *ctx, size_t n, const double *x, double *n2out, double *y, hipStream_t s) {
+    unsigned nb = grid_for(n);
+    if (nb > (unsigned)kRedBlocks) nb = kRedBlocks;
+    hipLaunchKernelGGL(k_mdot_partial, dim3(nb), dim3(kThreads), 0, s, n, 1, x, (size_t)0, x, ctx->red_partial);
+    hipLaunchKernelGGL(k_sum_normalize, dim3(grid_for(n)), dim3(kThreads), 0, s, n, (int)nb, ctx->red_partial, n2out,
+                       x, y);
+    return hipGetLastError();
+}
+
+hipError_t vec_dot_pmg_scale(frpmg_ctx *ctx, size_t n, const double *x, const double *qn2, double eps_p,
+                             double sigma, double *n2out, double *s_out, double *inv_out, hipStream_t s) {
+    unsigned nb = grid_for(n);
+    if (nb > (unsigned)kRedBlocks) nb = kRedBlocks;
+    hipLaunchKernelGGL(k_mdot_partial, dim3(nb), dim3(kThreads), 0, s, n, 1, x, (size_t)0, x, ctx->red_partial);
+    hipLaunchKernelGGL(k_sum_pmg_scale, dim3(1), dim3(kThreads), 0, s, (int)nb, ctx->red_partial, qn2, eps_p, sigma,
+                       n2out, s_out, inv_out);
+    return hipGetLastError();
 }
 
 hipError_t vec_mdot(frpmg_ctx *ctx, size_t n, int nvec, const double *V, size_t ldv, const double *w,
@@ -287,7 +383,7 @@ hipError_t scal_pmg_scale(const double *xn2, const double *qn2, double eps_p, do
 }
 
 hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_dir, const double *x, double *y,
-                          hipStream_t s) {
+                          hipStream_t s, const double *x0, bool accumulate) {
     const Transfer1D &t = ctx->tr[fine_level];
     const int Pin = restrict_dir ? t.P0 : t.P1;
     const int Pout = restrict_dir ? t.P1 : t.P0;
@@ -295,8 +391,9 @@ hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_di
     Mat1D M{};
     for (int o = 0; o < Pout; ++o)
         for (int j = 0; j < Pin; ++j) M.m[o][j] = restrict_dir ? t.G[o][j] : t.Pi[o][j];
-    const bool ok = (ctx->dim == 2) ? dispatch_sf<2>(Pin, Pout, Ne, ctx->nv, M, x, y, s)
-                                    : dispatch_sf<3>(Pin, Pout, Ne, ctx->nv, M, x, y, s);
+    const int acc = accumulate ? 1 : 0;
+    const bool ok = (ctx->dim == 2) ? dispatch_sf<2>(Pin, Pout, Ne, ctx->nv, M, x, x0, acc, y, s)
+                                    : dispatch_sf<3>(Pin, Pout, Ne, ctx->nv, M, x, x0, acc, y, s);
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
