@@ -170,6 +170,54 @@ def stage_3d(steps=1):
     return out
 
 
+def learned_ab(wl, steps=3):
+    """The learned coarse correction on the config-2 mesh: pairs harvested by
+    the solver from plain-pMG stages and from V-cycles on random directions
+    at two other seeded states, the network trained on the GPU, then the
+    config-2 stage timed with the learned and with the plain preconditioner
+    (FP64 factors both)."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    fr = capi.FR.from_workload(wl)
+    rng = np.random.default_rng(11)
+    t0 = time.perf_counter()
+    fr.lcc_harvest(enable=1, max_pairs=400000, stride=4, target_sweeps=2, reset=1)
+    for seed in (12, 13):
+        w = W.make_vortical_workload(seed=seed)
+        fr.solve_stage(capi.stage_config_for(w), fr.to_dev(w.dq))
+        dq = fr.to_dev(w.dq)
+        sig_a = 1.0 / w.dt + 1.0 / (w.a_ii * w.dt)
+        sig_s = 1.0 / w.dt + sig_a
+        fr.ej_factor(0, dq, sig_s)
+        fr.ej_factor(1, fr.restrict(0, dq), sig_s)
+        fr.pmg_set_point(dq, fr.residual(0, dq))
+        for i in range(200):
+            x = fr.to_dev(rng.standard_normal(fr.shape(0)))
+            if i % 2 == 1:
+                x = fr.prolong(1, fr.restrict(0, x))
+            fr.pmg_apply(x, sig_a)
+    fr.lcc_harvest(enable=0)
+    t_harvest = time.perf_counter() - t0
+    ts = fr.lcc_train(epochs=60, batch=256, lr=1e-3, seed=7, holdout=0.1, reinit=1)
+    dq = fr.to_dev(wl.dq)
+    out = {"pairs": fr.lcc_count(), "t_harvest_s": t_harvest, "t_train_s": ts["t_train"],
+           "val_loss_ratio": ts["val_loss"] / ts["val_loss_init"]}
+    for key, cfg in (("plain_pmg", capi.stage_config_for(wl)),
+                     ("learned", capi.stage_config_for(wl, precond=capi.PRECOND_PMG_LEARNED))):
+        fr.solve_stage(cfg, dq)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st = fr.solve_stage(cfg, dq)
+        torch.cuda.synchronize()
+        out[key] = {"dof_per_s": wl.dof() * steps / (time.perf_counter() - t0), "gmres_iters": st["gmres_iters"],
+                    "ptc_iters": st["ptc_iters"], "rel_res": st["rel_res"], "fallbacks": st["fallbacks"]}
+    out["speedup_vs_plain"] = out["learned"]["dof_per_s"] / out["plain_pmg"]["dof_per_s"]
+    fr.close()
+    return out
+
+
 def fr_prec(fr):
     return getattr(fr, "_last_prec", 0)
 
@@ -385,6 +433,8 @@ def main():
         rates.update(kernel_rates_3d())
         print("[bench] 3D ROW stage", file=sys.stderr, flush=True)
         result["stage_3d"] = stage_3d()
+        print("[bench] learned coarse correction: harvest, train, A/B", file=sys.stderr, flush=True)
+        result["learned_coarse"] = learned_ab(wl)
         result["kernels"] = rates
         dom = rates["ej_apply_fine"]
         result["roofline"] = {

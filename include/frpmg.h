@@ -232,8 +232,8 @@ fr_status gmres_solve_stage(frpmg_ctx *ctx, const stage_params *prm, const doubl
  * Learned coarse correction (not in the paper): an element-local, bias-free
  * ReLU network in -> 256 -> 256 -> out refines the element-local coarse EJ
  * step.  With C1 = B1^{-1} Gamma d (one coarse EJ application to the
- * restricted defect), the input row of an element is C1 on the element plus
- * the traces of C1 of its 2 dim face neighbours (standardised per variable,
+ * restricted defect), the input row of an element is C1 on the element and
+ * on its 2 dim face neighbours (standardised per variable,
  * divided by the row norm s) followed by dim geometry entries
  * ln(h_a / max h_a); the coarse correction is
  *   C = C1 + tau s (N(x, g) - N(-x, g)) / 2,
@@ -242,9 +242,8 @@ fr_status gmres_solve_stage(frpmg_ctx *ctx, const stage_params *prm, const doubl
  * what target_sweeps coarse EJ sweeps add to C1.  Products run on BF16 MFMA
  * with FP32 accumulation; FP32 master weights, Adam.
  * Feature row layout: [own (nv Np1, index v Np1 + i) | for each axis a:
- * the -a neighbour's trace at its + end, then the +a neighbour's trace at its
- * - end (nv NF1 each, index v NF1 + f) | geometry (dim)], zero padded to
- * nin_pad.
+ * the -a neighbour's values, then the +a neighbour's values (nv Np1 each,
+ * index v Np1 + i) | geometry (dim)], zero padded to nin_pad.
  * Weight layout (FP32, row-major): W1 [256 x nin_pad] | W2 [256 x 256] |
  * W3 [nout_pad x 256].
  * ------------------------------------------------------------------------ */

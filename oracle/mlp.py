@@ -1,8 +1,8 @@
 """FP64 oracle of the learned coarse correction (test infrastructure only).
 
 Not in the paper: a bias-free ReLU network N(x) = W3 relu(W2 relu(W1 x))
-applied per element to a feature row built from the restricted defect of
-the element and the defect traces of its face neighbours, replacing the
+applied per element to a feature row built from the element-local coarse
+step on the element and on its face neighbours, replacing the
 coarse smoothing sweeps of the p-multigrid V-cycle (Sec. 3.1's coarse
 correction C).  Everything here is the plain definition in FP64.
 """
@@ -10,7 +10,6 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import ops1d
 
 
 def relu(x):
@@ -45,28 +44,24 @@ def loss_grad(Ws, X, T, nout):
 
 def features(d1, dim, n, P1, in_scale, nin_pad, h):
     """Feature rows of a level-1 field d1 [nv][Np1][Ne]: the element's own
-    values, then per axis the trace of the -axis neighbour at its + end and of
-    the +axis neighbour at its - end, each divided by the variable's scale;
-    this defect part divided by its 2-norm s; then, per axis, ln(h_a / max h_a)
-    of the element (h: element widths per axis).  Returns (rows, s)."""
+    values, then per axis the values of the -axis neighbour and of the +axis
+    neighbour, each divided by the variable's scale; this defect part divided
+    by its 2-norm s; then, per axis, ln(h_a / max h_a) of the element (h:
+    element widths per axis).  Returns (rows, s)."""
     nv, Np, Ne = d1.shape
-    o = ops1d(P1)
-    NF = P1 ** (dim - 1)
     nn = list(n) + [1] * (3 - len(n))
     rows = np.zeros((Ne, nin_pad))
     s = np.zeros(Ne)
+    scale = np.repeat(in_scale[:nv], Np)
     for k in range(Ne):
         kc = [k % nn[0], (k // nn[0]) % nn[1], k // (nn[0] * nn[1])]
-        parts = [d1[:, :, k].reshape(-1) / np.repeat(in_scale[:nv], Np)]
+        parts = [d1[:, :, k].reshape(-1) / scale]
         for a in range(dim):
-            for side, w in ((-1, o["bp"]), (1, o["bm"])):
+            for side in (-1, 1):
                 c = list(kc)
                 c[a] = (c[a] + side) % nn[a]
                 kn = c[0] + nn[0] * (c[1] + nn[1] * c[2])
-                e = d1[:, :, kn].reshape(nv, *([P1] * dim)[::-1])       # [v][(i2)][i1][i0]
-                ax = dim - a                                           # array axis of direction a
-                tr = np.tensordot(e, w, axes=([ax], [0]))             # [v][face points]
-                parts.append((tr.reshape(nv, NF) / in_scale[:nv, None]).reshape(-1))
+                parts.append(d1[:, :, kn].reshape(-1) / scale)
         row = np.concatenate(parts)
         nr = float(np.linalg.norm(row))
         s[k] = nr

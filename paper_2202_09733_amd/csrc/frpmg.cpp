@@ -232,7 +232,7 @@ void lcc_alloc(frpmg_ctx *ctx) {
     Lcc &L = *Lp;
     const Level &C = ctx->lv[1];
     L.ngeo = ctx->dim;
-    L.nin = C.nb + 2 * ctx->dim * ctx->nv * C.NF + L.ngeo;
+    L.nin = C.nb * (1 + 2 * ctx->dim) + L.ngeo;
     L.nin_pad = round_up(L.nin, 32);
     L.nout = C.nb;
     L.nout_pad = round_up(L.nout, 32);

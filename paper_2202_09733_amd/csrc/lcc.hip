@@ -2,7 +2,7 @@
 //
 // An element-local, bias-free ReLU network N (in -> H -> H -> out) refines
 // the element-local coarse EJ step C1 = B1^{-1} Gamma d: it reads C1 on the
-// element, the traces of C1 of its 2 dim face neighbours and the element's
+// element and on its 2 dim face neighbours, and the element's
 // (log) sizes, and returns what a deeper coarse solve adds to C1; together
 // they replace the coarse smoothing sweeps of the V-cycle.  The C1 inputs are
 // standardised per variable (fixed scales from the training data) and divided
@@ -92,64 +92,70 @@ __global__ void k_f32_to_bf(size_t n, const float *__restrict__ a, __bf16 *__res
 }
 
 // Feature rows of one level-1 defect field d (layout [nv][Np1][Ne]):
-// [own d (nv Np1) | for each axis a: trace of the -a neighbour at its + end,
-//  trace of the +a neighbour at its - end (nv NF1 each)] / sigma_v, zero
-// padded to ld, then divided by the row norm s (s = 0: zero row).
+// [own d (nv Np1) | for each axis a: the -a neighbour's d, then the +a
+//  neighbour's d (nv Np1 each)] / sigma_v, zero padded to ld, then divided by
+// the row norm s (s = 0: zero row).
 // sign_rows: rows Ne..2Ne-1 receive the negated row (odd evaluation).
 // After the normalised defect part come dim geometry entries
 // ln(h_a(k) / max_a h), which do not scale with the defect.
+// One 64-lane wavefront per element row: each lane forms the entries
+// j = lane, lane + 64, ..., the row norm is a wavefront reduction.
+constexpr int kFeatPerLane = 16;  // rows up to 64 x 16 = 1024 entries
+
 template <int DIM>
-__global__ void k_features(int Ne, int nx, int ny, int P, const double *__restrict__ d, Ops1D ops,
-                           const float *__restrict__ in_scale, int ld, int nin, float *__restrict__ Xf,
-                           __bf16 *__restrict__ Xb, float *__restrict__ srow, int both_signs, MeshK mesh,
-                           double hx, double hy, double hz) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_features(int Ne, int nx, int ny, int P, const double *__restrict__ d,
+                                                  const float *__restrict__ in_scale, int ld, int nin,
+                                                  float *__restrict__ Xf, __bf16 *__restrict__ Xb,
+                                                  float *__restrict__ srow, int both_signs, MeshK mesh, double hx,
+                                                  double hy, double hz) {
+    const int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (k >= Ne) return;
     const int nv = DIM + 2;
     const int Np = (DIM == 2) ? P * P : P * P * P;
-    const int NF = (DIM == 2) ? P : P * P;
+    const int nblk = nv * Np;
     const int ix = k % nx, iy = (k / nx) % ny, iz = k / (nx * ny);
     const int nz = Ne / (nx * ny);
-    float *row = Xf + (size_t)k * ld;
-    int c = 0;
-    for (int v = 0; v < nv; ++v)
-        for (int i = 0; i < Np; ++i) row[c++] = (float)(d[((size_t)v * Np + i) * Ne + k] / in_scale[v]);
-    for (int a = 0; a < DIM; ++a) {
-        for (int side = 0; side < 2; ++side) {
-            // side 0: neighbour at -a (its + trace); side 1: neighbour at +a (its - trace)
-            int jx = ix, jy = iy, jz = iz;
-            const int s = side == 0 ? -1 : 1;
-            if (a == 0) jx = (ix + s + nx) % nx;
-            if (a == 1) jy = (iy + s + ny) % ny;
-            if (a == 2) jz = (iz + s + nz) % nz;
-            const int kn = jx + nx * (jy + ny * jz);
-            for (int v = 0; v < nv; ++v)
-                for (int f = 0; f < NF; ++f) {
-                    double t = 0.0;
-                    for (int j = 0; j < P; ++j) {
-                        int i;
-                        if (a == 0) i = j + P * f;
-                        else if (DIM == 2) i = f + P * j;
-                        else if (a == 1) i = (f % P) + P * (j + P * (f / P));
-                        else i = f + P * P * j;
-                        const double w = side == 0 ? ops.bp[j] : ops.bm[j];
-                        t += w * d[((size_t)v * Np + i) * Ne + kn];
-                    }
-                    row[c++] = (float)(t / in_scale[v]);
-                }
-        }
-    }
     const int ndef = nin - DIM;  // defect entries
+    float vals[kFeatPerLane];
     double ss = 0.0;
-    for (int j = 0; j < ndef; ++j) ss += (double)row[j] * row[j];
+#pragma unroll
+    for (int u = 0; u < kFeatPerLane; ++u) {
+        const int j = lane + 64 * u;
+        float x = 0.f;
+        if (j < ndef) {
+            const int part = j / nblk, rem = j - part * nblk;
+            const int v = rem / Np, i = rem - v * Np;
+            int kel = k;
+            if (part > 0) {
+                // part 1 + 2a + side: side 0 the -a neighbour, side 1 the +a neighbour
+                const int a = (part - 1) >> 1;
+                const int sgn = ((part - 1) & 1) ? 1 : -1;
+                int jx = ix, jy = iy, jz = iz;
+                if (a == 0) jx = (ix + sgn + nx) % nx;
+                if (a == 1) jy = (iy + sgn + ny) % ny;
+                if (a == 2) jz = (iz + sgn + nz) % nz;
+                kel = jx + nx * (jy + ny * jz);
+            }
+            x = (float)(d[((size_t)v * Np + i) * Ne + kel] / in_scale[v]);
+            ss += (double)x * x;
+        }
+        vals[u] = x;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
     const float sn = (float)sqrt(ss);
     const float inv = sn > 0.f ? 1.f / sn : 0.f;
     const int ic[3] = {ix, iy, iz};
     const double hmax[3] = {hx, hy, hz};
-    for (int j = 0; j < ld; ++j) {
+    float *row = Xf + (size_t)k * ld;
+#pragma unroll
+    for (int u = 0; u < kFeatPerLane; ++u) {
+        const int j = lane + 64 * u;
+        if (j >= ld) break;
         float x = 0.f, xm = 0.f;
         if (j < ndef) {
-            x = row[j] * inv;
+            x = vals[u] * inv;
             xm = -x;
         } else if (j < nin) {
             const int a = j - ndef;
@@ -160,7 +166,7 @@ __global__ void k_features(int Ne, int nx, int ny, int P, const double *__restri
         Xb[(size_t)k * ld + j] = to_bf(x);
         if (both_signs) Xb[(size_t)(Ne + k) * ld + j] = to_bf(xm);
     }
-    srow[k] = sn;
+    if (lane == 0) srow[k] = sn;
 }
 
 // Target rows: C (layout [nv][Np1][Ne]) / tau_v / s, zero padded.
@@ -309,13 +315,14 @@ hipError_t lcc_features(const frpmg_ctx *ctx, const double *d, const Lcc &L, flo
                         int both_signs, hipStream_t s) {
     const int Ne = ctx->mesh.Ne;
     const Level &C = ctx->lv[1];
-    dim3 grid((Ne + 127) / 128);
+    if (L.nin_pad > 64 * kFeatPerLane) return hipErrorInvalidValue;
+    dim3 grid((Ne + 3) / 4);  // four elements (wavefronts) per workgroup
     if (ctx->dim == 2)
-        hipLaunchKernelGGL(k_features<2>, grid, dim3(128), 0, s, Ne, ctx->mesh.n[0], ctx->mesh.n[1], C.P, d, C.ops,
+        hipLaunchKernelGGL(k_features<2>, grid, dim3(256), 0, s, Ne, ctx->mesh.n[0], ctx->mesh.n[1], C.P, d,
                            L.in_scale, L.nin_pad, L.nin, Xf, Xb, srow, both_signs, ctx->mesh, L.hmax[0], L.hmax[1],
                            L.hmax[2]);
     else
-        hipLaunchKernelGGL(k_features<3>, grid, dim3(128), 0, s, Ne, ctx->mesh.n[0], ctx->mesh.n[1], C.P, d, C.ops,
+        hipLaunchKernelGGL(k_features<3>, grid, dim3(256), 0, s, Ne, ctx->mesh.n[0], ctx->mesh.n[1], C.P, d,
                            L.in_scale, L.nin_pad, L.nin, Xf, Xb, srow, both_signs, ctx->mesh, L.hmax[0], L.hmax[1],
                            L.hmax[2]);
     return hipGetLastError();

@@ -60,8 +60,8 @@ def test_homogeneity_and_oddness():
 @pytest.mark.parametrize("dim,n,P1", [(2, (4, 6), 3), (3, (2, 4, 2), 3)])
 def test_features_of_elementwise_constant_field(dim, n, P1):
     """A field constant inside each element: own part = the constant, every
-    trace = the neighbour's constant (the end interpolants sum to one), so
-    the layout and the neighbour on each side are pinned."""
+    neighbour part = that neighbour's constant, so the layout and the
+    neighbour on each side are pinned."""
     nv = dim + 2
     Np = P1 ** dim
     NF = P1 ** (dim - 1)
@@ -70,7 +70,7 @@ def test_features_of_elementwise_constant_field(dim, n, P1):
     const = rng.uniform(1, 2, (nv, Ne))
     d1 = np.repeat(const[:, None, :], Np, axis=1)
     in_scale = np.array([1.0, 2.0, 4.0, 8.0, 16.0])
-    nin = nv * Np + 2 * dim * nv * NF
+    nin = nv * Np * (1 + 2 * dim)
     h = [np.linspace(1.0, 2.0, n[a]) for a in range(dim)]
     rows, s = mlp.features(d1, dim, n, P1, in_scale, nin + dim + 3, h)
     nn = list(n) + [1] * (3 - len(n))
@@ -84,8 +84,8 @@ def test_features_of_elementwise_constant_field(dim, n, P1):
                 c = list(kc)
                 c[a] = (c[a] + side) % nn[a]
                 kn = c[0] + nn[0] * (c[1] + nn[1] * c[2])
-                assert np.allclose(raw[off:off + nv * NF], np.repeat(const[:, kn] / in_scale[:nv], NF))
-                off += nv * NF
+                assert np.allclose(raw[off:off + nv * Np], np.repeat(const[:, kn] / in_scale[:nv], Np))
+                off += nv * Np
         for a in range(dim):
             assert abs(rows[k, nin + a] - np.log(h[a][kc[a]] / 2.0)) < 1e-14
         assert np.all(rows[k, nin + dim:] == 0.0)
