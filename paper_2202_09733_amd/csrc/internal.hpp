@@ -99,7 +99,8 @@ struct Level {
 };
 
 // Reduction scratch: partial sums per block and per vector.
-constexpr int kRedBlocks = 512;
+constexpr int kRedBlocks = 2048;     // capacity of the partial-sum buffer per vector
+constexpr size_t kRedLarge = 4u << 20;  // vectors at least this long use up to kRedBlocks partials, others 512
 
 // One captured Arnoldi step: the instantiated graph, the bit patterns of every
 // parameter and pointer it bakes in, and the operation counts of one replay.

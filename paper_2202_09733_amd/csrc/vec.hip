@@ -28,19 +28,33 @@ __device__ __forceinline__ double block_sum(double v, double *s_red) {
     return r;
 }
 
-// partial[vec * nblk + block] = sum over this block's strided share of V_vec . w
+// partial[vec * nblk + block] = sum over this block's strided share of V_vec . w.
+// The vectors are taken kChunk at a time with w read once per chunk; each
+// vector's terms are still summed in the same order (so the result does not
+// depend on the chunking).
+constexpr int kChunk = 8;
+
 __global__ void __launch_bounds__(kThreads) k_mdot_partial(size_t n, int nvec, const double *__restrict__ V,
                                                            size_t ldv, const double *__restrict__ w,
                                                            double *__restrict__ partial) {
     __shared__ double s_red[kThreads / 64];
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int vec = 0; vec < nvec; ++vec) {
-        const double *x = V + (size_t)vec * ldv;
-        double acc = 0.0;
-        for (size_t i = i0; i < n; i += stride) acc += x[i] * w[i];
-        const double tot = block_sum(acc, s_red);
-        if (threadIdx.x == 0) partial[(size_t)vec * gridDim.x + blockIdx.x] = tot;
+    for (int v0 = 0; v0 < nvec; v0 += kChunk) {
+        const int nc = min(kChunk, nvec - v0);
+        double acc[kChunk];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) acc[c] = 0.0;
+        for (size_t i = i0; i < n; i += stride) {
+            const double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c)
+                if (c < nc) acc[c] += V[(size_t)(v0 + c) * ldv + i] * wi;
+        }
+        for (int c = 0; c < nc; ++c) {
+            const double tot = block_sum(acc[c], s_red);
+            if (threadIdx.x == 0) partial[(size_t)(v0 + c) * gridDim.x + blockIdx.x] = tot;
+        }
     }
 }
 
@@ -197,6 +211,13 @@ unsigned grid_for(size_t n) {
     return (unsigned)b;
 }
 
+// partial sums per vector of a dot product of length n (fixed per n)
+unsigned red_blocks(size_t n) {
+    const unsigned nb = grid_for(n);
+    const unsigned cap = n >= kRedLarge ? (unsigned)kRedBlocks : 512u;
+    return nb > cap ? cap : nb;
+}
+
 // Restriction / prolongation, sum-factorised: one lane per (variable,
 // element) applies the 1D operator M (PO x PI) along x, then y (then z), all
 // in registers.  Compile-time sizes let the operator entries come from the
@@ -297,8 +318,7 @@ hipError_t vec_dot(frpmg_ctx *ctx, size_t n, const double *x, const double *y, d
 
 hipError_t vec_dot_fd_step(frpmg_ctx *ctx, size_t n, const double *v, const double *dqn2, double eps,
                            double *n2out, double *hout, hipStream_t s) {
-    unsigned nb = grid_for(n);
-    if (nb > (unsigned)kRedBlocks) nb = kRedBlocks;
+    const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_mdot_partial, dim3(nb), dim3(kThreads), 0, s, n, 1, v, (size_t)0, v, ctx->red_partial);
     hipLaunchKernelGGL(k_sum_fd_step, dim3(1), dim3(kThreads), 0, s, (int)nb, ctx->red_partial, dqn2, eps, n2out,
                        hout);
@@ -306,8 +326,7 @@ hipError_t vec_dot_fd_step(frpmg_ctx *ctx, size_t n, const double *v, const doub
 }
 
 hipError_t vec_dot_normalize(frpmg_ctx *ctx, size_t n, const double *x, double *n2out, double *y, hipStream_t s) {
-    unsigned nb = grid_for(n);
-    if (nb > (unsigned)kRedBlocks) nb = kRedBlocks;
+    const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_mdot_partial, dim3(nb), dim3(kThreads), 0, s, n, 1, x, (size_t)0, x, ctx->red_partial);
     hipLaunchKernelGGL(k_sum_normalize, dim3(grid_for(n)), dim3(kThreads), 0, s, n, (int)nb, ctx->red_partial, n2out,
                        x, y);
@@ -316,8 +335,7 @@ hipError_t vec_dot_normalize(frpmg_ctx *ctx, size_t n, const double *x, double *
 
 hipError_t vec_dot_pmg_scale(frpmg_ctx *ctx, size_t n, const double *x, const double *qn2, double eps_p,
                              double sigma, double *n2out, double *s_out, double *inv_out, hipStream_t s) {
-    unsigned nb = grid_for(n);
-    if (nb > (unsigned)kRedBlocks) nb = kRedBlocks;
+    const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_mdot_partial, dim3(nb), dim3(kThreads), 0, s, n, 1, x, (size_t)0, x, ctx->red_partial);
     hipLaunchKernelGGL(k_sum_pmg_scale, dim3(1), dim3(kThreads), 0, s, (int)nb, ctx->red_partial, qn2, eps_p, sigma,
                        n2out, s_out, inv_out);
@@ -326,8 +344,7 @@ hipError_t vec_dot_pmg_scale(frpmg_ctx *ctx, size_t n, const double *x, const do
 
 hipError_t vec_mdot(frpmg_ctx *ctx, size_t n, int nvec, const double *V, size_t ldv, const double *w,
                     double *dout, hipStream_t s) {
-    unsigned nb = grid_for(n);
-    if (nb > (unsigned)kRedBlocks) nb = kRedBlocks;
+    const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_mdot_partial, dim3(nb), dim3(kThreads), 0, s, n, nvec, V, ldv, w, ctx->red_partial);
     hipLaunchKernelGGL(k_sum_partials, dim3(nvec), dim3(kThreads), 0, s, (int)nb, ctx->red_partial, dout);
     return hipGetLastError();
