@@ -277,6 +277,14 @@ def only_kernel(args):
     sig = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
     x = torch.randn_like(dq)
     y = fr.empty(0)
+    if args.only_kernel == "stage":
+        # whole stage solves (set-up included) in the requested precision
+        for _ in range(args.reps):
+            _, st = fr.solve_stage(capi.stage_config_for(wl, precision=prec), dq)
+            print("[bench] stage: %d FGMRES, set-up %.3f s, solve %.3f s" % (st["gmres_iters"], st["t_setup"],
+                                                                           st["t_solve"]), file=sys.stderr)
+        torch.cuda.synchronize()
+        return
     if args.only_kernel == "ej_apply":
         fr.ej_factor(0, dq, sig, prec)
     rq = fr.residual(0, dq)
@@ -309,7 +317,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the EJ-only comparison and kernel rates")
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
-    ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "ej_factor", "residual", "jvp"],
+    ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "ej_factor", "residual", "jvp", "stage"],
                     help="profiling driver: set up the workload's state, launch one kernel family --reps times "
                          "and a 256 MiB device copy (counter calibration), print nothing else")
     ap.add_argument("--workload", default="config2", choices=["config2", "config4"],
