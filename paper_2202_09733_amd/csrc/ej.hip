@@ -9,6 +9,8 @@
 // the BF16-MFMA precision form at any size, use the blocked variant below.  Storing the inverse
 // turns every apply into a batched GEMV that streams the blocks once from
 // HBM with coalesced column reads, with no sequential triangular sweeps.
+#include <utility>
+
 #include "internal.hpp"
 
 namespace frpmg {
@@ -129,7 +131,7 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
 
 // ---------------------------------------------------------------------------
 // Blocked in-place Gauss-Jordan for blocks too large for LDS (n_b > 140, e.g.
-// 320 x 320 in 3D at p = 3).  Panels of kPanel columns are eliminated in LDS
+// 320 x 320 in 3D at p = 3).  Panels of kPanel columns are eliminated in registers
 // (pivot search over the full column, row swaps recorded); the product of the
 // panel's elementary transforms T = (I + W S^T) P (S = the panel's pivot rows)
 // is then applied to every other column at once as a GEMM:
@@ -139,94 +141,105 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
 // ---------------------------------------------------------------------------
 constexpr int kPanel = 32;
 
-template <int dummy = 0>
-__global__ void __launch_bounds__(kGJThreads) k_gj_panel(int nb, int c0, int bw, double *__restrict__ A,
-                                                         int *__restrict__ perm, int *__restrict__ status) {
-    extern __shared__ double Pn[];  // [bw][nb] column-major panel
-    double *colk = Pn + (size_t)bw * nb;
-    __shared__ double s_v[kGJThreads / 64];
-    __shared__ int s_i[kGJThreads / 64];
-    __shared__ int s_piv;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int RT = min(nt, ((nb + 63) / 64) * 64);
-    const int er = tid % RT, eg = tid / RT, ng = nt / RT;
-    double *Ak = A + (size_t)blockIdx.x * nb * nb;
-    for (int t = tid; t < bw * nb; t += nt) Pn[t] = Ak[(size_t)c0 * nb + t];
-    __syncthreads();
-    bool singular = false;
-    for (int cc = 0; cc < bw; ++cc) {
-        const int c = c0 + cc;
-        double best = -1.0;
-        int bi = 0x7fffffff;
-        for (int r = c + tid; r < nb; r += nt) argmax_combine(best, bi, fabs(Pn[cc * nb + r]), r);
+// Panel factorisation with the panel in registers: lane r owns row r of the
+// panel (kPanel values).  Per pivot step: the argmax of |column| over rows
+// >= c (wavefront shuffles, then across wavefronts through LDS; the lowest
+// row wins ties), then the pivot row and row c are exchanged through LDS,
+// every lane reads the pivot row and updates its own row.  Three barriers per
+// step and under 1 KB of LDS, so several blocks share a CU.  The steps are
+// instantiated per panel column so that every register index is a constant
+// (a runtime index would put the row in scratch memory).
+struct PanelLds {
+    double v[8];
+    int i[8];
+    int piv;
+    double pivrow[kPanel];  // the pivot row (old row p)
+    double oldc[kPanel];    // old row c, taken over by lane p
+};
+
+template <int CC>
+__device__ __forceinline__ void panel_step(double (&x)[kPanel], PanelLds &sh, int r, int nb, int c0, int bw,
+                                           int nw, int *__restrict__ perm, bool &singular) {
+    if (CC >= bw) return;
+    const int c = c0 + CC;
+    double best = (r >= c && r < nb) ? fabs(x[CC]) : -1.0;
+    int bi = (r >= c && r < nb) ? r : 0x7fffffff;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double v2 = __shfl_down(best, off, 64);
-            const int i2 = __shfl_down(bi, off, 64);
-            argmax_combine(best, bi, v2, i2);
-        }
-        if ((tid & 63) == 0) {
-            s_v[tid >> 6] = best;
-            s_i[tid >> 6] = bi;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double bv = s_v[0];
-            int ii = s_i[0];
-            for (int w = 1; w < nt / 64; ++w) argmax_combine(bv, ii, s_v[w], s_i[w]);
-            s_piv = ii;
-            perm[(size_t)blockIdx.x * nb + c] = ii;
-        }
-        __syncthreads();
-        const int p = s_piv;
-        if (p != c) {
-            for (int j = tid; j < bw; j += nt) {
-                const double t0 = Pn[j * nb + c];
-                Pn[j * nb + c] = Pn[j * nb + p];
-                Pn[j * nb + p] = t0;
-            }
-        }
-        __syncthreads();
-        double d = Pn[cc * nb + c];
-        if (d == 0.0) {
-            singular = true;
-            d = 1.0;
-        }
-        const double inv = 1.0 / d;
-        for (int r = tid; r < nb; r += nt) colk[r] = Pn[cc * nb + r];
-        __syncthreads();
-        for (int j = tid; j < bw; j += nt) Pn[j * nb + c] = (j == cc ? 1.0 : Pn[j * nb + c]) * inv;
-        __syncthreads();
-        // lane = (row er + k RT, column group eg): no division in the loop, and
-        // the pivot-row reads of four columns issue ahead of the updates
-        if (eg < ng) {
-            for (int r = er; r < nb; r += RT) {
-                if (r == c) continue;
-                const double f = colk[r];
-                int j = eg;
-                for (; j + 3 * ng < bw; j += 4 * ng) {
-                    double a[4], pv[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        a[u] = Pn[(j + u * ng) * nb + r];
-                        pv[u] = Pn[(j + u * ng) * nb + c];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const double cur = (j + u * ng == cc) ? 0.0 : a[u];
-                        Pn[(j + u * ng) * nb + r] = cur - f * pv[u];
-                    }
-                }
-                for (; j < bw; j += ng) {
-                    const double cur = (j == cc) ? 0.0 : Pn[j * nb + r];
-                    Pn[j * nb + r] = cur - f * Pn[j * nb + c];
-                }
-            }
-        }
-        __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+        const double v2 = __shfl_down(best, off, 64);
+        const int i2 = __shfl_down(bi, off, 64);
+        argmax_combine(best, bi, v2, i2);
     }
-    for (int t = tid; t < bw * nb; t += nt) Ak[(size_t)c0 * nb + t] = Pn[t];
-    if (singular && tid == 0) status[0] = 1;
+    if ((r & 63) == 0) {
+        sh.v[r >> 6] = best;
+        sh.i[r >> 6] = bi;
+    }
+    __syncthreads();
+    if (r == 0) {
+        double bv = sh.v[0];
+        int ii = sh.i[0];
+        for (int w = 1; w < nw; ++w) argmax_combine(bv, ii, sh.v[w], sh.i[w]);
+        sh.piv = ii;
+        perm[(size_t)blockIdx.x * nb + c] = ii;
+    }
+    __syncthreads();
+    const int p = sh.piv;
+    if (r == p) {
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) sh.pivrow[j] = x[j];
+    }
+    if (r == c && p != c) {
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) sh.oldc[j] = x[j];
+    }
+    __syncthreads();
+    if (r == p && p != c) {
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) x[j] = sh.oldc[j];
+    }
+    double d = sh.pivrow[CC];
+    if (d == 0.0) {
+        singular = true;
+        d = 1.0;
+    }
+    const double inv = 1.0 / d;
+    if (r == c) {
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) x[j] = (j == CC ? 1.0 : sh.pivrow[j]) * inv;
+    } else if (r < nb) {
+        const double f = x[CC];
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) {
+            const double pv = (j == CC ? 1.0 : sh.pivrow[j]) * inv;
+            x[j] = (j == CC ? 0.0 : x[j]) - f * pv;
+        }
+    }
+}
+
+template <int... CC>
+__device__ __forceinline__ void panel_steps(std::integer_sequence<int, CC...>, double (&x)[kPanel], PanelLds &sh,
+                                            int r, int nb, int c0, int bw, int nw, int *__restrict__ perm,
+                                            bool &singular) {
+    (panel_step<CC>(x, sh, r, nb, c0, bw, nw, perm, singular), ...);
+}
+
+__global__ void __launch_bounds__(512) k_gj_panel_reg(int nb, int c0, int bw, double *__restrict__ A,
+                                                      int *__restrict__ perm, int *__restrict__ status) {
+    __shared__ PanelLds sh;
+    const int r = threadIdx.x;
+    const int nw = blockDim.x >> 6;
+    double *Ak = A + (size_t)blockIdx.x * nb * nb;
+    double x[kPanel];
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) x[j] = (r < nb && j < bw) ? Ak[(size_t)(c0 + j) * nb + r] : 0.0;
+    bool singular = false;
+    panel_steps(std::make_integer_sequence<int, kPanel>{}, x, sh, r, nb, c0, bw, nw, perm, singular);
+    if (r < nb) {
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j)
+            if (j < bw) Ak[(size_t)(c0 + j) * nb + r] = x[j];
+    }
+    if (singular && r == 0) status[0] = 1;
 }
 
 constexpr int kUpdCols = 64;  // columns per update workgroup
@@ -479,14 +492,10 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
     if (nb > kMaxLdsBlock || precision == FR_PREC_FP32_BF16 || precision == FR_PREC_BF16_STORE) {
         if (nb > 512 || !L.perm) return hipErrorInvalidValue;
         const bool mfma = precision != FR_PREC_FP64;
-        const size_t lds_p = ((size_t)kPanel * nb + nb) * sizeof(double);
-        hipError_t e = hipFuncSetAttribute((const void *)k_gj_panel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_p);
-        if (e != hipSuccess) return e;
+        const int rows = ((nb + 63) / 64) * 64;  // one lane per block row
         for (int c0 = 0; c0 < nb; c0 += kPanel) {
             const int bw = min(kPanel, nb - c0);
-            hipLaunchKernelGGL(k_gj_panel<0>, dim3(Ne), dim3(kGJThreads), lds_p, s, nb, c0, bw, L.blk64, L.perm,
-                               L.dstatus);
+            hipLaunchKernelGGL(k_gj_panel_reg, dim3(Ne), dim3(rows), 0, s, nb, c0, bw, L.blk64, L.perm, L.dstatus);
             const int nrest = nb - bw;
             if (nrest > 0) {
                 const dim3 gu(Ne, (nrest + kUpdCols - 1) / kUpdCols);
