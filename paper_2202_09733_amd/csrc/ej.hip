@@ -2,13 +2,15 @@
 // element-Jacobi preconditioner; Sec. 3.2, EJ smoother).  The batched apply
 // with the stored inverses is in ej_apply.hip.
 //
-// Inversion: one workgroup per block, the whole FP64 block resident in LDS
-// (n_b <= 140 fits in the 160 KB of a CU), Gauss-Jordan elimination with
+// Inversion of small blocks (n_b <= 128: 2D up to p = 4): one workgroup per
+// block, the whole FP64 block resident in LDS, Gauss-Jordan elimination with
 // partial pivoting (largest |a|, first row on ties), the inverse written
-// back column-major in the requested storage precision.  Larger blocks, and
-// the BF16-MFMA precision form at any size, use the blocked variant below.  Storing the inverse
-// turns every apply into a batched GEMV that streams the blocks once from
-// HBM with coalesced column reads, with no sequential triangular sweeps.
+// back column-major in the requested storage precision.  Larger blocks (3D
+// from p = 2; an LDS-resident 135^2 block leaves one workgroup per CU and
+// ran 4x slower than the blocked form), and the BF16-MFMA precision form at
+// any size, use the blocked variant below.  Storing the inverse turns every
+// apply into a batched GEMV that streams the blocks once from HBM with
+// coalesced column reads, with no sequential triangular sweeps.
 #include <utility>
 
 #include "internal.hpp"
@@ -18,7 +20,7 @@ namespace frpmg {
 namespace {
 
 constexpr int kGJThreads = 256;
-constexpr int kMaxLdsBlock = 140;
+constexpr int kMaxLdsBlock = 128;
 
 __device__ __forceinline__ void argmax_combine(double &v, int &i, double v2, int i2) {
     if (v2 > v || (v2 == v && i2 < i)) {
@@ -130,14 +132,16 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
 }
 
 // ---------------------------------------------------------------------------
-// Blocked in-place Gauss-Jordan for blocks too large for LDS (n_b > 140, e.g.
-// 320 x 320 in 3D at p = 3).  Panels of kPanel columns are eliminated in registers
-// (pivot search over the full column, row swaps recorded); the product of the
-// panel's elementary transforms T = (I + W S^T) P (S = the panel's pivot rows)
-// is then applied to every other column at once as a GEMM:
+// Blocked in-place Gauss-Jordan for the larger blocks (135 x 135 and
+// 320 x 320 in 3D at p = 2, 3).  Panels of kPanel columns are eliminated in
+// registers (pivot search over the full column, row swaps recorded); the
+// product of the panel's elementary transforms T = (I + W S^T) P (S = the
+// panel's pivot rows) is then applied to every other column at once as a
+// GEMM:
 //     x <- (P x with the pivot rows zeroed) + T_panel (P x)_S,
-// where T_panel = the panel columns just written back.  After the last panel
-// the row interchanges are undone as column interchanges, last first.
+// where T_panel = the panel columns just written back.  The row interchanges
+// turn into column interchanges of the result, which are not carried out:
+// the column placement is recorded and the apply gathers r through it.
 // ---------------------------------------------------------------------------
 constexpr int kPanel = 32;
 
@@ -149,17 +153,27 @@ constexpr int kPanel = 32;
 // step and under 1 KB of LDS, so several blocks share a CU.  The steps are
 // instantiated per panel column so that every register index is a constant
 // (a runtime index would put the row in scratch memory).
+//
+// Each lane also tracks which input row its values came from; at the end the
+// panel writes the list of touched rows (the panel rows S in order, then
+// every other row whose content moved, with its source row) that the update
+// kernels use to apply the interchanges to the other columns as a gather.
+constexpr int kTouch = 2 * kPanel;            // S plus at most one moved row per pivot step
+static_assert(kTouchStride == 1 + 2 * kTouch, "touched-row list: count, rows[kTouch], sources[kTouch]");
+
 struct PanelLds {
     double v[8];
     int i[8];
+    int cnt[8];
     int piv;
+    int porg, corg;         // source rows of the pivot row and of row c
     double pivrow[kPanel];  // the pivot row (old row p)
     double oldc[kPanel];    // old row c, taken over by lane p
 };
 
 template <int CC>
-__device__ __forceinline__ void panel_step(double (&x)[kPanel], PanelLds &sh, int r, int nb, int c0, int bw,
-                                           int nw, int *__restrict__ perm, bool &singular) {
+__device__ __forceinline__ void panel_step(double (&x)[kPanel], int &org, PanelLds &sh, int r, int nb, int c0,
+                                           int bw, int nw, int *__restrict__ perm, bool &singular) {
     if (CC >= bw) return;
     const int c = c0 + CC;
     double best = (r >= c && r < nb) ? fabs(x[CC]) : -1.0;
@@ -187,16 +201,20 @@ __device__ __forceinline__ void panel_step(double (&x)[kPanel], PanelLds &sh, in
     if (r == p) {
 #pragma unroll
         for (int j = 0; j < kPanel; ++j) sh.pivrow[j] = x[j];
+        sh.porg = org;
     }
     if (r == c && p != c) {
 #pragma unroll
         for (int j = 0; j < kPanel; ++j) sh.oldc[j] = x[j];
+        sh.corg = org;
     }
     __syncthreads();
     if (r == p && p != c) {
 #pragma unroll
         for (int j = 0; j < kPanel; ++j) x[j] = sh.oldc[j];
+        org = sh.corg;
     }
+    if (r == c && p != c) org = sh.porg;
     double d = sh.pivrow[CC];
     if (d == 0.0) {
         singular = true;
@@ -217,14 +235,15 @@ __device__ __forceinline__ void panel_step(double (&x)[kPanel], PanelLds &sh, in
 }
 
 template <int... CC>
-__device__ __forceinline__ void panel_steps(std::integer_sequence<int, CC...>, double (&x)[kPanel], PanelLds &sh,
-                                            int r, int nb, int c0, int bw, int nw, int *__restrict__ perm,
-                                            bool &singular) {
-    (panel_step<CC>(x, sh, r, nb, c0, bw, nw, perm, singular), ...);
+__device__ __forceinline__ void panel_steps(std::integer_sequence<int, CC...>, double (&x)[kPanel], int &org,
+                                            PanelLds &sh, int r, int nb, int c0, int bw, int nw,
+                                            int *__restrict__ perm, bool &singular) {
+    (panel_step<CC>(x, org, sh, r, nb, c0, bw, nw, perm, singular), ...);
 }
 
 __global__ void __launch_bounds__(512) k_gj_panel_reg(int nb, int c0, int bw, double *__restrict__ A,
-                                                      int *__restrict__ perm, int *__restrict__ status) {
+                                                      int *__restrict__ perm, int *__restrict__ touch,
+                                                      int *__restrict__ status) {
     __shared__ PanelLds sh;
     const int r = threadIdx.x;
     const int nw = blockDim.x >> 6;
@@ -233,11 +252,33 @@ __global__ void __launch_bounds__(512) k_gj_panel_reg(int nb, int c0, int bw, do
 #pragma unroll
     for (int j = 0; j < kPanel; ++j) x[j] = (r < nb && j < bw) ? Ak[(size_t)(c0 + j) * nb + r] : 0.0;
     bool singular = false;
-    panel_steps(std::make_integer_sequence<int, kPanel>{}, x, sh, r, nb, c0, bw, nw, perm, singular);
+    int org = r;
+    panel_steps(std::make_integer_sequence<int, kPanel>{}, x, org, sh, r, nb, c0, bw, nw, perm, singular);
     if (r < nb) {
 #pragma unroll
         for (int j = 0; j < kPanel; ++j)
             if (j < bw) Ak[(size_t)(c0 + j) * nb + r] = x[j];
+    }
+    // touched-row list: slot r - c0 for the panel rows, then the moved rows in
+    // row order (a wavefront ballot ranks them within the wavefront)
+    const bool inS = r >= c0 && r < c0 + bw;
+    const bool moved = r < nb && !inS && org != r;
+    const unsigned long long m = __ballot(moved);
+    const int lane = r & 63, w = r >> 6;
+    if (lane == 0) sh.cnt[w] = __popcll(m);
+    __syncthreads();
+    int off = bw;
+    for (int w2 = 0; w2 < w; ++w2) off += sh.cnt[w2];
+    int *tl = touch + (size_t)blockIdx.x * kTouchStride;
+    const int slot = inS ? r - c0 : (moved ? off + __popcll(m & ((1ull << lane) - 1ull)) : -1);
+    if (slot >= 0) {
+        tl[1 + slot] = r;
+        tl[1 + kTouch + slot] = org;
+    }
+    if (r == 0) {
+        int n = bw;
+        for (int w2 = 0; w2 < nw; ++w2) n += sh.cnt[w2];
+        tl[0] = n;
     }
     if (singular && r == 0) status[0] = 1;
 }
@@ -246,110 +287,98 @@ constexpr int kUpdCols = 64;  // columns per update workgroup
 constexpr int kUpdRows = 64;  // rows per LDS chunk of T_panel
 constexpr int kMaxNb = 512;   // largest block the update kernels take
 
-// The row interchanges of one panel, applied by gathering instead of swapping
-// in place.  LDS state of one workgroup: src[r] = the row whose value ends at
-// row r after the panel's interchanges (identity outside the touched rows),
-// upos[r] = index of row r in the list of touched rows U (-1 if untouched),
-// and stage[u][jj] = the old value at touched row U[u] of tile column jj.
-struct PanelPerm {
-    int src[kMaxNb];
-    int upos[kMaxNb];
-    int rows[2 * kPanel];
+// The panel's touched-row list of one block in LDS: (P x)[rows[u]] =
+// x[src[u]], upos[r] = slot of row r (-1: untouched, (P x)[r] = x[r]).
+struct TouchLds {
+    int rows[kTouch];
+    int src[kTouch];
+    short upos[kMaxNb];
     int nu;
 };
 
-// Fill a PanelPerm for block k (all lanes take part; ends with a barrier).
-__device__ __forceinline__ void panel_perm(PanelPerm &pp, int nb, int c0, int bw, const int *__restrict__ perm,
-                                           int k) {
-    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
-        pp.src[r] = r;
-        pp.upos[r] = -1;
+// Workgroup -> (block, column tile).  Workgroups are dispatched round-robin
+// over the 8 XCDs; block k goes to XCD k mod 8 and its column tiles run back
+// to back there, so the panel columns they all read stay in that XCD's L2.
+__device__ __forceinline__ bool update_tile(int Ne, int ntile, int &k, int &tile) {
+    const int g = blockIdx.x, xcd = g & 7, i = g >> 3;
+    k = (i / ntile) * 8 + xcd;
+    tile = i - (i / ntile) * ntile;
+    return k < Ne;
+}
+
+// Load block k's touched-row list; every lane takes part, ends with a barrier.
+__device__ __forceinline__ void load_touch(TouchLds &t, const int *__restrict__ tl, int nb) {
+    const int tid = threadIdx.x;
+    for (int r = tid; r < nb; r += blockDim.x) t.upos[r] = -1;
+    const int nu = min(tl[0], kTouch);
+    if (tid < nu) {
+        t.rows[tid] = tl[1 + tid];
+        t.src[tid] = tl[1 + kTouch + tid];
     }
+    if (tid == 0) t.nu = nu;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int nu = 0;
-        for (int cc = 0; cc < bw; ++cc) {
-            const int c = c0 + cc, p = perm[(size_t)k * nb + c];
-            const int t = pp.src[c];
-            pp.src[c] = pp.src[p];
-            pp.src[p] = t;
-            if (pp.upos[c] < 0) {
-                pp.upos[c] = nu;
-                pp.rows[nu++] = c;
-            }
-            if (pp.upos[p] < 0) {
-                pp.upos[p] = nu;
-                pp.rows[nu++] = p;
-            }
-        }
-        pp.nu = nu;
-    }
+    if (tid < nu) t.upos[t.rows[tid]] = (short)tid;
     __syncthreads();
 }
 
-// stage[u][jj] = old value of touched row U[u] in tile column jj (0 beyond
-// the block's columns); every lane takes part, ends with a barrier.
-__device__ __forceinline__ void stage_touched(const PanelPerm &pp, double (*stage)[kUpdCols], const double *Ak,
+// stg[jj][u] = (P x_j)[rows[u]] = x_j[src[u]] for the tile's columns (0 beyond
+// the block); one column per wavefront per pass.  Read before any write of
+// the tile, so the in-place update cannot overwrite a value still needed.
+__device__ __forceinline__ void stage_touched(const TouchLds &t, double (*stg)[kTouch + 1], const double *Ak,
                                               int nb, int c0, int bw, int tile) {
     const int nrest = nb - bw;
-    for (int t = threadIdx.x; t < pp.nu * kUpdCols; t += blockDim.x) {
-        const int u = t / kUpdCols, jj = t % kUpdCols;
+    for (int i = threadIdx.x; i < kTouch * kUpdCols; i += blockDim.x) {
+        const int u = i % kTouch, jj = i / kTouch;
         const int ri = tile * kUpdCols + jj;
         double v = 0.0;
-        if (ri < nrest) {
+        if (u < t.nu && ri < nrest) {
             const int j = (ri < c0) ? ri : ri + bw;
-            v = Ak[(size_t)j * nb + pp.rows[u]];
+            v = Ak[(size_t)j * nb + t.src[u]];
         }
-        stage[u][jj] = v;
+        stg[jj][u] = v;
     }
-    __syncthreads();
 }
 
-// (P x)[r] of tile column jj: from the stage for touched rows, else from x
-__device__ __forceinline__ double permuted(const PanelPerm &pp, const double (*stage)[kUpdCols], const double *x,
-                                           int r, int jj) {
-    return pp.upos[r] >= 0 ? stage[pp.upos[pp.src[r]]][jj] : x[r];
-}
-
-// Apply the panel transform to the kUpdCols columns (outside the panel) of
-// one block: 256 lanes, each owns a 4 x 4 register tile of the output chunk.
-__global__ void __launch_bounds__(256) k_gj_update(int nb, int c0, int bw, double *__restrict__ A,
-                                                   const int *__restrict__ perm) {
-    __shared__ double xs[kPanel][kUpdCols];    // (P x)_S for the tile's columns
-    __shared__ double tp[kPanel][kUpdRows];    // T_panel rows chunk
+// Apply the panel transform to kUpdCols columns (outside the panel) of one
+// block: out = (P x with the rows S zeroed) + T_panel (P x)_S.  256 lanes,
+// each owns rows rl + 16a and columns cl + 16b (a, b < 4) of every 64-row
+// chunk, so each store instruction writes four 128-byte column segments.
+// The lane's untouched x values are loaded before the chunk's arithmetic and
+// written after it; touched rows come from the stage.
+__global__ void __launch_bounds__(256) k_gj_update(int Ne, int nb, int c0, int bw, double *__restrict__ A,
+                                                   const int *__restrict__ touch) {
+    __shared__ double stg[kUpdCols][kTouch + 1];  // (P x) on the touched rows; (P x)_S = slots 0..bw-1
+    __shared__ double tp[kPanel][kUpdRows];       // T_panel rows chunk
+    __shared__ TouchLds tl;
+    const int nrest = nb - bw, ntile = (nrest + kUpdCols - 1) / kUpdCols;
+    int k, tile;
+    if (!update_tile(Ne, ntile, k, tile)) return;
     const int tid = threadIdx.x;
-    const int k = blockIdx.x;
     double *Ak = A + (size_t)k * nb * nb;
-    const int nrest = nb - bw;
-    const int ri = blockIdx.y * kUpdCols + (tid % kUpdCols);  // rest-column index of this lane (phase 1)
-    // phase 1: row interchanges on the tile's columns in place (32 KB of LDS
-    // keeps five workgroups per CU, which beats the gather of the MFMA variant
-    // here), then gather (P x)_S
-    if (tid < kUpdCols) {
-        if (ri < nrest) {
-            const int j = (ri < c0) ? ri : ri + bw;
-            double *x = Ak + (size_t)j * nb;
-            for (int cc = 0; cc < bw; ++cc) {
-                const int c = c0 + cc, p = perm[(size_t)k * nb + c];
-                if (p != c) {
-                    const double t0 = x[c];
-                    x[c] = x[p];
-                    x[p] = t0;
-                }
-            }
-            for (int cc = 0; cc < bw; ++cc) xs[cc][tid] = x[c0 + cc];
-        } else {
-            for (int cc = 0; cc < bw; ++cc) xs[cc][tid] = 0.0;
-        }
+    load_touch(tl, touch + (size_t)k * kTouchStride, nb);
+    stage_touched(tl, stg, Ak, nb, c0, bw, tile);
+    const int rl = tid & 15, cl = tid >> 4;
+    int jcol[4];
+    bool cok[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int ri = tile * kUpdCols + cl + 16 * b;
+        cok[b] = ri < nrest;
+        jcol[b] = (ri < c0) ? ri : ri + bw;
     }
-    __syncthreads();
-    // phase 2: out[r][j] = (r in S ? 0 : x[r]) + sum_cc T[r][cc] xs[cc][j]
-    const int tr = (tid % 16) * 4;  // 4 rows
-    const int tc = (tid / 16) * 4;  // 4 columns
     for (int r0 = 0; r0 < nb; r0 += kUpdRows) {
-        for (int t = tid; t < bw * kUpdRows; t += 256) {
+        __syncthreads();  // the stage is complete; the previous chunk's tp reads are done
+        for (int t = tid; t < kPanel * kUpdRows; t += 256) {
             const int cc = t / kUpdRows, rr = t % kUpdRows;
-            tp[cc][rr] = (r0 + rr < nb) ? Ak[(size_t)(c0 + cc) * nb + r0 + rr] : 0.0;
+            tp[cc][rr] = (cc < bw && r0 + rr < nb) ? Ak[(size_t)(c0 + cc) * nb + r0 + rr] : 0.0;
+        }
+        double xo[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int r = r0 + rl + 16 * a;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                xo[a][b] = (r < nb && cok[b] && tl.upos[r] < 0) ? Ak[(size_t)jcol[b] * nb + r] : 0.0;
         }
         __syncthreads();
         double acc[4][4];
@@ -360,29 +389,27 @@ __global__ void __launch_bounds__(256) k_gj_update(int nb, int c0, int bw, doubl
         for (int cc = 0; cc < bw; ++cc) {
             double tv[4], xv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) tv[a] = tp[cc][tr + a];
+            for (int a = 0; a < 4; ++a) tv[a] = tp[cc][rl + 16 * a];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) xv[b] = xs[cc][tc + b];
+            for (int b = 0; b < 4; ++b) xv[b] = stg[cl + 16 * b][cc];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) acc[a][b] += tv[a] * xv[b];
         }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int rib = blockIdx.y * kUpdCols + tc + b;
-            if (rib >= nrest) continue;
-            const int j = (rib < c0) ? rib : rib + bw;
-            double *x = Ak + (size_t)j * nb;
+        for (int a = 0; a < 4; ++a) {
+            const int r = r0 + rl + 16 * a;
+            if (r >= nb) continue;
+            const bool inS = (r >= c0 && r < c0 + bw);
+            const int u = tl.upos[r];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int r = r0 + tr + a;
-                if (r >= nb) continue;
-                const bool inS = (r >= c0 && r < c0 + bw);
-                x[r] = (inS ? 0.0 : x[r]) + acc[a][b];
+            for (int b = 0; b < 4; ++b) {
+                if (!cok[b]) continue;
+                const double base = inS ? 0.0 : (u >= 0 ? stg[cl + 16 * b][u] : xo[a][b]);
+                Ak[(size_t)jcol[b] * nb + r] = base + acc[a][b];
             }
         }
-        __syncthreads();
     }
 }
 
@@ -391,36 +418,49 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // The same panel update on BF16-input MFMA with FP32 accumulation
 // (v_mfma_f32_16x16x32_bf16, K = the 32-column panel): each FP32 operand is
-// split into hi + lo BF16 parts and the product taken as hi*hi + hi*lo +
-// lo*hi (three MFMAs), ~16 mantissa bits.  Operands are staged k-contiguous
-// in LDS; wave w owns 16 output rows of the 64-row chunk and the four 16-column
-// blocks of the workgroup's 64 columns.
-__global__ void __launch_bounds__(256) k_gj_update_mfma(int nb, int c0, int bw, double *__restrict__ A,
-                                                        const int *__restrict__ perm) {
+// split into hi + lo BF16 parts and the product taken as hi*hi + lo*hi +
+// hi*lo (three MFMAs), ~16 mantissa bits.  The product is formed transposed,
+// (P x)_S^T T_panel^T, so that each lane's four results lie in one row of
+// four columns and each store instruction writes four 128-byte column
+// segments.  Operands are staged k-contiguous in LDS; wave w owns 16 rows of
+// the 64-row chunk and all 64 columns of the workgroup.
+__global__ void __launch_bounds__(256) k_gj_update_mfma(int Ne, int nb, int c0, int bw, double *__restrict__ A,
+                                                        const int *__restrict__ touch) {
     __shared__ __attribute__((aligned(16))) __bf16 xs_h[kUpdCols][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 xs_l[kUpdCols][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 tp_h[kUpdRows][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 tp_l[kUpdRows][kPanel];
-    __shared__ double stage[2 * kPanel][kUpdCols];
-    __shared__ PanelPerm pp;
+    __shared__ double stg[kUpdCols][kTouch + 1];
+    __shared__ TouchLds tl;
+    const int nrest = nb - bw, ntile = (nrest + kUpdCols - 1) / kUpdCols;
+    int k, tile;
+    if (!update_tile(Ne, ntile, k, tile)) return;
     const int tid = threadIdx.x;
-    const int k = blockIdx.x;
     double *Ak = A + (size_t)k * nb * nb;
-    const int nrest = nb - bw;
-    // phase 1: the panel's row interchanges as a gather, (P x)_S split in hi/lo
-    panel_perm(pp, nb, c0, bw, perm, k);
-    stage_touched(pp, stage, Ak, nb, c0, bw, blockIdx.y);
+    load_touch(tl, touch + (size_t)k * kTouchStride, nb);
+    stage_touched(tl, stg, Ak, nb, c0, bw, tile);
+    __syncthreads();
     for (int t = tid; t < kPanel * kUpdCols; t += 256) {
         const int cc = t % kPanel, jj = t / kPanel;
-        const float v = (cc < bw) ? (float)stage[pp.upos[pp.src[c0 + cc]]][jj] : 0.f;
+        const float v = (cc < bw) ? (float)stg[jj][cc] : 0.f;
         const __bf16 h = (__bf16)v;
         xs_h[jj][cc] = h;
         xs_l[jj][cc] = (__bf16)(v - (float)h);
     }
-    __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
+    int jcol[4][4];
+    bool cok[4][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ri = tile * kUpdCols + cb * 16 + 4 * g + v;
+            cok[cb][v] = ri < nrest;
+            jcol[cb][v] = (ri < c0) ? ri : ri + bw;
+        }
     for (int r0 = 0; r0 < nb; r0 += kUpdRows) {
+        __syncthreads();  // xs is complete; the previous chunk's tp reads are done
         for (int t = tid; t < kPanel * kUpdRows; t += 256) {
             const int cc = t / kUpdRows, rr = t % kUpdRows;
             const float v = (cc < bw && r0 + rr < nb) ? (float)Ak[(size_t)(c0 + cc) * nb + r0 + rr] : 0.f;
@@ -428,50 +468,66 @@ __global__ void __launch_bounds__(256) k_gj_update_mfma(int nb, int c0, int bw, 
             tp_h[rr][cc] = h;
             tp_l[rr][cc] = (__bf16)(v - (float)h);
         }
+        const int r = r0 + wave * 16 + r16;
+        const bool rok = r < nb;
+        const int u = rok ? tl.upos[r] : -1;
+        double xo[4][4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                xo[cb][v] = (rok && cok[cb][v] && u < 0) ? Ak[(size_t)jcol[cb][v] * nb + r] : 0.0;
         __syncthreads();
-        const int arow = wave * 16 + r16;
-        const bf16x8_t ah = *reinterpret_cast<const bf16x8_t *>(&tp_h[arow][8 * g]);
-        const bf16x8_t al = *reinterpret_cast<const bf16x8_t *>(&tp_l[arow][8 * g]);
+        const bf16x8_t th = *reinterpret_cast<const bf16x8_t *>(&tp_h[wave * 16 + r16][8 * g]);
+        const bf16x8_t tlo = *reinterpret_cast<const bf16x8_t *>(&tp_l[wave * 16 + r16][8 * g]);
+        const bool inS = (r >= c0 && r < c0 + bw);
 #pragma unroll
-        for (int cb = 0; cb < kUpdCols / 16; ++cb) {
-            const int bcol = cb * 16 + r16;
-            const bf16x8_t bh = *reinterpret_cast<const bf16x8_t *>(&xs_h[bcol][8 * g]);
-            const bf16x8_t bl = *reinterpret_cast<const bf16x8_t *>(&xs_l[bcol][8 * g]);
+        for (int cb = 0; cb < 4; ++cb) {
+            const bf16x8_t xh = *reinterpret_cast<const bf16x8_t *>(&xs_h[cb * 16 + r16][8 * g]);
+            const bf16x8_t xl = *reinterpret_cast<const bf16x8_t *>(&xs_l[cb * 16 + r16][8 * g]);
             f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-            const int rib = blockIdx.y * kUpdCols + bcol;
-            if (rib < nrest) {
-                const int j = (rib < c0) ? rib : rib + bw;
-                double *x = Ak + (size_t)j * nb;
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, th, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, th, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, tlo, acc, 0, 0, 0);
+            if (!rok) continue;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = r0 + wave * 16 + 4 * g + i;
-                    if (r >= nb) continue;
-                    const bool inS = (r >= c0 && r < c0 + bw);
-                    x[r] = (inS ? 0.0 : permuted(pp, stage, x, r, bcol)) + (double)acc[i];
-                }
+            for (int v = 0; v < 4; ++v) {
+                if (!cok[cb][v]) continue;
+                const int jj = cb * 16 + 4 * g + v;
+                const double base = inS ? 0.0 : (u >= 0 ? stg[jj][u] : xo[cb][v]);
+                Ak[(size_t)jcol[cb][v] * nb + r] = base + (double)acc[v];
             }
         }
-        __syncthreads();
     }
 }
 
-// Undo the row interchanges as column interchanges, last first.
-__global__ void __launch_bounds__(256) k_gj_unscramble(int nb, double *__restrict__ A, const int *__restrict__ perm) {
-    double *Ak = A + (size_t)blockIdx.x * nb * nb;
-    for (int c = nb - 1; c >= 0; --c) {
-        const int p = perm[(size_t)blockIdx.x * nb + c];
-        if (p != c) {
-            for (int r = threadIdx.x; r < nb; r += blockDim.x) {
-                const double t0 = Ak[(size_t)c * nb + r];
-                Ak[(size_t)c * nb + r] = Ak[(size_t)p * nb + r];
-                Ak[(size_t)p * nb + r] = t0;
+// The row interchanges of the elimination turn into column interchanges of
+// the result (undone last first).  Instead of moving columns, record where
+// each stored column belongs: the inverse is X[:, sigma(j)] = A[:, j], so
+// X r = sum_j A[:, j] r[sigma(j)] and the apply reads r through sigma.  One
+// lane composes the interchanges in LDS; the others fill and write out.
+__global__ void __launch_bounds__(64) k_gj_colperm(int nb, const int *__restrict__ perm, int *__restrict__ sigma) {
+    __shared__ int pi[kMaxNb];  // pi[c] = stored column that becomes column c of X
+    __shared__ int pv[kMaxNb];
+    const int tid = threadIdx.x;
+    const size_t base = (size_t)blockIdx.x * nb;
+    for (int c = tid; c < nb; c += blockDim.x) {
+        pi[c] = c;
+        pv[c] = perm[base + c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int c = nb - 1; c >= 0; --c) {
+            const int p = pv[c];
+            if (p != c) {
+                const int t = pi[c];
+                pi[c] = pi[p];
+                pi[p] = t;
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
+    for (int c = tid; c < nb; c += blockDim.x) sigma[base + pi[c]] = c;
 }
 
 __global__ void k_to_float(size_t n, const double *__restrict__ a, float *__restrict__ b) {
@@ -486,26 +542,33 @@ __global__ void k_to_bf16(size_t n, const double *__restrict__ a, __bf16 *__rest
 
 }  // namespace
 
+bool ej_blocked(int nb, int precision) {
+    return nb > kMaxLdsBlock || precision == FR_PREC_FP32_BF16 || precision == FR_PREC_BF16_STORE;
+}
+
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
     Level &L = ctx->lv[level];
     const int nb = L.nb, Ne = ctx->mesh.Ne;
-    if (nb > kMaxLdsBlock || precision == FR_PREC_FP32_BF16 || precision == FR_PREC_BF16_STORE) {
-        if (nb > 512 || !L.perm) return hipErrorInvalidValue;
-        const bool mfma = precision != FR_PREC_FP64;
+    if (ej_blocked(nb, precision)) {
+        if (nb > kMaxNb || !L.perm || !L.touch || !L.colperm) return hipErrorInvalidValue;
+        const bool mfma = precision == FR_PREC_FP32_BF16 || precision == FR_PREC_BF16_STORE;
         const int rows = ((nb + 63) / 64) * 64;  // one lane per block row
         for (int c0 = 0; c0 < nb; c0 += kPanel) {
             const int bw = min(kPanel, nb - c0);
-            hipLaunchKernelGGL(k_gj_panel_reg, dim3(Ne), dim3(rows), 0, s, nb, c0, bw, L.blk64, L.perm, L.dstatus);
+            hipLaunchKernelGGL(k_gj_panel_reg, dim3(Ne), dim3(rows), 0, s, nb, c0, bw, L.blk64, L.perm, L.touch,
+                               L.dstatus);
             const int nrest = nb - bw;
             if (nrest > 0) {
-                const dim3 gu(Ne, (nrest + kUpdCols - 1) / kUpdCols);
+                const int ntile = (nrest + kUpdCols - 1) / kUpdCols;
+                const dim3 gu((unsigned)(((Ne + 7) / 8) * 8 * ntile));
                 if (mfma)
-                    hipLaunchKernelGGL(k_gj_update_mfma, gu, dim3(256), 0, s, nb, c0, bw, L.blk64, L.perm);
+                    hipLaunchKernelGGL(k_gj_update_mfma, gu, dim3(256), 0, s, Ne, nb, c0, bw, L.blk64, L.touch);
                 else
-                    hipLaunchKernelGGL(k_gj_update, gu, dim3(256), 0, s, nb, c0, bw, L.blk64, L.perm);
+                    hipLaunchKernelGGL(k_gj_update, gu, dim3(256), 0, s, Ne, nb, c0, bw, L.blk64, L.touch);
             }
         }
-        hipLaunchKernelGGL(k_gj_unscramble, dim3(Ne), dim3(256), 0, s, nb, L.blk64, L.perm);
+        hipLaunchKernelGGL(k_gj_colperm, dim3(Ne), dim3(64), 0, s, nb, L.perm, L.colperm);
+        L.inv_cols = L.colperm;
         const size_t n = (size_t)Ne * nb * nb;
         if (precision == FR_PREC_FP64) {
             L.inv = L.blk64;
@@ -536,6 +599,7 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
                            L.dstatus);
         L.inv = L.inv32;
     }
+    L.inv_cols = nullptr;
     L.inv_prec = precision;
     return hipGetLastError();
 }

@@ -62,8 +62,11 @@ struct VecLoad<__bf16, 4> {
 // Each lane owns R consecutive rows of one block and streams the block
 // column by column with one wide load per column (R = 2 for FP64, 4 for FP32
 // and BF16 storage), so a wavefront reads whole contiguous column segments.
+// With a column placement (blocked inversion), stored column j multiplies
+// r[cols[j]]; the gather happens while r is staged in LDS.
 template <typename T, int R>
 __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int epb, const T *__restrict__ inv,
+                                                            const int *__restrict__ cols,
                                                             const double *__restrict__ r, double alpha,
                                                             double beta, double *__restrict__ y) {
     extern __shared__ double s_r[];  // [epb][nb]
@@ -71,7 +74,12 @@ __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int 
     const int ne = min(epb, Ne - k0);
     for (int t = threadIdx.x; t < epb * nb; t += blockDim.x) {
         const int e = t / nb, j = t - e * nb;
-        s_r[t] = (e < ne) ? r[(size_t)j * Ne + k0 + e] : 0.0;
+        double v = 0.0;
+        if (e < ne) {
+            const int jr = cols ? cols[(size_t)(k0 + e) * nb + j] : j;
+            v = r[(size_t)jr * Ne + k0 + e];
+        }
+        s_r[t] = v;
     }
     __syncthreads();
     const int tpe = nb / R;  // lanes per block
@@ -118,8 +126,8 @@ hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, d
     const size_t lds = (size_t)epb * nb * sizeof(double);
     dim3 grid((Ne + epb - 1) / epb);
     dim3 block(tpe >= kApplyThreads ? tpe : kApplyThreads);
-    hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, (const T *)L.inv, r, alpha, beta,
-                       y);
+    hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, (const T *)L.inv, L.inv_cols, r, alpha,
+                       beta, y);
     return hipGetLastError();
 }
 

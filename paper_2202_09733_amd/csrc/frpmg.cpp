@@ -152,10 +152,14 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
     REQUIRE(L.nb <= 512, "EJ block too large (n_b > 512)");
     const size_t nblk = (size_t)ctx->mesh.Ne * L.nb * L.nb;
     if (!L.blk64) L.blk64 = dalloc(ctx, nblk);
-    if ((L.nb > 140 || precision != FR_PREC_FP64) && !L.perm) {
+    if (ej_blocked(L.nb, precision) && !L.perm) {
         void *p = nullptr;
         HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * L.nb * sizeof(int)));
         L.perm = (int *)p;
+        HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * kTouchStride * sizeof(int)));
+        L.touch = (int *)p;
+        HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * L.nb * sizeof(int)));
+        L.colperm = (int *)p;
     }
     if ((precision == FR_PREC_FP32 || precision == FR_PREC_FP32_BF16) && !L.inv32) {
         void *p = nullptr;
@@ -940,6 +944,8 @@ void destroy_all(frpmg_ctx *ctx) {
         dfree(L.inv16);
         dfree(L.dstatus);
         dfree(L.perm);
+        dfree(L.touch);
+        dfree(L.colperm);
         dfree(L.r0);
     }
     for (int a = 0; a < 3; ++a) dfree(ctx->inv2h[a]);
@@ -1133,6 +1139,20 @@ fr_status ej_get_inverse(frpmg_ctx *ctx, int level, double *host_out) {
             std::vector<float> tmp(n);
             HIPCHK(hipMemcpy(tmp.data(), L.inv, n * sizeof(float), hipMemcpyDeviceToHost));
             for (size_t i = 0; i < n; ++i) host_out[i] = tmp[i];
+        }
+        if (L.inv_cols) {
+            // stored column j is column inv_cols[j] of the inverse
+            const int nb = L.nb;
+            std::vector<int> cols((size_t)ctx->mesh.Ne * nb);
+            HIPCHK(hipMemcpy(cols.data(), L.inv_cols, cols.size() * sizeof(int), hipMemcpyDeviceToHost));
+            std::vector<double> blk((size_t)nb * nb);
+            for (int k = 0; k < ctx->mesh.Ne; ++k) {
+                double *Bk = host_out + (size_t)k * nb * nb;
+                std::memcpy(blk.data(), Bk, blk.size() * sizeof(double));
+                for (int j = 0; j < nb; ++j)
+                    std::memcpy(Bk + (size_t)cols[(size_t)k * nb + j] * nb, blk.data() + (size_t)j * nb,
+                                nb * sizeof(double));
+            }
         }
     });
 }

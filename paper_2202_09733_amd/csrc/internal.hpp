@@ -95,8 +95,15 @@ struct Level {
     int inv_prec = -1;
     int *dstatus = nullptr;   // device flag: 1 = zero pivot seen
     int *perm = nullptr;      // pivot rows of the blocked inversion [Ne][nb]
+    int *touch = nullptr;     // the current panel's touched-row list [Ne][kTouchStride]
+    int *colperm = nullptr;   // column placement of the blocked inversion [Ne][nb]
+    const int *inv_cols = nullptr;  // nullptr: inv holds B^-1; else B^-1[:, inv_cols[j]] = inv[:, j]
     double *r0 = nullptr;     // scratch: R at the EJ linearisation point
 };
+
+// Blocked Gauss-Jordan: ints per block of one panel's touched-row list (the
+// count, then up to 64 rows and the rows their values come from).
+constexpr int kTouchStride = 129;
 
 // Reduction scratch: partial sums per block and per vector.
 constexpr int kRedBlocks = 2048;     // capacity of the partial-sum buffer per vector
@@ -192,6 +199,8 @@ hipError_t vec_dot_pmg_scale(frpmg_ctx *ctx, size_t n, const double *x, const do
                              double sigma, double *n2out, double *s_out, double *inv_out, hipStream_t s);
 
 // ej.hip
+// true when the blocks of this size and precision take the blocked inversion
+bool ej_blocked(int nb, int precision);
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s);
 // y = beta y + alpha B^{-1} r
 hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta, double *y,
