@@ -339,16 +339,100 @@ __device__ __forceinline__ void stage_touched(const TouchLds &t, double (*stg)[k
     }
 }
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Lane geometry shared by the two update kernels.  Both form the product
+// transposed, out^T = (P x)_S^T T_panel^T, on 16 x 16 MFMA tiles: wave w owns
+// rows wave*16 + r16 of each 64-row chunk, and lane (r16, g) holds the
+// results of that row in 16 columns of the tile: cb*16 + 4g + v for the
+// FP32-output MFMA, cb*16 + g + 4v for the FP64 one (cb, v < 4).  Each store
+// instruction therefore writes four 128-byte column segments.
+template <bool F64>
+struct UpdLane {
+    int r16, g, wave;
+    int ri0, nrest, c0, bw;
+    __device__ UpdLane(int tid, int tile, int nrest_, int c0_, int bw_) {
+        const int lane = tid & 63;
+        wave = tid >> 6;
+        r16 = lane & 15;
+        g = lane >> 4;
+        ri0 = tile * kUpdCols;
+        nrest = nrest_;
+        c0 = c0_;
+        bw = bw_;
+    }
+    // tile column of result (cb, v)
+    __device__ __forceinline__ int jj(int cb, int v) const { return cb * 16 + (F64 ? g + 4 * v : 4 * g + v); }
+    // its block column; false beyond the block
+    __device__ __forceinline__ bool col(int cb, int v, int &j) const {
+        const int ri = ri0 + jj(cb, v);
+        j = (ri < c0) ? ri : ri + bw;
+        return ri < nrest;
+    }
+};
+
+// The global reads of one 64-row chunk, issued ahead of their use: the
+// chunk of the panel columns T (eight values per lane, rows fastest; issued
+// before the previous chunk's product) and the lane's untouched x values
+// (touched rows come from the stage; issued right after the previous
+// chunk's stores).  Offsets within a block fit in 32 bits (n_b <= 512).
+struct ChunkLoads {
+    double tpv[8];
+    double xo[4][4];
+    template <bool F64>
+    __device__ void issue_t(const double *Ak, const UpdLane<F64> &L, int nb, int r0) {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int t = tid + 256 * i, cc = t >> 6, rr = t & 63;
+            tpv[i] = (cc < L.bw && r0 + rr < nb) ? Ak[(unsigned)((L.c0 + cc) * nb + r0 + rr)] : 0.0;
+        }
+    }
+    template <bool F64>
+    __device__ void issue_x(const double *Ak, const TouchLds &tl, const UpdLane<F64> &L, int nb, int r0) {
+        const int r = r0 + L.wave * 16 + L.r16;
+        const bool load = r < nb && tl.upos[r < nb ? r : 0] < 0;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int j;
+                const bool ok = L.col(cb, v, j);
+                xo[cb][v] = (load && ok) ? Ak[(unsigned)(j * nb + r)] : 0.0;
+            }
+    }
+};
+
+// Write the lane's results of one chunk: out = (P x, zero on S) + product.
+template <bool F64, typename Acc>
+__device__ __forceinline__ void store_chunk(double *Ak, const TouchLds &tl, const UpdLane<F64> &L,
+                                            const double (*stg)[kTouch + 1], const double (&xo)[4][4],
+                                            const Acc &acc, int nb, int r0) {
+    const int r = r0 + L.wave * 16 + L.r16;
+    if (r >= nb) return;
+    const bool inS = (r >= L.c0 && r < L.c0 + L.bw);
+    const int u = tl.upos[r];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int j;
+            if (!L.col(cb, v, j)) continue;
+            const double base = inS ? 0.0 : (u >= 0 ? stg[L.jj(cb, v)][u] : xo[cb][v]);
+            Ak[(unsigned)(j * nb + r)] = base + acc[cb][v];
+        }
+}
+
 // Apply the panel transform to kUpdCols columns (outside the panel) of one
-// block: out = (P x with the rows S zeroed) + T_panel (P x)_S.  256 lanes,
-// each owns rows rl + 16a and columns cl + 16b (a, b < 4) of every 64-row
-// chunk, so each store instruction writes four 128-byte column segments.
-// The lane's untouched x values are loaded before the chunk's arithmetic and
-// written after it; touched rows come from the stage.
-__global__ void __launch_bounds__(256) k_gj_update(int Ne, int nb, int c0, int bw, double *__restrict__ A,
-                                                   const int *__restrict__ touch) {
+// block in FP64 on v_mfma_f64_16x16x4f64 (A = stage^T: lane (r16, g) gives
+// column r16, panel column 4ks + g; B = T^T: panel column 4ks + g, row r16).
+// The next chunk's global reads are in flight while a chunk is multiplied.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_gj_update(int Ne, int nb, int c0, int bw, double *__restrict__ A, const int *__restrict__ touch) {
     __shared__ double stg[kUpdCols][kTouch + 1];  // (P x) on the touched rows; (P x)_S = slots 0..bw-1
-    __shared__ double tp[kPanel][kUpdRows];       // T_panel rows chunk
+    __shared__ double tp[kPanel][kUpdRows];       // T_panel chunk, [panel column][row]
     __shared__ TouchLds tl;
     const int nrest = nb - bw, ntile = (nrest + kUpdCols - 1) / kUpdCols;
     int k, tile;
@@ -357,75 +441,44 @@ __global__ void __launch_bounds__(256) k_gj_update(int Ne, int nb, int c0, int b
     double *Ak = A + (size_t)k * nb * nb;
     load_touch(tl, touch + (size_t)k * kTouchStride, nb);
     stage_touched(tl, stg, Ak, nb, c0, bw, tile);
-    const int rl = tid & 15, cl = tid >> 4;
-    int jcol[4];
-    bool cok[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int ri = tile * kUpdCols + cl + 16 * b;
-        cok[b] = ri < nrest;
-        jcol[b] = (ri < c0) ? ri : ri + bw;
-    }
+    const UpdLane<true> L(tid, tile, nrest, c0, bw);
+    ChunkLoads ld;
+    ld.issue_t(Ak, L, nb, 0);
+    ld.issue_x(Ak, tl, L, nb, 0);
     for (int r0 = 0; r0 < nb; r0 += kUpdRows) {
         __syncthreads();  // the stage is complete; the previous chunk's tp reads are done
-        for (int t = tid; t < kPanel * kUpdRows; t += 256) {
-            const int cc = t / kUpdRows, rr = t % kUpdRows;
-            tp[cc][rr] = (cc < bw && r0 + rr < nb) ? Ak[(size_t)(c0 + cc) * nb + r0 + rr] : 0.0;
-        }
-        double xo[4][4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int r = r0 + rl + 16 * a;
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                xo[a][b] = (r < nb && cok[b] && tl.upos[r] < 0) ? Ak[(size_t)jcol[b] * nb + r] : 0.0;
+        for (int i = 0; i < 8; ++i) {
+            const int t = tid + 256 * i;
+            tp[t >> 6][t & 63] = ld.tpv[i];
         }
         __syncthreads();
-        double acc[4][4];
+        const bool more = r0 + kUpdRows < nb;
+        if (more) ld.issue_t(Ak, L, nb, r0 + kUpdRows);
+        f64x4_t acc[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = f64x4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-        for (int cc = 0; cc < bw; ++cc) {
-            double tv[4], xv[4];
+        for (int ks = 0; ks < kPanel / 4; ++ks) {
+            const double bv = tp[4 * ks + L.g][L.wave * 16 + L.r16];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) tv[a] = tp[cc][rl + 16 * a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) xv[b] = stg[cl + 16 * b][cc];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] += tv[a] * xv[b];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int r = r0 + rl + 16 * a;
-            if (r >= nb) continue;
-            const bool inS = (r >= c0 && r < c0 + bw);
-            const int u = tl.upos[r];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (!cok[b]) continue;
-                const double base = inS ? 0.0 : (u >= 0 ? stg[cl + 16 * b][u] : xo[a][b]);
-                Ak[(size_t)jcol[b] * nb + r] = base + acc[a][b];
+            for (int cb = 0; cb < 4; ++cb) {
+                const double av = stg[cb * 16 + L.r16][4 * ks + L.g];
+                acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
             }
         }
+        store_chunk(Ak, tl, L, stg, ld.xo, acc, nb, r0);
+        if (more) ld.issue_x(Ak, tl, L, nb, r0 + kUpdRows);
     }
 }
-
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // The same panel update on BF16-input MFMA with FP32 accumulation
 // (v_mfma_f32_16x16x32_bf16, K = the 32-column panel): each FP32 operand is
 // split into hi + lo BF16 parts and the product taken as hi*hi + lo*hi +
-// hi*lo (three MFMAs), ~16 mantissa bits.  The product is formed transposed,
-// (P x)_S^T T_panel^T, so that each lane's four results lie in one row of
-// four columns and each store instruction writes four 128-byte column
-// segments.  Operands are staged k-contiguous in LDS; wave w owns 16 rows of
-// the 64-row chunk and all 64 columns of the workgroup.
-__global__ void __launch_bounds__(256) k_gj_update_mfma(int Ne, int nb, int c0, int bw, double *__restrict__ A,
-                                                        const int *__restrict__ touch) {
+// hi*lo (three MFMAs), ~16 mantissa bits.  Operands are staged k-contiguous
+// in LDS.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_gj_update_mfma(int Ne, int nb, int c0, int bw, double *__restrict__ A, const int *__restrict__ touch) {
     __shared__ __attribute__((aligned(16))) __bf16 xs_h[kUpdCols][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 xs_l[kUpdCols][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 tp_h[kUpdRows][kPanel];
@@ -439,6 +492,10 @@ __global__ void __launch_bounds__(256) k_gj_update_mfma(int Ne, int nb, int c0, 
     double *Ak = A + (size_t)k * nb * nb;
     load_touch(tl, touch + (size_t)k * kTouchStride, nb);
     stage_touched(tl, stg, Ak, nb, c0, bw, tile);
+    const UpdLane<false> L(tid, tile, nrest, c0, bw);
+    ChunkLoads ld;
+    ld.issue_t(Ak, L, nb, 0);
+    ld.issue_x(Ak, tl, L, nb, 0);
     __syncthreads();
     for (int t = tid; t < kPanel * kUpdCols; t += 256) {
         const int cc = t % kPanel, jj = t / kPanel;
@@ -447,57 +504,33 @@ __global__ void __launch_bounds__(256) k_gj_update_mfma(int Ne, int nb, int c0, 
         xs_h[jj][cc] = h;
         xs_l[jj][cc] = (__bf16)(v - (float)h);
     }
-    const int lane = tid & 63, wave = tid >> 6;
-    const int r16 = lane & 15, g = lane >> 4;
-    int jcol[4][4];
-    bool cok[4][4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int ri = tile * kUpdCols + cb * 16 + 4 * g + v;
-            cok[cb][v] = ri < nrest;
-            jcol[cb][v] = (ri < c0) ? ri : ri + bw;
-        }
     for (int r0 = 0; r0 < nb; r0 += kUpdRows) {
         __syncthreads();  // xs is complete; the previous chunk's tp reads are done
-        for (int t = tid; t < kPanel * kUpdRows; t += 256) {
-            const int cc = t / kUpdRows, rr = t % kUpdRows;
-            const float v = (cc < bw && r0 + rr < nb) ? (float)Ak[(size_t)(c0 + cc) * nb + r0 + rr] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int t = tid + 256 * i, cc = t >> 6, rr = t & 63;
+            const float v = (float)ld.tpv[i];
             const __bf16 h = (__bf16)v;
             tp_h[rr][cc] = h;
             tp_l[rr][cc] = (__bf16)(v - (float)h);
         }
-        const int r = r0 + wave * 16 + r16;
-        const bool rok = r < nb;
-        const int u = rok ? tl.upos[r] : -1;
-        double xo[4][4];
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                xo[cb][v] = (rok && cok[cb][v] && u < 0) ? Ak[(size_t)jcol[cb][v] * nb + r] : 0.0;
         __syncthreads();
-        const bf16x8_t th = *reinterpret_cast<const bf16x8_t *>(&tp_h[wave * 16 + r16][8 * g]);
-        const bf16x8_t tlo = *reinterpret_cast<const bf16x8_t *>(&tp_l[wave * 16 + r16][8 * g]);
-        const bool inS = (r >= c0 && r < c0 + bw);
+        const bool more = r0 + kUpdRows < nb;
+        if (more) ld.issue_t(Ak, L, nb, r0 + kUpdRows);
+        const bf16x8_t th = *reinterpret_cast<const bf16x8_t *>(&tp_h[L.wave * 16 + L.r16][8 * L.g]);
+        const bf16x8_t tlo = *reinterpret_cast<const bf16x8_t *>(&tp_l[L.wave * 16 + L.r16][8 * L.g]);
+        f32x4_t acc[4];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
-            const bf16x8_t xh = *reinterpret_cast<const bf16x8_t *>(&xs_h[cb * 16 + r16][8 * g]);
-            const bf16x8_t xl = *reinterpret_cast<const bf16x8_t *>(&xs_l[cb * 16 + r16][8 * g]);
-            f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, th, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, th, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, tlo, acc, 0, 0, 0);
-            if (!rok) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                if (!cok[cb][v]) continue;
-                const int jj = cb * 16 + 4 * g + v;
-                const double base = inS ? 0.0 : (u >= 0 ? stg[jj][u] : xo[cb][v]);
-                Ak[(size_t)jcol[cb][v] * nb + r] = base + (double)acc[v];
-            }
+            const bf16x8_t xh = *reinterpret_cast<const bf16x8_t *>(&xs_h[cb * 16 + L.r16][8 * L.g]);
+            const bf16x8_t xl = *reinterpret_cast<const bf16x8_t *>(&xs_l[cb * 16 + L.r16][8 * L.g]);
+            acc[cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, th, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, th, acc[cb], 0, 0, 0);
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, tlo, acc[cb], 0, 0, 0);
         }
+        store_chunk(Ak, tl, L, stg, ld.xo, acc, nb, r0);
+        if (more) ld.issue_x(Ak, tl, L, nb, r0 + kUpdRows);
     }
 }
 
