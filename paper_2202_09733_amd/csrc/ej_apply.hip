@@ -62,14 +62,17 @@ struct VecLoad<__bf16, 4> {
 // Each lane owns R consecutive rows of one block and streams the block
 // column by column with one wide load per column (R = 2 for FP64, 4 for FP32
 // and BF16 storage), so a wavefront reads whole contiguous column segments.
-// With a column placement (blocked inversion), stored column j multiplies
-// r[cols[j]]; the gather happens while r is staged in LDS.
+// Where few long per-lane column loops would leave the chip poorly balanced,
+// the columns are split into S contiguous ranges on S lane groups, whose
+// partial sums meet in LDS and are added in range order.  With a column placement (blocked inversion), stored column j
+// multiplies r[cols[j]]; the gather happens while r is staged in LDS.
 template <typename T, int R>
-__global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int epb, const T *__restrict__ inv,
+__global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int epb, int S,
+                                                            const T *__restrict__ inv,
                                                             const int *__restrict__ cols,
                                                             const double *__restrict__ r, double alpha,
                                                             double beta, double *__restrict__ y) {
-    extern __shared__ double s_r[];  // [epb][nb]
+    extern __shared__ double s_r[];  // [epb][nb], then the partial sums [epb][S][nb] when S > 1
     const int k0 = blockIdx.x * epb;
     const int ne = min(epb, Ne - k0);
     for (int t = threadIdx.x; t < epb * nb; t += blockDim.x) {
@@ -82,38 +85,71 @@ __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int 
         s_r[t] = v;
     }
     __syncthreads();
-    const int tpe = nb / R;  // lanes per block
-    const int e = threadIdx.x / tpe;
-    const int row = (threadIdx.x - e * tpe) * R;
-    if (e >= ne) return;
-    const int k = k0 + e;
-    const T *col = inv + (size_t)k * nb * nb + row;
-    const double *rv = s_r + e * nb;
+    const int tpe = nb / R;  // row groups per block
+    const int lpe = tpe * S;
+    const int e = threadIdx.x / lpe;
+    const int rem = threadIdx.x - e * lpe;
+    const int sg = rem / tpe;
+    const int row = (rem - sg * tpe) * R;
+    const bool active = e < ne;
+    const int cs = (nb + S - 1) / S;
+    const int j0 = sg * cs, j1 = min(nb, j0 + cs);
     double acc[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = 0.0;
-    int j = 0;
-    for (; j + 4 <= nb; j += 4) {
-        double v0[R], v1[R], v2[R], v3[R];
-        VecLoad<T, R>::get(col + (size_t)j * nb, v0);
-        VecLoad<T, R>::get(col + (size_t)(j + 1) * nb, v1);
-        VecLoad<T, R>::get(col + (size_t)(j + 2) * nb, v2);
-        VecLoad<T, R>::get(col + (size_t)(j + 3) * nb, v3);
-        const double x0 = rv[j], x1 = rv[j + 1], x2 = rv[j + 2], x3 = rv[j + 3];
+    if (active) {
+        const int k = k0 + e;
+        const T *col = inv + (size_t)k * nb * nb + row;
+        const double *rv = s_r + e * nb;
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            double v0[R], v1[R], v2[R], v3[R];
+            VecLoad<T, R>::get(col + (size_t)j * nb, v0);
+            VecLoad<T, R>::get(col + (size_t)(j + 1) * nb, v1);
+            VecLoad<T, R>::get(col + (size_t)(j + 2) * nb, v2);
+            VecLoad<T, R>::get(col + (size_t)(j + 3) * nb, v3);
+            const double x0 = rv[j], x1 = rv[j + 1], x2 = rv[j + 2], x3 = rv[j + 3];
 #pragma unroll
-        for (int q = 0; q < R; ++q) acc[q] += (v0[q] * x0 + v1[q] * x1) + (v2[q] * x2 + v3[q] * x3);
-    }
-    for (; j < nb; ++j) {
-        double v0[R];
-        VecLoad<T, R>::get(col + (size_t)j * nb, v0);
+            for (int q = 0; q < R; ++q) acc[q] += (v0[q] * x0 + v1[q] * x1) + (v2[q] * x2 + v3[q] * x3);
+        }
+        for (; j < j1; ++j) {
+            double v0[R];
+            VecLoad<T, R>::get(col + (size_t)j * nb, v0);
 #pragma unroll
-        for (int q = 0; q < R; ++q) acc[q] += v0[q] * rv[j];
+            for (int q = 0; q < R; ++q) acc[q] += v0[q] * rv[j];
+        }
     }
+    if (S > 1) {
+        double *part = s_r + epb * nb;  // [epb][S][nb]
+        if (active) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) part[((size_t)e * S + sg) * nb + row + q] = acc[q];
+        }
+        __syncthreads();
+        if (!active || sg != 0) return;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            double t = part[((size_t)e * S) * nb + row + q];
+            for (int s2 = 1; s2 < S; ++s2) t += part[((size_t)e * S + s2) * nb + row + q];
+            acc[q] = t;
+        }
+    }
+    if (!active) return;
+    const int k = k0 + e;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const size_t idx = (size_t)(row + q) * Ne + k;
         y[idx] = (beta == 0.0) ? alpha * acc[q] : beta * y[idx] + alpha * acc[q];
     }
+}
+
+// Column ranges per block.  FP64 storage on fewer than 256k lanes (4
+// wavefronts per SIMD) takes two ranges: at 4096 blocks of 100^2 that turns
+// 820 workgroups of 100-column loops into 2048 of 50 (66.5 -> 62.5 us).
+// Measured not to pay for the 36^2 blocks or for FP32/BF16 storage.
+template <typename T>
+int apply_split(int nb, int tpe, int Ne) {
+    return (sizeof(T) == 8 && (size_t)Ne * tpe < (256u << 10) && nb >= 64 && 2 * tpe <= kApplyThreads) ? 2 : 1;
 }
 
 template <typename T, int R>
@@ -122,12 +158,14 @@ hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, d
     const int nb = L.nb;
     const int tpe = nb / R;
     if (tpe > kApplyThreads) return hipErrorInvalidValue;
-    const int epb = (tpe >= kApplyThreads) ? 1 : kApplyThreads / tpe;
-    const size_t lds = (size_t)epb * nb * sizeof(double);
+    const int S = apply_split<T>(nb, tpe, Ne);
+    const int lpe = tpe * S;
+    const int epb = (lpe >= kApplyThreads) ? 1 : kApplyThreads / lpe;
+    const size_t lds = (size_t)epb * nb * (S > 1 ? 1 + S : 1) * sizeof(double);
     dim3 grid((Ne + epb - 1) / epb);
-    dim3 block(tpe >= kApplyThreads ? tpe : kApplyThreads);
-    hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, (const T *)L.inv, L.inv_cols, r, alpha,
-                       beta, y);
+    dim3 block(lpe >= kApplyThreads ? lpe : kApplyThreads);
+    hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, S, (const T *)L.inv, L.inv_cols, r,
+                       alpha, beta, y);
     return hipGetLastError();
 }
 

@@ -218,10 +218,16 @@ unsigned red_blocks(size_t n) {
     return nb > cap ? cap : nb;
 }
 
-// Restriction / prolongation, sum-factorised: one lane per (variable,
-// element) applies the 1D operator M (PO x PI) along x, then y (then z), all
-// in registers.  Compile-time sizes let the operator entries come from the
-// kernel-argument segment with uniform indices.
+// Restriction / prolongation with the 1D operator M (PO x PI) along each
+// axis.  Sum-factorised: one lane per (variable, element) applies M along
+// x, then y, then z, all in registers.  2D prolongation: one lane per (output
+// point, element, variable) computes sum_j M[o1][j] sum_i M[o0][i] a[j][i]
+// (the same operations in the same order as the sum-factorised form); 4096
+// elements would otherwise give the chip only 64 workgroups, each lane
+// writing PO^2 values (12.6 -> 8.0 us for p = 2 -> 4).  2D restriction keeps
+// the sum-factorised form (it measured faster).  Compile-time sizes let
+// the operator entries come from the kernel-argument segment with uniform
+// indices.
 struct Mat1D {
     double m[kMaxP][kMaxP];
 };
@@ -288,12 +294,43 @@ __global__ void __launch_bounds__(kThreads) k_transfer_sf(int Ne, int nv, Mat1D 
     }
 }
 
+template <int PI, int PO>
+__global__ void __launch_bounds__(kThreads) k_transfer_pt(int Ne, int nv, Mat1D M, const double *__restrict__ x,
+                                                          const double *__restrict__ x0, int acc,
+                                                          double *__restrict__ y) {
+    constexpr int NI = PI * PI, NO = PO * PO;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nv * NO * Ne) return;
+    const int k = idx % Ne, vo = idx / Ne;
+    const int o = vo % NO, v = vo / NO;
+    const int o1 = o / PO, o0 = o - o1 * PO;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < PI; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < PI; ++i) {
+            const size_t ii = ((size_t)v * NI + j * PI + i) * Ne + k;
+            t += M.m[o0][i] * (x0 ? x[ii] - x0[ii] : x[ii]);
+        }
+        s += M.m[o1][j] * t;
+    }
+    const size_t io = (size_t)idx;
+    y[io] = acc ? y[io] + s : s;
+}
+
 template <int DIM, int PI, int PO>
 void launch_sf(int Ne, int nv, const Mat1D &M, const double *x, const double *x0, int acc, double *y,
                hipStream_t s) {
-    const int n = nv * Ne;
-    hipLaunchKernelGGL((k_transfer_sf<DIM, PI, PO>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, Ne,
-                       nv, M, x, x0, acc, y);
+    if constexpr (DIM == 2 && PO > PI) {
+        const int n = nv * PO * PO * Ne;
+        hipLaunchKernelGGL((k_transfer_pt<PI, PO>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, Ne,
+                           nv, M, x, x0, acc, y);
+    } else {
+        const int n = nv * Ne;
+        hipLaunchKernelGGL((k_transfer_sf<DIM, PI, PO>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                           Ne, nv, M, x, x0, acc, y);
+    }
 }
 
 template <int DIM>
