@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int 
                                                             const double *__restrict__ r, double alpha,
                                                             double beta, double *__restrict__ y) {
     extern __shared__ double s_r[];  // [epb][nb], then the partial sums [epb][S][nb] when S > 1
-    const int k0 = blockIdx.x * epb;
+    const int k0 = xcd_block(blockIdx.x, gridDim.x) * epb;  // r and y lines stay within one XCD
     const int ne = min(epb, Ne - k0);
     for (int t = threadIdx.x; t < epb * nb; t += blockDim.x) {
         const int e = t / nb, j = t - e * nb;

@@ -101,6 +101,19 @@ struct Level {
     double *r0 = nullptr;     // scratch: R at the EJ linearisation point
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  Remap the hardware workgroup index so that every XCD
+// processes one contiguous range of logical workgroups: neighbouring
+// elements then share their 128-byte lines and face data through one L2
+// instead of each XCD fetching the same lines again.  A bijection on
+// [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int NX = 8;
+    const int x = b % NX, j = b / NX;
+    const int q = nb / NX, r = nb % NX;
+    return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
 // Blocked Gauss-Jordan: ints per block of one panel's touched-row list (the
 // count, then up to 64 rows and the rows their values come from).
 constexpr int kTouchStride = 129;

@@ -119,19 +119,6 @@ __device__ __forceinline__ int neighbour(const MeshK &m, int k, int a, int s) {
     return c[0] + m.n[0] * (c[1] + m.n[1] * c[2]);
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
-// with its own L2.  Remap the hardware workgroup index so that every XCD
-// processes one contiguous range of logical workgroups: neighbouring
-// elements then share their 128-byte lines and face data through one L2
-// instead of each XCD fetching the same lines again.  A bijection on
-// [0, nb).
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    constexpr int NX = 8;
-    const int x = b % NX, j = b / NX;
-    const int q = nb / NX, r = nb % NX;
-    return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
-}
-
 __device__ __forceinline__ double sval(const Scal &s) { return s.p ? *s.p : s.v; }
 
 struct SrcK {
