@@ -163,7 +163,7 @@ hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, d
     const int epb = (lpe >= kApplyThreads) ? 1 : kApplyThreads / lpe;
     const size_t lds = (size_t)epb * nb * (S > 1 ? 1 + S : 1) * sizeof(double);
     dim3 grid((Ne + epb - 1) / epb);
-    dim3 block(lpe >= kApplyThreads ? lpe : kApplyThreads);
+    dim3 block((epb * lpe + 63) / 64 * 64);  // whole wavefronts, none without a block row
     hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, S, (const T *)L.inv, L.inv_cols, r,
                        alpha, beta, y);
     return hipGetLastError();
