@@ -71,7 +71,8 @@ __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int 
                                                             const T *__restrict__ inv,
                                                             const int *__restrict__ cols,
                                                             const double *__restrict__ r, double alpha,
-                                                            double beta, double *__restrict__ y) {
+                                                            double beta, const double *yin, Scal scale,
+                                                            double *y) {
     extern __shared__ double s_r[];  // [epb][nb], then the partial sums [epb][S][nb] when S > 1
     const int k0 = xcd_block(blockIdx.x, gridDim.x) * epb;  // r and y lines stay within one XCD
     const int ne = min(epb, Ne - k0);
@@ -136,10 +137,11 @@ __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int 
     }
     if (!active) return;
     const int k = k0 + e;
+    const double sc = sval(scale);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const size_t idx = (size_t)(row + q) * Ne + k;
-        y[idx] = (beta == 0.0) ? alpha * acc[q] : beta * y[idx] + alpha * acc[q];
+        y[idx] = sc * ((beta == 0.0) ? alpha * acc[q] : beta * yin[idx] + alpha * acc[q]);
     }
 }
 
@@ -153,8 +155,8 @@ int apply_split(int nb, int tpe, int Ne) {
 }
 
 template <typename T, int R>
-hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, double beta, double *y,
-                        hipStream_t s) {
+hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, double beta, const double *yin,
+                        Scal scale, double *y, hipStream_t s) {
     const int nb = L.nb;
     const int tpe = nb / R;
     if (tpe > kApplyThreads) return hipErrorInvalidValue;
@@ -165,26 +167,31 @@ hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, d
     dim3 grid((Ne + epb - 1) / epb);
     dim3 block((epb * lpe + 63) / 64 * 64);  // whole wavefronts, none without a block row
     hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, S, (const T *)L.inv, L.inv_cols, r,
-                       alpha, beta, y);
+                       alpha, beta, yin, scale, y);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta, double *y,
-                    hipStream_t s) {
+hipError_t ej_apply_ex(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta,
+                       const double *yin, Scal scale, double *y, hipStream_t s) {
     const Level &L = ctx->lv[level];
     const int nb = L.nb, Ne = ctx->mesh.Ne;
     if (L.inv_prec == FR_PREC_FP64)
-        return (nb % 2 == 0) ? launch_apply<double, 2>(L, Ne, r, alpha, beta, y, s)
-                             : launch_apply<double, 1>(L, Ne, r, alpha, beta, y, s);
+        return (nb % 2 == 0) ? launch_apply<double, 2>(L, Ne, r, alpha, beta, yin, scale, y, s)
+                             : launch_apply<double, 1>(L, Ne, r, alpha, beta, yin, scale, y, s);
     if (L.inv_prec == FR_PREC_BF16_STORE)
-        return (nb % 4 == 0) ? launch_apply<__bf16, 4>(L, Ne, r, alpha, beta, y, s)
-                             : launch_apply<__bf16, 1>(L, Ne, r, alpha, beta, y, s);
+        return (nb % 4 == 0) ? launch_apply<__bf16, 4>(L, Ne, r, alpha, beta, yin, scale, y, s)
+                             : launch_apply<__bf16, 1>(L, Ne, r, alpha, beta, yin, scale, y, s);
     if (L.inv_prec >= 0)
-        return (nb % 4 == 0) ? launch_apply<float, 4>(L, Ne, r, alpha, beta, y, s)
-                             : launch_apply<float, 1>(L, Ne, r, alpha, beta, y, s);
+        return (nb % 4 == 0) ? launch_apply<float, 4>(L, Ne, r, alpha, beta, yin, scale, y, s)
+                             : launch_apply<float, 1>(L, Ne, r, alpha, beta, yin, scale, y, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta, double *y,
+                    hipStream_t s) {
+    return ej_apply_ex(ctx, level, r, alpha, beta, y, Scal{1.0, nullptr}, y, s);
 }
 
 }  // namespace frpmg

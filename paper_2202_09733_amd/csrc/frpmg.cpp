@@ -412,6 +412,18 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
         inv_s = Scal{0.0, ctx->scal + SC_PMG_INV};
     }
     double *Y = ctx->wY, *G = ctx->wG;
+    // post-smoothing; the last sweep writes the output, undoing the input scale
+    bool scaled_out = false;
+    auto post_smooth = [&]() {
+        for (int it = 0; it < p.n0; ++it) {
+            residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
+            cnt->R0++;
+            const bool last = it == p.n0 - 1;
+            HIPCHK(ej_apply_ex(ctx, 0, G, -1.0, 1.0, Y, last ? inv_s : one, last ? y : Y, s));
+            cnt->E0++;
+        }
+        scaled_out = true;
+    };
     // pre-smoothing: the first sweep starts at Y = 0, where G = -X
     HIPCHK(ej_apply(ctx, 0, Xs, 1.0, 0.0, Y, s));
     cnt->E0++;
@@ -436,25 +448,18 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
         HIPCHK(lcc_output(ctx, Lc, Lc.Y, Lc.srow, ctx->cZ, s));
         HIPCHK(vec_axpby(N1, one, Lc.dtmp, one, ctx->cZ, s));  // C = C1 + network refinement
         HIPCHK(transfer_apply(ctx, 0, false, ctx->cZ, Y, s, nullptr, true));  // Y += Pi C
-        for (int it = 0; it < p.n0; ++it) {
-            residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
-            cnt->R0++;
-            HIPCHK(ej_apply(ctx, 0, G, -1.0, 1.0, Y, s));
-            cnt->E0++;
-        }
+        post_smooth();
     } else if (coarse) {
         const size_t N1 = ctx->lv[1].N;
         // defect d = -G(Y); restrict Y and G
         residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
         cnt->R0++;
-        HIPCHK(transfer_apply(ctx, 0, true, Y, ctx->cZ0, s));
-        HIPCHK(transfer_apply(ctx, 0, true, G, ctx->cd, s));  // cd = Gamma G = -Gamma d
+        HIPCHK(transfer_restrict2(ctx, 0, Y, ctx->cZ0, G, ctx->cd, s));  // cd = Gamma G = -Gamma d
         // FAS forcing S1 = G1(Z0) + Gamma d  with G1(Z) = sigma Z - (R1(q1 + Z) - R1(q1))
         residual_lin(ctx, 1, ctx->q1, ctx->cZ0, one, ctx->r1, p.sigma_D, ctx->cd, ctx->cS, s);
         cnt->R1++;
-        // coarse sweeps; the first uses G1(Z0) - S1 = -Gamma d = cd
-        HIPCHK(vec_scale_copy(N1, one, ctx->cZ0, ctx->cZ, s));
-        HIPCHK(ej_apply(ctx, 1, ctx->cd, -1.0, 1.0, ctx->cZ, s));
+        // coarse sweeps; the first uses G1(Z0) - S1 = -Gamma d = cd: Z = Z0 - B1^{-1} cd
+        HIPCHK(ej_apply_ex(ctx, 1, ctx->cd, -1.0, 1.0, ctx->cZ0, one, ctx->cZ, s));
         cnt->E1++;
         for (int it = 1; it < p.n1; ++it) {
             residual_lin(ctx, 1, ctx->q1, ctx->cZ, one, ctx->r1, p.sigma_D, ctx->cS, ctx->cG, s);
@@ -495,15 +500,9 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
         }
         // Y += Pi (Z - Z0), one kernel
         HIPCHK(transfer_apply(ctx, 0, false, ctx->cZ, Y, s, ctx->cZ0, true));
-        // post-smoothing
-        for (int it = 0; it < p.n0; ++it) {
-            residual_lin(ctx, 0, ctx->pt_q, Y, one, ctx->pt_rq, p.sigma_D, Xs, G, s);
-            cnt->R0++;
-            HIPCHK(ej_apply(ctx, 0, G, -1.0, 1.0, Y, s));
-            cnt->E0++;
-        }
+        post_smooth();
     }
-    HIPCHK(vec_scale_copy(N0, inv_s, Y, y, s));
+    if (!scaled_out) HIPCHK(vec_scale_copy(N0, inv_s, Y, y, s));
 }
 
 // ---------------------------------------------------------------------------

@@ -53,6 +53,8 @@ struct Scal {
     const double *p;
 };
 
+__device__ __forceinline__ double sval(const Scal &s) { return s.p ? *s.p : s.v; }
+
 // How a residual launch forms the state it evaluates R at.
 enum SrcMode { SRC_PLAIN = 0, SRC_AXPY = 1 };
 // What a residual launch writes.
@@ -200,6 +202,9 @@ hipError_t scal_fd_step(const double *vn2, const double *dqn2, double eps, doubl
 hipError_t scal_pmg_scale(const double *xn2, const double *qn2, double eps_p, double sigma, double *s_out,
                           double *inv_out, hipStream_t s);
 // y = T x (or y += T (x - x0) with x0 / accumulate), T = restriction or prolongation
+// restriction of two vectors in one launch: y = Gamma x, y2 = Gamma x2
+hipError_t transfer_restrict2(const frpmg_ctx *ctx, int fine_level, const double *x, double *y, const double *x2,
+                              double *y2, hipStream_t s);
 hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_dir, const double *x,
                           double *y, hipStream_t s, const double *x0 = nullptr, bool accumulate = false);
 // ||v||^2 -> n2out and the FD step h = eps (1 + ||dq||) / ||v|| -> hout, one reduction
@@ -218,5 +223,8 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s);
 // y = beta y + alpha B^{-1} r
 hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta, double *y,
                     hipStream_t s);
+// y = scale (beta yin + alpha B^{-1} r); yin may be y
+hipError_t ej_apply_ex(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta,
+                       const double *yin, Scal scale, double *y, hipStream_t s);
 
 }  // namespace frpmg

@@ -119,8 +119,6 @@ __device__ __forceinline__ int neighbour(const MeshK &m, int k, int a, int s) {
     return c[0] + m.n[0] * (c[1] + m.n[1] * c[2]);
 }
 
-__device__ __forceinline__ double sval(const Scal &s) { return s.p ? *s.p : s.v; }
-
 struct SrcK {
     const double *dq;
     const double *v;

@@ -232,17 +232,26 @@ struct Mat1D {
     double m[kMaxP][kMaxP];
 };
 
-// input x (minus x0 when given); output written, or added to y (acc)
+// input x (minus x0 when given); output written, or added to y (acc).  With
+// x2 given, lanes beyond the first vector map x2 to y2 (written, no x0).
 template <int DIM, int PI, int PO>
-__global__ void __launch_bounds__(kThreads) k_transfer_sf(int Ne, int nv, Mat1D M, const double *__restrict__ x,
-                                                          const double *__restrict__ x0, int acc,
-                                                          double *__restrict__ y) {
+__global__ void __launch_bounds__(kThreads) k_transfer_sf(int Ne, int nv, Mat1D M, const double *x1,
+                                                          const double *x01, int acc1, double *y1,
+                                                          const double *x2, double *y2) {
     constexpr int NI = (DIM == 2) ? PI * PI : PI * PI * PI;
     constexpr int NO = (DIM == 2) ? PO * PO : PO * PO * PO;
     constexpr int PZI = (DIM == 2) ? 1 : PI;
     constexpr int PZO = (DIM == 2) ? 1 : PO;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nv * Ne) return;
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool second = idx >= nv * Ne;
+    if (second) {
+        idx -= nv * Ne;
+        if (!x2 || idx >= nv * Ne) return;
+    }
+    const double *__restrict__ x = second ? x2 : x1;
+    const double *__restrict__ x0 = second ? nullptr : x01;
+    const int acc = second ? 0 : acc1;
+    double *__restrict__ y = second ? y2 : y1;
     const int k = idx % Ne, v = idx / Ne;
     double a[NI];
 #pragma unroll
@@ -321,23 +330,24 @@ __global__ void __launch_bounds__(kThreads) k_transfer_pt(int Ne, int nv, Mat1D 
 
 template <int DIM, int PI, int PO>
 void launch_sf(int Ne, int nv, const Mat1D &M, const double *x, const double *x0, int acc, double *y,
-               hipStream_t s) {
+               const double *x2, double *y2, hipStream_t s) {
     if constexpr (DIM == 2 && PO > PI) {
+        if (x2) launch_sf<DIM, PI, PO>(Ne, nv, M, x2, nullptr, 0, y2, nullptr, nullptr, s);
         const int n = nv * PO * PO * Ne;
         hipLaunchKernelGGL((k_transfer_pt<PI, PO>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, Ne,
                            nv, M, x, x0, acc, y);
     } else {
-        const int n = nv * Ne;
+        const int n = nv * Ne * (x2 ? 2 : 1);
         hipLaunchKernelGGL((k_transfer_sf<DIM, PI, PO>), dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-                           Ne, nv, M, x, x0, acc, y);
+                           Ne, nv, M, x, x0, acc, y, x2, y2);
     }
 }
 
 template <int DIM>
 bool dispatch_sf(int PI, int PO, int Ne, int nv, const Mat1D &M, const double *x, const double *x0, int acc,
-                 double *y, hipStream_t s) {
+                 double *y, const double *x2, double *y2, hipStream_t s) {
 #define FR_SF(a, b) \
-    if (PI == a && PO == b) { launch_sf<DIM, a, b>(Ne, nv, M, x, x0, acc, y, s); return true; }
+    if (PI == a && PO == b) { launch_sf<DIM, a, b>(Ne, nv, M, x, x0, acc, y, x2, y2, s); return true; }
     FR_SF(2, 3) FR_SF(2, 4) FR_SF(3, 2) FR_SF(3, 4) FR_SF(4, 2) FR_SF(4, 3) FR_SF(2, 1) FR_SF(1, 2)
     FR_SF(3, 1) FR_SF(1, 3) FR_SF(4, 1) FR_SF(1, 4)
     if (DIM == 2) {
@@ -436,8 +446,10 @@ hipError_t scal_pmg_scale(const double *xn2, const double *qn2, double eps_p, do
     return hipGetLastError();
 }
 
-hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_dir, const double *x, double *y,
-                          hipStream_t s, const double *x0, bool accumulate) {
+namespace {
+
+hipError_t transfer_launch(const frpmg_ctx *ctx, int fine_level, bool restrict_dir, const double *x, double *y,
+                           const double *x0, bool accumulate, const double *x2, double *y2, hipStream_t s) {
     const Transfer1D &t = ctx->tr[fine_level];
     const int Pin = restrict_dir ? t.P0 : t.P1;
     const int Pout = restrict_dir ? t.P1 : t.P0;
@@ -446,10 +458,22 @@ hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_di
     for (int o = 0; o < Pout; ++o)
         for (int j = 0; j < Pin; ++j) M.m[o][j] = restrict_dir ? t.G[o][j] : t.Pi[o][j];
     const int acc = accumulate ? 1 : 0;
-    const bool ok = (ctx->dim == 2) ? dispatch_sf<2>(Pin, Pout, Ne, ctx->nv, M, x, x0, acc, y, s)
-                                    : dispatch_sf<3>(Pin, Pout, Ne, ctx->nv, M, x, x0, acc, y, s);
+    const bool ok = (ctx->dim == 2) ? dispatch_sf<2>(Pin, Pout, Ne, ctx->nv, M, x, x0, acc, y, x2, y2, s)
+                                    : dispatch_sf<3>(Pin, Pout, Ne, ctx->nv, M, x, x0, acc, y, x2, y2, s);
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t transfer_apply(const frpmg_ctx *ctx, int fine_level, bool restrict_dir, const double *x, double *y,
+                          hipStream_t s, const double *x0, bool accumulate) {
+    return transfer_launch(ctx, fine_level, restrict_dir, x, y, x0, accumulate, nullptr, nullptr, s);
+}
+
+hipError_t transfer_restrict2(const frpmg_ctx *ctx, int fine_level, const double *x, double *y, const double *x2,
+                              double *y2, hipStream_t s) {
+    return transfer_launch(ctx, fine_level, true, x, y, nullptr, false, x2, y2, s);
 }
 
 }  // namespace frpmg
