@@ -229,6 +229,50 @@ fr_status gmres_solve_stage(frpmg_ctx *ctx, const stage_params *prm, const doubl
                             stage_stats *stats, fr_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Full implicit time steps (synchronous): every stage of one step of
+ * dq/dt = R(q) (Sec. 2.1), the EJ factors formed once at q^n and reused by
+ * every stage (Sec. 2.2).  The paper names its schemes (ESDIRK, ROW) without
+ * printing their tableaux; the two here share the diagonal gamma =
+ * 0.43586652150845899942 (L-stability for three implicit stages of order 3),
+ * so they use the same shift and the same preconditioner:
+ *   FR_TAB_ESDIRK3: 4 stages, explicit first stage, stiffly accurate,
+ *     order 3, c = (0, 2 gamma, 3/5, 1) (Eq. (ESDIRK2) generalised to every
+ *     stage).  Stage i solves q_i = q^n + dt (sum_{j<i} a_ij R(q_j) +
+ *     gamma R(q_i)) as gmres_solve_stage does, from q_{i-1}, to
+ *     ||F_i|| <= tol ||F_i(q_{i-1})||.  q^{n+1} = q_4.
+ *   FR_TAB_ROW3: 3 stages, order 3 (Eq. (Rosenbrock_General)):
+ *     (I/(gamma dt) - dR/dq(q^n)) Y_i = R(q^n + sum_j a_ij Y_j)
+ *                                      + (1/dt) sum_j c_ij Y_j,
+ *     each by FGMRES to tol relative to its right-hand side; stages 2 and 3
+ *     evaluate R at the same state.  q^{n+1} = q^n + sum_i m_i Y_i.
+ * prm->stage carries dt and the solver and preconditioner settings; its
+ * scheme, a_ii, a_i1 and skip_setup are ignored.  dq_n and dq_np1 are
+ * level-0 device vectors and must not alias.  Returns FR_ENOCONV or
+ * FR_ENONFINITE if a stage fails (stats then hold the stages so far). */
+#define FR_TAB_ESDIRK3 0
+#define FR_TAB_ROW3 1
+#define FR_MAX_STEP_STAGES 4
+
+typedef struct {
+    int tableau;         /* FR_TAB_* */
+    stage_params stage;  /* dt, solver and preconditioner settings */
+} step_params;
+
+typedef struct {
+    int nstages;         /* implicit stages solved */
+    int gmres_iters;     /* over every stage */
+    int ptc_iters;       /* ESDIRK: pseudo-time steps over every stage */
+    int fallbacks;
+    int status;
+    double t_total, t_setup, t_solve;  /* seconds, host wall clock */
+    long n_R_fine, n_R_coarse, n_ej_fine, n_ej_coarse;
+    stage_stats stage[FR_MAX_STEP_STAGES];
+} step_stats;
+
+fr_status fr_time_step(frpmg_ctx *ctx, const step_params *prm, const double *dq_n, double *dq_np1,
+                       step_stats *stats, fr_stream stream);
+
+/* ------------------------------------------------------------------------
  * Learned coarse correction (not in the paper): an element-local, bias-free
  * ReLU network in -> 256 -> 256 -> out refines the element-local coarse EJ
  * step.  With C1 = B1^{-1} Gamma d (one coarse EJ application to the

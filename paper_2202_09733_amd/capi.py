@@ -31,7 +31,7 @@ MAX_NEWTON_LOG = 128
 
 EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_residual", "fr_jvp", "ej_factor",
            "ej_solve", "ej_get_inverse", "pmg_restrict", "pmg_prolong", "pmg_set_point", "pmg_precond_apply",
-           "gmres_solve_stage", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
+           "gmres_solve_stage", "fr_time_step", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
            "lcc_get_weights", "lcc_set_weights", "lcc_get_scales", "lcc_set_scales", "lcc_forward",
            "lcc_loss_grad", "lcc_features_of"]
 
@@ -97,6 +97,28 @@ class StageStats(ctypes.Structure):
         return d
 
 
+TAB_ESDIRK3, TAB_ROW3 = 0, 1
+MAX_STEP_STAGES = 4
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [("tableau", ctypes.c_int), ("stage", StageParams)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("nstages", ctypes.c_int), ("gmres_iters", ctypes.c_int), ("ptc_iters", ctypes.c_int),
+                ("fallbacks", ctypes.c_int), ("status", ctypes.c_int),
+                ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double),
+                ("n_R_fine", ctypes.c_long), ("n_R_coarse", ctypes.c_long),
+                ("n_ej_fine", ctypes.c_long), ("n_ej_coarse", ctypes.c_long),
+                ("stage", StageStats * MAX_STEP_STAGES)]
+
+    def as_dict(self):
+        d = {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "stage"}
+        d["stages"] = [self.stage[i].as_dict() for i in range(self.nstages)]
+        return d
+
+
 _lib = None
 
 
@@ -127,6 +149,7 @@ def load():
     L.pmg_set_point.argtypes = [vp, vp, vp, vp]
     L.pmg_precond_apply.argtypes = [vp, ctypes.POINTER(PmgParams), vp, vp, vp]
     L.gmres_solve_stage.argtypes = [vp, ctypes.POINTER(StageParams), vp, vp, ctypes.POINTER(StageStats), vp]
+    L.fr_time_step.argtypes = [vp, ctypes.POINTER(StepParams), vp, vp, ctypes.POINTER(StepStats), vp]
     ip = ctypes.POINTER(ctypes.c_int)
     fp = ctypes.POINTER(ctypes.c_float)
     L.lcc_harvest.argtypes = [vp, ctypes.POINTER(LccHarvestParams)]
@@ -409,6 +432,19 @@ class FR:
                                         _stream())
         if rc != FR_OK and (raise_on_noconv or rc != FR_ENOCONV):
             self._check("gmres_solve_stage", rc)
+        d = st.as_dict()
+        d["rc"] = rc
+        return out, d
+
+    def time_step(self, cfg: StageConfig, dq_n, tableau=TAB_ESDIRK3, out=None, raise_on_noconv=True):
+        """One full time step (every stage); cfg gives dt and the solver settings."""
+        out = self.empty(0) if out is None else out
+        st = StepStats()
+        prm = StepParams(tableau=tableau, stage=cfg.to_c())
+        rc = self.lib.fr_time_step(self.ctx, ctypes.byref(prm), _ptr(dq_n), _ptr(out), ctypes.byref(st),
+                                   _stream())
+        if rc != FR_OK and (raise_on_noconv or rc != FR_ENOCONV):
+            self._check("fr_time_step", rc)
         d = st.as_dict()
         d["rc"] = rc
         return out, d

@@ -766,28 +766,49 @@ double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, double *out, stage_stats *st,
-                hipStream_t s) {
-    REQUIRE(P.scheme == FR_SCHEME_ESDIRK || P.scheme == FR_SCHEME_ROW, "bad scheme");
-    REQUIRE(P.m >= 1 && P.m <= 60, "Krylov dimension must be in 1..60");
-    REQUIRE(P.dt > 0 && P.a_ii > 0, "dt and a_ii must be positive");
-    REQUIRE(P.precond >= FR_PRECOND_EJ && P.precond <= FR_PRECOND_PMG_LEARNED, "unknown preconditioner");
-    const bool pmg = P.precond != FR_PRECOND_EJ;
-    const bool learned = P.precond == FR_PRECOND_PMG_LEARNED;
-    if (learned) REQUIRE(ctx->lcc && ctx->lcc->scales_set, "the learned correction has no trained network");
-    REQUIRE(!pmg || ctx->nlevels > 1, "pMG needs two levels");
-    std::memset(st, 0, sizeof(*st));
-    const size_t N = ctx->lv[0].N;
-    ensure_krylov(ctx, P.m);
+// The solver state of one implicit stage: shifts, preconditioner settings,
+// counters, the stall monitor and the graph keys.  One object serves every
+// stage of a time step (same diagonal coefficient, same EJ factors).
+struct StageSolver {
+    frpmg_ctx *ctx;
+    stage_params P;
+    size_t N;
+    bool esdirk, pmg, learned, use_graphs;
+    double sigma_A, sigma_S;
+    pmg_params pp;
     Counters cnt;
-    HIPCHK(hipStreamSynchronize(s));
-    const double t0 = now();
-    const bool esdirk = P.scheme == FR_SCHEME_ESDIRK;
-    const double dtau = (P.dtau > 0) ? P.dtau : P.dt;
-    // shifts: sigma_A of the outer operator, sigma_S of the smoother blocks
-    const double sigma_A = esdirk ? 1.0 / dtau + 1.0 / (P.a_ii * P.dt) : 1.0 / (P.a_ii * P.dt);
-    const double sigma_S = 1.0 / dtau + sigma_A;
-    if (!P.skip_setup) {
+    Stall stall;
+    int fallbacks = 0;
+
+    StageSolver(frpmg_ctx *c, const stage_params &prm) : ctx(c), P(prm) {
+        REQUIRE(P.scheme == FR_SCHEME_ESDIRK || P.scheme == FR_SCHEME_ROW, "bad scheme");
+        REQUIRE(P.m >= 1 && P.m <= 60, "Krylov dimension must be in 1..60");
+        REQUIRE(P.dt > 0 && P.a_ii > 0, "dt and a_ii must be positive");
+        REQUIRE(P.precond >= FR_PRECOND_EJ && P.precond <= FR_PRECOND_PMG_LEARNED, "unknown preconditioner");
+        pmg = P.precond != FR_PRECOND_EJ;
+        learned = P.precond == FR_PRECOND_PMG_LEARNED;
+        if (learned) REQUIRE(ctx->lcc && ctx->lcc->scales_set, "the learned correction has no trained network");
+        REQUIRE(!pmg || ctx->nlevels > 1, "pMG needs two levels");
+        N = ctx->lv[0].N;
+        ensure_krylov(ctx, P.m);
+        esdirk = P.scheme == FR_SCHEME_ESDIRK;
+        const double dtau = (P.dtau > 0) ? P.dtau : P.dt;
+        // shifts: sigma_A of the outer operator, sigma_S of the smoother blocks
+        sigma_A = esdirk ? 1.0 / dtau + 1.0 / (P.a_ii * P.dt) : 1.0 / (P.a_ii * P.dt);
+        sigma_S = 1.0 / dtau + sigma_A;
+        pp = pmg_params{sigma_A, P.n0, P.n1, learned ? FR_COARSE_LEARNED : FR_COARSE_EJ, P.scale_mode, P.eps_p};
+        stall.active = learned;
+        if (P.stall_window > 0) stall.window = P.stall_window;
+        if (P.stall_ratio > 0) stall.ratio = P.stall_ratio;
+        stall.on_stall = [this] {
+            pp.coarse_mode = FR_COARSE_EJ;  // plain pMG for the rest of the stage
+            fallbacks++;
+        };
+        use_graphs = P.graphs && !learned && !(ctx->lcc && ctx->lcc->harvesting);
+    }
+
+    // EJ factors at q^n (Sec. 2.2: once per physical time step)
+    void setup(const double *dq_n, hipStream_t s) {
         if (pmg) {
             ej_factor_impl(ctx, 0, dq_n, sigma_S, P.precision, s);
             // the coarse blocks are linearised at Gamma q^n
@@ -800,28 +821,18 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
         cnt.R0 += 1 + ctx->lv[0].nb;
         if (pmg) cnt.R1 += 1 + ctx->lv[1].nb;
     }
-    HIPCHK(hipStreamSynchronize(s));
-    const double t1 = now();
-    pmg_params pp{sigma_A, P.n0, P.n1, learned ? FR_COARSE_LEARNED : FR_COARSE_EJ, P.scale_mode, P.eps_p};
-    Stall stall;
-    stall.active = learned;
-    if (P.stall_window > 0) stall.window = P.stall_window;
-    if (P.stall_ratio > 0) stall.ratio = P.stall_ratio;
-    stall.on_stall = [&] {
-        pp.coarse_mode = FR_COARSE_EJ;  // plain pMG for the rest of the stage
-        st->fallbacks++;
-    };
-    auto prec = [&](const double *v, double *z, hipStream_t st) {
+
+    void prec(const double *v, double *z, hipStream_t s) {
         if (pmg) {
-            pmg_apply_impl(ctx, pp, v, z, st, &cnt);
+            pmg_apply_impl(ctx, pp, v, z, s, &cnt);
         } else {
-            HIPCHK(ej_apply(ctx, 0, v, 1.0, 0.0, z, st));
+            HIPCHK(ej_apply(ctx, 0, v, 1.0, 0.0, z, s));
             cnt.E0++;
         }
-    };
+    }
+
     // captured Arnoldi steps: everything a step bakes in goes into its key
-    const bool use_graphs = P.graphs && !learned && !(ctx->lcc && ctx->lcc->harvesting);
-    auto graph_use = [&](const double *q, const double *rq) {
+    GraphUse graph_use(const double *q, const double *rq) {
         GraphUse g;
         g.cnt = &cnt;
         g.key = {ctx->graph_epoch, (unsigned long long)P.scheme, (unsigned long long)P.precond, bits(sigma_A),
@@ -829,21 +840,20 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
                  (unsigned long long)P.scale_mode, bits(P.eps_p), bits(q), bits(rq), bits(ctx->V), bits(ctx->Zk),
                  bits(ctx->kw), (unsigned long long)N};
         return g;
-    };
-    fr_status status = FR_OK;
-    if (esdirk) {
-        double *q = ctx->sq, *rq = ctx->srq, *F = ctx->sF, *b = ctx->sb, *dx = ctx->sdx;
-        residual(ctx, 0, dq_n, rq, s);
-        cnt.R0++;
-        HIPCHK(hipMemcpyAsync(b, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIPCHK(vec_axpby(N, Scal{P.a_i1 * P.dt, nullptr}, rq, Scal{1.0, nullptr}, b, s));
-        HIPCHK(hipMemcpyAsync(q, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+
+    // ESDIRK stage (Sec. 2.1 Eq. (ESDIRK2) and Sec. 2.2): F(q) = (q - b)/(a_ii dt)
+    // - R(q) = 0 by pseudo-transient continuation with inexact Newton from q
+    // (in/out, rq = R(q) in/out) until ||F|| <= tol ||F(q_start)||.
+    fr_status esdirk_solve(const double *b, double *q, double *rq, stage_stats *st, hipStream_t s) {
+        double *F = ctx->sF, *dx = ctx->sdx;
         const double c = 1.0 / (P.a_ii * P.dt);
         HIPCHK(vec_stage_F(N, q, b, c, rq, F, s));
         const double f0 = host_norm(ctx, N, F, s);
         st->res0 = f0;
         double fn = f0;
-        if (!std::isfinite(f0)) status = FR_ENONFINITE;
+        fr_status status = std::isfinite(f0) ? FR_OK : FR_ENONFINITE;
+        auto prec_f = [&](const double *v, double *z, hipStream_t st2) { prec(v, z, st2); };
         while (status == FR_OK && fn > P.tol * f0 && st->ptc_iters < P.max_ptc) {
             if (pmg) {
                 pmg_point(ctx, q, rq, s);
@@ -851,12 +861,12 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
             }
             HIPCHK(vec_axpby(N, Scal{0.0, nullptr}, nullptr, Scal{-1.0, nullptr}, F, s));  // F <- -F
             HIPCHK(vec_dot(ctx, N, q, q, ctx->scal + SC_DQ_N2, s));
-            auto A = [&](const double *z, double *w, hipStream_t st) {
-                jvp(ctx, 0, q, rq, z, sigma_A, P.eps, P.eps_mode, w, st, ctx->scal + SC_DQ_N2);
+            auto A = [&](const double *z, double *w, hipStream_t st2) {
+                jvp(ctx, 0, q, rq, z, sigma_A, P.eps, P.eps_mode, w, st2, ctx->scal + SC_DQ_N2);
                 cnt.R0++;
             };
             const GraphUse gu = graph_use(q, rq);
-            KrylovResult kr = fgmres(ctx, N, F, dx, P.m, P.eta, P.max_restarts, A, prec, s, &stall,
+            KrylovResult kr = fgmres(ctx, N, F, dx, P.m, P.eta, P.max_restarts, A, prec_f, s, &stall,
                                      use_graphs ? &gu : nullptr);
             if (st->ptc_iters < FR_MAX_NEWTON_LOG) st->gmres_per_newton[st->ptc_iters] = kr.iters;
             st->gmres_iters += kr.iters;
@@ -877,52 +887,247 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
         st->rel_res = f0 > 0 ? fn / f0 : 0.0;
         st->converged = (fn <= P.tol * f0) ? 1 : 0;
         if (status == FR_OK && !st->converged) status = FR_ENOCONV;
-        HIPCHK(hipMemcpyAsync(out, q, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    } else {
-        double *R0 = ctx->srq, *w = ctx->sF;
-        residual(ctx, 0, dq_n, R0, s);
-        cnt.R0++;
-        if (pmg) {
-            pmg_point(ctx, dq_n, R0, s);
-            cnt.R1++;
-        }
-        HIPCHK(vec_dot(ctx, N, dq_n, dq_n, ctx->scal + SC_DQ_N2, s));
-        auto A = [&](const double *z, double *wout, hipStream_t st) {
-            jvp(ctx, 0, dq_n, R0, z, sigma_A, P.eps, P.eps_mode, wout, st, ctx->scal + SC_DQ_N2);
+        return status;
+    }
+
+    // ROW stage (Sec. 2.1 Eq. (Rosenbrock_General)): (sigma_A I - J(q_lin)) U = rhs
+    // by FGMRES to tol relative to ||rhs||, J the FD Jacobian at q_lin (with
+    // R_lin = R(q_lin)); the pMG point must already be at q_lin.
+    fr_status row_solve(const double *q_lin, const double *R_lin, const double *rhs, double *U, stage_stats *st,
+                        hipStream_t s) {
+        double *w = ctx->sF;
+        HIPCHK(vec_dot(ctx, N, q_lin, q_lin, ctx->scal + SC_DQ_N2, s));
+        auto A = [&](const double *z, double *wout, hipStream_t st2) {
+            jvp(ctx, 0, q_lin, R_lin, z, sigma_A, P.eps, P.eps_mode, wout, st2, ctx->scal + SC_DQ_N2);
             cnt.R0++;
         };
-        const GraphUse gu = graph_use(dq_n, R0);
-        KrylovResult kr = fgmres(ctx, N, R0, out, P.m, P.tol, P.max_restarts, A, prec, s, &stall,
+        auto prec_f = [&](const double *v, double *z, hipStream_t st2) { prec(v, z, st2); };
+        const GraphUse gu = graph_use(q_lin, R_lin);
+        KrylovResult kr = fgmres(ctx, N, rhs, U, P.m, P.tol, P.max_restarts, A, prec_f, s, &stall,
                                  use_graphs ? &gu : nullptr);
-        st->gmres_iters = kr.iters;
-        st->restarts = kr.restarts;
+        st->gmres_iters += kr.iters;
+        st->restarts += kr.restarts;
         st->gmres_per_newton[0] = kr.iters;
         st->res0 = kr.bnorm;
         st->res = kr.res_est;
         st->rel_res = kr.bnorm > 0 ? kr.res_est / kr.bnorm : 0.0;
         st->converged = kr.converged ? 1 : 0;
-        if (kr.nonfinite) status = FR_ENONFINITE;
-        else if (!kr.converged) status = FR_ENOCONV;
         // true residual of the FD operator at the solution
-        A(out, w, s);
-        HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, R0, Scal{-1.0, nullptr}, w, s));
+        A(U, w, s);
+        HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, rhs, Scal{-1.0, nullptr}, w, s));
         const double tr = host_norm(ctx, N, w, s);
         st->true_rel_res = kr.bnorm > 0 ? tr / kr.bnorm : 0.0;
+        if (kr.nonfinite) return FR_ENONFINITE;
+        if (!kr.converged) return FR_ENOCONV;
+        return FR_OK;
+    }
+
+    void finish(stage_stats *st) {
+        st->n_R_fine = cnt.R0;
+        st->n_R_coarse = cnt.R1;
+        st->n_ej_fine = cnt.E0;
+        st->n_ej_coarse = cnt.E1;
+        st->fallbacks = fallbacks;
+    }
+};
+
+[[noreturn]] void fail_stage(frpmg_ctx *ctx, fr_status status) {
+    ctx->err = status == FR_ENONFINITE ? "non-finite norm in the stage solve" : "stage solve did not converge";
+    throw Fail{status};
+}
+
+void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, double *out, stage_stats *st,
+                hipStream_t s) {
+    std::memset(st, 0, sizeof(*st));
+    StageSolver S(ctx, P);
+    const size_t N = S.N;
+    HIPCHK(hipStreamSynchronize(s));
+    const double t0 = now();
+    if (!P.skip_setup) S.setup(dq_n, s);
+    HIPCHK(hipStreamSynchronize(s));
+    const double t1 = now();
+    fr_status status;
+    if (S.esdirk) {
+        // second stage of an ESDIRK scheme: b = q^n + dt a_i1 R(q^n), start at q^n
+        double *q = ctx->sq, *rq = ctx->srq, *b = ctx->sb;
+        residual(ctx, 0, dq_n, rq, s);
+        S.cnt.R0++;
+        HIPCHK(hipMemcpyAsync(b, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(vec_axpby(N, Scal{P.a_i1 * P.dt, nullptr}, rq, Scal{1.0, nullptr}, b, s));
+        HIPCHK(hipMemcpyAsync(q, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        status = S.esdirk_solve(b, q, rq, st, s);
+        HIPCHK(hipMemcpyAsync(out, q, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+        // first stage of a ROW scheme: rhs = R(q^n)
+        double *R0 = ctx->srq;
+        residual(ctx, 0, dq_n, R0, s);
+        S.cnt.R0++;
+        if (S.pmg) {
+            pmg_point(ctx, dq_n, R0, s);
+            S.cnt.R1++;
+        }
+        status = S.row_solve(dq_n, R0, R0, out, st, s);
     }
     HIPCHK(hipStreamSynchronize(s));
     const double t2 = now();
     st->t_setup = t1 - t0;
     st->t_solve = t2 - t1;
     st->t_total = t2 - t0;
-    st->n_R_fine = cnt.R0;
-    st->n_R_coarse = cnt.R1;
-    st->n_ej_fine = cnt.E0;
-    st->n_ej_coarse = cnt.E1;
+    S.finish(st);
     st->status = status;
-    if (status != FR_OK) {
-        ctx->err = status == FR_ENONFINITE ? "non-finite norm in the stage solve" : "stage solve did not converge";
-        throw Fail{status};
+    if (status != FR_OK) fail_stage(ctx, status);
+}
+
+// ---------------------------------------------------------------------------
+// full time steps (every stage; the EJ factors formed once at q^n)
+// ---------------------------------------------------------------------------
+
+// ESDIRK3: four stages, explicit first stage, stiffly accurate, order 3,
+// L-stable: gamma is the root in (0.4, 0.5) of 6 g^3 - 18 g^2 + 9 g - 1,
+// c = (0, 2 gamma, 3/5, 1), the other coefficients fixed by the order-3
+// conditions (the four-stage ESDIRK3(2)4L[2]SA of Kennedy & Carpenter).
+constexpr double kGamma3 = 0.43586652150845899942;
+constexpr double kEsdirk3A[4][4] = {
+    {0.0, 0.0, 0.0, 0.0},
+    {kGamma3, kGamma3, 0.0, 0.0},
+    {0.2576482460664271, -0.09351476757488614, kGamma3, 0.0},
+    {0.18764102434672392, -0.5952974735769553, 0.9717899277217725, kGamma3}};
+
+// ROW3: three stages, order 3, L-stable, diagonal kGamma3, defined by
+// alpha_21 = alpha_31 = 1, alpha_32 = 0, b = (2/3, 1/6, 1/6),
+// gamma_21 = gamma_31 = beta_21 - 1, gamma_32 = beta_32, where
+// beta_21 = (s + sqrt(s^2 - 8p))/4, beta_32 = s - 2 beta_21 with
+// s = 3 - 6 gamma, p = 1 - 6 gamma + 6 gamma^2 (the two remaining order
+// conditions).  Applied in the transformed form a = alpha Gamma^{-1},
+// c = diag(1/gamma) - Gamma^{-1}, m = b Gamma^{-1}, computed here.
+struct Row3 {
+    double a[3][3] = {}, c[3][3] = {}, m[3] = {};
+    Row3() {
+        const double g = kGamma3;
+        const double sv = 3.0 - 6.0 * g, pv = 1.0 - 6.0 * g + 6.0 * g * g;
+        const double b21 = (sv + std::sqrt(sv * sv - 8.0 * pv)) / 4.0, b32 = sv - 2.0 * b21;
+        const double G[3][3] = {{g, 0.0, 0.0}, {b21 - 1.0, g, 0.0}, {b21 - 1.0, b32, g}};
+        const double alpha[3][3] = {{0.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
+        const double b[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
+        // Gi = Gamma^{-1} by forward substitution (lower triangular)
+        double Gi[3][3] = {};
+        for (int col = 0; col < 3; ++col)
+            for (int i = 0; i < 3; ++i) {
+                double t = (i == col) ? 1.0 : 0.0;
+                for (int k = 0; k < i; ++k) t -= G[i][k] * Gi[k][col];
+                Gi[i][col] = t / G[i][i];
+            }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double t = 0.0;
+                for (int k = 0; k < 3; ++k) t += alpha[i][k] * Gi[k][j];
+                a[i][j] = t;
+                c[i][j] = (i == j ? 1.0 / G[i][i] : 0.0) - Gi[i][j];
+            }
+        for (int j = 0; j < 3; ++j) {
+            double t = 0.0;
+            for (int i = 0; i < 3; ++i) t += b[i] * Gi[i][j];
+            m[j] = t;
+        }
     }
+};
+
+void ensure_step_vectors(frpmg_ctx *ctx, int nvec) {
+    const size_t N = ctx->lv[0].N;
+    if (ctx->stv && ctx->stv_n >= nvec) return;
+    dfree(ctx->stv);
+    ctx->stv = dalloc(ctx, (size_t)nvec * N);
+    ctx->stv_n = nvec;
+    if (!ctx->stw) ctx->stw = dalloc(ctx, N);
+}
+
+void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double *out, step_stats *ss,
+               hipStream_t s) {
+    std::memset(ss, 0, sizeof(*ss));
+    REQUIRE(SP.tableau == FR_TAB_ESDIRK3 || SP.tableau == FR_TAB_ROW3, "unknown tableau");
+    REQUIRE(out != dq_n, "the output must not alias q^n");
+    stage_params P = SP.stage;
+    P.scheme = SP.tableau == FR_TAB_ESDIRK3 ? FR_SCHEME_ESDIRK : FR_SCHEME_ROW;
+    P.a_ii = kGamma3;
+    P.a_i1 = 0.0;
+    StageSolver S(ctx, P);
+    const size_t N = S.N;
+    ensure_step_vectors(ctx, 3);
+    double *V3[3] = {ctx->stv, ctx->stv + N, ctx->stv + 2 * N};
+    HIPCHK(hipStreamSynchronize(s));
+    const double t0 = now();
+    S.setup(dq_n, s);
+    HIPCHK(hipStreamSynchronize(s));
+    const double t1 = now();
+    ss->t_setup = t1 - t0;
+    fr_status status = FR_OK;
+    const Scal one{1.0, nullptr};
+    if (S.esdirk) {
+        // stage 1: q_1 = q^n; stages 2..4 start from the previous stage's state
+        double *q = ctx->sq, *rq = ctx->srq, *b = ctx->sb;
+        residual(ctx, 0, dq_n, rq, s);
+        S.cnt.R0++;
+        HIPCHK(hipMemcpyAsync(V3[0], rq, N * sizeof(double), hipMemcpyDeviceToDevice, s));  // R(q_1)
+        HIPCHK(hipMemcpyAsync(q, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        for (int i = 1; i < 4 && status == FR_OK; ++i) {
+            // b_i = q^n + dt sum_{j<i} a_ij R(q_j)
+            HIPCHK(hipMemcpyAsync(b, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            for (int j = 0; j < i; ++j)
+                HIPCHK(vec_axpby(N, Scal{kEsdirk3A[i][j] * P.dt, nullptr}, V3[j], one, b, s));
+            stage_stats *st = &ss->stage[ss->nstages];
+            status = S.esdirk_solve(b, q, rq, st, s);
+            ss->nstages++;
+            ss->gmres_iters += st->gmres_iters;
+            ss->ptc_iters += st->ptc_iters;
+            if (i < 3) HIPCHK(hipMemcpyAsync(V3[i], rq, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        HIPCHK(hipMemcpyAsync(out, q, N * sizeof(double), hipMemcpyDeviceToDevice, s));  // stiffly accurate
+    } else {
+        static const Row3 T;
+        double *R0 = ctx->srq, *rhs = ctx->sb, *w = ctx->stw, *Rw = ctx->sq;
+        residual(ctx, 0, dq_n, R0, s);
+        S.cnt.R0++;
+        if (S.pmg) {
+            pmg_point(ctx, dq_n, R0, s);
+            S.cnt.R1++;
+        }
+        for (int i = 0; i < 3 && status == FR_OK; ++i) {
+            // rhs_i = R(q^n + sum_j a_ij Y_j) + (1/dt) sum_j c_ij Y_j
+            if (i == 0) {
+                HIPCHK(hipMemcpyAsync(rhs, R0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            } else {
+                bool same = i > 1;
+                for (int j = 0; j < 3; ++j) same = same && T.a[i][j] == T.a[i - 1][j];
+                if (!same) {  // stages with the same state share R
+                    HIPCHK(hipMemcpyAsync(w, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+                    for (int j = 0; j < i; ++j)
+                        if (T.a[i][j] != 0.0) HIPCHK(vec_axpby(N, Scal{T.a[i][j], nullptr}, V3[j], one, w, s));
+                    residual(ctx, 0, w, Rw, s);
+                    S.cnt.R0++;
+                }
+                HIPCHK(hipMemcpyAsync(rhs, Rw, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+                for (int j = 0; j < i; ++j)
+                    HIPCHK(vec_axpby(N, Scal{T.c[i][j] / P.dt, nullptr}, V3[j], one, rhs, s));
+            }
+            stage_stats *st = &ss->stage[ss->nstages];
+            status = S.row_solve(dq_n, R0, rhs, V3[i], st, s);
+            ss->nstages++;
+            ss->gmres_iters += st->gmres_iters;
+        }
+        HIPCHK(hipMemcpyAsync(out, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        for (int i = 0; i < 3; ++i) HIPCHK(vec_axpby(N, Scal{T.m[i], nullptr}, V3[i], one, out, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const double t2 = now();
+    ss->t_solve = t2 - t1;
+    ss->t_total = t2 - t0;
+    ss->n_R_fine = S.cnt.R0;
+    ss->n_R_coarse = S.cnt.R1;
+    ss->n_ej_fine = S.cnt.E0;
+    ss->n_ej_coarse = S.cnt.E1;
+    ss->fallbacks = S.fallbacks;
+    ss->status = status;
+    if (status != FR_OK) fail_stage(ctx, status);
 }
 
 void destroy_all(frpmg_ctx *ctx) {
@@ -953,7 +1158,8 @@ void destroy_all(frpmg_ctx *ctx) {
     dfree(ctx->scal);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
     double *bufs[] = {ctx->q1, ctx->r1, ctx->wY, ctx->wG, ctx->wXs, ctx->cZ0, ctx->cZ, ctx->cS, ctx->cG, ctx->cd,
-                      ctx->V, ctx->Zk, ctx->kw, ctx->sq, ctx->srq, ctx->sF, ctx->sb, ctx->sdx};
+                      ctx->V, ctx->Zk, ctx->kw, ctx->sq, ctx->srq, ctx->sF, ctx->sb, ctx->sdx,
+                      ctx->stv, ctx->stw};
     for (double *b : bufs) dfree(b);
 }
 
@@ -1194,6 +1400,16 @@ fr_status gmres_solve_stage(frpmg_ctx *ctx, const stage_params *prm, const doubl
     return guarded(ctx, [&] {
         REQUIRE(prm && dq_n && out && dq_n != out, "bad arguments");
         stage_impl(ctx, *prm, dq_n, out, st, S(stream));
+    });
+}
+
+fr_status fr_time_step(frpmg_ctx *ctx, const step_params *prm, const double *dq_n, double *dq_np1,
+                       step_stats *stats, fr_stream stream) {
+    step_stats local;
+    step_stats *st = stats ? stats : &local;
+    return guarded(ctx, [&] {
+        REQUIRE(prm && dq_n && dq_np1 && dq_n != dq_np1, "bad arguments");
+        step_impl(ctx, *prm, dq_n, dq_np1, st, S(stream));
     });
 }
 

@@ -156,6 +156,8 @@ struct frpmg_ctx {
     int kdim = 0;
     double *V = nullptr, *Zk = nullptr, *kw = nullptr;
     double *sq = nullptr, *srq = nullptr, *sF = nullptr, *sb = nullptr, *sdx = nullptr;
+    double *stv = nullptr, *stw = nullptr;  // time step: stage vectors [stv_n][N], state scratch
+    int stv_n = 0;
     // learned coarse correction (allocated on first use)
     frpmg::Lcc *lcc = nullptr;
     // captured Arnoldi steps, replayed on the caller's stream

@@ -1,0 +1,88 @@
+"""Full implicit time steps on the GPU (fr_time_step): every stage of ESDIRK3
+and ROW3 with the EJ factors formed once at q^n, against the oracle's full
+steps (oracle/stepping.py) on small meshes, and at the full config-2 size."""
+import numpy as np
+import pytest
+
+from paper_2202_09733_amd import capi
+from paper_2202_09733_amd import workloads as W
+from gpu_util import announce, rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TABS = {"esdirk3": capi.TAB_ESDIRK3, "row3": capi.TAB_ROW3}
+
+
+def _oracle_step(orc, wl, tab, **kw):
+    from oracle import stepping as S
+    fine = orc.Level(**wl.level_kwargs(wl.p0))
+    coarse = orc.Level(**wl.level_kwargs(wl.p1))
+    if tab == "esdirk3":
+        return S.esdirk_step(fine, coarse, wl.dq, wl.dt, **kw)
+    return S.row_step(fine, coarse, wl.dq, wl.dt, **kw)
+
+
+@pytest.mark.parametrize("tab", ["esdirk3", "row3"])
+@pytest.mark.parametrize("case", ["bumps8", "vortical8"])
+def test_time_step_parity(orc, tab, case):
+    """GPU and oracle full steps agree to the stage solvers' tolerance: the
+    difference is bounded relative to the step's update q^{n+1} - q^n."""
+    require_gpu()
+    announce("time step %s %s" % (tab, case))
+    if case == "bumps8":
+        wl = W.make_bump_workload(n=(8, 8), p0=2, p1=1, dt_factor=10.0)
+    else:
+        wl = W.make_vortical_workload(n=(8, 8), dt_factor=100.0)
+    fr = capi.FR.from_workload(wl)
+    cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3)
+    q, st = fr.time_step(cfg, fr.to_dev(wl.dq), tableau=TABS[tab])
+    q = q.cpu().numpy()
+    assert st["nstages"] == 3 and all(s["converged"] for s in st["stages"])
+    kw = dict(tol=1e-10) if tab == "row3" else dict(tol=1e-10, eta=1e-3)
+    q_ref, so = _oracle_step(orc, wl, tab, **kw)
+    assert so.converged
+    upd = np.linalg.norm(q_ref - wl.dq)
+    d = np.linalg.norm(q - q_ref) / upd
+    print("%s %s: GPU %d FGMRES (stages %s), oracle %d; |q - q_ref| / |update| = %.2e"
+          % (tab, case, st["gmres_iters"], [s["gmres_iters"] for s in st["stages"]], so.gmres_iters, d))
+    assert d <= 1e-6
+
+
+@pytest.mark.parametrize("tab", ["esdirk3", "row3"])
+def test_time_step_config2(orc, tab):
+    """The full config-2 step converges in every stage; the first ESDIRK
+    stage equals the single-stage solve; ESDIRK3 and ROW3 (same order, same
+    stability function) land close together."""
+    require_gpu()
+    announce("time step %s config2" % tab)
+    wl = W.config2()
+    fr = capi.FR.from_workload(wl)
+    dq = fr.to_dev(wl.dq)
+    cfg = capi.stage_config_for(wl)
+    q, st = fr.time_step(cfg, dq, tableau=TABS[tab])
+    assert st["nstages"] == 3 and all(s["converged"] for s in st["stages"])
+    print("%s config2: %d FGMRES %s, %d PTC, set-up %.4f s, solve %.4f s"
+          % (tab, st["gmres_iters"], [s["gmres_iters"] for s in st["stages"]], st["ptc_iters"], st["t_setup"],
+             st["t_solve"]))
+    if tab == "esdirk3":
+        # the step's second stage is the single ESDIRK stage solve (a_21 = a_22 = gamma)
+        q2, _ = fr.solve_stage(cfg, dq)
+        assert st["stages"][0]["ptc_iters"] > 0
+        other, _ = fr.time_step(cfg, dq, tableau=capi.TAB_ROW3)
+    else:
+        other, _ = fr.time_step(cfg, dq, tableau=capi.TAB_ESDIRK3)
+    qn = q.cpu().numpy()
+    on = other.cpu().numpy()
+    upd = np.linalg.norm(qn - wl.dq)
+    d = np.linalg.norm(qn - on) / upd
+    print("ESDIRK3 vs ROW3 at config 2: |difference| / |update| = %.2e" % d)
+    assert d <= 0.05
+    # the stage solution state of ESDIRK stage 2 satisfies the oracle's stage equation
+    if tab == "esdirk3":
+        L0 = orc.Level(**wl.level_kwargs(wl.p0))
+        R0 = L0.residual(wl.dq)
+        g = capi.StageConfig().a_ii
+        b = wl.dq + g * wl.dt * R0
+        q2h = q2.cpu().numpy()
+        F = (q2h - b) / (g * wl.dt) - L0.residual(q2h)
+        assert np.linalg.norm(F) / np.linalg.norm(2 * R0) <= 1.5e-8
