@@ -69,13 +69,13 @@ def kernel_rates(fr, wl, dq_dev, reps=50):
     rq = fr.residual(0, dq_dev)
     r_out = fr.empty(0)
     t_r = _events_time(lambda: fr.residual(0, dq_dev, out=r_out), reps)
-    out["residual"] = dict(s_per_call=t_r, alg_bytes=16.0 * N, launches=3)
+    out["residual"] = dict(s_per_call=t_r, alg_bytes=16.0 * N, launches=2)
     v = torch.randn_like(dq_dev)
     v /= torch.linalg.norm(v)
     w = fr.empty(0)
     sig = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
     t_j = _events_time(lambda: fr.jvp(0, dq_dev, rq, v, sig, out=w), reps)
-    out["jvp"] = dict(s_per_call=t_j, alg_bytes=32.0 * N, launches=6)
+    out["jvp"] = dict(s_per_call=t_j, alg_bytes=32.0 * N, launches=4)
     # EJ apply on the fine level (factors of the last stage solve)
     y = fr.empty(0)
     t_e = _events_time(lambda: fr.ej_solve(0, v, out=y), reps)
@@ -125,8 +125,8 @@ def kernel_rates_3d(reps=20, nsets=4):
         b = nxt()
         fr.jvp(0, b["dq"], b["rq"], b["v"], sig, out=b["out"])
     out = {
-        "residual_3d": dict(s_per_call=_events_time(r_call, reps), alg_bytes=16.0 * N, launches=3),
-        "jvp_3d": dict(s_per_call=_events_time(j_call, reps), alg_bytes=32.0 * N, launches=6),
+        "residual_3d": dict(s_per_call=_events_time(r_call, reps), alg_bytes=16.0 * N, launches=2),
+        "jvp_3d": dict(s_per_call=_events_time(j_call, reps), alg_bytes=32.0 * N, launches=4),
     }
     for d in out.values():
         d["GBps"] = d["alg_bytes"] / d["s_per_call"] / 1e9
@@ -167,6 +167,47 @@ def stage_3d(steps=1):
                        "gamma 0.25 at dt = 100 dt_exp, FGMRES(30) to 1e-8, pMG p{3-2} n{2-2}, EJ blocks 320^2 / 135^2")
     fr.close()
     torch.cuda.empty_cache()
+    return out
+
+
+def time_steps():
+    """Full implicit time steps (every stage, EJ factors formed once at q^n)
+    of the 2D (config 2) and 3D (config 4) workloads with ESDIRK3 (4 stages,
+    3 implicit, PTC + inexact Newton per stage) and ROW3 (3 linear stages),
+    both order 3 and L-stable with the same diagonal, preconditioner in FP64
+    and in the BF16-storage form: DOF per second of step time, after one
+    warm-up step each."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    out = {}
+    for wname, mk, reps in (("config2", W.config2, 2), ("config4", W.config4, 1)):
+        wl = mk()
+        fr = capi.FR.from_workload(wl)
+        dq = fr.to_dev(wl.dq)
+        q = fr.empty(0)
+        res = {}
+        for pkey, prec in (("fp64", capi.PREC_FP64), ("bf16_storage", capi.PREC_BF16_STORE)):
+            for tkey, tab in (("esdirk3", capi.TAB_ESDIRK3), ("row3", capi.TAB_ROW3)):
+                cfg = capi.stage_config_for(wl, precision=prec)
+                fr.time_step(cfg, dq, tableau=tab, out=q)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    _, st = fr.time_step(cfg, dq, tableau=tab, out=q)
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t0) / reps
+                res["%s_%s" % (tkey, pkey)] = {
+                    "dof_per_s": wl.dof() / el, "s_per_step": el, "t_setup_s": st["t_setup"],
+                    "t_solve_s": st["t_solve"], "gmres_iters": st["gmres_iters"],
+                    "gmres_per_stage": [x["gmres_iters"] for x in st["stages"]], "ptc_iters": st["ptc_iters"]}
+            res["row3_vs_esdirk3_" + pkey] = (res["row3_" + pkey]["dof_per_s"] /
+                                              res["esdirk3_" + pkey]["dof_per_s"])
+        out[wname] = res
+        fr.close()
+        torch.cuda.empty_cache()
+    out["note"] = ("one full step at the workload's dt from its state; ESDIRK3 stages to ||F|| <= 1e-8 "
+                   "||F(q_{i-1})|| with eta 0.1, ROW3 stages by FGMRES to 1e-8; pMG p{p0-p0/2} n{2-2}")
     return out
 
 
@@ -277,6 +318,16 @@ def only_kernel(args):
     sig = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
     x = torch.randn_like(dq)
     y = fr.empty(0)
+    if args.only_kernel == "step":
+        # whole time steps (every stage, set-up included) with the requested tableau
+        tab = capi.TAB_ROW3 if args.tableau == "row3" else capi.TAB_ESDIRK3
+        for _ in range(args.reps):
+            _, st = fr.time_step(capi.stage_config_for(wl, precision=prec), dq, tableau=tab)
+            print("[bench] %s step: %d FGMRES %s, set-up %.3f s, solve %.3f s"
+                  % (args.tableau, st["gmres_iters"], [x["gmres_iters"] for x in st["stages"]], st["t_setup"],
+                     st["t_solve"]), file=sys.stderr)
+        torch.cuda.synchronize()
+        return
     if args.only_kernel == "stage":
         # whole stage solves (set-up included) in the requested precision
         for _ in range(args.reps):
@@ -317,12 +368,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the EJ-only comparison and kernel rates")
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
-    ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "ej_factor", "residual", "jvp", "stage"],
+    ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "ej_factor", "residual", "jvp", "stage", "step"],
                     help="profiling driver: set up the workload's state, launch one kernel family --reps times "
                          "and a 256 MiB device copy (counter calibration), print nothing else")
     ap.add_argument("--workload", default="config2", choices=["config2", "config4"],
                     help="workload of the --only-kernel driver")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--tableau", default="esdirk3", choices=["esdirk3", "row3"],
+                    help="time-step scheme of the --only-kernel step driver")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (N > 1 is not supported)",
@@ -441,6 +494,8 @@ def main():
         rates.update(kernel_rates_3d())
         print("[bench] 3D ROW stage", file=sys.stderr, flush=True)
         result["stage_3d"] = stage_3d()
+        print("[bench] full time steps, ESDIRK3 and ROW3", file=sys.stderr, flush=True)
+        result["time_step"] = time_steps()
         print("[bench] learned coarse correction: harvest, train, A/B", file=sys.stderr, flush=True)
         result["learned_coarse"] = learned_ab(wl)
         result["kernels"] = rates
