@@ -1,0 +1,97 @@
+"""Pins of the oracle's multi-level FAS V-cycle and of pMG as a nonlinear
+stage solver: two levels reproduce the two-level preconditioner bitwise; with
+a linear R a three-level cycle equals the closed-form recursive multigrid
+operator built from dense matrices; the nonlinear solver converges to the
+dense-Newton root of the stage equation."""
+import numpy as np
+import pytest
+
+from oracle import multilevel as ML
+from paper_2202_09733_amd import workloads as W
+from test_oracle_solver import _LinearLevel, _blocks_of, _state_matrix, _tiny, dense_jacobian, _dense_newton_stage
+
+
+def _level(orc, fine, p):
+    return orc.Level(dim=fine.dim, n=fine.n, h=fine.h, p=p, gamma=1.4, mu=1e-2, Pr=0.72, tau=0.1, qinf=fine.qinf)
+
+
+def test_two_levels_equal_the_two_level_preconditioner(orc):
+    fine, dq, rng = _tiny(orc, n=(4, 4), p=2, seed=21)
+    coarse = _level(orc, fine, 1)
+    sigma_D, sigma_S = 45.0, 60.0
+    fac0 = orc.lu_factor(fine.ej_blocks(dq, sigma_S))
+    fac1 = orc.lu_factor(coarse.ej_blocks(orc.restrict(dq, 2, 3, 2), sigma_S))
+    X = rng.standard_normal(fine.shape)
+    rq = fine.residual(dq)
+    for mode in (orc.SCALE_LITERAL, orc.SCALE_SCALED):
+        pm2 = orc.PMG(fine, coarse, fac0, fac1, orc.PMGParams(sigma_D=sigma_D, n0=2, n1=3, scale_mode=mode))
+        pm2.set_point(dq, rq)
+        pmL = ML.MultiPMG([fine, coarse], [fac0, fac1], ML.MultiPMGParams(sigma_D=sigma_D, n=(2, 3),
+                                                                            scale_mode=mode))
+        pmL.set_point(dq, rq)
+        assert np.array_equal(pm2.apply(X), pmL.apply(X))
+
+
+@pytest.mark.parametrize("n", [(2, 2, 2), (1, 2, 3), (2, 1, 4)])
+def test_three_levels_linear_is_recursive_multigrid(orc, n):
+    """With R linear on every level, the cycle is C_0 where C_l(r) = K_l r,
+    e += Pi C_{l+1}(Gamma (r - A_l e)), e += K_l (r - A_l e), and
+    C_{L-1} = K_{L-1}; K_l = n_l damped block-Jacobi sweeps from zero."""
+    fine, dq, rng = _tiny(orc, n=(3, 3), p=3, seed=22)
+    mid = _level(orc, fine, 2)
+    low = _level(orc, fine, 1)
+    q1 = orc.restrict(dq, 2, 4, 3)
+    q2 = orc.restrict(q1, 2, 3, 2)
+    Js = [dense_jacobian(fine, dq), dense_jacobian(mid, q1), dense_jacobian(low, q2)]
+    lev = [_LinearLevel(L, J) for L, J in zip((fine, mid, low), Js)]
+    sigma_D, sigma_S = 35.0, 50.0
+    facs = [orc.lu_factor(_blocks_of(J, L, sigma_S)) for J, L in zip(Js, (fine, mid, low))]
+    pm = ML.MultiPMG(lev, facs, ML.MultiPMGParams(sigma_D=sigma_D, n=n, scale_mode=orc.SCALE_LITERAL))
+    pm.set_point(np.zeros(fine.shape), np.zeros(fine.shape))
+    X = rng.standard_normal(fine.shape)
+    Y = pm.apply(X).reshape(-1)
+    # dense closed form
+    A, Bi = [], []
+    for J, L in zip(Js, (fine, mid, low)):
+        A.append(sigma_D * np.eye(L.N) - J)
+        B = np.zeros((L.N, L.N))
+        blk = _blocks_of(J, L, sigma_S)
+        for k in range(L.Ne):
+            idx = np.arange(L.nb) * L.Ne + k
+            B[np.ix_(idx, idx)] = blk[k]
+        Bi.append(np.linalg.inv(B))
+
+    def K(l):
+        S = np.zeros_like(A[l])
+        T = np.eye(A[l].shape[0])
+        for _ in range(n[l]):
+            S += T @ Bi[l]
+            T = T @ (np.eye(A[l].shape[0]) - Bi[l] @ A[l])
+        return S
+    pairs = [((fine, mid), 4, 3), ((mid, low), 3, 2)]
+    Gam, Pi = [], []
+    for (a, b), P0, P1 in pairs:
+        G1, P1m = orc.transfer1d(P0, P1)
+        Gam.append(_state_matrix(np.kron(G1, G1), (a, b)))
+        Pi.append(_state_matrix(np.kron(P1m, P1m), (b, a)))
+
+    def C(l, r):
+        Kl = K(l)
+        e = Kl @ r
+        if l == 2:
+            return e
+        e = e + Pi[l] @ C(l + 1, Gam[l] @ (r - A[l] @ e))
+        return e + Kl @ (r - A[l] @ e)
+    Yref = C(0, X.reshape(-1))
+    assert np.allclose(Y, Yref, rtol=0, atol=1e-11 * np.abs(Yref).max())
+
+
+@pytest.mark.parametrize("ps", [(2, 1), (3, 2, 1)])
+def test_pmg_nonlinear_solver_reaches_newton_root(orc, ps):
+    wl = W.make_bump_workload(n=(4, 4), p0=ps[0], p1=ps[1], Ma=0.2, dt_factor=3.0, seed=14, amp=5e-2)
+    levels = [orc.Level(**wl.level_kwargs(p)) for p in ps]
+    q, st = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=tuple([2] * (len(ps) - 1) + [4]), tol=1e-11)
+    assert st.converged, (st.vcycles, st.rel_res)
+    L0 = levels[0]
+    qref = _dense_newton_stage(L0, wl.dq, wl.dt, wl.a_ii, lambda x: dense_jacobian(L0, x))
+    assert np.linalg.norm(q - qref) <= 1e-8 * np.linalg.norm(qref - wl.dq)
