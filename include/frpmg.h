@@ -142,18 +142,25 @@ fr_status pmg_prolong(frpmg_ctx *ctx, int from, int to, const double *x, double 
 #define FR_SCALE_NORMALIZED 1 /* s = eps_p sigma_D / ||X||_2 */
 #define FR_SCALE_SCALED 2     /* s = eps_p sigma_D (1 + ||dq||_2) / ||X||_2, dq = the set point */
 
-/* Nonlinear pMG preconditioner parameters (Sec. 3.2). */
+/* Nonlinear pMG preconditioner parameters (Sec. 3.2).  The V-cycle runs
+ * over levels 0 .. L-1 of the context (L = levels, 0: all of them); every
+ * level but the coarsest takes n_l pre- and n_l post-sweeps around the
+ * correction from the level below (the two-level step of Sec. 3.1 applied
+ * recursively), the coarsest n_{L-1} sweeps: n{n0-n1} for two levels,
+ * n{n0-n1-n2} for three. */
 typedef struct {
     double sigma_D;   /* 1/dtau + 1/(a_ii dt) (ESDIRK) or 1/(a_ii dt) (ROW) */
     int n0, n1;       /* smoothing n{n0-n1} (Sec. 3.1) */
     int coarse_mode;  /* FR_COARSE_* */
     int scale_mode;   /* FR_SCALE_* */
     double eps_p;     /* scale for FR_SCALE_NORMALIZED */
+    int n2, n3;       /* sweeps on levels 2 and 3 (hierarchies of three and four levels) */
+    int levels;       /* levels the cycle uses (0: every level of the context; learned: 2) */
 } pmg_params;
 
 /* Set the linearisation point of the preconditioner: dq (level 0 state) and
- * rq = R_0(dq).  Restricts dq to level 1 and evaluates R_1 there.  The
- * pointers must stay valid until the next pmg_set_point. */
+ * rq = R_0(dq).  Restricts dq to every coarser level and evaluates R_l
+ * there.  The pointers must stay valid until the next pmg_set_point. */
 fr_status pmg_set_point(frpmg_ctx *ctx, const double *dq, const double *rq, fr_stream stream);
 
 /* y ~ A^{-1} x by one two-level FAS V-cycle on
@@ -198,7 +205,20 @@ typedef struct {
                           0: every kernel is launched from the host.  Both give bitwise identical results
                           (measured: no faster on MI355X).  Graphs are not used with the learned
                           preconditioner or while harvesting. */
+    int n2, n3;        /* pMG sweeps on levels 2 and 3 (see pmg_params) */
+    int pmg_levels;    /* levels of the pMG cycle (0: every level of the context) */
+    int solver;        /* FR_SOLVER_JFNK, or FR_SOLVER_PMG: ESDIRK stages solved by pMG V-cycles alone */
 } stage_params;
+
+/* FR_SOLVER_PMG (Sec. 3.1, pMG as the nonlinear solver; the baseline of
+ * Tabs. 2 and 4): each iteration applies one FAS V-cycle to X = -F(q) with
+ * sigma_D = 1/(a_ii dt) and literal scaling, so that the cycle's level-0
+ * equation is F(q + Y) = 0, and sets q <- q + Y; the smoothers take the
+ * pseudo-time step, blocks with sigma_S = 1/dtau + 1/(a_ii dt) formed at
+ * q^n.  Stops when ||F|| <= tol ||F(q^n)|| or after max_ptc cycles
+ * (ptc_iters counts the cycles, gmres_iters is 0). */
+#define FR_SOLVER_JFNK 0
+#define FR_SOLVER_PMG 1
 
 #define FR_MAX_NEWTON_LOG 128
 typedef struct {

@@ -51,7 +51,8 @@ class MeshDesc(ctypes.Structure):
 
 class PmgParams(ctypes.Structure):
     _fields_ = [("sigma_D", ctypes.c_double), ("n0", ctypes.c_int), ("n1", ctypes.c_int),
-                ("coarse_mode", ctypes.c_int), ("scale_mode", ctypes.c_int), ("eps_p", ctypes.c_double)]
+                ("coarse_mode", ctypes.c_int), ("scale_mode", ctypes.c_int), ("eps_p", ctypes.c_double),
+                ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("levels", ctypes.c_int)]
 
 
 class StageParams(ctypes.Structure):
@@ -62,7 +63,10 @@ class StageParams(ctypes.Structure):
                 ("n0", ctypes.c_int), ("n1", ctypes.c_int), ("eps", ctypes.c_double),
                 ("eps_mode", ctypes.c_int), ("scale_mode", ctypes.c_int), ("eps_p", ctypes.c_double),
                 ("skip_setup", ctypes.c_int), ("stall_window", ctypes.c_int), ("stall_ratio", ctypes.c_double),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int),
+                ("pmg_levels", ctypes.c_int), ("solver", ctypes.c_int)]
+
+SOLVER_JFNK, SOLVER_PMG = 0, 1
 
 
 class LccHarvestParams(ctypes.Structure):
@@ -216,6 +220,10 @@ class StageConfig:
     stall_window: int = 0
     stall_ratio: float = 0.0
     graphs: int = 0
+    n2: int = 2
+    n3: int = 2
+    pmg_levels: int = 0
+    solver: int = 0
 
     def to_c(self):
         return StageParams(**{f[0]: getattr(self, f[0]) for f in StageParams._fields_})
@@ -330,9 +338,10 @@ class FR:
         self._check("pmg_set_point", self.lib.pmg_set_point(self.ctx, _ptr(dq), _ptr(rq), _stream()))
 
     def pmg_apply(self, x, sigma_D, n0=2, n1=2, coarse_mode=COARSE_EJ, scale_mode=SCALE_SCALED, eps_p=1e-6,
-                  out=None):
+                  out=None, n2=2, n3=2, levels=0):
         out = self.empty(0) if out is None else out
-        prm = PmgParams(float(sigma_D), int(n0), int(n1), int(coarse_mode), int(scale_mode), float(eps_p))
+        prm = PmgParams(float(sigma_D), int(n0), int(n1), int(coarse_mode), int(scale_mode), float(eps_p),
+                        int(n2), int(n3), int(levels))
         self._check("pmg_precond_apply", self.lib.pmg_precond_apply(self.ctx, ctypes.byref(prm), _ptr(x),
                                                                     _ptr(out), _stream()))
         return out

@@ -375,9 +375,54 @@ void pmg_point(frpmg_ctx *ctx, const double *dq, const double *rq, hipStream_t s
     ctx->pt_q = dq;
     ctx->pt_rq = rq;
     HIPCHK(vec_dot(ctx, ctx->lv[0].N, dq, dq, ctx->scal + SC_PT_N2, s));
-    if (ctx->nlevels > 1) {
-        HIPCHK(transfer_apply(ctx, 0, true, dq, ctx->q1, s));
-        residual(ctx, 1, ctx->q1, ctx->r1, s);
+    for (int l = 1; l < ctx->nlevels; ++l) {
+        HIPCHK(transfer_apply(ctx, l - 1, true, l == 1 ? dq : ctx->mq[l - 1], ctx->mq[l], s));
+        residual(ctx, l, ctx->mq[l], ctx->mr[l], s);
+    }
+}
+
+int pmg_sweeps(const pmg_params &p, int l) {
+    return l == 0 ? p.n0 : l == 1 ? p.n1 : l == 2 ? p.n2 : p.n3;
+}
+
+// Levels l >= 1 of the FAS V-cycle (Sec. 3.1 applied recursively).  On entry:
+// Z0[l] = Gamma Y_{l-1}, cd[l] = Gamma G_{l-1}(Y_{l-1}) = -Gamma d_{l-1} and the
+// forcing S[l] = G_l(Z0; 0) + Gamma d_{l-1}, so that G_l(Z0; S) = cd[l].  On exit
+// Z[l] is the smoothed level-l solution.  G_l(Z; S) = sigma_D Z - [R_l(q_l + Z)
+// - R_l(q_l)] - S.
+void coarse_cycle(frpmg_ctx *ctx, const pmg_params &p, int l, int nlev, hipStream_t s, Counters *cnt) {
+    const Scal one{1.0, nullptr};
+    const int n = pmg_sweeps(p, l);
+    REQUIRE(n >= 1, "every coarse level needs at least one sweep (n1, n2, n3 >= 1)");
+    REQUIRE(ctx->lv[l].inv_prec >= 0, "a coarse level has no EJ factors");
+    long &R = cnt->R1;  // every coarse level counts as coarse
+    long &E = cnt->E1;
+    double *Z0 = ctx->mZ0[l], *Z = ctx->mZ[l], *S = ctx->mS[l], *G = ctx->mG[l], *cd = ctx->md[l];
+    // the first sweep starts from Z0, where G_l = cd: Z = Z0 - B_l^{-1} cd
+    HIPCHK(ej_apply_ex(ctx, l, cd, -1.0, 1.0, Z0, one, Z, s));
+    E++;
+    for (int it = 1; it < n; ++it) {
+        residual_lin(ctx, l, ctx->mq[l], Z, one, ctx->mr[l], p.sigma_D, S, G, s);
+        R++;
+        HIPCHK(ej_apply(ctx, l, G, -1.0, 1.0, Z, s));
+        E++;
+    }
+    if (l == nlev - 1) return;
+    // defect, restriction and FAS forcing of level l + 1
+    residual_lin(ctx, l, ctx->mq[l], Z, one, ctx->mr[l], p.sigma_D, S, G, s);
+    R++;
+    HIPCHK(transfer_restrict2(ctx, l, Z, ctx->mZ0[l + 1], G, ctx->md[l + 1], s));
+    residual_lin(ctx, l + 1, ctx->mq[l + 1], ctx->mZ0[l + 1], one, ctx->mr[l + 1], p.sigma_D, ctx->md[l + 1],
+                 ctx->mS[l + 1], s);
+    cnt->R1++;
+    coarse_cycle(ctx, p, l + 1, nlev, s, cnt);
+    // Z += Pi (Z_{l+1} - Z0_{l+1}), then post-smoothing
+    HIPCHK(transfer_apply(ctx, l, false, ctx->mZ[l + 1], Z, s, ctx->mZ0[l + 1], true));
+    for (int it = 0; it < n; ++it) {
+        residual_lin(ctx, l, ctx->mq[l], Z, one, ctx->mr[l], p.sigma_D, S, G, s);
+        R++;
+        HIPCHK(ej_apply(ctx, l, G, -1.0, 1.0, Z, s));
+        E++;
     }
 }
 
@@ -390,8 +435,10 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
     const size_t N0 = L0.N;
     const bool coarse = p.coarse_mode != FR_COARSE_NONE;
     const bool learned = p.coarse_mode == FR_COARSE_LEARNED;
+    const int nlev = learned ? 2 : (p.levels > 0 ? p.levels : ctx->nlevels);
     if (coarse) {
         REQUIRE(ctx->nlevels > 1, "pMG needs two levels");
+        REQUIRE(nlev >= 2 && nlev <= ctx->nlevels, "the cycle's levels exceed the context's");
         if (learned) {
             REQUIRE(ctx->lcc && ctx->lcc->scales_set, "the learned correction has no trained network");
         } else {
@@ -458,16 +505,10 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
         // FAS forcing S1 = G1(Z0) + Gamma d  with G1(Z) = sigma Z - (R1(q1 + Z) - R1(q1))
         residual_lin(ctx, 1, ctx->q1, ctx->cZ0, one, ctx->r1, p.sigma_D, ctx->cd, ctx->cS, s);
         cnt->R1++;
-        // coarse sweeps; the first uses G1(Z0) - S1 = -Gamma d = cd: Z = Z0 - B1^{-1} cd
-        HIPCHK(ej_apply_ex(ctx, 1, ctx->cd, -1.0, 1.0, ctx->cZ0, one, ctx->cZ, s));
-        cnt->E1++;
-        for (int it = 1; it < p.n1; ++it) {
-            residual_lin(ctx, 1, ctx->q1, ctx->cZ, one, ctx->r1, p.sigma_D, ctx->cS, ctx->cG, s);
-            cnt->R1++;
-            HIPCHK(ej_apply(ctx, 1, ctx->cG, -1.0, 1.0, ctx->cZ, s));
-            cnt->E1++;
-        }
-        if (ctx->lcc && ctx->lcc->harvesting && ctx->lcc->count < ctx->lcc->cap) {
+        // coarse levels (recursively below level 1); the first level-1 sweep uses
+        // G1(Z0) - S1 = -Gamma d = cd
+        coarse_cycle(ctx, p, 1, nlev, s, cnt);
+        if (nlev == 2 && ctx->lcc && ctx->lcc->harvesting && ctx->lcc->count < ctx->lcc->cap) {
             // record (Gamma d, correction after target_sweeps coarse sweeps) for a rotating subset
             Lcc &Lc = *ctx->lcc;
             HIPCHK(hipMemcpyAsync(Lc.Cuse, ctx->cZ, N1 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -773,7 +814,8 @@ struct StageSolver {
     frpmg_ctx *ctx;
     stage_params P;
     size_t N;
-    bool esdirk, pmg, learned, use_graphs;
+    bool esdirk, pmg, learned, use_graphs, nonlinear_pmg;
+    int nlev;
     double sigma_A, sigma_S;
     pmg_params pp;
     Counters cnt;
@@ -792,11 +834,19 @@ struct StageSolver {
         N = ctx->lv[0].N;
         ensure_krylov(ctx, P.m);
         esdirk = P.scheme == FR_SCHEME_ESDIRK;
+        REQUIRE(P.solver == FR_SOLVER_JFNK || P.solver == FR_SOLVER_PMG, "unknown solver");
+        nonlinear_pmg = P.solver == FR_SOLVER_PMG;
+        REQUIRE(!nonlinear_pmg || (esdirk && pmg && !learned), "the pMG nonlinear solver takes ESDIRK stages "
+                                                               "with the plain pMG hierarchy");
         const double dtau = (P.dtau > 0) ? P.dtau : P.dt;
-        // shifts: sigma_A of the outer operator, sigma_S of the smoother blocks
-        sigma_A = esdirk ? 1.0 / dtau + 1.0 / (P.a_ii * P.dt) : 1.0 / (P.a_ii * P.dt);
+        // shifts: sigma_A of the outer operator, sigma_S of the smoother blocks; the pMG
+        // nonlinear solver's cycles target the stage equation itself (no outer pseudo-time)
+        sigma_A = (esdirk && !nonlinear_pmg) ? 1.0 / dtau + 1.0 / (P.a_ii * P.dt) : 1.0 / (P.a_ii * P.dt);
         sigma_S = 1.0 / dtau + sigma_A;
-        pp = pmg_params{sigma_A, P.n0, P.n1, learned ? FR_COARSE_LEARNED : FR_COARSE_EJ, P.scale_mode, P.eps_p};
+        nlev = pmg ? (learned ? 2 : (P.pmg_levels > 0 ? P.pmg_levels : ctx->nlevels)) : 1;
+        REQUIRE(nlev <= ctx->nlevels, "pmg_levels exceeds the context's levels");
+        pp = pmg_params{sigma_A, P.n0, P.n1, learned ? FR_COARSE_LEARNED : FR_COARSE_EJ,
+                        nonlinear_pmg ? FR_SCALE_LITERAL : P.scale_mode, P.eps_p, P.n2, P.n3, nlev};
         stall.active = learned;
         if (P.stall_window > 0) stall.window = P.stall_window;
         if (P.stall_ratio > 0) stall.ratio = P.stall_ratio;
@@ -811,15 +861,46 @@ struct StageSolver {
     void setup(const double *dq_n, hipStream_t s) {
         if (pmg) {
             ej_factor_impl(ctx, 0, dq_n, sigma_S, P.precision, s);
-            // the coarse blocks are linearised at Gamma q^n
-            HIPCHK(transfer_apply(ctx, 0, true, dq_n, ctx->q1, s));
-            ej_factor_impl(ctx, 1, ctx->q1, sigma_S, P.precision, s);
+            // the coarse blocks are linearised at the restricted q^n
+            for (int l = 1; l < nlev; ++l) {
+                HIPCHK(transfer_apply(ctx, l - 1, true, l == 1 ? dq_n : ctx->mq[l - 1], ctx->mq[l], s));
+                ej_factor_impl(ctx, l, ctx->mq[l], sigma_S, P.precision, s);
+                cnt.R1 += 1 + ctx->lv[l].nb;
+            }
         } else {
             ej_factor_impl(ctx, 0, dq_n, sigma_A, P.precision, s);
         }
         // one base evaluation plus the element-local columns (nb evaluations' worth)
         cnt.R0 += 1 + ctx->lv[0].nb;
-        if (pmg) cnt.R1 += 1 + ctx->lv[1].nb;
+    }
+
+    // pMG as the nonlinear solver of an ESDIRK stage: V-cycles on F(q + Y) = 0
+    fr_status pmg_nonlinear_solve(const double *b, double *q, double *rq, stage_stats *st, hipStream_t s) {
+        double *F = ctx->sF, *dx = ctx->sdx;
+        const double c = 1.0 / (P.a_ii * P.dt);
+        HIPCHK(vec_stage_F(N, q, b, c, rq, F, s));
+        const double f0 = host_norm(ctx, N, F, s);
+        st->res0 = f0;
+        double fn = f0;
+        fr_status status = std::isfinite(f0) ? FR_OK : FR_ENONFINITE;
+        while (status == FR_OK && fn > P.tol * f0 && st->ptc_iters < P.max_ptc) {
+            pmg_point(ctx, q, rq, s);
+            cnt.R1 += nlev - 1;
+            HIPCHK(vec_axpby(N, Scal{0.0, nullptr}, nullptr, Scal{-1.0, nullptr}, F, s));  // F <- -F
+            pmg_apply_impl(ctx, pp, F, dx, s, &cnt);
+            HIPCHK(vec_axpby(N, Scal{1.0, nullptr}, dx, Scal{1.0, nullptr}, q, s));
+            residual(ctx, 0, q, rq, s);
+            cnt.R0++;
+            HIPCHK(vec_stage_F(N, q, b, c, rq, F, s));
+            fn = host_norm(ctx, N, F, s);
+            st->ptc_iters++;
+            if (!std::isfinite(fn)) status = FR_ENONFINITE;
+        }
+        st->res = fn;
+        st->rel_res = f0 > 0 ? fn / f0 : 0.0;
+        st->converged = (fn <= P.tol * f0) ? 1 : 0;
+        if (status == FR_OK && !st->converged) status = FR_ENOCONV;
+        return status;
     }
 
     void prec(const double *v, double *z, hipStream_t s) {
@@ -846,6 +927,7 @@ struct StageSolver {
     // - R(q) = 0 by pseudo-transient continuation with inexact Newton from q
     // (in/out, rq = R(q) in/out) until ||F|| <= tol ||F(q_start)||.
     fr_status esdirk_solve(const double *b, double *q, double *rq, stage_stats *st, hipStream_t s) {
+        if (nonlinear_pmg) return pmg_nonlinear_solve(b, q, rq, st, s);
         double *F = ctx->sF, *dx = ctx->sdx;
         const double c = 1.0 / (P.a_ii * P.dt);
         HIPCHK(vec_stage_F(N, q, b, c, rq, F, s));
@@ -857,7 +939,7 @@ struct StageSolver {
         while (status == FR_OK && fn > P.tol * f0 && st->ptc_iters < P.max_ptc) {
             if (pmg) {
                 pmg_point(ctx, q, rq, s);
-                cnt.R1++;
+                cnt.R1 += ctx->nlevels - 1;
             }
             HIPCHK(vec_axpby(N, Scal{0.0, nullptr}, nullptr, Scal{-1.0, nullptr}, F, s));  // F <- -F
             HIPCHK(vec_dot(ctx, N, q, q, ctx->scal + SC_DQ_N2, s));
@@ -964,7 +1046,7 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
         S.cnt.R0++;
         if (S.pmg) {
             pmg_point(ctx, dq_n, R0, s);
-            S.cnt.R1++;
+            S.cnt.R1 += ctx->nlevels - 1;
         }
         status = S.row_solve(dq_n, R0, R0, out, st, s);
     }
@@ -1089,7 +1171,7 @@ void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double
         S.cnt.R0++;
         if (S.pmg) {
             pmg_point(ctx, dq_n, R0, s);
-            S.cnt.R1++;
+            S.cnt.R1 += ctx->nlevels - 1;
         }
         for (int i = 0; i < 3 && status == FR_OK; ++i) {
             // rhs_i = R(q^n + sum_j a_ij Y_j) + (1/dt) sum_j c_ij Y_j
@@ -1151,6 +1233,10 @@ void destroy_all(frpmg_ctx *ctx) {
         dfree(L.touch);
         dfree(L.colperm);
         dfree(L.r0);
+    }
+    for (int l = 2; l < FR_MAX_LEVELS; ++l) {  // level 1 is freed through its names below
+        double *lb[] = {ctx->mq[l], ctx->mr[l], ctx->mZ0[l], ctx->mZ[l], ctx->mS[l], ctx->mG[l], ctx->md[l]};
+        for (double *b : lb) dfree(b);
     }
     for (int a = 0; a < 3; ++a) dfree(ctx->inv2h[a]);
     dfree(ctx->red_partial);
@@ -1248,15 +1334,24 @@ fr_status fr_create(const fr_mesh_desc *d, frpmg_ctx **out) {
         ctx->wY = dalloc(ctx, N0);
         ctx->wG = dalloc(ctx, N0);
         ctx->wXs = dalloc(ctx, N0);
+        for (int l = 1; l < d->nlevels; ++l) {
+            const size_t Nl = ctx->lv[l].N;
+            ctx->mq[l] = dalloc(ctx, Nl);
+            ctx->mr[l] = dalloc(ctx, Nl);
+            ctx->mZ0[l] = dalloc(ctx, Nl);
+            ctx->mZ[l] = dalloc(ctx, Nl);
+            ctx->mS[l] = dalloc(ctx, Nl);
+            ctx->mG[l] = dalloc(ctx, Nl);
+            ctx->md[l] = dalloc(ctx, Nl);
+        }
         if (d->nlevels > 1) {
-            const size_t N1 = ctx->lv[1].N;
-            ctx->q1 = dalloc(ctx, N1);
-            ctx->r1 = dalloc(ctx, N1);
-            ctx->cZ0 = dalloc(ctx, N1);
-            ctx->cZ = dalloc(ctx, N1);
-            ctx->cS = dalloc(ctx, N1);
-            ctx->cG = dalloc(ctx, N1);
-            ctx->cd = dalloc(ctx, N1);
+            ctx->q1 = ctx->mq[1];
+            ctx->r1 = ctx->mr[1];
+            ctx->cZ0 = ctx->mZ0[1];
+            ctx->cZ = ctx->mZ[1];
+            ctx->cS = ctx->mS[1];
+            ctx->cG = ctx->mG[1];
+            ctx->cd = ctx->md[1];
         }
         HIPCHK(hipDeviceSynchronize());
     });

@@ -151,6 +151,9 @@ struct frpmg_ctx {
     double *q1 = nullptr, *r1 = nullptr;     // restricted point and R_1 there
     double *wY = nullptr, *wG = nullptr, *wXs = nullptr;
     double *cZ0 = nullptr, *cZ = nullptr, *cS = nullptr, *cG = nullptr, *cd = nullptr;
+    // V-cycle work vectors of every coarse level l >= 1 (level 1: the names above)
+    double *mq[FR_MAX_LEVELS] = {}, *mr[FR_MAX_LEVELS] = {}, *mZ0[FR_MAX_LEVELS] = {}, *mZ[FR_MAX_LEVELS] = {};
+    double *mS[FR_MAX_LEVELS] = {}, *mG[FR_MAX_LEVELS] = {}, *md[FR_MAX_LEVELS] = {};
     const double *pt_q = nullptr, *pt_rq = nullptr;
     // Krylov workspaces (allocated at the first stage solve)
     int kdim = 0;
