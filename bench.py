@@ -211,6 +211,54 @@ def time_steps():
     return out
 
 
+def hierarchies():
+    """Other p-hierarchies and pMG as the nonlinear solver (one stage, set-up
+    included, after a warm-up): config 2 (ESDIRK stage) with JFNK-pMG
+    p{4-2} and p{4-2-1} and with the pMG nonlinear solver p{4-2} and p{4-2-1}
+    (to 1e-8 and to 1e-4 of ||F(q^n)||); config 4 (ROW stage) with GMRES-pMG
+    p{3-2} and p{3-2-1}."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    out = {}
+    for wname, mk, levels, runs in (
+            ("config2", W.config2, [4, 2, 1], (
+                ("jfnk_pmg_p42", dict(pmg_levels=2)),
+                ("jfnk_pmg_p421", dict(pmg_levels=3)),
+                ("pmg_solver_p42", dict(pmg_levels=2, solver=1, max_ptc=1000)),
+                ("pmg_solver_p421", dict(pmg_levels=3, solver=1, max_ptc=1000)),
+                ("jfnk_pmg_p42_tol1e-4", dict(pmg_levels=2, tol=1e-4)),
+                ("pmg_solver_p42_tol1e-4", dict(pmg_levels=2, solver=1, tol=1e-4, max_ptc=1000)))),
+            ("config4", W.config4, [3, 2, 1], (
+                ("gmres_pmg_p32", dict(pmg_levels=2)),
+                ("gmres_pmg_p321", dict(pmg_levels=3))))):
+        wl = mk()
+        fr = capi.FR.from_workload(wl, levels=levels)
+        dq = fr.to_dev(wl.dq)
+        q = fr.empty(0)
+        res = {}
+        for key, kw in runs:
+            cfg = capi.stage_config_for(wl, **kw)
+            try:
+                fr.solve_stage(cfg, dq, out=q, raise_on_noconv=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = fr.solve_stage(cfg, dq, out=q, raise_on_noconv=False)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                res[key] = {"dof_per_s": wl.dof() / el, "s_per_stage": el, "ptc_or_vcycles": st["ptc_iters"],
+                            "gmres_iters": st["gmres_iters"], "rel_res": st["rel_res"],
+                            "converged": st["converged"]}
+            except capi.FRError as ex:
+                res[key] = {"failed": str(ex)}
+        out[wname] = res
+        fr.close()
+        torch.cuda.empty_cache()
+    out["note"] = ("stage tolerance 1e-8 unless marked; the pMG nonlinear solver smooths with dtau = dt and "
+                   "counts V-cycles in ptc_or_vcycles; a failure entry records a diverged solve")
+    return out
+
+
 def learned_ab(wl, steps=3):
     """The learned coarse correction on the config-2 mesh: pairs harvested by
     the solver from plain-pMG stages and from V-cycles on random directions
@@ -496,6 +544,8 @@ def main():
         result["stage_3d"] = stage_3d()
         print("[bench] full time steps, ESDIRK3 and ROW3", file=sys.stderr, flush=True)
         result["time_step"] = time_steps()
+        print("[bench] p-hierarchies and the pMG nonlinear solver", file=sys.stderr, flush=True)
+        result["hierarchies"] = hierarchies()
         print("[bench] learned coarse correction: harvest, train, A/B", file=sys.stderr, flush=True)
         result["learned_coarse"] = learned_ab(wl)
         result["kernels"] = rates
