@@ -1280,6 +1280,10 @@ fr_status fr_create(const fr_mesh_desc *d, frpmg_ctx **out) {
         }
         REQUIRE(ne < (1L << 30), "too many elements");
         m.Ne = (int)ne;
+        for (int a = 0; a < 3; ++a) {
+            REQUIRE((unsigned long long)ne * (unsigned long long)m.n[a] < (1ULL << 40), "mesh too large");
+            m.rcp[a] = ((1ULL << 40) + (unsigned long long)m.n[a] - 1) / (unsigned long long)m.n[a];
+        }
         for (int a = 0; a < d->dim; ++a) {
             std::vector<double> ih(d->n[a]);
             for (int i = 0; i < d->n[a]; ++i) {

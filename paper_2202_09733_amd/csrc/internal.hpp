@@ -45,6 +45,7 @@ struct MeshK {
     int n[3];
     int Ne;
     const double *inv2h[3];  // device: 2 / h per axis index
+    unsigned long long rcp[3];  // ceil(2^40 / n[a]): k / n[a] = (k rcp[a]) >> 40 while k n[a] < 2^40
 };
 
 // Scalar that lives either on the host (p == nullptr) or in device memory.

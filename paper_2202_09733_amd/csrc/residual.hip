@@ -102,11 +102,17 @@ struct Shape {
     }
 };
 
+// k / n[a] by the rounded-up reciprocal (exact while k n[a] < 2^40, which
+// context creation checks): a multiply instead of a runtime division
+__device__ __forceinline__ int div_axis(const MeshK &m, int k, int a) {
+    return (int)(((unsigned long long)(unsigned)k * m.rcp[a]) >> 40);
+}
+
 __device__ __forceinline__ void coords(const MeshK &m, int k, int c[3]) {
-    c[0] = k % m.n[0];
-    int r = k / m.n[0];
-    c[1] = r % m.n[1];
-    c[2] = r / m.n[1];
+    const int r = div_axis(m, k, 0);
+    c[0] = k - r * m.n[0];
+    c[2] = div_axis(m, r, 1);
+    c[1] = r - c[2] * m.n[1];
 }
 
 __device__ __forceinline__ int neighbour(const MeshK &m, int k, int a, int s) {
