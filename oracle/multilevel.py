@@ -28,7 +28,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import SCALE_LITERAL, SCALE_NORMALIZED, SCALE_SCALED, lu_factor, lu_solve, prolong, restrict
+from . import (EPS_SCALED, SCALE_LITERAL, SCALE_NORMALIZED, SCALE_SCALED, StageStats, fgmres, jvp, lu_factor,
+               lu_solve, prolong, restrict)
+from . import mbnk as MB
 
 
 @dataclass
@@ -41,11 +43,18 @@ class MultiPMGParams:
 
 class MultiPMG:
     """levels: Level objects, finest first; facs: LU factors of each level's
-    blocks B_l = sigma_S I - dR_l/dq."""
+    blocks B_l = sigma_S I - dR_l/dq.  coarse_ilu: when given (an
+    ``mbnk.ILU0`` of the coarsest level's assembled sigma_S I - J), the
+    coarsest level smooths with MBNK sweeps instead of EJ sweeps."""
 
-    def __init__(self, levels, facs, prm: MultiPMGParams):
+    def __init__(self, levels, facs, prm: MultiPMGParams, coarse_ilu=None):
         assert len(levels) == len(facs) == len(prm.n) and len(levels) >= 1
-        self.levels, self.facs, self.prm = levels, facs, prm
+        self.levels, self.facs, self.prm, self.coarse_ilu = levels, facs, prm, coarse_ilu
+
+    def _smooth_step(self, l, G):
+        if self.coarse_ilu is not None and l == len(self.levels) - 1 and l > 0:
+            return MB.mbnk_sweep(self.coarse_ilu, G)
+        return lu_solve(self.facs[l], G)
 
     def set_point(self, dq: np.ndarray, rq: np.ndarray):
         self.q = [dq]
@@ -66,7 +75,7 @@ class MultiPMG:
         Y = Y0.copy()
         for it in range(n):
             G = G0 if it == 0 else self._G(l, Y, S)
-            Y = Y - lu_solve(self.facs[l], G)
+            Y = Y - self._smooth_step(l, G)
         if l == len(self.levels) - 1:
             return Y
         a, b = self.levels[l], self.levels[l + 1]
@@ -111,6 +120,55 @@ class NLStats:
     res: float = float("nan")
     rel_res: float = float("nan")
     converged: bool = False
+
+
+def coarse_mbnk(levels, dq_n, sigma_S):
+    """ILU0 of the coarsest level's assembled sigma_S I - J at the restricted q^n."""
+    q = dq_n
+    for l in range(1, len(levels)):
+        a, b = levels[l - 1], levels[l]
+        q = restrict(q, a.dim, a.P, b.P)
+    return MB.ilu0(MB.assemble(levels[-1], q, sigma_S))
+
+
+def esdirk_stage_ml(levels, dq_n, dt, a_ii, n=None, coarse="ej", eta=0.1, m=30, max_restarts=20, tol=1e-8,
+                    max_ptc=100, eps=1e-6, eps_mode=EPS_SCALED, dtau=None):
+    """The second ESDIRK stage as ``oracle.esdirk_stage`` (PTC + inexact Newton +
+    FGMRES) with the multi-level pMG preconditioner; coarse = "ej" or "mbnk"
+    (the coarsest level's smoother)."""
+    dtau = dt if dtau is None else dtau
+    n = tuple(n) if n is not None else tuple([2] * len(levels))
+    sigma_A = 1.0 / dtau + 1.0 / (a_ii * dt)
+    sigma_S = 1.0 / dtau + sigma_A
+    facs = hierarchy_factors(levels, dq_n, sigma_S)
+    ilu = coarse_mbnk(levels, dq_n, sigma_S) if coarse == "mbnk" else None
+    pm = MultiPMG(levels, facs, MultiPMGParams(sigma_D=sigma_A, n=n), coarse_ilu=ilu)
+    fine = levels[0]
+    R0 = fine.residual(dq_n)
+    b = dq_n + (a_ii * dt) * R0
+    q, rq = dq_n.copy(), R0
+    F = (q - b) / (a_ii * dt) - rq
+    st = StageStats()
+    f0 = float(np.linalg.norm(F))
+    st.res0 = f0
+    fn = f0
+    while fn > tol * f0 and st.ptc_iters < max_ptc:
+        pm.set_point(q, rq)
+        A = lambda v, q=q, rq=rq: jvp(fine, q, rq, v, sigma_A, eps, eps_mode)
+        dx, ks = fgmres(A, pm.apply, -F, m=m, tol=eta, max_restarts=max_restarts)
+        st.gmres_iters += ks.iters
+        st.gmres_per_newton.append(ks.iters)
+        q = q + dx
+        rq = fine.residual(q)
+        F = (q - b) / (a_ii * dt) - rq
+        fn = float(np.linalg.norm(F))
+        st.ptc_iters += 1
+        if not np.isfinite(fn):
+            break
+    st.res = fn
+    st.rel_res = fn / f0 if f0 > 0 else 0.0
+    st.converged = bool(fn <= tol * f0)
+    return q, st
 
 
 def pmg_nonlinear_stage(levels, dq_n, dt, a_ii, a_i1=None, n=None, dtau=None, tol=1e-8, max_vcycles=500):
