@@ -12,8 +12,8 @@
  *  - Array arguments are DEVICE pointers owned by the caller, contiguous,
  *    FP64, unless stated otherwise.  The library owns only its internal
  *    workspaces (EJ factors, Krylov basis, multigrid buffers), allocated at
- *    fr_create, at the first ej_factor of a level, or at the first
- *    gmres_solve_stage; no other call allocates.
+ *    fr_create, at the first ej_factor of a level, at the first mbnk_factor
+ *    of a level, or at the first gmres_solve_stage; no other call allocates.
  *  - State arrays hold the DEVIATION dq = q - q_inf of the conservative
  *    variables (rho, rho u, rho v, [rho w], E) from the reference state q_inf
  *    given at creation, in the layout [nvar][npts][nelem]: element index
@@ -127,6 +127,43 @@ fr_status ej_solve(frpmg_ctx *ctx, int level, const double *r, double *y, fr_str
  * k nb nb + col nb + row), converted to FP64.  Synchronous. */
 fr_status ej_get_inverse(frpmg_ctx *ctx, int level, double *host_out);
 
+/* ------------------------------------------------------------------------
+ * Matrix-based Newton-Krylov (MBNK) smoother (Sec. 3.2): one sweep solves
+ * the linearised pseudo-time step A delta = G, A = sigma I - dR/dq, by GMRES
+ * (at most 5 iterations, relative tolerance 1e-1 by default) right-
+ * preconditioned by ILU0, and sets Y <- Y - delta.  The library's reading:
+ *  - A keeps, for every element k, the diagonal block and the 2 dim blocks
+ *    that couple k to its face neighbours (R_k also depends on edge-diagonal
+ *    neighbours through the LDG gradient; those blocks are dropped).  Each
+ *    block column is a one-sided difference with the EJ step, elements of one
+ *    colour (at least three apart along an axis) perturbed together.
+ *  - ILU0 is taken in red-black element order (colour = parity of the
+ *    element's coordinate sum).  With face couplings only this keeps D_r on
+ *    red elements and U_b = D_b - sum_r O_br D_r^{-1} O_rb on black ones.
+ * One factorisation per context, for one level.
+ *
+ * mbnk_factor: assemble A at dq_lin (that level's state) and factor it.
+ *   Needs an even element count >= 4 per axis and blocks of at most 128
+ *   unknowns (FR_EINVAL otherwise).  Allocates its workspace at the first
+ *   call for a level (the blocks take (3 + 2 dim) Ne nb^2 doubles, the
+ *   formation batch up to 128 MiB per buffer).  Synchronises the stream;
+ *   FR_ESINGULAR on a zero pivot.
+ * mbnk_matvec: y = A x.  mbnk_ilu_solve: z = (L U)^{-1} r.
+ * mbnk_solve: delta ~ A^{-1} g by one GMRES(maxit <= 8) cycle from zero to
+ *   relative tolerance tol (convergence decided on the device, no host
+ *   synchronisation).  g may alias delta.
+ * Vectors are that level's size; matvec and ilu_solve outputs must not alias
+ * their inputs.
+ * mbnk_get_blocks: copy the assembled blocks to host buffers (either may be
+ *   null): D = [Ne][nb][nb], O = [Ne][2 dim][nb][nb], blocks column-major,
+ *   O's slot of the face neighbour across axis a on side s = -1 / +1 being
+ *   2 a + (s > 0).  Synchronous. */
+fr_status mbnk_factor(frpmg_ctx *ctx, int level, const double *dq_lin, double sigma, fr_stream stream);
+fr_status mbnk_matvec(frpmg_ctx *ctx, const double *x, double *y, fr_stream stream);
+fr_status mbnk_ilu_solve(frpmg_ctx *ctx, const double *r, double *z, fr_stream stream);
+fr_status mbnk_solve(frpmg_ctx *ctx, const double *g, double *delta, double tol, int maxit, fr_stream stream);
+fr_status mbnk_get_blocks(frpmg_ctx *ctx, double *host_D, double *host_O);
+
 /* Restriction Gamma (L2 projection, Sec. 3.1 Eq. (projection)) from level
  * `from` to the coarser level `to` = from + 1, and prolongation Pi
  * (Eq. (prolongation)) from level `from` to the finer level `to` = from - 1,
@@ -137,6 +174,8 @@ fr_status pmg_prolong(frpmg_ctx *ctx, int from, int to, const double *x, double 
 #define FR_COARSE_NONE 0    /* fine-level smoothing only (n0 pre-sweeps) */
 #define FR_COARSE_EJ 1      /* two-level V-cycle with EJ smoothing on level 1 */
 #define FR_COARSE_LEARNED 2 /* coarse sweeps replaced by the learned correction */
+#define FR_COARSE_MBNK 3    /* as FR_COARSE_EJ, with MBNK sweeps on the coarsest level of the cycle (the
+                               level of the last mbnk_factor) */
 
 #define FR_SCALE_LITERAL 0    /* s = 1 */
 #define FR_SCALE_NORMALIZED 1 /* s = eps_p sigma_D / ||X||_2 */
@@ -156,6 +195,8 @@ typedef struct {
     double eps_p;     /* scale for FR_SCALE_NORMALIZED */
     int n2, n3;       /* sweeps on levels 2 and 3 (hierarchies of three and four levels) */
     int levels;       /* levels the cycle uses (0: every level of the context; learned: 2) */
+    int mbnk_maxit;   /* FR_COARSE_MBNK: GMRES iterations per sweep, 1..8 (0: 5, Sec. 3.2) */
+    double mbnk_tol;  /* FR_COARSE_MBNK: relative GMRES tolerance per sweep (0: 1e-1, Sec. 3.2) */
 } pmg_params;
 
 /* Set the linearisation point of the preconditioner: dq (level 0 state) and
@@ -208,7 +249,14 @@ typedef struct {
     int n2, n3;        /* pMG sweeps on levels 2 and 3 (see pmg_params) */
     int pmg_levels;    /* levels of the pMG cycle (0: every level of the context) */
     int solver;        /* FR_SOLVER_JFNK, or FR_SOLVER_PMG: ESDIRK stages solved by pMG V-cycles alone */
+    int coarse_smoother; /* FR_SMOOTHER_EJ, or FR_SMOOTHER_MBNK on the coarsest level of the pMG cycle
+                            (its operator assembled by mbnk_factor at the restricted q^n) */
+    int mbnk_maxit;    /* MBNK GMRES iterations per sweep (0: 5) */
+    double mbnk_tol;   /* MBNK relative GMRES tolerance per sweep (0: 1e-1) */
 } stage_params;
+
+#define FR_SMOOTHER_EJ 0
+#define FR_SMOOTHER_MBNK 1
 
 /* FR_SOLVER_PMG (Sec. 3.1, pMG as the nonlinear solver; the baseline of
  * Tabs. 2 and 4): each iteration applies one FAS V-cycle to X = -F(q) with

@@ -171,17 +171,21 @@ def esdirk_stage_ml(levels, dq_n, dt, a_ii, n=None, coarse="ej", eta=0.1, m=30, 
     return q, st
 
 
-def pmg_nonlinear_stage(levels, dq_n, dt, a_ii, a_i1=None, n=None, dtau=None, tol=1e-8, max_vcycles=500):
+def pmg_nonlinear_stage(levels, dq_n, dt, a_ii, a_i1=None, n=None, dtau=None, tol=1e-8, max_vcycles=500,
+                        coarse="ej"):
     """Second ESDIRK stage q = q^n + dt (a_i1 R(q^n) + a_ii R(q)) solved by
     pMG as the nonlinear solver: V-cycles on F(q + Y) = 0, smoothers with the
     pseudo-time shift sigma_S = 1/dtau + 1/(a_ii dt), blocks frozen at q^n,
-    until ||F|| <= tol ||F(q^n)||."""
+    until ||F|| <= tol ||F(q^n)||; coarse = "ej" or "mbnk" (the coarsest
+    level's smoother)."""
     a_i1 = a_ii if a_i1 is None else a_i1
     dtau = dt if dtau is None else dtau
     n = tuple(n) if n is not None else tuple([2] * (len(levels) - 1) + [2])
     sigma = 1.0 / (a_ii * dt)
-    facs = hierarchy_factors(levels, dq_n, 1.0 / dtau + sigma)
-    pm = MultiPMG(levels, facs, MultiPMGParams(sigma_D=sigma, n=n, scale_mode=SCALE_LITERAL))
+    sigma_S = 1.0 / dtau + sigma
+    facs = hierarchy_factors(levels, dq_n, sigma_S)
+    ilu = coarse_mbnk(levels, dq_n, sigma_S) if coarse == "mbnk" else None
+    pm = MultiPMG(levels, facs, MultiPMGParams(sigma_D=sigma, n=n, scale_mode=SCALE_LITERAL), coarse_ilu=ilu)
     fine = levels[0]
     R0 = fine.residual(dq_n)
     b = dq_n + (a_i1 * dt) * R0

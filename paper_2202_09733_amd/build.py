@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfrpmg.so")
-SOURCES = ["residual.hip", "vec.hip", "ej.hip", "ej_apply.hip", "lcc.hip", "ops1d.cpp", "frpmg.cpp"]
+SOURCES = ["residual.hip", "vec.hip", "ej.hip", "ej_apply.hip", "mbnk.hip", "lcc.hip", "ops1d.cpp", "frpmg.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

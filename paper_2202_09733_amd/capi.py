@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGUL
                 -6: "EBREAKDOWN", -7: "ENONFINITE"}
 EPS_ABSOLUTE, EPS_NORMALIZED, EPS_SCALED = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_FP32_BF16, PREC_BF16_STORE = 0, 1, 2, 3
-COARSE_NONE, COARSE_EJ, COARSE_LEARNED = 0, 1, 2
+COARSE_NONE, COARSE_EJ, COARSE_LEARNED, COARSE_MBNK = 0, 1, 2, 3
+SMOOTHER_EJ, SMOOTHER_MBNK = 0, 1
 SCALE_LITERAL, SCALE_NORMALIZED, SCALE_SCALED = 0, 1, 2
 SCHEME_ESDIRK, SCHEME_ROW = 0, 1
 PRECOND_EJ, PRECOND_PMG, PRECOND_PMG_LEARNED = 0, 1, 2
@@ -33,7 +34,8 @@ EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_resi
            "ej_solve", "ej_get_inverse", "pmg_restrict", "pmg_prolong", "pmg_set_point", "pmg_precond_apply",
            "gmres_solve_stage", "fr_time_step", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
            "lcc_get_weights", "lcc_set_weights", "lcc_get_scales", "lcc_set_scales", "lcc_forward",
-           "lcc_loss_grad", "lcc_features_of"]
+           "lcc_loss_grad", "lcc_features_of", "mbnk_factor", "mbnk_matvec", "mbnk_ilu_solve", "mbnk_solve",
+           "mbnk_get_blocks"]
 
 
 class FRError(RuntimeError):
@@ -52,7 +54,8 @@ class MeshDesc(ctypes.Structure):
 class PmgParams(ctypes.Structure):
     _fields_ = [("sigma_D", ctypes.c_double), ("n0", ctypes.c_int), ("n1", ctypes.c_int),
                 ("coarse_mode", ctypes.c_int), ("scale_mode", ctypes.c_int), ("eps_p", ctypes.c_double),
-                ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("levels", ctypes.c_int)]
+                ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("levels", ctypes.c_int),
+                ("mbnk_maxit", ctypes.c_int), ("mbnk_tol", ctypes.c_double)]
 
 
 class StageParams(ctypes.Structure):
@@ -64,7 +67,8 @@ class StageParams(ctypes.Structure):
                 ("eps_mode", ctypes.c_int), ("scale_mode", ctypes.c_int), ("eps_p", ctypes.c_double),
                 ("skip_setup", ctypes.c_int), ("stall_window", ctypes.c_int), ("stall_ratio", ctypes.c_double),
                 ("graphs", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int),
-                ("pmg_levels", ctypes.c_int), ("solver", ctypes.c_int)]
+                ("pmg_levels", ctypes.c_int), ("solver", ctypes.c_int), ("coarse_smoother", ctypes.c_int),
+                ("mbnk_maxit", ctypes.c_int), ("mbnk_tol", ctypes.c_double)]
 
 SOLVER_JFNK, SOLVER_PMG = 0, 1
 
@@ -169,6 +173,11 @@ def load():
     L.lcc_forward.argtypes = [vp, vp, ctypes.c_int, vp, vp]
     L.lcc_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp, vp]
     L.lcc_features_of.argtypes = [vp, vp, vp, vp, vp]
+    L.mbnk_factor.argtypes = [vp, ctypes.c_int, vp, dp, vp]
+    L.mbnk_matvec.argtypes = [vp, vp, vp, vp]
+    L.mbnk_ilu_solve.argtypes = [vp, vp, vp, vp]
+    L.mbnk_solve.argtypes = [vp, vp, vp, dp, ctypes.c_int, vp]
+    L.mbnk_get_blocks.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("fr_destroy", "fr_last_error", "fr_level_size", "lcc_num_weights"):
@@ -224,6 +233,9 @@ class StageConfig:
     n3: int = 2
     pmg_levels: int = 0
     solver: int = 0
+    coarse_smoother: int = SMOOTHER_EJ
+    mbnk_maxit: int = 0
+    mbnk_tol: float = 0.0
 
     def to_c(self):
         return StageParams(**{f[0]: getattr(self, f[0]) for f in StageParams._fields_})
@@ -338,13 +350,46 @@ class FR:
         self._check("pmg_set_point", self.lib.pmg_set_point(self.ctx, _ptr(dq), _ptr(rq), _stream()))
 
     def pmg_apply(self, x, sigma_D, n0=2, n1=2, coarse_mode=COARSE_EJ, scale_mode=SCALE_SCALED, eps_p=1e-6,
-                  out=None, n2=2, n3=2, levels=0):
+                  out=None, n2=2, n3=2, levels=0, mbnk_maxit=0, mbnk_tol=0.0):
         out = self.empty(0) if out is None else out
         prm = PmgParams(float(sigma_D), int(n0), int(n1), int(coarse_mode), int(scale_mode), float(eps_p),
-                        int(n2), int(n3), int(levels))
+                        int(n2), int(n3), int(levels), int(mbnk_maxit), float(mbnk_tol))
         self._check("pmg_precond_apply", self.lib.pmg_precond_apply(self.ctx, ctypes.byref(prm), _ptr(x),
                                                                     _ptr(out), _stream()))
         return out
+
+    # -- MBNK smoother ------------------------------------------------------------
+    def mbnk_factor(self, level, dq_lin, sigma):
+        self._mb_level = level
+        self._check("mbnk_factor", self.lib.mbnk_factor(self.ctx, level, _ptr(dq_lin), float(sigma), _stream()))
+
+    def mbnk_matvec(self, x, out=None):
+        out = self.empty(self._mb_level) if out is None else out
+        self._check("mbnk_matvec", self.lib.mbnk_matvec(self.ctx, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def mbnk_ilu_solve(self, r, out=None):
+        out = self.empty(self._mb_level) if out is None else out
+        self._check("mbnk_ilu_solve", self.lib.mbnk_ilu_solve(self.ctx, _ptr(r), _ptr(out), _stream()))
+        return out
+
+    def mbnk_solve(self, g, tol=0.1, maxit=5, out=None):
+        out = self.empty(self._mb_level) if out is None else out
+        self._check("mbnk_solve", self.lib.mbnk_solve(self.ctx, _ptr(g), _ptr(out), float(tol), int(maxit),
+                                                      _stream()))
+        return out
+
+    def mbnk_blocks(self):
+        """Assembled blocks as numpy: D [Ne][nb][nb], O [Ne][2 dim][nb][nb], row-major."""
+        nb = self.nv * (self.levels[self._mb_level] + 1) ** self.dim
+        D = np.empty(self.Ne * nb * nb)
+        O = np.empty(self.Ne * 2 * self.dim * nb * nb)
+        dp_ = ctypes.POINTER(ctypes.c_double)
+        self._check("mbnk_get_blocks", self.lib.mbnk_get_blocks(self.ctx, D.ctypes.data_as(dp_),
+                                                                O.ctypes.data_as(dp_)))
+        D = D.reshape(self.Ne, nb, nb).transpose(0, 2, 1).copy()
+        O = O.reshape(self.Ne, 2 * self.dim, nb, nb).transpose(0, 1, 3, 2).copy()
+        return D, O
 
     # -- learned coarse correction ---------------------------------------------
     def lcc_dims(self):

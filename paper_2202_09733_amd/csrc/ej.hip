@@ -579,6 +579,17 @@ bool ej_blocked(int nb, int precision) {
     return nb > kMaxLdsBlock || precision == FR_PREC_FP32_BF16 || precision == FR_PREC_BF16_STORE;
 }
 
+hipError_t invert_blocks_f64(int count, int nb, const double *in, double *out, int *status, hipStream_t s) {
+    if (nb > kMaxLdsBlock || count < 0) return hipErrorInvalidValue;
+    if (count == 0) return hipSuccess;
+    const size_t lds = ((size_t)nb * nb + nb) * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void *)k_gj_invert<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gj_invert<double>, dim3(count), dim3(kGJThreads), lds, s, nb, in, out, status);
+    return hipGetLastError();
+}
+
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
     Level &L = ctx->lv[level];
     const int nb = L.nb, Ne = ctx->mesh.Ne;

@@ -144,6 +144,16 @@ void check_neighbours(frpmg_ctx *ctx) {
         REQUIRE(ctx->mesh.n[a] >= 2, "EJ formation needs at least two elements per axis");
 }
 
+// face data of a level's linearisation point, kept by the element-local block formation
+void ensure_face_save(frpmg_ctx *ctx, Level &L) {
+    if (L.fQp) return;
+    const size_t nface = (size_t)ctx->dim * ctx->nv * L.NF * ctx->mesh.Ne;
+    L.fQs = dalloc(ctx, nface);
+    L.fQp = dalloc(ctx, nface);
+    L.fSn = dalloc(ctx, nface);
+    L.fGt = dalloc(ctx, nface * (ctx->dim - 1));
+}
+
 void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, int precision, hipStream_t s) {
     REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
     REQUIRE(precision >= FR_PREC_FP64 && precision <= FR_PREC_BF16_STORE, "bad precision");
@@ -171,13 +181,7 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
         HIPCHK(hipMalloc(&p, nblk * sizeof(__bf16)));
         L.inv16 = (__bf16 *)p;
     }
-    if (!L.fQp) {
-        const size_t nface = (size_t)ctx->dim * ctx->nv * L.NF * ctx->mesh.Ne;
-        L.fQs = dalloc(ctx, nface);
-        L.fQp = dalloc(ctx, nface);
-        L.fSn = dalloc(ctx, nface);
-        L.fGt = dalloc(ctx, nface * (ctx->dim - 1));
-    }
+    ensure_face_save(ctx, L);
     ctx->graph_epoch++;  // captured steps bake in the factor buffers and precision
     HIPCHK(hipMemsetAsync(L.dstatus, 0, sizeof(int), s));
     HIPCHK(launch_ej_form(ctx, level, dq, sigma, s));
@@ -192,6 +196,123 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// MBNK smoother (Sec. 3.2): assembled face-neighbour Jacobian, red-black
+// block ILU0, GMRES sweeps
+// ---------------------------------------------------------------------------
+
+constexpr size_t kMbnkBatchDoubles = size_t(1) << 24;  // perturbed states per batched residual (128 MiB)
+constexpr int kMbnkGm = 256;                           // device scalars of the GMRES cycle
+
+void mbnk_free(frpmg_ctx *ctx) {
+    Mbnk *mb = ctx->mb;
+    if (!mb) return;
+    double *bufs[] = {mb->D, mb->O, mb->Rinv, mb->Binv, mb->qb, mb->rb, mb->Jpb, mb->Fsb, mb->V, mb->Z, mb->w, mb->gm};
+    for (double *b : bufs) dfree(b);
+    dfree(mb->status);
+    delete mb;
+    ctx->mb = nullptr;
+}
+
+// Smallest divisor of n that is at least 3: elements of one colour are then
+// at least three apart along the axis, across the periodic wrap too.
+int colour_stride(int n) {
+    for (int s = 3; s <= n; ++s)
+        if (n % s == 0) return s;
+    return 0;
+}
+
+void mbnk_alloc(frpmg_ctx *ctx, int level) {
+    if (ctx->mb && ctx->mb->level == level) return;
+    mbnk_free(ctx);
+    const Level &L = ctx->lv[level];
+    const MeshK &m = ctx->mesh;
+    Mbnk *mb = new Mbnk();
+    ctx->mb = mb;
+    mb->level = level;
+    mb->nb = L.nb;
+    mb->Ne = m.Ne;
+    mb->nface = 2 * ctx->dim;
+    mb->N = L.N;
+    mb->ncolour = 1;
+    for (int a = 0; a < ctx->dim; ++a) {
+        mb->stride[a] = colour_stride(m.n[a]);
+        mb->ncolour *= mb->stride[a];
+    }
+    const size_t nn = (size_t)L.nb * L.nb;
+    mb->D = dalloc(ctx, (size_t)m.Ne * nn);
+    mb->O = dalloc(ctx, (size_t)m.Ne * mb->nface * nn);
+    mb->Rinv = dalloc(ctx, (size_t)(m.Ne / 2) * nn);
+    mb->Binv = dalloc(ctx, (size_t)(m.Ne / 2) * nn);
+    // 2D: as many perturbed copies per launch as fit the batch budget, the
+    // launch grids and the element-index range; 3D: one copy
+    int batch = 1;
+    if (ctx->dim == 2) {
+        const size_t byb = std::max<size_t>(1, kMbnkBatchDoubles / L.N);
+        const size_t lim_grid = (size_t)65535 / L.nb;
+        const size_t lim_idx = ((size_t)1 << 31) / ((size_t)m.Ne * std::max(m.n[0], m.n[1]) + 1);
+        batch = (int)std::max<size_t>(1, std::min({byb, lim_grid, lim_idx, (size_t)mb->ncolour * L.nb}));
+    }
+    mb->batch = batch;
+    const size_t ntr = (size_t)ctx->dim * ctx->nv * L.NF * m.Ne * batch;
+    mb->qb = dalloc(ctx, L.N * batch);
+    mb->rb = dalloc(ctx, L.N * batch);
+    mb->Jpb = dalloc(ctx, ntr);
+    mb->Fsb = dalloc(ctx, ntr);
+    mb->mmax = kMbnkMaxIt;
+    mb->V = dalloc(ctx, (size_t)(kMbnkMaxIt + 1) * L.N);
+    mb->Z = dalloc(ctx, (size_t)kMbnkMaxIt * L.N);
+    mb->w = dalloc(ctx, L.N);
+    mb->gm = dalloc(ctx, kMbnkGm);
+    void *p = nullptr;
+    HIPCHK(hipMalloc(&p, sizeof(int)));
+    mb->status = (int *)p;
+}
+
+// Assemble sigma I - dR/dq of a level at dq on the face-neighbour block
+// pattern and factor it by red-black block ILU0.
+void mbnk_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s) {
+    REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
+    Level &L = ctx->lv[level];
+    REQUIRE(L.nb <= 128 && L.nb % 2 == 0, "MBNK takes element blocks of at most 128 unknowns");
+    for (int a = 0; a < ctx->dim; ++a)
+        REQUIRE(ctx->mesh.n[a] >= 4 && ctx->mesh.n[a] % 2 == 0,
+                "MBNK needs an even element count of at least 4 per axis (red-black order, distinct neighbours)");
+    mbnk_alloc(ctx, level);
+    ensure_face_save(ctx, L);
+    Mbnk &mb = *ctx->mb;
+    mb.ready = false;
+    ctx->graph_epoch++;
+    HIPCHK(hipMemsetAsync(mb.status, 0, sizeof(int), s));
+    HIPCHK(launch_ej_form(ctx, level, dq, sigma, s, mb.D));  // diagonal blocks and L.r0 = R(dq)
+    const int npairs = mb.ncolour * mb.nb;
+    for (int p0 = 0; p0 < npairs; p0 += mb.batch) {
+        const int cnt = std::min(mb.batch, npairs - p0);
+        HIPCHK(mb_perturb(ctx, mb, dq, p0, cnt, s));
+        HIPCHK(launch_residual_batch(ctx, level, cnt, mb.qb, mb.rb, mb.Jpb, mb.Fsb, s));
+        HIPCHK(mb_extract(ctx, mb, dq, L.r0, p0, cnt, s));
+    }
+    HIPCHK(mb_gather_red(ctx, mb, s));
+    HIPCHK(invert_blocks_f64(mb.Ne / 2, mb.nb, mb.Rinv, mb.Rinv, mb.status, s));
+    HIPCHK(mb_schur(ctx, mb, s));
+    HIPCHK(invert_blocks_f64(mb.Ne / 2, mb.nb, mb.Binv, mb.Binv, mb.status, s));
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(ctx->host_pinned, mb.status, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(&flag, ctx->host_pinned, sizeof(int));
+    if (flag) {
+        ctx->err = "zero pivot in an MBNK block";
+        throw Fail{FR_ESINGULAR};
+    }
+    mb.ready = true;
+}
+
+const Mbnk &mbnk_of(frpmg_ctx *ctx, int level) {
+    REQUIRE(ctx->mb && ctx->mb->ready && (level < 0 || ctx->mb->level == level),
+            "no MBNK factorisation of the level (mbnk_factor)");
+    return *ctx->mb;
+}
 
 // ---------------------------------------------------------------------------
 // learned coarse correction: buffers, forward pass, training step
@@ -394,10 +515,26 @@ void coarse_cycle(frpmg_ctx *ctx, const pmg_params &p, int l, int nlev, hipStrea
     const Scal one{1.0, nullptr};
     const int n = pmg_sweeps(p, l);
     REQUIRE(n >= 1, "every coarse level needs at least one sweep (n1, n2, n3 >= 1)");
-    REQUIRE(ctx->lv[l].inv_prec >= 0, "a coarse level has no EJ factors");
     long &R = cnt->R1;  // every coarse level counts as coarse
     long &E = cnt->E1;
     double *Z0 = ctx->mZ0[l], *Z = ctx->mZ[l], *S = ctx->mS[l], *G = ctx->mG[l], *cd = ctx->md[l];
+    if (p.coarse_mode == FR_COARSE_MBNK && l == nlev - 1) {
+        // MBNK sweeps on the coarsest level: Z <- Z - (sigma_S I - J)^{-1} G_l(Z) by GMRES
+        const Mbnk &mb = mbnk_of(ctx, l);
+        const int maxit = p.mbnk_maxit > 0 ? p.mbnk_maxit : 5;
+        const double tol = p.mbnk_tol > 0 ? p.mbnk_tol : 0.1;
+        REQUIRE(maxit <= kMbnkMaxIt, "mbnk_maxit exceeds 8");
+        HIPCHK(mb_sweep(ctx, mb, cd, Z0, Z, tol, maxit, s));
+        E++;
+        for (int it = 1; it < n; ++it) {
+            residual_lin(ctx, l, ctx->mq[l], Z, one, ctx->mr[l], p.sigma_D, S, G, s);
+            R++;
+            HIPCHK(mb_sweep(ctx, mb, G, Z, Z, tol, maxit, s));
+            E++;
+        }
+        return;
+    }
+    REQUIRE(ctx->lv[l].inv_prec >= 0, "a coarse level has no EJ factors");
     // the first sweep starts from Z0, where G_l = cd: Z = Z0 - B_l^{-1} cd
     HIPCHK(ej_apply_ex(ctx, l, cd, -1.0, 1.0, Z0, one, Z, s));
     E++;
@@ -442,9 +579,10 @@ void pmg_apply_impl(frpmg_ctx *ctx, const pmg_params &p, const double *x, double
         if (learned) {
             REQUIRE(ctx->lcc && ctx->lcc->scales_set, "the learned correction has no trained network");
         } else {
-            REQUIRE(ctx->lv[1].inv_prec >= 0, "level 1 has no EJ factors");
+            REQUIRE(p.coarse_mode == FR_COARSE_EJ || p.coarse_mode == FR_COARSE_MBNK, "unknown coarse mode");
+            if (p.coarse_mode == FR_COARSE_MBNK) (void)mbnk_of(ctx, nlev - 1);
+            else REQUIRE(ctx->lv[1].inv_prec >= 0, "level 1 has no EJ factors");
             REQUIRE(p.n1 >= 1, "n1 must be >= 1");
-            REQUIRE(p.coarse_mode == FR_COARSE_EJ, "unknown coarse mode");
         }
     }
     const Scal one{1.0, nullptr};
@@ -814,7 +952,7 @@ struct StageSolver {
     frpmg_ctx *ctx;
     stage_params P;
     size_t N;
-    bool esdirk, pmg, learned, use_graphs, nonlinear_pmg;
+    bool esdirk, pmg, learned, use_graphs, nonlinear_pmg, mbnk;
     int nlev;
     double sigma_A, sigma_S;
     pmg_params pp;
@@ -845,8 +983,14 @@ struct StageSolver {
         sigma_S = 1.0 / dtau + sigma_A;
         nlev = pmg ? (learned ? 2 : (P.pmg_levels > 0 ? P.pmg_levels : ctx->nlevels)) : 1;
         REQUIRE(nlev <= ctx->nlevels, "pmg_levels exceeds the context's levels");
-        pp = pmg_params{sigma_A, P.n0, P.n1, learned ? FR_COARSE_LEARNED : FR_COARSE_EJ,
-                        nonlinear_pmg ? FR_SCALE_LITERAL : P.scale_mode, P.eps_p, P.n2, P.n3, nlev};
+        REQUIRE(P.coarse_smoother == FR_SMOOTHER_EJ || P.coarse_smoother == FR_SMOOTHER_MBNK,
+                "unknown coarse smoother");
+        mbnk = pmg && P.coarse_smoother == FR_SMOOTHER_MBNK;
+        REQUIRE(!mbnk || !learned, "the MBNK smoother takes the plain pMG hierarchy");
+        REQUIRE(P.mbnk_maxit >= 0 && P.mbnk_maxit <= kMbnkMaxIt, "mbnk_maxit must be in 0..8");
+        pp = pmg_params{sigma_A, P.n0, P.n1, learned ? FR_COARSE_LEARNED : (mbnk ? FR_COARSE_MBNK : FR_COARSE_EJ),
+                        nonlinear_pmg ? FR_SCALE_LITERAL : P.scale_mode, P.eps_p, P.n2, P.n3, nlev,
+                        P.mbnk_maxit, P.mbnk_tol};
         stall.active = learned;
         if (P.stall_window > 0) stall.window = P.stall_window;
         if (P.stall_ratio > 0) stall.ratio = P.stall_ratio;
@@ -864,8 +1008,14 @@ struct StageSolver {
             // the coarse blocks are linearised at the restricted q^n
             for (int l = 1; l < nlev; ++l) {
                 HIPCHK(transfer_apply(ctx, l - 1, true, l == 1 ? dq_n : ctx->mq[l - 1], ctx->mq[l], s));
-                ej_factor_impl(ctx, l, ctx->mq[l], sigma_S, P.precision, s);
-                cnt.R1 += 1 + ctx->lv[l].nb;
+                if (mbnk && l == nlev - 1) {
+                    // the coarsest level smooths with MBNK: its assembled operator instead of EJ blocks
+                    mbnk_factor_impl(ctx, l, ctx->mq[l], sigma_S, s);
+                    cnt.R1 += 1 + ctx->lv[l].nb * (1 + ctx->mb->ncolour);
+                } else {
+                    ej_factor_impl(ctx, l, ctx->mq[l], sigma_S, P.precision, s);
+                    cnt.R1 += 1 + ctx->lv[l].nb;
+                }
             }
         } else {
             ej_factor_impl(ctx, 0, dq_n, sigma_A, P.precision, s);
@@ -919,7 +1069,9 @@ struct StageSolver {
         g.key = {ctx->graph_epoch, (unsigned long long)P.scheme, (unsigned long long)P.precond, bits(sigma_A),
                  bits(P.eps), (unsigned long long)P.eps_mode, (unsigned long long)P.n0, (unsigned long long)P.n1,
                  (unsigned long long)P.scale_mode, bits(P.eps_p), bits(q), bits(rq), bits(ctx->V), bits(ctx->Zk),
-                 bits(ctx->kw), (unsigned long long)N};
+                 bits(ctx->kw), (unsigned long long)N, (unsigned long long)P.n2, (unsigned long long)P.n3,
+                 (unsigned long long)nlev, (unsigned long long)pp.coarse_mode, (unsigned long long)P.mbnk_maxit,
+                 bits(P.mbnk_tol)};
         return g;
     }
 
@@ -1217,6 +1369,7 @@ void destroy_all(frpmg_ctx *ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     ctx->cap_stream = nullptr;
     lcc_free(ctx);
+    mbnk_free(ctx);
     for (int l = 0; l < FR_MAX_LEVELS; ++l) {
         Level &L = ctx->lv[l];
         dfree(L.Jp);
@@ -1458,6 +1611,47 @@ fr_status ej_get_inverse(frpmg_ctx *ctx, int level, double *host_out) {
                                 nb * sizeof(double));
             }
         }
+    });
+}
+
+fr_status mbnk_factor(frpmg_ctx *ctx, int level, const double *dq_lin, double sigma, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(dq_lin, "null pointer");
+        mbnk_factor_impl(ctx, level, dq_lin, sigma, S(stream));
+    });
+}
+
+fr_status mbnk_matvec(frpmg_ctx *ctx, const double *x, double *y, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(x && y && x != y, "bad pointers");
+        HIPCHK(mb_matvec(ctx, mbnk_of(ctx, -1), x, y, S(stream)));
+    });
+}
+
+fr_status mbnk_ilu_solve(frpmg_ctx *ctx, const double *r, double *z, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(r && z && r != z, "bad pointers");
+        HIPCHK(mb_ilu(ctx, mbnk_of(ctx, -1), r, z, S(stream)));
+    });
+}
+
+fr_status mbnk_solve(frpmg_ctx *ctx, const double *g, double *delta, double tol, int maxit, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(g && delta, "null pointer");
+        REQUIRE(maxit >= 1 && maxit <= kMbnkMaxIt, "maxit must be in 1..8");
+        REQUIRE(tol >= 0.0, "tol must be non-negative");
+        HIPCHK(mb_sweep(ctx, mbnk_of(ctx, -1), g, nullptr, delta, tol, maxit, S(stream)));
+    });
+}
+
+fr_status mbnk_get_blocks(frpmg_ctx *ctx, double *host_D, double *host_O) {
+    return guarded(ctx, [&] {
+        const Mbnk &mb = mbnk_of(ctx, -1);
+        const size_t nn = (size_t)mb.nb * mb.nb;
+        HIPCHK(hipDeviceSynchronize());
+        if (host_D) HIPCHK(hipMemcpy(host_D, mb.D, (size_t)mb.Ne * nn * sizeof(double), hipMemcpyDeviceToHost));
+        if (host_O)
+            HIPCHK(hipMemcpy(host_O, mb.O, (size_t)mb.Ne * mb.nface * nn * sizeof(double), hipMemcpyDeviceToHost));
     });
 }
 

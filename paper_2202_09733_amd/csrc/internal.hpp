@@ -48,6 +48,40 @@ struct MeshK {
     unsigned long long rcp[3];  // ceil(2^40 / n[a]): k / n[a] = (k rcp[a]) >> 40 while k n[a] < 2^40
 };
 
+// k / n[a] by the rounded-up reciprocal (exact while k n[a] < 2^40, which
+// context creation checks): a multiply instead of a runtime division
+__device__ __forceinline__ int div_axis(const MeshK &m, int k, int a) {
+    return (int)(((unsigned long long)(unsigned)k * m.rcp[a]) >> 40);
+}
+
+// element coordinates; in 2D, c[2] numbers independent copies of the mesh
+__device__ __forceinline__ void coords(const MeshK &m, int k, int c[3]) {
+    const int r = div_axis(m, k, 0);
+    c[0] = k - r * m.n[0];
+    c[2] = div_axis(m, r, 1);
+    c[1] = r - c[2] * m.n[1];
+}
+
+__device__ __forceinline__ int elem_index(const MeshK &m, const int c[3]) {
+    return c[0] + m.n[0] * (c[1] + m.n[1] * c[2]);
+}
+
+// the element across the face normal to axis a on side s = -1 / +1 (periodic)
+__device__ __forceinline__ int neighbour(const MeshK &m, int k, int a, int s) {
+    int c[3];
+    coords(m, k, c);
+    int x = c[a] + s;
+    if (x < 0) x += m.n[a];
+    if (x >= m.n[a]) x -= m.n[a];
+    c[a] = x;
+    return elem_index(m, c);
+}
+
+// Finite-difference step of one perturbed entry: 1e-7 max(1, |q_inf + dq|).
+__device__ __forceinline__ double fd_step(double qinf_v, double dqv) {
+    return 1e-7 * fmax(1.0, fabs(qinf_v + dqv));
+}
+
 // Scalar that lives either on the host (p == nullptr) or in device memory.
 struct Scal {
     double v;
@@ -133,6 +167,31 @@ struct StepGraph {
     long dR0 = 0, dR1 = 0, dE0 = 0, dE1 = 0;
 };
 
+// Matrix-based Newton-Krylov smoother of one level (Sec. 3.2): the
+// assembled sigma I - dR/dq on the face-neighbour block pattern, its block
+// ILU0 in red-black element order (colour = parity of the coordinate sum;
+// with an even element count per axis, elements 2c and 2c + 1 take opposite
+// colours, so c = k / 2 numbers each colour compactly), and the GMRES
+// workspace.  Blocks are column-major, entry (row, col) at col nb + row.
+struct Mbnk {
+    int level = -1;
+    int nb = 0, Ne = 0, nface = 0;
+    size_t N = 0;
+    double *D = nullptr;     // [Ne][nb][nb]: sigma I - dR_k/dq_k
+    double *O = nullptr;     // [Ne][2 dim][nb][nb]: -dR_k/dq_m, m the face neighbour of slot 2a + (side > 0)
+    double *Rinv = nullptr;  // [Ne/2][nb][nb]: D_k^{-1} of the red element of pair c
+    double *Binv = nullptr;  // [Ne/2][nb][nb]: (D_b - sum_r O_br D_r^{-1} O_rb)^{-1} of the black element
+    int stride[3] = {1, 1, 1};  // colouring of the neighbour-block differences
+    int ncolour = 0;
+    int batch = 0;           // perturbed copies per batched residual
+    double *qb = nullptr, *rb = nullptr, *Jpb = nullptr, *Fsb = nullptr;
+    int mmax = 0;            // GMRES workspace: basis V [mmax + 1][N], Z [mmax][N], w [N]
+    double *V = nullptr, *Z = nullptr, *w = nullptr;
+    double *gm = nullptr;    // device scalars of the GMRES cycle
+    int *status = nullptr;
+    bool ready = false;
+};
+
 }  // namespace frpmg
 
 struct frpmg_ctx {
@@ -164,6 +223,8 @@ struct frpmg_ctx {
     int stv_n = 0;
     // learned coarse correction (allocated on first use)
     frpmg::Lcc *lcc = nullptr;
+    // MBNK smoother (allocated at the first mbnk_factor)
+    frpmg::Mbnk *mb = nullptr;
     // captured Arnoldi steps, replayed on the caller's stream
     hipStream_t cap_stream = nullptr;
     std::vector<frpmg::StepGraph> graphs;
@@ -179,8 +240,15 @@ void gauss_legendre(int P, double *x, double *w);
 
 // residual.hip
 hipError_t launch_residual(const frpmg_ctx *ctx, int level, const ResidualArgs &a, hipStream_t s);
-// r0 = R(dq) and the FP64 blocks sigma I - dR_k/dq_k of every element into L.blk64
-hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s);
+// r0 = R(dq) and the FP64 blocks sigma I - dR_k/dq_k of every element into
+// out (null: L.blk64), [Ne][nb][nb] column-major per block
+hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s,
+                          double *out = nullptr);
+// r = R(dq) for `batch` independent copies of a 2D level's state, copy b at
+// elements b Ne .. (b + 1) Ne - 1 of [nv][Np][batch Ne] arrays; face buffers
+// Jp and Fs hold [dim][nv][NF][batch Ne].  3D: batch must be 1.
+hipError_t launch_residual_batch(const frpmg_ctx *ctx, int level, int batch, const double *dq, double *r,
+                                 double *Jp, double *Fs, hipStream_t s);
 
 // vec.hip
 hipError_t vec_dot(frpmg_ctx *ctx, size_t n, const double *x, const double *y, double *dout, hipStream_t s);
@@ -226,6 +294,31 @@ hipError_t vec_dot_pmg_scale(frpmg_ctx *ctx, size_t n, const double *x, const do
 // true when the blocks of this size and precision take the blocked inversion
 bool ej_blocked(int nb, int precision);
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s);
+// out[i] = in[i]^{-1} for `count` FP64 blocks of nb <= 128 (LDS Gauss-Jordan,
+// partial pivoting, exact column order); *status = 1 on a zero pivot.  in
+// may equal out.
+hipError_t invert_blocks_f64(int count, int nb, const double *in, double *out, int *status, hipStream_t s);
+
+// mbnk.hip
+constexpr int kMbnkMaxIt = 8;
+// colour-batch kernels of the neighbour-block formation: pairs p0 .. p0 + cnt - 1
+// (pair = colour nb + column) perturbed into qb ([nv][Np][cnt Ne]); their
+// residuals rb extracted into the off-diagonal blocks
+hipError_t mb_perturb(const frpmg_ctx *ctx, const Mbnk &mb, const double *dq, int p0, int cnt, hipStream_t s);
+hipError_t mb_extract(const frpmg_ctx *ctx, const Mbnk &mb, const double *dq, const double *r0, int p0, int cnt,
+                        hipStream_t s);
+// Rinv = red D blocks (inverted by the caller); Binv = black Schur complements
+hipError_t mb_gather_red(const frpmg_ctx *ctx, const Mbnk &mb, hipStream_t s);
+hipError_t mb_schur(const frpmg_ctx *ctx, const Mbnk &mb, hipStream_t s);
+// y = A x on the assembled pattern
+hipError_t mb_matvec(const frpmg_ctx *ctx, const Mbnk &mb, const double *x, double *y, hipStream_t s);
+// z = (L U)^{-1} r, three element-parallel steps; z must not alias r
+hipError_t mb_ilu(const frpmg_ctx *ctx, const Mbnk &mb, const double *r, double *z, hipStream_t s);
+// Yout = Yin - delta (Yin null: Yout = delta), delta ~ A^{-1} G by
+// right-ILU0-preconditioned GMRES(maxit <= kMbnkMaxIt) to relative tolerance
+// tol, every decision taken on the device.  G may alias Yin or Yout.
+hipError_t mb_sweep(frpmg_ctx *ctx, const Mbnk &mb, const double *G, const double *Yin, double *Yout, double tol,
+                      int maxit, hipStream_t s);
 // y = beta y + alpha B^{-1} r
 hipError_t ej_apply(const frpmg_ctx *ctx, int level, const double *r, double alpha, double beta, double *y,
                     hipStream_t s);

@@ -1,0 +1,423 @@
+// Matrix-based Newton-Krylov (MBNK) smoother on gfx950 (Sec. 3.2): the
+// coarsest pMG level solves its linearised pseudo-time step
+//   (sigma I - dR/dq) delta = G
+// by GMRES with at most five iterations to a relative tolerance of 1e-1,
+// right-preconditioned by ILU0, instead of one element-Jacobi application.
+//
+// The assembled operator keeps, for every element k, the diagonal block and
+// the 2 dim blocks that couple k to its face neighbours.  The off-diagonal
+// blocks come from one-sided differences of the residual, many elements
+// perturbed at once: elements of one colour lie at least three apart along
+// some axis, so the residual stencils of two perturbed elements (the element
+// and its face and edge neighbours) are disjoint and every difference
+// belongs to one perturbation.  A 2D level evaluates many (colour, column)
+// perturbations in one batched residual launch, each copy of the mesh being
+// an independent slab of elements.
+//
+// ILU0 runs in red-black element order.  With face couplings only, red rows
+// have no lower part, so the factorisation keeps D_r for red elements and
+// the Schur complements U_b = D_b - sum_r O_br D_r^{-1} O_rb for black ones
+// (ILU0 drops the fill between distinct black elements), and both
+// triangular solves are three element-parallel steps.  Every decision of the
+// GMRES cycle (convergence, breakdown) is taken on the device, so a sweep is
+// a fixed sequence of launches that a HIP graph can capture.
+#include "internal.hpp"
+
+namespace frpmg {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// device scalars of one GMRES cycle (doubles)
+constexpr int GM_H1 = 0;       // first Gram-Schmidt pass, up to 8 values
+constexpr int GM_H2 = 8;       // second pass
+constexpr int GM_N2 = 16;      // squared norm of the last normalised vector
+constexpr int GM_TARGET = 17;  // tol ||G||
+constexpr int GM_DONE = 18;    // 1 once the cycle has stopped
+constexpr int GM_JEND = 19;    // iterations whose directions form the update
+constexpr int GM_G = 24;       // rotated right-hand side, 9 values
+constexpr int GM_CS = 33;      // rotations, 8 each
+constexpr int GM_SN = 41;
+constexpr int GM_Y = 49;       // least-squares solution, 8 values
+constexpr int GM_H = 64;       // Hessenberg matrix, column-major 9 x 8
+constexpr int GM_SIZE = 64 + 9 * 8;
+constexpr int kMaxIt = kMbnkMaxIt;
+
+// the element of colour col (0 red, 1 black) among elements 2c and 2c + 1
+// (an even element count along axis 0 keeps both in one row)
+__device__ __forceinline__ int colour_elem(const MeshK &m, int c, int col) {
+    int x[3];
+    const int k0 = 2 * c;
+    coords(m, k0, x);
+    const int par = (x[0] + x[1] + (m.dim == 3 ? x[2] : 0)) & 1;
+    return par == col ? k0 : k0 + 1;
+}
+
+// colour of the neighbour-block differences: sum_a (c_a mod s_a) prod_{b<a} s_b
+__device__ __forceinline__ int fd_colour(const MeshK &m, int s0, int s1, int s2, int k) {
+    int x[3];
+    coords(m, k, x);
+    int col = x[0] % s0 + s0 * (x[1] % s1);
+    if (m.dim == 3) col += s0 * s1 * (x[2] % s2);
+    return col;
+}
+
+// qb[vi][b][k] = dq[vi][k], plus the step where pair p0 + b perturbs (vi, k)
+__global__ void __launch_bounds__(kThreads) k_mb_perturb(MeshK m, int nb, int Np, Phys ph, int s0, int s1, int s2,
+                                                         int p0, int cnt, const double *__restrict__ dq,
+                                                         double *__restrict__ qb) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m.Ne) return;
+    const int row = blockIdx.y;  // vi cnt + b
+    const int vi = row / cnt, b = row - vi * cnt;
+    const int pair = p0 + b;
+    const int colour = pair / nb, j = pair - colour * nb;
+    double u = dq[(size_t)vi * m.Ne + k];
+    if (vi == j && fd_colour(m, s0, s1, s2, k) == colour) u = u + fd_step(ph.qinf[vi / Np], u);
+    qb[((size_t)vi * cnt + b) * m.Ne + k] = u;
+}
+
+// O[k][slot(a, -side)][:, j] = -(R_b[:, k] - r0[:, k]) / h_m for every member
+// m of the pair's colour and k its face neighbour (a, side)
+__global__ void __launch_bounds__(kThreads) k_mb_extract(MeshK m, int nb, int Np, Phys ph, int s0, int s1, int s2,
+                                                         int p0, int cnt, int nface, const double *__restrict__ dq,
+                                                         const double *__restrict__ r0,
+                                                         const double *__restrict__ rb, double *__restrict__ O) {
+    const int b = blockIdx.y / nface, f = blockIdx.y - b * nface;
+    const int pair = p0 + b;
+    const int colour = pair / nb, j = pair - colour * nb;
+    const int M0 = m.n[0] / s0, M1 = m.n[1] / s1, M2 = (m.dim == 3) ? m.n[2] / s2 : 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M0 * M1 * M2 * nb) return;
+    const int mu = t / nb, row = t - mu * nb;
+    int c[3];
+    c[0] = colour % s0 + s0 * (mu % M0);
+    c[1] = (colour / s0) % s1 + s1 * ((mu / M0) % M1);
+    c[2] = (m.dim == 3) ? (colour / (s0 * s1)) + s2 * (mu / (M0 * M1)) : 0;
+    const int mel = elem_index(m, c);
+    const int k = neighbour(m, mel, f >> 1, (f & 1) ? 1 : -1);
+    const double base = dq[(size_t)j * m.Ne + mel];
+    const double h = (base + fd_step(ph.qinf[j / Np], base)) - base;
+    const double Rk = rb[((size_t)row * cnt + b) * m.Ne + k];
+    O[((size_t)k * nface + (f ^ 1)) * nb * nb + (size_t)j * nb + row] = -(Rk - r0[(size_t)row * m.Ne + k]) / h;
+}
+
+__global__ void __launch_bounds__(kThreads) k_mb_gather(MeshK m, int nb, int col, const double *__restrict__ D,
+                                                        double *__restrict__ out) {
+    const int c = blockIdx.x;
+    const int k = colour_elem(m, c, col);
+    const size_t nn = (size_t)nb * nb;
+    for (size_t t = threadIdx.x; t < nn; t += blockDim.x) out[c * nn + t] = D[(size_t)k * nn + t];
+}
+
+// U_b = D_b - sum_f O[b][f] (Rinv_r O[r][f^1]), r the red neighbour across face f
+__global__ void __launch_bounds__(kThreads) k_mb_schur(MeshK m, int nb, int nface, const double *__restrict__ D,
+                                                       const double *__restrict__ O,
+                                                       const double *__restrict__ Rinv, double *__restrict__ U) {
+    extern __shared__ double T[];  // nb x nb, column-major
+    const int c = blockIdx.x;
+    const int k = colour_elem(m, c, 1);
+    const int nn = nb * nb;
+    double *u = U + (size_t)c * nn;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) u[e] = D[(size_t)k * nn + e];
+    for (int f = 0; f < nface; ++f) {
+        const int r = neighbour(m, k, f >> 1, (f & 1) ? 1 : -1);
+        const double *ri = Rinv + (size_t)(r >> 1) * nn;
+        const double *orb = O + ((size_t)r * nface + (f ^ 1)) * nn;
+        const double *obr = O + ((size_t)k * nface + f) * nn;
+        __syncthreads();  // the previous face's products have read T
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+            const int i = e % nb, jj = e / nb;
+            double acc = 0.0;
+            for (int l = 0; l < nb; ++l) acc += ri[l * nb + i] * orb[jj * nb + l];
+            T[e] = acc;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+            const int i = e % nb, jj = e / nb;
+            double acc = 0.0;
+            for (int l = 0; l < nb; ++l) acc += obr[l * nb + i] * T[jj * nb + l];
+            u[e] -= acc;
+        }
+    }
+}
+
+enum RowMode { MB_MATVEC = 0, MB_INV = 1, MB_NBR_INV = 2 };
+
+// Block rows of the assembled operator, epb elements per workgroup, each lane
+// two consecutive rows of one element (one 16-byte load per block column):
+//   MB_MATVEC : y_k = D_k x_k + sum_f O[k][f] x_nbr(k,f)          (every element)
+//   MB_INV    : y_k = Inv_c r_k                                    (colour col)
+//   MB_NBR_INV: y_k = Inv_c (r_k - sum_f O[k][f] x_nbr(k,f))       (colour col)
+// Inv holds one block per pair index c of the colour.
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_mb_rows(MeshK m, int nb, int nface, int epb, int col, int count,
+                                                      const double *__restrict__ D, const double *__restrict__ O,
+                                                      const double *__restrict__ Inv, const double *x,
+                                                      const double *__restrict__ r, double *y) {
+    extern __shared__ double sh[];
+    __shared__ int s_k[64];
+    __shared__ int s_n[64][6];
+    const int nx = (MODE == MB_MATVEC) ? nface + 1 : nface;  // staged vectors per element
+    double *s_x = sh;                                      // [epb][nx][nb]
+    double *s_t = sh + (size_t)epb * (nface + 1) * nb;     // [epb][nb]
+    const int g0 = xcd_block(blockIdx.x, gridDim.x) * epb;
+    const int ne = min(epb, count - g0);
+    if ((int)threadIdx.x < ne) {
+        const int g = g0 + threadIdx.x;
+        const int k = (MODE == MB_MATVEC) ? g : colour_elem(m, g, col);
+        s_k[threadIdx.x] = k;
+        if (MODE != MB_INV)
+            for (int f = 0; f < nface; ++f) s_n[threadIdx.x][f] = neighbour(m, k, f >> 1, (f & 1) ? 1 : -1);
+    }
+    __syncthreads();
+    if (MODE != MB_INV) {
+        for (int t = threadIdx.x; t < epb * nx * nb; t += blockDim.x) {
+            const int e = t / (nx * nb);
+            const int rem = t - e * nx * nb;
+            const int f = rem / nb, j = rem - f * nb;
+            double v = 0.0;
+            if (e < ne) v = x[(size_t)j * m.Ne + (f < nface ? s_n[e][f] : s_k[e])];
+            s_x[t] = v;
+        }
+    }
+    if (MODE != MB_MATVEC) {
+        for (int t = threadIdx.x; t < epb * nb; t += blockDim.x) {
+            const int e = t / nb, j = t - e * nb;
+            s_t[t] = (e < ne) ? r[(size_t)j * m.Ne + s_k[e]] : 0.0;
+        }
+    }
+    __syncthreads();
+    const int tpe = nb / 2;
+    const int e = threadIdx.x / tpe;
+    const int row = (threadIdx.x - e * tpe) * 2;
+    const bool active = e < ne;
+    const size_t nn = (size_t)nb * nb;
+    double a0 = 0.0, a1 = 0.0;
+    if (MODE != MB_INV && active) {
+        const int k = s_k[e];
+        for (int f = 0; f < nx; ++f) {
+            const double *blk = (f < nface) ? O + ((size_t)k * nface + f) * nn : D + (size_t)k * nn;
+            blk += row;
+            const double *xv = s_x + ((size_t)e * nx + f) * nb;
+            int j = 0;
+            for (; j + 4 <= nb; j += 4) {
+                const double2 v0 = *reinterpret_cast<const double2 *>(blk + (size_t)j * nb);
+                const double2 v1 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 1) * nb);
+                const double2 v2 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 2) * nb);
+                const double2 v3 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 3) * nb);
+                a0 += (v0.x * xv[j] + v1.x * xv[j + 1]) + (v2.x * xv[j + 2] + v3.x * xv[j + 3]);
+                a1 += (v0.y * xv[j] + v1.y * xv[j + 1]) + (v2.y * xv[j + 2] + v3.y * xv[j + 3]);
+            }
+            for (; j < nb; ++j) {
+                const double2 v0 = *reinterpret_cast<const double2 *>(blk + (size_t)j * nb);
+                a0 += v0.x * xv[j];
+                a1 += v0.y * xv[j];
+            }
+        }
+    }
+    if (MODE == MB_MATVEC) {
+        if (active) {
+            const int k = s_k[e];
+            y[(size_t)row * m.Ne + k] = a0;
+            y[(size_t)(row + 1) * m.Ne + k] = a1;
+        }
+        return;
+    }
+    if (MODE == MB_NBR_INV && active) {
+        s_t[e * nb + row] -= a0;
+        s_t[e * nb + row + 1] -= a1;
+    }
+    __syncthreads();
+    if (!active) return;
+    const double *inv = Inv + (size_t)(g0 + e) * nn + row;
+    const double *tv = s_t + e * nb;
+    double b0 = 0.0, b1 = 0.0;
+    int j = 0;
+    for (; j + 4 <= nb; j += 4) {
+        const double2 v0 = *reinterpret_cast<const double2 *>(inv + (size_t)j * nb);
+        const double2 v1 = *reinterpret_cast<const double2 *>(inv + (size_t)(j + 1) * nb);
+        const double2 v2 = *reinterpret_cast<const double2 *>(inv + (size_t)(j + 2) * nb);
+        const double2 v3 = *reinterpret_cast<const double2 *>(inv + (size_t)(j + 3) * nb);
+        b0 += (v0.x * tv[j] + v1.x * tv[j + 1]) + (v2.x * tv[j + 2] + v3.x * tv[j + 3]);
+        b1 += (v0.y * tv[j] + v1.y * tv[j + 1]) + (v2.y * tv[j + 2] + v3.y * tv[j + 3]);
+    }
+    for (; j < nb; ++j) {
+        const double2 v0 = *reinterpret_cast<const double2 *>(inv + (size_t)j * nb);
+        b0 += v0.x * tv[j];
+        b1 += v0.y * tv[j];
+    }
+    const int k = s_k[e];
+    y[(size_t)row * m.Ne + k] = b0;
+    y[(size_t)(row + 1) * m.Ne + k] = b1;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES cycle bookkeeping (one lane): Givens rotations of the Hessenberg
+// column, convergence and breakdown, back substitution
+// ---------------------------------------------------------------------------
+
+__global__ void k_mb_gm_init(double *gm, double tol) {
+    if (threadIdx.x != 0) return;
+    const double beta = sqrt(gm[GM_N2]);
+    for (int i = 0; i <= kMaxIt; ++i) gm[GM_G + i] = 0.0;
+    gm[GM_G] = beta;
+    gm[GM_TARGET] = tol * beta;
+    gm[GM_DONE] = (beta == 0.0) ? 1.0 : 0.0;
+    gm[GM_JEND] = 0.0;
+}
+
+__global__ void k_mb_gm_step(double *gm, int j, int m) {
+    if (threadIdx.x != 0 || gm[GM_DONE] != 0.0) return;
+    double *H = gm + GM_H;  // H[i + 9 jj]
+    for (int i = 0; i <= j; ++i) H[i + 9 * j] = gm[GM_H1 + i] + gm[GM_H2 + i];
+    const double hn = sqrt(gm[GM_N2]);
+    H[j + 1 + 9 * j] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double cs = gm[GM_CS + i], sn = gm[GM_SN + i];
+        const double t = cs * H[i + 9 * j] + sn * H[i + 1 + 9 * j];
+        H[i + 1 + 9 * j] = -sn * H[i + 9 * j] + cs * H[i + 1 + 9 * j];
+        H[i + 9 * j] = t;
+    }
+    const double den = hypot(H[j + 9 * j], H[j + 1 + 9 * j]);
+    const double cs = H[j + 9 * j] / den, sn = H[j + 1 + 9 * j] / den;
+    gm[GM_CS + j] = cs;
+    gm[GM_SN + j] = sn;
+    H[j + 9 * j] = den;
+    H[j + 1 + 9 * j] = 0.0;
+    const double gj = gm[GM_G + j];
+    gm[GM_G + j + 1] = -sn * gj;
+    gm[GM_G + j] = cs * gj;
+    const double res = fabs(gm[GM_G + j + 1]);
+    if (hn == 0.0 || res <= gm[GM_TARGET] || j == m - 1) {
+        gm[GM_DONE] = 1.0;
+        gm[GM_JEND] = (double)(j + 1);
+    }
+}
+
+__global__ void k_mb_gm_solve(double *gm) {
+    if (threadIdx.x != 0) return;
+    const int jend = (int)gm[GM_JEND];
+    const double *H = gm + GM_H;
+    for (int i = kMaxIt - 1; i >= 0; --i) {
+        if (i >= jend) {
+            gm[GM_Y + i] = 0.0;
+            continue;
+        }
+        double t = gm[GM_G + i];
+        for (int k = i + 1; k < jend; ++k) t -= H[i + 9 * k] * gm[GM_Y + k];
+        gm[GM_Y + i] = t / H[i + 9 * i];
+    }
+}
+
+// yout = yin - sum_{i < jend} y_i Z_i  (yin null: yout = the sum)
+__global__ void __launch_bounds__(kThreads) k_mb_update(size_t n, const double *__restrict__ Z,
+                                                        const double *__restrict__ gm, const double *yin,
+                                                        double *yout) {
+    const int jend = (int)gm[GM_JEND];
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        double d = 0.0;
+        for (int i = 0; i < jend; ++i) d += gm[GM_Y + i] * Z[(size_t)i * n + t];
+        yout[t] = yin ? yin[t] - d : d;
+    }
+}
+
+unsigned grid_1d(size_t n) {
+    const size_t g = (n + kThreads - 1) / kThreads;
+    return (unsigned)std::min<size_t>(g, 8192);
+}
+
+template <int MODE>
+hipError_t launch_rows(const frpmg_ctx *ctx, const Mbnk &mb, int col, const double *Inv, const double *x,
+                       const double *r, double *y, hipStream_t s) {
+    const int nb = mb.nb;
+    if (nb % 2 || nb < 4 || nb > 128) return hipErrorInvalidValue;
+    const int tpe = nb / 2;
+    const int epb = std::min(64, std::max(1, kThreads / tpe));
+    const int count = (MODE == MB_MATVEC) ? mb.Ne : mb.Ne / 2;
+    const size_t lds = ((size_t)epb * (mb.nface + 1) * nb + (size_t)epb * nb) * sizeof(double);
+    const dim3 grid((count + epb - 1) / epb);
+    const dim3 block((epb * tpe + 63) / 64 * 64);
+    hipLaunchKernelGGL((k_mb_rows<MODE>), grid, block, lds, s, ctx->mesh, nb, mb.nface, epb, col, count, mb.D, mb.O,
+                       Inv, x, r, y);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t mb_perturb(const frpmg_ctx *ctx, const Mbnk &mb, const double *dq, int p0, int cnt, hipStream_t s) {
+    const Level &L = ctx->lv[mb.level];
+    if (cnt < 1 || (size_t)mb.nb * cnt > 65535) return hipErrorInvalidValue;
+    const dim3 grid((ctx->mesh.Ne + kThreads - 1) / kThreads, mb.nb * cnt);
+    hipLaunchKernelGGL(k_mb_perturb, grid, dim3(kThreads), 0, s, ctx->mesh, mb.nb, L.Np, ctx->phys, mb.stride[0],
+                       mb.stride[1], mb.stride[2], p0, cnt, dq, mb.qb);
+    return hipGetLastError();
+}
+
+hipError_t mb_extract(const frpmg_ctx *ctx, const Mbnk &mb, const double *dq, const double *r0, int p0, int cnt,
+                        hipStream_t s) {
+    const Level &L = ctx->lv[mb.level];
+    const MeshK &m = ctx->mesh;
+    int members = mb.nb;
+    for (int a = 0; a < ctx->dim; ++a) members *= m.n[a] / mb.stride[a];
+    if (cnt < 1 || (size_t)cnt * mb.nface > 65535) return hipErrorInvalidValue;
+    const dim3 grid((members + kThreads - 1) / kThreads, cnt * mb.nface);
+    hipLaunchKernelGGL(k_mb_extract, grid, dim3(kThreads), 0, s, m, mb.nb, L.Np, ctx->phys, mb.stride[0],
+                       mb.stride[1], mb.stride[2], p0, cnt, mb.nface, dq, r0, mb.rb, mb.O);
+    return hipGetLastError();
+}
+
+hipError_t mb_gather_red(const frpmg_ctx *ctx, const Mbnk &mb, hipStream_t s) {
+    hipLaunchKernelGGL(k_mb_gather, dim3(mb.Ne / 2), dim3(kThreads), 0, s, ctx->mesh, mb.nb, 0, mb.D, mb.Rinv);
+    return hipGetLastError();
+}
+
+hipError_t mb_schur(const frpmg_ctx *ctx, const Mbnk &mb, hipStream_t s) {
+    const size_t lds = (size_t)mb.nb * mb.nb * sizeof(double);
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_mb_schur, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mb_schur, dim3(mb.Ne / 2), dim3(kThreads), lds, s, ctx->mesh, mb.nb, mb.nface, mb.D, mb.O,
+                       mb.Rinv, mb.Binv);
+    return hipGetLastError();
+}
+
+hipError_t mb_matvec(const frpmg_ctx *ctx, const Mbnk &mb, const double *x, double *y, hipStream_t s) {
+    return launch_rows<MB_MATVEC>(ctx, mb, 0, nullptr, x, nullptr, y, s);
+}
+
+hipError_t mb_ilu(const frpmg_ctx *ctx, const Mbnk &mb, const double *r, double *z, hipStream_t s) {
+    hipError_t e = launch_rows<MB_INV>(ctx, mb, 0, mb.Rinv, nullptr, r, z, s);  // w_r = D_r^{-1} r_r
+    if (e != hipSuccess) return e;
+    e = launch_rows<MB_NBR_INV>(ctx, mb, 1, mb.Binv, z, r, z, s);  // z_b = U_b^{-1} (r_b - O_br w_r)
+    if (e != hipSuccess) return e;
+    return launch_rows<MB_NBR_INV>(ctx, mb, 0, mb.Rinv, z, r, z, s);  // z_r = D_r^{-1} (r_r - O_rb z_b)
+}
+
+hipError_t mb_sweep(frpmg_ctx *ctx, const Mbnk &mb, const double *G, const double *Yin, double *Yout, double tol,
+                      int maxit, hipStream_t s) {
+    if (maxit < 1 || maxit > kMaxIt || maxit > mb.mmax) return hipErrorInvalidValue;
+    const size_t N = mb.N;
+    double *gm = mb.gm;
+    hipError_t e = vec_dot_normalize(ctx, N, G, gm + GM_N2, mb.V, s);  // v_0 = G / ||G||
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mb_gm_init, dim3(1), dim3(64), 0, s, gm, tol);
+    for (int j = 0; j < maxit; ++j) {
+        double *vj = mb.V + (size_t)j * N;
+        double *zj = mb.Z + (size_t)j * N;
+        if ((e = mb_ilu(ctx, mb, vj, zj, s)) != hipSuccess) return e;
+        if ((e = mb_matvec(ctx, mb, zj, mb.w, s)) != hipSuccess) return e;
+        if ((e = vec_mdot(ctx, N, j + 1, mb.V, N, mb.w, gm + GM_H1, s)) != hipSuccess) return e;
+        if ((e = vec_gemv_sub(N, j + 1, mb.V, N, gm + GM_H1, mb.w, s)) != hipSuccess) return e;
+        if ((e = vec_mdot(ctx, N, j + 1, mb.V, N, mb.w, gm + GM_H2, s)) != hipSuccess) return e;
+        if ((e = vec_gemv_sub(N, j + 1, mb.V, N, gm + GM_H2, mb.w, s)) != hipSuccess) return e;
+        if ((e = vec_dot_normalize(ctx, N, mb.w, gm + GM_N2, mb.V + (size_t)(j + 1) * N, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_mb_gm_step, dim3(1), dim3(64), 0, s, gm, j, maxit);
+    }
+    hipLaunchKernelGGL(k_mb_gm_solve, dim3(1), dim3(64), 0, s, gm);
+    hipLaunchKernelGGL(k_mb_update, dim3(grid_1d(N)), dim3(kThreads), 0, s, N, mb.Z, gm, Yin, Yout);
+    return hipGetLastError();
+}
+
+}  // namespace frpmg

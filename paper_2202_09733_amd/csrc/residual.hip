@@ -32,6 +32,7 @@
 // arithmetic, so R(0) = 0 exactly.
 //
 // The element-Jacobi blocks are formed element-locally (k_ej_form, below).
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -102,40 +103,12 @@ struct Shape {
     }
 };
 
-// k / n[a] by the rounded-up reciprocal (exact while k n[a] < 2^40, which
-// context creation checks): a multiply instead of a runtime division
-__device__ __forceinline__ int div_axis(const MeshK &m, int k, int a) {
-    return (int)(((unsigned long long)(unsigned)k * m.rcp[a]) >> 40);
-}
-
-__device__ __forceinline__ void coords(const MeshK &m, int k, int c[3]) {
-    const int r = div_axis(m, k, 0);
-    c[0] = k - r * m.n[0];
-    c[2] = div_axis(m, r, 1);
-    c[1] = r - c[2] * m.n[1];
-}
-
-__device__ __forceinline__ int neighbour(const MeshK &m, int k, int a, int s) {
-    int c[3];
-    coords(m, k, c);
-    int x = c[a] + s;
-    if (x < 0) x += m.n[a];
-    if (x >= m.n[a]) x -= m.n[a];
-    c[a] = x;
-    return c[0] + m.n[0] * (c[1] + m.n[1] * c[2]);
-}
-
 struct SrcK {
     const double *dq;
     const double *v;
     Scal alpha;
     int Np;
 };
-
-// Finite-difference step of one perturbed entry: 1e-7 max(1, |q_inf + dq|).
-__device__ __forceinline__ double fd_step(double qinf_v, double dqv) {
-    return 1e-7 * fmax(1.0, fabs(qinf_v + dqv));
-}
 
 template <int MODE>
 __device__ __forceinline__ double load_state(const SrcK &s, const MeshK &m, int v, int i, int k, double alpha) {
@@ -810,23 +783,29 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_ej_form(MeshK m, Ops1D 
     }
 }
 
+// One evaluation on mesh m with face buffers Jp, Fs ([dim][nv][NF][m.Ne]).
 template <int DIM, int P, int MODE, int OUT>
-hipError_t run(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, const FaceSave *save, hipStream_t s) {
+hipError_t run_on(const frpmg_ctx *ctx, const Level &L, const MeshK &m, double *Jp, double *Fs,
+                  const ResidualArgs &a, const FaceSave *save, hipStream_t s) {
     using S = Shape<DIM, P>;
-    const MeshK &m = ctx->mesh;
     SrcK src{a.dq, a.v, a.alpha, S::NP};
     const dim3 g1((m.Ne + S::EBF - 1) / S::EBF);
     if (save) {
-        hipLaunchKernelGGL((k_faces<DIM, P, MODE, true>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, L.Jp,
-                           L.Fs, *save);
+        hipLaunchKernelGGL((k_faces<DIM, P, MODE, true>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, Jp, Fs,
+                           *save);
     } else {
-        hipLaunchKernelGGL((k_faces<DIM, P, MODE, false>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, L.Jp,
-                           L.Fs, FaceSave{nullptr, nullptr, nullptr, nullptr});
+        hipLaunchKernelGGL((k_faces<DIM, P, MODE, false>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, Jp,
+                           Fs, FaceSave{nullptr, nullptr, nullptr, nullptr});
     }
     OutK o{a.r, a.r0, a.x, a.v, a.sigma};
     hipLaunchKernelGGL((k_volume<DIM, P, MODE, OUT>), dim3((m.Ne + S::EB - 1) / S::EB), dim3(S::NT), 0, s, m, src,
-                       L.ops, ctx->phys, L.Jp, L.Fs, o);
+                       L.ops, ctx->phys, Jp, Fs, o);
     return hipGetLastError();
+}
+
+template <int DIM, int P, int MODE, int OUT>
+hipError_t run(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, const FaceSave *save, hipStream_t s) {
+    return run_on<DIM, P, MODE, OUT>(ctx, L, ctx->mesh, L.Jp, L.Fs, a, save, s);
 }
 
 template <int DIM, int P>
@@ -840,7 +819,7 @@ hipError_t dispatch_modes(const frpmg_ctx *ctx, const Level &L, const ResidualAr
 }
 
 template <int DIM, int P>
-hipError_t form(const frpmg_ctx *ctx, const Level &L, const double *dq, double sigma, hipStream_t s) {
+hipError_t form(const frpmg_ctx *ctx, const Level &L, const double *dq, double sigma, double *out, hipStream_t s) {
     using S = Shape<DIM, P>;
     const MeshK &m = ctx->mesh;
     const FaceSave sv{L.fQs, L.fQp, L.fSn, L.fGt};
@@ -854,7 +833,7 @@ hipError_t form(const frpmg_ctx *ctx, const Level &L, const double *dq, double s
     const int ncb = (L.nb + S::EB - 1) / S::EB;
     const size_t nblk = (size_t)m.Ne * ncb;
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    FormK fk{dq, sv, L.r0, L.blk64, sigma, L.nb};
+    FormK fk{dq, sv, L.r0, out, sigma, L.nb};
     hipLaunchKernelGGL((k_ej_form<DIM, P>), dim3((unsigned)nblk), dim3(S::NT), 0, s, m, L.ops, ctx->phys, fk);
     return hipGetLastError();
 }
@@ -880,21 +859,57 @@ hipError_t launch_residual(const frpmg_ctx *ctx, int level, const ResidualArgs &
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s) {
+hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s,
+                          double *out) {
     const Level &L = ctx->lv[level];
-    if (!L.fQs || !L.fQp || !L.fSn || !L.fGt || !L.blk64) return hipErrorInvalidValue;
+    if (!out) out = L.blk64;
+    if (!L.fQs || !L.fQp || !L.fSn || !L.fGt || !out || !L.r0) return hipErrorInvalidValue;
     if (ctx->dim == 2) {
         switch (L.P) {
-            case 2: return form<2, 2>(ctx, L, dq, sigma, s);
-            case 3: return form<2, 3>(ctx, L, dq, sigma, s);
-            case 4: return form<2, 4>(ctx, L, dq, sigma, s);
-            case 5: return form<2, 5>(ctx, L, dq, sigma, s);
+            case 2: return form<2, 2>(ctx, L, dq, sigma, out, s);
+            case 3: return form<2, 3>(ctx, L, dq, sigma, out, s);
+            case 4: return form<2, 4>(ctx, L, dq, sigma, out, s);
+            case 5: return form<2, 5>(ctx, L, dq, sigma, out, s);
         }
     } else {
         switch (L.P) {
-            case 2: return form<3, 2>(ctx, L, dq, sigma, s);
-            case 3: return form<3, 3>(ctx, L, dq, sigma, s);
-            case 4: return form<3, 4>(ctx, L, dq, sigma, s);
+            case 2: return form<3, 2>(ctx, L, dq, sigma, out, s);
+            case 3: return form<3, 3>(ctx, L, dq, sigma, out, s);
+            case 4: return form<3, 4>(ctx, L, dq, sigma, out, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_residual_batch(const frpmg_ctx *ctx, int level, int batch, const double *dq, double *r,
+                                 double *Jp, double *Fs, hipStream_t s) {
+    const Level &L = ctx->lv[level];
+    MeshK m = ctx->mesh;
+    if (batch < 1 || (ctx->dim == 3 && batch != 1)) return hipErrorInvalidValue;
+    // copy b occupies elements b Ne .. (b + 1) Ne - 1: the third coordinate of
+    // a 2D element, which no face or neighbour lookup changes
+    const unsigned long long ne = (unsigned long long)m.Ne * (unsigned long long)batch;
+    if (ne > 0x7fffffffULL || ne * (unsigned long long)std::max(m.n[0], m.n[1]) >= (1ULL << 40))
+        return hipErrorInvalidValue;
+    m.Ne = (int)ne;
+    if (ctx->dim == 2) m.n[2] = batch;
+    ResidualArgs a;
+    a.src = SRC_PLAIN;
+    a.dq = dq;
+    a.out = OUT_R;
+    a.r = r;
+    if (ctx->dim == 2) {
+        switch (L.P) {
+            case 2: return run_on<2, 2, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
+            case 3: return run_on<2, 3, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
+            case 4: return run_on<2, 4, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
+            case 5: return run_on<2, 5, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
+        }
+    } else {
+        switch (L.P) {
+            case 2: return run_on<3, 2, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
+            case 3: return run_on<3, 3, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
+            case 4: return run_on<3, 4, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
         }
     }
     return hipErrorInvalidValue;

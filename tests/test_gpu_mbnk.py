@@ -1,0 +1,231 @@
+"""MBNK smoother on the GPU against the oracle (oracle/mbnk.py): assembled
+blocks, block-sparse product, red-black ILU0 solve, GMRES sweep, the V-cycle
+with MBNK on its coarsest level, and stage solves that use it."""
+import numpy as np
+import pytest
+
+from paper_2202_09733_amd import capi
+from paper_2202_09733_amd import workloads as W
+from gpu_util import announce, rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+U = 2.2e-16
+
+
+def _spec(dim, n, Ma, seed):
+    rng = np.random.default_rng(seed)
+    h = [rng.uniform(0.02, 0.2, n[a]) for a in range(dim)]
+    qinf, _ = W.reference_state(dim, Ma, u_dir=(0.8, 0.6, 0.0))
+    return dict(dim=dim, n=n, h=h, gamma=1.4, mu=2e-3, Pr=0.72, tau=0.1, qinf=qinf), rng
+
+
+def _block_bar(fr, ol, dq, level, scale):
+    """Difference allowed between two independently FD-formed blocks: the
+    rounding of R amplified by the step 1e-7 max(1, |q|)."""
+    rq = ol.residual(dq)
+    dR = rel(fr.residual(level, fr.to_dev(dq)).cpu().numpy(), rq)
+    return max(1e-10, 10 * 2 * max(dR, U) * np.abs(rq).max() / 1e-7 / scale)
+
+
+CASES = [(2, (10, 8), 1, 30.0), (2, (6, 4), 2, 50.0), (3, (4, 4, 4), 1, 20.0)]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=["2d_p1", "2d_p2", "3d_p1"])
+def factored(request, orc):
+    require_gpu()
+    from oracle import mbnk as MB
+    dim, n, p, sigma = request.param
+    announce("mbnk factor dim=%d n=%s p=%d" % (dim, n, p))
+    spec, rng = _spec(dim, n, 0.1, seed=500 + p + dim)
+    fr = capi.FR(spec["dim"], spec["n"], spec["h"], [p], spec["gamma"], spec["mu"], spec["Pr"], spec["tau"],
+                 spec["qinf"])
+    ol = orc.Level(p=p, **spec)
+    dq = W.random_state(ol.shape, rng, spec["qinf"], amp=0.02)
+    A = MB.assemble(ol, dq, sigma)
+    f = MB.ilu0(A)
+    fr.mbnk_factor(0, fr.to_dev(dq), sigma)
+    return dict(fr=fr, ol=ol, dq=dq, A=A, f=f, rng=rng, sigma=sigma, MB=MB)
+
+
+def test_assembled_blocks_parity(factored):
+    fr, ol, A = factored["fr"], factored["ol"], factored["A"]
+    D, O = fr.mbnk_blocks()
+    scale = max(np.abs(A.D).max(), np.abs(A.O).max())
+    bar = _block_bar(fr, ol, factored["dq"], 0, scale)
+    eD = np.abs(D - A.D).max() / scale
+    eO = np.abs(O - A.O).max() / scale
+    print("blocks: max |D - D_ref| / max|A| = %.2e, |O - O_ref| %.2e (bar %.2e)" % (eD, eO, bar))
+    assert eD <= bar and eO <= bar
+    # every off-diagonal slot was written: no block is left all zero
+    assert np.all(np.abs(O).reshape(ol.Ne, O.shape[1], -1).max(axis=2) > 0)
+
+
+def test_matvec_ilu_and_sweep_parity(factored):
+    fr, ol, A, f, MB, rng = (factored[k] for k in ("fr", "ol", "A", "f", "MB", "rng"))
+    x = rng.standard_normal(ol.shape)
+    y = fr.mbnk_matvec(fr.to_dev(x)).cpu().numpy()
+    e_mv = rel(y, MB.matvec(A, x))
+    z = fr.mbnk_ilu_solve(fr.to_dev(x)).cpu().numpy()
+    e_ilu = rel(z, MB.ilu0_solve(f, x))
+    d = fr.mbnk_solve(fr.to_dev(x), tol=0.1, maxit=5).cpu().numpy()
+    e_sw = rel(d, MB.mbnk_sweep(f, x))
+    d8 = fr.mbnk_solve(fr.to_dev(x), tol=1e-12, maxit=8).cpu().numpy()
+    e_sw8 = rel(d8, MB.mbnk_sweep(f, x, tol=1e-12, maxit=8))
+    print("matvec %.2e, ilu %.2e, sweep(5, 1e-1) %.2e, sweep(8, 1e-12) %.2e" % (e_mv, e_ilu, e_sw, e_sw8))
+    # both sides form their blocks by finite differences (see the block bar)
+    assert e_mv <= 1e-6 and e_ilu <= 1e-6 and e_sw <= 1e-6 and e_sw8 <= 1e-6
+
+
+def test_ilu_reproduces_red_rows_and_sweep_reduces_residual(factored):
+    """Properties of the GPU's own factorisation: L U = A on the red rows (the
+    fill ILU0 drops couples black elements only), so A (LU)^{-1} r = r there;
+    the sweep's delta meets its relative tolerance whenever it stops early."""
+    fr, ol, MB, rng = (factored[k] for k in ("fr", "ol", "MB", "rng"))
+    r = rng.standard_normal(ol.shape)
+    z = fr.mbnk_ilu_solve(fr.to_dev(r))
+    Az = fr.mbnk_matvec(z).cpu().numpy().reshape(ol.nb, ol.Ne)
+    red = np.array([MB.red(ol, k) for k in range(ol.Ne)])
+    R = r.reshape(ol.nb, ol.Ne)
+    assert rel(Az[:, red], R[:, red]) <= 1e-11
+    assert rel(Az[:, ~red], R[:, ~red]) > 1e-8  # the dropped fill shows on black rows
+    def solve(tol, maxit):
+        d = fr.mbnk_solve(fr.to_dev(r), tol=tol, maxit=maxit)
+        return d.cpu().numpy(), np.linalg.norm(r - fr.mbnk_matvec(d).cpu().numpy()) / np.linalg.norm(r)
+    d1, res1 = solve(0.0, 1)
+    d8, res8 = solve(0.0, 8)
+    assert res8 < res1  # GMRES minimises the residual over a growing space
+    # a tolerance just above the one-iteration residual stops the cycle there
+    d_stop, res_stop = solve(res1 * 1.01, 8)
+    assert np.array_equal(d_stop, d1) and res_stop <= res1 * 1.01
+    # zero right-hand side: delta = 0 exactly; repeated calls agree bitwise
+    zero = fr.mbnk_solve(fr.to_dev(np.zeros(ol.shape))).cpu().numpy()
+    assert not np.any(zero)
+    a = fr.mbnk_solve(fr.to_dev(r)).cpu().numpy()
+    b = fr.mbnk_solve(fr.to_dev(r)).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_blocks_sampled_config2_coarse(orc):
+    """Full-size coarse level of the config-2 workload (64 x 64, p=2): the
+    formation takes several batched residual launches; sampled block columns
+    against single-element differences of the oracle's residual."""
+    require_gpu()
+    from oracle import mbnk as MB
+    announce("mbnk factor config2 coarse p2 (sampled)")
+    wl = W.config2()
+    fr = capi.FR.from_workload(wl, levels=[wl.p0, wl.p1])
+    L1 = orc.Level(**wl.level_kwargs(wl.p1))
+    q1 = orc.restrict(wl.dq, 2, wl.p0 + 1, wl.p1 + 1)
+    sigma = 1.0 / wl.dt + 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
+    fr.mbnk_factor(1, fr.to_dev(q1), sigma)
+    D, O = fr.mbnk_blocks()
+    r0 = L1.residual(q1)
+    bar = _block_bar(fr, L1, q1, 1, np.abs(D).max())
+    rng = np.random.default_rng(9)
+    nb, Ne = L1.nb, L1.Ne
+    worst = 0.0
+    for m in rng.choice(Ne, 4, replace=False):
+        for j in rng.choice(nb, 2, replace=False):
+            v, i = divmod(int(j), L1.Np)
+            qp = q1.copy()
+            hj = 1e-7 * max(1.0, abs(L1.qinf[v] + q1[v, i, m]))
+            qp[v, i, m] = q1[v, i, m] + hj
+            h = qp[v, i, m] - q1[v, i, m]
+            d = ((L1.residual(qp) - r0) / h).reshape(nb, Ne)
+            col_d = sigma * (np.arange(nb) == j) - d[:, m]
+            worst = max(worst, np.abs(D[m][:, j] - col_d).max())
+            for a in range(2):
+                for s in (-1, 1):
+                    k = MB.face_neighbour(L1, m, a, s)
+                    worst = max(worst, np.abs(O[k, MB.slot(a, -s)][:, j] + d[:, k]).max())
+    worst /= np.abs(D).max()
+    print("config-2 coarse blocks, sampled columns: worst difference / max|D| = %.2e (bar %.2e)" % (worst, bar))
+    assert worst <= bar
+
+
+@pytest.mark.parametrize("ps", [(2, 1), (3, 2, 1)])
+def test_pmg_apply_mbnk_parity(orc, ps):
+    require_gpu()
+    from oracle import multilevel as ML
+    announce("pmg apply MBNK coarse p%s" % (ps,))
+    wl = W.make_vortical_workload(n=(8, 8), p0=ps[0], p1=ps[1], dt_factor=1000.0)
+    fr = capi.FR.from_workload(wl, levels=list(ps))
+    levels = [orc.Level(**wl.level_kwargs(p)) for p in ps]
+    sigA = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
+    sigS = 1.0 / wl.dt + sigA
+    facs = ML.hierarchy_factors(levels, wl.dq, sigS)
+    ilu = ML.coarse_mbnk(levels, wl.dq, sigS)
+    n = tuple([2] * (len(ps) - 1) + [3])
+    pm = ML.MultiPMG(levels, facs, ML.MultiPMGParams(sigma_D=sigA, n=n), coarse_ilu=ilu)
+    rq = levels[0].residual(wl.dq)
+    pm.set_point(wl.dq, rq)
+    rng = np.random.default_rng(16)
+    X = rng.standard_normal(levels[0].shape)
+    X /= np.linalg.norm(X)
+    Y_ref = pm.apply(X)
+    qs = [wl.dq]
+    for l in range(1, len(ps)):
+        qs.append(orc.restrict(qs[-1], 2, ps[l - 1] + 1, ps[l] + 1))
+    for l in range(len(ps) - 1):
+        fr.ej_factor(l, fr.to_dev(qs[l]), sigS)
+    fr.mbnk_factor(len(ps) - 1, fr.to_dev(qs[-1]), sigS)
+    fr.pmg_set_point(fr.to_dev(wl.dq), fr.to_dev(rq))
+    Y = fr.pmg_apply(fr.to_dev(X), sigA, n0=n[0], n1=n[1], n2=n[-1], coarse_mode=capi.COARSE_MBNK).cpu().numpy()
+    # the EJ-coarse cycle of the same hierarchy differs: MBNK changes the coarsest solve
+    pm_ej = ML.MultiPMG(levels, facs, ML.MultiPMGParams(sigma_D=sigA, n=n))
+    pm_ej.set_point(wl.dq, rq)
+    e = rel(Y, Y_ref)
+    print("p%s MBNK-coarse cycle vs oracle %.2e; vs the EJ-coarse cycle %.2e" % (ps, e, rel(Y, pm_ej.apply(X))))
+    assert e <= 1e-6
+    assert rel(Y_ref, pm_ej.apply(X)) > 1e-4
+
+
+@pytest.mark.parametrize("solver", ["jfnk", "pmg"])
+def test_stage_mbnk_matches_oracle(orc, solver):
+    require_gpu()
+    from oracle import multilevel as ML
+    announce("stage MBNK coarse, %s solver" % solver)
+    wl = W.make_bump_workload(n=(8, 8), p0=3, p1=1, Ma=0.1, dt_factor=10.0 if solver == "jfnk" else 3.0, seed=21)
+    ps = (3, 1)
+    fr = capi.FR.from_workload(wl, levels=list(ps))
+    levels = [orc.Level(**wl.level_kwargs(p)) for p in ps]
+    if solver == "jfnk":
+        cfg = capi.stage_config_for(wl, coarse_smoother=capi.SMOOTHER_MBNK, tol=1e-10)
+        q, st = fr.solve_stage(cfg, fr.to_dev(wl.dq))
+        q_ref, so = ML.esdirk_stage_ml(levels, wl.dq, wl.dt, wl.a_ii, coarse="mbnk", tol=1e-10)
+        its, its_ref = st["gmres_iters"], so.gmres_iters
+    else:
+        cfg = capi.stage_config_for(wl, coarse_smoother=capi.SMOOTHER_MBNK, solver=capi.SOLVER_PMG, tol=1e-10,
+                                    max_ptc=300, n1=4)
+        q, st = fr.solve_stage(cfg, fr.to_dev(wl.dq))
+        q_ref, so = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), tol=1e-10, max_vcycles=300,
+                                           coarse="mbnk")
+        its, its_ref = st["ptc_iters"], so.vcycles
+    d = np.linalg.norm(q.cpu().numpy() - q_ref) / np.linalg.norm(q_ref - wl.dq)
+    print("%s with MBNK coarse: GPU %d iterations, oracle %d; |q - q_ref| / |update| = %.2e"
+          % (solver, its, its_ref, d))
+    assert st["converged"] == 1 and so.converged
+    assert abs(its - its_ref) <= 1
+    assert d <= 1e-8
+
+
+def test_stage_mbnk_config2_and_graphs(orc):
+    """Config-2 stage with MBNK on the p=2 level converges to 1e-8 in the
+    oracle's F; captured Arnoldi steps replay it bitwise."""
+    require_gpu()
+    announce("stage config2 MBNK coarse (eager and graphs)")
+    wl = W.config2()
+    fr = capi.FR.from_workload(wl)
+    dq = fr.to_dev(wl.dq)
+    q, st = fr.solve_stage(capi.stage_config_for(wl, coarse_smoother=capi.SMOOTHER_MBNK), dq)
+    qg, sg = fr.solve_stage(capi.stage_config_for(wl, coarse_smoother=capi.SMOOTHER_MBNK, graphs=1), dq)
+    print("config 2 MBNK coarse: %d PTC / %d FGMRES, %.3f s (setup %.3f s); graphs %.3f s"
+          % (st["ptc_iters"], st["gmres_iters"], st["t_total"], st["t_setup"], sg["t_total"]))
+    L0 = orc.Level(**wl.level_kwargs(wl.p0))
+    R0 = L0.residual(wl.dq)
+    b = wl.dq + wl.a_ii * wl.dt * R0
+    qh = q.cpu().numpy()
+    F = (qh - b) / (wl.a_ii * wl.dt) - L0.residual(qh)
+    assert st["converged"] == 1 and np.linalg.norm(F) / np.linalg.norm(2 * R0) <= 1.5e-8
+    assert np.array_equal(qg.cpu().numpy(), qh) and sg["gmres_iters"] == st["gmres_iters"]
