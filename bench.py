@@ -259,6 +259,49 @@ def hierarchies():
     return out
 
 
+def smoothers():
+    """Coarsest-level smoother (Sec. 3.2: EJ or MBNK) on the config-2 ESDIRK
+    stage for the hierarchies p{4-2}, p{4-2-1} and p{4-1}: one stage each,
+    set-up included, after a warm-up; JFNK-pMG and the pMG nonlinear solver."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    wl = W.config2()
+    out = {}
+    for levels, runs in (
+            ([4, 2, 1], (("p42_ej", dict(pmg_levels=2)),
+                         ("p42_mbnk", dict(pmg_levels=2, coarse_smoother=1)),
+                         ("p42_mbnk_graphs", dict(pmg_levels=2, coarse_smoother=1, graphs=1)),
+                         ("p421_ej", dict(pmg_levels=3)),
+                         ("p421_mbnk", dict(pmg_levels=3, coarse_smoother=1)),
+                         ("pmg_solver_p42_ej", dict(pmg_levels=2, solver=1, max_ptc=1000)),
+                         ("pmg_solver_p42_mbnk", dict(pmg_levels=2, solver=1, max_ptc=1000, coarse_smoother=1)))),
+            ([4, 1], (("p41_ej", dict()),
+                      ("p41_mbnk", dict(coarse_smoother=1))))):
+        fr = capi.FR.from_workload(wl, levels=levels)
+        dq = fr.to_dev(wl.dq)
+        q = fr.empty(0)
+        for key, kw in runs:
+            cfg = capi.stage_config_for(wl, **kw)
+            try:
+                fr.solve_stage(cfg, dq, out=q, raise_on_noconv=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = fr.solve_stage(cfg, dq, out=q, raise_on_noconv=False)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                out[key] = {"dof_per_s": wl.dof() / el, "s_per_stage": el, "t_setup": st["t_setup"],
+                            "ptc_or_vcycles": st["ptc_iters"], "gmres_iters": st["gmres_iters"],
+                            "rel_res": st["rel_res"], "converged": st["converged"]}
+            except capi.FRError as ex:
+                out[key] = {"failed": str(ex)}
+        fr.close()
+        torch.cuda.empty_cache()
+    out["note"] = ("config-2 stage to 1e-8; MBNK: GMRES(5, 1e-1) with red-black ILU0 on the coarsest level, "
+                   "n1 = 2 sweeps; ptc_or_vcycles counts V-cycles for the pMG nonlinear solver")
+    return out
+
+
 def learned_ab(wl, steps=3):
     """The learned coarse correction on the config-2 mesh: pairs harvested by
     the solver from plain-pMG stages and from V-cycles on random directions
@@ -377,9 +420,10 @@ def only_kernel(args):
         torch.cuda.synchronize()
         return
     if args.only_kernel == "stage":
-        # whole stage solves (set-up included) in the requested precision
+        # whole stage solves (set-up included) in the requested precision and coarse smoother
+        sm = capi.SMOOTHER_MBNK if args.coarse_smoother == "mbnk" else capi.SMOOTHER_EJ
         for _ in range(args.reps):
-            _, st = fr.solve_stage(capi.stage_config_for(wl, precision=prec), dq)
+            _, st = fr.solve_stage(capi.stage_config_for(wl, precision=prec, coarse_smoother=sm), dq)
             print("[bench] stage: %d FGMRES, set-up %.3f s, solve %.3f s" % (st["gmres_iters"], st["t_setup"],
                                                                            st["t_solve"]), file=sys.stderr)
         torch.cuda.synchronize()
@@ -422,6 +466,8 @@ def main():
     ap.add_argument("--workload", default="config2", choices=["config2", "config4"],
                     help="workload of the --only-kernel driver")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--coarse-smoother", default="ej", choices=["ej", "mbnk"],
+                    help="coarsest-level smoother of the --only-kernel stage driver")
     ap.add_argument("--tableau", default="esdirk3", choices=["esdirk3", "row3"],
                     help="time-step scheme of the --only-kernel step driver")
     args = ap.parse_args()
@@ -546,6 +592,8 @@ def main():
         result["time_step"] = time_steps()
         print("[bench] p-hierarchies and the pMG nonlinear solver", file=sys.stderr, flush=True)
         result["hierarchies"] = hierarchies()
+        print("[bench] coarse smoothers", file=sys.stderr, flush=True)
+        result["smoothers"] = smoothers()
         print("[bench] learned coarse correction: harvest, train, A/B", file=sys.stderr, flush=True)
         result["learned_coarse"] = learned_ab(wl)
         result["kernels"] = rates

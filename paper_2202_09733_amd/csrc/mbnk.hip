@@ -143,25 +143,34 @@ __global__ void __launch_bounds__(kThreads) k_mb_schur(MeshK m, int nb, int nfac
     }
 }
 
-enum RowMode { MB_MATVEC = 0, MB_INV = 1, MB_NBR_INV = 2 };
+enum RowMode { MB_MATVEC = 0, MB_INV = 1, MB_NBR_INV = 2, MB_MATVEC_BLACK = 3 };
 
-// Block rows of the assembled operator, epb elements per workgroup, each lane
-// two consecutive rows of one element (one 16-byte load per block column):
+// Block rows of the assembled operator, epb elements per workgroup:
 //   MB_MATVEC : y_k = D_k x_k + sum_f O[k][f] x_nbr(k,f)          (every element)
 //   MB_INV    : y_k = Inv_c r_k                                    (colour col)
 //   MB_NBR_INV: y_k = Inv_c (r_k - sum_f O[k][f] x_nbr(k,f))       (colour col)
-// Inv holds one block per pair index c of the colour.
+//   MB_MATVEC_BLACK: the product for x = (L U)^{-1} r: y_k = r_k on red
+//               elements, where the factorisation keeps A's rows exactly
+//               (L = I and U = A there), the product on black ones (pairs c)
+// Inv holds one block per pair index c of the colour.  Each lane owns two
+// consecutive rows of one element and reads them with one 16-byte load per
+// block column; the columns of every block are split into S contiguous
+// ranges on S lane groups (more lanes in flight on the small coarse level),
+// whose partial sums meet in LDS and are added in range order.
 template <int MODE>
-__global__ void __launch_bounds__(kThreads) k_mb_rows(MeshK m, int nb, int nface, int epb, int col, int count,
-                                                      const double *__restrict__ D, const double *__restrict__ O,
+__global__ void __launch_bounds__(kThreads) k_mb_rows(MeshK m, int nb, int nface, int epb, int S, int col,
+                                                      int count, const double *__restrict__ D,
+                                                      const double *__restrict__ O,
                                                       const double *__restrict__ Inv, const double *x,
                                                       const double *__restrict__ r, double *y) {
     extern __shared__ double sh[];
     __shared__ int s_k[64];
     __shared__ int s_n[64][6];
-    const int nx = (MODE == MB_MATVEC) ? nface + 1 : nface;  // staged vectors per element
+    constexpr bool MV = (MODE == MB_MATVEC || MODE == MB_MATVEC_BLACK);
+    const int nx = MV ? nface + 1 : nface;  // staged vectors per element
     double *s_x = sh;                                      // [epb][nx][nb]
     double *s_t = sh + (size_t)epb * (nface + 1) * nb;     // [epb][nb]
+    double *s_p = s_t + (size_t)epb * nb;                  // [epb][S][nb] partial sums
     const int g0 = xcd_block(blockIdx.x, gridDim.x) * epb;
     const int ne = min(epb, count - g0);
     if ((int)threadIdx.x < ne) {
@@ -182,75 +191,97 @@ __global__ void __launch_bounds__(kThreads) k_mb_rows(MeshK m, int nb, int nface
             s_x[t] = v;
         }
     }
-    if (MODE != MB_MATVEC) {
+    if (MODE == MB_MATVEC_BLACK) {
+        // the red element of each pair (k ^ 1): its rows of A z equal r
+        for (int t = threadIdx.x; t < ne * nb; t += blockDim.x) {
+            const int e = t / nb, j = t - e * nb;
+            const size_t idx = (size_t)j * m.Ne + (s_k[e] ^ 1);
+            y[idx] = r[idx];
+        }
+    }
+    if (!MV) {
         for (int t = threadIdx.x; t < epb * nb; t += blockDim.x) {
             const int e = t / nb, j = t - e * nb;
             s_t[t] = (e < ne) ? r[(size_t)j * m.Ne + s_k[e]] : 0.0;
         }
     }
     __syncthreads();
-    const int tpe = nb / 2;
-    const int e = threadIdx.x / tpe;
-    const int row = (threadIdx.x - e * tpe) * 2;
+    const int tpe = nb / 2, lpe = tpe * S;
+    const int e = threadIdx.x / lpe;
+    const int rem = threadIdx.x - e * lpe;
+    const int sg = rem / tpe;
+    const int row = (rem - sg * tpe) * 2;
     const bool active = e < ne;
+    const int cs = (nb + S - 1) / S;
+    const int j0 = min(nb, sg * cs), j1 = min(nb, j0 + cs);
     const size_t nn = (size_t)nb * nb;
-    double a0 = 0.0, a1 = 0.0;
-    if (MODE != MB_INV && active) {
-        const int k = s_k[e];
-        for (int f = 0; f < nx; ++f) {
-            const double *blk = (f < nface) ? O + ((size_t)k * nface + f) * nn : D + (size_t)k * nn;
-            blk += row;
-            const double *xv = s_x + ((size_t)e * nx + f) * nb;
-            int j = 0;
-            for (; j + 4 <= nb; j += 4) {
-                const double2 v0 = *reinterpret_cast<const double2 *>(blk + (size_t)j * nb);
-                const double2 v1 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 1) * nb);
-                const double2 v2 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 2) * nb);
-                const double2 v3 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 3) * nb);
-                a0 += (v0.x * xv[j] + v1.x * xv[j + 1]) + (v2.x * xv[j + 2] + v3.x * xv[j + 3]);
-                a1 += (v0.y * xv[j] + v1.y * xv[j + 1]) + (v2.y * xv[j + 2] + v3.y * xv[j + 3]);
-            }
-            for (; j < nb; ++j) {
-                const double2 v0 = *reinterpret_cast<const double2 *>(blk + (size_t)j * nb);
-                a0 += v0.x * xv[j];
-                a1 += v0.y * xv[j];
+    // partial sums of the S ranges, added in range order by group 0
+    auto reduce = [&](double &a0, double &a1) {
+        if (S == 1) return;
+        if (active) {
+            s_p[((size_t)e * S + sg) * nb + row] = a0;
+            s_p[((size_t)e * S + sg) * nb + row + 1] = a1;
+        }
+        __syncthreads();
+        if (active && sg == 0) {
+            a0 = s_p[(size_t)e * S * nb + row];
+            a1 = s_p[(size_t)e * S * nb + row + 1];
+            for (int q = 1; q < S; ++q) {
+                a0 += s_p[((size_t)e * S + q) * nb + row];
+                a1 += s_p[((size_t)e * S + q) * nb + row + 1];
             }
         }
-    }
-    if (MODE == MB_MATVEC) {
+        __syncthreads();
+    };
+    auto gemv = [&](const double *blk, const double *xv, double &a0, double &a1) {
+        blk += row;
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            const double2 v0 = *reinterpret_cast<const double2 *>(blk + (size_t)j * nb);
+            const double2 v1 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 1) * nb);
+            const double2 v2 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 2) * nb);
+            const double2 v3 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 3) * nb);
+            a0 += (v0.x * xv[j] + v1.x * xv[j + 1]) + (v2.x * xv[j + 2] + v3.x * xv[j + 3]);
+            a1 += (v0.y * xv[j] + v1.y * xv[j + 1]) + (v2.y * xv[j + 2] + v3.y * xv[j + 3]);
+        }
+        for (; j < j1; ++j) {
+            const double2 v0 = *reinterpret_cast<const double2 *>(blk + (size_t)j * nb);
+            a0 += v0.x * xv[j];
+            a1 += v0.y * xv[j];
+        }
+    };
+    double a0 = 0.0, a1 = 0.0;
+    if (MODE != MB_INV) {
         if (active) {
+            const int k = s_k[e];
+            for (int f = 0; f < nx; ++f) {
+                const double *blk = (f < nface) ? O + ((size_t)k * nface + f) * nn : D + (size_t)k * nn;
+                gemv(blk, s_x + ((size_t)e * nx + f) * nb, a0, a1);
+            }
+        }
+        reduce(a0, a1);
+    }
+    if (MV) {
+        if (active && sg == 0) {
             const int k = s_k[e];
             y[(size_t)row * m.Ne + k] = a0;
             y[(size_t)(row + 1) * m.Ne + k] = a1;
         }
         return;
     }
-    if (MODE == MB_NBR_INV && active) {
+    if (MODE == MB_NBR_INV && active && sg == 0) {
         s_t[e * nb + row] -= a0;
         s_t[e * nb + row + 1] -= a1;
     }
     __syncthreads();
-    if (!active) return;
-    const double *inv = Inv + (size_t)(g0 + e) * nn + row;
-    const double *tv = s_t + e * nb;
     double b0 = 0.0, b1 = 0.0;
-    int j = 0;
-    for (; j + 4 <= nb; j += 4) {
-        const double2 v0 = *reinterpret_cast<const double2 *>(inv + (size_t)j * nb);
-        const double2 v1 = *reinterpret_cast<const double2 *>(inv + (size_t)(j + 1) * nb);
-        const double2 v2 = *reinterpret_cast<const double2 *>(inv + (size_t)(j + 2) * nb);
-        const double2 v3 = *reinterpret_cast<const double2 *>(inv + (size_t)(j + 3) * nb);
-        b0 += (v0.x * tv[j] + v1.x * tv[j + 1]) + (v2.x * tv[j + 2] + v3.x * tv[j + 3]);
-        b1 += (v0.y * tv[j] + v1.y * tv[j + 1]) + (v2.y * tv[j + 2] + v3.y * tv[j + 3]);
+    if (active) gemv(Inv + (size_t)(g0 + e) * nn, s_t + e * nb, b0, b1);
+    reduce(b0, b1);
+    if (active && sg == 0) {
+        const int k = s_k[e];
+        y[(size_t)row * m.Ne + k] = b0;
+        y[(size_t)(row + 1) * m.Ne + k] = b1;
     }
-    for (; j < nb; ++j) {
-        const double2 v0 = *reinterpret_cast<const double2 *>(inv + (size_t)j * nb);
-        b0 += v0.x * tv[j];
-        b1 += v0.y * tv[j];
-    }
-    const int k = s_k[e];
-    y[(size_t)row * m.Ne + k] = b0;
-    y[(size_t)(row + 1) * m.Ne + k] = b1;
 }
 
 // ---------------------------------------------------------------------------
@@ -328,19 +359,29 @@ unsigned grid_1d(size_t n) {
     return (unsigned)std::min<size_t>(g, 8192);
 }
 
+// Column ranges per block: up to 4, while the launch has fewer than 256k
+// lanes (4 wavefronts per SIMD) and every range keeps at least 4 columns.
+int row_split(int nb, int count) {
+    const int tpe = nb / 2;
+    int S = 1;
+    while (S < 4 && (size_t)count * tpe * S < (256u << 10) && nb / (2 * S) >= 4 && tpe * 2 * S <= kThreads) S *= 2;
+    return S;
+}
+
 template <int MODE>
 hipError_t launch_rows(const frpmg_ctx *ctx, const Mbnk &mb, int col, const double *Inv, const double *x,
                        const double *r, double *y, hipStream_t s) {
     const int nb = mb.nb;
     if (nb % 2 || nb < 4 || nb > 128) return hipErrorInvalidValue;
-    const int tpe = nb / 2;
-    const int epb = std::min(64, std::max(1, kThreads / tpe));
     const int count = (MODE == MB_MATVEC) ? mb.Ne : mb.Ne / 2;
-    const size_t lds = ((size_t)epb * (mb.nface + 1) * nb + (size_t)epb * nb) * sizeof(double);
+    const int S = row_split(nb, MODE == MB_MATVEC_BLACK ? mb.Ne : count);
+    const int lpe = (nb / 2) * S;
+    const int epb = std::min(64, std::max(1, kThreads / lpe));
+    const size_t lds = ((size_t)epb * (mb.nface + 1) * nb + (size_t)epb * nb * (1 + S)) * sizeof(double);
     const dim3 grid((count + epb - 1) / epb);
-    const dim3 block((epb * tpe + 63) / 64 * 64);
-    hipLaunchKernelGGL((k_mb_rows<MODE>), grid, block, lds, s, ctx->mesh, nb, mb.nface, epb, col, count, mb.D, mb.O,
-                       Inv, x, r, y);
+    const dim3 block((epb * lpe + 63) / 64 * 64);
+    hipLaunchKernelGGL((k_mb_rows<MODE>), grid, block, lds, s, ctx->mesh, nb, mb.nface, epb, S, col, count, mb.D,
+                       mb.O, Inv, x, r, y);
     return hipGetLastError();
 }
 
@@ -407,7 +448,8 @@ hipError_t mb_sweep(frpmg_ctx *ctx, const Mbnk &mb, const double *G, const doubl
         double *vj = mb.V + (size_t)j * N;
         double *zj = mb.Z + (size_t)j * N;
         if ((e = mb_ilu(ctx, mb, vj, zj, s)) != hipSuccess) return e;
-        if ((e = mb_matvec(ctx, mb, zj, mb.w, s)) != hipSuccess) return e;
+        // w = A z_j with z_j = (L U)^{-1} v_j: the red rows of A z_j are v_j's
+        if ((e = launch_rows<MB_MATVEC_BLACK>(ctx, mb, 1, nullptr, zj, vj, mb.w, s)) != hipSuccess) return e;
         if ((e = vec_mdot(ctx, N, j + 1, mb.V, N, mb.w, gm + GM_H1, s)) != hipSuccess) return e;
         if ((e = vec_gemv_sub(N, j + 1, mb.V, N, gm + GM_H1, mb.w, s)) != hipSuccess) return e;
         if ((e = vec_mdot(ctx, N, j + 1, mb.V, N, mb.w, gm + GM_H2, s)) != hipSuccess) return e;
