@@ -20,7 +20,8 @@ def _level(orc, dim, n, p, h=None, Ma=0.3, mu=1e-2, u_dir=(1.0, 0.0, 0.0)):
     return orc.Level(dim=dim, n=n, h=h, p=p, gamma=GAM, mu=mu, Pr=0.72, tau=0.1, qinf=qinf)
 
 
-@pytest.mark.parametrize("dim,n,p", [(2, (4, 6), 1), (2, (4, 4), 4), (3, (2, 4, 2), 2), (3, (2, 2, 2), 3)])
+@pytest.mark.parametrize("dim,n,p", [(2, (4, 6), 1), (2, (4, 4), 4), (3, (2, 4, 2), 2), (3, (2, 2, 2), 3),
+                                     (2, (4, 6), 0), (3, (3, 2, 4), 0)])
 def test_freestream_is_exact_zero(orc, dim, n, p):
     h = [np.geomspace(0.01, 0.2, n[a]) for a in range(dim)]
     L = _level(orc, dim, n, p, h=h, Ma=1e-3)
@@ -39,7 +40,7 @@ def test_other_uniform_state_is_steady(orc, dim, n, p):
     assert np.abs(r).max() < 1e-11 * 100.0
 
 
-@pytest.mark.parametrize("dim,n,p", [(2, (6, 4), 2), (2, (4, 4), 4), (3, (2, 4, 2), 3)])
+@pytest.mark.parametrize("dim,n,p", [(2, (6, 4), 2), (2, (4, 4), 4), (3, (2, 4, 2), 3), (2, (6, 4), 0)])
 def test_discrete_conservation(orc, dim, n, p):
     """sum_e sum_i w_i |J_e| R = 0 per variable on a periodic mesh."""
     rng = np.random.default_rng(0)
@@ -175,3 +176,53 @@ def test_axis_cycle_symmetry_3d(orc):
     r = La.residual(dq)
     r2 = Lb.residual(_cycle_xyz(dq, P, nn))
     assert np.allclose(r2, _cycle_xyz(r, P, nn), rtol=0, atol=1e-12 * np.abs(r).max())
+
+
+def _dp(a):
+    import ctypes
+    return np.ascontiguousarray(a).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@pytest.mark.parametrize("dim,n", [(2, (5, 4)), (3, (3, 4, 3))])
+def test_p0_is_first_order_finite_volume(orc, dim, n):
+    """At p = 0 (one point per element) FR with the DG-recovering corrections
+    is the cell-centred finite-volume scheme: R_k = -sum_a (F*_{k+1/2} -
+    F*_{k-1/2}) / h_a.  Built here from the pinned pointwise fluxes: Roe
+    inviscid flux; LDG viscous flux of the -axis element f^V(q_L, grad q_L)
+    plus tau (q_R - q_L), with the element gradient (q_{k+e_b} - q_k) / h_b
+    (common solution = the +axis element's trace)."""
+    rng = np.random.default_rng(40 + dim)
+    h = [rng.uniform(0.05, 0.2, n[a]) for a in range(dim)]
+    L = _level(orc, dim, n, 0, h=h, Ma=0.3, u_dir=(0.8, 0.6, 0.0))
+    dq = W.random_state(L.shape, rng, L.qinf, amp=0.05)
+    r = L.residual(dq)
+    nv, Ne = dim + 2, L.Ne
+    q = dq[:, 0, :]                       # [nv][Ne]
+    e = np.arange(Ne)
+    c = [e % n[0], (e // n[0]) % n[1], e // (n[0] * n[1])]
+
+    def nbr(k, a, s):
+        cc = [c[b][k] for b in range(3)]
+        cc[a] = (cc[a] + s) % n[a]
+        return cc[0] + n[0] * (cc[1] + n[1] * cc[2])
+
+    grad = np.zeros((Ne, dim, nv))
+    for k in range(Ne):
+        for b in range(dim):
+            grad[k, b] = (q[:, nbr(k, b, 1)] - q[:, k]) / h[b][c[b][k]]
+    lib = orc.lib()
+
+    def face_flux(kL, kR, a):
+        Fi = np.zeros(nv)
+        lib.or_roe_dflux(dim, a, GAM, _dp(L.qinf), _dp(q[:, kL]), _dp(q[:, kR]), _dp(Fi))
+        Fv = np.zeros(nv)
+        lib.or_viscous_flux(dim, a, GAM, L.mu, L.Pr, _dp(L.qinf), _dp(q[:, kL]),
+                            _dp(grad[kL].reshape(-1)), _dp(Fv))
+        return Fi - (Fv + L.tau * (q[:, kR] - q[:, kL]))
+
+    ref = np.zeros((nv, Ne))
+    for k in range(Ne):
+        for a in range(dim):
+            up, dn = nbr(k, a, 1), nbr(k, a, -1)
+            ref[:, k] -= (face_flux(k, up, a) - face_flux(dn, k, a)) / h[a][c[a][k]]
+    assert np.allclose(r[:, 0, :], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
