@@ -66,7 +66,8 @@ typedef struct {
     int n[3];             /* elements per axis (n[2] ignored for dim = 2) */
     const double *h[3];   /* host arrays of element widths */
     int nlevels;          /* 1 .. FR_MAX_LEVELS */
-    int p[FR_MAX_LEVELS]; /* polynomial degree per level, 1 <= p <= 4, dim 3: p <= 3 */
+    int p[FR_MAX_LEVELS]; /* polynomial degree per level, 0 <= p <= 4, dim 3: p <= 3 (p = 0: one point
+                             per element, the cell-centred finite-volume scheme) */
     double gamma, mu, Pr, tau;
     double qinf[5];
 } fr_mesh_desc;

@@ -1462,7 +1462,7 @@ fr_status fr_create(const fr_mesh_desc *d, frpmg_ctx **out) {
         REQUIRE(ph.pinf > 0.0, "reference pressure must be positive");
         for (int l = 0; l < d->nlevels; ++l) {
             const int p = d->p[l];
-            REQUIRE(p >= 1 && p <= (d->dim == 2 ? 4 : 3), "polynomial degree out of range");
+            REQUIRE(p >= 0 && p <= (d->dim == 2 ? 4 : 3), "polynomial degree out of range");
             if (l > 0) REQUIRE(p < d->p[l - 1], "levels must have decreasing degree");
             Level &L = ctx->lv[l];
             L.p = p;

@@ -48,11 +48,12 @@ struct Shape {
     static constexpr int NV = DIM + 2;
     static constexpr int NP = (DIM == 2) ? P * P : P * P * P;
     static constexpr int NF = (DIM == 2) ? P : P * P;
-    // volume kernel: one lane per (element, point)
-    static constexpr int EB = (256 / NP) > 0 ? (256 / NP) : 1;
+    // volume kernel: one lane per (element, point); one point per element
+    // (p = 0) takes 64 elements per workgroup to bound the LDS staging
+    static constexpr int EB = (P == 1) ? 64 : ((256 / NP) > 0 ? (256 / NP) : 1);
     static constexpr int NT = round64(NP * EB);
     // face kernel: one lane per (element, + face point)
-    static constexpr int EBF = (256 / (DIM * NF)) > 0 ? (256 / (DIM * NF)) : 1;
+    static constexpr int EBF = (P == 1) ? 64 : ((256 / (DIM * NF)) > 0 ? (256 / (DIM * NF)) : 1);
     static constexpr int NTF = round64(DIM * NF * EBF);
 
     // local point on the line along axis a through face point f, position j
@@ -844,6 +845,7 @@ hipError_t launch_residual(const frpmg_ctx *ctx, int level, const ResidualArgs &
     const Level &L = ctx->lv[level];
     if (ctx->dim == 2) {
         switch (L.P) {
+            case 1: return dispatch_modes<2, 1>(ctx, L, a, nullptr, s);
             case 2: return dispatch_modes<2, 2>(ctx, L, a, nullptr, s);
             case 3: return dispatch_modes<2, 3>(ctx, L, a, nullptr, s);
             case 4: return dispatch_modes<2, 4>(ctx, L, a, nullptr, s);
@@ -851,6 +853,7 @@ hipError_t launch_residual(const frpmg_ctx *ctx, int level, const ResidualArgs &
         }
     } else {
         switch (L.P) {
+            case 1: return dispatch_modes<3, 1>(ctx, L, a, nullptr, s);
             case 2: return dispatch_modes<3, 2>(ctx, L, a, nullptr, s);
             case 3: return dispatch_modes<3, 3>(ctx, L, a, nullptr, s);
             case 4: return dispatch_modes<3, 4>(ctx, L, a, nullptr, s);
@@ -866,6 +869,7 @@ hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, dou
     if (!L.fQs || !L.fQp || !L.fSn || !L.fGt || !out || !L.r0) return hipErrorInvalidValue;
     if (ctx->dim == 2) {
         switch (L.P) {
+            case 1: return form<2, 1>(ctx, L, dq, sigma, out, s);
             case 2: return form<2, 2>(ctx, L, dq, sigma, out, s);
             case 3: return form<2, 3>(ctx, L, dq, sigma, out, s);
             case 4: return form<2, 4>(ctx, L, dq, sigma, out, s);
@@ -873,6 +877,7 @@ hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, dou
         }
     } else {
         switch (L.P) {
+            case 1: return form<3, 1>(ctx, L, dq, sigma, out, s);
             case 2: return form<3, 2>(ctx, L, dq, sigma, out, s);
             case 3: return form<3, 3>(ctx, L, dq, sigma, out, s);
             case 4: return form<3, 4>(ctx, L, dq, sigma, out, s);
@@ -900,6 +905,7 @@ hipError_t launch_residual_batch(const frpmg_ctx *ctx, int level, int batch, con
     a.r = r;
     if (ctx->dim == 2) {
         switch (L.P) {
+            case 1: return run_on<2, 1, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
             case 2: return run_on<2, 2, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
             case 3: return run_on<2, 3, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
             case 4: return run_on<2, 4, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
@@ -907,6 +913,7 @@ hipError_t launch_residual_batch(const frpmg_ctx *ctx, int level, int batch, con
         }
     } else {
         switch (L.P) {
+            case 1: return run_on<3, 1, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
             case 2: return run_on<3, 2, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
             case 3: return run_on<3, 3, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);
             case 4: return run_on<3, 4, SRC_PLAIN, OUT_R>(ctx, L, m, Jp, Fs, a, nullptr, s);

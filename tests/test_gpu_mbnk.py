@@ -28,10 +28,10 @@ def _block_bar(fr, ol, dq, level, scale):
     return max(1e-10, 10 * 2 * max(dR, U) * np.abs(rq).max() / 1e-7 / scale)
 
 
-CASES = [(2, (10, 8), 1, 30.0), (2, (6, 4), 2, 50.0), (3, (4, 4, 4), 1, 20.0)]
+CASES = [(2, (10, 8), 1, 30.0), (2, (6, 4), 2, 50.0), (3, (4, 4, 4), 1, 20.0), (2, (8, 6), 0, 20.0)]
 
 
-@pytest.fixture(scope="module", params=CASES, ids=["2d_p1", "2d_p2", "3d_p1"])
+@pytest.fixture(scope="module", params=CASES, ids=["2d_p1", "2d_p2", "3d_p1", "2d_p0"])
 def factored(request, orc):
     require_gpu()
     from oracle import mbnk as MB

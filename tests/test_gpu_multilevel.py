@@ -1,6 +1,7 @@
 """Multi-level pMG on the GPU: the three-level FAS V-cycle against the
 oracle's (oracle/multilevel.py), stage solves with p{4-2-1}, and pMG as the
-standalone nonlinear stage solver against the oracle's."""
+standalone nonlinear stage solver against the oracle's, with hierarchies
+down to p = 0 (p{3-1-0}, p{3-2-1-0})."""
 import numpy as np
 import pytest
 
@@ -70,7 +71,7 @@ def test_stage_three_levels_config2(orc):
     assert st["converged"] == 1 and np.linalg.norm(F) / np.linalg.norm(2 * R0) <= 1.5e-8
 
 
-@pytest.mark.parametrize("ps", [(2, 1), (3, 2, 1)])
+@pytest.mark.parametrize("ps", [(2, 1), (3, 2, 1), (3, 1, 0), (3, 2, 1, 0)])
 def test_pmg_nonlinear_solver_parity(orc, ps):
     require_gpu()
     announce("pMG nonlinear solver p%s" % (ps,))
@@ -79,7 +80,7 @@ def test_pmg_nonlinear_solver_parity(orc, ps):
     fr = capi.FR.from_workload(wl, levels=list(ps))
     n = tuple([2] * (len(ps) - 1) + [4])
     cfg = capi.stage_config_for(wl, solver=capi.SOLVER_PMG, tol=1e-10, max_ptc=200, n0=n[0], n1=n[1],
-                                n2=n[2] if len(n) > 2 else 2)
+                                n2=n[2] if len(n) > 2 else 2, n3=n[3] if len(n) > 3 else 2)
     q, st = fr.solve_stage(cfg, fr.to_dev(wl.dq))
     levels = [orc.Level(**wl.level_kwargs(p)) for p in ps]
     q_ref, so = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=n, tol=1e-10, max_vcycles=200)

@@ -45,6 +45,7 @@ def _pair(orc, spec, levels):
 RES_CASES = [
     (2, (12, 10), 1, 0.3), (2, (8, 6), 2, 1e-3), (2, (6, 4), 3, 0.1), (2, (6, 4), 4, 1e-3),
     (3, (4, 4, 2), 2, 0.1), (3, (3, 2, 2), 3, 0.3), (3, (2, 2, 2), 1, 0.2),
+    (2, (12, 10), 0, 0.3), (3, (3, 4, 2), 0, 0.1),
 ]
 
 
@@ -96,7 +97,8 @@ def test_residual_sampled_3d_config(orc):
     assert rel(r, r_ref) <= 1e-10
 
 
-@pytest.mark.parametrize("dim,n,p0,p1", [(2, (6, 4), 4, 2), (2, (8, 6), 2, 1), (3, (4, 2, 2), 3, 2)])
+@pytest.mark.parametrize("dim,n,p0,p1", [(2, (6, 4), 4, 2), (2, (8, 6), 2, 1), (3, (4, 2, 2), 3, 2), (2, (6, 4), 3, 0),
+                                          (3, (4, 2, 2), 1, 0)])
 def test_transfer_parity(orc, dim, n, p0, p1):
     require_gpu()
     announce("transfer dim=%d p%d->p%d" % (dim, p0, p1))
@@ -110,7 +112,8 @@ def test_transfer_parity(orc, dim, n, p0, p1):
     assert rel(w, orc.prolong(z, dim, p0 + 1, p1 + 1)) <= 1e-14
 
 
-@pytest.mark.parametrize("dim,n,p,Ma", [(2, (6, 4), 4, 1e-3), (2, (8, 6), 2, 0.1), (3, (3, 2, 2), 3, 0.2)])
+@pytest.mark.parametrize("dim,n,p,Ma", [(2, (6, 4), 4, 1e-3), (2, (8, 6), 2, 0.1), (3, (3, 2, 2), 3, 0.2),
+                                        (2, (8, 6), 0, 0.1)])
 def test_jvp_parity(orc, dim, n, p, Ma):
     require_gpu()
     announce("jvp dim=%d p=%d Ma=%g" % (dim, p, Ma))
@@ -134,7 +137,7 @@ def test_jvp_parity(orc, dim, n, p, Ma):
 
 
 @pytest.mark.parametrize("dim,n,p,sigma", [(2, (4, 4), 2, 50.0), (2, (4, 2), 4, 5e3), (3, (2, 2, 2), 2, 20.0),
-                                           (3, (2, 2, 2), 3, 40.0)])
+                                           (3, (2, 2, 2), 3, 40.0), (2, (6, 4), 0, 30.0), (3, (2, 2, 2), 0, 20.0)])
 def test_ej_blocks_and_solve_parity(orc, dim, n, p, sigma):
     require_gpu()
     announce("ej dim=%d p=%d" % (dim, p))
