@@ -203,7 +203,7 @@ def time_steps():
                     "gmres_per_stage": [x["gmres_iters"] for x in st["stages"]], "ptc_iters": st["ptc_iters"]}
             res["row3_vs_esdirk3_" + pkey] = (res["row3_" + pkey]["dof_per_s"] /
                                               res["esdirk3_" + pkey]["dof_per_s"])
-        out[wname] = res
+        out.setdefault(wname, {}).update(res)
         fr.close()
         torch.cuda.empty_cache()
     out["note"] = ("one full step at the workload's dt from its state; ESDIRK3 stages to ||F|| <= 1e-8 "
@@ -214,9 +214,10 @@ def time_steps():
 def hierarchies():
     """Other p-hierarchies and pMG as the nonlinear solver (one stage, set-up
     included, after a warm-up): config 2 (ESDIRK stage) with JFNK-pMG
-    p{4-2} and p{4-2-1} and with the pMG nonlinear solver p{4-2} and p{4-2-1}
-    (to 1e-8 and to 1e-4 of ||F(q^n)||); config 4 (ROW stage) with GMRES-pMG
-    p{3-2} and p{3-2-1}."""
+    p{4-2}, p{4-2-1}, p{4-2-1-0} and the p{4-0} negative control, and with
+    the pMG nonlinear solver p{4-2}, p{4-2-1} and p{4-2-1-0} (to 1e-8 and to
+    1e-4 of ||F(q^n)||); config 4 (ROW stage) with GMRES-pMG p{3-2},
+    p{3-2-1} and the p{3-0} negative control."""
     import torch
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
@@ -229,9 +230,17 @@ def hierarchies():
                 ("pmg_solver_p421", dict(pmg_levels=3, solver=1, max_ptc=1000)),
                 ("jfnk_pmg_p42_tol1e-4", dict(pmg_levels=2, tol=1e-4)),
                 ("pmg_solver_p42_tol1e-4", dict(pmg_levels=2, solver=1, tol=1e-4, max_ptc=1000)))),
+            ("config2", W.config2, [4, 0], (
+                ("jfnk_pmg_p40", dict()),
+                ("jfnk_pmg_p40_mbnk", dict(coarse_smoother=1)))),
+            ("config2", W.config2, [4, 2, 1, 0], (
+                ("jfnk_pmg_p4210", dict()),
+                ("pmg_solver_p4210", dict(solver=1, max_ptc=1000)))),
             ("config4", W.config4, [3, 2, 1], (
                 ("gmres_pmg_p32", dict(pmg_levels=2)),
-                ("gmres_pmg_p321", dict(pmg_levels=3))))):
+                ("gmres_pmg_p321", dict(pmg_levels=3)))),
+            ("config4", W.config4, [3, 0], (
+                ("gmres_pmg_p30", dict()),))):
         wl = mk()
         fr = capi.FR.from_workload(wl, levels=levels)
         dq = fr.to_dev(wl.dq)
@@ -251,7 +260,7 @@ def hierarchies():
                             "converged": st["converged"]}
             except capi.FRError as ex:
                 res[key] = {"failed": str(ex)}
-        out[wname] = res
+        out.setdefault(wname, {}).update(res)
         fr.close()
         torch.cuda.empty_cache()
     out["note"] = ("stage tolerance 1e-8 unless marked; the pMG nonlinear solver smooths with dtau = dt and "
