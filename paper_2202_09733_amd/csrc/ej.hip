@@ -2,13 +2,14 @@
 // element-Jacobi preconditioner; Sec. 3.2, EJ smoother).  The batched apply
 // with the stored inverses is in ej_apply.hip.
 //
-// Inversion of small blocks (n_b <= 128: 2D up to p = 4): one workgroup per
-// block, the whole FP64 block resident in LDS, Gauss-Jordan elimination with
-// partial pivoting (largest |a|, first row on ties), the inverse written
-// back column-major in the requested storage precision.  Larger blocks (3D
-// from p = 2; an LDS-resident 135^2 block leaves one workgroup per CU and
-// ran 4x slower than the blocked form), and the BF16-MFMA precision form at
-// any size, use the blocked variant below.  Storing the inverse turns every
+// Inversion of small blocks (EJ blocks of n_b <= 64: 2D up to p = 3, 3D
+// p <= 1; the kernel takes up to 128): one workgroup per block, the whole
+// FP64 block resident in LDS, Gauss-Jordan elimination with partial pivoting
+// (largest |a|, first row on ties), the inverse written back column-major in
+// the requested storage precision.  Larger blocks (2D p = 4 and 3D from
+// p = 2: an LDS-resident 135^2 block leaves one workgroup per CU and ran 4x
+// slower than the blocked form, 100^2 blocks 2x), and the BF16-MFMA precision
+// form at any size, use the blocked variant below.  Storing the inverse turns every
 // apply into a batched GEMV that streams the blocks once from HBM with
 // coalesced column reads, with no sequential triangular sweeps.
 #include <utility>
@@ -132,8 +133,8 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
 }
 
 // ---------------------------------------------------------------------------
-// Blocked in-place Gauss-Jordan for the larger blocks (135 x 135 and
-// 320 x 320 in 3D at p = 2, 3).  Panels of kPanel columns are eliminated in
+// Blocked in-place Gauss-Jordan for the larger blocks (100 x 100 in 2D at
+// p = 4; 135 x 135 and 320 x 320 in 3D at p = 2, 3).  Panels of kPanel columns are eliminated in
 // registers (pivot search over the full column, row swaps recorded); the
 // product of the panel's elementary transforms T = (I + W S^T) P (S = the
 // panel's pivot rows) is then applied to every other column at once as a
