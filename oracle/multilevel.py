@@ -172,20 +172,27 @@ def esdirk_stage_ml(levels, dq_n, dt, a_ii, n=None, coarse="ej", eta=0.1, m=30, 
 
 
 def pmg_nonlinear_stage(levels, dq_n, dt, a_ii, a_i1=None, n=None, dtau=None, tol=1e-8, max_vcycles=500,
-                        coarse="ej"):
+                        coarse="ej", refresh=0):
     """Second ESDIRK stage q = q^n + dt (a_i1 R(q^n) + a_ii R(q)) solved by
     pMG as the nonlinear solver: V-cycles on F(q + Y) = 0, smoothers with the
-    pseudo-time shift sigma_S = 1/dtau + 1/(a_ii dt), blocks frozen at q^n,
+    pseudo-time shift sigma_S = 1/dtau + 1/(a_ii dt), blocks formed at q^n,
     until ||F|| <= tol ||F(q^n)||; coarse = "ej" or "mbnk" (the coarsest
-    level's smoother)."""
+    level's smoother).  refresh > 0 re-forms the smoothers at the current
+    iterate every `refresh` V-cycles (Sec. 4.2.2 updates them every 20
+    pseudo-time iterations for this solver)."""
     a_i1 = a_ii if a_i1 is None else a_i1
     dtau = dt if dtau is None else dtau
     n = tuple(n) if n is not None else tuple([2] * (len(levels) - 1) + [2])
     sigma = 1.0 / (a_ii * dt)
     sigma_S = 1.0 / dtau + sigma
-    facs = hierarchy_factors(levels, dq_n, sigma_S)
-    ilu = coarse_mbnk(levels, dq_n, sigma_S) if coarse == "mbnk" else None
-    pm = MultiPMG(levels, facs, MultiPMGParams(sigma_D=sigma, n=n, scale_mode=SCALE_LITERAL), coarse_ilu=ilu)
+    prm = MultiPMGParams(sigma_D=sigma, n=n, scale_mode=SCALE_LITERAL)
+
+    def smoothers(q):
+        facs = hierarchy_factors(levels, q, sigma_S)
+        ilu = coarse_mbnk(levels, q, sigma_S) if coarse == "mbnk" else None
+        return MultiPMG(levels, facs, prm, coarse_ilu=ilu)
+
+    pm = smoothers(dq_n)
     fine = levels[0]
     R0 = fine.residual(dq_n)
     b = dq_n + (a_i1 * dt) * R0
@@ -194,6 +201,8 @@ def pmg_nonlinear_stage(levels, dq_n, dt, a_ii, a_i1=None, n=None, dtau=None, to
     st = NLStats(res0=float(np.linalg.norm(F)))
     fn = st.res0
     while fn > tol * st.res0 and st.vcycles < max_vcycles:
+        if refresh > 0 and st.vcycles > 0 and st.vcycles % refresh == 0:
+            pm = smoothers(q)
         pm.set_point(q, rq)
         q = q + pm.apply(-F)
         rq = fine.residual(q)

@@ -95,3 +95,22 @@ def test_pmg_nonlinear_solver_reaches_newton_root(orc, ps):
     L0 = levels[0]
     qref = _dense_newton_stage(L0, wl.dq, wl.dt, wl.a_ii, lambda x: dense_jacobian(L0, x))
     assert np.linalg.norm(q - qref) <= 1e-8 * np.linalg.norm(qref - wl.dq)
+
+
+def test_pmg_nonlinear_solver_with_refreshed_smoothers(orc):
+    """Smoothers re-formed at the current iterate every 2 V-cycles: the solver
+    still converges to the dense-Newton root, and the refresh changes the
+    iterates (the first refresh happens before the third cycle)."""
+    wl = W.make_bump_workload(n=(4, 4), p0=2, p1=1, Ma=0.2, dt_factor=3.0, seed=14, amp=5e-2)
+    levels = [orc.Level(**wl.level_kwargs(p)) for p in (2, 1)]
+    q, st = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), tol=1e-11, refresh=2)
+    assert st.converged
+    L0 = levels[0]
+    qref = _dense_newton_stage(L0, wl.dq, wl.dt, wl.a_ii, lambda x: dense_jacobian(L0, x))
+    assert np.linalg.norm(q - qref) <= 1e-8 * np.linalg.norm(qref - wl.dq)
+    q2, _ = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), max_vcycles=2, tol=0.0, refresh=2)
+    q2b, _ = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), max_vcycles=2, tol=0.0)
+    assert np.array_equal(q2, q2b)  # no refresh within the first two cycles
+    q3, _ = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), max_vcycles=3, tol=0.0, refresh=2)
+    q3b, _ = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), max_vcycles=3, tol=0.0)
+    assert not np.array_equal(q3, q3b)
