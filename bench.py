@@ -233,6 +233,7 @@ def hierarchies():
                 ("jfnk_pmg_p42", dict(pmg_levels=2)),
                 ("jfnk_pmg_p421", dict(pmg_levels=3)),
                 ("pmg_solver_p42", dict(pmg_levels=2, solver=1, max_ptc=1000)),
+                ("pmg_solver_p42_refresh20", dict(pmg_levels=2, solver=1, max_ptc=1000, smoother_refresh=20)),
                 ("pmg_solver_p421", dict(pmg_levels=3, solver=1, max_ptc=1000)),
                 ("jfnk_pmg_p42_tol1e-4", dict(pmg_levels=2, tol=1e-4)),
                 ("pmg_solver_p42_tol1e-4", dict(pmg_levels=2, solver=1, tol=1e-4, max_ptc=1000)))),

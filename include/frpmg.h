@@ -254,6 +254,8 @@ typedef struct {
                             (its operator assembled by mbnk_factor at the restricted q^n) */
     int mbnk_maxit;    /* MBNK GMRES iterations per sweep (0: 5) */
     double mbnk_tol;   /* MBNK relative GMRES tolerance per sweep (0: 1e-1) */
+    int smoother_refresh; /* FR_SOLVER_PMG: re-form the smoothers at the current iterate every this many
+                             V-cycles (0: formed once at q^n; Sec. 4.2.2 uses 20) */
 } stage_params;
 
 #define FR_SMOOTHER_EJ 0

@@ -68,7 +68,7 @@ class StageParams(ctypes.Structure):
                 ("skip_setup", ctypes.c_int), ("stall_window", ctypes.c_int), ("stall_ratio", ctypes.c_double),
                 ("graphs", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int),
                 ("pmg_levels", ctypes.c_int), ("solver", ctypes.c_int), ("coarse_smoother", ctypes.c_int),
-                ("mbnk_maxit", ctypes.c_int), ("mbnk_tol", ctypes.c_double)]
+                ("mbnk_maxit", ctypes.c_int), ("mbnk_tol", ctypes.c_double), ("smoother_refresh", ctypes.c_int)]
 
 SOLVER_JFNK, SOLVER_PMG = 0, 1
 
@@ -236,6 +236,7 @@ class StageConfig:
     coarse_smoother: int = SMOOTHER_EJ
     mbnk_maxit: int = 0
     mbnk_tol: float = 0.0
+    smoother_refresh: int = 0
 
     def to_c(self):
         return StageParams(**{f[0]: getattr(self, f[0]) for f in StageParams._fields_})

@@ -988,6 +988,7 @@ struct StageSolver {
         mbnk = pmg && P.coarse_smoother == FR_SMOOTHER_MBNK;
         REQUIRE(!mbnk || !learned, "the MBNK smoother takes the plain pMG hierarchy");
         REQUIRE(P.mbnk_maxit >= 0 && P.mbnk_maxit <= kMbnkMaxIt, "mbnk_maxit must be in 0..8");
+        REQUIRE(P.smoother_refresh >= 0, "smoother_refresh must be >= 0");
         pp = pmg_params{sigma_A, P.n0, P.n1, learned ? FR_COARSE_LEARNED : (mbnk ? FR_COARSE_MBNK : FR_COARSE_EJ),
                         nonlinear_pmg ? FR_SCALE_LITERAL : P.scale_mode, P.eps_p, P.n2, P.n3, nlev,
                         P.mbnk_maxit, P.mbnk_tol};
@@ -1034,6 +1035,8 @@ struct StageSolver {
         double fn = f0;
         fr_status status = std::isfinite(f0) ? FR_OK : FR_ENONFINITE;
         while (status == FR_OK && fn > P.tol * f0 && st->ptc_iters < P.max_ptc) {
+            if (P.smoother_refresh > 0 && st->ptc_iters > 0 && st->ptc_iters % P.smoother_refresh == 0)
+                setup(q, s);  // smoothers re-formed at the current iterate
             pmg_point(ctx, q, rq, s);
             cnt.R1 += nlev - 1;
             HIPCHK(vec_axpby(N, Scal{0.0, nullptr}, nullptr, Scal{-1.0, nullptr}, F, s));  // F <- -F

@@ -91,3 +91,27 @@ def test_pmg_nonlinear_solver_parity(orc, ps):
     assert st["converged"] == 1 and so.converged and st["gmres_iters"] == 0
     assert abs(st["ptc_iters"] - so.vcycles) <= 1
     assert d <= 1e-8
+
+
+def test_pmg_nonlinear_solver_refresh_parity(orc):
+    """Smoothers re-formed at the current iterate every 3 V-cycles, against
+    the oracle's same schedule."""
+    require_gpu()
+    announce("pMG nonlinear solver with smoother refresh")
+    from oracle import multilevel as ML
+    wl = W.make_bump_workload(n=(8, 8), p0=3, p1=1, dt_factor=3.0)
+    ps = (3, 1)
+    fr = capi.FR.from_workload(wl, levels=list(ps))
+    cfg = capi.stage_config_for(wl, solver=capi.SOLVER_PMG, tol=1e-10, max_ptc=200, n0=2, n1=4,
+                                smoother_refresh=3)
+    q, st = fr.solve_stage(cfg, fr.to_dev(wl.dq))
+    levels = [orc.Level(**wl.level_kwargs(p)) for p in ps]
+    q_ref, so = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), tol=1e-10, max_vcycles=200,
+                                       refresh=3)
+    q0, s0 = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), tol=1e-10, max_vcycles=200)
+    d = np.linalg.norm(q.cpu().numpy() - q_ref) / np.linalg.norm(q_ref - wl.dq)
+    print("refresh every 3: GPU %d V-cycles, oracle %d (without refresh %d); |q - q_ref| / |update| = %.2e"
+          % (st["ptc_iters"], so.vcycles, s0.vcycles, d))
+    assert st["converged"] == 1 and so.converged
+    assert abs(st["ptc_iters"] - so.vcycles) <= 1
+    assert d <= 1e-8
