@@ -165,9 +165,11 @@ def stage_3d(steps=1):
             _, st = fr.solve_stage(cfg, dq, out=Y)
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / steps
+        v_ap = torch.randn_like(dq)
+        t_ap = _events_time(lambda: fr.ej_solve(0, v_ap, out=Y), 5)
         out[key] = {"dof_per_s": wl.dof() / el, "s_per_stage": el, "t_setup_s": st["t_setup"],
                     "t_solve_s": st["t_solve"], "gmres_iters": st["gmres_iters"], "rel_res": st["rel_res"],
-                    "true_rel_res": st["true_rel_res"]}
+                    "true_rel_res": st["true_rel_res"], "fine_ej_apply_ms": t_ap * 1e3}
     out["bf16_storage"]["speedup_vs_fp64"] = out["bf16_storage"]["dof_per_s"] / out["fp64"]["dof_per_s"]
     out["workload"] = ("config4: 3D NS FR periodic 32^3 p=3 (10,485,760 DOF) TGV, Ma 0.1, Re 1600, first ROW stage "
                        "gamma 0.25 at dt = 100 dt_exp, FGMRES(30) to 1e-8, pMG p{3-2} n{2-2}, EJ blocks 320^2 / 135^2")
@@ -591,11 +593,15 @@ def main():
                     _, stv = fr.solve_stage(cfgv, dq, out=fr.empty(0))
                 torch.cuda.synchronize()
                 vv = dof * args.steps / (time.perf_counter() - ta)
+                # the fine apply with this variant's stored inverse
+                v_ap = torch.randn_like(dq)
+                y_ap = fr.empty(0)
+                t_ap = _events_time(lambda: fr.ej_solve(0, v_ap, out=y_ap), 50)
                 result[key] = {
                     "value": vv, "speedup_vs_fp64": vv / result["value"],
                     "dof_per_s_without_setup": dof / stv["t_solve"], "t_setup_s": stv["t_setup"],
                     "ptc_iters": stv["ptc_iters"], "gmres_iters": stv["gmres_iters"], "rel_res": stv["rel_res"],
-                    "note": note}
+                    "fine_ej_apply_us": t_ap * 1e6, "note": note}
         # re-create the pMG factors for the kernel-rate measurements
         fr.solve_stage(cfg, dq, out=out)
         print("[bench] kernel rates", file=sys.stderr, flush=True)

@@ -13,28 +13,46 @@ namespace {
 
 constexpr int kApplyThreads = 256;
 
-template <typename T, int R>
+// Loads of the stored inverse, with or without the non-temporal hint (NT).
+// An inverse larger than the 256 MB last-level cache is streamed from HBM on
+// every apply: the hint keeps it from displacing r and y, and the 26.8 GB
+// config-4 stream runs at 6.2 TB/s instead of 4.9 (config 2, 328 MB: 55
+// instead of 57 us).  A smaller one (the FP32/BF16 config-2 inverses, every
+// coarse level of config 2) is served from that cache by the V-cycle's
+// repeated applies, which the hint would defeat (BF16: 17 -> 20 us).
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+
+template <bool NT, typename U>
+__device__ __forceinline__ U ld(const U *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+__device__ __forceinline__ double bf16_bits(unsigned int h) { return (double)__uint_as_float(h << 16); }
+
+template <typename T, int R, bool NT>
 struct VecLoad;
-template <>
-struct VecLoad<double, 1> {
-    __device__ static void get(const double *p, double *o) { o[0] = p[0]; }
+template <bool NT>
+struct VecLoad<double, 1, NT> {
+    __device__ static void get(const double *p, double *o) { o[0] = ld<NT>(p); }
 };
-template <>
-struct VecLoad<double, 2> {
+template <bool NT>
+struct VecLoad<double, 2, NT> {
     __device__ static void get(const double *p, double *o) {
-        const double2 v = *reinterpret_cast<const double2 *>(p);
+        const nt_d2 v = ld<NT>(reinterpret_cast<const nt_d2 *>(p));
         o[0] = v.x;
         o[1] = v.y;
     }
 };
-template <>
-struct VecLoad<float, 1> {
-    __device__ static void get(const float *p, double *o) { o[0] = p[0]; }
+template <bool NT>
+struct VecLoad<float, 1, NT> {
+    __device__ static void get(const float *p, double *o) { o[0] = ld<NT>(p); }
 };
-template <>
-struct VecLoad<float, 4> {
+template <bool NT>
+struct VecLoad<float, 4, NT> {
     __device__ static void get(const float *p, double *o) {
-        const float4 v = *reinterpret_cast<const float4 *>(p);
+        const nt_f4 v = ld<NT>(reinterpret_cast<const nt_f4 *>(p));
         o[0] = v.x;
         o[1] = v.y;
         o[2] = v.z;
@@ -42,19 +60,21 @@ struct VecLoad<float, 4> {
     }
 };
 
-template <>
-struct VecLoad<__bf16, 1> {
-    __device__ static void get(const __bf16 *p, double *o) { o[0] = (float)p[0]; }
-};
-template <>
-struct VecLoad<__bf16, 4> {
+// BF16 entries are loaded as their bit patterns (the upper half of an FP32)
+template <bool NT>
+struct VecLoad<__bf16, 1, NT> {
     __device__ static void get(const __bf16 *p, double *o) {
-        typedef __bf16 b4 __attribute__((ext_vector_type(4)));
-        const b4 v = *reinterpret_cast<const b4 *>(p);
-        o[0] = (float)v.x;
-        o[1] = (float)v.y;
-        o[2] = (float)v.z;
-        o[3] = (float)v.w;
+        o[0] = bf16_bits(ld<NT>(reinterpret_cast<const unsigned short *>(p)));
+    }
+};
+template <bool NT>
+struct VecLoad<__bf16, 4, NT> {
+    __device__ static void get(const __bf16 *p, double *o) {
+        const unsigned long long u = ld<NT>(reinterpret_cast<const unsigned long long *>(p));
+        o[0] = bf16_bits((unsigned int)(u & 0xffffu));
+        o[1] = bf16_bits((unsigned int)((u >> 16) & 0xffffu));
+        o[2] = bf16_bits((unsigned int)((u >> 32) & 0xffffu));
+        o[3] = bf16_bits((unsigned int)(u >> 48));
     }
 };
 
@@ -66,7 +86,7 @@ struct VecLoad<__bf16, 4> {
 // the columns are split into S contiguous ranges on S lane groups, whose
 // partial sums meet in LDS and are added in range order.  With a column placement (blocked inversion), stored column j
 // multiplies r[cols[j]]; the gather happens while r is staged in LDS.
-template <typename T, int R>
+template <typename T, int R, bool NT>
 __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int epb, int S,
                                                             const T *__restrict__ inv,
                                                             const int *__restrict__ cols,
@@ -109,14 +129,14 @@ __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int 
             // of 100^2, no change in FP64)
             for (; j + 8 <= j1; j += 8) {
                 double v0[R], v1[R], v2[R], v3[R], v4[R], v5[R], v6[R], v7[R];
-                VecLoad<T, R>::get(col + (size_t)j * nb, v0);
-                VecLoad<T, R>::get(col + (size_t)(j + 1) * nb, v1);
-                VecLoad<T, R>::get(col + (size_t)(j + 2) * nb, v2);
-                VecLoad<T, R>::get(col + (size_t)(j + 3) * nb, v3);
-                VecLoad<T, R>::get(col + (size_t)(j + 4) * nb, v4);
-                VecLoad<T, R>::get(col + (size_t)(j + 5) * nb, v5);
-                VecLoad<T, R>::get(col + (size_t)(j + 6) * nb, v6);
-                VecLoad<T, R>::get(col + (size_t)(j + 7) * nb, v7);
+                VecLoad<T, R, NT>::get(col + (size_t)j * nb, v0);
+                VecLoad<T, R, NT>::get(col + (size_t)(j + 1) * nb, v1);
+                VecLoad<T, R, NT>::get(col + (size_t)(j + 2) * nb, v2);
+                VecLoad<T, R, NT>::get(col + (size_t)(j + 3) * nb, v3);
+                VecLoad<T, R, NT>::get(col + (size_t)(j + 4) * nb, v4);
+                VecLoad<T, R, NT>::get(col + (size_t)(j + 5) * nb, v5);
+                VecLoad<T, R, NT>::get(col + (size_t)(j + 6) * nb, v6);
+                VecLoad<T, R, NT>::get(col + (size_t)(j + 7) * nb, v7);
 #pragma unroll
                 for (int q = 0; q < R; ++q)
                     acc[q] += ((v0[q] * rv[j] + v1[q] * rv[j + 1]) + (v2[q] * rv[j + 2] + v3[q] * rv[j + 3])) +
@@ -125,17 +145,17 @@ __global__ void __launch_bounds__(kApplyThreads) k_ej_apply(int nb, int Ne, int 
         }
         for (; j + 4 <= j1; j += 4) {
             double v0[R], v1[R], v2[R], v3[R];
-            VecLoad<T, R>::get(col + (size_t)j * nb, v0);
-            VecLoad<T, R>::get(col + (size_t)(j + 1) * nb, v1);
-            VecLoad<T, R>::get(col + (size_t)(j + 2) * nb, v2);
-            VecLoad<T, R>::get(col + (size_t)(j + 3) * nb, v3);
+            VecLoad<T, R, NT>::get(col + (size_t)j * nb, v0);
+            VecLoad<T, R, NT>::get(col + (size_t)(j + 1) * nb, v1);
+            VecLoad<T, R, NT>::get(col + (size_t)(j + 2) * nb, v2);
+            VecLoad<T, R, NT>::get(col + (size_t)(j + 3) * nb, v3);
             const double x0 = rv[j], x1 = rv[j + 1], x2 = rv[j + 2], x3 = rv[j + 3];
 #pragma unroll
             for (int q = 0; q < R; ++q) acc[q] += (v0[q] * x0 + v1[q] * x1) + (v2[q] * x2 + v3[q] * x3);
         }
         for (; j < j1; ++j) {
             double v0[R];
-            VecLoad<T, R>::get(col + (size_t)j * nb, v0);
+            VecLoad<T, R, NT>::get(col + (size_t)j * nb, v0);
 #pragma unroll
             for (int q = 0; q < R; ++q) acc[q] += v0[q] * rv[j];
         }
@@ -174,6 +194,9 @@ int apply_split(int nb, int tpe, int Ne) {
     return (sizeof(T) == 8 && (size_t)Ne * tpe < (256u << 10) && nb >= 64 && 2 * tpe <= kApplyThreads) ? 2 : 1;
 }
 
+// inverses above this size take the non-temporal loads (see VecLoad)
+constexpr size_t kStreamedInverse = size_t(192) << 20;
+
 template <typename T, int R>
 hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, double beta, const double *yin,
                         Scal scale, double *y, hipStream_t s) {
@@ -186,8 +209,12 @@ hipError_t launch_apply(const Level &L, int Ne, const double *r, double alpha, d
     const size_t lds = (size_t)epb * nb * (S > 1 ? 1 + S : 1) * sizeof(double);
     dim3 grid((Ne + epb - 1) / epb);
     dim3 block((epb * lpe + 63) / 64 * 64);  // whole wavefronts, none without a block row
-    hipLaunchKernelGGL((k_ej_apply<T, R>), grid, block, lds, s, nb, Ne, epb, S, (const T *)L.inv, L.inv_cols, r,
-                       alpha, beta, yin, scale, y);
+    if ((size_t)Ne * nb * nb * sizeof(T) > kStreamedInverse)
+        hipLaunchKernelGGL((k_ej_apply<T, R, true>), grid, block, lds, s, nb, Ne, epb, S, (const T *)L.inv,
+                           L.inv_cols, r, alpha, beta, yin, scale, y);
+    else
+        hipLaunchKernelGGL((k_ej_apply<T, R, false>), grid, block, lds, s, nb, Ne, epb, S, (const T *)L.inv,
+                           L.inv_cols, r, alpha, beta, yin, scale, y);
     return hipGetLastError();
 }
 
