@@ -146,12 +146,11 @@ void check_neighbours(frpmg_ctx *ctx) {
 
 // face data of a level's linearisation point, kept by the element-local block formation
 void ensure_face_save(frpmg_ctx *ctx, Level &L) {
-    if (L.fQp) return;
     const size_t nface = (size_t)ctx->dim * ctx->nv * L.NF * ctx->mesh.Ne;
-    L.fQs = dalloc(ctx, nface);
-    L.fQp = dalloc(ctx, nface);
-    L.fSn = dalloc(ctx, nface);
-    L.fGt = dalloc(ctx, nface * (ctx->dim - 1));
+    if (!L.fQs) L.fQs = dalloc(ctx, nface);
+    if (!L.fQp) L.fQp = dalloc(ctx, nface);
+    if (!L.fSn) L.fSn = dalloc(ctx, nface);
+    if (!L.fGt) L.fGt = dalloc(ctx, nface * (ctx->dim - 1));
 }
 
 void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, int precision, hipStream_t s) {
@@ -224,8 +223,8 @@ int colour_stride(int n) {
 }
 
 void mbnk_alloc(frpmg_ctx *ctx, int level) {
-    if (ctx->mb && ctx->mb->level == level) return;
-    mbnk_free(ctx);
+    if (ctx->mb && ctx->mb->level == level && ctx->mb->allocated) return;
+    mbnk_free(ctx);  // also a workspace left partial by a failed allocation
     const Level &L = ctx->lv[level];
     const MeshK &m = ctx->mesh;
     Mbnk *mb = new Mbnk();
@@ -268,6 +267,7 @@ void mbnk_alloc(frpmg_ctx *ctx, int level) {
     void *p = nullptr;
     HIPCHK(hipMalloc(&p, sizeof(int)));
     mb->status = (int *)p;
+    mb->allocated = true;
 }
 
 // Assemble sigma I - dR/dq of a level at dq on the face-neighbour block

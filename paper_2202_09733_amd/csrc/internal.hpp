@@ -189,7 +189,8 @@ struct Mbnk {
     double *V = nullptr, *Z = nullptr, *w = nullptr;
     double *gm = nullptr;    // device scalars of the GMRES cycle
     int *status = nullptr;
-    bool ready = false;
+    bool allocated = false;  // every buffer above is in place
+    bool ready = false;      // a factorisation is complete
 };
 
 }  // namespace frpmg
