@@ -32,7 +32,7 @@ def measured_traffic():
     changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_ej_apply_config2.md")
+    path = os.path.join(ROOT, "profiles", "k_ej_apply_vortical64.md")
     csrc = os.path.join(ROOT, "paper_2202_09733_amd", "csrc")
     try:
         txt = open(path).read()
@@ -106,7 +106,7 @@ def kernel_rates_3d(reps=20, nsets=4):
     import torch
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
-    wl = W.config4()
+    wl = W.tgv_32cubed_p3()
     fr = capi.FR.from_workload(wl, levels=[wl.p0])
     N = wl.dof()
     base = fr.to_dev(wl.dq)
@@ -151,7 +151,7 @@ def stage_3d(steps=1):
     import torch
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
-    wl = W.config4()
+    wl = W.tgv_32cubed_p3()
     fr = capi.FR.from_workload(wl)
     dq = fr.to_dev(wl.dq)
     out = {}
@@ -171,7 +171,7 @@ def stage_3d(steps=1):
                     "t_solve_s": st["t_solve"], "gmres_iters": st["gmres_iters"], "rel_res": st["rel_res"],
                     "true_rel_res": st["true_rel_res"], "fine_ej_apply_ms": t_ap * 1e3}
     out["bf16_storage"]["speedup_vs_fp64"] = out["bf16_storage"]["dof_per_s"] / out["fp64"]["dof_per_s"]
-    out["workload"] = ("config4: 3D NS FR periodic 32^3 p=3 (10,485,760 DOF) TGV, Ma 0.1, Re 1600, first ROW stage "
+    out["workload"] = ("3D NS FR periodic 32^3 p=3 (10,485,760 DOF) TGV, Ma 0.1, Re 1600, first ROW stage "
                        "gamma 0.25 at dt = 100 dt_exp, FGMRES(30) to 1e-8, pMG p{3-2} n{2-2}, EJ blocks 320^2 / 135^2")
     fr.close()
     torch.cuda.empty_cache()
@@ -180,7 +180,7 @@ def stage_3d(steps=1):
 
 def time_steps():
     """Full implicit time steps (every stage, EJ factors formed once at q^n)
-    of the 2D (config 2) and 3D (config 4) workloads with ESDIRK3 (4 stages,
+    of the 2D (64x64, p = 4) and 3D (32^3, p = 3) workloads with ESDIRK3 (4 stages,
     3 implicit, PTC + inexact Newton per stage) and ROW3 (3 linear stages),
     both order 3 and L-stable with the same diagonal, preconditioner in FP64
     and in the BF16-storage form: DOF per second of step time, after one
@@ -189,7 +189,7 @@ def time_steps():
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
     out = {}
-    for wname, mk, reps in (("config2", W.config2, 2), ("config4", W.config4, 1)):
+    for wname, mk, reps in (("vortical2d", W.vortical_64x64_p4, 2), ("tgv3d", W.tgv_32cubed_p3, 1)):
         wl = mk()
         fr = capi.FR.from_workload(wl)
         dq = fr.to_dev(wl.dq)
@@ -221,17 +221,17 @@ def time_steps():
 
 def hierarchies():
     """Other p-hierarchies and pMG as the nonlinear solver (one stage, set-up
-    included, after a warm-up): config 2 (ESDIRK stage) with JFNK-pMG
+    included, after a warm-up): the 2D 64x64 workload (ESDIRK stage) with JFNK-pMG
     p{4-2}, p{4-2-1}, p{4-2-1-0} and the p{4-0} negative control, and with
     the pMG nonlinear solver p{4-2}, p{4-2-1} and p{4-2-1-0} (to 1e-8 and to
-    1e-4 of ||F(q^n)||); config 4 (ROW stage) with GMRES-pMG p{3-2},
+    1e-4 of ||F(q^n)||); the 3D 32^3 workload (ROW stage) with GMRES-pMG p{3-2},
     p{3-2-1} and the p{3-0} negative control."""
     import torch
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
     out = {}
     for wname, mk, levels, runs in (
-            ("config2", W.config2, [4, 2, 1], (
+            ("vortical2d", W.vortical_64x64_p4, [4, 2, 1], (
                 ("jfnk_pmg_p42", dict(pmg_levels=2)),
                 ("jfnk_pmg_p421", dict(pmg_levels=3)),
                 ("pmg_solver_p42", dict(pmg_levels=2, solver=1, max_ptc=1000)),
@@ -239,16 +239,16 @@ def hierarchies():
                 ("pmg_solver_p421", dict(pmg_levels=3, solver=1, max_ptc=1000)),
                 ("jfnk_pmg_p42_tol1e-4", dict(pmg_levels=2, tol=1e-4)),
                 ("pmg_solver_p42_tol1e-4", dict(pmg_levels=2, solver=1, tol=1e-4, max_ptc=1000)))),
-            ("config2", W.config2, [4, 0], (
+            ("vortical2d", W.vortical_64x64_p4, [4, 0], (
                 ("jfnk_pmg_p40", dict()),
                 ("jfnk_pmg_p40_mbnk", dict(coarse_smoother=1)))),
-            ("config2", W.config2, [4, 2, 1, 0], (
+            ("vortical2d", W.vortical_64x64_p4, [4, 2, 1, 0], (
                 ("jfnk_pmg_p4210", dict()),
                 ("pmg_solver_p4210", dict(solver=1, max_ptc=1000)))),
-            ("config4", W.config4, [3, 2, 1], (
+            ("tgv3d", W.tgv_32cubed_p3, [3, 2, 1], (
                 ("gmres_pmg_p32", dict(pmg_levels=2)),
                 ("gmres_pmg_p321", dict(pmg_levels=3)))),
-            ("config4", W.config4, [3, 0], (
+            ("tgv3d", W.tgv_32cubed_p3, [3, 0], (
                 ("gmres_pmg_p30", dict()),))):
         wl = mk()
         fr = capi.FR.from_workload(wl, levels=levels)
@@ -278,13 +278,13 @@ def hierarchies():
 
 
 def smoothers():
-    """Coarsest-level smoother (Sec. 3.2: EJ or MBNK) on the config-2 ESDIRK
+    """Coarsest-level smoother (Sec. 3.2: EJ or MBNK) on the 64x64 vortical ESDIRK
     stage for the hierarchies p{4-2}, p{4-2-1} and p{4-1}: one stage each,
     set-up included, after a warm-up; JFNK-pMG and the pMG nonlinear solver."""
     import torch
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
-    wl = W.config2()
+    wl = W.vortical_64x64_p4()
     out = {}
     for levels, runs in (
             ([4, 2, 1], (("p42_ej", dict(pmg_levels=2)),
@@ -315,16 +315,16 @@ def smoothers():
                 out[key] = {"failed": str(ex)}
         fr.close()
         torch.cuda.empty_cache()
-    out["note"] = ("config-2 stage to 1e-8; MBNK: GMRES(5, 1e-1) with red-black ILU0 on the coarsest level, "
+    out["note"] = ("64x64 vortical stage to 1e-8; MBNK: GMRES(5, 1e-1) with red-black ILU0 on the coarsest level, "
                    "n1 = 2 sweeps; ptc_or_vcycles counts V-cycles for the pMG nonlinear solver")
     return out
 
 
 def learned_ab(wl, steps=3):
-    """The learned coarse correction on the config-2 mesh: pairs harvested by
+    """The learned coarse correction on the 64x64 vortical mesh: pairs harvested by
     the solver from plain-pMG stages and from V-cycles on random directions
     at two other seeded states, the network trained on the GPU, then the
-    config-2 stage timed with the learned and with the plain preconditioner
+    64x64 stage timed with the learned and with the plain preconditioner
     (FP64 factors both)."""
     import torch
     from paper_2202_09733_amd import capi
@@ -404,7 +404,7 @@ def cpu_baseline(wl, st, n_sample_iters=3):
     total = t_setup + st["ptc_iters"] * t_ptc + st["gmres_iters"] * t_iter
     dof = wl.dof()
     return dict(value=dof / total, unit="DOF/s", cores=1, kind="oracle",
-                sample=("oracle run on the config-2 stage: preconditioner set-up in full (coloured EJ formation "
+                sample=("oracle run on the 64x64 vortical stage: preconditioner set-up in full (coloured EJ formation "
                         "and block LU on both levels, %.1f s) and the first %d preconditioned FGMRES iterations "
                         "(%.3f s each), one thread; extrapolated to the GPU stage's %d PTC steps and %d FGMRES "
                         "iterations = %.1f s of oracle time; measuring took %.1f s")
@@ -420,7 +420,7 @@ def only_kernel(args):
     import torch
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
-    wl = W.config2() if args.workload == "config2" else W.config4()
+    wl = W.vortical_64x64_p4() if args.workload == "vortical2d" else W.tgv_32cubed_p3()
     fr = capi.FR.from_workload(wl)
     prec = PRECISIONS[args.precision]
     dq = fr.to_dev(wl.dq)
@@ -481,7 +481,7 @@ def main():
     ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "ej_factor", "residual", "jvp", "stage", "step"],
                     help="profiling driver: set up the workload's state, launch one kernel family --reps times "
                          "and a 256 MiB device copy (counter calibration), print nothing else")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config4"],
+    ap.add_argument("--workload", default="vortical2d", choices=["vortical2d", "tgv3d"],
                     help="workload of the --only-kernel driver")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--coarse-smoother", default="ej", choices=["ej", "mbnk"],
@@ -490,7 +490,7 @@ def main():
                     help="time-step scheme of the --only-kernel step driver")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (N > 1 is not supported)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (N > 1 is not supported)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -501,7 +501,7 @@ def main():
     if args.only_kernel:
         only_kernel(args)
         return
-    wl = W.config2()
+    wl = W.vortical_64x64_p4()
     fr = capi.FR.from_workload(wl)
     prec = PRECISIONS[args.precision]
     fr._last_prec = prec
@@ -541,7 +541,7 @@ def main():
         "dtype": "f64" if prec == capi.PREC_FP64 else "f64 (EJ factors %s)" % args.precision,
         "data": "synthetic",
         "config": {
-            "workload": "config2: 2D NS FR 64x64 y-stretched (AR 1-100), p=4 (409,600 DOF), Ma 1e-3, ESDIRK3 "
+            "workload": "2D NS FR 64x64 y-stretched (AR 1-100), p=4 (409,600 DOF), Ma 1e-3, ESDIRK3 "
                         "stage at dt=1000 dt_exp, PTC+JFNK+FGMRES(30), pMG p{4-2} n{2-2} EJ smoothers",
             "dof": dof, "setup_included": True,
         },

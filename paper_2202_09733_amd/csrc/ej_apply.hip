@@ -16,9 +16,9 @@ constexpr int kApplyThreads = 256;
 // Loads of the stored inverse, with or without the non-temporal hint (NT).
 // An inverse larger than the 256 MB last-level cache is streamed from HBM on
 // every apply: the hint keeps it from displacing r and y, and the 26.8 GB
-// config-4 stream runs at 6.2 TB/s instead of 4.9 (config 2, 328 MB: 55
-// instead of 57 us).  A smaller one (the FP32/BF16 config-2 inverses, every
-// coarse level of config 2) is served from that cache by the V-cycle's
+// 32^3 p = 3 stream runs at 6.2 TB/s instead of 4.9 (64x64 p = 4, 328 MB: 55
+// instead of 57 us).  A smaller one (the FP32/BF16 64x64 p = 4 inverses, every
+// coarse level of that mesh) is served from that cache by the V-cycle's
 // repeated applies, which the hint would defeat (BF16: 17 -> 20 us).
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef float nt_f4 __attribute__((ext_vector_type(4)));

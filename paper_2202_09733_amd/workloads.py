@@ -15,16 +15,16 @@ Workload recipes (the paper's meshes and spin-up solutions are not available,
 so these stand in for the stiffness of its cases: low Mach number and
 high-aspect-ratio elements):
 
-* ``config1``  periodic 8x8 on [0,1]^2, p{2-1}, Re 1000, Ma 0.1, freestream
+* ``bumps_8x8_p2``      periodic 8x8 on [0,1]^2, p{2-1}, Re 1000, Ma 0.1, freestream
   (1, 1, 0) plus four periodic Gaussian bumps (sigma 0.08, centres U[0,1)^2,
   amplitudes U(-1e-2, 1e-2) for rho, u, v independently), p = p_inf; one
   ESDIRK3 stage, dt = 10 dt_exp.
-* ``config2``  64x64, x uniform on [0,1], y geometric h_y,j = h_x 100^((j-63)/63)
+* ``vortical_64x64_p4`` 64x64, x uniform on [0,1], y geometric h_y,j = h_x 100^((j-63)/63)
   (aspect ratio 100 -> 1), p{4-2}, Ma 1e-3, Re 1000; u = 1 + u', v = v' from a
   random streamfunction with |kx|,|ky| <= 4, amplitudes N(0,1)/|k|^2, phases
   U[0, 2pi), scaled to max |u'| = 1e-3; rho = 1, p = p_inf; ESDIRK3 stage,
   dt = 1000 dt_exp.
-* ``config4``  periodic 32^3 on [0, 2pi)^3, p{3-2}, Re 1600, Ma 0.1,
+* ``tgv_32cubed_p3``    periodic 32^3 on [0, 2pi)^3, p{3-2}, Re 1600, Ma 0.1,
   Taylor-Green vortex plus N(0,1) 1e-3 noise on u, v, w; first ROW stage
   (gamma 0.25), dt = 100 dt_exp.
 
@@ -154,7 +154,7 @@ def _gaussian_bumps(rng, X, Y, n_bumps=4, sigma=0.08, amp=1e-2):
 
 def make_bump_workload(n=(8, 8), p0=2, p1=1, Ma=0.1, Re=1000.0, seed=1, dt_factor=10.0,
                        scheme="esdirk", name="bumps", amp=1e-2):
-    """2D periodic unit square, uniform elements, Gaussian bumps (config 1 recipe)."""
+    """2D periodic unit square, uniform elements, Gaussian bumps (the recipe of ``bumps_8x8_p2``)."""
     dim = 2
     h = [np.full(n[0], 1.0 / n[0]), np.full(n[1], 1.0 / n[1])]
     rng = np.random.default_rng(seed)
@@ -186,7 +186,7 @@ def stretched_widths(nx, ny, ratio=100.0):
 def make_vortical_workload(n=(64, 64), p0=4, p1=2, Ma=1e-3, Re=1000.0, seed=2, dt_factor=1000.0,
                            amp=1e-3, kmax=4, ratio=100.0, scheme="esdirk", name="vortical"):
     """2D y-stretched periodic mesh with a smooth random vortical perturbation
-    (config 2 recipe)."""
+    (the recipe of ``vortical_64x64_p4``)."""
     dim = 2
     h = stretched_widths(n[0], n[1], ratio)
     Lx = float(np.sum(h[0]))
@@ -224,7 +224,7 @@ def make_vortical_workload(n=(64, 64), p0=4, p1=2, Ma=1e-3, Re=1000.0, seed=2, d
 def make_tgv_workload(n=(32, 32, 32), p0=3, p1=2, Ma=0.1, Re=1600.0, seed=4, dt_factor=100.0,
                       noise=1e-3, scheme="row", name="tgv"):
     """3D periodic [0, 2pi)^3 Taylor-Green vortex plus seeded velocity noise
-    (config 4 recipe)."""
+    (the recipe of ``tgv_32cubed_p3``)."""
     dim = 3
     L = 2.0 * math.pi
     h = [np.full(n[a], L / n[a]) for a in range(3)]
@@ -250,17 +250,17 @@ def make_tgv_workload(n=(32, 32, 32), p0=3, p1=2, Ma=0.1, Re=1600.0, seed=4, dt_
                     scheme=scheme, Ma=Ma, Re=Re, seed=seed, extra=dict(dt_exp=dt_exp))
 
 
-def config1():
-    return make_bump_workload(name="config1: 2D NS FR periodic 8x8 p=2, Ma 0.1, ESDIRK3 stage")
+def bumps_8x8_p2():
+    return make_bump_workload(name="2D NS FR periodic 8x8 p=2, Ma 0.1, ESDIRK3 stage")
 
 
-def config2():
+def vortical_64x64_p4():
     return make_vortical_workload(
-        name="config2: 2D NS FR 64x64 y-stretched (AR 1-100) p=4, Ma 1e-3, ESDIRK3 stage, CFL~1000")
+        name="2D NS FR 64x64 y-stretched (AR 1-100) p=4, Ma 1e-3, ESDIRK3 stage, CFL~1000")
 
 
-def config4():
-    return make_tgv_workload(name="config4: 3D NS FR periodic 32^3 p=3 TGV, Ma 0.1, ROW stage")
+def tgv_32cubed_p3():
+    return make_tgv_workload(name="3D NS FR periodic 32^3 p=3 TGV, Ma 0.1, ROW stage")
 
 
 def random_state(level_shape, rng, qinf, amp=1e-2):

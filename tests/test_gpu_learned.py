@@ -118,7 +118,7 @@ def test_harvest_train_and_use_on_held_out_state(orc):
     FGMRES iterations.  Iteration counts and times of both preconditioners
     are printed (the A/B comparison)."""
     require_gpu()
-    announce("lcc harvest/train/use, config-2 mesh")
+    announce("lcc harvest/train/use, 64x64 vortical mesh")
     wl_eval = W.make_vortical_workload(seed=2)
     fr = capi.FR.from_workload(W.make_vortical_workload(seed=12))
     rng = np.random.default_rng(11)

@@ -106,14 +106,14 @@ def test_ilu_reproduces_red_rows_and_sweep_reduces_residual(factored):
     assert np.array_equal(a, b)
 
 
-def test_blocks_sampled_config2_coarse(orc):
-    """Full-size coarse level of the config-2 workload (64 x 64, p=2): the
+def test_blocks_sampled_vortical64_coarse(orc):
+    """Full-size coarse level of the 64 x 64 vortical workload (p=2): the
     formation takes several batched residual launches; sampled block columns
     against single-element differences of the oracle's residual."""
     require_gpu()
     from oracle import mbnk as MB
-    announce("mbnk factor config2 coarse p2 (sampled)")
-    wl = W.config2()
+    announce("mbnk factor vortical 64x64 coarse p2 (sampled)")
+    wl = W.vortical_64x64_p4()
     fr = capi.FR.from_workload(wl, levels=[wl.p0, wl.p1])
     L1 = orc.Level(**wl.level_kwargs(wl.p1))
     q1 = orc.restrict(wl.dq, 2, wl.p0 + 1, wl.p1 + 1)
@@ -140,7 +140,7 @@ def test_blocks_sampled_config2_coarse(orc):
                     k = MB.face_neighbour(L1, m, a, s)
                     worst = max(worst, np.abs(O[k, MB.slot(a, -s)][:, j] + d[:, k]).max())
     worst /= np.abs(D).max()
-    print("config-2 coarse blocks, sampled columns: worst difference / max|D| = %.2e (bar %.2e)" % (worst, bar))
+    print("64x64 coarse blocks, sampled columns: worst difference / max|D| = %.2e (bar %.2e)" % (worst, bar))
     assert worst <= bar
 
 
@@ -210,17 +210,17 @@ def test_stage_mbnk_matches_oracle(orc, solver):
     assert d <= 1e-8
 
 
-def test_stage_mbnk_config2_and_graphs(orc):
+def test_stage_mbnk_vortical64_and_graphs(orc):
     """Config-2 stage with MBNK on the p=2 level converges to 1e-8 in the
     oracle's F; captured Arnoldi steps replay it bitwise."""
     require_gpu()
-    announce("stage config2 MBNK coarse (eager and graphs)")
-    wl = W.config2()
+    announce("stage vortical 64x64 MBNK coarse (eager and graphs)")
+    wl = W.vortical_64x64_p4()
     fr = capi.FR.from_workload(wl)
     dq = fr.to_dev(wl.dq)
     q, st = fr.solve_stage(capi.stage_config_for(wl, coarse_smoother=capi.SMOOTHER_MBNK), dq)
     qg, sg = fr.solve_stage(capi.stage_config_for(wl, coarse_smoother=capi.SMOOTHER_MBNK, graphs=1), dq)
-    print("config 2 MBNK coarse: %d PTC / %d FGMRES, %.3f s (setup %.3f s); graphs %.3f s"
+    print("vortical 64x64 MBNK coarse: %d PTC / %d FGMRES, %.3f s (setup %.3f s); graphs %.3f s"
           % (st["ptc_iters"], st["gmres_iters"], st["t_total"], st["t_setup"], sg["t_total"]))
     L0 = orc.Level(**wl.level_kwargs(wl.p0))
     R0 = L0.residual(wl.dq)

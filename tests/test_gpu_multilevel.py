@@ -51,16 +51,16 @@ def test_pmg_apply_three_levels_parity(orc):
     assert rel(Y, Y2) > 1e-4  # the third level changes the cycle
 
 
-def test_stage_three_levels_config2(orc):
-    """The config-2 stage with the p{4-2-1} preconditioner reaches 1e-8 in the
+def test_stage_three_levels_vortical64(orc):
+    """The 64x64 vortical stage with the p{4-2-1} preconditioner reaches 1e-8 in the
     oracle's F."""
     require_gpu()
-    announce("stage config2 p{4-2-1}")
-    wl = W.config2()
+    announce("stage vortical 64x64 p{4-2-1}")
+    wl = W.vortical_64x64_p4()
     fr = capi.FR.from_workload(wl, levels=[4, 2, 1])
     q, st = fr.solve_stage(capi.stage_config_for(wl), fr.to_dev(wl.dq))
     q2, st2 = fr.solve_stage(capi.stage_config_for(wl, pmg_levels=2), fr.to_dev(wl.dq))
-    print("config 2: p{4-2-1} %d PTC / %d FGMRES (%.3f s); p{4-2} %d / %d (%.3f s)"
+    print("vortical 64x64: p{4-2-1} %d PTC / %d FGMRES (%.3f s); p{4-2} %d / %d (%.3f s)"
           % (st["ptc_iters"], st["gmres_iters"], st["t_total"], st2["ptc_iters"], st2["gmres_iters"],
              st2["t_total"]))
     L0 = orc.Level(**wl.level_kwargs(wl.p0))

@@ -1,6 +1,6 @@
 """GPU parity: every ABI call of the HIP library against the FP64 CPU oracle
 on the same seeded inputs.  Sizes span several workgroup tiles with ragged
-tails; the config-1 and config-2 meshes are also checked at full size.
+tails; the 8x8 bump and 64x64 vortical meshes are also checked at full size.
 
 Bars (normwise relative error unless stated):
   * residual R: 1e-10 (both sides FP64, deviation form, no cancellation
@@ -67,7 +67,7 @@ def test_residual_parity(orc, dim, n, p, Ma):
     assert np.array_equal(r, r2)
 
 
-@pytest.mark.parametrize("which", ["config1", "config2"])
+@pytest.mark.parametrize("which", ["bumps_8x8_p2", "vortical_64x64_p4"])
 def test_residual_parity_full_size(orc, which):
     require_gpu()
     announce("residual full size " + which)
@@ -88,8 +88,8 @@ def test_residual_sampled_3d_config(orc):
     """3D 32^3 p=3 Taylor-Green state: full-size GPU residual; the oracle's
     residual is evaluated on the same state and compared on every entry."""
     require_gpu()
-    announce("residual full size config4 (3D 32^3 p=3)")
-    wl = W.config4()
+    announce("residual full size TGV 32^3 p=3")
+    wl = W.tgv_32cubed_p3()
     fr = capi.FR.from_workload(wl)
     ol = orc.Level(**wl.level_kwargs(wl.p0))
     r = fr.residual(0, fr.to_dev(wl.dq)).cpu().numpy()
@@ -221,10 +221,10 @@ def _oracle_F(orc, wl, q):
 
 
 @pytest.mark.parametrize("precond", [capi.PRECOND_PMG, capi.PRECOND_EJ])
-def test_stage_config1_matches_oracle(orc, precond):
+def test_stage_bumps8_matches_oracle(orc, precond):
     require_gpu()
-    announce("stage config1 precond=%d" % precond)
-    wl = W.config1()
+    announce("stage bumps 8x8 precond=%d" % precond)
+    wl = W.bumps_8x8_p2()
     fr = capi.FR.from_workload(wl)
     cfg = capi.stage_config_for(wl, precond=precond)
     q, st = fr.solve_stage(cfg, fr.to_dev(wl.dq))
@@ -242,12 +242,12 @@ def test_stage_config1_matches_oracle(orc, precond):
     print("gpu ptc/gmres", st["ptc_iters"], st["gmres_iters"], "oracle", so.ptc_iters, so.gmres_iters)
 
 
-def test_stage_config2_full_size(orc):
-    """Full config-2 stage on the GPU (pMG p{4-2}); the oracle's residual at
+def test_stage_vortical64_full_size(orc):
+    """Full 64x64 vortical stage on the GPU (pMG p{4-2}); the oracle's residual at
     the GPU's final state confirms ||F|| <= 1e-8 ||F(q^n)||."""
     require_gpu()
-    announce("stage config2 full size pMG")
-    wl = W.config2()
+    announce("stage vortical 64x64 full size pMG")
+    wl = W.vortical_64x64_p4()
     fr = capi.FR.from_workload(wl)
     q, st = fr.solve_stage(capi.stage_config_for(wl), fr.to_dev(wl.dq))
     print(st)
@@ -269,14 +269,14 @@ def test_row_stage_tiny_matches_oracle(orc):
 
 
 @pytest.fixture(scope="module")
-def config4_oracle_rhs(orc):
-    wl = W.config4()
+def tgv32_oracle_rhs(orc):
+    wl = W.tgv_32cubed_p3()
     L0 = orc.Level(**wl.level_kwargs(wl.p0))
     return wl, L0, L0.residual(wl.dq)
 
 
 @pytest.mark.parametrize("precision", [capi.PREC_FP64, capi.PREC_FP32, capi.PREC_BF16_STORE])
-def test_row_stage_config4_full_size(orc, config4_oracle_rhs, precision):
+def test_row_stage_tgv32_full_size(orc, tgv32_oracle_rhs, precision):
     """3D 32^3 p=3 first ROW stage with pMG p{3-2} (fine blocks 320 x 320,
     blocked Gauss-Jordan) with the EJ inverses in FP64, FP32, or from the
     BF16-MFMA factorisation stored in BF16.  FGMRES stops on its residual
@@ -286,8 +286,8 @@ def test_row_stage_config4_full_size(orc, config4_oracle_rhs, precision):
     the oracle recomputes at the GPU solution, is bounded by 1e-6 and must
     agree with the GPU's own recomputation."""
     require_gpu()
-    announce("row stage config4 full size, precision %d" % precision)
-    wl, L0, R0 = config4_oracle_rhs
+    announce("row stage TGV 32^3 full size, precision %d" % precision)
+    wl, L0, R0 = tgv32_oracle_rhs
     fr = capi.FR.from_workload(wl)
     dq = fr.to_dev(wl.dq)
     Y, st = fr.solve_stage(capi.stage_config_for(wl, precision=precision), dq)
@@ -303,7 +303,7 @@ def test_row_stage_config4_full_size(orc, config4_oracle_rhs, precision):
     assert abs(true_orc - st["true_rel_res"]) <= 0.1 * true_orc
 
 
-@pytest.mark.parametrize("case", ["esdirk_config2", "row_3d"])
+@pytest.mark.parametrize("case", ["esdirk_vortical64", "row_3d"])
 def test_graph_replay_matches_eager(orc, case):
     """Arnoldi steps captured as HIP graphs and replayed (many replays per
     stage, with host synchronisations and host-launched work between them,
@@ -312,8 +312,8 @@ def test_graph_replay_matches_eager(orc, case):
     host-launched kernels."""
     require_gpu()
     announce("graph replay vs eager: %s" % case)
-    if case == "esdirk_config2":
-        wl = W.config2()
+    if case == "esdirk_vortical64":
+        wl = W.vortical_64x64_p4()
     else:
         wl = W.make_tgv_workload(n=(8, 8, 8))
     fr = capi.FR.from_workload(wl)

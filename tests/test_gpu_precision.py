@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 def test_fp32_inverse_and_solve_error(orc):
     require_gpu()
-    announce("fp32 EJ storage error, config2 8x8")
+    announce("fp32 EJ storage error, vortical 8x8")
     wl = W.make_vortical_workload(n=(8, 8), dt_factor=1000.0)
     fr = capi.FR.from_workload(wl)
     sig = 2.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
@@ -35,10 +35,10 @@ def test_fp32_inverse_and_solve_error(orc):
     assert e_y <= 1e-5
 
 
-def test_fp32_stage_converges_config2_full(orc):
+def test_fp32_stage_converges_vortical64_full(orc):
     require_gpu()
-    announce("stage config2 with FP32 EJ storage")
-    wl = W.config2()
+    announce("stage vortical 64x64 with FP32 EJ storage")
+    wl = W.vortical_64x64_p4()
     fr = capi.FR.from_workload(wl)
     dq = fr.to_dev(wl.dq)
     q64, s64 = fr.solve_stage(capi.stage_config_for(wl, precision=capi.PREC_FP64), dq)
@@ -82,10 +82,10 @@ def test_bf16_mfma_factor_error(orc, dim):
     assert e <= 2.0 ** -15 * cond
 
 
-def test_bf16_mfma_stage_converges_config2(orc):
+def test_bf16_mfma_stage_converges_vortical64(orc):
     require_gpu()
-    announce("stage config2 with BF16-MFMA EJ factors")
-    wl = W.config2()
+    announce("stage vortical 64x64 with BF16-MFMA EJ factors")
+    wl = W.vortical_64x64_p4()
     fr = capi.FR.from_workload(wl)
     q, st = fr.solve_stage(capi.stage_config_for(wl, precision=capi.PREC_FP32_BF16), fr.to_dev(wl.dq))
     assert st["converged"] == 1
@@ -98,12 +98,12 @@ def test_bf16_mfma_stage_converges_config2(orc):
     assert np.linalg.norm(F) / np.linalg.norm(2 * R0) <= 1.5e-8
 
 
-def test_bf16_storage_stage_converges_config2(orc):
+def test_bf16_storage_stage_converges_vortical64(orc):
     """EJ inverses stored in BF16 (applied with FP64 accumulation): the stage
     still reaches 1e-8 in the oracle's FP64 F; iteration counts stated."""
     require_gpu()
-    announce("stage config2 with BF16-stored EJ inverses")
-    wl = W.config2()
+    announce("stage vortical 64x64 with BF16-stored EJ inverses")
+    wl = W.vortical_64x64_p4()
     fr = capi.FR.from_workload(wl)
     dq = fr.to_dev(wl.dq)
     sig = 2.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)

@@ -1,6 +1,6 @@
 """Full implicit time steps on the GPU (fr_time_step): every stage of ESDIRK3
 and ROW3 with the EJ factors formed once at q^n, against the oracle's full
-steps (oracle/stepping.py) on small meshes, and at the full config-2 size."""
+steps (oracle/stepping.py) on small meshes, and at the full 64x64 vortical size."""
 import numpy as np
 import pytest
 
@@ -49,19 +49,19 @@ def test_time_step_parity(orc, tab, case):
 
 
 @pytest.mark.parametrize("tab", ["esdirk3", "row3"])
-def test_time_step_config2(orc, tab):
-    """The full config-2 step converges in every stage; the first ESDIRK
+def test_time_step_vortical64(orc, tab):
+    """The full 64x64 vortical step converges in every stage; the first ESDIRK
     stage equals the single-stage solve; ESDIRK3 and ROW3 (same order, same
     stability function) land close together."""
     require_gpu()
-    announce("time step %s config2" % tab)
-    wl = W.config2()
+    announce("time step %s vortical 64x64 p4" % tab)
+    wl = W.vortical_64x64_p4()
     fr = capi.FR.from_workload(wl)
     dq = fr.to_dev(wl.dq)
     cfg = capi.stage_config_for(wl)
     q, st = fr.time_step(cfg, dq, tableau=TABS[tab])
     assert st["nstages"] == 3 and all(s["converged"] for s in st["stages"])
-    print("%s config2: %d FGMRES %s, %d PTC, set-up %.4f s, solve %.4f s"
+    print("%s vortical 64x64: %d FGMRES %s, %d PTC, set-up %.4f s, solve %.4f s"
           % (tab, st["gmres_iters"], [s["gmres_iters"] for s in st["stages"]], st["ptc_iters"], st["t_setup"],
              st["t_solve"]))
     if tab == "esdirk3":
@@ -75,7 +75,7 @@ def test_time_step_config2(orc, tab):
     on = other.cpu().numpy()
     upd = np.linalg.norm(qn - wl.dq)
     d = np.linalg.norm(qn - on) / upd
-    print("ESDIRK3 vs ROW3 at config 2: |difference| / |update| = %.2e" % d)
+    print("ESDIRK3 vs ROW3 on the 64x64 workload: |difference| / |update| = %.2e" % d)
     assert d <= 0.05
     # the stage solution state of ESDIRK stage 2 satisfies the oracle's stage equation
     if tab == "esdirk3":
