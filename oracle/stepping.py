@@ -10,27 +10,46 @@ The paper integrates in time with ESDIRK schemes (Sec. 2.1, Eq. (ESDIRK2) and
 the stage equations around it) and with ROW schemes (Sec. 2.1, Eq.
 (Rosenbrock_General)), and forms the preconditioner at the start of each
 physical time step (Sec. 2.2).  It names its tableaux without printing them,
-so the oracle derives its own from the order conditions (Hairer & Wanner,
-Solving ODEs II, Sec. IV.6 and IV.7):
+so the oracle builds its own (Hairer & Wanner, Solving ODEs II, Sec. IV.6
+and IV.7), in pairs that share the diagonal gamma (hence the shift
+1/(gamma dt) and the preconditioner):
 
-* ESDIRK3: four stages, explicit first stage, stiffly accurate, order 3,
-  diagonal gamma = the root in (0.4, 0.5) of 6 g^3 - 18 g^2 + 9 g - 1
-  (L-stability), abscissae c = (0, 2 gamma, 3/5, 1).  The remaining
-  coefficients follow from the four order-3 conditions.
-* ROW3: three stages, order 3, L-stable, the same gamma (so both schemes
-  share the shift 1/(gamma dt) and the same preconditioner), alpha_21 =
-  alpha_31 = 1, alpha_32 = 0 (stages 2 and 3 evaluate R at the same state),
-  b = (2/3, 1/6, 1/6), beta_31 = beta_21; beta_21 and beta_32 follow from
-  the two remaining order conditions.  Used in the transformed form of the
-  paper's Eq. (Rosenbrock_General):
-      (I/(gamma dt) - J) Y_i = R(q^n + sum_j a_ij Y_j) + (1/dt) sum_j c_ij Y_j,
-      q^{n+1} = q^n + sum_i m_i Y_i.
+* order 2 (the paper's ESDIRK2 / ROW2 comparison of Sec. 4.2), gamma =
+  1 - 1/sqrt(2) (L-stability of two implicit stages of order 2):
+  - ESDIRK2: three stages, explicit first stage, stiffly accurate,
+    c = (0, 2 gamma, 1), b from the two order-2 conditions (Kennedy &
+    Carpenter's ESDIRK2(1)3L[2]SA);
+  - ROW2: two stages, alpha_21 = 1, b = (1/2, 1/2), beta_21 from the
+    remaining order-2 condition.
+* order 3, gamma = the root in (0.4, 0.5) of 6 g^3 - 18 g^2 + 9 g - 1:
+  - ESDIRK3: four stages, explicit first stage, stiffly accurate,
+    c = (0, 2 gamma, 3/5, 1), the rest from the four order-3 conditions;
+  - ROW3: three stages, alpha_21 = alpha_31 = 1, alpha_32 = 0 (stages 2 and
+    3 evaluate R at the same state), b = (2/3, 1/6, 1/6), beta_31 =
+    beta_21; beta_21 and beta_32 from the two remaining order conditions.
+* order 4 (the ESDIRK4 / ROW4 comparison of Sec. 4.3):
+  - ESDIRK4: the six-stage ESDIRK of Bijl et al. (2002), i.e. the implicit
+    tableau of Kennedy & Carpenter's ARK4(3)6L[2]SA, gamma = 1/4, with its
+    published rational coefficients;
+  - ROW4: four stages, gamma = 0.5728160624821349 (1/x with x the second
+    root of the Laguerre polynomial L_4: L-stability at s = p = 4),
+    Shampine's alpha (alpha_21 = 1, alpha_31 = alpha_41 = 12/25,
+    alpha_32 = alpha_42 = 3/25, alpha_43 = 0: stages 3 and 4 evaluate R at
+    the same state) and b = (8/27, 1/8, 0, 125/216), gamma_31 = 0, and the
+    other beta_ij from the order-4 conditions.
+
+ROW schemes are used in the transformed form of the paper's
+Eq. (Rosenbrock_General):
+    (I/(gamma dt) - J) Y_i = R(q^n + sum_j a_ij Y_j) + (1/dt) sum_j c_ij Y_j,
+    q^{n+1} = q^n + sum_i m_i Y_i,
+with a = alpha Gamma^{-1}, c = diag(1/gamma) - Gamma^{-1}, m = b Gamma^{-1}.
 """
 from __future__ import annotations
 
 from dataclasses import dataclass, field
 
 import numpy as np
+import scipy.linalg
 
 from . import EPS_SCALED, StageStats, _setup_precond, fgmres, jvp
 
@@ -84,6 +103,17 @@ class ROWTableau:
     m: np.ndarray = field(default=None)  # transformed: b Gam^{-1}
 
 
+def _row(alpha: np.ndarray, Gam: np.ndarray, b: np.ndarray, g: float) -> ROWTableau:
+    """A ROW tableau with its transformed coefficients a = alpha Gamma^{-1},
+    c = diag(1/gamma) - Gamma^{-1}, m = b Gamma^{-1}."""
+    Gi = scipy.linalg.solve_triangular(Gam, np.eye(len(b)), lower=True)
+    t = ROWTableau(alpha=alpha, Gam=Gam, b=b, gamma=g)
+    t.a = alpha @ Gi
+    t.cm = np.diag(1.0 / np.diag(Gam)) - Gi
+    t.m = b @ Gi
+    return t
+
+
 def row3_tableau() -> ROWTableau:
     """ROW3 from the Rosenbrock order conditions with beta_ij = alpha_ij +
     gamma_ij, beta_i' = sum_j beta_ij: sum b = 1, sum b beta' = 1/2 - gamma,
@@ -99,12 +129,95 @@ def row3_tableau() -> ROWTableau:
     x = (s_ + np.sqrt(s_ * s_ - 8.0 * p_)) / 4.0
     y = s_ - 2.0 * x
     Gam = np.array([[g, 0.0, 0.0], [x - 1.0, g, 0.0], [x - 1.0, y, g]])
-    Gi = np.linalg.inv(Gam)
-    t = ROWTableau(alpha=alpha, Gam=Gam, b=b, gamma=g)
-    t.a = alpha @ Gi
-    t.cm = np.diag(1.0 / np.diag(Gam)) - Gi
-    t.m = b @ Gi
-    return t
+    return _row(alpha, Gam, b, g)
+
+
+def gamma2() -> float:
+    """1 - 1/sqrt(2): the root in (0, 1) of g^2 - 2 g + 1/2, which makes two
+    implicit stages of order 2 L-stable."""
+    return 1.0 - 1.0 / np.sqrt(2.0)
+
+
+def esdirk2_tableau() -> ESDIRKTableau:
+    """ESDIRK2: c = (0, 2 gamma, 1), stiffly accurate, b from sum b = 1 and
+    sum b c = 1/2 with b_3 = gamma, c_3 = 1."""
+    g = gamma2()
+    b2 = (0.5 - g) / (2.0 * g)
+    b1 = 1.0 - b2 - g
+    A = np.array([[0.0, 0.0, 0.0], [g, g, 0.0], [b1, b2, g]])
+    return ESDIRKTableau(A=A, b=A[2].copy(), c=A.sum(axis=1), gamma=g)
+
+
+def row2_tableau() -> ROWTableau:
+    """ROW2: alpha_21 = 1, b = (1/2, 1/2); sum b beta' = 1/2 - gamma gives
+    beta_21 = 1 - 2 gamma, so gamma_21 = beta_21 - alpha_21 = -2 gamma."""
+    g = gamma2()
+    alpha = np.array([[0.0, 0.0], [1.0, 0.0]])
+    Gam = np.array([[g, 0.0], [-2.0 * g, g]])
+    return _row(alpha, Gam, np.array([0.5, 0.5]), g)
+
+
+def esdirk4_tableau() -> ESDIRKTableau:
+    """ESDIRK4: gamma = 1/4, c = (0, 1/2, 83/250, 31/50, 17/20, 1), stiffly
+    accurate; the published rational coefficients of the implicit tableau of
+    Kennedy & Carpenter's ARK4(3)6L[2]SA (the ESDIRK4 of Bijl et al.)."""
+    g = 0.25
+    A = np.zeros((6, 6))
+    A[1, :2] = [g, g]
+    A[2, :3] = [8611.0 / 62500.0, -1743.0 / 31250.0, g]
+    A[3, :4] = [5012029.0 / 34652500.0, -654441.0 / 2922500.0, 174375.0 / 388108.0, g]
+    A[4, :5] = [15267082809.0 / 155376265600.0, -71443401.0 / 120774400.0, 730878875.0 / 902184768.0,
+                2285395.0 / 8070912.0, g]
+    A[5, :] = [82889.0 / 524892.0, 0.0, 15625.0 / 83664.0, 69875.0 / 102672.0, -2260.0 / 8211.0, g]
+    return ESDIRKTableau(A=A, b=A[5].copy(), c=A.sum(axis=1), gamma=g)
+
+
+def gamma4() -> float:
+    """1/x with x the second-smallest root of the Laguerre polynomial
+    L_4(x) = (x^4 - 16 x^3 + 72 x^2 - 96 x + 24)/24: the diagonal that makes
+    four stages of order 4 L-stable (and A-stable)."""
+    c = [1.0, -16.0, 72.0, -96.0, 24.0]
+    x = sorted(r.real for r in np.roots(c))[1]
+    for _ in range(3):  # Newton polish
+        x -= np.polyval(c, x) / np.polyval([4.0, -48.0, 144.0, -96.0], x)
+    return float(1.0 / x)
+
+
+def row4_tableau() -> ROWTableau:
+    """ROW4 from the eight order-4 Rosenbrock conditions (Hairer & Wanner,
+    Table IV.7.1) with alpha and b fixed as in Shampine's method and
+    gamma_31 = 0.  With alpha_1 = 0, alpha_2 = 1, alpha_3 = alpha_4 = 3/5 and
+    b_3 = 0 the conditions on beta reduce to
+      b4 alpha_3 alpha_32 beta_21 = 1/8 - g/3,
+      b4 beta_43 beta_32 beta_21 = 1/24 - g/2 + 3g^2/2 - g^3,
+      b4 (beta_42 beta_21 + beta_43 beta_3') = 1/6 - g + g^2,
+      b4 (beta_42 alpha_2^2 + beta_43 alpha_3^2) = 1/12 - g/3,
+      b2 beta_21 + b4 beta_4' = 1/2 - g,
+    solved in this order."""
+    g = gamma4()
+    b = np.array([8.0 / 27.0, 1.0 / 8.0, 0.0, 125.0 / 216.0])
+    a31, a32 = 12.0 / 25.0, 3.0 / 25.0
+    a3 = a31 + a32
+    alpha = np.array([[0.0, 0.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0], [a31, a32, 0.0, 0.0], [a31, a32, 0.0, 0.0]])
+    b2, b4 = b[1], b[3]
+    B21 = (1.0 / 8.0 - g / 3.0) / (b4 * a3 * a32)
+    P8 = (1.0 / 24.0 - g / 2.0 + 1.5 * g * g - g ** 3) / (b4 * B21)  # beta_43 beta_32
+    Q4 = (1.0 / 6.0 - g + g * g) / b4
+    S7 = (1.0 / 12.0 - g / 3.0) / b4
+    T2 = (0.5 - g - b2 * B21) / b4  # beta_4'
+    B31 = a31  # gamma_31 = 0
+    # beta_42 = S7 - a3^2 beta_43; Q4 = beta_42 B21 + beta_43 B31 + P8
+    B43 = (Q4 - P8 - S7 * B21) / (B31 - a3 * a3 * B21)
+    B32 = P8 / B43
+    B42 = S7 - a3 * a3 * B43
+    B41 = T2 - B42 - B43
+    beta = np.array([[0.0, 0.0, 0.0, 0.0], [B21, 0.0, 0.0, 0.0], [B31, B32, 0.0, 0.0], [B41, B42, B43, 0.0]])
+    Gam = beta - alpha + g * np.eye(4)
+    return _row(alpha, Gam, b, g)
+
+
+ESDIRK_TABLEAUX = {"esdirk2": esdirk2_tableau, "esdirk3": esdirk3_tableau, "esdirk4": esdirk4_tableau}
+ROW_TABLEAUX = {"row2": row2_tableau, "row3": row3_tableau, "row4": row4_tableau}
 
 
 def stability(z: complex, A: np.ndarray, b: np.ndarray) -> complex:
