@@ -180,42 +180,51 @@ def stage_3d(steps=1):
 
 def time_steps():
     """Full implicit time steps (every stage, EJ factors formed once at q^n)
-    of the 2D (64x64, p = 4) and 3D (32^3, p = 3) workloads with ESDIRK3 (4 stages,
-    3 implicit, PTC + inexact Newton per stage) and ROW3 (3 linear stages),
-    both order 3 and L-stable with the same diagonal, preconditioner in FP64
-    and in the BF16-storage form: DOF per second of step time, after one
-    warm-up step each."""
+    of the 2D (64x64, p = 4) and 3D (32^3, p = 3) workloads with the ESDIRK
+    (PTC + inexact Newton per implicit stage) and ROW (one linear solve per
+    stage) schemes of orders 2, 3 and 4, each pair of one order sharing its
+    diagonal; preconditioner in FP64 and in the BF16-storage form: DOF per
+    second of step time, after one warm-up step each.  The 3D workload runs
+    the order-2 pair in FP64 and the order-3 pair in both forms."""
     import torch
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
+    tabs = {"esdirk2": capi.TAB_ESDIRK2, "row2": capi.TAB_ROW2, "esdirk3": capi.TAB_ESDIRK3,
+            "row3": capi.TAB_ROW3, "esdirk4": capi.TAB_ESDIRK4, "row4": capi.TAB_ROW4}
+    precs = {"fp64": capi.PREC_FP64, "bf16_storage": capi.PREC_BF16_STORE}
+    plans = (("vortical2d", W.vortical_64x64_p4, 2, ((2, ("fp64", "bf16_storage")), (3, ("fp64", "bf16_storage")),
+                                                      (4, ("fp64", "bf16_storage")))),
+             ("tgv3d", W.tgv_32cubed_p3, 1, ((2, ("fp64",)), (3, ("fp64", "bf16_storage")))))
     out = {}
-    for wname, mk, reps in (("vortical2d", W.vortical_64x64_p4, 2), ("tgv3d", W.tgv_32cubed_p3, 1)):
+    for wname, mk, reps, orders in plans:
         wl = mk()
         fr = capi.FR.from_workload(wl)
         dq = fr.to_dev(wl.dq)
         q = fr.empty(0)
         res = {}
-        for pkey, prec in (("fp64", capi.PREC_FP64), ("bf16_storage", capi.PREC_BF16_STORE)):
-            for tkey, tab in (("esdirk3", capi.TAB_ESDIRK3), ("row3", capi.TAB_ROW3)):
-                cfg = capi.stage_config_for(wl, precision=prec)
-                fr.time_step(cfg, dq, tableau=tab, out=q)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    _, st = fr.time_step(cfg, dq, tableau=tab, out=q)
-                torch.cuda.synchronize()
-                el = (time.perf_counter() - t0) / reps
-                res["%s_%s" % (tkey, pkey)] = {
-                    "dof_per_s": wl.dof() / el, "s_per_step": el, "t_setup_s": st["t_setup"],
-                    "t_solve_s": st["t_solve"], "gmres_iters": st["gmres_iters"],
-                    "gmres_per_stage": [x["gmres_iters"] for x in st["stages"]], "ptc_iters": st["ptc_iters"]}
-            res["row3_vs_esdirk3_" + pkey] = (res["row3_" + pkey]["dof_per_s"] /
-                                              res["esdirk3_" + pkey]["dof_per_s"])
+        for order, pkeys in orders:
+            for pkey in pkeys:
+                for tkey in ("esdirk%d" % order, "row%d" % order):
+                    cfg = capi.stage_config_for(wl, precision=precs[pkey])
+                    fr.time_step(cfg, dq, tableau=tabs[tkey], out=q)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        _, st = fr.time_step(cfg, dq, tableau=tabs[tkey], out=q)
+                    torch.cuda.synchronize()
+                    el = (time.perf_counter() - t0) / reps
+                    res["%s_%s" % (tkey, pkey)] = {
+                        "dof_per_s": wl.dof() / el, "s_per_step": el, "t_setup_s": st["t_setup"],
+                        "t_solve_s": st["t_solve"], "gmres_iters": st["gmres_iters"],
+                        "gmres_per_stage": [x["gmres_iters"] for x in st["stages"]], "ptc_iters": st["ptc_iters"]}
+                res["row%d_vs_esdirk%d_%s" % (order, order, pkey)] = (
+                    res["row%d_%s" % (order, pkey)]["dof_per_s"] / res["esdirk%d_%s" % (order, pkey)]["dof_per_s"])
         out.setdefault(wname, {}).update(res)
         fr.close()
         torch.cuda.empty_cache()
-    out["note"] = ("one full step at the workload's dt from its state; ESDIRK3 stages to ||F|| <= 1e-8 "
-                   "||F(q_{i-1})|| with eta 0.1, ROW3 stages by FGMRES to 1e-8; pMG p{p0-p0/2} n{2-2}")
+    out["note"] = ("one full step at the workload's dt from its state; ESDIRK stages to ||F|| <= 1e-8 "
+                   "||F(q_{i-1})|| with eta 0.1, ROW stages by FGMRES to 1e-8; pMG p{p0-p0/2} n{2-2}; "
+                   "gamma = 1 - 1/sqrt(2) (order 2), 0.4359 (order 3), 1/4 (ESDIRK4), 0.5728 (ROW4)")
     return out
 
 
@@ -429,7 +438,8 @@ def only_kernel(args):
     y = fr.empty(0)
     if args.only_kernel == "step":
         # whole time steps (every stage, set-up included) with the requested tableau
-        tab = capi.TAB_ROW3 if args.tableau == "row3" else capi.TAB_ESDIRK3
+        tab = {"esdirk2": capi.TAB_ESDIRK2, "row2": capi.TAB_ROW2, "esdirk3": capi.TAB_ESDIRK3,
+               "row3": capi.TAB_ROW3, "esdirk4": capi.TAB_ESDIRK4, "row4": capi.TAB_ROW4}[args.tableau]
         for _ in range(args.reps):
             _, st = fr.time_step(capi.stage_config_for(wl, precision=prec), dq, tableau=tab)
             print("[bench] %s step: %d FGMRES %s, set-up %.3f s, solve %.3f s"
@@ -486,7 +496,7 @@ def main():
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--coarse-smoother", default="ej", choices=["ej", "mbnk"],
                     help="coarsest-level smoother of the --only-kernel stage driver")
-    ap.add_argument("--tableau", default="esdirk3", choices=["esdirk3", "row3"],
+    ap.add_argument("--tableau", default="esdirk3", choices=["esdirk2", "row2", "esdirk3", "row3", "esdirk4", "row4"],
                     help="time-step scheme of the --only-kernel step driver")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

@@ -302,27 +302,44 @@ fr_status gmres_solve_stage(frpmg_ctx *ctx, const stage_params *prm, const doubl
 /* ------------------------------------------------------------------------
  * Full implicit time steps (synchronous): every stage of one step of
  * dq/dt = R(q) (Sec. 2.1), the EJ factors formed once at q^n and reused by
- * every stage (Sec. 2.2).  The paper names its schemes (ESDIRK, ROW) without
- * printing their tableaux; the two here share the diagonal gamma =
- * 0.43586652150845899942 (L-stability for three implicit stages of order 3),
- * so they use the same shift and the same preconditioner:
- *   FR_TAB_ESDIRK3: 4 stages, explicit first stage, stiffly accurate,
- *     order 3, c = (0, 2 gamma, 3/5, 1) (Eq. (ESDIRK2) generalised to every
- *     stage).  Stage i solves q_i = q^n + dt (sum_{j<i} a_ij R(q_j) +
- *     gamma R(q_i)) as gmres_solve_stage does, from q_{i-1}, to
- *     ||F_i|| <= tol ||F_i(q_{i-1})||.  q^{n+1} = q_4.
- *   FR_TAB_ROW3: 3 stages, order 3 (Eq. (Rosenbrock_General)):
- *     (I/(gamma dt) - dR/dq(q^n)) Y_i = R(q^n + sum_j a_ij Y_j)
- *                                      + (1/dt) sum_j c_ij Y_j,
- *     each by FGMRES to tol relative to its right-hand side; stages 2 and 3
- *     evaluate R at the same state.  q^{n+1} = q^n + sum_i m_i Y_i.
+ * every stage (Sec. 2.2).  The paper names its schemes (ESDIRK2/ESDIRK4,
+ * ROW2/ROW4) without printing their tableaux.  The ones here come in pairs of
+ * one order that share the diagonal gamma, hence one shift 1/(gamma dt) and
+ * one preconditioner per pair; all are L-stable:
+ *   order 2, gamma = 1 - 1/sqrt(2):
+ *     FR_TAB_ESDIRK2: 3 stages, c = (0, 2 gamma, 1) (ESDIRK2(1)3L[2]SA);
+ *     FR_TAB_ROW2: 2 stages, alpha_21 = 1, b = (1/2, 1/2).
+ *   order 3, gamma = 0.43586652150845899942:
+ *     FR_TAB_ESDIRK3: 4 stages, c = (0, 2 gamma, 3/5, 1)
+ *       (ESDIRK3(2)4L[2]SA);
+ *     FR_TAB_ROW3: 3 stages, alpha_21 = alpha_31 = 1, alpha_32 = 0,
+ *       b = (2/3, 1/6, 1/6), beta_31 = beta_21.
+ *   order 4:
+ *     FR_TAB_ESDIRK4: 6 stages, gamma = 1/4, the implicit tableau of
+ *       ARK4(3)6L[2]SA (the ESDIRK4 of Bijl et al.);
+ *     FR_TAB_ROW4: 4 stages, gamma = 0.57281606248213485, Shampine's alpha
+ *       and b, gamma_31 = 0, the other beta_ij from the order-4 conditions.
+ * ESDIRK schemes have an explicit first stage and are stiffly accurate
+ * (Eq. (ESDIRK2) generalised to every stage): stage i solves
+ *   q_i = q^n + dt (sum_{j<i} a_ij R(q_j) + gamma R(q_i))
+ * as gmres_solve_stage does, from q_{i-1}, to ||F_i|| <= tol ||F_i(q_{i-1})||;
+ * q^{n+1} = q_s.  ROW schemes use the transformed form of
+ * Eq. (Rosenbrock_General):
+ *   (I/(gamma dt) - dR/dq(q^n)) Y_i = R(q^n + sum_j a_ij Y_j)
+ *                                    + (1/dt) sum_j c_ij Y_j,
+ * each by FGMRES to tol relative to its right-hand side; stages whose states
+ * coincide share one R evaluation.  q^{n+1} = q^n + sum_i m_i Y_i.
  * prm->stage carries dt and the solver and preconditioner settings; its
  * scheme, a_ii, a_i1 and skip_setup are ignored.  dq_n and dq_np1 are
  * level-0 device vectors and must not alias.  Returns FR_ENOCONV or
  * FR_ENONFINITE if a stage fails (stats then hold the stages so far). */
 #define FR_TAB_ESDIRK3 0
 #define FR_TAB_ROW3 1
-#define FR_MAX_STEP_STAGES 4
+#define FR_TAB_ESDIRK2 2
+#define FR_TAB_ROW2 3
+#define FR_TAB_ESDIRK4 4
+#define FR_TAB_ROW4 5
+#define FR_MAX_STEP_STAGES 5 /* implicit stages: ESDIRK4 has five */
 
 typedef struct {
     int tableau;         /* FR_TAB_* */
@@ -342,6 +359,22 @@ typedef struct {
 
 fr_status fr_time_step(frpmg_ctx *ctx, const step_params *prm, const double *dq_n, double *dq_np1,
                        step_stats *stats, fr_stream stream);
+
+/* The coefficients fr_time_step uses for a tableau (host only: no context,
+ * no device).  ESDIRK: rosenbrock = 0, stages = s (the first explicit),
+ * A row-major s x s in A[6][6] (b = last row, stiffly accurate).  ROW:
+ * rosenbrock = 1, stages = s, the transformed a, c (strictly lower) in
+ * a[4][4], c[4][4] and m in m[4].  Unused entries are zero.  Returns
+ * FR_EINVAL for an unknown tableau or a null pointer. */
+typedef struct {
+    int rosenbrock;
+    int stages;
+    double gamma;
+    double A[6][6];
+    double a[4][4], c[4][4], m[4];
+} fr_tableau;
+
+fr_status fr_step_tableau(int tableau, fr_tableau *out);
 
 /* ------------------------------------------------------------------------
  * Learned coarse correction (not in the paper): an element-local, bias-free

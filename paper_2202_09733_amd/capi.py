@@ -32,7 +32,7 @@ MAX_NEWTON_LOG = 128
 
 EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_residual", "fr_jvp", "ej_factor",
            "ej_solve", "ej_get_inverse", "pmg_restrict", "pmg_prolong", "pmg_set_point", "pmg_precond_apply",
-           "gmres_solve_stage", "fr_time_step", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
+           "gmres_solve_stage", "fr_time_step", "fr_step_tableau", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
            "lcc_get_weights", "lcc_set_weights", "lcc_get_scales", "lcc_set_scales", "lcc_forward",
            "lcc_loss_grad", "lcc_features_of", "mbnk_factor", "mbnk_matvec", "mbnk_ilu_solve", "mbnk_solve",
            "mbnk_get_blocks"]
@@ -105,12 +105,18 @@ class StageStats(ctypes.Structure):
         return d
 
 
-TAB_ESDIRK3, TAB_ROW3 = 0, 1
-MAX_STEP_STAGES = 4
+TAB_ESDIRK3, TAB_ROW3, TAB_ESDIRK2, TAB_ROW2, TAB_ESDIRK4, TAB_ROW4 = 0, 1, 2, 3, 4, 5
+MAX_STEP_STAGES = 5
 
 
 class StepParams(ctypes.Structure):
     _fields_ = [("tableau", ctypes.c_int), ("stage", StageParams)]
+
+
+class Tableau(ctypes.Structure):
+    _fields_ = [("rosenbrock", ctypes.c_int), ("stages", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("A", (ctypes.c_double * 6) * 6), ("a", (ctypes.c_double * 4) * 4),
+                ("c", (ctypes.c_double * 4) * 4), ("m", ctypes.c_double * 4)]
 
 
 class StepStats(ctypes.Structure):
@@ -158,6 +164,7 @@ def load():
     L.pmg_precond_apply.argtypes = [vp, ctypes.POINTER(PmgParams), vp, vp, vp]
     L.gmres_solve_stage.argtypes = [vp, ctypes.POINTER(StageParams), vp, vp, ctypes.POINTER(StageStats), vp]
     L.fr_time_step.argtypes = [vp, ctypes.POINTER(StepParams), vp, vp, ctypes.POINTER(StepStats), vp]
+    L.fr_step_tableau.argtypes = [ctypes.c_int, ctypes.POINTER(Tableau)]
     ip = ctypes.POINTER(ctypes.c_int)
     fp = ctypes.POINTER(ctypes.c_float)
     L.lcc_harvest.argtypes = [vp, ctypes.POINTER(LccHarvestParams)]
@@ -184,6 +191,25 @@ def load():
             f.restype = ctypes.c_int
     _lib = L
     return L
+
+
+def step_tableau(tableau):
+    """The coefficients the library's full time step uses for a tableau
+    (host call, no device): a dict with gamma and either A (ESDIRK, s x s)
+    or the transformed a, c, m (ROW)."""
+    t = Tableau()
+    rc = load().fr_step_tableau(int(tableau), ctypes.byref(t))
+    if rc != FR_OK:
+        raise FRError("fr_step_tableau", rc, "unknown tableau %r" % (tableau,))
+    s = t.stages
+    out = {"rosenbrock": bool(t.rosenbrock), "stages": s, "gamma": t.gamma}
+    if t.rosenbrock:
+        out["a"] = [[t.a[i][j] for j in range(s)] for i in range(s)]
+        out["c"] = [[t.c[i][j] for j in range(s)] for i in range(s)]
+        out["m"] = [t.m[i] for i in range(s)]
+    else:
+        out["A"] = [[t.A[i][j] for j in range(s)] for i in range(s)]
+    return out
 
 
 def _stream():

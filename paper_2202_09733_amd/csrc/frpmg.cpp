@@ -1219,55 +1219,165 @@ void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, doubl
 // full time steps (every stage; the EJ factors formed once at q^n)
 // ---------------------------------------------------------------------------
 
-// ESDIRK3: four stages, explicit first stage, stiffly accurate, order 3,
-// L-stable: gamma is the root in (0.4, 0.5) of 6 g^3 - 18 g^2 + 9 g - 1,
-// c = (0, 2 gamma, 3/5, 1), the other coefficients fixed by the order-3
-// conditions (the four-stage ESDIRK3(2)4L[2]SA of Kennedy & Carpenter).
-constexpr double kGamma3 = 0.43586652150845899942;
-constexpr double kEsdirk3A[4][4] = {
-    {0.0, 0.0, 0.0, 0.0},
-    {kGamma3, kGamma3, 0.0, 0.0},
-    {0.2576482460664271, -0.09351476757488614, kGamma3, 0.0},
-    {0.18764102434672392, -0.5952974735769553, 0.9717899277217725, kGamma3}};
+// Tableaux of the full time steps, in pairs of one order that share the
+// diagonal gamma (so one shift 1/(gamma dt) and one preconditioner serve both
+// schemes of a pair).  The schemes are named in Sec. 2.1 without their
+// coefficients; these are derived from the order conditions (Hairer & Wanner,
+// Solving ODEs II, Sec. IV.6-IV.7) or taken from their publication.
+constexpr int kMaxEsdirkStages = 6, kMaxRowStages = 4;
 
-// ROW3: three stages, order 3, L-stable, diagonal kGamma3, defined by
-// alpha_21 = alpha_31 = 1, alpha_32 = 0, b = (2/3, 1/6, 1/6),
-// gamma_21 = gamma_31 = beta_21 - 1, gamma_32 = beta_32, where
-// beta_21 = (s + sqrt(s^2 - 8p))/4, beta_32 = s - 2 beta_21 with
-// s = 3 - 6 gamma, p = 1 - 6 gamma + 6 gamma^2 (the two remaining order
-// conditions).  Applied in the transformed form a = alpha Gamma^{-1},
-// c = diag(1/gamma) - Gamma^{-1}, m = b Gamma^{-1}, computed here.
-struct Row3 {
-    double a[3][3] = {}, c[3][3] = {}, m[3] = {};
-    Row3() {
-        const double g = kGamma3;
-        const double sv = 3.0 - 6.0 * g, pv = 1.0 - 6.0 * g + 6.0 * g * g;
-        const double b21 = (sv + std::sqrt(sv * sv - 8.0 * pv)) / 4.0, b32 = sv - 2.0 * b21;
-        const double G[3][3] = {{g, 0.0, 0.0}, {b21 - 1.0, g, 0.0}, {b21 - 1.0, b32, g}};
-        const double alpha[3][3] = {{0.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {1.0, 0.0, 0.0}};
-        const double b[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
-        // Gi = Gamma^{-1} by forward substitution (lower triangular)
-        double Gi[3][3] = {};
-        for (int col = 0; col < 3; ++col)
-            for (int i = 0; i < 3; ++i) {
-                double t = (i == col) ? 1.0 : 0.0;
-                for (int k = 0; k < i; ++k) t -= G[i][k] * Gi[k][col];
-                Gi[i][col] = t / G[i][i];
-            }
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                double t = 0.0;
-                for (int k = 0; k < 3; ++k) t += alpha[i][k] * Gi[k][j];
-                a[i][j] = t;
-                c[i][j] = (i == j ? 1.0 / G[i][i] : 0.0) - Gi[i][j];
-            }
-        for (int j = 0; j < 3; ++j) {
-            double t = 0.0;
-            for (int i = 0; i < 3; ++i) t += b[i] * Gi[i][j];
-            m[j] = t;
-        }
-    }
+struct EsdirkTab {
+    int s = 0;       // stages, the first explicit; q^{n+1} = q_s (stiffly accurate)
+    double g = 0.0;  // a_ii, i >= 1
+    double A[kMaxEsdirkStages][kMaxEsdirkStages] = {};
 };
+
+struct RowTab {
+    int s = 0;
+    double g = 0.0;
+    // transformed coefficients a = alpha Gamma^{-1}, c = diag(1/gamma) -
+    // Gamma^{-1}, m = b Gamma^{-1}
+    double a[kMaxRowStages][kMaxRowStages] = {}, c[kMaxRowStages][kMaxRowStages] = {}, m[kMaxRowStages] = {};
+};
+
+// order 2: gamma = 1 - 1/sqrt(2) (two implicit stages of order 2 L-stable)
+// order 3: gamma = the root in (0.4, 0.5) of 6 g^3 - 18 g^2 + 9 g - 1
+// order 4 (ROW): gamma = 1/x, x the second root of the Laguerre polynomial L_4
+constexpr double kGamma3 = 0.43586652150845899942;
+constexpr double kGamma4 = 0.57281606248213485;
+
+EsdirkTab esdirk_tab(int tableau) {
+    EsdirkTab T;
+    if (tableau == FR_TAB_ESDIRK2) {
+        // c = (0, 2 gamma, 1); b_2 c_2 + gamma = 1/2 and sum b = 1
+        // (Kennedy & Carpenter's ESDIRK2(1)3L[2]SA)
+        const double g = 1.0 - std::sqrt(0.5);
+        const double b2 = (0.5 - g) / (2.0 * g), b1 = 1.0 - b2 - g;
+        T.s = 3;
+        T.g = g;
+        T.A[1][0] = T.A[1][1] = g;
+        T.A[2][0] = b1;
+        T.A[2][1] = b2;
+        T.A[2][2] = g;
+    } else if (tableau == FR_TAB_ESDIRK3) {
+        // c = (0, 2 gamma, 3/5, 1), the rest fixed by the order-3 conditions
+        // (Kennedy & Carpenter's ESDIRK3(2)4L[2]SA)
+        const double A[4][4] = {{0.0, 0.0, 0.0, 0.0},
+                                {kGamma3, kGamma3, 0.0, 0.0},
+                                {0.2576482460664271, -0.09351476757488614, kGamma3, 0.0},
+                                {0.18764102434672392, -0.5952974735769553, 0.9717899277217725, kGamma3}};
+        T.s = 4;
+        T.g = kGamma3;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) T.A[i][j] = A[i][j];
+    } else {
+        // six stages, gamma = 1/4: the implicit tableau of Kennedy &
+        // Carpenter's ARK4(3)6L[2]SA (the ESDIRK4 of Bijl et al.), published
+        // as rationals
+        const double g = 0.25;
+        const double A[6][6] = {
+            {0.0, 0.0, 0.0, 0.0, 0.0, 0.0},
+            {g, g, 0.0, 0.0, 0.0, 0.0},
+            {8611.0 / 62500.0, -1743.0 / 31250.0, g, 0.0, 0.0, 0.0},
+            {5012029.0 / 34652500.0, -654441.0 / 2922500.0, 174375.0 / 388108.0, g, 0.0, 0.0},
+            {15267082809.0 / 155376265600.0, -71443401.0 / 120774400.0, 730878875.0 / 902184768.0,
+             2285395.0 / 8070912.0, g, 0.0},
+            {82889.0 / 524892.0, 0.0, 15625.0 / 83664.0, 69875.0 / 102672.0, -2260.0 / 8211.0, g}};
+        T.s = 6;
+        T.g = g;
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) T.A[i][j] = A[i][j];
+    }
+    return T;
+}
+
+// (alpha, Gamma = beta - alpha + gamma I, b) -> transformed coefficients
+RowTab row_transform(int s, double g, const double alpha[kMaxRowStages][kMaxRowStages],
+                     const double beta[kMaxRowStages][kMaxRowStages], const double *b) {
+    RowTab T;
+    T.s = s;
+    T.g = g;
+    double G[kMaxRowStages][kMaxRowStages] = {}, Gi[kMaxRowStages][kMaxRowStages] = {};
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < i; ++j) G[i][j] = beta[i][j] - alpha[i][j];
+    for (int i = 0; i < s; ++i) G[i][i] = g;
+    // Gamma^{-1} by forward substitution, column by column
+    for (int col = 0; col < s; ++col)
+        for (int i = col; i < s; ++i) {
+            double t = (i == col) ? 1.0 : 0.0;
+            for (int k = col; k < i; ++k) t -= G[i][k] * Gi[k][col];
+            Gi[i][col] = t / G[i][i];
+        }
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < i; ++j) {
+            double t = 0.0;
+            for (int k = j; k < i; ++k) t += alpha[i][k] * Gi[k][j];
+            T.a[i][j] = t;
+            T.c[i][j] = -Gi[i][j];
+        }
+    for (int j = 0; j < s; ++j) {
+        double t = 0.0;
+        for (int i = j; i < s; ++i) t += b[i] * Gi[i][j];
+        T.m[j] = t;
+    }
+    return T;
+}
+
+RowTab row_tab(int tableau) {
+    double al[kMaxRowStages][kMaxRowStages] = {}, be[kMaxRowStages][kMaxRowStages] = {};
+    if (tableau == FR_TAB_ROW2) {
+        // alpha_21 = 1, b = (1/2, 1/2); sum b beta' = 1/2 - gamma
+        const double g = 1.0 - std::sqrt(0.5), b[2] = {0.5, 0.5};
+        al[1][0] = 1.0;
+        be[1][0] = 1.0 - 2.0 * g;
+        return row_transform(2, g, al, be, b);
+    }
+    if (tableau == FR_TAB_ROW3) {
+        // alpha_21 = alpha_31 = 1, alpha_32 = 0, b = (2/3, 1/6, 1/6),
+        // beta_31 = beta_21; with s = 3 - 6 gamma, p = 1 - 6 gamma + 6 gamma^2
+        // the two remaining order-3 conditions give beta_21 =
+        // (s + sqrt(s^2 - 8p))/4, beta_32 = s - 2 beta_21
+        const double g = kGamma3, b[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
+        const double sv = 3.0 - 6.0 * g, pv = 1.0 - 6.0 * g + 6.0 * g * g;
+        const double b21 = (sv + std::sqrt(sv * sv - 8.0 * pv)) / 4.0;
+        al[1][0] = al[2][0] = 1.0;
+        be[1][0] = be[2][0] = b21;
+        be[2][1] = sv - 2.0 * b21;
+        return row_transform(3, g, al, be, b);
+    }
+    // ROW4: Shampine's alpha (alpha_21 = 1, alpha_31 = alpha_41 = 12/25,
+    // alpha_32 = alpha_42 = 3/25: stages 3 and 4 share one state) and
+    // b = (8/27, 1/8, 0, 125/216), gamma_31 = 0, the L-stable gamma of four
+    // stages of order 4; the order-4 conditions on beta, taken one at a time
+    // (alpha_2 = 1, alpha_3 = alpha_4 = 3/5, b_3 = 0):
+    //   b4 alpha_3 alpha_32 beta_21        = 1/8 - g/3
+    //   b4 beta_43 beta_32 beta_21         = 1/24 - g/2 + 3g^2/2 - g^3
+    //   b4 (beta_42 + alpha_3^2 beta_43)   = 1/12 - g/3
+    //   b4 (beta_42 beta_21 + beta_43 beta_3') = 1/6 - g + g^2
+    //   b2 beta_21 + b4 beta_4'            = 1/2 - g
+    const double g = kGamma4, b[4] = {8.0 / 27.0, 1.0 / 8.0, 0.0, 125.0 / 216.0};
+    const double a31 = 12.0 / 25.0, a32 = 3.0 / 25.0, a3 = a31 + a32, b2 = b[1], b4 = b[3];
+    const double B21 = (1.0 / 8.0 - g / 3.0) / (b4 * a3 * a32);
+    const double prod = (1.0 / 24.0 - g / 2.0 + 1.5 * g * g - g * g * g) / (b4 * B21);  // beta_43 beta_32
+    const double S7 = (1.0 / 12.0 - g / 3.0) / b4, Q4 = (1.0 / 6.0 - g + g * g) / b4;
+    const double B31 = a31;
+    const double B43 = (Q4 - prod - S7 * B21) / (B31 - a3 * a3 * B21);
+    const double B32 = prod / B43, B42 = S7 - a3 * a3 * B43;
+    const double B41 = (0.5 - g - b2 * B21) / b4 - B42 - B43;
+    al[1][0] = 1.0;
+    al[2][0] = al[3][0] = a31;
+    al[2][1] = al[3][1] = a32;
+    be[1][0] = B21;
+    be[2][0] = B31;
+    be[2][1] = B32;
+    be[3][0] = B41;
+    be[3][1] = B42;
+    be[3][2] = B43;
+    return row_transform(4, g, al, be, b);
+}
+
+bool is_esdirk_tab(int t) { return t == FR_TAB_ESDIRK2 || t == FR_TAB_ESDIRK3 || t == FR_TAB_ESDIRK4; }
+bool is_row_tab(int t) { return t == FR_TAB_ROW2 || t == FR_TAB_ROW3 || t == FR_TAB_ROW4; }
 
 void ensure_step_vectors(frpmg_ctx *ctx, int nvec) {
     const size_t N = ctx->lv[0].N;
@@ -1281,16 +1391,21 @@ void ensure_step_vectors(frpmg_ctx *ctx, int nvec) {
 void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double *out, step_stats *ss,
                hipStream_t s) {
     std::memset(ss, 0, sizeof(*ss));
-    REQUIRE(SP.tableau == FR_TAB_ESDIRK3 || SP.tableau == FR_TAB_ROW3, "unknown tableau");
+    const bool esdirk = is_esdirk_tab(SP.tableau);
+    REQUIRE(esdirk || is_row_tab(SP.tableau), "unknown tableau");
     REQUIRE(out != dq_n, "the output must not alias q^n");
+    const EsdirkTab TE = esdirk ? esdirk_tab(SP.tableau) : EsdirkTab{};
+    const RowTab TR = esdirk ? RowTab{} : row_tab(SP.tableau);
     stage_params P = SP.stage;
-    P.scheme = SP.tableau == FR_TAB_ESDIRK3 ? FR_SCHEME_ESDIRK : FR_SCHEME_ROW;
-    P.a_ii = kGamma3;
+    P.scheme = esdirk ? FR_SCHEME_ESDIRK : FR_SCHEME_ROW;
+    P.a_ii = esdirk ? TE.g : TR.g;
     P.a_i1 = 0.0;
     StageSolver S(ctx, P);
     const size_t N = S.N;
-    ensure_step_vectors(ctx, 3);
-    double *V3[3] = {ctx->stv, ctx->stv + N, ctx->stv + 2 * N};
+    const int nvec = esdirk ? TE.s - 1 : TR.s;  // ESDIRK: R(q_j), j < s - 1; ROW: Y_i
+    ensure_step_vectors(ctx, nvec);
+    double *V[kMaxEsdirkStages];
+    for (int j = 0; j < nvec; ++j) V[j] = ctx->stv + (size_t)j * N;
     HIPCHK(hipStreamSynchronize(s));
     const double t0 = now();
     S.setup(dq_n, s);
@@ -1299,28 +1414,27 @@ void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double
     ss->t_setup = t1 - t0;
     fr_status status = FR_OK;
     const Scal one{1.0, nullptr};
-    if (S.esdirk) {
-        // stage 1: q_1 = q^n; stages 2..4 start from the previous stage's state
+    if (esdirk) {
+        // stage 1: q_1 = q^n; stages 2..s start from the previous stage's state
         double *q = ctx->sq, *rq = ctx->srq, *b = ctx->sb;
         residual(ctx, 0, dq_n, rq, s);
         S.cnt.R0++;
-        HIPCHK(hipMemcpyAsync(V3[0], rq, N * sizeof(double), hipMemcpyDeviceToDevice, s));  // R(q_1)
+        HIPCHK(hipMemcpyAsync(V[0], rq, N * sizeof(double), hipMemcpyDeviceToDevice, s));  // R(q_1)
         HIPCHK(hipMemcpyAsync(q, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-        for (int i = 1; i < 4 && status == FR_OK; ++i) {
+        for (int i = 1; i < TE.s && status == FR_OK; ++i) {
             // b_i = q^n + dt sum_{j<i} a_ij R(q_j)
             HIPCHK(hipMemcpyAsync(b, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
             for (int j = 0; j < i; ++j)
-                HIPCHK(vec_axpby(N, Scal{kEsdirk3A[i][j] * P.dt, nullptr}, V3[j], one, b, s));
+                if (TE.A[i][j] != 0.0) HIPCHK(vec_axpby(N, Scal{TE.A[i][j] * P.dt, nullptr}, V[j], one, b, s));
             stage_stats *st = &ss->stage[ss->nstages];
             status = S.esdirk_solve(b, q, rq, st, s);
             ss->nstages++;
             ss->gmres_iters += st->gmres_iters;
             ss->ptc_iters += st->ptc_iters;
-            if (i < 3) HIPCHK(hipMemcpyAsync(V3[i], rq, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if (i < TE.s - 1) HIPCHK(hipMemcpyAsync(V[i], rq, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         }
         HIPCHK(hipMemcpyAsync(out, q, N * sizeof(double), hipMemcpyDeviceToDevice, s));  // stiffly accurate
     } else {
-        static const Row3 T;
         double *R0 = ctx->srq, *rhs = ctx->sb, *w = ctx->stw, *Rw = ctx->sq;
         residual(ctx, 0, dq_n, R0, s);
         S.cnt.R0++;
@@ -1328,31 +1442,31 @@ void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double
             pmg_point(ctx, dq_n, R0, s);
             S.cnt.R1 += ctx->nlevels - 1;
         }
-        for (int i = 0; i < 3 && status == FR_OK; ++i) {
+        for (int i = 0; i < TR.s && status == FR_OK; ++i) {
             // rhs_i = R(q^n + sum_j a_ij Y_j) + (1/dt) sum_j c_ij Y_j
             if (i == 0) {
                 HIPCHK(hipMemcpyAsync(rhs, R0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
             } else {
                 bool same = i > 1;
-                for (int j = 0; j < 3; ++j) same = same && T.a[i][j] == T.a[i - 1][j];
+                for (int j = 0; j < TR.s; ++j) same = same && TR.a[i][j] == TR.a[i - 1][j];
                 if (!same) {  // stages with the same state share R
                     HIPCHK(hipMemcpyAsync(w, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
                     for (int j = 0; j < i; ++j)
-                        if (T.a[i][j] != 0.0) HIPCHK(vec_axpby(N, Scal{T.a[i][j], nullptr}, V3[j], one, w, s));
+                        if (TR.a[i][j] != 0.0) HIPCHK(vec_axpby(N, Scal{TR.a[i][j], nullptr}, V[j], one, w, s));
                     residual(ctx, 0, w, Rw, s);
                     S.cnt.R0++;
                 }
                 HIPCHK(hipMemcpyAsync(rhs, Rw, N * sizeof(double), hipMemcpyDeviceToDevice, s));
                 for (int j = 0; j < i; ++j)
-                    HIPCHK(vec_axpby(N, Scal{T.c[i][j] / P.dt, nullptr}, V3[j], one, rhs, s));
+                    if (TR.c[i][j] != 0.0) HIPCHK(vec_axpby(N, Scal{TR.c[i][j] / P.dt, nullptr}, V[j], one, rhs, s));
             }
             stage_stats *st = &ss->stage[ss->nstages];
-            status = S.row_solve(dq_n, R0, rhs, V3[i], st, s);
+            status = S.row_solve(dq_n, R0, rhs, V[i], st, s);
             ss->nstages++;
             ss->gmres_iters += st->gmres_iters;
         }
         HIPCHK(hipMemcpyAsync(out, dq_n, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-        for (int i = 0; i < 3; ++i) HIPCHK(vec_axpby(N, Scal{T.m[i], nullptr}, V3[i], one, out, s));
+        for (int i = 0; i < TR.s; ++i) HIPCHK(vec_axpby(N, Scal{TR.m[i], nullptr}, V[i], one, out, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     const double t2 = now();
@@ -1707,6 +1821,31 @@ fr_status fr_time_step(frpmg_ctx *ctx, const step_params *prm, const double *dq_
         REQUIRE(prm && dq_n && dq_np1 && dq_n != dq_np1, "bad arguments");
         step_impl(ctx, *prm, dq_n, dq_np1, st, S(stream));
     });
+}
+
+fr_status fr_step_tableau(int tableau, fr_tableau *out) {
+    if (!out || !(is_esdirk_tab(tableau) || is_row_tab(tableau))) return FR_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    if (is_esdirk_tab(tableau)) {
+        const EsdirkTab T = esdirk_tab(tableau);
+        out->stages = T.s;
+        out->gamma = T.g;
+        for (int i = 0; i < T.s; ++i)
+            for (int j = 0; j < T.s; ++j) out->A[i][j] = T.A[i][j];
+    } else {
+        const RowTab T = row_tab(tableau);
+        out->rosenbrock = 1;
+        out->stages = T.s;
+        out->gamma = T.g;
+        for (int i = 0; i < T.s; ++i) {
+            for (int j = 0; j < T.s; ++j) {
+                out->a[i][j] = T.a[i][j];
+                out->c[i][j] = T.c[i][j];
+            }
+            out->m[i] = T.m[i];
+        }
+    }
+    return FR_OK;
 }
 
 fr_status lcc_harvest(frpmg_ctx *ctx, const lcc_harvest_params *prm) {

@@ -33,7 +33,8 @@ def test_stage_at_steady_state_is_exact(case):
     assert not np.any(out.cpu().numpy())
 
 
-@pytest.mark.parametrize("tableau", [capi.TAB_ESDIRK3, capi.TAB_ROW3])
+@pytest.mark.parametrize("tableau", [capi.TAB_ESDIRK2, capi.TAB_ROW2, capi.TAB_ESDIRK3, capi.TAB_ROW3,
+                                     capi.TAB_ESDIRK4, capi.TAB_ROW4])
 def test_time_step_at_steady_state_is_exact(tableau):
     require_gpu()
     announce("time step at the freestream, tableau %d" % tableau)

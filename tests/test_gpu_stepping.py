@@ -1,6 +1,7 @@
-"""Full implicit time steps on the GPU (fr_time_step): every stage of ESDIRK3
-and ROW3 with the EJ factors formed once at q^n, against the oracle's full
-steps (oracle/stepping.py) on small meshes, and at the full 64x64 vortical size."""
+"""Full implicit time steps on the GPU (fr_time_step): every stage of the
+ESDIRK2/3/4 and ROW2/3/4 schemes with the EJ factors formed once at q^n,
+against the oracle's full steps (oracle/stepping.py) on small meshes, and at
+the full 64x64 vortical size."""
 import numpy as np
 import pytest
 
@@ -10,19 +11,22 @@ from gpu_util import announce, rel, require_gpu
 
 pytestmark = pytest.mark.gpu
 
-TABS = {"esdirk3": capi.TAB_ESDIRK3, "row3": capi.TAB_ROW3}
+TABS = {"esdirk3": capi.TAB_ESDIRK3, "row3": capi.TAB_ROW3, "esdirk2": capi.TAB_ESDIRK2,
+        "row2": capi.TAB_ROW2, "esdirk4": capi.TAB_ESDIRK4, "row4": capi.TAB_ROW4}
+# implicit stages: ESDIRK s - 1 (explicit first stage), ROW s
+NSTAGES = {"esdirk2": 2, "row2": 2, "esdirk3": 3, "row3": 3, "esdirk4": 5, "row4": 4}
 
 
 def _oracle_step(orc, wl, tab, **kw):
     from oracle import stepping as S
     fine = orc.Level(**wl.level_kwargs(wl.p0))
     coarse = orc.Level(**wl.level_kwargs(wl.p1))
-    if tab == "esdirk3":
-        return S.esdirk_step(fine, coarse, wl.dq, wl.dt, **kw)
-    return S.row_step(fine, coarse, wl.dq, wl.dt, **kw)
+    if tab.startswith("esdirk"):
+        return S.esdirk_step(fine, coarse, wl.dq, wl.dt, tab=S.ESDIRK_TABLEAUX[tab](), **kw)
+    return S.row_step(fine, coarse, wl.dq, wl.dt, tab=S.ROW_TABLEAUX[tab](), **kw)
 
 
-@pytest.mark.parametrize("tab", ["esdirk3", "row3"])
+@pytest.mark.parametrize("tab", list(TABS))
 @pytest.mark.parametrize("case", ["bumps8", "vortical8"])
 def test_time_step_parity(orc, tab, case):
     """GPU and oracle full steps agree to the stage solvers' tolerance: the
@@ -37,8 +41,8 @@ def test_time_step_parity(orc, tab, case):
     cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3)
     q, st = fr.time_step(cfg, fr.to_dev(wl.dq), tableau=TABS[tab])
     q = q.cpu().numpy()
-    assert st["nstages"] == 3 and all(s["converged"] for s in st["stages"])
-    kw = dict(tol=1e-10) if tab == "row3" else dict(tol=1e-10, eta=1e-3)
+    assert st["nstages"] == NSTAGES[tab] and all(s["converged"] for s in st["stages"])
+    kw = dict(tol=1e-10) if tab.startswith("row") else dict(tol=1e-10, eta=1e-3)
     q_ref, so = _oracle_step(orc, wl, tab, **kw)
     assert so.converged
     upd = np.linalg.norm(q_ref - wl.dq)
@@ -86,3 +90,34 @@ def test_time_step_vortical64(orc, tab):
         q2h = q2.cpu().numpy()
         F = (q2h - b) / (g * wl.dt) - L0.residual(q2h)
         assert np.linalg.norm(F) / np.linalg.norm(2 * R0) <= 1.5e-8
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_time_step_pairs_vortical64(order):
+    """The order-2 and order-4 pairs at the full 64x64 vortical size: every
+    stage of both schemes converges.  The order-2 pair shares its stability
+    function (same gamma, two implicit stages each), so its two steps land
+    close together, as the order-3 pair's do; the order-4 schemes differ in
+    their stage counts and stability functions, so only convergence is
+    checked for them."""
+    require_gpu()
+    announce("time steps of order %d, vortical 64x64 p4" % order)
+    wl = W.vortical_64x64_p4()
+    fr = capi.FR.from_workload(wl)
+    dq = fr.to_dev(wl.dq)
+    cfg = capi.stage_config_for(wl)
+    names = ["esdirk%d" % order, "row%d" % order]
+    out = {}
+    for n in names:
+        q, st = fr.time_step(cfg, dq, tableau=TABS[n])
+        assert st["nstages"] == NSTAGES[n] and all(s["converged"] for s in st["stages"]), st
+        print("%s vortical 64x64: %d FGMRES %s, %d PTC, set-up %.4f s, solve %.4f s"
+              % (n, st["gmres_iters"], [s["gmres_iters"] for s in st["stages"]], st["ptc_iters"],
+                 st["t_setup"], st["t_solve"]))
+        out[n] = q.cpu().numpy()
+    upd = np.linalg.norm(out[names[1]] - wl.dq)
+    d = np.linalg.norm(out[names[0]] - out[names[1]]) / upd
+    print("%s vs %s: |difference| / |update| = %.2e" % (names[0], names[1], d))
+    assert np.all(np.isfinite(out[names[0]])) and np.all(np.isfinite(out[names[1]]))
+    if order == 2:
+        assert d <= 0.05
