@@ -52,9 +52,12 @@ struct Shape {
     // (p = 0) takes 64 elements per workgroup to bound the LDS staging
     static constexpr int EB = (P == 1) ? 64 : ((256 / NP) > 0 ? (256 / NP) : 1);
     static constexpr int NT = round64(NP * EB);
-    // face kernel: one lane per (element, + face point)
-    static constexpr int EBF = (P == 1) ? 64 : ((256 / (DIM * NF)) > 0 ? (256 / (DIM * NF)) : 1);
-    static constexpr int NTF = round64(DIM * NF * EBF);
+    // face kernel: one lane per (element, + face point), the lanes of each
+    // flux direction in whole wavefronts (LPA per axis), so that no
+    // wavefront runs two directions' flux code one after the other
+    static constexpr int EBF = (NF >= 64) ? 1 : 64 / NF;
+    static constexpr int LPA = round64(NF * EBF);
+    static constexpr int NTF = DIM * LPA;
 
     // local point on the line along axis a through face point f, position j
     __device__ __forceinline__ static int line(int a, int f, int j) {
@@ -454,18 +457,17 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NTF)) __attribute__((amdgpu_wa
         s_qp[t] = s;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < DIM * NF * EB; t += blockDim.x) {
-        const int e = t % EB;
-        const int r = t / EB;
-        const int f = r % NF, a = r / NF;
-        if (e >= ne) continue;
-        if (a == 0) {
-            face_flux<DIM, P, 0, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
-        } else if (a == 1) {
-            face_flux<DIM, P, 1, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
-        } else {
-            if constexpr (DIM == 3) face_flux<DIM, P, 2, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
-        }
+    // one face point per lane; the direction is uniform over each wavefront
+    const int a = __builtin_amdgcn_readfirstlane((int)threadIdx.x / S::LPA);
+    const int rest = threadIdx.x % S::LPA;
+    const int e = rest % EB, f = rest / EB;
+    if (rest >= NF * EB || e >= ne) return;
+    if (a == 0) {
+        face_flux<DIM, P, 0, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
+    } else if (a == 1) {
+        face_flux<DIM, P, 1, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
+    } else {
+        if constexpr (DIM == 3) face_flux<DIM, P, 2, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
     }
 }
 
