@@ -54,8 +54,11 @@ struct Shape {
     static constexpr int NT = round64(NP * EB);
     // face kernel: one lane per (element, + face point), the lanes of each
     // flux direction in whole wavefronts (LPA per axis), so that no
-    // wavefront runs two directions' flux code one after the other
-    static constexpr int EBF = (NF >= 64) ? 1 : 64 / NF;
+    // wavefront runs two directions' flux code one after the other.  2D
+    // fills half of each wavefront (32 lanes per direction): the kernel is
+    // latency-bound there, and twice the workgroups spread it over more CUs
+    // (config-2 residual 19.3 -> 17.5 us)
+    static constexpr int EBF = (DIM == 2) ? (NF >= 32 ? 1 : 32 / NF) : (NF >= 64 ? 1 : 64 / NF);
     static constexpr int LPA = round64(NF * EBF);
     static constexpr int NTF = DIM * LPA;
 
