@@ -37,9 +37,10 @@ constexpr int kChunk = 8;
 __global__ void __launch_bounds__(kThreads) k_mdot_partial(size_t n, int nvec, const double *__restrict__ V,
                                                            size_t ldv, const double *__restrict__ w,
                                                            double *__restrict__ partial) {
-    __shared__ double s_red[kThreads / 64];
+    __shared__ double s_part[kChunk][kThreads / 64];
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int v0 = 0; v0 < nvec; v0 += kChunk) {
         const int nc = min(kChunk, nvec - v0);
         double acc[kChunk];
@@ -51,10 +52,27 @@ __global__ void __launch_bounds__(kThreads) k_mdot_partial(size_t n, int nvec, c
             for (int c = 0; c < kChunk; ++c)
                 if (c < nc) acc[c] += V[(size_t)(v0 + c) * ldv + i] * wi;
         }
-        for (int c = 0; c < nc; ++c) {
-            const double tot = block_sum(acc[c], s_red);
-            if (threadIdx.x == 0) partial[(size_t)(v0 + c) * gridDim.x + blockIdx.x] = tot;
+        // the chunk's block sums in one pass: each wavefront reduces its nc
+        // values by shuffles, then lane c of the block adds vector c's four
+        // wavefront sums in wavefront order (the order of block_sum, so the
+        // bits do not change), with one barrier per chunk instead of two per
+        // vector
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+            if (c < nc) {
+                double v = acc[c];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+                if (lane == 0) s_part[c][wid] = v;
+            }
         }
+        __syncthreads();
+        if ((int)threadIdx.x < nc) {
+            double tot = 0.0;
+            for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) tot += s_part[threadIdx.x][w2];
+            partial[(size_t)(v0 + threadIdx.x) * gridDim.x + blockIdx.x] = tot;
+        }
+        __syncthreads();  // s_part is rewritten by the next chunk
     }
 }
 
