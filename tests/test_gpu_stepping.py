@@ -121,3 +121,25 @@ def test_time_step_pairs_vortical64(order):
     assert np.all(np.isfinite(out[names[0]])) and np.all(np.isfinite(out[names[1]]))
     if order == 2:
         assert d <= 0.05
+
+
+@pytest.mark.parametrize("tab", ["esdirk2", "row2", "row4"])
+def test_time_step_parity_3d(orc, tab):
+    """The same comparison on a 2^3 Taylor-Green mesh (p{3-2}, 3D kernels),
+    at its large dt (100 dt_exp): every stage converges and the GPU step
+    matches the oracle's to the solvers' tolerance."""
+    require_gpu()
+    announce("time step %s tgv 2x2x2 p3" % tab)
+    wl = W.make_tgv_workload(n=(2, 2, 2))
+    fr = capi.FR.from_workload(wl)
+    cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3)
+    q, st = fr.time_step(cfg, fr.to_dev(wl.dq), tableau=TABS[tab])
+    q = q.cpu().numpy()
+    assert st["nstages"] == NSTAGES[tab] and all(s["converged"] for s in st["stages"])
+    kw = dict(tol=1e-10) if tab.startswith("row") else dict(tol=1e-10, eta=1e-3)
+    q_ref, so = _oracle_step(orc, wl, tab, **kw)
+    assert so.converged
+    d = np.linalg.norm(q - q_ref) / np.linalg.norm(q_ref - wl.dq)
+    print("%s tgv2: GPU %d FGMRES, oracle %d; |q - q_ref| / |update| = %.2e"
+          % (tab, st["gmres_iters"], so.gmres_iters, d))
+    assert d <= 1e-6
