@@ -143,3 +143,25 @@ def test_time_step_parity_3d(orc, tab):
     print("%s tgv2: GPU %d FGMRES, oracle %d; |q - q_ref| / |update| = %.2e"
           % (tab, st["gmres_iters"], so.gmres_iters, d))
     assert d <= 1e-6
+
+
+@pytest.mark.parametrize("tab", ["esdirk2", "row2"])
+def test_time_step_parity_ej_preconditioner(orc, tab):
+    """Full steps with the element-Jacobi preconditioner instead of pMG
+    (the paper's JFNK-EJ / GMRES-EJ baseline): GPU against the oracle on
+    the 8x8 bump mesh."""
+    require_gpu()
+    announce("time step %s bumps8 EJ preconditioner" % tab)
+    wl = W.make_bump_workload(n=(8, 8), p0=2, p1=1, dt_factor=10.0)
+    fr = capi.FR.from_workload(wl)
+    cfg = capi.stage_config_for(wl, precond=capi.PRECOND_EJ, tol=1e-10, eta=1e-3)
+    q, st = fr.time_step(cfg, fr.to_dev(wl.dq), tableau=TABS[tab])
+    q = q.cpu().numpy()
+    assert st["nstages"] == NSTAGES[tab] and all(s["converged"] for s in st["stages"])
+    kw = dict(tol=1e-10, precond="ej") if tab.startswith("row") else dict(tol=1e-10, eta=1e-3, precond="ej")
+    q_ref, so = _oracle_step(orc, wl, tab, **kw)
+    assert so.converged
+    d = np.linalg.norm(q - q_ref) / np.linalg.norm(q_ref - wl.dq)
+    print("%s bumps8 EJ: GPU %d FGMRES, oracle %d; |q - q_ref| / |update| = %.2e"
+          % (tab, st["gmres_iters"], so.gmres_iters, d))
+    assert d <= 1e-6
