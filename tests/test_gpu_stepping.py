@@ -165,3 +165,31 @@ def test_time_step_parity_ej_preconditioner(orc, tab):
     print("%s bumps8 EJ: GPU %d FGMRES, oracle %d; |q - q_ref| / |update| = %.2e"
           % (tab, st["gmres_iters"], so.gmres_iters, d))
     assert d <= 1e-6
+
+
+@pytest.mark.parametrize("tab", ["esdirk2", "row2"])
+def test_time_step_mbnk_coarse_smoother(tab):
+    """Full steps with MBNK sweeps on the coarsest level: a different
+    preconditioner for the same stage equations, so every stage converges and
+    the step equals the EJ-smoothed one to the solvers' tolerance."""
+    require_gpu()
+    announce("time step %s bumps8 MBNK coarse" % tab)
+    wl = W.make_bump_workload(n=(8, 8), p0=2, p1=1, dt_factor=10.0)
+    fr = capi.FR.from_workload(wl)
+    dq = fr.to_dev(wl.dq)
+    out = {}
+    for sm in (capi.SMOOTHER_EJ, capi.SMOOTHER_MBNK):
+        cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3, coarse_smoother=sm)
+        q, st = fr.time_step(cfg, dq, tableau=TABS[tab])
+        assert st["nstages"] == NSTAGES[tab] and all(s["converged"] for s in st["stages"]), st
+        out[sm] = (q.cpu().numpy(), st["gmres_iters"], st["n_R_coarse"])
+    # the MBNK set-up assembles the coarse operator by coloured differences:
+    # n_b (1 + colours) coarse residuals against n_b for the EJ blocks
+    print("coarse residual evaluations: %d with EJ smoothing, %d with MBNK"
+          % (out[capi.SMOOTHER_EJ][2], out[capi.SMOOTHER_MBNK][2]))
+    assert out[capi.SMOOTHER_MBNK][2] > out[capi.SMOOTHER_EJ][2]
+    qe, qm = out[capi.SMOOTHER_EJ][0], out[capi.SMOOTHER_MBNK][0]
+    d = np.linalg.norm(qm - qe) / np.linalg.norm(qe - wl.dq)
+    print("%s bumps8: EJ coarse %d FGMRES, MBNK coarse %d; |difference| / |update| = %.2e"
+          % (tab, out[capi.SMOOTHER_EJ][1], out[capi.SMOOTHER_MBNK][1], d))
+    assert d <= 1e-6
