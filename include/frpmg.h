@@ -91,12 +91,18 @@ fr_status fr_residual(frpmg_ctx *ctx, int level, const double *dq, double *r, fr
 #define FR_EPS_ABSOLUTE 0   /* h = eps */
 #define FR_EPS_NORMALIZED 1 /* h = eps / ||v||_2 (perturbation of norm eps) */
 #define FR_EPS_SCALED 2     /* h = eps (1 + ||dq||_2) / ||v||_2 (Knoll-Keyes scaling) */
+#define FR_FD_CENTRAL 4     /* ORed into an FR_EPS_* mode: central instead of one-sided difference */
 
 /* Finite-difference shifted Jacobian-vector product (Sec. 2.2, the matrix-
  * free product with fixed eps = 1e-6):
  *   w = shift v - (R(dq + h v) - rq) / h,
- * rq = R(dq) supplied by the caller.  All arrays of the level's size; w must
- * not alias the inputs. */
+ * rq = R(dq) supplied by the caller.  With FR_FD_CENTRAL ORed into eps_mode
+ * (not in the paper, which takes the one-sided difference):
+ *   w = shift v - (R(dq + h v) - R(dq - h v)) / (2 h)
+ * (rq unused; two residual evaluations), whose truncation error is O(h^2)
+ * instead of O(h), so that the FD operator is linear in v to rounding and a
+ * Krylov solve's estimate and its recomputed residual agree.  All arrays of
+ * the level's size; w must not alias the inputs. */
 fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const double *v,
                  double shift, double eps, int eps_mode, double *w, fr_stream stream);
 
@@ -114,7 +120,8 @@ fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, 
  * every block by Gauss-Jordan elimination with partial pivoting and stores
  * the inverse in the requested precision.  Needs at least two elements per
  * axis (FR_EINVAL otherwise).
- * Returns FR_ESINGULAR if a block has an exact zero pivot.  Synchronises the
+ * Returns FR_ESINGULAR if a block has an exact zero pivot, FR_ENONFINITE if a
+ * pivot is NaN or infinite (a non-finite state or block).  Synchronises the
  * stream at the end (to report the pivot status). */
 fr_status ej_factor(frpmg_ctx *ctx, int level, const double *dq_lin, double sigma, int precision,
                     fr_stream stream);
@@ -148,7 +155,7 @@ fr_status ej_get_inverse(frpmg_ctx *ctx, int level, double *host_out);
  *   unknowns (FR_EINVAL otherwise).  Allocates its workspace at the first
  *   call for a level (the blocks take (3 + 2 dim) Ne nb^2 doubles, the
  *   formation batch up to 128 MiB per buffer).  Synchronises the stream;
- *   FR_ESINGULAR on a zero pivot.
+ *   FR_ESINGULAR on a zero pivot, FR_ENONFINITE on a NaN or infinite one.
  * mbnk_matvec: y = A x.  mbnk_ilu_solve: z = (L U)^{-1} r.
  * mbnk_solve: delta ~ A^{-1} g by one GMRES(maxit <= 8) cycle from zero to
  *   relative tolerance tol (convergence decided on the device, no host
@@ -235,7 +242,7 @@ typedef struct {
     int precision;     /* FR_PREC_* of the EJ factors */
     int n0, n1;        /* pMG smoothing */
     double eps;        /* FD step of the JVP */
-    int eps_mode;      /* FR_EPS_* */
+    int eps_mode;      /* FR_EPS_*, optionally ORed with FR_FD_CENTRAL */
     int scale_mode;    /* FR_SCALE_* of the preconditioner */
     double eps_p;      /* preconditioner scale */
     int skip_setup;    /* 1: reuse the EJ factors already in the context */
@@ -449,6 +456,12 @@ fr_status lcc_forward(frpmg_ctx *ctx, const float *X, int rows, float *Y, fr_str
 fr_status lcc_loss_grad(frpmg_ctx *ctx, const float *X, const float *T, int rows, double *loss, float *grad,
                         fr_stream stream);
 fr_status lcc_features_of(frpmg_ctx *ctx, const double *d1, float *rows_out, float *s_out, fr_stream stream);
+/* One Adam step (Kingma and Ba: beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-
+ * corrected moments) of the FP32 master weights with the device gradient
+ * grad (FP32, layout as the weights) and step size lr; refreshes the BF16
+ * copies.  The moments and the step count continue from the last training
+ * step (lcc_set_weights resets them).  Asynchronous. */
+fr_status lcc_adam_step(frpmg_ctx *ctx, const float *grad, double lr, fr_stream stream);
 
 #ifdef __cplusplus
 }

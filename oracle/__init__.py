@@ -238,9 +238,13 @@ def fd_step(v: np.ndarray, eps: float, mode: int, dq: np.ndarray | None = None) 
     return eps / nv
 
 
-def jvp(level: Level, dq, rq, v, shift, eps=1e-6, mode=EPS_SCALED):
-    """w = shift v - (R(q + h v) - R(q)) / h  (Sec. 2.2, matrix-free product)."""
+def jvp(level: Level, dq, rq, v, shift, eps=1e-6, mode=EPS_SCALED, central=False):
+    """w = shift v - (R(q + h v) - R(q)) / h  (Sec. 2.2, matrix-free product).
+    central=True (not the paper's form): w = shift v - (R(q + h v) -
+    R(q - h v)) / (2 h), second-order accurate in h (rq unused)."""
     h = fd_step(v, eps, mode, dq)
+    if central:
+        return shift * v - (level.residual(dq + h * v) - level.residual(dq - h * v)) / (2.0 * h)
     return shift * v - (level.residual(dq + h * v) - rq) / h
 
 
@@ -361,6 +365,7 @@ class PMGParams:
     scale_mode: int = SCALE_SCALED
     eps_p: float = 1e-6
     coarse: bool = True     # False: fine-level smoothing only (no coarse correction, no post-sweeps)
+    learned: object = None  # mlp.LearnedCoarse: the coarse sweeps replaced by the learned correction
 
 
 class PMG:
@@ -376,6 +381,11 @@ class PMG:
     1/s after: LITERAL s = 1; NORMALIZED s = eps_p sigma_D / ||X||;
     SCALED s = eps_p sigma_D (1 + ||q||) / ||X||, so that Y is a small
     perturbation of the state in the same sense as the FD matvec step.
+
+    With ``prm.learned`` (an ``mlp.LearnedCoarse``) the coarse sweeps are
+    replaced by the learned correction (not in the paper): C1 = B1^{-1} Gamma d
+    from the restricted defect d = -G(Y), the correction C = learned(C1), and
+    Y <- Y + Pi C before the post-sweeps.
 
     fine/coarse: Level objects; fac0/fac1: LU factors of B on each level.
     """
@@ -418,6 +428,12 @@ class PMG:
         # defect and restriction; FAS forcing S1 = F1(Gamma Y) + Gamma d
         d = -self._G(Y, Xs)
         P1 = self.coarse.P
+        if p.learned is not None:
+            C1 = lu_solve(self.fac1, restrict(d, dim, P0, P1))
+            Y = Y + prolong(p.learned.correct(C1), dim, P0, P1)
+            for it in range(p.n0):
+                Y = Y - lu_solve(self.fac0, self._G(Y, Xs))
+            return Y / s
         Z0 = restrict(Y, dim, P0, P1)
         dc = restrict(d, dim, P0, P1)
         S1 = self._G1(Z0, 0.0) + dc
@@ -511,12 +527,13 @@ def esdirk_stage(fine: Level, coarse: Level | None, dq_n, dt, a_ii, a_i1=None, p
 
 
 def row_stage(fine: Level, coarse: Level | None, dq_n, dt, a_ii, precond="pmg", m=30,
-              max_restarts=50, tol=1e-8, eps=1e-6, eps_mode=EPS_SCALED, pmg_kw=None):
+              max_restarts=50, tol=1e-8, eps=1e-6, eps_mode=EPS_SCALED, pmg_kw=None, central=False):
     """First stage of a Rosenbrock-Wanner scheme (Sec. 2.1 Eq.
     (Rosenbrock_General) with i = 1): (I/(a_ii dt) - dR/dq(q^n)) Y = R(q^n),
     solved by FGMRES with the FD matvec to ||R(q^n) - A_h Y|| <= tol ||R(q^n)||.
     The preconditioner is the ROW form of Sec. 3.2 (pseudo-time terms of the
-    outer solver dropped; dtau* = dt)."""
+    outer solver dropped; dtau* = dt).  central=True takes the central FD
+    product (jvp) for the Krylov solve and the recomputed residual."""
     pmg_kw = dict(pmg_kw or {})
     sigma = 1.0 / (a_ii * dt)
     sigma_S = 1.0 / dt + sigma
@@ -525,7 +542,7 @@ def row_stage(fine: Level, coarse: Level | None, dq_n, dt, a_ii, precond="pmg", 
     R0 = fine.residual(dq_n)
     if pm is not None:
         pm.set_point(dq_n, R0)
-    A = lambda v: jvp(fine, dq_n, R0, v, sigma, eps, eps_mode)
+    A = lambda v: jvp(fine, dq_n, R0, v, sigma, eps, eps_mode, central)
     Y, ks = fgmres(A, M, R0, m=m, tol=tol, max_restarts=max_restarts)
     st.gmres_iters = ks.iters
     st.gmres_per_newton.append(ks.iters)

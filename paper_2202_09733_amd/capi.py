@@ -21,6 +21,7 @@ FR_ESINGULAR, FR_ENOCONV, FR_EBREAKDOWN, FR_ENONFINITE = -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGULAR", -5: "ENOCONV",
                 -6: "EBREAKDOWN", -7: "ENONFINITE"}
 EPS_ABSOLUTE, EPS_NORMALIZED, EPS_SCALED = 0, 1, 2
+FD_CENTRAL = 4  # ORed into an EPS_* mode: central difference
 PREC_FP64, PREC_FP32, PREC_FP32_BF16, PREC_BF16_STORE = 0, 1, 2, 3
 COARSE_NONE, COARSE_EJ, COARSE_LEARNED, COARSE_MBNK = 0, 1, 2, 3
 SMOOTHER_EJ, SMOOTHER_MBNK = 0, 1
@@ -34,7 +35,7 @@ EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_resi
            "ej_solve", "ej_get_inverse", "pmg_restrict", "pmg_prolong", "pmg_set_point", "pmg_precond_apply",
            "gmres_solve_stage", "fr_time_step", "fr_step_tableau", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
            "lcc_get_weights", "lcc_set_weights", "lcc_get_scales", "lcc_set_scales", "lcc_forward",
-           "lcc_loss_grad", "lcc_features_of", "mbnk_factor", "mbnk_matvec", "mbnk_ilu_solve", "mbnk_solve",
+           "lcc_loss_grad", "lcc_features_of", "lcc_adam_step", "mbnk_factor", "mbnk_matvec", "mbnk_ilu_solve", "mbnk_solve",
            "mbnk_get_blocks"]
 
 
@@ -180,6 +181,7 @@ def load():
     L.lcc_forward.argtypes = [vp, vp, ctypes.c_int, vp, vp]
     L.lcc_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp, vp]
     L.lcc_features_of.argtypes = [vp, vp, vp, vp, vp]
+    L.lcc_adam_step.argtypes = [vp, vp, dp, vp]
     L.mbnk_factor.argtypes = [vp, ctypes.c_int, vp, dp, vp]
     L.mbnk_matvec.argtypes = [vp, vp, vp, vp]
     L.mbnk_ilu_solve.argtypes = [vp, vp, vp, vp]
@@ -495,6 +497,14 @@ class FR:
             out.append(gh[off:off + r * c].reshape(r, c).copy())
             off += r * c
         return loss.value, out
+
+    def lcc_adam_step(self, grads, lr):
+        """One Adam step of the master weights with the given per-layer gradients."""
+        import torch
+        g = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float32).reshape(-1) for x in grads]))
+        gd = torch.as_tensor(g, device=self.device).contiguous()
+        self._check("lcc_adam_step", self.lib.lcc_adam_step(self.ctx, _fptr(gd), float(lr), _stream()))
+        torch.cuda.synchronize(self.device)
 
     def lcc_features_of(self, d1):
         import torch

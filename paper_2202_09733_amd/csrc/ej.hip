@@ -12,6 +12,7 @@
 // form at any size, use the blocked variant below.  Storing the inverse turns every
 // apply into a batched GEMV that streams the blocks once from HBM with
 // coalesced column reads, with no sequential triangular sweeps.
+#include <cfloat>
 #include <utility>
 
 #include "internal.hpp"
@@ -47,7 +48,7 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
     const int er = tid % RT, eg = tid / RT, ng = nt / RT;
     for (int t = tid; t < nb * nb; t += nt) A[t] = B[base + t];
     __syncthreads();
-    bool singular = false;
+    int flags = 0;
     for (int c = 0; c < nb; ++c) {
         // pivot search in column c, rows c..nb-1
         double best = -1.0;
@@ -68,6 +69,8 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
             double bv = s_v[0];
             int ii = s_i[0];
             for (int w = 1; w < nt / 64; ++w) argmax_combine(bv, ii, s_v[w], s_i[w]);
+            // a column of NaNs compares false everywhere: keep row c
+            if (ii < c || ii >= nb) ii = c;
             s_piv = ii;
             perm[c] = ii;
         }
@@ -83,8 +86,10 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
         __syncthreads();
         double d = A[c * nb + c];
         if (d == 0.0) {
-            singular = true;
+            flags |= kPivZero;
             d = 1.0;
+        } else if (!(fabs(d) <= DBL_MAX)) {
+            flags |= kPivNonfinite;
         }
         const double inv = 1.0 / d;
         for (int r = tid; r < nb; r += nt) colk[r] = A[c * nb + r];
@@ -129,7 +134,7 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
         __syncthreads();
     }
     for (int t = tid; t < nb * nb; t += nt) out[base + t] = (T)A[t];
-    if (singular && tid == 0) status[0] = 1;
+    if (flags && tid == 0) atomicOr(status, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -174,7 +179,7 @@ struct PanelLds {
 
 template <int CC>
 __device__ __forceinline__ void panel_step(double (&x)[kPanel], int &org, PanelLds &sh, int r, int nb, int c0,
-                                           int bw, int nw, int *__restrict__ perm, bool &singular) {
+                                           int bw, int nw, int *__restrict__ perm, int &flags) {
     if (CC >= bw) return;
     const int c = c0 + CC;
     double best = (r >= c && r < nb) ? fabs(x[CC]) : -1.0;
@@ -194,6 +199,7 @@ __device__ __forceinline__ void panel_step(double (&x)[kPanel], int &org, PanelL
         double bv = sh.v[0];
         int ii = sh.i[0];
         for (int w = 1; w < nw; ++w) argmax_combine(bv, ii, sh.v[w], sh.i[w]);
+        if (ii < c || ii >= nb) ii = c;  // a column of NaNs compares false everywhere
         sh.piv = ii;
         perm[(size_t)blockIdx.x * nb + c] = ii;
     }
@@ -218,8 +224,10 @@ __device__ __forceinline__ void panel_step(double (&x)[kPanel], int &org, PanelL
     if (r == c && p != c) org = sh.porg;
     double d = sh.pivrow[CC];
     if (d == 0.0) {
-        singular = true;
+        flags |= kPivZero;
         d = 1.0;
+    } else if (!(fabs(d) <= DBL_MAX)) {
+        flags |= kPivNonfinite;
     }
     const double inv = 1.0 / d;
     if (r == c) {
@@ -238,8 +246,8 @@ __device__ __forceinline__ void panel_step(double (&x)[kPanel], int &org, PanelL
 template <int... CC>
 __device__ __forceinline__ void panel_steps(std::integer_sequence<int, CC...>, double (&x)[kPanel], int &org,
                                             PanelLds &sh, int r, int nb, int c0, int bw, int nw,
-                                            int *__restrict__ perm, bool &singular) {
-    (panel_step<CC>(x, org, sh, r, nb, c0, bw, nw, perm, singular), ...);
+                                            int *__restrict__ perm, int &flags) {
+    (panel_step<CC>(x, org, sh, r, nb, c0, bw, nw, perm, flags), ...);
 }
 
 __global__ void __launch_bounds__(512) k_gj_panel_reg(int nb, int c0, int bw, double *__restrict__ A,
@@ -252,9 +260,9 @@ __global__ void __launch_bounds__(512) k_gj_panel_reg(int nb, int c0, int bw, do
     double x[kPanel];
 #pragma unroll
     for (int j = 0; j < kPanel; ++j) x[j] = (r < nb && j < bw) ? Ak[(size_t)(c0 + j) * nb + r] : 0.0;
-    bool singular = false;
+    int flags = 0;
     int org = r;
-    panel_steps(std::make_integer_sequence<int, kPanel>{}, x, org, sh, r, nb, c0, bw, nw, perm, singular);
+    panel_steps(std::make_integer_sequence<int, kPanel>{}, x, org, sh, r, nb, c0, bw, nw, perm, flags);
     if (r < nb) {
 #pragma unroll
         for (int j = 0; j < kPanel; ++j)
@@ -281,7 +289,7 @@ __global__ void __launch_bounds__(512) k_gj_panel_reg(int nb, int c0, int bw, do
         for (int w2 = 0; w2 < nw; ++w2) n += sh.cnt[w2];
         tl[0] = n;
     }
-    if (singular && r == 0) status[0] = 1;
+    if (flags && r == 0) atomicOr(status, flags);
 }
 
 constexpr int kUpdCols = 64;  // columns per update workgroup

@@ -100,9 +100,9 @@ void residual(frpmg_ctx *ctx, int level, const double *dq, double *r, hipStream_
     HIPCHK(launch_residual(ctx, level, a, s));
 }
 
-// out = sigma v - (R(dq + alpha v) - r0) / alpha - x   (x optional)
+// out = sigma v - (R(dq + alpha v) - r0) / (dscale alpha) - x   (x optional)
 void residual_lin(frpmg_ctx *ctx, int level, const double *dq, const double *v, Scal alpha, const double *r0,
-                  double sigma, const double *x, double *out, hipStream_t s) {
+                  double sigma, const double *x, double *out, hipStream_t s, double dscale = 1.0) {
     ResidualArgs a;
     a.src = SRC_AXPY;
     a.dq = dq;
@@ -113,13 +113,23 @@ void residual_lin(frpmg_ctx *ctx, int level, const double *dq, const double *v, 
     a.r0 = r0;
     a.x = x;
     a.sigma = sigma;
+    a.dscale = dscale;
     HIPCHK(launch_residual(ctx, level, a, s));
 }
 
-// w = shift v - (R(dq + h v) - rq) / h.  dqn2: device ||dq||^2 for the
-// SCALED step (computed here when null).
+bool valid_eps_mode(int mode) {
+    const int step = mode & ~FR_FD_CENTRAL;
+    return step >= FR_EPS_ABSOLUTE && step <= FR_EPS_SCALED;
+}
+
+// One-sided: w = shift v - (R(dq + h v) - rq) / h.  With FR_FD_CENTRAL in
+// mode: w = shift v - (R(dq + h v) - R(dq - h v)) / (2 h) (rq unused; the
+// level's V-cycle G vector holds R(dq - h v)).  dqn2: device ||dq||^2 for
+// the SCALED step (computed here when null).
 void jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const double *v, double shift,
          double eps, int mode, double *w, hipStream_t s, const double *dqn2 = nullptr) {
+    const bool central = (mode & FR_FD_CENTRAL) != 0;
+    mode &= ~FR_FD_CENTRAL;
     Scal h{eps, nullptr};
     const size_t N = ctx->lv[level].N;
     if (mode == FR_EPS_NORMALIZED || mode == FR_EPS_SCALED) {
@@ -134,7 +144,20 @@ void jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, const do
         HIPCHK(vec_dot_fd_step(ctx, N, v, size, eps, ctx->scal + SC_JVP_N2, ctx->scal + SC_JVP_H, s));
         h = Scal{0.0, ctx->scal + SC_JVP_H};
     }
-    residual_lin(ctx, level, dq, v, h, rq, shift, nullptr, w, s);
+    if (!central) {
+        residual_lin(ctx, level, dq, v, h, rq, shift, nullptr, w, s);
+        return;
+    }
+    double *rm = level == 0 ? ctx->wG : ctx->mG[level];
+    ResidualArgs a;
+    a.src = SRC_AXPY;
+    a.dq = dq;
+    a.v = v;
+    a.alpha = Scal{-h.v, h.p, -1.0};
+    a.out = OUT_R;
+    a.r = rm;
+    HIPCHK(launch_residual(ctx, level, a, s));
+    residual_lin(ctx, level, dq, v, h, rm, shift, nullptr, w, s, 2.0);
 }
 
 // The element-local block formation takes the face neighbours as
@@ -189,6 +212,10 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
     HIPCHK(hipMemcpyAsync(ctx->host_pinned, L.dstatus, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     std::memcpy(&flag, ctx->host_pinned, sizeof(int));
+    if (flag & kPivNonfinite) {
+        ctx->err = "non-finite pivot in an element-Jacobi block (NaN or Inf in the blocks)";
+        throw Fail{FR_ENONFINITE};
+    }
     if (flag) {
         ctx->err = "zero pivot in an element-Jacobi block";
         throw Fail{FR_ESINGULAR};
@@ -301,6 +328,10 @@ void mbnk_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma,
     HIPCHK(hipMemcpyAsync(ctx->host_pinned, mb.status, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     std::memcpy(&flag, ctx->host_pinned, sizeof(int));
+    if (flag & kPivNonfinite) {
+        ctx->err = "non-finite pivot in an MBNK block (NaN or Inf in the blocks)";
+        throw Fail{FR_ENONFINITE};
+    }
     if (flag) {
         ctx->err = "zero pivot in an MBNK block";
         throw Fail{FR_ESINGULAR};
@@ -963,6 +994,7 @@ struct StageSolver {
     StageSolver(frpmg_ctx *c, const stage_params &prm) : ctx(c), P(prm) {
         REQUIRE(P.scheme == FR_SCHEME_ESDIRK || P.scheme == FR_SCHEME_ROW, "bad scheme");
         REQUIRE(P.m >= 1 && P.m <= 60, "Krylov dimension must be in 1..60");
+        REQUIRE(valid_eps_mode(P.eps_mode), "bad eps_mode");
         REQUIRE(P.dt > 0 && P.a_ii > 0, "dt and a_ii must be positive");
         REQUIRE(P.precond >= FR_PRECOND_EJ && P.precond <= FR_PRECOND_PMG_LEARNED, "unknown preconditioner");
         pmg = P.precond != FR_PRECOND_EJ;
@@ -1668,7 +1700,7 @@ fr_status fr_jvp(frpmg_ctx *ctx, int level, const double *dq, const double *rq, 
         REQUIRE(dq && rq && v && w, "null pointer");
         REQUIRE(w != dq && w != rq && w != v, "w must not alias the inputs");
         REQUIRE(eps > 0.0, "eps must be positive");
-        REQUIRE(eps_mode >= FR_EPS_ABSOLUTE && eps_mode <= FR_EPS_SCALED, "bad eps_mode");
+        REQUIRE(valid_eps_mode(eps_mode), "bad eps_mode");
         jvp(ctx, level, dq, rq, v, shift, eps, eps_mode, w, S(stream));
     });
 }
@@ -1861,12 +1893,21 @@ fr_status lcc_harvest(frpmg_ctx *ctx, const lcc_harvest_params *prm) {
         if (prm->enable) {
             REQUIRE(prm->max_pairs > 0 && prm->stride >= 1 && prm->target_sweeps >= 1, "bad harvest parameters");
             if (!L.HX || prm->max_pairs != L.cap) {
+                // new capacity: the pairs harvested so far (up to the new capacity) move over
+                float *hx = talloc<float>(ctx, (size_t)prm->max_pairs * L.nin_pad);
+                float *ht = talloc<float>(ctx, (size_t)prm->max_pairs * L.nout_pad);
+                const int keep = L.HX ? std::min(L.count, prm->max_pairs) : 0;
+                HIPCHK(hipDeviceSynchronize());
+                if (keep > 0) {
+                    HIPCHK(hipMemcpy(hx, L.HX, (size_t)keep * L.nin_pad * sizeof(float), hipMemcpyDeviceToDevice));
+                    HIPCHK(hipMemcpy(ht, L.HT, (size_t)keep * L.nout_pad * sizeof(float), hipMemcpyDeviceToDevice));
+                }
                 dfree(L.HX);
                 dfree(L.HT);
-                L.HX = talloc<float>(ctx, (size_t)prm->max_pairs * L.nin_pad);
-                L.HT = talloc<float>(ctx, (size_t)prm->max_pairs * L.nout_pad);
+                L.HX = hx;
+                L.HT = ht;
                 L.cap = prm->max_pairs;
-                L.count = std::min(L.count, L.cap);
+                L.count = keep;
             }
             L.stride = prm->stride;
             L.target_sweeps = prm->target_sweeps;
@@ -1993,6 +2034,24 @@ fr_status lcc_loss_grad(frpmg_ctx *ctx, const float *X, const float *T, int rows
     });
 }
 
+fr_status lcc_adam_step(frpmg_ctx *ctx, const float *grad, double lr, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(grad && lr > 0.0, "bad arguments");
+        lcc_alloc(ctx);
+        Lcc &L = *ctx->lcc;
+        hipStream_t s = S(stream);
+        L.adam_step++;
+        size_t off = 0;
+        for (int l = 0; l < 3; ++l) {
+            const size_t m = (size_t)L.wrows[l] * L.wcols[l];
+            HIPCHK(hipMemcpyAsync(L.G[l], grad + off, m * sizeof(float), hipMemcpyDeviceToDevice, s));
+            HIPCHK(lcc_adam(m, L.W[l], L.G[l], L.Mo[l], L.Vo[l], L.Wb[l], (float)lr, kAdamB1, kAdamB2, kAdamEps,
+                            L.adam_step, s));
+            off += m;
+        }
+    });
+}
+
 fr_status lcc_features_of(frpmg_ctx *ctx, const double *d1, float *rows_out, float *s_out, fr_stream stream) {
     return guarded(ctx, [&] {
         REQUIRE(d1 && rows_out && s_out, "null pointer");
@@ -2025,7 +2084,12 @@ fr_status lcc_train(frpmg_ctx *ctx, const lcc_train_params *prm, lcc_train_stats
         const int nval = std::min(L.count - B, std::max(0, (int)(L.count * prm->holdout)));
         const int ntrain = L.count - nval;
         const int spe = ntrain / B;
-        if (!L.perm) L.perm = talloc<int>(ctx, (size_t)L.cap + B);
+        // batch index lists: at most count <= cap entries are written
+        if (!L.perm || L.perm_cap < (size_t)L.cap) {
+            dfree(L.perm);
+            L.perm = talloc<int>(ctx, (size_t)L.cap);
+            L.perm_cap = (size_t)L.cap;
+        }
         auto val_loss = [&]() {
             const int nb = nval / B;
             if (nb == 0) return 0.0;
@@ -2056,7 +2120,7 @@ fr_status lcc_train(frpmg_ctx *ctx, const lcc_train_params *prm, lcc_train_stats
                 L.adam_step++;
                 for (int l = 0; l < 3; ++l)
                     HIPCHK(lcc_adam((size_t)L.wrows[l] * L.wcols[l], L.W[l], L.G[l], L.Mo[l], L.Vo[l], L.Wb[l],
-                                    (float)prm->lr, 0.9f, 0.999f, 1e-8f, L.adam_step, s));
+                                    (float)prm->lr, kAdamB1, kAdamB2, kAdamEps, L.adam_step, s));
                 out->steps++;
                 if (e == 0 && b == 0) {
                     HIPCHK(hipMemcpyAsync(ctx->host_pinned, L.lval, sizeof(double), hipMemcpyDeviceToHost, s));

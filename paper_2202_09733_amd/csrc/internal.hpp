@@ -83,12 +83,14 @@ __device__ __forceinline__ double fd_step(double qinf_v, double dqv) {
 }
 
 // Scalar that lives either on the host (p == nullptr) or in device memory.
+// a scalar argument: the host value v, or m times the device value *p
 struct Scal {
     double v;
     const double *p;
+    double m = 1.0;
 };
 
-__device__ __forceinline__ double sval(const Scal &s) { return s.p ? *s.p : s.v; }
+__device__ __forceinline__ double sval(const Scal &s) { return s.p ? s.m * *s.p : s.v; }
 
 // How a residual launch forms the state it evaluates R at.
 enum SrcMode { SRC_PLAIN = 0, SRC_AXPY = 1 };
@@ -105,6 +107,7 @@ struct ResidualArgs {
     const double *r0 = nullptr;   // OUT_LIN: R at the base state
     const double *x = nullptr;    // OUT_LIN: optional subtrahend
     double sigma = 0.0;           // OUT_LIN shift
+    double dscale = 1.0;          // OUT_LIN: the difference is divided by dscale alpha
 };
 
 template <typename T>
@@ -130,7 +133,7 @@ struct Level {
     float *inv32 = nullptr;
     __bf16 *inv16 = nullptr;
     int inv_prec = -1;
-    int *dstatus = nullptr;   // device flag: 1 = zero pivot seen
+    int *dstatus = nullptr;   // device pivot flags (kPivZero | kPivNonfinite)
     int *perm = nullptr;      // pivot rows of the blocked inversion [Ne][nb]
     int *touch = nullptr;     // the current panel's touched-row list [Ne][kTouchStride]
     int *colperm = nullptr;   // column placement of the blocked inversion [Ne][nb]
@@ -292,12 +295,15 @@ hipError_t vec_dot_pmg_scale(frpmg_ctx *ctx, size_t n, const double *x, const do
                              double sigma, double *n2out, double *s_out, double *inv_out, hipStream_t s);
 
 // ej.hip
+// pivot flags the inversion kernels OR into their status word
+constexpr int kPivZero = 1;       // an exact zero pivot
+constexpr int kPivNonfinite = 2;  // a NaN or infinite pivot
 // true when the blocks of this size and precision take the blocked inversion
 bool ej_blocked(int nb, int precision);
 hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s);
 // out[i] = in[i]^{-1} for `count` FP64 blocks of nb <= 128 (LDS Gauss-Jordan,
-// partial pivoting, exact column order); *status = 1 on a zero pivot.  in
-// may equal out.
+// partial pivoting, exact column order); the pivot flags are ORed into
+// *status.  in may equal out.
 hipError_t invert_blocks_f64(int count, int nb, const double *in, double *out, int *status, hipStream_t s);
 
 // mbnk.hip

@@ -7,6 +7,9 @@ namespace frpmg {
 
 enum { LCC_EP_F32 = 0, LCC_EP_RELU = 1, LCC_EP_MASK = 2 };
 
+// Adam hyper-parameters (Kingma and Ba's defaults)
+constexpr float kAdamB1 = 0.9f, kAdamB2 = 0.999f, kAdamEps = 1e-8f;
+
 struct Lcc {
     int nin = 0, nin_pad = 0, nh = 256, nout = 0, nout_pad = 0, ngeo = 0;
     int wrows[3] = {0, 0, 0}, wcols[3] = {0, 0, 0};
@@ -35,6 +38,7 @@ struct Lcc {
     __bf16 *bdY = nullptr, *bdYT = nullptr, *bdH2 = nullptr, *bdH2T = nullptr, *bdH1 = nullptr, *bdH1T = nullptr;
     float *bY = nullptr, *bT = nullptr;
     int *perm = nullptr;
+    size_t perm_cap = 0;
     double *lpart = nullptr, *lval = nullptr;
     int adam_step = 0;
 };

@@ -569,6 +569,7 @@ struct OutK {
     const double *x;
     const double *vdir;
     double sigma;
+    double dscale;
 };
 
 template <int DIM, int P, int MODE, int OUT>
@@ -617,7 +618,7 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK sr
         if (OUT == OUT_R) {
             o.r[idx] = R;
         } else {
-            double val = o.sigma * o.vdir[idx] - (R - o.r0[idx]) / alpha;
+            double val = o.sigma * o.vdir[idx] - (R - o.r0[idx]) / (alpha * o.dscale);
             if (o.x) val -= o.x[idx];
             o.r[idx] = val;
         }
@@ -803,7 +804,7 @@ hipError_t run_on(const frpmg_ctx *ctx, const Level &L, const MeshK &m, double *
         hipLaunchKernelGGL((k_faces<DIM, P, MODE, false>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, Jp,
                            Fs, FaceSave{nullptr, nullptr, nullptr, nullptr});
     }
-    OutK o{a.r, a.r0, a.x, a.v, a.sigma};
+    OutK o{a.r, a.r0, a.x, a.v, a.sigma, a.dscale};
     hipLaunchKernelGGL((k_volume<DIM, P, MODE, OUT>), dim3((m.Ne + S::EB - 1) / S::EB), dim3(S::NT), 0, s, m, src,
                        L.ops, ctx->phys, Jp, Fs, o);
     return hipGetLastError();

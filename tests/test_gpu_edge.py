@@ -95,3 +95,79 @@ def test_boundary_rejects_bad_arguments():
     assert ex.value.code == capi.FR_EINVAL
     # the context still works after the refusals
     assert not np.any(fr.mbnk_solve(fr.to_dev(np.zeros(fr.shape(1)))).cpu().numpy())
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_state_is_reported(bad):
+    """A NaN or Inf in the state reaches the EJ factorisation as a non-finite
+    pivot: ej_factor, the stage solve (both schemes) and the time step return
+    FR_ENONFINITE, and the context still solves a finite stage afterwards."""
+    require_gpu()
+    announce("non-finite state (%r)" % bad)
+    wl = W.make_bump_workload(n=(8, 8), p0=2, p1=1, Ma=0.1, dt_factor=10.0, seed=3)
+    fr = capi.FR.from_workload(wl)
+    dq = wl.dq.copy()
+    dq[1, 3, 5] = bad
+    d_bad = fr.to_dev(dq)
+    with pytest.raises(capi.FRError) as ex:
+        fr.ej_factor(0, d_bad, 10.0)
+    assert ex.value.code == capi.FR_ENONFINITE
+    for scheme in (capi.SCHEME_ESDIRK, capi.SCHEME_ROW):
+        with pytest.raises(capi.FRError) as ex:
+            fr.solve_stage(capi.stage_config_for(wl, scheme=scheme), d_bad)
+        assert ex.value.code == capi.FR_ENONFINITE
+    with pytest.raises(capi.FRError) as ex:
+        fr.time_step(capi.stage_config_for(wl), d_bad, tableau=capi.TAB_ROW2)
+    assert ex.value.code == capi.FR_ENONFINITE
+    q, st = fr.solve_stage(capi.stage_config_for(wl), fr.to_dev(wl.dq))
+    assert st["converged"] == 1 and np.all(np.isfinite(q.cpu().numpy()))
+
+
+@pytest.mark.parametrize("p,precision", [(1, capi.PREC_FP64), (2, capi.PREC_FP64), (4, capi.PREC_FP64),
+                                         (4, capi.PREC_BF16_STORE)])
+def test_zero_pivot_is_reported(orc, p, precision):
+    """At rest (u = 0) without viscosity or penalty and with sigma = 0, a
+    density perturbation changes no flux, so every block has an exactly zero
+    column (the oracle's blocks show it and its LU reports the zero pivot):
+    ej_factor returns FR_ESINGULAR, in the LDS (p = 1, 2) and the blocked
+    (p = 4) Gauss-Jordan."""
+    require_gpu()
+    announce("zero pivot p=%d precision %d" % (p, precision))
+    qinf, _ = W.reference_state(2, 0.1, u_dir=(0.0, 0.0, 0.0), speed=0.0)
+    h = [np.full(4, 0.25), np.full(4, 0.25)]
+    L = orc.Level(dim=2, n=(4, 4), h=h, p=p, gamma=1.4, mu=0.0, Pr=0.72, tau=0.0, qinf=qinf)
+    B = L.ej_blocks(np.zeros(L.shape), 0.0)
+    assert np.any(np.all(B[0] == 0.0, axis=0))
+    assert orc.lu_factor(B)[2] != 0
+    fr = capi.FR(2, (4, 4), h, [p], 1.4, 0.0, 0.72, 0.0, qinf)
+    with pytest.raises(capi.FRError) as ex:
+        fr.ej_factor(0, fr.to_dev(np.zeros(L.shape)), 0.0, precision)
+    assert ex.value.code == capi.FR_ESINGULAR
+    # a non-zero shift makes the same blocks regular
+    fr.ej_factor(0, fr.to_dev(np.zeros(L.shape)), 10.0, precision)
+
+
+def test_iteration_caps_are_reported():
+    """One pseudo-time step (ESDIRK), one Krylov iteration without restarts
+    (ROW), one V-cycle (pMG nonlinear solver) and a time step with one
+    pseudo-time step per stage: FR_ENOCONV, with the statistics of the work
+    done."""
+    require_gpu()
+    announce("iteration caps")
+    wl = W.make_bump_workload(n=(8, 8), p0=2, p1=1, Ma=0.1, dt_factor=10.0, seed=3)
+    fr = capi.FR.from_workload(wl)
+    dq = fr.to_dev(wl.dq)
+    _, st = fr.solve_stage(capi.stage_config_for(wl, max_ptc=1), dq, raise_on_noconv=False)
+    assert st["rc"] == capi.FR_ENOCONV and st["converged"] == 0 and st["ptc_iters"] == 1
+    _, st = fr.solve_stage(capi.stage_config_for(wl, scheme=capi.SCHEME_ROW, m=1, max_restarts=0), dq,
+                           raise_on_noconv=False)
+    assert st["rc"] == capi.FR_ENOCONV and st["converged"] == 0 and st["gmres_iters"] == 1
+    _, st = fr.solve_stage(capi.stage_config_for(wl, solver=capi.SOLVER_PMG, max_ptc=1), dq,
+                           raise_on_noconv=False)
+    assert st["rc"] == capi.FR_ENOCONV and st["ptc_iters"] == 1
+    _, st = fr.time_step(capi.stage_config_for(wl, max_ptc=1), dq, tableau=capi.TAB_ESDIRK2,
+                         raise_on_noconv=False)
+    assert st["rc"] == capi.FR_ENOCONV
+    with pytest.raises(capi.FRError) as ex:
+        fr.solve_stage(capi.stage_config_for(wl, max_ptc=1), dq)
+    assert ex.value.code == capi.FR_ENOCONV

@@ -127,13 +127,48 @@ def test_jvp_parity(orc, dim, n, p, Ma):
     r_gpu = fr.residual(0, d_q).cpu().numpy()
     dR = rel(r_gpu, rq)
     sigma = 123.0
-    for eps, mode in [(1e-2, capi.EPS_ABSOLUTE), (1e-6, capi.EPS_NORMALIZED), (1e-6, capi.EPS_SCALED)]:
-        w_ref = orc.jvp(ol, dq, rq, v, sigma, eps=eps, mode=mode)
-        w = fr.jvp(0, d_q, d_rq, d_v, sigma, eps=eps, eps_mode=mode).cpu().numpy()
+    for eps, mode, central in [(1e-2, capi.EPS_ABSOLUTE, False), (1e-6, capi.EPS_NORMALIZED, False),
+                               (1e-6, capi.EPS_SCALED, False), (1e-2, capi.EPS_ABSOLUTE, True),
+                               (1e-6, capi.EPS_SCALED, True)]:
+        w_ref = orc.jvp(ol, dq, rq, v, sigma, eps=eps, mode=mode, central=central)
+        gmode = mode | (capi.FD_CENTRAL if central else 0)
+        w = fr.jvp(0, d_q, d_rq, d_v, sigma, eps=eps, eps_mode=gmode).cpu().numpy()
         h = orc.fd_step(v, eps, mode, dq)
-        dRv = np.linalg.norm(ol.residual(dq + h * v) - rq)
+        # the difference of the two residuals the product divides (norm), and
+        # the rounding of each, amplified by that division
+        dRv = h * np.linalg.norm(sigma * v - w_ref) * (2.0 if central else 1.0)
         bar = max(1e-10, 10 * 2 * max(dR, U) * np.linalg.norm(rq) / dRv)
-        assert rel(w, w_ref) <= bar, (eps, rel(w, w_ref), bar)
+        assert rel(w, w_ref) <= bar, (eps, central, rel(w, w_ref), bar)
+
+
+@pytest.mark.parametrize("which", ["vortical_64x64_p4", "tgv_32cubed_p3"])
+def test_jvp_parity_full_size(orc, which):
+    """The production FD JVP (SCALED step, eps = 1e-6) at full size, 409,600
+    and 10,485,760 unknowns, element by element against the oracle on the
+    same state and direction: normwise bar as in test_jvp_parity, and the
+    largest entry error relative to the largest entry."""
+    require_gpu()
+    announce("jvp full size " + which)
+    wl = getattr(W, which)()
+    fr = capi.FR.from_workload(wl)
+    ol = orc.Level(**wl.level_kwargs(wl.p0))
+    rng = np.random.default_rng(77)
+    v = rng.standard_normal(ol.shape)
+    v /= np.linalg.norm(v)
+    rq = ol.residual(wl.dq)
+    sigma = 1.0 / (wl.a_ii * wl.dt)
+    w_ref = orc.jvp(ol, wl.dq, rq, v, sigma, eps=1e-6, mode=orc.EPS_SCALED)
+    d_q = fr.to_dev(wl.dq)
+    dR = rel(fr.residual(0, d_q).cpu().numpy(), rq)
+    w = fr.jvp(0, d_q, fr.to_dev(rq), fr.to_dev(v), sigma, eps=1e-6, eps_mode=capi.EPS_SCALED).cpu().numpy()
+    h = orc.fd_step(v, 1e-6, orc.EPS_SCALED, wl.dq)
+    dRv = h * np.linalg.norm(sigma * v - w_ref)   # ||R(q + h v) - R(q)||
+    bar = max(1e-10, 10 * 2 * max(dR, U) * np.linalg.norm(rq) / dRv)
+    e = rel(w, w_ref)
+    e_max = np.abs(w - w_ref).max() / np.abs(w_ref).max()
+    print("%s: JVP rel err %.2e (bar %.2e), max entry err %.2e of max |w|; residual rel err %.2e"
+          % (which, e, bar, e_max, dR))
+    assert e <= bar and e_max <= 10 * bar
 
 
 @pytest.mark.parametrize("dim,n,p,sigma", [(2, (4, 4), 2, 50.0), (2, (4, 2), 4, 5e3), (3, (2, 2, 2), 2, 20.0),
@@ -276,30 +311,37 @@ def tgv32_oracle_rhs(orc):
 
 
 @pytest.mark.parametrize("precision", [capi.PREC_FP64, capi.PREC_FP32, capi.PREC_BF16_STORE])
-def test_row_stage_tgv32_full_size(orc, tgv32_oracle_rhs, precision):
+@pytest.mark.parametrize("central", [False, True])
+def test_row_stage_tgv32_full_size(orc, tgv32_oracle_rhs, precision, central):
     """3D 32^3 p=3 first ROW stage with pMG p{3-2} (fine blocks 320 x 320,
     blocked Gauss-Jordan) with the EJ inverses in FP64, FP32, or from the
     BF16-MFMA factorisation stored in BF16.  FGMRES stops on its residual
     estimate (1e-8).  The one-sided FD operator at the paper's eps = 1e-6 is
     itself accurate only to O(h) ~ 1e-7 relative here (per-entry step ~5e-7
-    of O(1) velocities), so the residual of the re-applied FD operator, which
-    the oracle recomputes at the GPU solution, is bounded by 1e-6 and must
-    agree with the GPU's own recomputation."""
+    of O(1) velocities), so the residual of the re-applied one-sided FD
+    operator, which the oracle recomputes at the GPU solution, is bounded by
+    1e-6 and must agree with the GPU's own recomputation.  With the central
+    product (O(h^2)) the recomputed residual meets the stage tolerance itself:
+    1e-8 plus the FD rounding floor u ||R|| / h (a few 1e-10)."""
     require_gpu()
-    announce("row stage TGV 32^3 full size, precision %d" % precision)
+    announce("row stage TGV 32^3 full size, precision %d, central %d" % (precision, central))
     wl, L0, R0 = tgv32_oracle_rhs
     fr = capi.FR.from_workload(wl)
     dq = fr.to_dev(wl.dq)
-    Y, st = fr.solve_stage(capi.stage_config_for(wl, precision=precision), dq)
+    mode = capi.EPS_SCALED | (capi.FD_CENTRAL if central else 0)
+    Y, st = fr.solve_stage(capi.stage_config_for(wl, precision=precision, eps_mode=mode), dq)
     print({k: st[k] for k in ("gmres_iters", "restarts", "rel_res", "true_rel_res", "t_setup", "t_solve")})
     assert st["converged"] == 1 and st["rel_res"] <= 1e-8
     Y = Y.cpu().numpy()
     fr.close()
     sigma = 1.0 / (wl.a_ii * wl.dt)
-    AY = orc.jvp(L0, wl.dq, R0, Y, sigma, eps=1e-6, mode=orc.EPS_SCALED)
+    AY = orc.jvp(L0, wl.dq, R0, Y, sigma, eps=1e-6, mode=orc.EPS_SCALED, central=central)
     true_orc = np.linalg.norm(R0 - AY) / np.linalg.norm(R0)
     print("oracle FD residual at the GPU solution %.3e, GPU %.3e" % (true_orc, st["true_rel_res"]))
-    assert true_orc <= 1e-6
+    if central:
+        assert true_orc <= 1.5e-8 and st["true_rel_res"] <= 1.5e-8
+    else:
+        assert true_orc <= 1e-6
     assert abs(true_orc - st["true_rel_res"]) <= 0.1 * true_orc
 
 

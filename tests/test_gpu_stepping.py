@@ -30,7 +30,13 @@ def _oracle_step(orc, wl, tab, **kw):
 @pytest.mark.parametrize("case", ["bumps8", "vortical8"])
 def test_time_step_parity(orc, tab, case):
     """GPU and oracle full steps agree to the stage solvers' tolerance: the
-    difference is bounded relative to the step's update q^{n+1} - q^n."""
+    difference is bounded relative to the step's update q^{n+1} - q^n.  The
+    ESDIRK stages' Newton iterations overshoot the 1e-10 stage tolerance, so
+    both sides land on the same root to 1e-10 of the update; a ROW stage stops
+    once its Krylov estimate reaches 1e-10, and the two sides' one-sided FD
+    operators (the same definition, different Krylov vectors) leave the FD
+    truncation error, O(1e-7) relative, in each stage's right-hand side
+    consistency, so ROW steps agree to 5e-8."""
     require_gpu()
     announce("time step %s %s" % (tab, case))
     if case == "bumps8":
@@ -49,7 +55,7 @@ def test_time_step_parity(orc, tab, case):
     d = np.linalg.norm(q - q_ref) / upd
     print("%s %s: GPU %d FGMRES (stages %s), oracle %d; |q - q_ref| / |update| = %.2e"
           % (tab, case, st["gmres_iters"], [s["gmres_iters"] for s in st["stages"]], so.gmres_iters, d))
-    assert d <= 1e-6
+    assert d <= (1e-10 if tab.startswith("esdirk") else 5e-8)
 
 
 @pytest.mark.parametrize("tab", ["esdirk3", "row3"])
@@ -142,7 +148,7 @@ def test_time_step_parity_3d(orc, tab):
     d = np.linalg.norm(q - q_ref) / np.linalg.norm(q_ref - wl.dq)
     print("%s tgv2: GPU %d FGMRES, oracle %d; |q - q_ref| / |update| = %.2e"
           % (tab, st["gmres_iters"], so.gmres_iters, d))
-    assert d <= 1e-6
+    assert d <= (1e-10 if tab.startswith("esdirk") else 5e-8)
 
 
 @pytest.mark.parametrize("tab", ["esdirk2", "row2"])
@@ -164,7 +170,7 @@ def test_time_step_parity_ej_preconditioner(orc, tab):
     d = np.linalg.norm(q - q_ref) / np.linalg.norm(q_ref - wl.dq)
     print("%s bumps8 EJ: GPU %d FGMRES, oracle %d; |q - q_ref| / |update| = %.2e"
           % (tab, st["gmres_iters"], so.gmres_iters, d))
-    assert d <= 1e-6
+    assert d <= (1e-10 if tab.startswith("esdirk") else 5e-8)
 
 
 @pytest.mark.parametrize("tab", ["esdirk2", "row2"])
@@ -192,4 +198,4 @@ def test_time_step_mbnk_coarse_smoother(tab):
     d = np.linalg.norm(qm - qe) / np.linalg.norm(qe - wl.dq)
     print("%s bumps8: EJ coarse %d FGMRES, MBNK coarse %d; |difference| / |update| = %.2e"
           % (tab, out[capi.SMOOTHER_EJ][1], out[capi.SMOOTHER_MBNK][1], d))
-    assert d <= 1e-6
+    assert d <= (1e-9 if tab.startswith("esdirk") else 5e-8)

@@ -328,3 +328,49 @@ def test_pmg_beats_ej_on_stiff_case(orc):
     _, s_pm = orc.esdirk_stage(L0, L1, wl.dq, wl.dt, wl.a_ii, precond="pmg", eta=0.1)
     assert s_ej.converged and s_pm.converged
     assert s_pm.gmres_iters * 2 < s_ej.gmres_iters
+
+
+def test_central_jvp_is_second_order(orc, tiny2d):
+    """The central FD product converges to the dense Jacobian at second
+    order in the step (error falls ~100x per decade of eps, against ~10x for
+    the one-sided product), and is odd in the step: the product along -v is
+    minus the product along v, exactly."""
+    L, dq, J = tiny2d
+    rq = L.residual(dq)
+    v = np.random.default_rng(2).standard_normal(L.shape)
+    sigma = 3.7
+    ref = sigma * v.reshape(-1) - J @ v.reshape(-1)
+    err = {}
+    for central in (False, True):
+        err[central] = []
+        for eps in [1e-2, 1e-3]:
+            w = orc.jvp(L, dq, rq, v, sigma, eps=eps, mode=orc.EPS_NORMALIZED, central=central)
+            err[central].append(np.linalg.norm(w.reshape(-1) - ref) / np.linalg.norm(ref))
+    one, cen = err[False], err[True]
+    assert 5 < one[0] / one[1] < 20
+    assert cen[0] / cen[1] > 50
+    assert cen[1] < 1e-2 * one[1]
+    wp = orc.jvp(L, dq, rq, v, 0.0, eps=1e-4, mode=orc.EPS_NORMALIZED, central=True)
+    wm = orc.jvp(L, dq, rq, -v, 0.0, eps=1e-4, mode=orc.EPS_NORMALIZED, central=True)
+    assert np.array_equal(wp, -wm)
+
+
+def test_central_row_stage_meets_its_recomputed_residual(orc):
+    """With the central product the ROW stage's FD operator is linear to
+    O(h^2), so the residual recomputed at the FGMRES solution meets the
+    stage tolerance that the Krylov estimate met, and the solution equals
+    numpy.linalg.solve(sigma I - J, R) closer than the one-sided stage's."""
+    L, dq, _ = _tiny(orc, p=1, amp=0.2)
+    L1 = None
+    dt, g = 0.05, 0.25
+    sigma = 1.0 / (g * dt)
+    R0 = L.residual(dq)
+    J = dense_jacobian(L, dq)
+    Yx = np.linalg.solve(sigma * np.eye(L.N) - J, R0.reshape(-1))
+    out = {}
+    for central in (False, True):
+        Y, st = orc.row_stage(L, L1, dq, dt, g, precond="ej", tol=1e-10, central=central)
+        out[central] = (st.rel_res, np.linalg.norm(Y.reshape(-1) - Yx) / np.linalg.norm(Yx))
+    # rounding of the two residuals over the 2h difference adds ~u/h ~ 1e-10
+    assert out[True][0] <= 3e-10 and out[False][0] > 10 * out[True][0]
+    assert out[True][1] < 0.1 * out[False][1]
