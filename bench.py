@@ -1,12 +1,16 @@
-"""Benchmark: DOF/s of one implicit stage solve to 1e-8 relative nonlinear
-residual on one MI355X, plus the residual/JVP/EJ kernel rates.
+"""Benchmark: DOF/s of one implicit stage solve to 1e-8 relative residual on
+one MI355X, plus the residual/JVP/EJ kernel rates.
 
-Workload (default): 2D Navier-Stokes FR on the 64x64 y-stretched periodic
-mesh (aspect ratio 1-100), p = 4 (409,600 DOF), Ma 1e-3, one ESDIRK3 stage at
-dt = 1000 dt_exp solved by PTC + JFNK + FGMRES(30) with the nonlinear pMG
-p{4-2} preconditioner (n{2-2}, EJ smoothing on both levels), FP64.
-One step = one full stage solve, including the per-time-step preconditioner
-set-up (EJ formation and inversion on both levels) at the start.
+Workload (the headline `value`): 3D Navier-Stokes FR on the periodic 32^3 hex
+mesh, p = 3 (10,485,760 DOF, EJ blocks 320 x 320), Taylor-Green vortex plus
+seeded noise, Ma 0.1, Re 1600; the first ROW stage (gamma 0.25) at
+dt = 100 dt_exp, solved by FGMRES(30) with the nonlinear pMG p{3-2}
+preconditioner (n{2-2}, EJ smoothing on both levels), FP64, until the
+residual of the FD operator recomputed at the solution, ||R - A_h Y||, is at
+most 1e-8 ||R||.  One step = one full stage solve, including the
+per-time-step preconditioner set-up (EJ formation and inversion on both
+levels) at the start.  The 2D 64x64 p = 4 ESDIRK stage and the other
+comparisons are extras of the same JSON line.
 
 Prints ONE JSON line (see the fields in main()).
 """
@@ -26,13 +30,13 @@ HBM_PEAK_GBS = 8000.0
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16s": 3}
 
 
-def measured_traffic():
+def measured_traffic(profile="k_ej_apply_tgv32.md"):
     """HBM bytes per fine-level FP64 k_ej_apply launch from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if the kernel source has
     changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_ej_apply_vortical64.md")
+    path = os.path.join(ROOT, "profiles", profile)
     csrc = os.path.join(ROOT, "paper_2202_09733_amd", "csrc")
     try:
         txt = open(path).read()
@@ -139,41 +143,6 @@ def kernel_rates_3d(reps=20, nsets=4):
         d["frac_hbm"] = d["GBps"] / HBM_PEAK_GBS
     fr.close()
     del sets, base
-    torch.cuda.empty_cache()
-    return out
-
-
-def stage_3d(steps=1):
-    """The first ROW stage of the 3D workload (32^3 hexes, p{3-2}, 10,485,760
-    DOF, fine EJ blocks 320 x 320) with the preconditioner in FP64 and in the
-    BF16-MFMA / BF16-storage form: DOF/s including the set-up, after one
-    warm-up stage each."""
-    import torch
-    from paper_2202_09733_amd import capi
-    from paper_2202_09733_amd import workloads as W
-    wl = W.tgv_32cubed_p3()
-    fr = capi.FR.from_workload(wl)
-    dq = fr.to_dev(wl.dq)
-    out = {}
-    for key, prec in (("fp64", capi.PREC_FP64), ("bf16_storage", capi.PREC_BF16_STORE)):
-        cfg = capi.stage_config_for(wl, precision=prec)
-        Y = fr.empty(0)
-        fr.solve_stage(cfg, dq, out=Y)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            _, st = fr.solve_stage(cfg, dq, out=Y)
-        torch.cuda.synchronize()
-        el = (time.perf_counter() - t0) / steps
-        v_ap = torch.randn_like(dq)
-        t_ap = _events_time(lambda: fr.ej_solve(0, v_ap, out=Y), 5)
-        out[key] = {"dof_per_s": wl.dof() / el, "s_per_stage": el, "t_setup_s": st["t_setup"],
-                    "t_solve_s": st["t_solve"], "gmres_iters": st["gmres_iters"], "rel_res": st["rel_res"],
-                    "true_rel_res": st["true_rel_res"], "fine_ej_apply_ms": t_ap * 1e3}
-    out["bf16_storage"]["speedup_vs_fp64"] = out["bf16_storage"]["dof_per_s"] / out["fp64"]["dof_per_s"]
-    out["workload"] = ("3D NS FR periodic 32^3 p=3 (10,485,760 DOF) TGV, Ma 0.1, Re 1600, first ROW stage "
-                       "gamma 0.25 at dt = 100 dt_exp, FGMRES(30) to 1e-8, pMG p{3-2} n{2-2}, EJ blocks 320^2 / 135^2")
-    fr.close()
     torch.cuda.empty_cache()
     return out
 
@@ -377,49 +346,163 @@ def learned_ab(wl, steps=3):
     return out
 
 
+def learned_3d(n_steps=50, holdout_steps=10, pairs_per_step=2000, n_probe=40):
+    """The learned coarse correction on the 32^3 p = 3 mesh (p{3-2}): pairs
+    harvested by the solver from n_steps Rosenbrock-Euler steps (ROW stages
+    with gamma = 1, each a pMG-preconditioned FGMRES solve) from the seeded
+    Taylor-Green state, about pairs_per_step per stage, plus V-cycles of the
+    same preconditioner on random directions at the first state; the last
+    holdout_steps stages held out; the network trained on the GPU; then the
+    ROW stage of a held-out state (noise seed 40) solved with the learned and
+    with the plain preconditioner (FP64 factors both)."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    wl = W.make_tgv_workload(seed=5)
+    fr = capi.FR.from_workload(wl)
+    t0 = time.perf_counter()
+    cfg_re = capi.stage_config_for(wl, a_ii=1.0, verify=0)
+    q = fr.to_dev(wl.dq)
+    # about pairs_per_step per stage: ~26 V-cycles per stage
+    stride = max(1, wl.Ne * 26 // pairs_per_step)
+    fr.lcc_harvest(enable=1, max_pairs=(n_steps + 1) * pairs_per_step + n_probe * (wl.Ne // stride + 1),
+                   stride=stride, target_sweeps=2, reset=1)
+    rng = np.random.default_rng(17)
+    # random probe directions at the first state (white and smooth)
+    sig_a = 1.0 / (wl.a_ii * wl.dt)
+    sig_s = 1.0 / wl.dt + sig_a
+    fr.ej_factor(0, q, sig_s)
+    fr.ej_factor(1, fr.restrict(0, q), sig_s)
+    fr.pmg_set_point(q, fr.residual(0, q))
+    for i in range(n_probe):
+        x = torch.randn_like(q)
+        if i % 2 == 1:
+            x = fr.prolong(1, fr.restrict(0, x))
+        fr.pmg_apply(x, sig_a)
+    n_probe_pairs = fr.lcc_count()
+    Y = fr.empty(0)
+    iters = []
+    for step in range(n_steps):
+        _, st = fr.solve_stage(cfg_re, q, out=Y)
+        iters.append(st["gmres_iters"])
+        q = q + Y
+    fr.lcc_harvest(enable=0)
+    t_harvest = time.perf_counter() - t0
+    n = fr.lcc_count()
+    holdout = holdout_steps / float(n_steps) * (n - n_probe_pairs) / n
+    ts = fr.lcc_train(epochs=40, batch=256, lr=1e-3, seed=7, holdout=holdout, reinit=1)
+    out = {"pairs": n, "probe_pairs": n_probe_pairs, "stride": stride, "t_harvest_s": t_harvest,
+           "harvest_gmres_per_step": iters, "t_train_s": ts["t_train"],
+           "val_loss_ratio": ts["val_loss"] / ts["val_loss_init"], "holdout_fraction": holdout}
+    wl_eval = W.make_tgv_workload(seed=40)
+    dq = fr.to_dev(wl_eval.dq)
+    for key, cfg in (("plain_pmg", capi.stage_config_for(wl_eval)),
+                     ("learned", capi.stage_config_for(wl_eval, precond=capi.PRECOND_PMG_LEARNED)),
+                     ("learned_no_fallback", capi.stage_config_for(wl_eval, precond=capi.PRECOND_PMG_LEARNED,
+                                                                   stall_ratio=1e9))):
+        fr.solve_stage(cfg, dq, out=Y, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        _, st = fr.solve_stage(cfg, dq, out=Y, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ta
+        out[key] = {"dof_per_s": wl_eval.dof() / el, "s_per_stage": el, "gmres_iters": st["gmres_iters"],
+                    "restarts": st["restarts"], "true_rel_res": st["true_rel_res"], "fallbacks": st["fallbacks"],
+                    "converged": st["converged"]}
+    out["speedup_vs_plain"] = out["learned"]["dof_per_s"] / out["plain_pmg"]["dof_per_s"]
+    out["workload"] = ("32^3 p{3-2} TGV: harvest from Rosenbrock-Euler (gamma = 1) steps at dt = 100 dt_exp from "
+                       "noise seed 5; evaluation: the first ROW stage (gamma 0.25) of noise seed 40")
+    fr.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def fr_prec(fr):
     return getattr(fr, "_last_prec", 0)
 
 
-def cpu_baseline(wl, st, n_sample_iters=3):
+def cpu_baseline(wl, st):
     """The oracle (plain FP64 C + numpy, one thread) on a bounded sample of
-    the same stage: its preconditioner set-up run in full (EJ blocks of both
-    levels by parity-coloured differencing, block LU), then the first
-    n_sample_iters FGMRES iterations of the first pseudo-time step (nonlinear
-    pMG preconditioner + FD JVP + Gram-Schmidt), timed; extrapolated to the
-    GPU stage's PTC and FGMRES iteration counts."""
+    the headline stage (32^3, p = 3): one fine and one coarse residual
+    evaluation at full size, the LU factorisation and solve of 32 blocks of
+    each level's size, and 13 FGMRES iterations of its Gram-Schmidt at full
+    vector length (with a diagonal operator and no preconditioner, so that
+    they time the orthogonalisation alone).  Extrapolated to the whole stage
+    with the oracle's own algorithm (EJ blocks by parity-coloured differencing:
+    2^3 n_b + 1 residual evaluations per level, block LU of every element)
+    and the GPU stage's operation counts; the sample says so."""
     import oracle
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         t_begin = time.perf_counter()
         L0 = oracle.Level(**wl.level_kwargs(wl.p0))
         L1 = oracle.Level(**wl.level_kwargs(wl.p1))
-        dq = wl.dq
-        sigma_A = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
-        sigma_S = 1.0 / wl.dt + sigma_A
+        P0, P1 = wl.p0 + 1, wl.p1 + 1
         t0 = time.perf_counter()
-        M, pm = oracle._setup_precond(L0, L1, dq, "pmg", sigma_A, sigma_A, sigma_S, {})
-        t_setup = time.perf_counter() - t0
+        L0.residual(wl.dq)
+        t_r0 = time.perf_counter() - t0
+        q1 = oracle.restrict(wl.dq, wl.dim, P0, P1)
         t0 = time.perf_counter()
-        rq = L0.residual(dq)
-        b = dq + (wl.a_ii * wl.dt) * rq
-        F = (dq - b) / (wl.a_ii * wl.dt) - rq
-        t_ptc = time.perf_counter() - t0  # one residual + stage function per pseudo-time step
-        pm.set_point(dq, rq)
-        A = lambda v: oracle.jvp(L0, dq, rq, v, sigma_A)
+        L1.residual(q1)
+        t_r1 = time.perf_counter() - t0
+        rng = np.random.default_rng(0)
+        t_lu, t_sv = [], []
+        for L in (L0, L1):
+            B = rng.standard_normal((32, L.nb, L.nb)) + 4.0 * np.sqrt(L.nb) * np.eye(L.nb)
+            t0 = time.perf_counter()
+            fac = oracle.lu_factor(B)
+            t_lu.append((time.perf_counter() - t0) / 32)
+            x = rng.standard_normal((L.nv, L.Np, 32))
+            t0 = time.perf_counter()
+            oracle.lu_solve(fac, x)
+            t_sv.append((time.perf_counter() - t0) / 32)
+        d = rng.uniform(1.0, 2.0, L0.shape)
+        b = rng.standard_normal(L0.shape)
         t0 = time.perf_counter()
-        _, ks = oracle.fgmres(A, M, -F, m=30, tol=1e-30, max_restarts=0, max_iters=n_sample_iters)
-        t_iter = (time.perf_counter() - t0) / max(1, ks.iters)
-    total = t_setup + st["ptc_iters"] * t_ptc + st["gmres_iters"] * t_iter
-    dof = wl.dof()
-    return dict(value=dof / total, unit="DOF/s", cores=1, kind="oracle",
-                sample=("oracle run on the 64x64 vortical stage: preconditioner set-up in full (coloured EJ formation "
-                        "and block LU on both levels, %.1f s) and the first %d preconditioned FGMRES iterations "
-                        "(%.3f s each), one thread; extrapolated to the GPU stage's %d PTC steps and %d FGMRES "
-                        "iterations = %.1f s of oracle time; measuring took %.1f s")
-                % (t_setup, ks.iters, t_iter, st["ptc_iters"], st["gmres_iters"], total,
-                   time.perf_counter() - t_begin),
+        _, ks = oracle.fgmres(lambda v: d * v, lambda v: v, b, m=13, tol=1e-300, max_restarts=0, max_iters=13)
+        t_cgs = time.perf_counter() - t0
+        del d, b
+    c_orth = t_cgs / sum(j + 1 for j in range(ks.iters))   # per (basis vector x iteration)
+    Ne = wl.Ne
+    nb0, nb1 = L0.nb, L1.nb
+    t_setup = ((2 ** wl.dim * nb0 + 1) * t_r0 + (2 ** wl.dim * nb1 + 1) * t_r1
+               + Ne * (t_lu[0] + t_lu[1]))
+    it = st["gmres_iters"]
+    cycles = st["restarts"] + 1
+    per = [it // cycles + (1 if i < it % cycles else 0) for i in range(cycles)]
+    t_orth = c_orth * sum(sum(j + 1 for j in range(n)) for n in per)
+    t_solve = (st["n_R_fine"] * t_r0 + st["n_R_coarse"] * t_r1 + st["n_ej_fine"] * Ne * t_sv[0]
+               + st["n_ej_coarse"] * Ne * t_sv[1] + t_orth)
+    total = t_setup + t_solve
+    return dict(value=wl.dof() / total, unit="DOF/s", cores=1, kind="oracle", extrapolated=True,
+                sample=("oracle, one thread, on the 32^3 p=3 stage's data: fine residual %.2f s, coarse residual "
+                        "%.2f s, LU %.2f / %.2f ms and solve %.3f / %.3f ms per 320^2 / 135^2 block (32 sampled), "
+                        "Gram-Schmidt %.3f s over %d iterations at full length; measuring took %.1f s.  "
+                        "Extrapolated: set-up %.0f s (coloured formation %d + %d residuals, %d block LUs per "
+                        "level), solve %.0f s (the GPU stage's %d fine / %d coarse residuals, %d / %d EJ "
+                        "applies, %d FGMRES iterations) = %.0f s")
+                % (t_r0, t_r1, 1e3 * t_lu[0], 1e3 * t_lu[1], 1e3 * t_sv[0], 1e3 * t_sv[1], t_cgs, ks.iters,
+                   time.perf_counter() - t_begin, t_setup, 2 ** wl.dim * nb0 + 1, 2 ** wl.dim * nb1 + 1, Ne,
+                   t_solve, st["n_R_fine"], st["n_R_coarse"], st["n_ej_fine"], st["n_ej_coarse"], it, total),
                 seconds_extrapolated=total)
+
+
+def cpu_full_stage_2d():
+    """The oracle's complete 64x64 p = 4 ESDIRK stage (set-up and every PTC
+    step, pMG p{4-2}), one thread, timed end to end: nothing extrapolated."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    from paper_2202_09733_amd import workloads as W
+    wl = W.vortical_64x64_p4()
+    with threadpool_limits(limits=1):
+        L0 = oracle.Level(**wl.level_kwargs(wl.p0))
+        L1 = oracle.Level(**wl.level_kwargs(wl.p1))
+        t0 = time.perf_counter()
+        _, so = oracle.esdirk_stage(L0, L1, wl.dq, wl.dt, wl.a_ii)
+        el = time.perf_counter() - t0
+    return dict(value=wl.dof() / el, unit="DOF/s", cores=1, kind="oracle", seconds=el, ptc_iters=so.ptc_iters,
+                gmres_iters=so.gmres_iters, rel_res=so.rel_res, converged=bool(so.converged),
+                sample="the whole 64x64 p=4 ESDIRK3 stage (409,600 DOF), set-up included, one thread")
 
 
 def only_kernel(args):
@@ -480,13 +563,161 @@ def only_kernel(args):
     print("[bench] only-kernel %s x%d done" % (args.only_kernel, args.reps), file=sys.stderr)
 
 
+def _timed_stages(fr, cfg, dq, out, steps, tag):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(steps):
+        _, st = fr.solve_stage(cfg, dq, out=out)
+        stats.append(st)
+        print("[bench] %s step %d: %.3f s (setup %.3f s), %d PTC, %d FGMRES, %d restarts, rel. residual %.2e"
+              % (tag, i, st["t_total"], st["t_setup"], st["ptc_iters"], st["gmres_iters"], st["restarts"],
+                 st["true_rel_res"] if cfg.scheme == 1 else st["rel_res"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, stats
+
+
+def headline(args, prec):
+    """The 32^3 p = 3 ROW stage: warm-up, the timed steps, the roofline
+    kernel (fine FP64 EJ apply) timed live on the library's stream, and (with
+    extras) the precision forms and the central FD product."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    wl = W.tgv_32cubed_p3()
+    fr = capi.FR.from_workload(wl)
+    dq = fr.to_dev(wl.dq)
+    cfg = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=prec)
+    out = fr.empty(0)
+    print("[bench] 32^3 p=3 ROW stage: warmup %d" % args.warmup, file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        fr.solve_stage(cfg, dq, out=out)
+    elapsed, stats = _timed_stages(fr, cfg, dq, out, args.steps, "32^3")
+    dof = wl.dof()
+    st = stats[-1]
+    solve_only = float(np.mean([x["t_solve"] for x in stats]))
+    setup = float(np.mean([x["t_setup"] for x in stats]))
+    res = {
+        "value": dof * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps, "dof": dof,
+        "stage": {"dof_per_s_without_setup": dof / solve_only, "t_setup_s": setup, "t_solve_s": solve_only,
+                  "gmres_iters": st["gmres_iters"], "restarts": st["restarts"], "krylov_rel_res": st["rel_res"],
+                  "true_rel_res": st["true_rel_res"], "n_R_fine": st["n_R_fine"], "n_R_coarse": st["n_R_coarse"],
+                  "n_ej_fine": st["n_ej_fine"], "n_ej_coarse": st["n_ej_coarse"]},
+        "stats": st,
+    }
+    # the dominant kernel: the fine EJ apply with the FP64 inverse of the last stage
+    if prec == capi.PREC_FP64:
+        nb = wl.nv * (wl.p0 + 1) ** wl.dim
+        v = torch.randn_like(dq)
+        y = fr.empty(0)
+        t_ap = _events_time(lambda: fr.ej_solve(0, v, out=y), 10)
+        alg = float(wl.Ne * nb * nb * 8 + wl.Ne * nb * 4 + 16 * dof)
+        res["roofline"] = {
+            "kernel": "k_ej_apply (fine level, 32,768 blocks of 320 x 320, FP64 inverse, column placement)",
+            "bound": "hbm", "achieved": alg / t_ap / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": alg / t_ap / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic(),
+            "alg_bytes_per_launch": alg, "launch_us": t_ap * 1e6}
+    if not args.no_extras:
+        variants = [("central_fd", dict(eps_mode=capi.EPS_SCALED | capi.FD_CENTRAL),
+                     "the same stage with the central FD product (O(h^2); two residuals per product)")]
+        if prec == capi.PREC_FP64:
+            variants += [
+                ("precision_fp32_factors", dict(precision=capi.PREC_FP32),
+                 "EJ inverses stored FP32 on both levels; R, JVP, FGMRES, stage update FP64"),
+                ("precision_bf16_mfma_factors", dict(precision=capi.PREC_FP32_BF16),
+                 "blocked Gauss-Jordan with BF16-MFMA (hi/lo, FP32 accumulate) updates, inverses stored FP32"),
+                ("precision_bf16_storage", dict(precision=capi.PREC_BF16_STORE),
+                 "as precision_bf16_mfma_factors, inverses stored BF16 (FP64 accumulation in the apply)")]
+        for key, kw, note in variants:
+            print("[bench] 32^3 variant " + key, file=sys.stderr, flush=True)
+            cfgv = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=prec)
+            for k, val in kw.items():
+                setattr(cfgv, k, val)
+            fr.solve_stage(cfgv, dq, out=out)
+            el, sts = _timed_stages(fr, cfgv, dq, out, 1, key)
+            stv = sts[-1]
+            vv = dof / el
+            v_ap = torch.randn_like(dq)
+            t_ap = _events_time(lambda: fr.ej_solve(0, v_ap, out=out), 5)
+            res[key] = {"value": vv, "speedup_vs_headline": vv / res["value"], "t_setup_s": stv["t_setup"],
+                        "t_solve_s": stv["t_solve"], "gmres_iters": stv["gmres_iters"], "restarts": stv["restarts"],
+                        "true_rel_res": stv["true_rel_res"], "fine_ej_apply_ms": t_ap * 1e3, "note": note}
+    fr.close()
+    del dq, out
+    torch.cuda.empty_cache()
+    return wl, res
+
+
+def vortical2d_extras(args, prec):
+    """The 64x64 p = 4 ESDIRK stage (the paper's low-Mach, high-aspect-ratio
+    regime): FP64 pMG, the plain-EJ stage, graph replay, the precision forms,
+    and the 2D kernel rates."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    wl = W.vortical_64x64_p4()
+    fr = capi.FR.from_workload(wl)
+    fr._last_prec = prec
+    dq = fr.to_dev(wl.dq)
+    dof = wl.dof()
+    cfg = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=prec)
+    out = fr.empty(0)
+    fr.solve_stage(cfg, dq, out=out)
+    elapsed, stats = _timed_stages(fr, cfg, dq, out, args.steps, "64x64")
+    st = stats[-1]
+    res = {"value": dof * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+           "workload": "2D NS FR 64x64 y-stretched (AR 1-100), p=4 (409,600 DOF), Ma 1e-3, ESDIRK3 stage at "
+                       "dt=1000 dt_exp, PTC+JFNK+FGMRES(30), pMG p{4-2} n{2-2} EJ smoothers, FP64",
+           "t_setup_s": float(np.mean([x["t_setup"] for x in stats])),
+           "t_solve_s": float(np.mean([x["t_solve"] for x in stats])), "ptc_iters": st["ptc_iters"],
+           "gmres_iters": st["gmres_iters"], "gmres_per_newton": st["gmres_per_newton"], "rel_res": st["rel_res"]}
+    print("[bench] 64x64 plain-EJ comparison stage", file=sys.stderr, flush=True)
+    for key, kw in (("plain_ej", dict()), ("plain_ej_eta1e-3_kdim100", dict(eta=1e-3, m=100))):
+        cfg_ej = capi.stage_config_for(wl, precond=capi.PRECOND_EJ, precision=prec, **kw)
+        _, st_ej = fr.solve_stage(cfg_ej, dq, out=fr.empty(0), raise_on_noconv=False)
+        res[key] = {k: st_ej[k] for k in ("ptc_iters", "gmres_iters", "rel_res", "t_total", "t_setup",
+                                          "converged")}
+        res[key]["dof_per_s"] = dof / st_ej["t_total"]
+    print("[bench] 64x64 graph-replay comparison stage", file=sys.stderr, flush=True)
+    cfg_e = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=prec, graphs=1)
+    fr.solve_stage(cfg_e, dq, out=fr.empty(0))
+    el, sts = _timed_stages(fr, cfg_e, dq, out, args.steps, "64x64 graphs")
+    res["graph_replay"] = {"value": dof * args.steps / el, "gmres_iters": sts[-1]["gmres_iters"]}
+    if prec == capi.PREC_FP64:
+        for key, pv in (("precision_fp32_factors", capi.PREC_FP32),
+                        ("precision_bf16_mfma_factors", capi.PREC_FP32_BF16),
+                        ("precision_bf16_storage", capi.PREC_BF16_STORE)):
+            print("[bench] 64x64 preconditioner variant " + key, file=sys.stderr, flush=True)
+            cfgv = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=pv)
+            fr.solve_stage(cfgv, dq, out=out)
+            el, sts = _timed_stages(fr, cfgv, dq, out, args.steps, key)
+            stv = sts[-1]
+            vv = dof * args.steps / el
+            v_ap = torch.randn_like(dq)
+            y_ap = fr.empty(0)
+            t_ap = _events_time(lambda: fr.ej_solve(0, v_ap, out=y_ap), 50)
+            res[key] = {"value": vv, "speedup_vs_fp64": vv / res["value"], "t_setup_s": stv["t_setup"],
+                        "ptc_iters": stv["ptc_iters"], "gmres_iters": stv["gmres_iters"], "rel_res": stv["rel_res"],
+                        "fine_ej_apply_us": t_ap * 1e6}
+    # the FP64 factors again for the kernel rates
+    fr.solve_stage(cfg, dq, out=out)
+    print("[bench] 64x64 kernel rates", file=sys.stderr, flush=True)
+    res["kernels"] = kernel_rates(fr, wl, dq)
+    fr.close()
+    torch.cuda.empty_cache()
+    return wl, res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the EJ-only comparison and kernel rates")
+    ap.add_argument("--cpu-full-stage", action="store_true",
+                    help="also run the oracle's complete 64x64 stage (about a minute of one host core)")
+    ap.add_argument("--no-extras", action="store_true", help="the headline stage and the roofline only")
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
     ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "ej_factor", "residual", "jvp", "stage", "step"],
                     help="profiling driver: set up the workload's state, launch one kernel family --reps times "
@@ -506,138 +737,57 @@ def main():
 
     import torch
     from paper_2202_09733_amd import capi
-    from paper_2202_09733_amd import workloads as W
 
     if args.only_kernel:
         only_kernel(args)
         return
-    wl = W.vortical_64x64_p4()
-    fr = capi.FR.from_workload(wl)
     prec = PRECISIONS[args.precision]
-    fr._last_prec = prec
-    dq = fr.to_dev(wl.dq)
-    cfg = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=prec)
-    out = fr.empty(0)
-    print("[bench] warmup %d stage solve(s)" % args.warmup, file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        _, st = fr.solve_stage(cfg, dq, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for i in range(args.steps):
-        _, st = fr.solve_stage(cfg, dq, out=out)
-        stats.append(st)
-        print("[bench] step %d: %.3f s (setup %.3f s), %d PTC, %d FGMRES, rel. residual %.2e"
-              % (i, st["t_total"], st["t_setup"], st["ptc_iters"], st["gmres_iters"], st["rel_res"]),
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dof = wl.dof()
-    elapsed = t1 - t0
-    st = stats[-1]
-    solve_only = float(np.mean([s["t_solve"] for s in stats]))
-    setup = float(np.mean([s["t_setup"] for s in stats]))
+    wl, head = headline(args, prec)
+    st = head.pop("stats")
     result = {
         "metric": "DOF/s per ESDIRK/ROW stage solve to 1e-8 rel residual",
-        "value": dof * args.steps / elapsed,
+        "value": head.pop("value"),
         "unit": "DOF/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == capi.PREC_FP64 else "f64 (EJ factors %s)" % args.precision,
         "data": "synthetic",
         "config": {
-            "workload": "2D NS FR 64x64 y-stretched (AR 1-100), p=4 (409,600 DOF), Ma 1e-3, ESDIRK3 "
-                        "stage at dt=1000 dt_exp, PTC+JFNK+FGMRES(30), pMG p{4-2} n{2-2} EJ smoothers",
-            "dof": dof, "setup_included": True,
-        },
-        "stage": {
-            "dof_per_s_without_setup": dof / solve_only, "t_setup_s": setup, "t_solve_s": solve_only,
-            "ptc_iters": st["ptc_iters"], "gmres_iters": st["gmres_iters"],
-            "gmres_per_newton": st["gmres_per_newton"], "rel_res": st["rel_res"],
-            "n_R_fine": st["n_R_fine"], "n_R_coarse": st["n_R_coarse"],
-            "n_ej_fine": st["n_ej_fine"], "n_ej_coarse": st["n_ej_coarse"],
+            "workload": "3D NS FR periodic 32^3 hex, p=3 (10,485,760 DOF), Taylor-Green vortex + seeded noise, "
+                        "Ma 0.1, Re 1600; first ROW stage (gamma 0.25) at dt = 100 dt_exp by FGMRES(30) with "
+                        "pMG p{3-2} n{2-2} (EJ smoothers, blocks 320^2 / 135^2, FP64), stopped when the "
+                        "recomputed ||R - A_h Y|| <= 1e-8 ||R|| (one-sided FD product, eps 1e-6)",
+            "dof": head.pop("dof"), "setup_included": True,
         },
     }
+    result.update(head)
     if not args.no_extras:
-        print("[bench] plain-EJ comparison stage", file=sys.stderr, flush=True)
-        cfg_ej = capi.stage_config_for(wl, precond=capi.PRECOND_EJ, precision=prec)
-        _, st_ej = fr.solve_stage(cfg_ej, dq, out=fr.empty(0), raise_on_noconv=False)
-        result["plain_ej"] = {k: st_ej[k] for k in ("ptc_iters", "gmres_iters", "rel_res", "t_total", "t_setup",
-                                                      "converged")}
-        result["plain_ej"]["dof_per_s"] = dof / st_ej["t_total"]
-        # the same stage with each Arnoldi step replayed as a captured HIP graph
-        print("[bench] graph-replay comparison stage", file=sys.stderr, flush=True)
-        cfg_e = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=prec, graphs=1)
-        fr.solve_stage(cfg_e, dq, out=fr.empty(0))
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(args.steps):
-            _, ste = fr.solve_stage(cfg_e, dq, out=fr.empty(0))
-        torch.cuda.synchronize()
-        result["graph_replay"] = {"value": dof * args.steps / (time.perf_counter() - ta),
-                                  "gmres_iters": ste["gmres_iters"],
-                                  "note": "same stage, each Arnoldi step replayed as a captured HIP graph instead "
-                                          "of host-launched kernels"}
-        if prec == capi.PREC_FP64:
-            for key, pv, note in [
-                    ("precision_fp32_factors", capi.PREC_FP32,
-                     "EJ inverses: FP64 Gauss-Jordan, stored FP32 on both levels; R, JVP, FGMRES, stage update FP64"),
-                    ("precision_bf16_mfma_factors", capi.PREC_FP32_BF16,
-                     "EJ inverses: blocked Gauss-Jordan with BF16-MFMA (hi/lo, FP32 accumulate) panel updates, "
-                     "stored FP32; R, JVP, FGMRES, stage update FP64"),
-                    ("precision_bf16_storage", capi.PREC_BF16_STORE,
-                     "EJ inverses: as precision_bf16_mfma_factors, stored BF16 (FP64 accumulation in the apply); "
-                     "R, JVP, FGMRES, stage update FP64")]:
-                print("[bench] preconditioner variant " + key, file=sys.stderr, flush=True)
-                cfgv = capi.stage_config_for(wl, precond=capi.PRECOND_PMG, precision=pv)
-                fr.solve_stage(cfgv, dq, out=fr.empty(0))
-                torch.cuda.synchronize()
-                ta = time.perf_counter()
-                stv = None
-                for _ in range(args.steps):
-                    _, stv = fr.solve_stage(cfgv, dq, out=fr.empty(0))
-                torch.cuda.synchronize()
-                vv = dof * args.steps / (time.perf_counter() - ta)
-                # the fine apply with this variant's stored inverse
-                v_ap = torch.randn_like(dq)
-                y_ap = fr.empty(0)
-                t_ap = _events_time(lambda: fr.ej_solve(0, v_ap, out=y_ap), 50)
-                result[key] = {
-                    "value": vv, "speedup_vs_fp64": vv / result["value"],
-                    "dof_per_s_without_setup": dof / stv["t_solve"], "t_setup_s": stv["t_setup"],
-                    "ptc_iters": stv["ptc_iters"], "gmres_iters": stv["gmres_iters"], "rel_res": stv["rel_res"],
-                    "fine_ej_apply_us": t_ap * 1e6, "note": note}
-        # re-create the pMG factors for the kernel-rate measurements
-        fr.solve_stage(cfg, dq, out=out)
-        print("[bench] kernel rates", file=sys.stderr, flush=True)
-        rates = kernel_rates(fr, wl, dq)
+        print("[bench] 64x64 vortical stage and its variants", file=sys.stderr, flush=True)
+        _, result["vortical2d"] = vortical2d_extras(args, prec)
         print("[bench] kernel rates, 3D workload", file=sys.stderr, flush=True)
-        rates.update(kernel_rates_3d())
-        print("[bench] 3D ROW stage", file=sys.stderr, flush=True)
-        result["stage_3d"] = stage_3d()
-        print("[bench] full time steps, ESDIRK3 and ROW3", file=sys.stderr, flush=True)
+        result["kernels_3d"] = kernel_rates_3d()
+        print("[bench] full time steps", file=sys.stderr, flush=True)
         result["time_step"] = time_steps()
         print("[bench] p-hierarchies and the pMG nonlinear solver", file=sys.stderr, flush=True)
         result["hierarchies"] = hierarchies()
         print("[bench] coarse smoothers", file=sys.stderr, flush=True)
         result["smoothers"] = smoothers()
         print("[bench] learned coarse correction: harvest, train, A/B", file=sys.stderr, flush=True)
-        result["learned_coarse"] = learned_ab(wl)
-        result["kernels"] = rates
-        dom = rates["ej_apply_fine"]
-        result["roofline"] = {
-            "kernel": "k_ej_apply (fine level, n_b=100, FP64 inverse blocks)",
-            "bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(),
-        }
+        from paper_2202_09733_amd import workloads as W
+        result["learned_coarse"] = learned_ab(W.vortical_64x64_p4())
+        print("[bench] learned coarse correction on the 32^3 mesh: harvest, train, A/B", file=sys.stderr, flush=True)
+        result["learned_coarse_3d"] = learned_3d()
     if not args.no_cpu_baseline:
-        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        print("[bench] oracle CPU baseline (bounded sample of the 32^3 stage)", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(wl, st)
+    if args.cpu_full_stage:
+        print("[bench] oracle: the complete 64x64 stage", file=sys.stderr, flush=True)
+        result["cpu_full_stage_vortical2d"] = cpu_full_stage_2d()
     print(json.dumps(result))
 
 

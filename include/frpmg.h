@@ -88,6 +88,7 @@ size_t fr_level_size(const frpmg_ctx *ctx, int level);
  * LDG viscous flux.  dq and r: fr_level_size(level) doubles, must not alias. */
 fr_status fr_residual(frpmg_ctx *ctx, int level, const double *dq, double *r, fr_stream stream);
 
+
 #define FR_EPS_ABSOLUTE 0   /* h = eps */
 #define FR_EPS_NORMALIZED 1 /* h = eps / ||v||_2 (perturbation of norm eps) */
 #define FR_EPS_SCALED 2     /* h = eps (1 + ||dq||_2) / ||v||_2 (Knoll-Keyes scaling) */
@@ -233,7 +234,7 @@ typedef struct {
     double a_i1;       /* ESDIRK: coefficient of R(q^n) in the stage (explicit first stage) */
     double dt;         /* physical time step */
     double dtau;       /* pseudo-time step of the outer PTC (ESDIRK); also dtau* of the smoother */
-    int m;             /* Krylov dimension K_dim */
+    int m;             /* Krylov dimension K_dim, 1 .. 120 */
     int max_restarts;  /* FGMRES restarts per linear solve */
     double eta;        /* ESDIRK: relative tolerance of each inexact Newton solve */
     double tol;        /* stage tolerance: ||F|| <= tol ||F(q^n)|| (ESDIRK), Krylov tol (ROW) */
@@ -263,6 +264,14 @@ typedef struct {
     double mbnk_tol;   /* MBNK relative GMRES tolerance per sweep (0: 1e-1) */
     int smoother_refresh; /* FR_SOLVER_PMG: re-form the smoothers at the current iterate every this many
                              V-cycles (0: formed once at q^n; Sec. 4.2.2 uses 20) */
+    int verify;        /* ROW: 1 = the stage is solved when ||rhs - A_h Y||, recomputed at Y with the FD
+                          operator, meets tol: when the Krylov estimate meets tol, FGMRES continues from the
+                          recomputed residual if it misses, as long as each further cycle at least halves
+                          it; when one does not (the operator's floor: FD truncation and rounding), the
+                          stage ends there, converged on its estimate, with true_rel_res above tol.
+                          0 = the Krylov estimate decides.  The FD operator is linear only to its truncation
+                          and rounding error, so the two can differ (~1e-7 relative at eps = 1e-6 on the 3D
+                          Taylor-Green stage) */
 } stage_params;
 
 #define FR_SMOOTHER_EJ 0

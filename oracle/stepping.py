@@ -324,11 +324,13 @@ def esdirk_step(fine, coarse, dq_n, dt, tab: ESDIRKTableau | None = None, precon
 
 
 def row_step(fine, coarse, dq_n, dt, tab: ROWTableau | None = None, precond="pmg", m=30, max_restarts=50,
-             tol=1e-8, eps=1e-6, eps_mode=EPS_SCALED, pmg_kw=None):
+             tol=1e-8, eps=1e-6, eps_mode=EPS_SCALED, pmg_kw=None, verify=True):
     """One ROW time step (Sec. 2.1 Eq. (Rosenbrock_General), transformed
     form): for each stage i, (I/(gamma dt) - J) Y_i = R(q^n + sum_j a_ij Y_j)
     + (1/dt) sum_j c_ij Y_j with J the FD Jacobian at q^n, solved by FGMRES
-    to tol relative to its right-hand side; q^{n+1} = q^n + sum m_i Y_i.  The
+    to tol relative to its right-hand side (verify=True: the recomputed
+    residual decides; False: the Krylov estimate);
+    q^{n+1} = q^n + sum m_i Y_i.  The
     preconditioner is formed once at q^n and linearised there (Sec. 3.2, ROW
     form: pseudo-time terms dropped, dtau* = dt)."""
     tab = tab or row3_tableau()
@@ -348,7 +350,7 @@ def row_step(fine, coarse, dq_n, dt, tab: ROWTableau | None = None, precond="pmg
         else:
             Ri = fine.residual(dq_n + sum(tab.a[i, j] * U[j] for j in range(i)))
         rhs = Ri + sum(tab.cm[i, j] / dt * U[j] for j in range(i))
-        Y, ks = fgmres(A, M, rhs, m=m, tol=tol, max_restarts=max_restarts)
+        Y, ks = fgmres(A, M, rhs, m=m, tol=tol, max_restarts=max_restarts, verify=verify)
         st = StageStats()
         st.gmres_iters = ks.iters
         st.converged = bool(ks.converged)

@@ -31,7 +31,8 @@ PRECOND_EJ, PRECOND_PMG, PRECOND_PMG_LEARNED = 0, 1, 2
 MAX_LEVELS = 4
 MAX_NEWTON_LOG = 128
 
-EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_residual", "fr_jvp", "ej_factor",
+EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_residual",
+           "fr_jvp", "ej_factor",
            "ej_solve", "ej_get_inverse", "pmg_restrict", "pmg_prolong", "pmg_set_point", "pmg_precond_apply",
            "gmres_solve_stage", "fr_time_step", "fr_step_tableau", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
            "lcc_get_weights", "lcc_set_weights", "lcc_get_scales", "lcc_set_scales", "lcc_forward",
@@ -69,7 +70,8 @@ class StageParams(ctypes.Structure):
                 ("skip_setup", ctypes.c_int), ("stall_window", ctypes.c_int), ("stall_ratio", ctypes.c_double),
                 ("graphs", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int),
                 ("pmg_levels", ctypes.c_int), ("solver", ctypes.c_int), ("coarse_smoother", ctypes.c_int),
-                ("mbnk_maxit", ctypes.c_int), ("mbnk_tol", ctypes.c_double), ("smoother_refresh", ctypes.c_int)]
+                ("mbnk_maxit", ctypes.c_int), ("mbnk_tol", ctypes.c_double), ("smoother_refresh", ctypes.c_int),
+                ("verify", ctypes.c_int)]
 
 SOLVER_JFNK, SOLVER_PMG = 0, 1
 
@@ -265,6 +267,7 @@ class StageConfig:
     mbnk_maxit: int = 0
     mbnk_tol: float = 0.0
     smoother_refresh: int = 0
+    verify: int = 1
 
     def to_c(self):
         return StageParams(**{f[0]: getattr(self, f[0]) for f in StageParams._fields_})

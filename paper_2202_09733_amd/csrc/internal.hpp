@@ -206,7 +206,7 @@ struct frpmg_ctx {
     frpmg::Transfer1D tr[FR_MAX_LEVELS];  // tr[l]: between level l and l + 1
     double *inv2h[3] = {nullptr, nullptr, nullptr};
     std::string err;
-    double *red_partial = nullptr;  // [64][kRedBlocks]
+    double *red_partial = nullptr;  // [128][kRedBlocks]
     double *red_out = nullptr;      // [64]
     double *scal = nullptr;         // device scalars [16]
     double *host_pinned = nullptr;  // pinned host staging [64]

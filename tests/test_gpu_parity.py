@@ -290,17 +290,25 @@ def test_stage_vortical64_full_size(orc):
     assert _oracle_F(orc, wl, q.cpu().numpy()) <= 1.5e-8
 
 
-def test_row_stage_tiny_matches_oracle(orc):
+@pytest.mark.parametrize("tol,verify", [(1e-10, 0), (1e-8, 1)])
+def test_row_stage_tiny_matches_oracle(orc, tol, verify):
+    """A ROW stage stopped on the Krylov estimate at 1e-10 (below the
+    recomputed residual's rounding floor on this mesh), and on the
+    recomputed residual at 1e-8: GPU against the oracle."""
     require_gpu()
-    announce("row stage tiny")
+    announce("row stage tiny, tol %g, verify %d" % (tol, verify))
     wl = W.make_bump_workload(n=(4, 4), p0=2, p1=1, Ma=0.2, dt_factor=10.0, seed=13, scheme="row", amp=5e-2)
     fr = capi.FR.from_workload(wl)
-    Y, st = fr.solve_stage(capi.stage_config_for(wl, tol=1e-10), fr.to_dev(wl.dq))
+    Y, st = fr.solve_stage(capi.stage_config_for(wl, tol=tol, verify=verify), fr.to_dev(wl.dq))
     L0 = orc.Level(**wl.level_kwargs(wl.p0))
     L1 = orc.Level(**wl.level_kwargs(wl.p1))
-    Y_ref, so = orc.row_stage(L0, L1, wl.dq, wl.dt, wl.a_ii, tol=1e-10)
-    assert st["converged"] == 1
-    assert rel(Y.cpu().numpy(), Y_ref) <= 1e-7
+    Y_ref, so = orc.row_stage(L0, L1, wl.dq, wl.dt, wl.a_ii, tol=tol, verify=bool(verify))
+    assert st["converged"] == 1 and so.converged
+    if verify:
+        assert st["true_rel_res"] <= tol
+    e = rel(Y.cpu().numpy(), Y_ref)
+    print("row stage tiny: GPU %d FGMRES, oracle %d; rel. difference %.2e" % (st["gmres_iters"], so.gmres_iters, e))
+    assert e <= (1e-7 if not verify else 1e-6)
 
 
 @pytest.fixture(scope="module")
@@ -315,14 +323,12 @@ def tgv32_oracle_rhs(orc):
 def test_row_stage_tgv32_full_size(orc, tgv32_oracle_rhs, precision, central):
     """3D 32^3 p=3 first ROW stage with pMG p{3-2} (fine blocks 320 x 320,
     blocked Gauss-Jordan) with the EJ inverses in FP64, FP32, or from the
-    BF16-MFMA factorisation stored in BF16.  FGMRES stops on its residual
-    estimate (1e-8).  The one-sided FD operator at the paper's eps = 1e-6 is
-    itself accurate only to O(h) ~ 1e-7 relative here (per-entry step ~5e-7
-    of O(1) velocities), so the residual of the re-applied one-sided FD
-    operator, which the oracle recomputes at the GPU solution, is bounded by
-    1e-6 and must agree with the GPU's own recomputation.  With the central
-    product (O(h^2)) the recomputed residual meets the stage tolerance itself:
-    1e-8 plus the FD rounding floor u ||R|| / h (a few 1e-10)."""
+    BF16-MFMA factorisation stored in BF16, and the one-sided (the paper's)
+    or the central FD product.  The stage is solved when the residual of the
+    FD operator recomputed at the solution, ||R - A_h Y||, meets 1e-8 of ||R||
+    (the FD operator is linear only to its truncation error, ~1e-7 relative
+    here, so the Krylov estimate alone stops early and FGMRES continues from
+    the recomputed residual); the oracle recomputes it at the GPU solution."""
     require_gpu()
     announce("row stage TGV 32^3 full size, precision %d, central %d" % (precision, central))
     wl, L0, R0 = tgv32_oracle_rhs
@@ -331,17 +337,14 @@ def test_row_stage_tgv32_full_size(orc, tgv32_oracle_rhs, precision, central):
     mode = capi.EPS_SCALED | (capi.FD_CENTRAL if central else 0)
     Y, st = fr.solve_stage(capi.stage_config_for(wl, precision=precision, eps_mode=mode), dq)
     print({k: st[k] for k in ("gmres_iters", "restarts", "rel_res", "true_rel_res", "t_setup", "t_solve")})
-    assert st["converged"] == 1 and st["rel_res"] <= 1e-8
+    assert st["converged"] == 1 and st["true_rel_res"] <= 1e-8
     Y = Y.cpu().numpy()
     fr.close()
     sigma = 1.0 / (wl.a_ii * wl.dt)
     AY = orc.jvp(L0, wl.dq, R0, Y, sigma, eps=1e-6, mode=orc.EPS_SCALED, central=central)
     true_orc = np.linalg.norm(R0 - AY) / np.linalg.norm(R0)
     print("oracle FD residual at the GPU solution %.3e, GPU %.3e" % (true_orc, st["true_rel_res"]))
-    if central:
-        assert true_orc <= 1.5e-8 and st["true_rel_res"] <= 1.5e-8
-    else:
-        assert true_orc <= 1e-6
+    assert true_orc <= 1.1e-8
     assert abs(true_orc - st["true_rel_res"]) <= 0.1 * true_orc
 
 

@@ -44,11 +44,13 @@ def test_time_step_parity(orc, tab, case):
     else:
         wl = W.make_vortical_workload(n=(8, 8), dt_factor=100.0)
     fr = capi.FR.from_workload(wl)
-    cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3)
+    # ROW stages stop on the Krylov estimate here: 1e-10 is below the floor
+    # of the recomputed FD residual on these meshes (its rounding, ~1e-9)
+    cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3, verify=0)
     q, st = fr.time_step(cfg, fr.to_dev(wl.dq), tableau=TABS[tab])
     q = q.cpu().numpy()
     assert st["nstages"] == NSTAGES[tab] and all(s["converged"] for s in st["stages"])
-    kw = dict(tol=1e-10) if tab.startswith("row") else dict(tol=1e-10, eta=1e-3)
+    kw = dict(tol=1e-10, verify=False) if tab.startswith("row") else dict(tol=1e-10, eta=1e-3)
     q_ref, so = _oracle_step(orc, wl, tab, **kw)
     assert so.converged
     upd = np.linalg.norm(q_ref - wl.dq)
@@ -138,11 +140,13 @@ def test_time_step_parity_3d(orc, tab):
     announce("time step %s tgv 2x2x2 p3" % tab)
     wl = W.make_tgv_workload(n=(2, 2, 2))
     fr = capi.FR.from_workload(wl)
-    cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3)
+    # ROW stages stop on the Krylov estimate here: 1e-10 is below the floor
+    # of the recomputed FD residual on these meshes (its rounding, ~1e-9)
+    cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3, verify=0)
     q, st = fr.time_step(cfg, fr.to_dev(wl.dq), tableau=TABS[tab])
     q = q.cpu().numpy()
     assert st["nstages"] == NSTAGES[tab] and all(s["converged"] for s in st["stages"])
-    kw = dict(tol=1e-10) if tab.startswith("row") else dict(tol=1e-10, eta=1e-3)
+    kw = dict(tol=1e-10, verify=False) if tab.startswith("row") else dict(tol=1e-10, eta=1e-3)
     q_ref, so = _oracle_step(orc, wl, tab, **kw)
     assert so.converged
     d = np.linalg.norm(q - q_ref) / np.linalg.norm(q_ref - wl.dq)
@@ -160,11 +164,12 @@ def test_time_step_parity_ej_preconditioner(orc, tab):
     announce("time step %s bumps8 EJ preconditioner" % tab)
     wl = W.make_bump_workload(n=(8, 8), p0=2, p1=1, dt_factor=10.0)
     fr = capi.FR.from_workload(wl)
-    cfg = capi.stage_config_for(wl, precond=capi.PRECOND_EJ, tol=1e-10, eta=1e-3)
+    cfg = capi.stage_config_for(wl, precond=capi.PRECOND_EJ, tol=1e-10, eta=1e-3, verify=0)
     q, st = fr.time_step(cfg, fr.to_dev(wl.dq), tableau=TABS[tab])
     q = q.cpu().numpy()
     assert st["nstages"] == NSTAGES[tab] and all(s["converged"] for s in st["stages"])
-    kw = dict(tol=1e-10, precond="ej") if tab.startswith("row") else dict(tol=1e-10, eta=1e-3, precond="ej")
+    kw = (dict(tol=1e-10, precond="ej", verify=False) if tab.startswith("row")
+          else dict(tol=1e-10, eta=1e-3, precond="ej"))
     q_ref, so = _oracle_step(orc, wl, tab, **kw)
     assert so.converged
     d = np.linalg.norm(q - q_ref) / np.linalg.norm(q_ref - wl.dq)
@@ -185,7 +190,7 @@ def test_time_step_mbnk_coarse_smoother(tab):
     dq = fr.to_dev(wl.dq)
     out = {}
     for sm in (capi.SMOOTHER_EJ, capi.SMOOTHER_MBNK):
-        cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3, coarse_smoother=sm)
+        cfg = capi.stage_config_for(wl, tol=1e-10, eta=1e-3, coarse_smoother=sm, verify=0)
         q, st = fr.time_step(cfg, dq, tableau=TABS[tab])
         assert st["nstages"] == NSTAGES[tab] and all(s["converged"] for s in st["stages"]), st
         out[sm] = (q.cpu().numpy(), st["gmres_iters"], st["n_R_coarse"])
@@ -199,3 +204,26 @@ def test_time_step_mbnk_coarse_smoother(tab):
     print("%s bumps8: EJ coarse %d FGMRES, MBNK coarse %d; |difference| / |update| = %.2e"
           % (tab, out[capi.SMOOTHER_EJ][1], out[capi.SMOOTHER_MBNK][1], d))
     assert d <= (1e-9 if tab.startswith("esdirk") else 5e-8)
+
+
+@pytest.mark.parametrize("tab", ["row2", "row3"])
+@pytest.mark.parametrize("case", ["bumps8", "vortical8"])
+def test_time_step_parity_verified_row(orc, tab, case):
+    """ROW steps whose stages stop on the recomputed residual of the FD
+    operator (the stage definition) at 1e-8: every stage of both sides meets
+    it, and the steps agree to the tolerance relative to the update."""
+    require_gpu()
+    announce("time step %s %s, verified stages" % (tab, case))
+    if case == "bumps8":
+        wl = W.make_bump_workload(n=(8, 8), p0=2, p1=1, dt_factor=10.0)
+    else:
+        wl = W.make_vortical_workload(n=(8, 8), dt_factor=100.0)
+    fr = capi.FR.from_workload(wl)
+    q, st = fr.time_step(capi.stage_config_for(wl, tol=1e-8, verify=1), fr.to_dev(wl.dq), tableau=TABS[tab])
+    assert all(s["converged"] for s in st["stages"]) and all(s["true_rel_res"] <= 1e-8 for s in st["stages"])
+    q_ref, so = _oracle_step(orc, wl, tab, tol=1e-8, verify=True)
+    assert so.converged
+    d = np.linalg.norm(q.cpu().numpy() - q_ref) / np.linalg.norm(q_ref - wl.dq)
+    print("%s %s verified: GPU %d FGMRES (stages %s), oracle %d; |q - q_ref| / |update| = %.2e"
+          % (tab, case, st["gmres_iters"], [s["gmres_iters"] for s in st["stages"]], so.gmres_iters, d))
+    assert d <= 5e-8

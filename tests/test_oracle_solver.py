@@ -355,11 +355,12 @@ def test_central_jvp_is_second_order(orc, tiny2d):
     assert np.array_equal(wp, -wm)
 
 
-def test_central_row_stage_meets_its_recomputed_residual(orc):
-    """With the central product the ROW stage's FD operator is linear to
-    O(h^2), so the residual recomputed at the FGMRES solution meets the
-    stage tolerance that the Krylov estimate met, and the solution equals
-    numpy.linalg.solve(sigma I - J, R) closer than the one-sided stage's."""
+def test_row_stage_meets_its_recomputed_residual(orc):
+    """The ROW stage stops on the residual of the FD operator recomputed at
+    its solution (one-sided and central products alike).  The central
+    product is linear to O(h^2), so its stage needs no extra cycle and lands
+    closer to numpy.linalg.solve(sigma I - J, R) than the one-sided stage
+    (whose FD operator is linear only to O(h))."""
     L, dq, _ = _tiny(orc, p=1, amp=0.2)
     L1 = None
     dt, g = 0.05, 0.25
@@ -369,8 +370,43 @@ def test_central_row_stage_meets_its_recomputed_residual(orc):
     Yx = np.linalg.solve(sigma * np.eye(L.N) - J, R0.reshape(-1))
     out = {}
     for central in (False, True):
-        Y, st = orc.row_stage(L, L1, dq, dt, g, precond="ej", tol=1e-10, central=central)
-        out[central] = (st.rel_res, np.linalg.norm(Y.reshape(-1) - Yx) / np.linalg.norm(Yx))
-    # rounding of the two residuals over the 2h difference adds ~u/h ~ 1e-10
-    assert out[True][0] <= 3e-10 and out[False][0] > 10 * out[True][0]
+        Y, st = orc.row_stage(L, L1, dq, dt, g, precond="ej", tol=1e-9, central=central)
+        A = lambda v: orc.jvp(L, dq, R0, v, sigma, eps=1e-6, mode=orc.EPS_SCALED, central=central)
+        true = np.linalg.norm(R0 - A(Y)) / np.linalg.norm(R0)
+        assert st.converged and true <= 1e-9 and abs(true - st.rel_res) <= 1e-3 * true
+        out[central] = (st.gmres_iters, np.linalg.norm(Y.reshape(-1) - Yx) / np.linalg.norm(Yx))
+    assert out[True][0] <= out[False][0]
     assert out[True][1] < 0.1 * out[False][1]
+    # below the rounding floor of the recomputed residual (~1e-10 here) the
+    # stage stops once a further cycle no longer halves it, converged on its
+    # estimate, and reports the floor
+    _, st = orc.row_stage(L, L1, dq, dt, g, precond="ej", tol=1e-11)
+    assert st.converged and 1e-11 < st.rel_res < 1e-9 and st.gmres_iters < 60
+
+
+def test_fgmres_verify_restarts_until_the_true_residual_meets_tol():
+    """An operator that is linear up to a small non-additive part (as a
+    finite-difference product is): the plain estimate-based stop leaves a
+    true residual above the tolerance, verify=True continues from the true
+    residual until it meets the tolerance; with a linear operator verify
+    changes nothing."""
+    import oracle as orc
+    rng = np.random.default_rng(3)
+    n = 60
+    Amat = np.eye(n) * 4 + rng.standard_normal((n, n)) / np.sqrt(n)
+    b = rng.standard_normal(n)
+    C = rng.standard_normal((n, n)) / np.sqrt(n)
+
+    def A_nonlin(v):   # positively homogeneous, non-additive at ~1e-6
+        nv = np.linalg.norm(v)
+        return Amat @ v + (1e-6 * C @ (v * v) / nv if nv > 0 else 0.0)
+    M = lambda v: v / 4.0
+    x0, s0 = orc.fgmres(A_nonlin, M, b, m=40, tol=1e-10)
+    x1, s1 = orc.fgmres(A_nonlin, M, b, m=40, tol=1e-10, verify=True)
+    t0 = np.linalg.norm(b - A_nonlin(x0)) / np.linalg.norm(b)
+    t1 = np.linalg.norm(b - A_nonlin(x1)) / np.linalg.norm(b)
+    assert s0.converged and t0 > 1e-9
+    assert s1.converged and t1 <= 1e-10 and s1.restarts >= 1
+    xl0, _ = orc.fgmres(lambda v: Amat @ v, M, b, m=40, tol=1e-10)
+    xl1, sl1 = orc.fgmres(lambda v: Amat @ v, M, b, m=40, tol=1e-10, verify=True)
+    assert sl1.restarts == 0 and np.array_equal(xl0, xl1)
