@@ -88,6 +88,19 @@ size_t fr_level_size(const frpmg_ctx *ctx, int level);
  * LDG viscous flux.  dq and r: fr_level_size(level) doubles, must not alias. */
 fr_status fr_residual(frpmg_ctx *ctx, int level, const double *dq, double *r, fr_stream stream);
 
+/* fr_residual for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and bitwise the same r, with the face data that the face
+ * kernel hands to the volume kernel (common fluxes and state jumps on every
+ * element's + faces, 2 dim (dim + 2) (p + 1)^(dim - 1) Ne doubles) kept in a
+ * fixed 64 MiB device array that the library holds on each device until the
+ * process ends, instead of the context's buffers.  Allocates nothing.  A
+ * level whose face data exceed 64 MiB (3D p = 3: more than ~17,000
+ * elements) returns FR_EINVAL.  Every call on a device shares that device's
+ * array, whose contents the next call overwrites: calls that overlap on one
+ * device (other streams, host threads or contexts) race, and the caller
+ * must serialise them.  Asynchronous on the stream. */
+fr_status fr_residual_noalloc(frpmg_ctx *ctx, int level, const double *dq, double *r, fr_stream stream);
 
 #define FR_EPS_ABSOLUTE 0   /* h = eps */
 #define FR_EPS_NORMALIZED 1 /* h = eps / ||v||_2 (perturbation of norm eps) */

@@ -31,7 +31,7 @@ PRECOND_EJ, PRECOND_PMG, PRECOND_PMG_LEARNED = 0, 1, 2
 MAX_LEVELS = 4
 MAX_NEWTON_LOG = 128
 
-EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_residual",
+EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_residual", "fr_residual_noalloc",
            "fr_jvp", "ej_factor",
            "ej_solve", "ej_get_inverse", "pmg_restrict", "pmg_prolong", "pmg_set_point", "pmg_precond_apply",
            "gmres_solve_stage", "fr_time_step", "fr_step_tableau", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
@@ -157,6 +157,7 @@ def load():
     L.fr_level_size.argtypes = [vp, ctypes.c_int]
     L.fr_level_size.restype = ctypes.c_size_t
     L.fr_residual.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.fr_residual_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.fr_jvp.argtypes = [vp, ctypes.c_int, vp, vp, vp, dp, dp, ctypes.c_int, vp, vp]
     L.ej_factor.argtypes = [vp, ctypes.c_int, vp, dp, ctypes.c_int, vp]
     L.ej_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -342,6 +343,12 @@ class FR:
     def residual(self, level, dq, out=None):
         out = self.empty(level) if out is None else out
         self._check("fr_residual", self.lib.fr_residual(self.ctx, level, _ptr(dq), _ptr(out), _stream()))
+        return out
+
+    def residual_noalloc(self, level, dq, out=None):
+        out = self.empty(level) if out is None else out
+        self._check("fr_residual_noalloc", self.lib.fr_residual_noalloc(self.ctx, level, _ptr(dq), _ptr(out),
+                                                                        _stream()))
         return out
 
     def jvp(self, level, dq, rq, v, shift, eps=1e-6, eps_mode=EPS_SCALED, out=None):

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <functional>
+#include <mutex>
 #include <random>
 
 #include "internal.hpp"
@@ -55,6 +56,18 @@ fr_status guarded(frpmg_ctx *ctx, F &&f) {
         return FR_ENOMEM;
     }
 }
+
+// Scratch of fr_residual_noalloc, for callers that cannot allocate: the
+// face data that the face kernel hands to the volume kernel (common fluxes
+// and state jumps on each element's + faces).  Every device the library
+// runs on holds its own copy until the process ends.  Host code never passes
+// the symbol itself to a kernel: each device's address is taken once, with
+// that device current, at fr_create.
+constexpr size_t kNoallocBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoallocBytes / sizeof(double)];
+std::mutex g_scratch_mu;
+double *g_scratch_addr[kMaxDevices] = {};
 
 double *dalloc(frpmg_ctx *ctx, size_t n) {
     void *p = nullptr;
@@ -1676,6 +1689,18 @@ fr_status fr_create(const fr_mesh_desc *d, frpmg_ctx **out) {
             ctx->mG[l] = dalloc(ctx, Nl);
             ctx->md[l] = dalloc(ctx, Nl);
         }
+        {
+            int dev = 0;
+            HIPCHK(hipGetDevice(&dev));
+            REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+            std::lock_guard<std::mutex> lock(g_scratch_mu);
+            if (!g_scratch_addr[dev]) {
+                double *ptr = nullptr;
+                HIPCHK(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)));
+                g_scratch_addr[dev] = ptr;
+            }
+            ctx->noalloc_scratch = g_scratch_addr[dev];
+        }
         if (d->nlevels > 1) {
             ctx->q1 = ctx->mq[1];
             ctx->r1 = ctx->mr[1];
@@ -1716,6 +1741,26 @@ fr_status fr_residual(frpmg_ctx *ctx, int level, const double *dq, double *r, fr
         REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
         REQUIRE(dq && r && dq != r, "bad pointers");
         residual(ctx, level, dq, r, S(stream));
+    });
+}
+
+fr_status fr_residual_noalloc(frpmg_ctx *ctx, int level, const double *dq, double *r, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
+        REQUIRE(dq && r && dq != r, "bad pointers");
+        REQUIRE(ctx->noalloc_scratch, "no scratch address for this device");
+        const Level &L = ctx->lv[level];
+        // common fluxes, then state jumps, each [dim][nv][NF][Ne], the second 256-byte aligned
+        const size_t nface = ((size_t)ctx->dim * ctx->nv * L.NF * ctx->mesh.Ne + 31) / 32 * 32;
+        if (2 * nface * sizeof(double) > kNoallocBytes) {
+            char msg[160];
+            std::snprintf(msg, sizeof msg, "fr_residual_noalloc: the level's face data (%zu bytes) exceed the %zu-byte "
+                          "scratch", 2 * nface * sizeof(double), kNoallocBytes);
+            ctx->err = msg;
+            throw Fail{FR_EINVAL};
+        }
+        double *Fs = ctx->noalloc_scratch, *Jp = ctx->noalloc_scratch + nface;
+        HIPCHK(launch_residual_batch(ctx, level, 1, dq, r, Jp, Fs, S(stream)));
     });
 }
 

@@ -210,6 +210,7 @@ struct frpmg_ctx {
     double *red_out = nullptr;      // [64]
     double *scal = nullptr;         // device scalars [16]
     double *host_pinned = nullptr;  // pinned host staging [64]
+    double *noalloc_scratch = nullptr;  // this device's address of fr_residual_noalloc's array
     // preconditioner workspaces (allocated at creation)
     double *pq = nullptr, *prq = nullptr;    // linearisation point (borrowed pointers)
     double *q1 = nullptr, *r1 = nullptr;     // restricted point and R_1 there
