@@ -173,7 +173,10 @@ def test_learned_vcycle_matches_oracle(orc, case):
     print("%s: learned V-cycle vs oracle %.2e (plain V-cycle %.2e); learned vs plain %.3f"
           % (case, e_l, e_p, rel(Y_ref, Y_plain_ref)))
     assert rel(Y_ref, Y_plain_ref) > 1e-3      # the network changes the cycle
-    assert e_l <= 1e-5
+    # the GPU forms the feature rows in FP32 and the oracle in FP64 before
+    # both round them to BF16: an entry near a rounding boundary can round
+    # one BF16 step (2^-8 of itself) apart; measured 1.5e-7 (2D), 8.7e-6 (3D)
+    assert e_l <= 3e-5
 
 
 def test_harvest_capacity_change_keeps_pairs_and_trains(orc):
