@@ -136,6 +136,21 @@ def prolong(x: np.ndarray, dim: int, P0: int, P1: int) -> np.ndarray:
     return np.ascontiguousarray(np.einsum("ij,vjk->vik", Pd, x))
 
 
+def level_restrict(fine, coarse, x: np.ndarray) -> np.ndarray:
+    """Gamma from one level of a p-hierarchy to the next coarser one: the
+    uniform transfer, or element by element on mixed-degree levels."""
+    if hasattr(fine, "restrict_to"):
+        return fine.restrict_to(coarse, x)
+    return restrict(x, fine.dim, fine.P, coarse.P)
+
+
+def level_prolong(fine, coarse, x: np.ndarray) -> np.ndarray:
+    """Pi from a coarse level back to the finer one (see level_restrict)."""
+    if hasattr(fine, "prolong_from"):
+        return fine.prolong_from(coarse, x)
+    return prolong(x, fine.dim, fine.P, coarse.P)
+
+
 # ---------------------------------------------------------------------------
 # One polynomial level of the FR discretisation
 # ---------------------------------------------------------------------------
@@ -416,7 +431,7 @@ class PMG:
         """Linearisation point: the current Newton iterate and R there."""
         self.q, self.rq = dq, rq
         if self.coarse is not None and self.prm.coarse:
-            self.q1 = restrict(dq, self.fine.dim, self.fine.P, self.coarse.P)
+            self.q1 = level_restrict(self.fine, self.coarse, dq)
             self.r1 = self.coarse.residual(self.q1)
 
     def _G(self, Y, X):
@@ -435,7 +450,6 @@ class PMG:
             size = 1.0 + float(np.linalg.norm(self.q)) if p.scale_mode == SCALE_SCALED else 1.0
             s = p.eps_p * p.sigma_D * size / xn if xn > 0 else 1.0
         Xs = s * X
-        dim, P0 = self.fine.dim, self.fine.P
         # pre-smoothing (the first sweep starts from Y = 0 where G = -X)
         Y = np.zeros_like(X)
         for it in range(p.n0):
@@ -445,22 +459,21 @@ class PMG:
             return Y / s
         # defect and restriction; FAS forcing S1 = F1(Gamma Y) + Gamma d
         d = -self._G(Y, Xs)
-        P1 = self.coarse.P
         if p.learned is not None:
-            C1 = lu_solve(self.fac1, restrict(d, dim, P0, P1))
-            Y = Y + prolong(p.learned.correct(C1), dim, P0, P1)
+            C1 = lu_solve(self.fac1, level_restrict(self.fine, self.coarse, d))
+            Y = Y + level_prolong(self.fine, self.coarse, p.learned.correct(C1))
             for it in range(p.n0):
                 Y = Y - lu_solve(self.fac0, self._G(Y, Xs))
             return Y / s
-        Z0 = restrict(Y, dim, P0, P1)
-        dc = restrict(d, dim, P0, P1)
+        Z0 = level_restrict(self.fine, self.coarse, Y)
+        dc = level_restrict(self.fine, self.coarse, d)
         S1 = self._G1(Z0, 0.0) + dc
         Z = Z0.copy()
         for it in range(p.n1):
             Gc = -dc if it == 0 else self._G1(Z, S1)
             Z = Z - lu_solve(self.fac1, Gc)
         # prolongate the coarse change and post-smooth
-        Y = Y + prolong(Z - Z0, dim, P0, P1)
+        Y = Y + level_prolong(self.fine, self.coarse, Z - Z0)
         for it in range(p.n0):
             Y = Y - lu_solve(self.fac0, self._G(Y, Xs))
         return Y / s
@@ -491,7 +504,7 @@ def _setup_precond(fine, coarse, dq_lin, kind, sigma_EJ, sigma_D, sigma_S, pmg_k
     fac1 = None
     use_coarse = pmg_kw.get("coarse", True)
     if coarse is not None and use_coarse:
-        q1 = restrict(dq_lin, fine.dim, fine.P, coarse.P)
+        q1 = level_restrict(fine, coarse, dq_lin)
         fac1 = lu_factor(coarse.ej_blocks(q1, sigma_S))
     pm = PMG(fine, coarse, fac0, fac1, PMGParams(sigma_D=sigma_D, **pmg_kw))
     return pm.apply, pm

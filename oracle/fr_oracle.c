@@ -728,3 +728,333 @@ void or_lu_solve_batch(int nblk, int n, const double *LU, const int32_t *piv,
     }
     free(t);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Mixed polynomial degrees (p-adaptation, Sec. 3.3)                         */
+/* ------------------------------------------------------------------------ */
+
+/* Element k carries degree deg[k] (P_k = deg[k] + 1 points per direction,
+ * P_k <= m->P).  States are stored padded, [nvar][m->P^dim][nelem]: element k
+ * uses local points i < P_k^dim numbered i = i0 + P_k (i1 + P_k i2); the
+ * entries beyond are ignored on input and written as zero.
+ *
+ * The paper leaves the coupling of elements of different degree to its
+ * reference on p-adaptation; this oracle fixes the following reading.  At a
+ * face between the -axis element L and the +axis element R:
+ *   - the common solution is R's trace, as in the uniform scheme; L sees it
+ *     through the L2 projection onto L's face polynomials (exact
+ *     interpolation when P_L >= P_R);
+ *   - the common flux is formed at the Gauss-Legendre points of the larger
+ *     of the two degrees (the mortar), from both traces and L's gradient
+ *     trace carried there by L2 projection (exact for the lower side), and
+ *     is returned to each side's face points by L2 projection (which keeps
+ *     its integral over the face, so the scheme stays conservative).
+ * Every face map is the tensor product over the face directions of the 1D
+ * L2 projection between the two point sets; with equal degrees no map is
+ * applied and every operation is that of or_residual, so a uniform degree
+ * map reproduces or_residual bit for bit. */
+
+/* T[b * Pa + a]: 1D L2 projection from the Pa-point to the Pb-point space. */
+static void proj1d(int Pa, int Pb, double *T)
+{
+    double Pi[OR_MAXP * OR_MAXP];
+    or_transfer1d(Pa, Pb, T, Pi);
+}
+
+/* y[fb] = sum_fa T_face[fb][fa] x[fa] between faces of Pa and Pb points per
+ * direction (dim - 1 directions, first fastest); xs, ys strides. */
+static void face_map(int dim, int Pa, int Pb, const double *T, const double *x, size_t xs,
+                     double *y, size_t ys)
+{
+    int nfa = ipow(Pa, dim - 1), nfb = ipow(Pb, dim - 1);
+    for (int fb = 0; fb < nfb; ++fb) {
+        int b0 = fb % Pb, b1 = fb / Pb;
+        double s = 0.0;
+        for (int fa = 0; fa < nfa; ++fa) {
+            int a0 = fa % Pa, a1 = fa / Pa;
+            double c = T[b0 * Pa + a0];
+            if (dim == 3) c *= T[b1 * Pa + a1];
+            s += c * x[(size_t)fa * xs];
+        }
+        y[(size_t)fb * ys] = s;
+    }
+}
+
+int or_residual_pa(const or_mesh *m, const int *deg, const double *dq, double *r)
+{
+    const int dim = m->dim, nv = dim + 2, PM = m->P;
+    const int Ne = mesh_ne(m), NpM = ipow(PM, dim), NFM = ipow(PM, dim - 1);
+    ops1d o[OR_MAXP + 1];
+    for (int P = 1; P <= PM; ++P) make_ops1d(P, &o[P]);
+    for (int k = 0; k < Ne; ++k)
+        if (deg[k] < 0 || deg[k] + 1 > PM) return -3;
+
+#define PQ(arr, v, i, k) (arr)[((size_t)(v) * NpM + (i)) * Ne + (k)]
+#define PT(arr, a, v, f, k) (arr)[(((size_t)(a) * nv + (v)) * NFM + (f)) * Ne + (k)]
+#define PG(arr, c, v, i, k) (arr)[(((size_t)(c) * nv + (v)) * NpM + (i)) * Ne + (k)]
+#define PGT(arr, a, c, v, f, k) (arr)[((((size_t)(a) * dim + (c)) * nv + (v)) * NFM + (f)) * Ne + (k)]
+
+    size_t ntr = (size_t)dim * nv * NFM * Ne;
+    size_t ngr = (size_t)dim * nv * NpM * Ne;
+    double *Tm = calloc(ntr, sizeof(double)), *Tp = calloc(ntr, sizeof(double));
+    double *Qs = calloc(ntr, sizeof(double));
+    double *G = calloc(ngr, sizeof(double)), *GTp = calloc(ntr * dim, sizeof(double));
+    double *Fl = calloc(ngr, sizeof(double));
+    double *FTm = calloc(ntr, sizeof(double)), *FTp = calloc(ntr, sizeof(double));
+    double *Fsp = calloc(ntr, sizeof(double)), *Fsm = calloc(ntr, sizeof(double));
+    if (!Tm || !Tp || !Qs || !G || !GTp || !Fl || !FTm || !FTp || !Fsp || !Fsm) {
+        free(Tm); free(Tp); free(Qs); free(G); free(GTp); free(Fl); free(FTm); free(FTp); free(Fsp); free(Fsm);
+        return -2;
+    }
+
+    /* (1) own traces at both ends of every line, at the element's own points */
+    for (int k = 0; k < Ne; ++k) {
+        const int P = deg[k] + 1, NF = ipow(P, dim - 1);
+        for (int a = 0; a < dim; ++a)
+            for (int v = 0; v < nv; ++v)
+                for (int f = 0; f < NF; ++f) {
+                    double sm = 0.0, sp = 0.0;
+                    for (int j = 0; j < P; ++j) {
+                        double q = PQ(dq, v, line_point(dim, P, a, f, j), k);
+                        sm += o[P].bm[j] * q;
+                        sp += o[P].bp[j] * q;
+                    }
+                    PT(Tm, a, v, f, k) = sm;
+                    PT(Tp, a, v, f, k) = sp;
+                }
+    }
+
+    /* (2) the common solution on each + face seen from its owner: the + neighbour's
+     * minus trace, L2-projected onto the owner's face points when the degrees differ */
+    for (int k = 0; k < Ne; ++k) {
+        const int P = deg[k] + 1, NF = ipow(P, dim - 1);
+        for (int a = 0; a < dim; ++a) {
+            int kp = neighbour(m, k, a, +1);
+            const int Pn = deg[kp] + 1;
+            double T[OR_MAXP * OR_MAXP];
+            if (Pn != P) proj1d(Pn, P, T);
+            for (int v = 0; v < nv; ++v) {
+                if (Pn == P) {
+                    for (int f = 0; f < NF; ++f) PT(Qs, a, v, f, k) = PT(Tm, a, v, f, kp);
+                } else {
+                    face_map(dim, Pn, P, T, &PT(Tm, a, v, 0, kp), (size_t)Ne, &PT(Qs, a, v, 0, k), (size_t)Ne);
+                }
+            }
+        }
+    }
+
+    /* (3) corrected gradient (correction at the + end only, as in the uniform scheme) */
+    for (int k = 0; k < Ne; ++k) {
+        const int P = deg[k] + 1, Np = ipow(P, dim);
+        int ck[3];
+        elem_coords(m, k, ck);
+        for (int c = 0; c < dim; ++c) {
+            double jac = 2.0 / m->h[c][ck[c]];
+            for (int v = 0; v < nv; ++v)
+                for (int i = 0; i < Np; ++i) {
+                    int f, ic;
+                    point_split(dim, P, c, i, &f, &ic);
+                    double s = 0.0;
+                    for (int j = 0; j < P; ++j)
+                        s += o[P].D[ic][j] * PQ(dq, v, line_point(dim, P, c, f, j), k);
+                    s += (PT(Qs, c, v, f, k) - PT(Tp, c, v, f, k)) * o[P].gRd[ic];
+                    PG(G, c, v, i, k) = jac * s;
+                }
+        }
+    }
+
+    /* (4) traces of every gradient component at the + end of each axis */
+    for (int k = 0; k < Ne; ++k) {
+        const int P = deg[k] + 1, NF = ipow(P, dim - 1);
+        for (int a = 0; a < dim; ++a)
+            for (int c = 0; c < dim; ++c)
+                for (int v = 0; v < nv; ++v)
+                    for (int f = 0; f < NF; ++f) {
+                        double s = 0.0;
+                        for (int j = 0; j < P; ++j)
+                            s += o[P].bp[j] * PG(G, c, v, line_point(dim, P, a, f, j), k);
+                        PGT(GTp, a, c, v, f, k) = s;
+                    }
+    }
+
+    /* (5) pointwise flux deviation and (6) its traces along its own axis */
+    for (int k = 0; k < Ne; ++k) {
+        const int P = deg[k] + 1, Np = ipow(P, dim), NF = ipow(P, dim - 1);
+        for (int i = 0; i < Np; ++i) {
+            double q[5], grad[3][5];
+            state_t s;
+            for (int v = 0; v < nv; ++v) q[v] = PQ(dq, v, i, k);
+            for (int c = 0; c < dim; ++c)
+                for (int v = 0; v < nv; ++v) grad[c][v] = PG(G, c, v, i, k);
+            primitives(dim, m->gamma, m->qinf, q, &s);
+            for (int a = 0; a < dim; ++a) {
+                double FI[5], FV[5];
+                inviscid_dflux(dim, a, m->qinf, &s, FI);
+                viscous_flux(dim, a, m->gamma, m->mu, m->Pr, &s, grad, FV);
+                for (int v = 0; v < nv; ++v) PG(Fl, a, v, i, k) = FI[v] - FV[v];
+            }
+        }
+        for (int a = 0; a < dim; ++a)
+            for (int v = 0; v < nv; ++v)
+                for (int f = 0; f < NF; ++f) {
+                    double sm = 0.0, sp = 0.0;
+                    for (int j = 0; j < P; ++j) {
+                        double fl = PG(Fl, a, v, line_point(dim, P, a, f, j), k);
+                        sm += o[P].bm[j] * fl;
+                        sp += o[P].bp[j] * fl;
+                    }
+                    PT(FTm, a, v, f, k) = sm;
+                    PT(FTp, a, v, f, k) = sp;
+                }
+    }
+
+    /* (7) common flux on every face (the + face of k), at the mortar points
+     * when the degrees differ; Fsp = on k's + face at k's points, Fsm = on the
+     * + neighbour's - face at its points */
+    for (int k = 0; k < Ne; ++k) {
+        const int P = deg[k] + 1, NF = ipow(P, dim - 1);
+        for (int a = 0; a < dim; ++a) {
+            int kp = neighbour(m, k, a, +1);
+            const int Pn = deg[kp] + 1;
+            const int Pm = P > Pn ? P : Pn, NFm = ipow(Pm, dim - 1);
+            double TL[OR_MAXP * OR_MAXP], TR_[OR_MAXP * OR_MAXP], TbL[OR_MAXP * OR_MAXP],
+                TbR[OR_MAXP * OR_MAXP];
+            if (P != Pm) { proj1d(P, Pm, TL); proj1d(Pm, P, TbL); }
+            if (Pn != Pm) { proj1d(Pn, Pm, TR_); proj1d(Pm, Pn, TbR); }
+            /* both traces and the owner's gradient trace at the mortar points */
+            double qLm[5][OR_MAXP * OR_MAXP], qRm[5][OR_MAXP * OR_MAXP], gm[3][5][OR_MAXP * OR_MAXP];
+            double Fm[5][OR_MAXP * OR_MAXP];
+            for (int v = 0; v < nv; ++v) {
+                if (P == Pm) {
+                    for (int f = 0; f < NFm; ++f) qLm[v][f] = PT(Tp, a, v, f, k);
+                    for (int c = 0; c < dim; ++c)
+                        for (int f = 0; f < NFm; ++f) gm[c][v][f] = PGT(GTp, a, c, v, f, k);
+                } else {
+                    face_map(dim, P, Pm, TL, &PT(Tp, a, v, 0, k), (size_t)Ne, qLm[v], 1);
+                    for (int c = 0; c < dim; ++c)
+                        face_map(dim, P, Pm, TL, &PGT(GTp, a, c, v, 0, k), (size_t)Ne, gm[c][v], 1);
+                }
+                if (Pn == Pm) {
+                    for (int f = 0; f < NFm; ++f) qRm[v][f] = PT(Tm, a, v, f, kp);
+                } else {
+                    face_map(dim, Pn, Pm, TR_, &PT(Tm, a, v, 0, kp), (size_t)Ne, qRm[v], 1);
+                }
+            }
+            for (int f = 0; f < NFm; ++f) {
+                double qL[5], qR[5], Fr[5], FV[5], grad[3][5];
+                state_t sL;
+                for (int v = 0; v < nv; ++v) {
+                    qL[v] = qLm[v][f];
+                    qR[v] = qRm[v][f];
+                }
+                for (int c = 0; c < dim; ++c)
+                    for (int v = 0; v < nv; ++v) grad[c][v] = gm[c][v][f];
+                roe_dflux(dim, a, m->gamma, m->qinf, qL, qR, Fr);
+                primitives(dim, m->gamma, m->qinf, qL, &sL);
+                viscous_flux(dim, a, m->gamma, m->mu, m->Pr, &sL, grad, FV);
+                for (int v = 0; v < nv; ++v) Fm[v][f] = Fr[v] - (FV[v] + m->tau * (qR[v] - qL[v]));
+            }
+            for (int v = 0; v < nv; ++v) {
+                if (P == Pm) {
+                    for (int f = 0; f < NF; ++f) PT(Fsp, a, v, f, k) = Fm[v][f];
+                } else {
+                    face_map(dim, Pm, P, TbL, Fm[v], 1, &PT(Fsp, a, v, 0, k), (size_t)Ne);
+                }
+                if (Pn == Pm) {
+                    for (int f = 0; f < ipow(Pn, dim - 1); ++f) PT(Fsm, a, v, f, kp) = Fm[v][f];
+                } else {
+                    face_map(dim, Pm, Pn, TbR, Fm[v], 1, &PT(Fsm, a, v, 0, kp), (size_t)Ne);
+                }
+            }
+        }
+    }
+
+    /* (8) R = -sum_a (2/h_a) [D f_a + (F*_- - f^-) g_L' + (F*_+ - f^+) g_R'] */
+    for (int k = 0; k < Ne; ++k) {
+        const int P = deg[k] + 1, Np = ipow(P, dim);
+        int ck[3];
+        elem_coords(m, k, ck);
+        for (int v = 0; v < nv; ++v) {
+            for (int i = 0; i < Np; ++i) {
+                double acc = 0.0;
+                for (int a = 0; a < dim; ++a) {
+                    int f, ia;
+                    point_split(dim, P, a, i, &f, &ia);
+                    double s = 0.0;
+                    for (int j = 0; j < P; ++j)
+                        s += o[P].D[ia][j] * PG(Fl, a, v, line_point(dim, P, a, f, j), k);
+                    s += (PT(Fsm, a, v, f, k) - PT(FTm, a, v, f, k)) * o[P].gLd[ia];
+                    s += (PT(Fsp, a, v, f, k) - PT(FTp, a, v, f, k)) * o[P].gRd[ia];
+                    acc += (2.0 / m->h[a][ck[a]]) * s;
+                }
+                PQ(r, v, i, k) = -acc;
+            }
+            for (int i = Np; i < NpM; ++i) PQ(r, v, i, k) = 0.0;
+        }
+    }
+#undef PQ
+#undef PT
+#undef PG
+#undef PGT
+    free(Tm); free(Tp); free(Qs); free(G); free(GTp); free(Fl); free(FTm); free(FTp); free(Fsp); free(Fsm);
+    return 0;
+}
+
+/* EJ blocks on a mixed-degree mesh, as or_ej_blocks (same colouring, step
+ * and one-sided difference) with or_residual_pa.  Blocks are n_b = nvar
+ * m->P^dim square in the padded numbering v m->P^dim + i; the rows and
+ * columns of element k's unused points hold the identity. */
+int or_ej_blocks_pa(const or_mesh *m, const int *deg, const double *dq, const double *r0, double sigma, double *B)
+{
+    const int dim = m->dim, nv = dim + 2;
+    const int Ne = mesh_ne(m), Np = ipow(m->P, dim), nb = nv * Np;
+    for (int a = 0; a < dim; ++a)
+        if (m->n[a] % 2 != 0) return -1;
+    size_t N = (size_t)nv * Np * Ne;
+    double *qp = malloc(sizeof(double) * N);
+    double *rp = malloc(sizeof(double) * N);
+    double *hk = malloc(sizeof(double) * Ne);
+    int *col = malloc(sizeof(int) * Ne);
+    if (!qp || !rp || !hk || !col) { free(qp); free(rp); free(hk); free(col); return -2; }
+    for (int k = 0; k < Ne; ++k) {
+        int c[3];
+        elem_coords(m, k, c);
+        col[k] = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
+    }
+    for (int k = 0; k < Ne; ++k) {
+        double *Bk = B + (size_t)k * nb * nb;
+        memset(Bk, 0, sizeof(double) * nb * nb);
+        for (int j = 0; j < nb; ++j) Bk[(size_t)j * nb + j] = 1.0;
+    }
+    int ncol = 1 << dim;
+    for (int colour = 0; colour < ncol; ++colour)
+        for (int j = 0; j < nb; ++j) {
+            int jv = j / Np, ji = j % Np;
+            int any = 0;
+            memcpy(qp, dq, sizeof(double) * N);
+            for (int k = 0; k < Ne; ++k) {
+                hk[k] = 0.0;
+                if (col[k] != colour || ji >= ipow(deg[k] + 1, dim)) continue;
+                size_t idx = ((size_t)jv * Np + ji) * Ne + k;
+                double hj = 1e-7 * fmax(1.0, fabs(m->qinf[jv] + dq[idx]));
+                qp[idx] = dq[idx] + hj;
+                hk[k] = qp[idx] - dq[idx];
+                any = 1;
+            }
+            if (!any) continue;
+            int rc = or_residual_pa(m, deg, qp, rp);
+            if (rc) { free(qp); free(rp); free(hk); free(col); return rc; }
+            for (int k = 0; k < Ne; ++k) {
+                if (hk[k] == 0.0) continue;
+                const int Npk = ipow(deg[k] + 1, dim);
+                double *Bk = B + (size_t)k * nb * nb;
+                for (int row = 0; row < nb; ++row) {
+                    if (row % Np >= Npk) continue;
+                    size_t idx = (size_t)row * Ne + k;
+                    Bk[(size_t)row * nb + j] = (row == j ? sigma : 0.0) - (rp[idx] - r0[idx]) / hk[k];
+                }
+            }
+        }
+    free(qp); free(rp); free(hk); free(col);
+    return 0;
+}

@@ -29,7 +29,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import (EPS_SCALED, SCALE_LITERAL, SCALE_NORMALIZED, SCALE_SCALED, StageStats, fgmres, jvp, lu_factor,
-               lu_solve, prolong, restrict)
+               level_prolong, level_restrict, lu_solve)
 from . import mbnk as MB
 
 
@@ -61,7 +61,7 @@ class MultiPMG:
         self.r = [rq]
         for l in range(1, len(self.levels)):
             a, b = self.levels[l - 1], self.levels[l]
-            ql = restrict(self.q[-1], a.dim, a.P, b.P)
+            ql = level_restrict(a, b, self.q[-1])
             self.q.append(ql)
             self.r.append(b.residual(ql))
 
@@ -80,11 +80,11 @@ class MultiPMG:
             return Y
         a, b = self.levels[l], self.levels[l + 1]
         d = -self._G(l, Y, S)
-        Z0 = restrict(Y, a.dim, a.P, b.P)
-        dc = restrict(d, a.dim, a.P, b.P)
+        Z0 = level_restrict(a, b, Y)
+        dc = level_restrict(a, b, d)
         S1 = self._G(l + 1, Z0, 0.0) + dc
         Z = self._cycle(l + 1, S1, Z0, -dc)
-        Y = Y + prolong(Z - Z0, a.dim, a.P, b.P)
+        Y = Y + level_prolong(a, b, Z - Z0)
         for it in range(n):
             Y = Y - lu_solve(self.facs[l], self._G(l, Y, S))
         return Y
@@ -108,7 +108,7 @@ def hierarchy_factors(levels, dq_n, sigma_S):
     for l, L in enumerate(levels):
         if l > 0:
             a = levels[l - 1]
-            q = restrict(q, a.dim, a.P, L.P)
+            q = level_restrict(a, L, q)
         facs.append(lu_factor(L.ej_blocks(q, sigma_S)))
     return facs
 
@@ -127,7 +127,7 @@ def coarse_mbnk(levels, dq_n, sigma_S):
     q = dq_n
     for l in range(1, len(levels)):
         a, b = levels[l - 1], levels[l]
-        q = restrict(q, a.dim, a.P, b.P)
+        q = level_restrict(a, b, q)
     return MB.ilu0(MB.assemble(levels[-1], q, sigma_S))
 
 

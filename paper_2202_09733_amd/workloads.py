@@ -274,3 +274,97 @@ def random_state(level_shape, rng, qinf, amp=1e-2):
     vel = [uinf[b] + amp * rng.uniform(-1, 1, (Np, Ne)) for b in range(dim)]
     p = pinf * (1.0 + amp * rng.uniform(-1, 1, (Np, Ne)))
     return deviation_from_primitives(qinf, pinf, rho, vel, p)
+
+
+# ---------------------------------------------------------------------------
+# mixed polynomial degrees (p-adaptive meshes)
+# ---------------------------------------------------------------------------
+
+def degree_rings(n, p_max, p_min=1, centre=(0.5, 0.5, 0.5), ring=0.125):
+    """A synthetic p-adaptive degree map on the unit box: p_max on elements
+    whose centre lies within `ring` of `centre` (periodic distance), one degree
+    less per further `ring` of distance, down to p_min -- the high degrees
+    sit on a localised feature, as the smoothness indicator puts them."""
+    dim = len(n)
+    Ne = int(np.prod(n))
+    e = np.arange(Ne)
+    ec = [e % n[0], (e // n[0]) % n[1]] + ([e // (n[0] * n[1])] if dim == 3 else [])
+    d2 = np.zeros(Ne)
+    for a in range(dim):
+        x = (ec[a] + 0.5) / n[a]
+        dx = np.abs(x - centre[a])
+        dx = np.minimum(dx, 1.0 - dx)
+        d2 += dx * dx
+    deg = p_max - np.floor(np.sqrt(d2) / ring).astype(np.int64)
+    return np.clip(deg, p_min, p_max).astype(np.int32)
+
+
+def random_state_pa(deg, dim, rng, qinf, amp=1e-2):
+    """random_state on a mixed-degree mesh, padded [nvar][P_max^dim][nelem]:
+    element k's first (deg[k] + 1)^dim points hold values, the rest zero."""
+    deg = np.asarray(deg)
+    Pm = int(deg.max()) + 1
+    full = random_state((dim + 2, Pm ** dim, deg.shape[0]), rng, qinf, amp)
+    npts = (deg.astype(np.int64) + 1) ** dim
+    mask = np.arange(Pm ** dim)[:, None] < npts[None, :]
+    return np.ascontiguousarray(full * mask[None])
+
+
+def sample_pa(deg, n, h, dim, fn):
+    """Evaluate fn(coords) -> [nvar][npts] arrays at every element's own
+    Gauss-Legendre points, padded to the largest degree."""
+    deg = np.asarray(deg)
+    Pm = int(deg.max()) + 1
+    out = None
+    for p in np.unique(deg):
+        X = point_coords(n, h, int(p), dim)
+        vals = fn(X)
+        if out is None:
+            out = np.zeros((vals.shape[0], Pm ** dim, deg.shape[0]))
+        sel = deg == p
+        out[:, :(int(p) + 1) ** dim, sel] = vals[:, :, sel]
+    return np.ascontiguousarray(out)
+
+
+def make_padapt_workload(n=(32, 32), p_max=4, Ma=0.1, Re=1000.0, seed=6, dt_factor=100.0, amp=5e-2,
+                         kmax=4, ring=0.125, name="p-adaptive vortical"):
+    """2D periodic unit square with the vortical perturbation of
+    ``make_vortical_workload`` (uniform elements, |u'| <= amp) and the
+    degree map ``degree_rings`` (p_max at the centre down to 1); each element
+    holds the field at its own points.  First ROW stage."""
+    dim = 2
+    h = [np.full(n[a], 1.0 / n[a]) for a in range(dim)]
+    rng = np.random.default_rng(seed)
+    qinf, pinf = reference_state(dim, Ma)
+    modes = []
+    for kx in range(-kmax, kmax + 1):
+        for ky in range(-kmax, kmax + 1):
+            if kx == 0 and ky == 0:
+                continue
+            modes.append((kx, ky, rng.normal() / (kx * kx + ky * ky), rng.uniform(0.0, 2.0 * math.pi)))
+
+    def vel(X, Y):
+        up = np.zeros_like(X)
+        vp = np.zeros_like(X)
+        for kx, ky, A, phi in modes:
+            s = -A * np.sin(2.0 * math.pi * (kx * X + ky * Y) + phi)
+            up += s * (2.0 * math.pi * ky)
+            vp -= s * (2.0 * math.pi * kx)
+        return up, vp
+
+    Xf, Yf = point_coords(n, h, p_max, dim)
+    u0, v0 = vel(Xf, Yf)
+    scale = amp / float(np.max(np.sqrt(u0 * u0 + v0 * v0)))
+    deg = degree_rings(n, p_max, ring=ring)
+
+    def field(X):
+        up, vp = vel(X[0], X[1])
+        rho = np.ones_like(X[0])
+        return deviation_from_primitives(qinf, pinf, rho, [1.0 + scale * up, scale * vp], np.full_like(X[0], pinf))
+
+    dq = sample_pa(deg, n, h, dim, field)
+    c = math.sqrt(GAMMA * pinf)
+    dt_exp = float(h[0][0]) / ((1.0 + amp + c) * (2 * p_max + 1))
+    return Workload(name=name, dim=dim, n=tuple(n), h=h, p0=p_max, p1=max(p_max - 2, 0), gamma=GAMMA,
+                    mu=1.0 / Re, Pr=PRANDTL, tau=LDG_TAU, qinf=qinf, dq=dq, dt=dt_factor * dt_exp,
+                    a_ii=ROW_GAMMA, scheme="row", Ma=Ma, Re=Re, seed=seed, extra=dict(dt_exp=dt_exp, deg=deg))
