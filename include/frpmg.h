@@ -313,6 +313,9 @@ typedef struct {
     long n_R_fine, n_R_coarse, n_ej_fine, n_ej_coarse;
     int fallbacks;
     int gmres_per_newton[FR_MAX_NEWTON_LOG];
+    double t_precond, t_jvp, t_ortho; /* seconds of the Arnoldi steps' preconditioner, FD product and
+                                         orthogonalisation (HIP events on the stream, summed over the
+                                         stage; 0 when the steps replay captured graphs) */
 } stage_stats;
 
 /* One implicit stage (synchronous).

@@ -99,7 +99,8 @@ class StageStats(ctypes.Structure):
                 ("t_total", ctypes.c_double), ("t_setup", ctypes.c_double), ("t_solve", ctypes.c_double),
                 ("n_R_fine", ctypes.c_long), ("n_R_coarse", ctypes.c_long),
                 ("n_ej_fine", ctypes.c_long), ("n_ej_coarse", ctypes.c_long),
-                ("fallbacks", ctypes.c_int), ("gmres_per_newton", ctypes.c_int * MAX_NEWTON_LOG)]
+                ("fallbacks", ctypes.c_int), ("gmres_per_newton", ctypes.c_int * MAX_NEWTON_LOG),
+                ("t_precond", ctypes.c_double), ("t_jvp", ctypes.c_double), ("t_ortho", ctypes.c_double)]
 
     def as_dict(self):
         d = {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "gmres_per_newton"}

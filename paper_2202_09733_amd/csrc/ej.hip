@@ -151,77 +151,92 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
 // ---------------------------------------------------------------------------
 constexpr int kPanel = 32;
 
-// Panel factorisation with the panel in registers: lane r owns row r of the
-// panel (kPanel values).  Per pivot step: the argmax of |column| over rows
-// >= c (wavefront shuffles, then across wavefronts through LDS; the lowest
-// row wins ties), then the pivot row and row c are exchanged through LDS,
-// every lane reads the pivot row and updates its own row.  Three barriers per
-// step and under 1 KB of LDS, so several blocks share a CU.  The steps are
-// instantiated per panel column so that every register index is a constant
-// (a runtime index would put the row in scratch memory).
-//
-// Each lane also tracks which input row its values came from; at the end the
-// panel writes the list of touched rows (the panel rows S in order, then
-// every other row whose content moved, with its source row) that the update
-// kernels use to apply the interchanges to the other columns as a gather.
+// The panel kernel also tracks which input row each lane's values came from;
+// at the end it writes the list of touched rows (the panel rows S in order,
+// then every other row whose content moved, with its source row) that the
+// update kernels use to apply the interchanges to the other columns as a
+// gather.
 constexpr int kTouch = 2 * kPanel;            // S plus at most one moved row per pivot step
 static_assert(kTouchStride == 1 + 2 * kTouch, "touched-row list: count, rows[kTouch], sources[kTouch]");
 
-struct PanelLds {
-    double v[8];
-    int i[8];
-    int cnt[8];
-    int piv;
-    int porg, corg;         // source rows of the pivot row and of row c
-    double pivrow[kPanel];  // the pivot row (old row p)
-    double oldc[kPanel];    // old row c, taken over by lane p
+// Panel factorisation with the panel in registers, two wavefronts per block:
+// lane t of the workgroup owns rows t, t + 128, ... (kPanel values each, RPL
+// rows), so a pivot step needs two barriers between two wavefronts (one
+// wavefront per 64 rows took three barriers across up to five wavefronts and
+// spent most of its time waiting at them).  Per step: each wavefront's argmax
+// by shuffles (the lowest row wins ties), combined through LDS (barrier); the
+// owners of the pivot row and of row c put them in LDS (barrier); every lane
+// swaps and eliminates its rows against the pivot row, read column by column
+// from LDS.  The steps are instantiated per panel column so that every
+// register index is a constant (a runtime index would put the rows in scratch
+// memory).  Outputs: the panel columns in place, the pivot rows, the
+// touched-row list and the pivot flags.
+constexpr int kPanel2Threads = 128;
+
+struct Panel2Lds {
+    double v[2];
+    int i[2];
+    int cnt[4][2];
+    int porg, corg;
+    double pivrow[kPanel];
+    double oldc[kPanel];
 };
 
-template <int CC>
-__device__ __forceinline__ void panel_step(double (&x)[kPanel], int &org, PanelLds &sh, int r, int nb, int c0,
-                                           int bw, int nw, int *__restrict__ perm, int &flags) {
+template <int RPL, int CC>
+__device__ __forceinline__ void panel2_step(double (&x)[RPL][kPanel], int (&org)[RPL], Panel2Lds &sh, int t, int nb,
+                                            int c0, int bw, int *__restrict__ perm, int &flags) {
     if (CC >= bw) return;
     const int c = c0 + CC;
-    double best = (r >= c && r < nb) ? fabs(x[CC]) : -1.0;
-    int bi = (r >= c && r < nb) ? r : 0x7fffffff;
+    double best = -1.0;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * kPanel2Threads + t;
+        if (r >= c && r < nb) argmax_combine(best, bi, fabs(x[s][CC]), r);
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        const double v2 = __shfl_down(best, off, 64);
-        const int i2 = __shfl_down(bi, off, 64);
+        const double v2 = __shfl_xor(best, off, 64);
+        const int i2 = __shfl_xor(bi, off, 64);
         argmax_combine(best, bi, v2, i2);
     }
-    if ((r & 63) == 0) {
-        sh.v[r >> 6] = best;
-        sh.i[r >> 6] = bi;
+    if ((t & 63) == 0) {
+        sh.v[t >> 6] = best;
+        sh.i[t >> 6] = bi;
     }
     __syncthreads();
-    if (r == 0) {
-        double bv = sh.v[0];
-        int ii = sh.i[0];
-        for (int w = 1; w < nw; ++w) argmax_combine(bv, ii, sh.v[w], sh.i[w]);
-        if (ii < c || ii >= nb) ii = c;  // a column of NaNs compares false everywhere
-        sh.piv = ii;
-        perm[(size_t)blockIdx.x * nb + c] = ii;
+    double bv = sh.v[0];
+    int p = sh.i[0];
+    argmax_combine(bv, p, sh.v[1], sh.i[1]);
+    if (p < c || p >= nb) p = c;  // a column of NaNs compares false everywhere: keep row c
+    if (t == 0) perm[(size_t)blockIdx.x * nb + c] = p;
+    const int sp = p / kPanel2Threads, tp = p - sp * kPanel2Threads;
+    const int sc = c / kPanel2Threads, tc = c - sc * kPanel2Threads;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        if (s == sp && t == tp) {
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j) sh.pivrow[j] = x[s][j];
+            sh.porg = org[s];
+        }
+        if (s == sc && t == tc && p != c) {
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j) sh.oldc[j] = x[s][j];
+            sh.corg = org[s];
+        }
     }
     __syncthreads();
-    const int p = sh.piv;
-    if (r == p) {
+    if (p != c) {
 #pragma unroll
-        for (int j = 0; j < kPanel; ++j) sh.pivrow[j] = x[j];
-        sh.porg = org;
-    }
-    if (r == c && p != c) {
+        for (int s = 0; s < RPL; ++s) {
+            if (s == sp && t == tp) {
 #pragma unroll
-        for (int j = 0; j < kPanel; ++j) sh.oldc[j] = x[j];
-        sh.corg = org;
+                for (int j = 0; j < kPanel; ++j) x[s][j] = sh.oldc[j];
+                org[s] = sh.corg;
+            }
+            if (s == sc && t == tc) org[s] = sh.porg;
+        }
     }
-    __syncthreads();
-    if (r == p && p != c) {
-#pragma unroll
-        for (int j = 0; j < kPanel; ++j) x[j] = sh.oldc[j];
-        org = sh.corg;
-    }
-    if (r == c && p != c) org = sh.porg;
     double d = sh.pivrow[CC];
     if (d == 0.0) {
         flags |= kPivZero;
@@ -230,66 +245,100 @@ __device__ __forceinline__ void panel_step(double (&x)[kPanel], int &org, PanelL
         flags |= kPivNonfinite;
     }
     const double inv = 1.0 / d;
-    if (r == c) {
+    // every row: x - f pv with f its multiplier (column CC: -f / d); rows
+    // beyond the block compute values nobody stores; row c then takes the
+    // scaled pivot row (one lane)
+    double f[RPL];
 #pragma unroll
-        for (int j = 0; j < kPanel; ++j) x[j] = (j == CC ? 1.0 : sh.pivrow[j]) * inv;
-    } else if (r < nb) {
-        const double f = x[CC];
+    for (int s = 0; s < RPL; ++s) f[s] = x[s][CC];
 #pragma unroll
-        for (int j = 0; j < kPanel; ++j) {
-            const double pv = (j == CC ? 1.0 : sh.pivrow[j]) * inv;
-            x[j] = (j == CC ? 0.0 : x[j]) - f * pv;
+    for (int j = 0; j < kPanel; ++j) {
+        const double pv = (j == CC ? 1.0 : sh.pivrow[j]) * inv;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) x[s][j] = (j == CC ? 0.0 : x[s][j]) - f[s] * pv;
+    }
+    // the pivot row is read again below: keep the compiler from holding it in
+    // registers across the loop (it would not fit beside the rows)
+    __asm__ volatile("" ::: "memory");
+    if (t == tc) {
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            if (s == sc) {
+#pragma unroll
+                for (int j = 0; j < kPanel; ++j) x[s][j] = (j == CC ? 1.0 : sh.pivrow[j]) * inv;
+            }
         }
     }
 }
 
-template <int... CC>
-__device__ __forceinline__ void panel_steps(std::integer_sequence<int, CC...>, double (&x)[kPanel], int &org,
-                                            PanelLds &sh, int r, int nb, int c0, int bw, int nw,
-                                            int *__restrict__ perm, int &flags) {
-    (panel_step<CC>(x, org, sh, r, nb, c0, bw, nw, perm, flags), ...);
+template <int RPL, int... CC>
+__device__ __forceinline__ void panel2_steps(std::integer_sequence<int, CC...>, double (&x)[RPL][kPanel],
+                                             int (&org)[RPL], Panel2Lds &sh, int t, int nb, int c0, int bw,
+                                             int *__restrict__ perm, int &flags) {
+    (panel2_step<RPL, CC>(x, org, sh, t, nb, c0, bw, perm, flags), ...);
 }
 
-__global__ void __launch_bounds__(512) k_gj_panel_reg(int nb, int c0, int bw, double *__restrict__ A,
-                                                      int *__restrict__ perm, int *__restrict__ touch,
-                                                      int *__restrict__ status) {
-    __shared__ PanelLds sh;
-    const int r = threadIdx.x;
-    const int nw = blockDim.x >> 6;
+template <int RPL>
+__global__ void __launch_bounds__(kPanel2Threads, RPL <= 3 ? 2 : 1)
+k_gj_panel2(int nb, int c0, int bw, double *__restrict__ A,
+                                                             int *__restrict__ perm, int *__restrict__ touch,
+                                                             int *__restrict__ status) {
+    __shared__ Panel2Lds sh;
+    const int t = threadIdx.x;
     double *Ak = A + (size_t)blockIdx.x * nb * nb;
-    double x[kPanel];
+    double x[RPL][kPanel];
+    int org[RPL];
 #pragma unroll
-    for (int j = 0; j < kPanel; ++j) x[j] = (r < nb && j < bw) ? Ak[(size_t)(c0 + j) * nb + r] : 0.0;
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * kPanel2Threads + t;
+        org[s] = r;
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) x[s][j] = (r < nb && j < bw) ? Ak[(size_t)(c0 + j) * nb + r] : 0.0;
+    }
     int flags = 0;
-    int org = r;
-    panel_steps(std::make_integer_sequence<int, kPanel>{}, x, org, sh, r, nb, c0, bw, nw, perm, flags);
-    if (r < nb) {
+    panel2_steps<RPL>(std::make_integer_sequence<int, kPanel>{}, x, org, sh, t, nb, c0, bw, perm, flags);
 #pragma unroll
-        for (int j = 0; j < kPanel; ++j)
-            if (j < bw) Ak[(size_t)(c0 + j) * nb + r] = x[j];
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * kPanel2Threads + t;
+        if (r < nb) {
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j)
+                if (j < bw) Ak[(size_t)(c0 + j) * nb + r] = x[s][j];
+        }
     }
     // touched-row list: slot r - c0 for the panel rows, then the moved rows in
-    // row order (a wavefront ballot ranks them within the wavefront)
-    const bool inS = r >= c0 && r < c0 + bw;
-    const bool moved = r < nb && !inS && org != r;
-    const unsigned long long m = __ballot(moved);
-    const int lane = r & 63, w = r >> 6;
-    if (lane == 0) sh.cnt[w] = __popcll(m);
+    // row order, ranked by wavefront ballots per slot (rows s*128 + t: slot
+    // major, then wavefront, then lane)
+    const int lane = t & 63, w = t >> 6;
+    unsigned long long m[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * kPanel2Threads + t;
+        const bool inS = r >= c0 && r < c0 + bw;
+        m[s] = __ballot(r < nb && !inS && org[s] != r);
+        if (lane == 0) sh.cnt[s][w] = __popcll(m[s]);
+    }
     __syncthreads();
-    int off = bw;
-    for (int w2 = 0; w2 < w; ++w2) off += sh.cnt[w2];
     int *tl = touch + (size_t)blockIdx.x * kTouchStride;
-    const int slot = inS ? r - c0 : (moved ? off + __popcll(m & ((1ull << lane) - 1ull)) : -1);
-    if (slot >= 0) {
-        tl[1 + slot] = r;
-        tl[1 + kTouch + slot] = org;
+    int off = bw;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * kPanel2Threads + t;
+        const bool inS = r >= c0 && r < c0 + bw;
+        const int base = off + (w == 1 ? sh.cnt[s][0] : 0);
+        int slot = -1;
+        if (inS)
+            slot = r - c0;
+        else if ((m[s] >> lane) & 1ull)
+            slot = base + __popcll(m[s] & ((1ull << lane) - 1ull));
+        if (slot >= 0) {
+            tl[1 + slot] = r;
+            tl[1 + kTouch + slot] = org[s];
+        }
+        off += sh.cnt[s][0] + sh.cnt[s][1];
     }
-    if (r == 0) {
-        int n = bw;
-        for (int w2 = 0; w2 < nw; ++w2) n += sh.cnt[w2];
-        tl[0] = n;
-    }
-    if (flags && r == 0) atomicOr(status, flags);
+    if (t == 0) tl[0] = off;
+    if (flags && t == 0) atomicOr(status, flags);
 }
 
 constexpr int kUpdCols = 64;  // columns per update workgroup
@@ -303,6 +352,17 @@ struct TouchLds {
     int src[kTouch];
     short upos[kMaxNb];
     int nu;
+};
+
+// The columns an update launch transforms: tile column ri < n is block column
+// j = lo + ri, shifted past the excluded window [skip_lo, skip_lo + skip_w)
+// (the panel's own columns).
+struct ColMap {
+    int lo, n, skip_lo, skip_w;
+    __device__ __forceinline__ int col(int ri) const {
+        const int j = lo + ri;
+        return j >= skip_lo ? j + skip_w : j;
+    }
 };
 
 // Workgroup -> (block, column tile).  Workgroups are dispatched round-robin
@@ -334,16 +394,12 @@ __device__ __forceinline__ void load_touch(TouchLds &t, const int *__restrict__ 
 // the block); one column per wavefront per pass.  Read before any write of
 // the tile, so the in-place update cannot overwrite a value still needed.
 __device__ __forceinline__ void stage_touched(const TouchLds &t, double (*stg)[kTouch + 1], const double *Ak,
-                                              int nb, int c0, int bw, int tile) {
-    const int nrest = nb - bw;
+                                              int nb, const ColMap &cm, int tile) {
     for (int i = threadIdx.x; i < kTouch * kUpdCols; i += blockDim.x) {
         const int u = i % kTouch, jj = i / kTouch;
         const int ri = tile * kUpdCols + jj;
         double v = 0.0;
-        if (u < t.nu && ri < nrest) {
-            const int j = (ri < c0) ? ri : ri + bw;
-            v = Ak[(size_t)j * nb + t.src[u]];
-        }
+        if (u < t.nu && ri < cm.n) v = Ak[(size_t)cm.col(ri) * nb + t.src[u]];
         stg[jj][u] = v;
     }
 }
@@ -361,24 +417,25 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 template <bool F64>
 struct UpdLane {
     int r16, g, wave;
-    int ri0, nrest, c0, bw;
-    __device__ UpdLane(int tid, int tile, int nrest_, int c0_, int bw_) {
+    int ri0, c0, bw;  // c0, bw: the panel (its columns hold T, its rows are S)
+    ColMap cm;
+    __device__ UpdLane(int tid, int tile, const ColMap &cm_, int c0_, int bw_) {
         const int lane = tid & 63;
         wave = tid >> 6;
         r16 = lane & 15;
         g = lane >> 4;
         ri0 = tile * kUpdCols;
-        nrest = nrest_;
+        cm = cm_;
         c0 = c0_;
         bw = bw_;
     }
     // tile column of result (cb, v)
     __device__ __forceinline__ int jj(int cb, int v) const { return cb * 16 + (F64 ? g + 4 * v : 4 * g + v); }
-    // its block column; false beyond the block
+    // its block column; false beyond the launch's columns
     __device__ __forceinline__ bool col(int cb, int v, int &j) const {
         const int ri = ri0 + jj(cb, v);
-        j = (ri < c0) ? ri : ri + bw;
-        return ri < nrest;
+        j = cm.col(ri);
+        return ri < cm.n;
     }
 };
 
@@ -439,18 +496,18 @@ __device__ __forceinline__ void store_chunk(double *Ak, const TouchLds &tl, cons
 // column r16, panel column 4ks + g; B = T^T: panel column 4ks + g, row r16).
 // The next chunk's global reads are in flight while a chunk is multiplied.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_gj_update(int Ne, int nb, int c0, int bw, double *__restrict__ A, const int *__restrict__ touch) {
+k_gj_update(int Ne, int nb, int c0, int bw, ColMap cm, double *__restrict__ A, const int *__restrict__ touch) {
     __shared__ double stg[kUpdCols][kTouch + 1];  // (P x) on the touched rows; (P x)_S = slots 0..bw-1
     __shared__ double tp[kPanel][kUpdRows];       // T_panel chunk, [panel column][row]
     __shared__ TouchLds tl;
-    const int nrest = nb - bw, ntile = (nrest + kUpdCols - 1) / kUpdCols;
+    const int ntile = (cm.n + kUpdCols - 1) / kUpdCols;
     int k, tile;
     if (!update_tile(Ne, ntile, k, tile)) return;
     const int tid = threadIdx.x;
     double *Ak = A + (size_t)k * nb * nb;
     load_touch(tl, touch + (size_t)k * kTouchStride, nb);
-    stage_touched(tl, stg, Ak, nb, c0, bw, tile);
-    const UpdLane<true> L(tid, tile, nrest, c0, bw);
+    stage_touched(tl, stg, Ak, nb, cm, tile);
+    const UpdLane<true> L(tid, tile, cm, c0, bw);
     ChunkLoads ld;
     ld.issue_t(Ak, L, nb, 0);
     ld.issue_x(Ak, tl, L, nb, 0);
@@ -487,21 +544,21 @@ k_gj_update(int Ne, int nb, int c0, int bw, double *__restrict__ A, const int *_
 // hi*lo (three MFMAs), ~16 mantissa bits.  Operands are staged k-contiguous
 // in LDS.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_gj_update_mfma(int Ne, int nb, int c0, int bw, double *__restrict__ A, const int *__restrict__ touch) {
+k_gj_update_mfma(int Ne, int nb, int c0, int bw, ColMap cm, double *__restrict__ A, const int *__restrict__ touch) {
     __shared__ __attribute__((aligned(16))) __bf16 xs_h[kUpdCols][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 xs_l[kUpdCols][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 tp_h[kUpdRows][kPanel];
     __shared__ __attribute__((aligned(16))) __bf16 tp_l[kUpdRows][kPanel];
     __shared__ double stg[kUpdCols][kTouch + 1];
     __shared__ TouchLds tl;
-    const int nrest = nb - bw, ntile = (nrest + kUpdCols - 1) / kUpdCols;
+    const int ntile = (cm.n + kUpdCols - 1) / kUpdCols;
     int k, tile;
     if (!update_tile(Ne, ntile, k, tile)) return;
     const int tid = threadIdx.x;
     double *Ak = A + (size_t)k * nb * nb;
     load_touch(tl, touch + (size_t)k * kTouchStride, nb);
-    stage_touched(tl, stg, Ak, nb, c0, bw, tile);
-    const UpdLane<false> L(tid, tile, nrest, c0, bw);
+    stage_touched(tl, stg, Ak, nb, cm, tile);
+    const UpdLane<false> L(tid, tile, cm, c0, bw);
     ChunkLoads ld;
     ld.issue_t(Ak, L, nb, 0);
     ld.issue_x(Ak, tl, L, nb, 0);
@@ -610,20 +667,33 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
     if (ej_blocked(nb, precision)) {
         if (nb > kMaxNb || !L.perm || !L.touch || !L.colperm) return hipErrorInvalidValue;
         const bool mfma = precision == FR_PREC_FP32_BF16 || precision == FR_PREC_BF16_STORE;
-        const int rows = ((nb + 63) / 64) * 64;  // one lane per block row
+        const int rpl = (nb + kPanel2Threads - 1) / kPanel2Threads;  // rows per lane of the panel kernel
+        if (rpl > 4) return hipErrorInvalidValue;
+        auto panel = [&](int c, int bw, int *touch) {
+            const dim3 gp(Ne), bp(kPanel2Threads);
+            if (rpl == 1)
+                hipLaunchKernelGGL(k_gj_panel2<1>, gp, bp, 0, s, nb, c, bw, L.blk64, L.perm, touch, L.dstatus);
+            else if (rpl == 2)
+                hipLaunchKernelGGL(k_gj_panel2<2>, gp, bp, 0, s, nb, c, bw, L.blk64, L.perm, touch, L.dstatus);
+            else if (rpl == 3)
+                hipLaunchKernelGGL(k_gj_panel2<3>, gp, bp, 0, s, nb, c, bw, L.blk64, L.perm, touch, L.dstatus);
+            else
+                hipLaunchKernelGGL(k_gj_panel2<4>, gp, bp, 0, s, nb, c, bw, L.blk64, L.perm, touch, L.dstatus);
+        };
+        // one panel's transform applied to the columns cm lists
+        auto update = [&](int c, int bw, const ColMap &cm, const int *touch) {
+            if (cm.n <= 0) return;
+            const int ntile = (cm.n + kUpdCols - 1) / kUpdCols;
+            const dim3 gu((unsigned)(((Ne + 7) / 8) * 8 * ntile));
+            if (mfma)
+                hipLaunchKernelGGL(k_gj_update_mfma, gu, dim3(256), 0, s, Ne, nb, c, bw, cm, L.blk64, touch);
+            else
+                hipLaunchKernelGGL(k_gj_update, gu, dim3(256), 0, s, Ne, nb, c, bw, cm, L.blk64, touch);
+        };
         for (int c0 = 0; c0 < nb; c0 += kPanel) {
             const int bw = min(kPanel, nb - c0);
-            hipLaunchKernelGGL(k_gj_panel_reg, dim3(Ne), dim3(rows), 0, s, nb, c0, bw, L.blk64, L.perm, L.touch,
-                               L.dstatus);
-            const int nrest = nb - bw;
-            if (nrest > 0) {
-                const int ntile = (nrest + kUpdCols - 1) / kUpdCols;
-                const dim3 gu((unsigned)(((Ne + 7) / 8) * 8 * ntile));
-                if (mfma)
-                    hipLaunchKernelGGL(k_gj_update_mfma, gu, dim3(256), 0, s, Ne, nb, c0, bw, L.blk64, L.touch);
-                else
-                    hipLaunchKernelGGL(k_gj_update, gu, dim3(256), 0, s, Ne, nb, c0, bw, L.blk64, L.touch);
-            }
+            panel(c0, bw, L.touch);
+            update(c0, bw, ColMap{0, nb - bw, c0, bw}, L.touch);
         }
         hipLaunchKernelGGL(k_gj_colperm, dim3(Ne), dim3(64), 0, s, nb, L.perm, L.colperm);
         L.inv_cols = L.colperm;

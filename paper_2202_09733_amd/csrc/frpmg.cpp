@@ -15,6 +15,8 @@
 #include <mutex>
 #include <random>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "internal.hpp"
 #include "lcc.hpp"
 
@@ -80,6 +82,14 @@ void dfree(void *p) {
 }
 
 hipStream_t S(fr_stream s) { return (hipStream_t)s; }
+
+// a named range on the profiler's timeline (roctx; no cost without a profiler)
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 int ipow(int b, int e) {
     int r = 1;
@@ -191,6 +201,7 @@ void ensure_face_save(frpmg_ctx *ctx, Level &L) {
 }
 
 void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, int precision, hipStream_t s) {
+    Range range(level == 0 ? "ej_factor level 0" : "ej_factor coarse level");
     REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
     REQUIRE(precision >= FR_PREC_FP64 && precision <= FR_PREC_BF16_STORE, "bad precision");
     check_neighbours(ctx);
@@ -850,27 +861,40 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
         for (int j = 0; j < m; ++j) {
             // one Arnoldi step: z_j = M v_j, w = A z_j, CGS2 against v_0..v_j,
             // v_{j+1} = w / ||w|| (the norm stays on the device)
+            const bool timed = !gu && ctx->ph_ev[0];
             auto step = [&, j](hipStream_t st) {
                 double *vj = V + (size_t)j * ld;
                 double *zj = Z + (size_t)j * ld;
+                if (timed) HIPCHK(hipEventRecord(ctx->ph_ev[0], st));
                 M(vj, zj, st);
+                if (timed) HIPCHK(hipEventRecord(ctx->ph_ev[1], st));
                 A(zj, w, st);
+                if (timed) HIPCHK(hipEventRecord(ctx->ph_ev[2], st));
                 HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H1, st));
                 HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H1, w, st));
                 HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H2, st));
                 HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H2, w, st));
                 HIPCHK(vec_dot_normalize(ctx, N, w, ctx->red_out + RO_N2, V + (size_t)(j + 1) * ld, st));
+                if (timed) HIPCHK(hipEventRecord(ctx->ph_ev[3], st));
             };
             if (gu) {
                 std::vector<unsigned long long> key = gu->key;
                 key.push_back((unsigned long long)j);
                 run_graph(ctx, key, gu->cnt, step, s);
             } else {
+                Range r("arnoldi step");
                 step(s);
             }
             HIPCHK(hipMemcpyAsync(ctx->host_pinned, ctx->red_out, RO_SIZE * sizeof(double), hipMemcpyDeviceToHost,
                                   s));
             HIPCHK(hipStreamSynchronize(s));
+            if (timed) {
+                for (int ph = 0; ph < 3; ++ph) {
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, ctx->ph_ev[ph], ctx->ph_ev[ph + 1]));
+                    ctx->ph_acc[ph] += 1e-3 * ms;
+                }
+            }
             const double *hp = ctx->host_pinned;
             for (int i = 0; i <= j; ++i) Hc(i, j) = hp[RO_H1 + i] + hp[RO_H2 + i];
             const double hn = std::sqrt(hp[RO_N2]);
@@ -1004,11 +1028,14 @@ void ensure_krylov(frpmg_ctx *ctx, int m) {
     if (!ctx->sF) ctx->sF = dalloc(ctx, N);
     if (!ctx->sb) ctx->sb = dalloc(ctx, N);
     if (!ctx->sdx) ctx->sdx = dalloc(ctx, N);
+    for (auto &e : ctx->ph_ev)
+        if (!e) HIPCHK(hipEventCreate(&e));
 }
 
 double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
 
 // The solver state of one implicit stage: shifts, preconditioner settings,
 // counters, the stall monitor and the graph keys.  One object serves every
@@ -1236,6 +1263,9 @@ struct StageSolver {
         st->n_ej_fine = cnt.E0;
         st->n_ej_coarse = cnt.E1;
         st->fallbacks = fallbacks;
+        st->t_precond = ctx->ph_acc[0];
+        st->t_jvp = ctx->ph_acc[1];
+        st->t_ortho = ctx->ph_acc[2];
     }
 };
 
@@ -1247,11 +1277,16 @@ struct StageSolver {
 void stage_impl(frpmg_ctx *ctx, const stage_params &P, const double *dq_n, double *out, stage_stats *st,
                 hipStream_t s) {
     std::memset(st, 0, sizeof(*st));
+    Range range("stage");
     StageSolver S(ctx, P);
     const size_t N = S.N;
+    for (double &a : ctx->ph_acc) a = 0.0;
     HIPCHK(hipStreamSynchronize(s));
     const double t0 = now();
-    if (!P.skip_setup) S.setup(dq_n, s);
+    if (!P.skip_setup) {
+        Range rs("stage set-up");
+        S.setup(dq_n, s);
+    }
     HIPCHK(hipStreamSynchronize(s));
     const double t1 = now();
     fr_status status;
@@ -1461,6 +1496,7 @@ void ensure_step_vectors(frpmg_ctx *ctx, int nvec) {
 
 void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double *out, step_stats *ss,
                hipStream_t s) {
+    Range range("time step");
     std::memset(ss, 0, sizeof(*ss));
     const bool esdirk = is_esdirk_tab(SP.tableau);
     REQUIRE(esdirk || is_row_tab(SP.tableau), "unknown tableau");
@@ -1498,7 +1534,11 @@ void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double
             for (int j = 0; j < i; ++j)
                 if (TE.A[i][j] != 0.0) HIPCHK(vec_axpby(N, Scal{TE.A[i][j] * P.dt, nullptr}, V[j], one, b, s));
             stage_stats *st = &ss->stage[ss->nstages];
+            for (double &a : ctx->ph_acc) a = 0.0;
             status = S.esdirk_solve(b, q, rq, st, s);
+            st->t_precond = ctx->ph_acc[0];
+            st->t_jvp = ctx->ph_acc[1];
+            st->t_ortho = ctx->ph_acc[2];
             ss->nstages++;
             ss->gmres_iters += st->gmres_iters;
             ss->ptc_iters += st->ptc_iters;
@@ -1532,7 +1572,11 @@ void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double
                     if (TR.c[i][j] != 0.0) HIPCHK(vec_axpby(N, Scal{TR.c[i][j] / P.dt, nullptr}, V[j], one, rhs, s));
             }
             stage_stats *st = &ss->stage[ss->nstages];
+            for (double &a : ctx->ph_acc) a = 0.0;
             status = S.row_solve(dq_n, R0, rhs, V[i], st, s);
+            st->t_precond = ctx->ph_acc[0];
+            st->t_jvp = ctx->ph_acc[1];
+            st->t_ortho = ctx->ph_acc[2];
             ss->nstages++;
             ss->gmres_iters += st->gmres_iters;
         }
@@ -1554,6 +1598,10 @@ void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double
 
 void destroy_all(frpmg_ctx *ctx) {
     clear_graphs(ctx);
+    for (auto &e : ctx->ph_ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     ctx->cap_stream = nullptr;
     lcc_free(ctx);

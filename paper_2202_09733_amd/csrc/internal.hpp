@@ -33,6 +33,16 @@ struct Transfer1D {
     double Pi[kMaxP][kMaxP];  // prolongation, P0 x P1
 };
 
+// Operators of every degree for meshes of mixed degree (p-adaptation):
+// the 1D operators by point count, the 1D L2 projections between point
+// counts (proj[Pa][Pb][b][a], from Pa to Pb points) and the Legendre
+// coefficients of a P-point interpolant (modal[P][n][i]).
+struct PaTables {
+    Ops1D ops[kMaxP + 1];
+    double proj[kMaxP + 1][kMaxP + 1][kMaxP][kMaxP];
+    double modal[kMaxP + 1][kMaxP][kMaxP];
+};
+
 struct Phys {
     double gam, mu, Pr, tau;
     double qinf[5];
@@ -116,7 +126,26 @@ struct DevBuf {
     size_t n = 0;
 };
 
+// Mixed polynomial degrees on one level (p-adaptation, Sec. 3.3).  The
+// level's P, Np, NF and nb are those of its largest degree; states, face
+// arrays and EJ blocks keep that padded size.
+struct PaLevel {
+    std::vector<int> Pk_host;     // points per direction of every element
+    int *Pk = nullptr;            // the same on the device [Ne]
+    int *cls = nullptr;           // device: element ids grouped by point count
+    int cls_off[kMaxP + 2] = {};  // class P is cls[cls_off[P] .. cls_off[P + 1])
+    int *mixed = nullptr;         // device: faces between different degrees, k * 4 + a (k the -axis element)
+    int nmixed = 0;
+    double *Fm = nullptr;         // common flux on - faces at the element's points [dim][nv][NF][Ne]
+    double *Mq = nullptr;         // mixed faces: the -axis element's + trace [dim][nv][NF][Ne]
+    double *Mn = nullptr;         // mixed faces: the +axis element's - trace at its points [dim][nv][NF][Ne]
+    double *Mg = nullptr;         // mixed faces: the -axis element's gradient trace [dim][dim][nv][NF][Ne]
+    double *fdv = nullptr;        // EJ formation: perturbation vector [N] (zero between columns)
+    double *fdr = nullptr;        // EJ formation: perturbed residual [N]
+};
+
 struct Level {
+    PaLevel *pa = nullptr;  // mixed degrees (nullptr: every element has degree p)
     int p = 0, P = 0, Np = 0, NF = 0, nb = 0;
     size_t N = 0;  // state length
     Ops1D ops{};
@@ -135,7 +164,7 @@ struct Level {
     int inv_prec = -1;
     int *dstatus = nullptr;   // device pivot flags (kPivZero | kPivNonfinite)
     int *perm = nullptr;      // pivot rows of the blocked inversion [Ne][nb]
-    int *touch = nullptr;     // the current panel's touched-row list [Ne][kTouchStride]
+    int *touch = nullptr;     // the panel's touched-row lists [Ne][kTouchStride]
     int *colperm = nullptr;   // column placement of the blocked inversion [Ne][nb]
     const int *inv_cols = nullptr;  // nullptr: inv holds B^-1; else B^-1[:, inv_cols[j]] = inv[:, j]
     double *r0 = nullptr;     // scratch: R at the EJ linearisation point
@@ -204,6 +233,8 @@ struct frpmg_ctx {
     frpmg::Phys phys{};
     frpmg::Level lv[FR_MAX_LEVELS];
     frpmg::Transfer1D tr[FR_MAX_LEVELS];  // tr[l]: between level l and l + 1
+    frpmg::PaTables *pa_tab = nullptr;       // device: operators of every degree (mixed-degree levels)
+    frpmg::PaTables *pa_tab_host = nullptr;  // host copy
     double *inv2h[3] = {nullptr, nullptr, nullptr};
     std::string err;
     double *red_partial = nullptr;  // [128][kRedBlocks]
@@ -230,6 +261,10 @@ struct frpmg_ctx {
     frpmg::Lcc *lcc = nullptr;
     // MBNK smoother (allocated at the first mbnk_factor)
     frpmg::Mbnk *mb = nullptr;
+    // per-phase timing of host-launched Arnoldi steps (events created at the first stage solve):
+    // preconditioner, FD product, orthogonalisation and normalisation, seconds summed over a stage
+    hipEvent_t ph_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double ph_acc[3] = {0.0, 0.0, 0.0};
     // captured Arnoldi steps, replayed on the caller's stream
     hipStream_t cap_stream = nullptr;
     std::vector<frpmg::StepGraph> graphs;
@@ -241,6 +276,7 @@ namespace frpmg {
 // ops1d.cpp
 void build_ops1d(int P, Ops1D &o);
 void build_transfer(int P0, int P1, Transfer1D &t);
+void build_pa_tables(PaTables &t);
 void gauss_legendre(int P, double *x, double *w);
 
 // residual.hip
@@ -252,6 +288,17 @@ hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, dou
 // r = R(dq) for `batch` independent copies of a 2D level's state, copy b at
 // elements b Ne .. (b + 1) Ne - 1 of [nv][Np][batch Ne] arrays; face buffers
 // Jp and Fs hold [dim][nv][NF][batch Ne].  3D: batch must be 1.
+// mixed-degree levels (residual.hip)
+hipError_t launch_residual_pa(const frpmg_ctx *ctx, int level, const ResidualArgs &a, hipStream_t s);
+hipError_t launch_ej_form_pa(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s,
+                             double *out);
+hipError_t pa_transfer(const frpmg_ctx *ctx, int from, int to, const double *x, double *y, const double *x0,
+                       bool accumulate, const double *x2, double *y2, hipStream_t s);
+hipError_t pa_project(const frpmg_ctx *ctx, const int *Pfrom, int NpF, const double *x, const int *Pto, int NpT,
+                      double *y, hipStream_t s);
+hipError_t pa_indicator(const frpmg_ctx *ctx, int level, const double *dq, int var, double *eta, hipStream_t s);
+hipError_t pa_adapt(const frpmg_ctx *ctx, const double *eta, const int *deg_in, int *deg_out, int p_min, int p_max,
+                    double nu_max, double nu_min, hipStream_t s);
 hipError_t launch_residual_batch(const frpmg_ctx *ctx, int level, int batch, const double *dq, double *r,
                                  double *Jp, double *Fs, hipStream_t s);
 

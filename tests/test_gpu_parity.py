@@ -288,6 +288,11 @@ def test_stage_vortical64_full_size(orc):
     print(st)
     assert st["converged"] == 1
     assert _oracle_F(orc, wl, q.cpu().numpy()) <= 1.5e-8
+    # per-phase times of the Arnoldi steps (HIP events) fit inside the solve
+    phases = st["t_precond"] + st["t_jvp"] + st["t_ortho"]
+    print("phases: preconditioner %.4f s, FD product %.4f s, orthogonalisation %.4f s of %.4f s"
+          % (st["t_precond"], st["t_jvp"], st["t_ortho"], st["t_solve"]))
+    assert min(st["t_precond"], st["t_jvp"], st["t_ortho"]) > 0 and phases <= st["t_solve"]
 
 
 @pytest.mark.parametrize("tol,verify", [(1e-10, 0), (1e-8, 1)])
