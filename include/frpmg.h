@@ -488,6 +488,79 @@ fr_status lcc_features_of(frpmg_ctx *ctx, const double *d1, float *rows_out, flo
  * step (lcc_set_weights resets them).  Asynchronous. */
 fr_status lcc_adam_step(frpmg_ctx *ctx, const float *grad, double lr, fr_stream stream);
 
+/* ------------------------------------------------------------------------
+ * p-adaptive FR (Sec. 3.3, "Coupling with p-adaptation")
+ *
+ * A context becomes p-adaptive when fr_set_degrees gives every element of
+ * the finest level its own degree.  Every level then keeps the state layout
+ * of its largest degree p (the context's p[l]), padded: element k of degree
+ * d_k uses local points i < (d_k + 1)^dim numbered i = a + P_k (b + P_k c),
+ * P_k = d_k + 1; the remaining entries of an input are ignored where stated
+ * and every output writes them as 0 (state vectors of a solve stay 0 there).
+ * EJ blocks keep n_b = nvar (p + 1)^dim with the identity on unused points.
+ * fr_residual, fr_jvp, ej_factor/ej_solve, pmg_restrict/pmg_prolong,
+ * pmg_precond_apply (EJ smoothing on every level), gmres_solve_stage and
+ * fr_time_step then act on the mixed-degree discretisation; the MBNK
+ * smoother, the learned correction and fr_residual_noalloc are refused
+ * (FR_EINVAL).
+ *
+ * Face coupling (the paper defers it to its p-adaptation reference; this is
+ * the library's reading): the common solution at a face is the +axis
+ * element's trace, seen by the -axis element through the L2 projection onto
+ * its own face polynomials; the common flux is formed at the Gauss-Legendre
+ * points of the larger of the two degrees from both traces and the -axis
+ * element's gradient trace carried there by L2 projection, and returned to
+ * both sides by L2 projection (so the scheme stays conservative).  Faces of
+ * equal degree are unchanged, so a uniform degree map gives the uniform
+ * operator.
+ * ------------------------------------------------------------------------ */
+
+/* Nested p-hierarchy (Sec. 3.3): out[l * ne + k] = the degree of element k on
+ * p-sublevel l (l < nlevels, order gap 1 or 2), from its finest degree deg[k]:
+ * each sublevel lowers the finest degree by the gap but keeps at least as many
+ * degrees as sublevels remain below it, stays below the sublevel above and
+ * stops at 0 -- for P4 with three sublevels this gives p{4-2-0}, p{3-1-0},
+ * p{2-1-0}, p{1-0-0} (gap 2) and p{4-3-2}, p{3-2-1}, p{2-1-0}, p{1-0-0}
+ * (gap 1), the paper's listed hierarchies.  Host arrays; no context. */
+fr_status fr_pa_hierarchy(const int *deg, int ne, int nlevels, int gap, int *out);
+
+/* Give the finest level the per-element degrees host_deg[Ne] (HOST array,
+ * 0 <= deg <= p[0]) and every coarser level its nested degrees (fr_pa_hierarchy
+ * with the given gap); the largest degree on each level must equal the
+ * context's p[l] (FR_EINVAL otherwise).  host_deg = NULL returns to uniform
+ * degrees.  Synchronises the device, drops the EJ factors of every level and
+ * allocates the level's face and formation buffers.  EJ blocks of a
+ * mixed-degree level are formed by coloured one-sided differences of the
+ * full residual (even element counts per axis). */
+fr_status fr_set_degrees(frpmg_ctx *ctx, const int *host_deg, int gap);
+
+/* Degrees of the elements of a level (HOST array of Ne ints). */
+fr_status fr_get_degrees(frpmg_ctx *ctx, int level, int *host_out);
+
+/* Spectral-decay smoothness indicator (Sec. 3.3): eta[k] = ||s_p - s_{p-1}||
+ * / ||s_p|| over element k of s = q_inf[var] + dq[var] (var = 1: rho u, the
+ * paper's default), where s_p is the element's polynomial and s_{p-1} keeps
+ * its Legendre modes of degree <= p - 1 in every direction (the tensor space
+ * one degree lower; the library's reading).  Every element needs degree >= 1.
+ * dq: padded state of the level; eta: Ne device doubles. */
+fr_status fr_pa_indicator(frpmg_ctx *ctx, int level, const double *dq, int var, double *eta, fr_stream stream);
+
+/* Degree update (Sec. 3.3): deg_out[k] = deg_in[k] + 1 where
+ * eta[k] > nu_max eta_max, - 1 where eta[k] < nu_min eta_max (eta_max = the
+ * largest eta), clipped to [p_min, p_max]; the paper takes nu_max = 0.2,
+ * nu_min = 0.001, p_min = 1.  Device arrays of Ne entries; deg_out may alias
+ * deg_in. */
+fr_status fr_pa_adapt(frpmg_ctx *ctx, const double *eta, const int *deg_in, int *deg_out, int p_min, int p_max,
+                      double nu_max, double nu_min, fr_stream stream);
+
+/* y = the state x carried element by element from the degree map deg_from
+ * (padded to degree p_from) to deg_to (padded to p_to) by L2 projection
+ * (exact when the degree rises).  Device arrays: deg_* Ne ints, x and y
+ * padded states, not aliased.  An element whose degree lies outside
+ * [0, p_from] or [0, p_to] gets NaN entries. */
+fr_status fr_pa_project(frpmg_ctx *ctx, const int *deg_from, int p_from, const double *x, const int *deg_to, int p_to,
+                        double *y, fr_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

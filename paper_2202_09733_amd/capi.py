@@ -37,7 +37,8 @@ EXPORTS = ["fr_create", "fr_destroy", "fr_last_error", "fr_level_size", "fr_resi
            "gmres_solve_stage", "fr_time_step", "fr_step_tableau", "lcc_harvest", "lcc_harvest_count", "lcc_train", "lcc_dims", "lcc_num_weights",
            "lcc_get_weights", "lcc_set_weights", "lcc_get_scales", "lcc_set_scales", "lcc_forward",
            "lcc_loss_grad", "lcc_features_of", "lcc_adam_step", "mbnk_factor", "mbnk_matvec", "mbnk_ilu_solve", "mbnk_solve",
-           "mbnk_get_blocks"]
+           "mbnk_get_blocks", "fr_pa_hierarchy", "fr_set_degrees", "fr_get_degrees", "fr_pa_indicator",
+           "fr_pa_adapt", "fr_pa_project"]
 
 
 class FRError(RuntimeError):
@@ -159,6 +160,12 @@ def load():
     L.fr_level_size.restype = ctypes.c_size_t
     L.fr_residual.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.fr_residual_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.fr_pa_hierarchy.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.fr_set_degrees.argtypes = [vp, vp, ctypes.c_int]
+    L.fr_get_degrees.argtypes = [vp, ctypes.c_int, vp]
+    L.fr_pa_indicator.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp]
+    L.fr_pa_adapt.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, dp, dp, vp]
+    L.fr_pa_project.argtypes = [vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp]
     L.fr_jvp.argtypes = [vp, ctypes.c_int, vp, vp, vp, dp, dp, ctypes.c_int, vp, vp]
     L.ej_factor.argtypes = [vp, ctypes.c_int, vp, dp, ctypes.c_int, vp]
     L.ej_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -228,6 +235,23 @@ def _ptr(t):
     assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), \
         "expected a contiguous float64 CUDA tensor"
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _iptr(t):
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32 and t.is_contiguous(), \
+        "expected a contiguous int32 CUDA tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def nested_degrees(deg, nlevels, gap):
+    """Per-element degrees of every p-sublevel, [nlevels][Ne] (fr_pa_hierarchy)."""
+    d = np.ascontiguousarray(np.asarray(deg, dtype=np.int32))
+    out = np.empty((nlevels, d.shape[0]), dtype=np.int32)
+    rc = load().fr_pa_hierarchy(d.ctypes.data, d.shape[0], int(nlevels), int(gap), out.ctypes.data)
+    if rc != FR_OK:
+        raise FRError("fr_pa_hierarchy", rc, "bad degrees, level count or gap")
+    return out
 
 
 def _fptr(t):
@@ -312,6 +336,15 @@ class FR:
         levels = [wl.p0, wl.p1] if levels is None else levels
         return cls(wl.dim, wl.n, wl.h, levels, wl.gamma, wl.mu, wl.Pr, wl.tau, wl.qinf, device=device)
 
+    @classmethod
+    def from_padapt(cls, wl, deg, nlevels=2, gap=2, device="cuda:0"):
+        """A context whose finest level has the degree map deg and whose
+        coarser levels the nested degrees (fr_set_degrees)."""
+        levels = [int(x) for x in nested_degrees(deg, nlevels, gap).max(axis=1)]
+        fr = cls(wl.dim, wl.n, wl.h, levels, wl.gamma, wl.mu, wl.Pr, wl.tau, wl.qinf, device=device)
+        fr.set_degrees(deg, gap)
+        return fr
+
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             self.lib.fr_destroy(self.ctx)
@@ -383,6 +416,41 @@ class FR:
     def prolong(self, frm, x, out=None):
         out = self.empty(frm - 1) if out is None else out
         self._check("pmg_prolong", self.lib.pmg_prolong(self.ctx, frm, frm - 1, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    def set_degrees(self, deg, gap=2):
+        if deg is None:
+            self._check("fr_set_degrees", self.lib.fr_set_degrees(self.ctx, None, int(gap)))
+            return
+        d = np.ascontiguousarray(np.asarray(deg, dtype=np.int32))
+        assert d.shape == (self.Ne,)
+        self._check("fr_set_degrees", self.lib.fr_set_degrees(self.ctx, d.ctypes.data, int(gap)))
+
+    def get_degrees(self, level):
+        out = np.empty(self.Ne, dtype=np.int32)
+        self._check("fr_get_degrees", self.lib.fr_get_degrees(self.ctx, level, out.ctypes.data))
+        return out
+
+    def pa_indicator(self, level, dq, var=1, out=None):
+        import torch
+        out = torch.empty(self.Ne, dtype=torch.float64, device=self.device) if out is None else out
+        self._check("fr_pa_indicator", self.lib.fr_pa_indicator(self.ctx, level, _ptr(dq), int(var), _ptr(out),
+                                                                _stream()))
+        return out
+
+    def pa_adapt(self, eta, deg_in, p_max, p_min=1, nu_max=0.2, nu_min=0.001, out=None):
+        import torch
+        out = torch.empty(self.Ne, dtype=torch.int32, device=self.device) if out is None else out
+        self._check("fr_pa_adapt", self.lib.fr_pa_adapt(self.ctx, _ptr(eta), _iptr(deg_in), _iptr(out), int(p_min),
+                                                        int(p_max), float(nu_max), float(nu_min), _stream()))
+        return out
+
+    def pa_project(self, deg_from, p_from, x, deg_to, p_to, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.nv, (p_to + 1) ** self.dim, self.Ne), dtype=torch.float64, device=self.device)
+        self._check("fr_pa_project", self.lib.fr_pa_project(self.ctx, _iptr(deg_from), int(p_from), _ptr(x),
+                                                            _iptr(deg_to), int(p_to), _ptr(out), _stream()))
         return out
 
     def pmg_set_point(self, dq, rq):

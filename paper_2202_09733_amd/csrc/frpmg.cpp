@@ -228,7 +228,12 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
         HIPCHK(hipMalloc(&p, nblk * sizeof(__bf16)));
         L.inv16 = (__bf16 *)p;
     }
-    ensure_face_save(ctx, L);
+    if (L.pa) {
+        for (int a = 0; a < ctx->dim; ++a)
+            REQUIRE(ctx->mesh.n[a] % 2 == 0, "EJ formation on a mixed-degree level needs even element counts");
+    } else {
+        ensure_face_save(ctx, L);
+    }
     ctx->graph_epoch++;  // captured steps bake in the factor buffers and precision
     HIPCHK(hipMemsetAsync(L.dstatus, 0, sizeof(int), s));
     HIPCHK(launch_ej_form(ctx, level, dq, sigma, s));
@@ -327,6 +332,7 @@ void mbnk_alloc(frpmg_ctx *ctx, int level) {
 void mbnk_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s) {
     REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
     Level &L = ctx->lv[level];
+    REQUIRE(!L.pa, "MBNK smoothing is not available on mixed-degree levels");
     REQUIRE(L.nb <= 128 && L.nb % 2 == 0, "MBNK takes element blocks of at most 128 unknowns");
     for (int a = 0; a < ctx->dim; ++a)
         REQUIRE(ctx->mesh.n[a] >= 4 && ctx->mesh.n[a] % 2 == 0,
@@ -408,6 +414,7 @@ void lcc_init_weights(frpmg_ctx *ctx, uint64_t seed) {
 void lcc_alloc(frpmg_ctx *ctx) {
     if (ctx->lcc) return;
     REQUIRE(ctx->nlevels > 1, "the learned correction needs two levels");
+    REQUIRE(!ctx->lv[0].pa, "the learned correction is not available on mixed-degree levels");
     Lcc *Lp = new Lcc();
     ctx->lcc = Lp;
     Lcc &L = *Lp;
@@ -1596,6 +1603,104 @@ void step_impl(frpmg_ctx *ctx, const step_params &SP, const double *dq_n, double
     if (status != FR_OK) fail_stage(ctx, status);
 }
 
+// ---------------------------------------------------------------------------
+// mixed polynomial degrees (p-adaptation, Sec. 3.3)
+// ---------------------------------------------------------------------------
+
+void pa_free_level(Level &L) {
+    if (!L.pa) return;
+    PaLevel &pa = *L.pa;
+    dfree(pa.Pk);
+    dfree(pa.cls);
+    dfree(pa.mixed);
+    dfree(pa.Fm);
+    dfree(pa.Mq);
+    dfree(pa.Mn);
+    dfree(pa.Mg);
+    dfree(pa.fdv);
+    dfree(pa.fdr);
+    delete L.pa;
+    L.pa = nullptr;
+}
+
+// Degrees of every element on each p-sublevel of a nested hierarchy (order
+// gap 1 or 2): each sublevel lowers the finest degree by the gap, keeps at
+// least as many degrees as sublevels remain below it, stays below the
+// sublevel above and stops at 0 (Sec. 3.3 lists the hierarchies this gives
+// for P4 down to P1 with three sublevels).
+void pa_nested(const int *deg, int ne, int nlev, int gap, int *out) {
+    for (int k = 0; k < ne; ++k) {
+        int prev = deg[k];
+        out[k] = prev;
+        for (int l = 1; l < nlev; ++l) {
+            int pl = std::min(prev - 1, std::max(deg[k] - gap * l, nlev - 1 - l));
+            pl = std::max(pl, 0);
+            out[(size_t)l * ne + k] = pl;
+            prev = pl;
+        }
+    }
+}
+
+void ensure_pa_tables(frpmg_ctx *ctx) {
+    if (ctx->pa_tab) return;
+    ctx->pa_tab_host = new PaTables();
+    build_pa_tables(*ctx->pa_tab_host);
+    void *p = nullptr;
+    HIPCHK(hipMalloc(&p, sizeof(PaTables)));
+    ctx->pa_tab = (PaTables *)p;
+    HIPCHK(hipMemcpy(ctx->pa_tab, ctx->pa_tab_host, sizeof(PaTables), hipMemcpyHostToDevice));
+}
+
+void pa_build_level(frpmg_ctx *ctx, int l, const int *deg) {
+    Level &L = ctx->lv[l];
+    const MeshK &m = ctx->mesh;
+    const int Ne = m.Ne;
+    pa_free_level(L);
+    L.pa = new PaLevel();
+    PaLevel &pa = *L.pa;
+    pa.Pk_host.resize(Ne);
+    std::vector<int> cls;
+    cls.reserve(Ne);
+    for (int P = 1; P <= kMaxP; ++P) {
+        pa.cls_off[P] = (int)cls.size();
+        for (int k = 0; k < Ne; ++k)
+            if (deg[k] + 1 == P) cls.push_back(k);
+    }
+    pa.cls_off[kMaxP + 1] = (int)cls.size();
+    std::vector<int> mixed;
+    for (int k = 0; k < Ne; ++k) {
+        pa.Pk_host[k] = deg[k] + 1;
+        int c[3] = {k % m.n[0], (k / m.n[0]) % m.n[1], (ctx->dim == 3) ? k / (m.n[0] * m.n[1]) : 0};
+        for (int a = 0; a < ctx->dim; ++a) {
+            int d[3] = {c[0], c[1], c[2]};
+            d[a] = (d[a] + 1) % m.n[a];
+            const int kn = d[0] + m.n[0] * (d[1] + m.n[1] * d[2]);
+            if (deg[kn] != deg[k]) mixed.push_back(k * 4 + a);
+        }
+    }
+    pa.nmixed = (int)mixed.size();
+    void *p = nullptr;
+    HIPCHK(hipMalloc(&p, (size_t)Ne * sizeof(int)));
+    pa.Pk = (int *)p;
+    HIPCHK(hipMemcpy(pa.Pk, pa.Pk_host.data(), (size_t)Ne * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&p, (size_t)Ne * sizeof(int)));
+    pa.cls = (int *)p;
+    HIPCHK(hipMemcpy(pa.cls, cls.data(), (size_t)Ne * sizeof(int), hipMemcpyHostToDevice));
+    if (pa.nmixed > 0) {
+        HIPCHK(hipMalloc(&p, (size_t)pa.nmixed * sizeof(int)));
+        pa.mixed = (int *)p;
+        HIPCHK(hipMemcpy(pa.mixed, mixed.data(), (size_t)pa.nmixed * sizeof(int), hipMemcpyHostToDevice));
+    }
+    const size_t nface = (size_t)ctx->dim * ctx->nv * L.NF * Ne;
+    pa.Fm = dalloc(ctx, nface);
+    pa.Mq = dalloc(ctx, nface);
+    pa.Mn = dalloc(ctx, nface);
+    pa.Mg = dalloc(ctx, nface * ctx->dim);
+    pa.fdv = dalloc(ctx, L.N);
+    pa.fdr = dalloc(ctx, L.N);
+    HIPCHK(hipMemset(pa.fdv, 0, L.N * sizeof(double)));
+}
+
 void destroy_all(frpmg_ctx *ctx) {
     clear_graphs(ctx);
     for (auto &e : ctx->ph_ev) {
@@ -1606,6 +1711,10 @@ void destroy_all(frpmg_ctx *ctx) {
     ctx->cap_stream = nullptr;
     lcc_free(ctx);
     mbnk_free(ctx);
+    for (int l = 0; l < FR_MAX_LEVELS; ++l) pa_free_level(ctx->lv[l]);
+    dfree(ctx->pa_tab);
+    delete ctx->pa_tab_host;
+    ctx->pa_tab_host = nullptr;
     for (int l = 0; l < FR_MAX_LEVELS; ++l) {
         Level &L = ctx->lv[l];
         dfree(L.Jp);
@@ -1798,6 +1907,7 @@ fr_status fr_residual_noalloc(frpmg_ctx *ctx, int level, const double *dq, doubl
         REQUIRE(dq && r && dq != r, "bad pointers");
         REQUIRE(ctx->noalloc_scratch, "no scratch address for this device");
         const Level &L = ctx->lv[level];
+        REQUIRE(!L.pa, "fr_residual_noalloc takes uniform-degree levels");
         // common fluxes, then state jumps, each [dim][nv][NF][Ne], the second 256-byte aligned
         const size_t nface = ((size_t)ctx->dim * ctx->nv * L.NF * ctx->mesh.Ne + 31) / 32 * 32;
         if (2 * nface * sizeof(double) > kNoallocBytes) {
@@ -2255,6 +2365,95 @@ fr_status lcc_train(frpmg_ctx *ctx, const lcc_train_params *prm, lcc_train_stats
         L.weights_set = 1;
         HIPCHK(hipStreamSynchronize(s));
         out->t_train = now() - t0;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// mixed polynomial degrees (p-adaptation)
+// ---------------------------------------------------------------------------
+
+fr_status fr_pa_hierarchy(const int *deg, int ne, int nlevels, int gap, int *out) {
+    if (!deg || !out || ne < 1 || nlevels < 1 || nlevels > FR_MAX_LEVELS || (gap != 1 && gap != 2)) return FR_EINVAL;
+    for (int k = 0; k < ne; ++k)
+        if (deg[k] < 0 || deg[k] >= kMaxP) return FR_EINVAL;
+    pa_nested(deg, ne, nlevels, gap, out);
+    return FR_OK;
+}
+
+fr_status fr_set_degrees(frpmg_ctx *ctx, const int *host_deg, int gap) {
+    return guarded(ctx, [&] {
+        HIPCHK(hipDeviceSynchronize());
+        clear_graphs(ctx);
+        ctx->graph_epoch++;
+        for (int l = 0; l < ctx->nlevels; ++l) {
+            pa_free_level(ctx->lv[l]);
+            ctx->lv[l].inv_prec = -1;
+        }
+        if (!host_deg) return;
+        REQUIRE(gap == 1 || gap == 2, "order gap must be 1 or 2");
+        REQUIRE(!ctx->mb, "MBNK smoothing is set up on this context");
+        const int Ne = ctx->mesh.Ne;
+        std::vector<int> deg((size_t)ctx->nlevels * Ne);
+        for (int k = 0; k < Ne; ++k)
+            REQUIRE(host_deg[k] >= 0 && host_deg[k] <= ctx->lv[0].p, "element degree outside [0, p of level 0]");
+        pa_nested(host_deg, Ne, ctx->nlevels, gap, deg.data());
+        for (int l = 0; l < ctx->nlevels; ++l) {
+            const int mx = *std::max_element(deg.begin() + (size_t)l * Ne, deg.begin() + (size_t)(l + 1) * Ne);
+            if (mx != ctx->lv[l].p) {
+                char msg[160];
+                std::snprintf(msg, sizeof msg,
+                              "level %d of the nested hierarchy has largest degree %d but the context has p = %d", l, mx,
+                              ctx->lv[l].p);
+                ctx->err = msg;
+                throw Fail{FR_EINVAL};
+            }
+        }
+        ensure_pa_tables(ctx);
+        for (int l = 0; l < ctx->nlevels; ++l) pa_build_level(ctx, l, deg.data() + (size_t)l * Ne);
+        HIPCHK(hipDeviceSynchronize());
+    });
+}
+
+fr_status fr_get_degrees(frpmg_ctx *ctx, int level, int *host_out) {
+    return guarded(ctx, [&] {
+        REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
+        REQUIRE(host_out, "bad pointer");
+        const Level &L = ctx->lv[level];
+        for (int k = 0; k < ctx->mesh.Ne; ++k) host_out[k] = L.pa ? L.pa->Pk_host[k] - 1 : L.p;
+    });
+}
+
+fr_status fr_pa_indicator(frpmg_ctx *ctx, int level, const double *dq, int var, double *eta, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
+        REQUIRE(dq && eta, "bad pointers");
+        REQUIRE(var >= 0 && var < ctx->nv, "bad variable");
+        const Level &L = ctx->lv[level];
+        REQUIRE(L.pa, "the level has no degree map (fr_set_degrees)");
+        for (int k = 0; k < ctx->mesh.Ne; ++k) REQUIRE(L.pa->Pk_host[k] >= 2, "the indicator needs degree >= 1");
+        HIPCHK(pa_indicator(ctx, level, dq, var, eta, S(stream)));
+    });
+}
+
+fr_status fr_pa_adapt(frpmg_ctx *ctx, const double *eta, const int *deg_in, int *deg_out, int p_min, int p_max,
+                      double nu_max, double nu_min, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(eta && deg_in && deg_out, "bad pointers");
+        REQUIRE(p_min >= 0 && p_min <= p_max && p_max <= (ctx->dim == 2 ? 4 : 3), "bad degree range");
+        REQUIRE(nu_min >= 0.0 && nu_min <= nu_max, "bad thresholds");
+        HIPCHK(pa_adapt(ctx, eta, deg_in, deg_out, p_min, p_max, nu_max, nu_min, S(stream)));
+    });
+}
+
+fr_status fr_pa_project(frpmg_ctx *ctx, const int *deg_from, int p_from, const double *x, const int *deg_to,
+                        int p_to, double *y, fr_stream stream) {
+    return guarded(ctx, [&] {
+        REQUIRE(deg_from && deg_to && x && y && x != y, "bad pointers");
+        const int pmax = ctx->dim == 2 ? 4 : 3;
+        REQUIRE(p_from >= 0 && p_from <= pmax && p_to >= 0 && p_to <= pmax, "bad padded degree");
+        ensure_pa_tables(ctx);
+        const int NpF = ipow(p_from + 1, ctx->dim), NpT = ipow(p_to + 1, ctx->dim);
+        HIPCHK(pa_project(ctx, deg_from, NpF, x, deg_to, NpT, y, S(stream)));
     });
 }
 

@@ -294,8 +294,8 @@ hipError_t launch_ej_form_pa(const frpmg_ctx *ctx, int level, const double *dq, 
                              double *out);
 hipError_t pa_transfer(const frpmg_ctx *ctx, int from, int to, const double *x, double *y, const double *x0,
                        bool accumulate, const double *x2, double *y2, hipStream_t s);
-hipError_t pa_project(const frpmg_ctx *ctx, const int *Pfrom, int NpF, const double *x, const int *Pto, int NpT,
-                      double *y, hipStream_t s);
+hipError_t pa_project(const frpmg_ctx *ctx, const int *deg_from, int NpF, const double *x, const int *deg_to,
+                      int NpT, double *y, hipStream_t s);
 hipError_t pa_indicator(const frpmg_ctx *ctx, int level, const double *dq, int var, double *eta, hipStream_t s);
 hipError_t pa_adapt(const frpmg_ctx *ctx, const double *eta, const int *deg_in, int *deg_out, int p_min, int p_max,
                     double nu_max, double nu_min, hipStream_t s);

@@ -143,4 +143,40 @@ void build_transfer(int P0, int P1, Transfer1D &t) {
     }
 }
 
+void build_pa_tables(PaTables &t) {
+    t = PaTables{};
+    for (int P = 1; P <= kMaxP; ++P) build_ops1d(P, t.ops[P]);
+    // 1D L2 projection from the Pa-point to the Pb-point polynomial space:
+    // truncation of the Legendre expansion for Pb < Pa, exact interpolation
+    // for Pb > Pa, the identity for Pb = Pa
+    for (int Pa = 1; Pa <= kMaxP; ++Pa)
+        for (int Pb = 1; Pb <= kMaxP; ++Pb) {
+            if (Pa == Pb) {
+                for (int i = 0; i < Pa; ++i) t.proj[Pa][Pb][i][i] = 1.0;
+            } else if (Pb < Pa) {
+                Transfer1D tr;
+                build_transfer(Pa, Pb, tr);
+                for (int b = 0; b < Pb; ++b)
+                    for (int a = 0; a < Pa; ++a) t.proj[Pa][Pb][b][a] = tr.G[b][a];
+            } else {
+                Transfer1D tr;
+                build_transfer(Pb, Pa, tr);
+                for (int b = 0; b < Pb; ++b)
+                    for (int a = 0; a < Pa; ++a) t.proj[Pa][Pb][b][a] = tr.Pi[b][a];
+            }
+        }
+    // Legendre coefficients of the P-point interpolant: c_n = (2n+1)/2 sum_i w_i L_n(x_i) s_i
+    // (Gauss-Legendre with P points integrates L_n s, degree <= 2P - 2, exactly)
+    for (int P = 1; P <= kMaxP; ++P) {
+        double x[kMaxP], w[kMaxP];
+        gauss_legendre(P, x, w);
+        for (int n = 0; n < P; ++n)
+            for (int i = 0; i < P; ++i) {
+                double L, dL;
+                legendre_pair(n, x[i], L, dL);
+                t.modal[P][n][i] = (2.0 * n + 1.0) * 0.5 * w[i] * L;
+            }
+    }
+}
+
 }  // namespace frpmg

@@ -845,10 +845,571 @@ hipError_t form(const frpmg_ctx *ctx, const Level &L, const double *dq, double s
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// mixed polynomial degrees (p-adaptation, Sec. 3.3)
+// ---------------------------------------------------------------------------
+//
+// Element k has P_k points per direction; states are padded to the level's
+// largest P (point stride NpM) and face arrays to its NFM points per face.
+// The elements of each point count form a class, launched with that count as
+// a compile-time constant (element ids from a list, so every wavefront runs
+// one degree).  A face between elements of equal degree is treated exactly as
+// in the uniform kernels.  At a face between different degrees, the common
+// solution seen from the -axis element is the L2 projection of the +axis
+// element's trace onto its face points (exact interpolation when the -axis
+// side has the larger degree); the common flux is formed at the points of the
+// larger degree (the mortar) from both traces and the -axis element's
+// gradient trace projected there, and is returned to both sides by L2
+// projection, which keeps its integral over the face (k_pa_mortar).
+
+constexpr int kMaxNF3 = 16;  // face points of a 3D element (p <= 3)
+
+struct PaK {
+    const int *Pk;         // points per direction of every element
+    const int *list;       // element ids of the launched class
+    int count;             // elements in the list
+    int NpM, NFM;          // padded points per element / per face
+    const PaTables *tab;   // operators of every degree
+    double *Fm;            // common flux on - faces [dim][nv][NFM][Ne]
+    double *Mq, *Mn, *Mg;  // mortar inputs, on the + face of the -axis element
+};
+
+// local point on the line along axis a through face point f, position j (P at run time)
+__device__ __forceinline__ int line_rt(int dim, int P, int a, int f, int j) {
+    if (a == 0) return j + P * f;
+    if (dim == 2) return f + P * j;
+    if (a == 1) return (f % P) + P * (j + P * (f / P));
+    return f + P * P * j;
+}
+
+// value at face point fb (Pb points per direction) of the L2 projection of the
+// face function x (Pa points per direction, entry fa at x[fa * xs]): the tensor
+// product of the 1D projections over the face's dim - 1 directions
+__device__ __forceinline__ double face_map_pt(const PaTables *tab, int dim, int Pa, int Pb, int fb,
+                                              const double *x, size_t xs) {
+    const int b0 = fb % Pb, b1 = fb / Pb;
+    const int nfa = (dim == 2) ? Pa : Pa * Pa;
+    double s = 0.0;
+    for (int fa = 0; fa < nfa; ++fa) {
+        const int a0 = fa % Pa, a1 = fa / Pa;
+        double c = tab->proj[Pa][Pb][b0][a0];
+        if (dim == 3) c *= tab->proj[Pa][Pb][b1][a1];
+        s += c * x[(size_t)fa * xs];
+    }
+    return s;
+}
+
+// One + face point of a class-P element: the state jump and, at a face of
+// equal degrees, the common flux (written for both elements); at a face of
+// different degrees, the mortar inputs.
+template <int DIM, int P, int A, int EB>
+__device__ __forceinline__ void pa_face_flux(const MeshK &m, const Ops1D &ops, const Phys &ph, const PaK &pk,
+                                             const double *s_u, const double *s_t, const double *s_qp,
+                                             const double *s_ih, int e, int f, int k, int kn, int pn,
+                                             double *__restrict__ Fs, double *__restrict__ Jp) {
+    constexpr int NV = DIM + 2;
+    double qL[NV], qR[NV], g[DIM][NV], Sn[NV], F[NV];
+    plus_face_state<DIM, P, A, EB, EB>(ops, s_u, s_t, s_qp, s_ih, e, f, qL, qR, g, Sn);
+    const size_t Ne = (size_t)m.Ne;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Jp[((size_t)(A * NV + v) * pk.NFM + f) * Ne + k] = qR[v] - qL[v];
+    if (pn == P) {
+        common_flux<DIM, A>(ph, qL, qR, g, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t o = ((size_t)(A * NV + v) * pk.NFM + f) * Ne;
+            Fs[o + k] = F[v];
+            pk.Fm[o + kn] = F[v];
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            pk.Mq[((size_t)(A * NV + v) * pk.NFM + f) * Ne + k] = qL[v];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+                pk.Mg[(((size_t)(A * DIM + c) * NV + v) * pk.NFM + f) * Ne + k] = g[c][v];
+        }
+    }
+}
+
+// + faces of the class-P elements (one lane per face point, as k_faces).
+template <int DIM, int P, int MODE>
+__global__ void __launch_bounds__((Shape<DIM, P>::NTF)) k_pa_faces(MeshK m, SrcK src, Ops1D ops_in, Phys ph, PaK pk,
+                                                                double *__restrict__ Jp, double *__restrict__ Fs) {
+    using S = Shape<DIM, P>;
+    constexpr int EB = S::EBF, NV = S::NV, NP = S::NP, NF = S::NF;
+    constexpr int NFACE = DIM * NV * NF * EB;
+    constexpr int NFN = (DIM == 2) ? kMaxP : kMaxNF3;  // a neighbour's face points, at most
+    __shared__ Ops1D ops;
+    __shared__ double s_u[NV * NP * EB];
+    __shared__ double s_tn[DIM * NV * NFN * EB];  // + neighbours' minus traces at their own points
+    __shared__ double s_t[NFACE];                 // q* on the + faces at own points
+    __shared__ double s_qp[NFACE];                // own + traces
+    __shared__ double s_ih[DIM * EB];
+    __shared__ int s_k[EB], s_kn[DIM * EB], s_pn[DIM * EB];
+    if (threadIdx.x == 0) ops = ops_in;
+    const int b0 = xcd_block(blockIdx.x, gridDim.x) * EB;
+    const int ne = min(EB, pk.count - b0);
+    const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
+    for (int t = threadIdx.x; t < EB; t += blockDim.x) s_k[t] = (t < ne) ? pk.list[b0 + t] : 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < DIM * EB; t += blockDim.x) {
+        const int e = t % EB, a = t / EB;
+        int kn = 0, pn = P;
+        double ih = 0.0;
+        if (e < ne) {
+            const int k = s_k[e];
+            kn = neighbour(m, k, a, +1);
+            pn = pk.Pk[kn];
+            int c[3];
+            coords(m, k, c);
+            ih = m.inv2h[a][c[a]];
+        }
+        s_kn[t] = kn;
+        s_pn[t] = pn;
+        s_ih[t] = ih;
+    }
+    for (int t = threadIdx.x; t < NV * NP * EB; t += blockDim.x) {
+        const int e = t % EB, vi = t / EB;
+        s_u[t] = (e < ne) ? load_state<MODE>(src, m, vi / NP, vi % NP, s_k[e], alpha) : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < DIM * NV * NFN * EB; t += blockDim.x) {
+        const int e = t % EB;
+        int r = t / EB;
+        const int f = r % NFN;
+        r /= NFN;
+        const int v = r % NV, a = r / NV;
+        const int pn = s_pn[a * EB + e];
+        double val = 0.0;
+        if (e < ne && f < ((DIM == 2) ? pn : pn * pn)) {
+            const int kn = s_kn[a * EB + e];
+            if (pn == P) {
+#pragma unroll
+                for (int j = 0; j < P; ++j) val += ops.bm[j] * load_state<MODE>(src, m, v, S::line(a, f, j), kn, alpha);
+            } else {
+                const double *bmn = pk.tab->ops[pn].bm;
+                for (int j = 0; j < pn; ++j)
+                    val += bmn[j] * load_state<MODE>(src, m, v, line_rt(DIM, pn, a, f, j), kn, alpha);
+            }
+        }
+        s_tn[t] = val;
+    }
+    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
+        const int e = t % EB;
+        int r = t / EB;
+        const int f = r % NF;
+        r /= NF;
+        const int v = r % NV, a = r / NV;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) s += ops.bp[j] * s_u[(v * NP + S::line(a, f, j)) * EB + e];
+        s_qp[t] = s;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
+        const int e = t % EB;
+        int r = t / EB;
+        const int f = r % NF;
+        r /= NF;
+        const int v = r % NV, a = r / NV;
+        const int pn = s_pn[a * EB + e];
+        const double *tn = &s_tn[(a * NV + v) * NFN * EB + e];
+        s_t[t] = (pn == P) ? tn[f * EB] : face_map_pt(pk.tab, DIM, pn, P, f, tn, EB);
+    }
+    // mixed faces: the neighbour's trace at its own points, for the mortar
+    for (int t = threadIdx.x; t < DIM * NV * NFN * EB; t += blockDim.x) {
+        const int e = t % EB;
+        int r = t / EB;
+        const int f = r % NFN;
+        r /= NFN;
+        const int v = r % NV, a = r / NV;
+        const int pn = s_pn[a * EB + e];
+        if (e < ne && pn != P && f < ((DIM == 2) ? pn : pn * pn))
+            pk.Mn[((size_t)(a * NV + v) * pk.NFM + f) * m.Ne + s_k[e]] = s_tn[t];
+    }
+    __syncthreads();
+    const int a = __builtin_amdgcn_readfirstlane((int)threadIdx.x / S::LPA);
+    const int rest = threadIdx.x % S::LPA;
+    const int e = rest % EB, f = rest / EB;
+    if (rest >= NF * EB || e >= ne) return;
+    const int k = s_k[e], kn = s_kn[a * EB + e], pn = s_pn[a * EB + e];
+    if (a == 0) {
+        pa_face_flux<DIM, P, 0, EB>(m, ops, ph, pk, s_u, s_t, s_qp, s_ih, e, f, k, kn, pn, Fs, Jp);
+    } else if (a == 1) {
+        pa_face_flux<DIM, P, 1, EB>(m, ops, ph, pk, s_u, s_t, s_qp, s_ih, e, f, k, kn, pn, Fs, Jp);
+    } else {
+        if constexpr (DIM == 3) pa_face_flux<DIM, P, 2, EB>(m, ops, ph, pk, s_u, s_t, s_qp, s_ih, e, f, k, kn, pn, Fs, Jp);
+    }
+}
+
+// The common flux on faces between elements of different degree: one lane
+// per mortar point forms it from the mortar inputs projected there, then the
+// lanes project it back onto the -axis element's + face (Fs) and the +axis
+// element's - face (Fm).
+template <int DIM>
+__global__ void __launch_bounds__(64) k_pa_mortar(MeshK m, Phys ph, PaK pk, const int *__restrict__ faces,
+                                                  int nfaces, double *__restrict__ Fs) {
+    constexpr int NV = DIM + 2;
+    constexpr int NFMM = (DIM == 2) ? kMaxP : kMaxNF3;
+    constexpr int FB = 64 / NFMM;
+    __shared__ double sF[FB][NV][NFMM];
+    const int slot = threadIdx.x / NFMM, fm = threadIdx.x % NFMM;
+    const int fi = blockIdx.x * FB + slot;
+    const bool act = slot < FB && fi < nfaces;
+    int k = 0, a = 0, kn = 0, Pk = 1, Pn = 1, Pm = 1;
+    if (act) {
+        const int code = faces[fi];
+        k = code >> 2;
+        a = code & 3;
+        kn = neighbour(m, k, a, +1);
+        Pk = pk.Pk[k];
+        Pn = pk.Pk[kn];
+        Pm = max(Pk, Pn);
+    }
+    const size_t Ne = (size_t)m.Ne;
+    if (act && fm < ((DIM == 2) ? Pm : Pm * Pm)) {
+        double qL[NV], qR[NV], g[DIM][NV], F[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double *xq = pk.Mq + ((size_t)(a * NV + v) * pk.NFM) * Ne + k;
+            const double *xn = pk.Mn + ((size_t)(a * NV + v) * pk.NFM) * Ne + k;
+            qL[v] = (Pk == Pm) ? xq[fm * Ne] : face_map_pt(pk.tab, DIM, Pk, Pm, fm, xq, Ne);
+            qR[v] = (Pn == Pm) ? xn[fm * Ne] : face_map_pt(pk.tab, DIM, Pn, Pm, fm, xn, Ne);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const double *xg = pk.Mg + (((size_t)(a * DIM + c) * NV + v) * pk.NFM) * Ne + k;
+                g[c][v] = (Pk == Pm) ? xg[fm * Ne] : face_map_pt(pk.tab, DIM, Pk, Pm, fm, xg, Ne);
+            }
+        }
+        if (a == 0) {
+            common_flux<DIM, 0>(ph, qL, qR, g, F);
+        } else if (a == 1) {
+            common_flux<DIM, 1>(ph, qL, qR, g, F);
+        } else {
+            if constexpr (DIM == 3) common_flux<DIM, 2>(ph, qL, qR, g, F);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sF[slot][v][fm] = F[v];
+    }
+    __syncthreads();
+    if (!act) return;
+    const int nfk = (DIM == 2) ? Pk : Pk * Pk, nfn = (DIM == 2) ? Pn : Pn * Pn;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const size_t o = ((size_t)(a * NV + v) * pk.NFM + fm) * Ne;
+        if (fm < nfk)
+            Fs[o + k] = (Pk == Pm) ? sF[slot][v][fm] : face_map_pt(pk.tab, DIM, Pm, Pk, fm, &sF[slot][v][0], 1);
+        if (fm < nfn)
+            pk.Fm[o + kn] = (Pn == Pm) ? sF[slot][v][fm] : face_map_pt(pk.tab, DIM, Pm, Pn, fm, &sF[slot][v][0], 1);
+    }
+}
+
+// Divergence of the class-P elements (k_volume with element ids from the
+// list, padded strides and the - face fluxes from Fm); writes the padding
+// entries of the output too.
+template <int DIM, int P, int MODE, int OUT>
+__global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_pa_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, PaK pk,
+                                                                const double *__restrict__ Jp,
+                                                                const double *__restrict__ Fs, OutK o) {
+    using S = Shape<DIM, P>;
+    constexpr int EB = S::EB, NV = S::NV, NP = S::NP, NF = S::NF;
+    constexpr int NFACE = DIM * NV * NF * EB;
+    __shared__ Ops1D ops;
+    __shared__ double s_u[NV * NP * EB];
+    __shared__ double s_t[NFACE];
+    __shared__ double s_fm[NFACE];
+    __shared__ double s_fp[NFACE];
+    __shared__ double s_ih[DIM * EB];
+    __shared__ int s_k[EB];
+    if (threadIdx.x == 0) ops = ops_in;
+    const int b0 = xcd_block(blockIdx.x, gridDim.x) * EB;
+    const int ne = min(EB, pk.count - b0);
+    const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
+    const size_t Ne = (size_t)m.Ne;
+    for (int t = threadIdx.x; t < EB; t += blockDim.x) s_k[t] = (t < ne) ? pk.list[b0 + t] : 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < NV * NP * EB; t += blockDim.x) {
+        const int e = t % EB, vi = t / EB;
+        s_u[t] = (e < ne) ? load_state<MODE>(src, m, vi / NP, vi % NP, s_k[e], alpha) : 0.0;
+    }
+    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
+        const int e = t % EB;
+        const int r = t / EB;  // (a * NV + v) * NF + f
+        double vt = 0.0, vp = 0.0, vm = 0.0;
+        if (e < ne) {
+            const size_t idx = ((size_t)(r / NF) * pk.NFM + r % NF) * Ne + s_k[e];
+            vt = Jp[idx];
+            vp = Fs[idx];
+            vm = pk.Fm[idx];
+        }
+        s_t[t] = vt;
+        s_fp[t] = vp;
+        s_fm[t] = vm;
+    }
+    for (int t = threadIdx.x; t < DIM * EB; t += blockDim.x) {
+        const int e = t % EB, a = t / EB;
+        double val = 0.0;
+        if (e < ne) {
+            int c[3];
+            coords(m, s_k[e], c);
+            val = m.inv2h[a][c[a]];
+        }
+        s_ih[t] = val;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int e = t % EB, i = t / EB;
+    const bool active = (t < NP * EB) && (e < ne);
+    double acc[NV];
+    divergence<DIM, P, EB, EB>(ops, ph, s_u, s_t, s_fm, s_fp, s_ih, active, e, i, acc);
+    // the padding entries (R = 0 there)
+    const int npad = pk.NpM - NP;
+    for (int u = threadIdx.x; u < NV * npad * EB; u += blockDim.x) {
+        const int e2 = u % EB, r = u / EB;
+        if (e2 >= ne) continue;
+        const int v = r / npad, i2 = NP + r % npad;
+        const size_t idx = ((size_t)v * pk.NpM + i2) * Ne + s_k[e2];
+        if (OUT == OUT_R) {
+            o.r[idx] = 0.0;
+        } else {
+            double val = o.sigma * o.vdir[idx] - (0.0 - o.r0[idx]) / (alpha * o.dscale);
+            if (o.x) val -= o.x[idx];
+            o.r[idx] = val;
+        }
+    }
+    if (!active) return;
+    const int k = s_k[e];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double R = -acc[v];
+        const size_t idx = ((size_t)v * pk.NpM + i) * Ne + k;
+        if (OUT == OUT_R) {
+            o.r[idx] = R;
+        } else {
+            double val = o.sigma * o.vdir[idx] - (R - o.r0[idx]) / (alpha * o.dscale);
+            if (o.x) val -= o.x[idx];
+            o.r[idx] = val;
+        }
+    }
+}
+
+// ---- EJ blocks of a mixed-degree level by coloured one-sided differences --
+
+__global__ void k_pa_blk_identity(size_t total, int nb, double *__restrict__ B) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t nn = (size_t)nb * nb;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const size_t w = t % nn;
+        B[t] = (w / nb == w % nb) ? 1.0 : 0.0;
+    }
+}
+
+__device__ __forceinline__ int elem_colour(const MeshK &m, int k) {
+    int c[3];
+    coords(m, k, c);
+    return (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
+}
+
+// v[j][k] = the step of entry j of every element k of the colour that has it
+// (set), or 0 (clear)
+__global__ void k_pa_fd_set(MeshK m, const int *__restrict__ Pk, int colour, int j, int NpM, Phys ph,
+                            const double *__restrict__ dq, double *__restrict__ v, int set) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m.Ne || elem_colour(m, k) != colour) return;
+    const int P = Pk[k];
+    const int np = (m.dim == 2) ? P * P : P * P * P;
+    if (j % NpM >= np) return;
+    const size_t idx = (size_t)j * m.Ne + k;
+    v[idx] = set ? fd_step(ph.qinf[j / NpM], dq[idx]) : 0.0;
+}
+
+// column j of B_k = sigma e_j - (R_k(q + h e_j) - R_k(q)) / h on the valid rows
+__global__ void k_pa_fd_extract(MeshK m, const int *__restrict__ Pk, int colour, int j, int NpM, int nb,
+                                const double *__restrict__ dq, const double *__restrict__ v,
+                                const double *__restrict__ rp, const double *__restrict__ r0, double sigma,
+                                double *__restrict__ B) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)m.Ne * nb) return;
+    const int k = (int)(t % m.Ne), row = (int)(t / m.Ne);
+    if (elem_colour(m, k) != colour) return;
+    const int P = Pk[k];
+    const int np = (m.dim == 2) ? P * P : P * P * P;
+    if (j % NpM >= np || row % NpM >= np) return;
+    const size_t jc = (size_t)j * m.Ne + k;
+    const double base = dq[jc];
+    const double hact = (base + v[jc]) - base;
+    const size_t idx = (size_t)row * m.Ne + k;
+    double val = -(rp[idx] - r0[idx]) / hact;
+    if (row == j) val += sigma;
+    B[(size_t)k * nb * nb + (size_t)j * nb + row] = val;
+}
+
+// ---- per-element transfers, indicator and degree update ------------------
+
+// y (=, or += when acc) the per-element L2 projection of x - x0 (x0 optional)
+// from Pf[k] + dP to Pt[k] + dP points per direction (dP = 1: degree maps); y2 likewise from x2 (optional).
+// One lane per output entry; padding of y is zeroed unless accumulating.
+__global__ void k_pa_transfer(int dim, int nv, int Ne, const int *__restrict__ Pf, int NpF, const int *__restrict__ Pt,
+                              int NpT, int dP, const PaTables *__restrict__ tab, const double *__restrict__ x,
+                              const double *__restrict__ x0, double *__restrict__ y, int acc,
+                              const double *__restrict__ x2, double *__restrict__ y2) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)nv * NpT * Ne) return;
+    const int k = (int)(t % Ne);
+    const int r = (int)(t / Ne);
+    const int v = r / NpT, i = r % NpT;
+    const int pf = Pf[k] + dP, pt = Pt[k] + dP;
+    const int nf = (dim == 2) ? pf * pf : pf * pf * pf, nt = (dim == 2) ? pt * pt : pt * pt * pt;
+    if (pf < 1 || pt < 1 || nf > NpF || nt > NpT) {  // a degree beyond the padded layout: no value
+        y[t] = __builtin_nan("");
+        if (y2) y2[t] = __builtin_nan("");
+        return;
+    }
+    if (i >= nt) {
+        if (!acc) {
+            y[t] = 0.0;
+            if (y2) y2[t] = 0.0;
+        }
+        return;
+    }
+    const size_t xb = (size_t)v * NpF * Ne + k;
+    double s = 0.0, s2 = 0.0;
+    if (pf == pt) {
+        s = x[xb + (size_t)i * Ne] - (x0 ? x0[xb + (size_t)i * Ne] : 0.0);
+        if (x2) s2 = x2[xb + (size_t)i * Ne];
+    } else {
+        const int b0 = i % pt, b1 = (i / pt) % pt, b2 = i / (pt * pt);
+        for (int i2 = 0; i2 < nf; ++i2) {
+            const int a0 = i2 % pf, a1 = (i2 / pf) % pf, a2 = i2 / (pf * pf);
+            double c = tab->proj[pf][pt][b0][a0] * tab->proj[pf][pt][b1][a1];
+            if (dim == 3) c *= tab->proj[pf][pt][b2][a2];
+            const size_t xi = xb + (size_t)i2 * Ne;
+            s += c * (x[xi] - (x0 ? x0[xi] : 0.0));
+            if (x2) s2 += c * x2[xi];
+        }
+    }
+    y[t] = acc ? y[t] + s : s;
+    if (x2) y2[t] = s2;
+}
+
+// eta_k = ||s_p - s_{p-1}|| / ||s_p|| of s = q_inf[var] + dq[var]: the energy
+// of the Legendre modes whose largest index is p over that of all modes (the
+// element's Jacobian cancels).  One lane per element.
+__global__ void k_pa_indicator(int dim, int Ne, const int *__restrict__ Pk, int NpM, const PaTables *__restrict__ tab,
+                               double qv, const double *__restrict__ s, double *__restrict__ eta) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Ne) return;
+    const int P = Pk[k];
+    double u[kMaxNF3 * 4], w[kMaxNF3 * 4];  // 2D: P^2 <= 25; 3D: P^3 <= 64 (p <= 3)
+    const int np = (dim == 2) ? P * P : P * P * P;
+    for (int i = 0; i < np; ++i) u[i] = qv + s[(size_t)i * Ne + k];
+    // modal coefficients, one direction at a time
+    const double(*M)[kMaxP] = tab->modal[P];
+    const int stride[3] = {1, P, P * P};
+    for (int d = 0; d < dim; ++d) {
+        const int st = stride[d];
+        for (int i = 0; i < np; ++i) {
+            const int id = (i / st) % P, base = i - id * st;
+            double acc = 0.0;
+            for (int j = 0; j < P; ++j) acc += M[id][j] * u[base + j * st];
+            w[i] = acc;
+        }
+        for (int i = 0; i < np; ++i) u[i] = w[i];
+    }
+    double e_all = 0.0, e_top = 0.0;
+    for (int i = 0; i < np; ++i) {
+        const int n0 = i % P, n1 = (i / P) % P, n2 = (dim == 3) ? i / (P * P) : 0;
+        double nrm = (2.0 / (2.0 * n0 + 1.0)) * (2.0 / (2.0 * n1 + 1.0));
+        if (dim == 3) nrm *= 2.0 / (2.0 * n2 + 1.0);
+        const double en = nrm * u[i] * u[i];
+        e_all += en;
+        if (max(n0, max(n1, n2)) == P - 1) e_top += en;
+    }
+    eta[k] = (e_all > 0.0) ? sqrt(e_top / e_all) : 0.0;
+}
+
+// Degree update: p + 1 where eta > nu_max eta_max, p - 1 where
+// eta < nu_min eta_max, within [p_min, p_max].  One workgroup.
+__global__ void __launch_bounds__(1024) k_pa_adapt(int Ne, const double *__restrict__ eta,
+                                                   const int *__restrict__ deg_in, int *__restrict__ deg_out,
+                                                   int p_min, int p_max, double nu_max, double nu_min) {
+    __shared__ double red[1024];
+    double mx = 0.0;
+    for (int k = threadIdx.x; k < Ne; k += blockDim.x) mx = fmax(mx, eta[k]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double emax = red[0];
+    for (int k = threadIdx.x; k < Ne; k += blockDim.x) {
+        int p = deg_in[k];
+        if (eta[k] > nu_max * emax) p += 1;
+        if (eta[k] < nu_min * emax) p -= 1;
+        deg_out[k] = min(max(p, p_min), p_max);
+    }
+}
+
+// ---- launchers ------------------------------------------------------------
+
+template <int DIM, int P, int MODE, int OUT>
+void pa_class(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, const PaK &base, bool faces_phase,
+              hipStream_t s) {
+    using S = Shape<DIM, P>;
+    PaK pk = base;
+    pk.list = L.pa->cls + L.pa->cls_off[P];
+    pk.count = L.pa->cls_off[P + 1] - L.pa->cls_off[P];
+    if (pk.count <= 0) return;
+    const Ops1D &ops = ctx->pa_tab_host->ops[P];
+    SrcK src{a.dq, a.v, a.alpha, L.Np};
+    if (faces_phase) {
+        const dim3 g((pk.count + S::EBF - 1) / S::EBF);
+        hipLaunchKernelGGL((k_pa_faces<DIM, P, MODE>), g, dim3(S::NTF), 0, s, ctx->mesh, src, ops, ctx->phys, pk,
+                           L.Jp, L.Fs);
+    } else {
+        OutK o{a.r, a.r0, a.x, a.v, a.sigma, a.dscale};
+        const dim3 g((pk.count + S::EB - 1) / S::EB);
+        hipLaunchKernelGGL((k_pa_volume<DIM, P, MODE, OUT>), g, dim3(S::NT), 0, s, ctx->mesh, src, ops, ctx->phys,
+                           pk, L.Jp, L.Fs, o);
+    }
+}
+
+template <int DIM, int MODE, int OUT>
+hipError_t pa_run(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, hipStream_t s) {
+    const PaLevel &pa = *L.pa;
+    PaK base{pa.Pk, nullptr, 0, L.Np, L.NF, ctx->pa_tab, pa.Fm, pa.Mq, pa.Mn, pa.Mg};
+    for (int phase = 0; phase < 2; ++phase) {
+        const bool faces = phase == 0;
+        pa_class<DIM, 1, MODE, OUT>(ctx, L, a, base, faces, s);
+        pa_class<DIM, 2, MODE, OUT>(ctx, L, a, base, faces, s);
+        pa_class<DIM, 3, MODE, OUT>(ctx, L, a, base, faces, s);
+        pa_class<DIM, 4, MODE, OUT>(ctx, L, a, base, faces, s);
+        if constexpr (DIM == 2) pa_class<DIM, 5, MODE, OUT>(ctx, L, a, base, faces, s);
+        if (faces && pa.nmixed > 0) {
+            constexpr int FB = 64 / ((DIM == 2) ? kMaxP : kMaxNF3);
+            hipLaunchKernelGGL((k_pa_mortar<DIM>), dim3((pa.nmixed + FB - 1) / FB), dim3(64), 0, s, ctx->mesh,
+                               ctx->phys, base, pa.mixed, pa.nmixed, L.Fs);
+        }
+    }
+    return hipGetLastError();
+}
+
+template <int DIM>
+hipError_t pa_dispatch(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, hipStream_t s) {
+    if (a.src == SRC_PLAIN && a.out == OUT_R) return pa_run<DIM, SRC_PLAIN, OUT_R>(ctx, L, a, s);
+    if (a.src == SRC_AXPY && a.out == OUT_R) return pa_run<DIM, SRC_AXPY, OUT_R>(ctx, L, a, s);
+    if (a.src == SRC_AXPY && a.out == OUT_LIN) return pa_run<DIM, SRC_AXPY, OUT_LIN>(ctx, L, a, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 hipError_t launch_residual(const frpmg_ctx *ctx, int level, const ResidualArgs &a, hipStream_t s) {
     const Level &L = ctx->lv[level];
+    if (L.pa) return launch_residual_pa(ctx, level, a, s);
     if (ctx->dim == 2) {
         switch (L.P) {
             case 1: return dispatch_modes<2, 1>(ctx, L, a, nullptr, s);
@@ -872,6 +1433,7 @@ hipError_t launch_ej_form(const frpmg_ctx *ctx, int level, const double *dq, dou
                           double *out) {
     const Level &L = ctx->lv[level];
     if (!out) out = L.blk64;
+    if (L.pa) return launch_ej_form_pa(ctx, level, dq, sigma, s, out);
     if (!L.fQs || !L.fQp || !L.fSn || !L.fGt || !out || !L.r0) return hipErrorInvalidValue;
     if (ctx->dim == 2) {
         switch (L.P) {
@@ -926,6 +1488,87 @@ hipError_t launch_residual_batch(const frpmg_ctx *ctx, int level, int batch, con
         }
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_residual_pa(const frpmg_ctx *ctx, int level, const ResidualArgs &a, hipStream_t s) {
+    const Level &L = ctx->lv[level];
+    if (!L.pa || !ctx->pa_tab || !ctx->pa_tab_host) return hipErrorInvalidValue;
+    return ctx->dim == 2 ? pa_dispatch<2>(ctx, L, a, s) : pa_dispatch<3>(ctx, L, a, s);
+}
+
+hipError_t launch_ej_form_pa(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s,
+                             double *out) {
+    const Level &L = ctx->lv[level];
+    if (!L.pa || !out || !L.r0) return hipErrorInvalidValue;
+    const PaLevel &pa = *L.pa;
+    const MeshK &m = ctx->mesh;
+    for (int a = 0; a < ctx->dim; ++a)
+        if (m.n[a] % 2) return hipErrorInvalidValue;
+    ResidualArgs a0;
+    a0.src = SRC_PLAIN;
+    a0.dq = dq;
+    a0.out = OUT_R;
+    a0.r = L.r0;
+    hipError_t err = launch_residual_pa(ctx, level, a0, s);
+    if (err != hipSuccess) return err;
+    const size_t total = (size_t)m.Ne * L.nb * L.nb;
+    hipLaunchKernelGGL(k_pa_blk_identity, dim3(4096), dim3(256), 0, s, total, L.nb, out);
+    const dim3 ge((m.Ne + 255) / 256);
+    const dim3 gx((unsigned)(((size_t)m.Ne * L.nb + 255) / 256));
+    ResidualArgs ap;
+    ap.src = SRC_AXPY;
+    ap.dq = dq;
+    ap.v = pa.fdv;
+    ap.alpha = Scal{1.0, nullptr};
+    ap.out = OUT_R;
+    ap.r = pa.fdr;
+    const int ncol = 1 << ctx->dim;
+    for (int colour = 0; colour < ncol; ++colour)
+        for (int j = 0; j < L.nb; ++j) {
+            hipLaunchKernelGGL(k_pa_fd_set, ge, dim3(256), 0, s, m, pa.Pk, colour, j, L.Np, ctx->phys, dq, pa.fdv, 1);
+            err = launch_residual_pa(ctx, level, ap, s);
+            if (err != hipSuccess) return err;
+            hipLaunchKernelGGL(k_pa_fd_extract, gx, dim3(256), 0, s, m, pa.Pk, colour, j, L.Np, L.nb, dq, pa.fdv,
+                               pa.fdr, L.r0, sigma, out);
+            hipLaunchKernelGGL(k_pa_fd_set, ge, dim3(256), 0, s, m, pa.Pk, colour, j, L.Np, ctx->phys, dq, pa.fdv, 0);
+        }
+    return hipGetLastError();
+}
+
+hipError_t pa_project(const frpmg_ctx *ctx, const int *deg_from, int NpF, const double *x, const int *deg_to, int NpT,
+                      double *y, hipStream_t s) {
+    if (!ctx->pa_tab) return hipErrorInvalidValue;
+    const size_t n = (size_t)ctx->nv * NpT * ctx->mesh.Ne;
+    hipLaunchKernelGGL(k_pa_transfer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ctx->dim, ctx->nv,
+                       ctx->mesh.Ne, deg_from, NpF, deg_to, NpT, 1, ctx->pa_tab, x, nullptr, y, 0, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t pa_transfer(const frpmg_ctx *ctx, int from, int to, const double *x, double *y, const double *x0,
+                       bool accumulate, const double *x2, double *y2, hipStream_t s) {
+    const Level &A = ctx->lv[from], &B = ctx->lv[to];
+    if (!A.pa || !B.pa || !ctx->pa_tab) return hipErrorInvalidValue;
+    const size_t n = (size_t)ctx->nv * B.Np * ctx->mesh.Ne;
+    hipLaunchKernelGGL(k_pa_transfer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ctx->dim, ctx->nv,
+                       ctx->mesh.Ne, A.pa->Pk, A.Np, B.pa->Pk, B.Np, 0, ctx->pa_tab, x, x0, y, accumulate ? 1 : 0, x2,
+                       y2);
+    return hipGetLastError();
+}
+
+hipError_t pa_indicator(const frpmg_ctx *ctx, int level, const double *dq, int var, double *eta, hipStream_t s) {
+    const Level &L = ctx->lv[level];
+    if (!L.pa || var < 0 || var >= ctx->nv) return hipErrorInvalidValue;
+    const int Ne = ctx->mesh.Ne;
+    hipLaunchKernelGGL(k_pa_indicator, dim3((Ne + 127) / 128), dim3(128), 0, s, ctx->dim, Ne, L.pa->Pk, L.Np,
+                       ctx->pa_tab, ctx->phys.qinf[var], dq + (size_t)var * L.Np * Ne, eta);
+    return hipGetLastError();
+}
+
+hipError_t pa_adapt(const frpmg_ctx *ctx, const double *eta, const int *deg_in, int *deg_out, int p_min, int p_max,
+                    double nu_max, double nu_min, hipStream_t s) {
+    hipLaunchKernelGGL(k_pa_adapt, dim3(1), dim3(1024), 0, s, ctx->mesh.Ne, eta, deg_in, deg_out, p_min, p_max,
+                       nu_max, nu_min);
+    return hipGetLastError();
 }
 
 }  // namespace frpmg

@@ -468,6 +468,9 @@ namespace {
 
 hipError_t transfer_launch(const frpmg_ctx *ctx, int fine_level, bool restrict_dir, const double *x, double *y,
                            const double *x0, bool accumulate, const double *x2, double *y2, hipStream_t s) {
+    if (ctx->lv[fine_level].pa)
+        return restrict_dir ? pa_transfer(ctx, fine_level, fine_level + 1, x, y, x0, accumulate, x2, y2, s)
+                            : pa_transfer(ctx, fine_level + 1, fine_level, x, y, x0, accumulate, x2, y2, s);
     const Transfer1D &t = ctx->tr[fine_level];
     const int Pin = restrict_dir ? t.P0 : t.P1;
     const int Pout = restrict_dir ? t.P1 : t.P0;
