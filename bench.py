@@ -512,8 +512,12 @@ def only_kernel(args):
     import torch
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
-    wl = W.vortical_64x64_p4() if args.workload == "vortical2d" else W.tgv_32cubed_p3()
-    fr = capi.FR.from_workload(wl)
+    if args.workload == "padapt2d":
+        wl = W.make_padapt_workload()
+        fr = capi.FR.from_padapt(wl, wl.extra["deg"], nlevels=2, gap=2)
+    else:
+        wl = W.vortical_64x64_p4() if args.workload == "vortical2d" else W.tgv_32cubed_p3()
+        fr = capi.FR.from_workload(wl)
     prec = PRECISIONS[args.precision]
     dq = fr.to_dev(wl.dq)
     sig = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
@@ -709,6 +713,67 @@ def vortical2d_extras(args, prec):
     return wl, res
 
 
+def padapt():
+    """p-adaptive FR (Sec. 3.3) on the 32 x 32 vortical mesh: the first ROW
+    stage on the ring degree map (degrees 1..4, nested p{4-2} pMG) beside
+    the uniform p = 4 stage on the same mesh, field and step; residual launch
+    times of both; one adaptation cycle (indicator, degree update, L2
+    projection of the state, new degree map)."""
+    import torch
+    from paper_2202_09733_amd import capi
+    from paper_2202_09733_amd import workloads as W
+    out = {}
+    for key, uni in (("p_adaptive", False), ("uniform_p4", True)):
+        wl = W.make_padapt_workload(uniform=uni)
+        deg = wl.extra["deg"]
+        fr = capi.FR.from_padapt(wl, deg, nlevels=2, gap=2) if not uni else capi.FR.from_workload(wl, levels=[4, 2])
+        dq = fr.to_dev(wl.dq)
+        dof = int(wl.nv * np.sum((deg.astype(np.int64) + 1) ** 2))
+        cfg = capi.stage_config_for(wl, precond=capi.PRECOND_PMG)
+        y = fr.empty(0)
+        fr.solve_stage(cfg, dq, out=y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            _, st = fr.solve_stage(cfg, dq, out=y)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        r = fr.empty(0)
+        t_res = _events_time(lambda: fr.residual(0, dq, out=r), 50)
+        out[key] = {"dof": dof, "degrees": np.bincount(deg, minlength=5).tolist(), "stage_s": el,
+                    "dof_per_s": dof / el, "gmres_iters": st["gmres_iters"], "true_rel_res": st["true_rel_res"],
+                    "t_setup_s": st["t_setup"], "residual_us": t_res * 1e6}
+        if not uni:
+            d_deg = torch.as_tensor(deg, device=fr.device)
+
+            def cycle():
+                eta = fr.pa_indicator(0, dq)
+                new = fr.pa_adapt(eta, d_deg, p_max=4)
+                fr.pa_project(d_deg, 4, dq, new, 4)
+                return new
+
+            new = cycle()
+            torch.cuda.synchronize()
+            t_dev = _events_time(cycle, 20)
+            nd = new.cpu().numpy()
+            # host cost of installing a degree map (lists, buffers, tables): the
+            # current map again, since the context's level degrees are fixed
+            t0 = time.perf_counter()
+            fr.set_degrees(deg, 2)
+            t_set = time.perf_counter() - t0
+            out[key]["adapt_cycle"] = {"indicator_adapt_project_us": t_dev * 1e6, "set_degrees_ms": t_set * 1e3,
+                                       "raised": int(np.sum(nd > deg)), "lowered": int(np.sum(nd < deg)),
+                                       "new_degrees": np.bincount(nd, minlength=5).tolist()}
+        fr.close()
+        torch.cuda.empty_cache()
+    out["workload"] = ("2D NS FR periodic 32x32, Ma 0.1, Re 1000, vortical field |u'| <= 0.05; degrees in rings "
+                       "(4 at the centre down to 1) vs p = 4 everywhere; first ROW stage at dt = 100 dt_exp, "
+                       "FGMRES(30), pMG p{4-2} (nested, order gap 2), EJ smoothers, FP64, recomputed residual 1e-8")
+    out["time_ratio_uniform_over_adaptive"] = out["uniform_p4"]["stage_s"] / out["p_adaptive"]["stage_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -722,7 +787,7 @@ def main():
     ap.add_argument("--only-kernel", default=None, choices=["ej_apply", "ej_factor", "residual", "jvp", "stage", "step"],
                     help="profiling driver: set up the workload's state, launch one kernel family --reps times "
                          "and a 256 MiB device copy (counter calibration), print nothing else")
-    ap.add_argument("--workload", default="vortical2d", choices=["vortical2d", "tgv3d"],
+    ap.add_argument("--workload", default="vortical2d", choices=["vortical2d", "tgv3d", "padapt2d"],
                     help="workload of the --only-kernel driver")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--coarse-smoother", default="ej", choices=["ej", "mbnk"],
@@ -775,6 +840,8 @@ def main():
         result["time_step"] = time_steps()
         print("[bench] p-hierarchies and the pMG nonlinear solver", file=sys.stderr, flush=True)
         result["hierarchies"] = hierarchies()
+        print("[bench] p-adaptive stage", file=sys.stderr, flush=True)
+        result["p_adaptive"] = padapt()
         print("[bench] coarse smoothers", file=sys.stderr, flush=True)
         result["smoothers"] = smoothers()
         print("[bench] learned coarse correction: harvest, train, A/B", file=sys.stderr, flush=True)

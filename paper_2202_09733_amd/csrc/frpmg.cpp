@@ -1617,8 +1617,11 @@ void pa_free_level(Level &L) {
     dfree(pa.Mq);
     dfree(pa.Mn);
     dfree(pa.Mg);
-    dfree(pa.fdv);
-    dfree(pa.fdr);
+    dfree(pa.PkB);
+    dfree(pa.clsB);
+    dfree(pa.mixedB);
+    double *bb[] = {pa.JpB, pa.FsB, pa.FmB, pa.MqB, pa.MnB, pa.MgB, pa.qB, pa.rB};
+    for (double *b : bb) dfree(b);
     delete L.pa;
     L.pa = nullptr;
 }
@@ -1696,9 +1699,46 @@ void pa_build_level(frpmg_ctx *ctx, int l, const int *deg) {
     pa.Mq = dalloc(ctx, nface);
     pa.Mn = dalloc(ctx, nface);
     pa.Mg = dalloc(ctx, nface * ctx->dim);
-    pa.fdv = dalloc(ctx, L.N);
-    pa.fdr = dalloc(ctx, L.N);
-    HIPCHK(hipMemset(pa.fdv, 0, L.N * sizeof(double)));
+    // copies for the coloured-difference EJ formation: as many (colour,
+    // column) perturbations per evaluation as fit in 512 MiB, at most 64
+    const size_t per_copy = (2 * L.N + (5 + (size_t)ctx->dim) * nface) * sizeof(double) + 2 * (size_t)Ne * sizeof(int);
+    const long npairs = (long)(1 << ctx->dim) * L.nb;
+    long B = (long)((size_t(512) << 20) / per_copy);
+    B = std::max(1L, std::min({B, 64L, npairs}));
+    if ((long)Ne * B >= (1L << 29)) B = std::max(1L, ((1L << 29) - 1) / Ne);  // face codes (id * 4 + axis) stay in an int
+    pa.fdB = (int)B;
+    std::vector<int> PkB((size_t)B * Ne), clsB;
+    std::vector<int> mixedB;
+    clsB.reserve((size_t)B * Ne);
+    for (long b = 0; b < B; ++b)
+        for (int k = 0; k < Ne; ++k) PkB[(size_t)b * Ne + k] = pa.Pk_host[k];
+    for (int P = 1; P <= kMaxP; ++P) {
+        pa.clsB_off[P] = (int)clsB.size();
+        for (long b = 0; b < B; ++b)
+            for (int u = pa.cls_off[P]; u < pa.cls_off[P + 1]; ++u) clsB.push_back((int)(b * Ne) + cls[u]);
+    }
+    pa.clsB_off[kMaxP + 1] = (int)clsB.size();
+    for (long b = 0; b < B; ++b)
+        for (int code : mixed) mixedB.push_back(((int)(b * Ne) + (code >> 2)) * 4 + (code & 3));
+    HIPCHK(hipMalloc(&p, PkB.size() * sizeof(int)));
+    pa.PkB = (int *)p;
+    HIPCHK(hipMemcpy(pa.PkB, PkB.data(), PkB.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&p, clsB.size() * sizeof(int)));
+    pa.clsB = (int *)p;
+    HIPCHK(hipMemcpy(pa.clsB, clsB.data(), clsB.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!mixedB.empty()) {
+        HIPCHK(hipMalloc(&p, mixedB.size() * sizeof(int)));
+        pa.mixedB = (int *)p;
+        HIPCHK(hipMemcpy(pa.mixedB, mixedB.data(), mixedB.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    pa.JpB = dalloc(ctx, nface * B);
+    pa.FsB = dalloc(ctx, nface * B);
+    pa.FmB = dalloc(ctx, nface * B);
+    pa.MqB = dalloc(ctx, nface * B);
+    pa.MnB = dalloc(ctx, nface * B);
+    pa.MgB = dalloc(ctx, nface * ctx->dim * B);
+    pa.qB = dalloc(ctx, L.N * B);
+    pa.rB = dalloc(ctx, L.N * B);
 }
 
 void destroy_all(frpmg_ctx *ctx) {

@@ -140,8 +140,14 @@ struct PaLevel {
     double *Mq = nullptr;         // mixed faces: the -axis element's + trace [dim][nv][NF][Ne]
     double *Mn = nullptr;         // mixed faces: the +axis element's - trace at its points [dim][nv][NF][Ne]
     double *Mg = nullptr;         // mixed faces: the -axis element's gradient trace [dim][dim][nv][NF][Ne]
-    double *fdv = nullptr;        // EJ formation: perturbation vector [N] (zero between columns)
-    double *fdr = nullptr;        // EJ formation: perturbed residual [N]
+    // EJ formation: fdB perturbed copies of the level evaluated together
+    // (element id b Ne + k is element k of copy b); the lists and buffers
+    // above, repeated per copy
+    int fdB = 0;
+    int *PkB = nullptr, *clsB = nullptr, *mixedB = nullptr;
+    int clsB_off[kMaxP + 2] = {};
+    double *JpB = nullptr, *FsB = nullptr, *FmB = nullptr, *MqB = nullptr, *MnB = nullptr, *MgB = nullptr;
+    double *qB = nullptr, *rB = nullptr;  // [nv][Np][fdB Ne]
 };
 
 struct Level {

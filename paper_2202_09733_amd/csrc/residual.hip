@@ -869,11 +869,24 @@ struct PaK {
     const int *Pk;         // points per direction of every element
     const int *list;       // element ids of the launched class
     int count;             // elements in the list
+    int ne0;               // elements per mesh copy: id k is element k % ne0 of copy k / ne0
     int NpM, NFM;          // padded points per element / per face
     const PaTables *tab;   // operators of every degree
     double *Fm;            // common flux on - faces [dim][nv][NFM][Ne]
     double *Mq, *Mn, *Mg;  // mortar inputs, on the + face of the -axis element
 };
+
+// + neighbour of element id k along a, within k's mesh copy
+__device__ __forceinline__ int pa_plus_neighbour(const MeshK &m, const PaK &pk, int k, int a) {
+    const int kb = (k / pk.ne0) * pk.ne0;
+    return kb + neighbour(m, k - kb, a, +1);
+}
+
+__device__ __forceinline__ double pa_inv2h(const MeshK &m, const PaK &pk, int k, int a) {
+    int c[3];
+    coords(m, k % pk.ne0, c);
+    return m.inv2h[a][c[a]];
+}
 
 // local point on the line along axis a through face point f, position j (P at run time)
 __device__ __forceinline__ int line_rt(int dim, int P, int a, int f, int j) {
@@ -933,23 +946,46 @@ __device__ __forceinline__ void pa_face_flux(const MeshK &m, const Ops1D &ops, c
     }
 }
 
-// + faces of the class-P elements (one lane per face point, as k_faces).
-template <int DIM, int P, int MODE>
-__global__ void __launch_bounds__((Shape<DIM, P>::NTF)) k_pa_faces(MeshK m, SrcK src, Ops1D ops_in, Phys ph, PaK pk,
-                                                                double *__restrict__ Jp, double *__restrict__ Fs) {
+// LDS of one class's face workgroup, in doubles: the class's 1D operators,
+// the state [v][i][slot], the + neighbours' minus traces at their own points
+// [a][v][f][slot], q* and the own + traces on the + faces at own points,
+// 2/h, then the slots' element ids and their + neighbours' ids and point counts.
+template <int DIM, int P>
+struct PaFacesLds {
     using S = Shape<DIM, P>;
+    static constexpr int EB = S::EBF, NV = S::NV, NP = S::NP, NF = S::NF;
+    static constexpr int NFN = (DIM == 2) ? kMaxP : kMaxNF3;  // a neighbour's face points, at most
+    static constexpr int NFACE = DIM * NV * NF * EB;
+    static constexpr int OPS = (int)(sizeof(Ops1D) / sizeof(double));
+    static constexpr int U = OPS, TN = U + NV * NP * EB, T = TN + DIM * NV * NFN * EB, QP = T + NFACE,
+                         IH = QP + NFACE, INTS = IH + DIM * EB;
+    static constexpr int DOUBLES = INTS + (EB + 2 * DIM * EB + 1) / 2;
+};
+
+// + faces of the class-P elements of workgroup blk of the class (one lane
+// per face point, as k_faces).
+template <int DIM, int P, int MODE>
+__device__ __forceinline__ void pa_faces_body(const MeshK &m, const SrcK &src, const Phys &ph, const PaK &pk,
+                                              double *__restrict__ Jp, double *__restrict__ Fs, int blk,
+                                              double *lds) {
+    using S = Shape<DIM, P>;
+    using LD = PaFacesLds<DIM, P>;
     constexpr int EB = S::EBF, NV = S::NV, NP = S::NP, NF = S::NF;
     constexpr int NFACE = DIM * NV * NF * EB;
-    constexpr int NFN = (DIM == 2) ? kMaxP : kMaxNF3;  // a neighbour's face points, at most
-    __shared__ Ops1D ops;
-    __shared__ double s_u[NV * NP * EB];
-    __shared__ double s_tn[DIM * NV * NFN * EB];  // + neighbours' minus traces at their own points
-    __shared__ double s_t[NFACE];                 // q* on the + faces at own points
-    __shared__ double s_qp[NFACE];                // own + traces
-    __shared__ double s_ih[DIM * EB];
-    __shared__ int s_k[EB], s_kn[DIM * EB], s_pn[DIM * EB];
-    if (threadIdx.x == 0) ops = ops_in;
-    const int b0 = xcd_block(blockIdx.x, gridDim.x) * EB;
+    constexpr int NFN = LD::NFN;
+    const Ops1D &ops = *reinterpret_cast<const Ops1D *>(lds);
+    double *s_u = lds + LD::U;
+    double *s_tn = lds + LD::TN;
+    double *s_t = lds + LD::T;
+    double *s_qp = lds + LD::QP;
+    double *s_ih = lds + LD::IH;
+    int *s_k = reinterpret_cast<int *>(lds + LD::INTS);
+    int *s_kn = s_k + EB, *s_pn = s_kn + DIM * EB;
+    {
+        const double *src_ops = reinterpret_cast<const double *>(&pk.tab->ops[P]);
+        for (int t = threadIdx.x; t < LD::OPS; t += blockDim.x) lds[t] = src_ops[t];
+    }
+    const int b0 = blk * EB;
     const int ne = min(EB, pk.count - b0);
     const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
     for (int t = threadIdx.x; t < EB; t += blockDim.x) s_k[t] = (t < ne) ? pk.list[b0 + t] : 0;
@@ -960,11 +996,9 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NTF)) k_pa_faces(MeshK m, SrcK
         double ih = 0.0;
         if (e < ne) {
             const int k = s_k[e];
-            kn = neighbour(m, k, a, +1);
+            kn = pa_plus_neighbour(m, pk, k, a);
             pn = pk.Pk[kn];
-            int c[3];
-            coords(m, k, c);
-            ih = m.inv2h[a][c[a]];
+            ih = pa_inv2h(m, pk, k, a);
         }
         s_kn[t] = kn;
         s_pn[t] = pn;
@@ -1044,8 +1078,26 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NTF)) k_pa_faces(MeshK m, SrcK
     }
 }
 
-// The common flux on faces between elements of different degree: one lane
-// per mortar point forms it from the mortar inputs projected there, then the
+// face_map_pt with the 1D projection T (rows of kMaxP, T[b kMaxP + a]) and
+// the input (contiguous) in LDS
+__device__ __forceinline__ double face_map_lds(const double *T, int dim, int Pa, int Pb, int fb, const double *x) {
+    const int b0 = fb % Pb, b1 = fb / Pb;
+    const int nfa = (dim == 2) ? Pa : Pa * Pa;
+    double s = 0.0;
+    for (int fa = 0; fa < nfa; ++fa) {
+        const int a0 = fa % Pa, a1 = fa / Pa;
+        double c = T[b0 * kMaxP + a0];
+        if (dim == 3) c *= T[b1 * kMaxP + a1];
+        s += c * x[fa];
+    }
+    return s;
+}
+
+// The common flux on faces between elements of different degree.  The
+// workgroup first stages the 1D projections and, for each of its faces, the
+// mortar inputs (the -axis element's + trace and gradient trace, the +axis
+// element's - trace) in LDS, all loads in flight at once; then one lane per
+// mortar point forms the flux from the inputs projected there, and the
 // lanes project it back onto the -axis element's + face (Fs) and the +axis
 // element's - face (Fm).
 template <int DIM>
@@ -1054,33 +1106,77 @@ __global__ void __launch_bounds__(64) k_pa_mortar(MeshK m, Phys ph, PaK pk, cons
     constexpr int NV = DIM + 2;
     constexpr int NFMM = (DIM == 2) ? kMaxP : kMaxNF3;
     constexpr int FB = 64 / NFMM;
+    constexpr int NIN = (2 + DIM) * NV;  // q+ of the -axis element, q- of the +axis one, the gradient trace
+    constexpr int NT = (kMaxP + 1) * (kMaxP + 1) * kMaxP * kMaxP;
+    __shared__ double sT[NT];
+    __shared__ double sIn[FB][NIN][NFMM];
     __shared__ double sF[FB][NV][NFMM];
-    const int slot = threadIdx.x / NFMM, fm = threadIdx.x % NFMM;
-    const int fi = blockIdx.x * FB + slot;
-    const bool act = slot < FB && fi < nfaces;
-    int k = 0, a = 0, kn = 0, Pk = 1, Pn = 1, Pm = 1;
+    __shared__ int sk[FB], skn[FB], sa[FB], spk[FB], spn[FB];
+    const int tid = threadIdx.x;
+    const size_t Ne = (size_t)m.Ne;
+    if (tid < FB) {
+        const int fi = blockIdx.x * FB + tid;
+        int k = 0, a = 0, kn = 0, Pk = 1, Pn = 1;
+        if (fi < nfaces) {
+            const int code = faces[fi];
+            k = code >> 2;
+            a = code & 3;
+            kn = pa_plus_neighbour(m, pk, k, a);
+            Pk = pk.Pk[k];
+            Pn = pk.Pk[kn];
+        }
+        sk[tid] = k;
+        skn[tid] = kn;
+        sa[tid] = a;
+        spk[tid] = (fi < nfaces) ? Pk : 0;
+        spn[tid] = Pn;
+    }
+    {
+        const double *tab = &pk.tab->proj[0][0][0][0];
+        for (int t = tid; t < NT; t += 64) sT[t] = tab[t];
+    }
+    __syncthreads();
+    for (int t = tid; t < FB * NIN * NFMM; t += 64) {
+        const int slot = t / (NIN * NFMM), r = t % (NIN * NFMM);
+        const int q = r / NFMM, f = r % NFMM;
+        const int Pk = spk[slot];
+        double val = 0.0;
+        if (Pk > 0) {
+            const int a = sa[slot], Pn = spn[slot];
+            const int nfk = (DIM == 2) ? Pk : Pk * Pk, nfn = (DIM == 2) ? Pn : Pn * Pn;
+            if (q < NV) {
+                if (f < nfk) val = pk.Mq[((size_t)(a * NV + q) * pk.NFM + f) * Ne + sk[slot]];
+            } else if (q < 2 * NV) {
+                if (f < nfn) val = pk.Mn[((size_t)(a * NV + q - NV) * pk.NFM + f) * Ne + sk[slot]];
+            } else {
+                const int cv = q - 2 * NV;  // c * NV + v
+                if (f < nfk) val = pk.Mg[((size_t)(a * DIM * NV + cv) * pk.NFM + f) * Ne + sk[slot]];
+            }
+        }
+        sIn[slot][q][f] = val;
+    }
+    __syncthreads();
+    const int slot = tid / NFMM, fm = tid % NFMM;
+    const bool act = slot < FB && spk[slot < FB ? slot : 0] > 0;
+    int a = 0, Pk = 1, Pn = 1, Pm = 1;
     if (act) {
-        const int code = faces[fi];
-        k = code >> 2;
-        a = code & 3;
-        kn = neighbour(m, k, a, +1);
-        Pk = pk.Pk[k];
-        Pn = pk.Pk[kn];
+        a = sa[slot];
+        Pk = spk[slot];
+        Pn = spn[slot];
         Pm = max(Pk, Pn);
     }
-    const size_t Ne = (size_t)m.Ne;
     if (act && fm < ((DIM == 2) ? Pm : Pm * Pm)) {
+        const double *TkM = &sT[((Pk * (kMaxP + 1) + Pm) * kMaxP) * kMaxP];
+        const double *TnM = &sT[((Pn * (kMaxP + 1) + Pm) * kMaxP) * kMaxP];
         double qL[NV], qR[NV], g[DIM][NV], F[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double *xq = pk.Mq + ((size_t)(a * NV + v) * pk.NFM) * Ne + k;
-            const double *xn = pk.Mn + ((size_t)(a * NV + v) * pk.NFM) * Ne + k;
-            qL[v] = (Pk == Pm) ? xq[fm * Ne] : face_map_pt(pk.tab, DIM, Pk, Pm, fm, xq, Ne);
-            qR[v] = (Pn == Pm) ? xn[fm * Ne] : face_map_pt(pk.tab, DIM, Pn, Pm, fm, xn, Ne);
+            qL[v] = (Pk == Pm) ? sIn[slot][v][fm] : face_map_lds(TkM, DIM, Pk, Pm, fm, sIn[slot][v]);
+            qR[v] = (Pn == Pm) ? sIn[slot][NV + v][fm] : face_map_lds(TnM, DIM, Pn, Pm, fm, sIn[slot][NV + v]);
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                const double *xg = pk.Mg + (((size_t)(a * DIM + c) * NV + v) * pk.NFM) * Ne + k;
-                g[c][v] = (Pk == Pm) ? xg[fm * Ne] : face_map_pt(pk.tab, DIM, Pk, Pm, fm, xg, Ne);
+                const double *x = sIn[slot][2 * NV + c * NV + v];
+                g[c][v] = (Pk == Pm) ? x[fm] : face_map_lds(TkM, DIM, Pk, Pm, fm, x);
             }
         }
         if (a == 0) {
@@ -1095,36 +1191,56 @@ __global__ void __launch_bounds__(64) k_pa_mortar(MeshK m, Phys ph, PaK pk, cons
     }
     __syncthreads();
     if (!act) return;
+    const int k = sk[slot], kn = skn[slot];
     const int nfk = (DIM == 2) ? Pk : Pk * Pk, nfn = (DIM == 2) ? Pn : Pn * Pn;
+    const double *TMk = &sT[((Pm * (kMaxP + 1) + Pk) * kMaxP) * kMaxP];
+    const double *TMn = &sT[((Pm * (kMaxP + 1) + Pn) * kMaxP) * kMaxP];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const size_t o = ((size_t)(a * NV + v) * pk.NFM + fm) * Ne;
-        if (fm < nfk)
-            Fs[o + k] = (Pk == Pm) ? sF[slot][v][fm] : face_map_pt(pk.tab, DIM, Pm, Pk, fm, &sF[slot][v][0], 1);
-        if (fm < nfn)
-            pk.Fm[o + kn] = (Pn == Pm) ? sF[slot][v][fm] : face_map_pt(pk.tab, DIM, Pm, Pn, fm, &sF[slot][v][0], 1);
+        if (fm < nfk) Fs[o + k] = (Pk == Pm) ? sF[slot][v][fm] : face_map_lds(TMk, DIM, Pm, Pk, fm, sF[slot][v]);
+        if (fm < nfn) pk.Fm[o + kn] = (Pn == Pm) ? sF[slot][v][fm] : face_map_lds(TMn, DIM, Pm, Pn, fm, sF[slot][v]);
     }
 }
 
-// Divergence of the class-P elements (k_volume with element ids from the
-// list, padded strides and the - face fluxes from Fm); writes the padding
-// entries of the output too.
-template <int DIM, int P, int MODE, int OUT>
-__global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_pa_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, PaK pk,
-                                                                const double *__restrict__ Jp,
-                                                                const double *__restrict__ Fs, OutK o) {
+// LDS of one class's volume workgroup (doubles): operators, state, state
+// jumps and common fluxes on both face sets, 2/h, element ids.  One point per
+// element (p = 0) takes 128 elements per 256-lane workgroup in 2D.
+template <int DIM, int P>
+struct PaVolLds {
     using S = Shape<DIM, P>;
-    constexpr int EB = S::EB, NV = S::NV, NP = S::NP, NF = S::NF;
+    static constexpr int EB = (P == 1) ? (DIM == 2 ? 128 : 64) : S::EB;
+    static constexpr int NV = S::NV, NP = S::NP, NF = S::NF;
+    static constexpr int NFACE = DIM * NV * NF * EB;
+    static constexpr int OPS = (int)(sizeof(Ops1D) / sizeof(double));
+    static constexpr int U = OPS, T = U + NV * NP * EB, FM = T + NFACE, FP = FM + NFACE, IH = FP + NFACE,
+                         INTS = IH + DIM * EB;
+    static constexpr int DOUBLES = INTS + (EB + 1) / 2;
+};
+
+// Divergence of the class-P elements of workgroup blk of the class
+// (k_volume with element ids from the list, padded strides and the - face
+// fluxes from Fm); also writes the padding entries of the output (0).
+template <int DIM, int P, int MODE, int OUT>
+__device__ __forceinline__ void pa_volume_body(const MeshK &m, const SrcK &src, const Phys &ph, const PaK &pk,
+                                               const double *__restrict__ Jp, const double *__restrict__ Fs,
+                                               const OutK &o, int blk, double *lds) {
+    using S = Shape<DIM, P>;
+    using LD = PaVolLds<DIM, P>;
+    constexpr int EB = LD::EB, NV = S::NV, NP = S::NP, NF = S::NF;
     constexpr int NFACE = DIM * NV * NF * EB;
-    __shared__ Ops1D ops;
-    __shared__ double s_u[NV * NP * EB];
-    __shared__ double s_t[NFACE];
-    __shared__ double s_fm[NFACE];
-    __shared__ double s_fp[NFACE];
-    __shared__ double s_ih[DIM * EB];
-    __shared__ int s_k[EB];
-    if (threadIdx.x == 0) ops = ops_in;
-    const int b0 = xcd_block(blockIdx.x, gridDim.x) * EB;
+    const Ops1D &ops = *reinterpret_cast<const Ops1D *>(lds);
+    double *s_u = lds + LD::U;
+    double *s_t = lds + LD::T;
+    double *s_fm = lds + LD::FM;
+    double *s_fp = lds + LD::FP;
+    double *s_ih = lds + LD::IH;
+    int *s_k = reinterpret_cast<int *>(lds + LD::INTS);
+    {
+        const double *src_ops = reinterpret_cast<const double *>(&pk.tab->ops[P]);
+        for (int t = threadIdx.x; t < LD::OPS; t += blockDim.x) lds[t] = src_ops[t];
+    }
+    const int b0 = blk * EB;
     const int ne = min(EB, pk.count - b0);
     const double alpha = (MODE == SRC_AXPY) ? sval(src.alpha) : 0.0;
     const size_t Ne = (size_t)m.Ne;
@@ -1150,13 +1266,7 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_pa_volume(MeshK m, SrcK
     }
     for (int t = threadIdx.x; t < DIM * EB; t += blockDim.x) {
         const int e = t % EB, a = t / EB;
-        double val = 0.0;
-        if (e < ne) {
-            int c[3];
-            coords(m, s_k[e], c);
-            val = m.inv2h[a][c[a]];
-        }
-        s_ih[t] = val;
+        s_ih[t] = (e < ne) ? pa_inv2h(m, pk, s_k[e], a) : 0.0;
     }
     __syncthreads();
     const int t = threadIdx.x;
@@ -1164,20 +1274,13 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_pa_volume(MeshK m, SrcK
     const bool active = (t < NP * EB) && (e < ne);
     double acc[NV];
     divergence<DIM, P, EB, EB>(ops, ph, s_u, s_t, s_fm, s_fp, s_ih, active, e, i, acc);
-    // the padding entries (R = 0 there)
+    // the padding entries: 0 (the inputs' padding is not read)
     const int npad = pk.NpM - NP;
     for (int u = threadIdx.x; u < NV * npad * EB; u += blockDim.x) {
         const int e2 = u % EB, r = u / EB;
         if (e2 >= ne) continue;
         const int v = r / npad, i2 = NP + r % npad;
-        const size_t idx = ((size_t)v * pk.NpM + i2) * Ne + s_k[e2];
-        if (OUT == OUT_R) {
-            o.r[idx] = 0.0;
-        } else {
-            double val = o.sigma * o.vdir[idx] - (0.0 - o.r0[idx]) / (alpha * o.dscale);
-            if (o.x) val -= o.x[idx];
-            o.r[idx] = val;
-        }
+        o.r[((size_t)v * pk.NpM + i2) * Ne + s_k[e2]] = 0.0;
     }
     if (!active) return;
     const int k = s_k[e];
@@ -1192,6 +1295,63 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_pa_volume(MeshK m, SrcK
             if (o.x) val -= o.x[idx];
             o.r[idx] = val;
         }
+    }
+}
+
+// One launch per phase for every class: workgroups [boff[P], boff[P + 1])
+// take class P (its elements cls[eoff[P] .. eoff[P + 1])), the body is the
+// class's own compile-time instantiation and the LDS is carved from one
+// dynamic buffer sized for the largest class.
+struct PaGrid {
+    const int *cls;
+    int eoff[kMaxP + 2];
+    int boff[kMaxP + 2];
+};
+
+__device__ __forceinline__ int pa_class_of(const PaGrid &g, int b) {
+    int P = 1;
+    while (P < kMaxP && b >= g.boff[P + 1]) ++P;
+    return P;
+}
+
+template <int DIM, int MODE>
+__global__ void __launch_bounds__(DIM == 2 ? 128 : 192) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_pa_faces_all(MeshK m, SrcK src, Phys ph, PaK pk, PaGrid g, double *__restrict__ Jp, double *__restrict__ Fs) {
+    extern __shared__ double lds[];
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int P = pa_class_of(g, b);
+    pk.list = g.cls + g.eoff[P];
+    pk.count = g.eoff[P + 1] - g.eoff[P];
+    const int blk = b - g.boff[P];
+    switch (P) {
+        case 1: pa_faces_body<DIM, 1, MODE>(m, src, ph, pk, Jp, Fs, blk, lds); break;
+        case 2: pa_faces_body<DIM, 2, MODE>(m, src, ph, pk, Jp, Fs, blk, lds); break;
+        case 3: pa_faces_body<DIM, 3, MODE>(m, src, ph, pk, Jp, Fs, blk, lds); break;
+        case 4: pa_faces_body<DIM, 4, MODE>(m, src, ph, pk, Jp, Fs, blk, lds); break;
+        default:
+            if constexpr (DIM == 2) pa_faces_body<DIM, 5, MODE>(m, src, ph, pk, Jp, Fs, blk, lds);
+            break;
+    }
+}
+
+template <int DIM, int MODE, int OUT>
+__global__ void __launch_bounds__(256) k_pa_volume_all(MeshK m, SrcK src, Phys ph, PaK pk, PaGrid g,
+                                                       const double *__restrict__ Jp, const double *__restrict__ Fs,
+                                                       OutK o) {
+    extern __shared__ double lds[];
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int P = pa_class_of(g, b);
+    pk.list = g.cls + g.eoff[P];
+    pk.count = g.eoff[P + 1] - g.eoff[P];
+    const int blk = b - g.boff[P];
+    switch (P) {
+        case 1: pa_volume_body<DIM, 1, MODE, OUT>(m, src, ph, pk, Jp, Fs, o, blk, lds); break;
+        case 2: pa_volume_body<DIM, 2, MODE, OUT>(m, src, ph, pk, Jp, Fs, o, blk, lds); break;
+        case 3: pa_volume_body<DIM, 3, MODE, OUT>(m, src, ph, pk, Jp, Fs, o, blk, lds); break;
+        case 4: pa_volume_body<DIM, 4, MODE, OUT>(m, src, ph, pk, Jp, Fs, o, blk, lds); break;
+        default:
+            if constexpr (DIM == 2) pa_volume_body<DIM, 5, MODE, OUT>(m, src, ph, pk, Jp, Fs, o, blk, lds);
+            break;
     }
 }
 
@@ -1212,38 +1372,54 @@ __device__ __forceinline__ int elem_colour(const MeshK &m, int k) {
     return (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
 }
 
-// v[j][k] = the step of entry j of every element k of the colour that has it
-// (set), or 0 (clear)
-__global__ void k_pa_fd_set(MeshK m, const int *__restrict__ Pk, int colour, int j, int NpM, Phys ph,
-                            const double *__restrict__ dq, double *__restrict__ v, int set) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m.Ne || elem_colour(m, k) != colour) return;
-    const int P = Pk[k];
-    const int np = (m.dim == 2) ? P * P : P * P * P;
-    if (j % NpM >= np) return;
-    const size_t idx = (size_t)j * m.Ne + k;
-    v[idx] = set ? fd_step(ph.qinf[j / NpM], dq[idx]) : 0.0;
+// Copy b of a batch of perturbed states: dq plus, on the elements of the
+// colour of pair t0 + b, the step of that pair's column (pair t: colour
+// t / n_b, column t % n_b; pairs beyond npairs are left unperturbed).
+// qB is [nv][NpM][B ne0].
+__global__ void k_pa_fd_perturb(MeshK m, const int *__restrict__ Pk, int NpM, int nv, int nb, int B, int t0,
+                                int npairs, Phys ph, const double *__restrict__ dq, double *__restrict__ qB) {
+    const int ne0 = m.Ne;
+    const size_t total = (size_t)nv * NpM * B * ne0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int k = (int)(t % ne0);
+        const size_t r = t / ne0;
+        const int b = (int)(r % B);
+        const int vi = (int)(r / B);
+        const double base = dq[(size_t)vi * ne0 + k];
+        double val = base;
+        const int pair = t0 + b;
+        if (pair < npairs && vi == pair % nb && elem_colour(m, k) == pair / nb) {
+            const int P = Pk[k];
+            const int np = (m.dim == 2) ? P * P : P * P * P;
+            if (vi % NpM < np) val = base + fd_step(ph.qinf[vi / NpM], base);
+        }
+        qB[t] = val;
+    }
 }
 
-// column j of B_k = sigma e_j - (R_k(q + h e_j) - R_k(q)) / h on the valid rows
-__global__ void k_pa_fd_extract(MeshK m, const int *__restrict__ Pk, int colour, int j, int NpM, int nb,
-                                const double *__restrict__ dq, const double *__restrict__ v,
-                                const double *__restrict__ rp, const double *__restrict__ r0, double sigma,
-                                double *__restrict__ B) {
+// column j of B_k = sigma e_j - (R_k(q + h e_j) - R_k(q)) / h on the valid
+// rows, for the elements perturbed in copy b (pair t0 + b)
+__global__ void k_pa_fd_extract(MeshK m, const int *__restrict__ Pk, int NpM, int nb, int B, int t0, int npairs,
+                                Phys ph, const double *__restrict__ dq, const double *__restrict__ rB,
+                                const double *__restrict__ r0, double sigma, double *__restrict__ Bk) {
+    const int ne0 = m.Ne;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (size_t)m.Ne * nb) return;
-    const int k = (int)(t % m.Ne), row = (int)(t / m.Ne);
-    if (elem_colour(m, k) != colour) return;
+    if (t >= (size_t)B * nb * ne0) return;
+    const int k = (int)(t % ne0);
+    const size_t r = t / ne0;
+    const int row = (int)(r % nb), b = (int)(r / nb);
+    const int pair = t0 + b;
+    if (pair >= npairs || elem_colour(m, k) != pair / nb) return;
+    const int j = pair % nb;
     const int P = Pk[k];
     const int np = (m.dim == 2) ? P * P : P * P * P;
     if (j % NpM >= np || row % NpM >= np) return;
-    const size_t jc = (size_t)j * m.Ne + k;
-    const double base = dq[jc];
-    const double hact = (base + v[jc]) - base;
-    const size_t idx = (size_t)row * m.Ne + k;
-    double val = -(rp[idx] - r0[idx]) / hact;
+    const double base = dq[(size_t)j * ne0 + k];
+    const double hact = (base + fd_step(ph.qinf[j / NpM], base)) - base;
+    double val = -(rB[((size_t)row * B + b) * ne0 + k] - r0[(size_t)row * ne0 + k]) / hact;
     if (row == j) val += sigma;
-    B[(size_t)k * nb * nb + (size_t)j * nb + row] = val;
+    Bk[(size_t)k * nb * nb + (size_t)j * nb + row] = val;
 }
 
 // ---- per-element transfers, indicator and degree update ------------------
@@ -1355,53 +1531,96 @@ __global__ void __launch_bounds__(1024) k_pa_adapt(int Ne, const double *__restr
 
 // ---- launchers ------------------------------------------------------------
 
-template <int DIM, int P, int MODE, int OUT>
-void pa_class(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, const PaK &base, bool faces_phase,
-              hipStream_t s) {
-    using S = Shape<DIM, P>;
-    PaK pk = base;
-    pk.list = L.pa->cls + L.pa->cls_off[P];
-    pk.count = L.pa->cls_off[P + 1] - L.pa->cls_off[P];
-    if (pk.count <= 0) return;
-    const Ops1D &ops = ctx->pa_tab_host->ops[P];
-    SrcK src{a.dq, a.v, a.alpha, L.Np};
-    if (faces_phase) {
-        const dim3 g((pk.count + S::EBF - 1) / S::EBF);
-        hipLaunchKernelGGL((k_pa_faces<DIM, P, MODE>), g, dim3(S::NTF), 0, s, ctx->mesh, src, ops, ctx->phys, pk,
-                           L.Jp, L.Fs);
-    } else {
-        OutK o{a.r, a.r0, a.x, a.v, a.sigma, a.dscale};
-        const dim3 g((pk.count + S::EB - 1) / S::EB);
-        hipLaunchKernelGGL((k_pa_volume<DIM, P, MODE, OUT>), g, dim3(S::NT), 0, s, ctx->mesh, src, ops, ctx->phys,
-                           pk, L.Jp, L.Fs, o);
+// The elements one mixed-degree evaluation covers: a level, or fdB
+// perturbed copies of it (ids b Ne + k), with the lists and face buffers
+// sized for them.
+struct PaSet {
+    MeshK m;  // the level's mesh; Ne = every id of the set
+    int ne0;
+    const int *Pk, *cls, *mixed;
+    const int *cls_off;  // host
+    int nmixed;
+    double *Jp, *Fs, *Fm, *Mq, *Mn, *Mg;
+};
+
+PaSet pa_level_set(const frpmg_ctx *ctx, const Level &L) {
+    const PaLevel &pa = *L.pa;
+    return PaSet{ctx->mesh, ctx->mesh.Ne, pa.Pk, pa.cls, pa.mixed, pa.cls_off, pa.nmixed,
+                 L.Jp, L.Fs, pa.Fm, pa.Mq, pa.Mn, pa.Mg};
+}
+
+PaSet pa_batch_set(const frpmg_ctx *ctx, const Level &L) {
+    const PaLevel &pa = *L.pa;
+    MeshK m = ctx->mesh;
+    m.Ne = ctx->mesh.Ne * pa.fdB;
+    return PaSet{m, ctx->mesh.Ne, pa.PkB, pa.clsB, pa.mixedB, pa.clsB_off, pa.nmixed * pa.fdB,
+                 pa.JpB, pa.FsB, pa.FmB, pa.MqB, pa.MnB, pa.MgB};
+}
+
+template <int DIM>
+constexpr int pa_max_p() {
+    return DIM == 2 ? 5 : 4;
+}
+
+// workgroup ranges of the classes for one phase, and the LDS the largest needs
+template <int DIM, bool FACES>
+size_t pa_grid(const PaSet &ps, PaGrid &g) {
+    g.cls = ps.cls;
+    size_t lds = 0;
+    int nb = 0;
+    auto one = [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        constexpr int EB = FACES ? PaFacesLds<DIM, P>::EB : PaVolLds<DIM, P>::EB;
+        constexpr int DBL = FACES ? PaFacesLds<DIM, P>::DOUBLES : PaVolLds<DIM, P>::DOUBLES;
+        const int cnt = ps.cls_off[P + 1] - ps.cls_off[P];
+        g.eoff[P] = ps.cls_off[P];
+        g.boff[P] = nb;
+        nb += (cnt + EB - 1) / EB;
+        if (cnt > 0) lds = std::max(lds, (size_t)DBL * sizeof(double));
+    };
+    one(std::integral_constant<int, 1>{});
+    one(std::integral_constant<int, 2>{});
+    one(std::integral_constant<int, 3>{});
+    one(std::integral_constant<int, 4>{});
+    if constexpr (DIM == 2) one(std::integral_constant<int, 5>{});
+    for (int P = pa_max_p<DIM>() + 1; P <= kMaxP + 1; ++P) {
+        g.eoff[P] = ps.cls_off[pa_max_p<DIM>() + 1];
+        g.boff[P] = nb;
     }
+    g.eoff[0] = g.boff[0] = 0;
+    return lds;
 }
 
 template <int DIM, int MODE, int OUT>
-hipError_t pa_run(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, hipStream_t s) {
-    const PaLevel &pa = *L.pa;
-    PaK base{pa.Pk, nullptr, 0, L.Np, L.NF, ctx->pa_tab, pa.Fm, pa.Mq, pa.Mn, pa.Mg};
-    for (int phase = 0; phase < 2; ++phase) {
-        const bool faces = phase == 0;
-        pa_class<DIM, 1, MODE, OUT>(ctx, L, a, base, faces, s);
-        pa_class<DIM, 2, MODE, OUT>(ctx, L, a, base, faces, s);
-        pa_class<DIM, 3, MODE, OUT>(ctx, L, a, base, faces, s);
-        pa_class<DIM, 4, MODE, OUT>(ctx, L, a, base, faces, s);
-        if constexpr (DIM == 2) pa_class<DIM, 5, MODE, OUT>(ctx, L, a, base, faces, s);
-        if (faces && pa.nmixed > 0) {
-            constexpr int FB = 64 / ((DIM == 2) ? kMaxP : kMaxNF3);
-            hipLaunchKernelGGL((k_pa_mortar<DIM>), dim3((pa.nmixed + FB - 1) / FB), dim3(64), 0, s, ctx->mesh,
-                               ctx->phys, base, pa.mixed, pa.nmixed, L.Fs);
-        }
+hipError_t pa_run(const frpmg_ctx *ctx, const Level &L, const PaSet &ps, const ResidualArgs &a, hipStream_t s) {
+    PaK pk{ps.Pk, nullptr, 0, ps.ne0, L.Np, L.NF, ctx->pa_tab, ps.Fm, ps.Mq, ps.Mn, ps.Mg};
+    SrcK src{a.dq, a.v, a.alpha, L.Np};
+    PaGrid gf, gv;
+    const size_t lf = pa_grid<DIM, true>(ps, gf), lv = pa_grid<DIM, false>(ps, gv);
+    const int nf = gf.boff[kMaxP + 1], nv = gv.boff[kMaxP + 1];
+    if (nf > 0) {
+        hipLaunchKernelGGL((k_pa_faces_all<DIM, MODE>), dim3(nf), dim3(DIM == 2 ? 128 : 192), lf, s, ps.m, src,
+                           ctx->phys, pk, gf, ps.Jp, ps.Fs);
+    }
+    if (ps.nmixed > 0) {
+        constexpr int FB = 64 / ((DIM == 2) ? kMaxP : kMaxNF3);
+        hipLaunchKernelGGL((k_pa_mortar<DIM>), dim3((ps.nmixed + FB - 1) / FB), dim3(64), 0, s, ps.m, ctx->phys, pk,
+                           ps.mixed, ps.nmixed, ps.Fs);
+    }
+    if (nv > 0) {
+        OutK o{a.r, a.r0, a.x, a.v, a.sigma, a.dscale};
+        hipLaunchKernelGGL((k_pa_volume_all<DIM, MODE, OUT>), dim3(nv), dim3(256), lv, s, ps.m, src, ctx->phys, pk,
+                           gv, ps.Jp, ps.Fs, o);
     }
     return hipGetLastError();
 }
 
 template <int DIM>
-hipError_t pa_dispatch(const frpmg_ctx *ctx, const Level &L, const ResidualArgs &a, hipStream_t s) {
-    if (a.src == SRC_PLAIN && a.out == OUT_R) return pa_run<DIM, SRC_PLAIN, OUT_R>(ctx, L, a, s);
-    if (a.src == SRC_AXPY && a.out == OUT_R) return pa_run<DIM, SRC_AXPY, OUT_R>(ctx, L, a, s);
-    if (a.src == SRC_AXPY && a.out == OUT_LIN) return pa_run<DIM, SRC_AXPY, OUT_LIN>(ctx, L, a, s);
+hipError_t pa_dispatch(const frpmg_ctx *ctx, const Level &L, const PaSet &ps, const ResidualArgs &a,
+                       hipStream_t s) {
+    if (a.src == SRC_PLAIN && a.out == OUT_R) return pa_run<DIM, SRC_PLAIN, OUT_R>(ctx, L, ps, a, s);
+    if (a.src == SRC_AXPY && a.out == OUT_R) return pa_run<DIM, SRC_AXPY, OUT_R>(ctx, L, ps, a, s);
+    if (a.src == SRC_AXPY && a.out == OUT_LIN) return pa_run<DIM, SRC_AXPY, OUT_LIN>(ctx, L, ps, a, s);
     return hipErrorInvalidValue;
 }
 
@@ -1493,7 +1712,8 @@ hipError_t launch_residual_batch(const frpmg_ctx *ctx, int level, int batch, con
 hipError_t launch_residual_pa(const frpmg_ctx *ctx, int level, const ResidualArgs &a, hipStream_t s) {
     const Level &L = ctx->lv[level];
     if (!L.pa || !ctx->pa_tab || !ctx->pa_tab_host) return hipErrorInvalidValue;
-    return ctx->dim == 2 ? pa_dispatch<2>(ctx, L, a, s) : pa_dispatch<3>(ctx, L, a, s);
+    const PaSet ps = pa_level_set(ctx, L);
+    return ctx->dim == 2 ? pa_dispatch<2>(ctx, L, ps, a, s) : pa_dispatch<3>(ctx, L, ps, a, s);
 }
 
 hipError_t launch_ej_form_pa(const frpmg_ctx *ctx, int level, const double *dq, double sigma, hipStream_t s,
@@ -1513,25 +1733,26 @@ hipError_t launch_ej_form_pa(const frpmg_ctx *ctx, int level, const double *dq, 
     if (err != hipSuccess) return err;
     const size_t total = (size_t)m.Ne * L.nb * L.nb;
     hipLaunchKernelGGL(k_pa_blk_identity, dim3(4096), dim3(256), 0, s, total, L.nb, out);
-    const dim3 ge((m.Ne + 255) / 256);
-    const dim3 gx((unsigned)(((size_t)m.Ne * L.nb + 255) / 256));
+    // (colour, column) pairs, fdB per evaluation of the perturbed copies
+    const PaSet ps = pa_batch_set(ctx, L);
+    const int B = pa.fdB;
+    const int npairs = (1 << ctx->dim) * L.nb;
+    const size_t nq = (size_t)ctx->nv * L.Np * B * m.Ne;
+    const dim3 gq((unsigned)std::min<size_t>((nq + 255) / 256, 65536));
+    const dim3 gx((unsigned)(((size_t)B * L.nb * m.Ne + 255) / 256));
     ResidualArgs ap;
-    ap.src = SRC_AXPY;
-    ap.dq = dq;
-    ap.v = pa.fdv;
-    ap.alpha = Scal{1.0, nullptr};
+    ap.src = SRC_PLAIN;
+    ap.dq = pa.qB;
     ap.out = OUT_R;
-    ap.r = pa.fdr;
-    const int ncol = 1 << ctx->dim;
-    for (int colour = 0; colour < ncol; ++colour)
-        for (int j = 0; j < L.nb; ++j) {
-            hipLaunchKernelGGL(k_pa_fd_set, ge, dim3(256), 0, s, m, pa.Pk, colour, j, L.Np, ctx->phys, dq, pa.fdv, 1);
-            err = launch_residual_pa(ctx, level, ap, s);
-            if (err != hipSuccess) return err;
-            hipLaunchKernelGGL(k_pa_fd_extract, gx, dim3(256), 0, s, m, pa.Pk, colour, j, L.Np, L.nb, dq, pa.fdv,
-                               pa.fdr, L.r0, sigma, out);
-            hipLaunchKernelGGL(k_pa_fd_set, ge, dim3(256), 0, s, m, pa.Pk, colour, j, L.Np, ctx->phys, dq, pa.fdv, 0);
-        }
+    ap.r = pa.rB;
+    for (int t0 = 0; t0 < npairs; t0 += B) {
+        hipLaunchKernelGGL(k_pa_fd_perturb, gq, dim3(256), 0, s, m, pa.Pk, L.Np, ctx->nv, L.nb, B, t0, npairs,
+                           ctx->phys, dq, pa.qB);
+        err = ctx->dim == 2 ? pa_dispatch<2>(ctx, L, ps, ap, s) : pa_dispatch<3>(ctx, L, ps, ap, s);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k_pa_fd_extract, gx, dim3(256), 0, s, m, pa.Pk, L.Np, L.nb, B, t0, npairs, ctx->phys,
+                           dq, pa.rB, L.r0, sigma, out);
+    }
     return hipGetLastError();
 }
 

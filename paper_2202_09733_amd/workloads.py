@@ -327,11 +327,12 @@ def sample_pa(deg, n, h, dim, fn):
 
 
 def make_padapt_workload(n=(32, 32), p_max=4, Ma=0.1, Re=1000.0, seed=6, dt_factor=100.0, amp=5e-2,
-                         kmax=4, ring=0.125, name="p-adaptive vortical"):
+                         kmax=4, ring=0.125, uniform=False, name="p-adaptive vortical"):
     """2D periodic unit square with the vortical perturbation of
     ``make_vortical_workload`` (uniform elements, |u'| <= amp) and the
     degree map ``degree_rings`` (p_max at the centre down to 1); each element
-    holds the field at its own points.  First ROW stage."""
+    holds the field at its own points.  First ROW stage.  uniform=True: the
+    same mesh, field and step with p_max on every element."""
     dim = 2
     h = [np.full(n[a], 1.0 / n[a]) for a in range(dim)]
     rng = np.random.default_rng(seed)
@@ -356,6 +357,8 @@ def make_padapt_workload(n=(32, 32), p_max=4, Ma=0.1, Re=1000.0, seed=6, dt_fact
     u0, v0 = vel(Xf, Yf)
     scale = amp / float(np.max(np.sqrt(u0 * u0 + v0 * v0)))
     deg = degree_rings(n, p_max, ring=ring)
+    if uniform:
+        deg = np.full_like(deg, p_max)
 
     def field(X):
         up, vp = vel(X[0], X[1])
