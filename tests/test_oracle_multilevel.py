@@ -114,3 +114,21 @@ def test_pmg_nonlinear_solver_with_refreshed_smoothers(orc):
     q3, _ = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), max_vcycles=3, tol=0.0, refresh=2)
     q3b, _ = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, n=(2, 4), max_vcycles=3, tol=0.0)
     assert not np.array_equal(q3, q3b)
+
+
+def test_three_level_nonlinear_solver_diverges_on_the_vortical_stage(orc):
+    """Behaviour of the method itself under these readings: on a 16 x 16
+    version of the low-Mach vortical ESDIRK stage (p{4-2} / p{4-2-1},
+    n{2-2}/{2-2-2}, dtau = dt) the two-level pMG nonlinear solver contracts
+    (1.3e-5 of its starting residual after 20 V-cycles, 7.8e-9 after 60)
+    while the three-level one grows (9x after 20, 1.2e6x after 60 V-cycles).
+    The GPU's three-level nonlinear solver diverges on the full-size stage in
+    the same way, so that divergence is the method's, not the port's."""
+    wl = W.make_vortical_workload(n=(16, 16), dt_factor=1000.0)
+    out = {}
+    for hier in ((4, 2), (4, 2, 1)):
+        levels = [orc.Level(**wl.level_kwargs(p)) for p in hier]
+        _, st = ML.pmg_nonlinear_stage(levels, wl.dq, wl.dt, wl.a_ii, tol=1e-8, max_vcycles=20)
+        out[hier] = st.rel_res
+    assert out[(4, 2)] < 1e-4
+    assert out[(4, 2, 1)] > 1.0
