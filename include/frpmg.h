@@ -165,8 +165,9 @@ fr_status ej_get_inverse(frpmg_ctx *ctx, int level, double *host_out);
  * One factorisation per context, for one level.
  *
  * mbnk_factor: assemble A at dq_lin (that level's state) and factor it.
- *   Needs an even element count >= 4 per axis and blocks of at most 128
- *   unknowns (FR_EINVAL otherwise).  Allocates its workspace at the first
+ *   Needs an even element count >= 4 per axis and blocks of at most 136
+ *   unknowns, i.e. every 2D level and the 3D levels up to p = 2 (135)
+ *   (FR_EINVAL otherwise).  Allocates its workspace at the first
  *   call for a level (the blocks take (3 + 2 dim) Ne nb^2 doubles, the
  *   formation batch up to 128 MiB per buffer).  Synchronises the stream;
  *   FR_ESINGULAR on a zero pivot, FR_ENONFINITE on a NaN or infinite one.

@@ -22,7 +22,7 @@ namespace frpmg {
 namespace {
 
 constexpr int kGJThreads = 256;
-constexpr int kMaxLdsBlock = 128;
+constexpr int kMaxLdsBlock = kMbnkMaxNb;  // LDS form: EJ blocks up to 64, MBNK blocks up to 136 (147 KB of LDS)
 
 __device__ __forceinline__ void argmax_combine(double &v, int &i, double v2, int i2) {
     if (v2 > v || (v2 == v && i2 < i)) {

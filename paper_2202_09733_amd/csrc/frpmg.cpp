@@ -333,7 +333,7 @@ void mbnk_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma,
     REQUIRE(level >= 0 && level < ctx->nlevels, "bad level");
     Level &L = ctx->lv[level];
     REQUIRE(!L.pa, "MBNK smoothing is not available on mixed-degree levels");
-    REQUIRE(L.nb <= 128 && L.nb % 2 == 0, "MBNK takes element blocks of at most 128 unknowns");
+    REQUIRE(L.nb <= kMbnkMaxNb, "MBNK takes element blocks of at most 136 unknowns");
     for (int a = 0; a < ctx->dim; ++a)
         REQUIRE(ctx->mesh.n[a] >= 4 && ctx->mesh.n[a] % 2 == 0,
                 "MBNK needs an even element count of at least 4 per axis (red-black order, distinct neighbours)");

@@ -362,6 +362,9 @@ hipError_t invert_blocks_f64(int count, int nb, const double *in, double *out, i
 
 // mbnk.hip
 constexpr int kMbnkMaxIt = 8;
+// largest MBNK block (the 3D p = 2 coarse level has 135 unknowns per element);
+// its LDS Gauss-Jordan and Schur products keep a whole FP64 block in LDS
+constexpr int kMbnkMaxNb = 136;
 // colour-batch kernels of the neighbour-block formation: pairs p0 .. p0 + cnt - 1
 // (pair = colour nb + column) perturbed into qb ([nv][Np][cnt Ne]); their
 // residuals rb extracted into the off-diagonal blocks

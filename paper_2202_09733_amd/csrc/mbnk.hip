@@ -154,10 +154,11 @@ enum RowMode { MB_MATVEC = 0, MB_INV = 1, MB_NBR_INV = 2, MB_MATVEC_BLACK = 3 };
 //               (L = I and U = A there), the product on black ones (pairs c)
 // Inv holds one block per pair index c of the colour.  Each lane owns two
 // consecutive rows of one element and reads them with one 16-byte load per
-// block column; the columns of every block are split into S contiguous
+// block column (an odd block size, whose columns alternate 16-byte alignment,
+// takes two 8-byte loads and leaves the last lane's second row empty); the columns of every block are split into S contiguous
 // ranges on S lane groups (more lanes in flight on the small coarse level),
 // whose partial sums meet in LDS and are added in range order.
-template <int MODE>
+template <int MODE, bool EVEN>
 __global__ void __launch_bounds__(kThreads) k_mb_rows(MeshK m, int nb, int nface, int epb, int S, int col,
                                                       int count, const double *__restrict__ D,
                                                       const double *__restrict__ O,
@@ -206,11 +207,12 @@ __global__ void __launch_bounds__(kThreads) k_mb_rows(MeshK m, int nb, int nface
         }
     }
     __syncthreads();
-    const int tpe = nb / 2, lpe = tpe * S;
+    const int tpe = (nb + 1) / 2, lpe = tpe * S;
     const int e = threadIdx.x / lpe;
     const int rem = threadIdx.x - e * lpe;
     const int sg = rem / tpe;
     const int row = (rem - sg * tpe) * 2;
+    const bool two = EVEN || row + 1 < nb;  // the lane's second row exists
     const bool active = e < ne;
     const int cs = (nb + S - 1) / S;
     const int j0 = min(nb, sg * cs), j1 = min(nb, j0 + cs);
@@ -220,32 +222,40 @@ __global__ void __launch_bounds__(kThreads) k_mb_rows(MeshK m, int nb, int nface
         if (S == 1) return;
         if (active) {
             s_p[((size_t)e * S + sg) * nb + row] = a0;
-            s_p[((size_t)e * S + sg) * nb + row + 1] = a1;
+            if (two) s_p[((size_t)e * S + sg) * nb + row + 1] = a1;
         }
         __syncthreads();
         if (active && sg == 0) {
             a0 = s_p[(size_t)e * S * nb + row];
-            a1 = s_p[(size_t)e * S * nb + row + 1];
+            a1 = two ? s_p[(size_t)e * S * nb + row + 1] : 0.0;
             for (int q = 1; q < S; ++q) {
                 a0 += s_p[((size_t)e * S + q) * nb + row];
-                a1 += s_p[((size_t)e * S + q) * nb + row + 1];
+                if (two) a1 += s_p[((size_t)e * S + q) * nb + row + 1];
             }
         }
         __syncthreads();
+    };
+    // two rows of column j: one 16-byte load, or two 8-byte ones (odd n_b)
+    auto ld2 = [&](const double *p) -> double2 {
+        if constexpr (EVEN) {
+            return *reinterpret_cast<const double2 *>(p);
+        } else {
+            return double2{p[0], two ? p[1] : 0.0};
+        }
     };
     auto gemv = [&](const double *blk, const double *xv, double &a0, double &a1) {
         blk += row;
         int j = j0;
         for (; j + 4 <= j1; j += 4) {
-            const double2 v0 = *reinterpret_cast<const double2 *>(blk + (size_t)j * nb);
-            const double2 v1 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 1) * nb);
-            const double2 v2 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 2) * nb);
-            const double2 v3 = *reinterpret_cast<const double2 *>(blk + (size_t)(j + 3) * nb);
+            const double2 v0 = ld2(blk + (size_t)j * nb);
+            const double2 v1 = ld2(blk + (size_t)(j + 1) * nb);
+            const double2 v2 = ld2(blk + (size_t)(j + 2) * nb);
+            const double2 v3 = ld2(blk + (size_t)(j + 3) * nb);
             a0 += (v0.x * xv[j] + v1.x * xv[j + 1]) + (v2.x * xv[j + 2] + v3.x * xv[j + 3]);
             a1 += (v0.y * xv[j] + v1.y * xv[j + 1]) + (v2.y * xv[j + 2] + v3.y * xv[j + 3]);
         }
         for (; j < j1; ++j) {
-            const double2 v0 = *reinterpret_cast<const double2 *>(blk + (size_t)j * nb);
+            const double2 v0 = ld2(blk + (size_t)j * nb);
             a0 += v0.x * xv[j];
             a1 += v0.y * xv[j];
         }
@@ -265,13 +275,13 @@ __global__ void __launch_bounds__(kThreads) k_mb_rows(MeshK m, int nb, int nface
         if (active && sg == 0) {
             const int k = s_k[e];
             y[(size_t)row * m.Ne + k] = a0;
-            y[(size_t)(row + 1) * m.Ne + k] = a1;
+            if (two) y[(size_t)(row + 1) * m.Ne + k] = a1;
         }
         return;
     }
     if (MODE == MB_NBR_INV && active && sg == 0) {
         s_t[e * nb + row] -= a0;
-        s_t[e * nb + row + 1] -= a1;
+        if (two) s_t[e * nb + row + 1] -= a1;
     }
     __syncthreads();
     double b0 = 0.0, b1 = 0.0;
@@ -280,7 +290,7 @@ __global__ void __launch_bounds__(kThreads) k_mb_rows(MeshK m, int nb, int nface
     if (active && sg == 0) {
         const int k = s_k[e];
         y[(size_t)row * m.Ne + k] = b0;
-        y[(size_t)(row + 1) * m.Ne + k] = b1;
+        if (two) y[(size_t)(row + 1) * m.Ne + k] = b1;
     }
 }
 
@@ -362,7 +372,7 @@ unsigned grid_1d(size_t n) {
 // Column ranges per block: up to 4, while the launch has fewer than 256k
 // lanes (4 wavefronts per SIMD) and every range keeps at least 4 columns.
 int row_split(int nb, int count) {
-    const int tpe = nb / 2;
+    const int tpe = (nb + 1) / 2;
     int S = 1;
     while (S < 4 && (size_t)count * tpe * S < (256u << 10) && nb / (2 * S) >= 4 && tpe * 2 * S <= kThreads) S *= 2;
     return S;
@@ -372,16 +382,20 @@ template <int MODE>
 hipError_t launch_rows(const frpmg_ctx *ctx, const Mbnk &mb, int col, const double *Inv, const double *x,
                        const double *r, double *y, hipStream_t s) {
     const int nb = mb.nb;
-    if (nb % 2 || nb < 4 || nb > 128) return hipErrorInvalidValue;
+    if (nb < 4 || nb > kMbnkMaxNb) return hipErrorInvalidValue;
     const int count = (MODE == MB_MATVEC) ? mb.Ne : mb.Ne / 2;
     const int S = row_split(nb, MODE == MB_MATVEC_BLACK ? mb.Ne : count);
-    const int lpe = (nb / 2) * S;
+    const int lpe = ((nb + 1) / 2) * S;
     const int epb = std::min(64, std::max(1, kThreads / lpe));
     const size_t lds = ((size_t)epb * (mb.nface + 1) * nb + (size_t)epb * nb * (1 + S)) * sizeof(double);
     const dim3 grid((count + epb - 1) / epb);
     const dim3 block((epb * lpe + 63) / 64 * 64);
-    hipLaunchKernelGGL((k_mb_rows<MODE>), grid, block, lds, s, ctx->mesh, nb, mb.nface, epb, S, col, count, mb.D,
-                       mb.O, Inv, x, r, y);
+    if (nb % 2 == 0)
+        hipLaunchKernelGGL((k_mb_rows<MODE, true>), grid, block, lds, s, ctx->mesh, nb, mb.nface, epb, S, col, count,
+                           mb.D, mb.O, Inv, x, r, y);
+    else
+        hipLaunchKernelGGL((k_mb_rows<MODE, false>), grid, block, lds, s, ctx->mesh, nb, mb.nface, epb, S, col,
+                           count, mb.D, mb.O, Inv, x, r, y);
     return hipGetLastError();
 }
 

@@ -28,10 +28,13 @@ def _block_bar(fr, ol, dq, level, scale):
     return max(1e-10, 10 * 2 * max(dR, U) * np.abs(rq).max() / 1e-7 / scale)
 
 
-CASES = [(2, (10, 8), 1, 30.0), (2, (6, 4), 2, 50.0), (3, (4, 4, 4), 1, 20.0), (2, (8, 6), 0, 20.0)]
+CASES = [(2, (10, 8), 1, 30.0), (2, (6, 4), 2, 50.0), (3, (4, 4, 4), 1, 20.0), (2, (8, 6), 0, 20.0),
+         (3, (4, 4, 4), 2, 20.0)]
 
 
-@pytest.fixture(scope="module", params=CASES, ids=["2d_p1", "2d_p2", "3d_p1", "2d_p0"])
+# 3d_p2: the 3D p = 2 coarse level, 135^2 blocks (odd: the block-row kernel
+# takes its two-loads path); the oracle's assembly takes ~35 s of host time
+@pytest.fixture(scope="module", params=CASES, ids=["2d_p1", "2d_p2", "3d_p1", "2d_p0", "3d_p2"])
 def factored(request, orc):
     require_gpu()
     from oracle import mbnk as MB
@@ -179,6 +182,37 @@ def test_pmg_apply_mbnk_parity(orc, ps):
     print("p%s MBNK-coarse cycle vs oracle %.2e; vs the EJ-coarse cycle %.2e" % (ps, e, rel(Y, pm_ej.apply(X))))
     assert e <= 1e-6
     assert rel(Y_ref, pm_ej.apply(X)) > 1e-4
+
+
+def test_pmg_apply_mbnk_parity_3d(orc):
+    """3D p{3-2}: the V-cycle with MBNK sweeps on the p = 2 level (135^2
+    blocks) against the oracle's on a 4^3 Taylor-Green state."""
+    require_gpu()
+    from oracle import multilevel as ML
+    announce("pmg apply MBNK coarse 3D p{3-2}")
+    wl = W.make_tgv_workload(n=(4, 4, 4), p0=3, p1=2, dt_factor=20.0)
+    fr = capi.FR.from_workload(wl, levels=[3, 2])
+    levels = [orc.Level(**wl.level_kwargs(p)) for p in (3, 2)]
+    sigA = 1.0 / wl.dt + 1.0 / (wl.a_ii * wl.dt)
+    sigS = 1.0 / wl.dt + sigA
+    facs = ML.hierarchy_factors(levels, wl.dq, sigS)
+    ilu = ML.coarse_mbnk(levels, wl.dq, sigS)
+    n = (2, 2)
+    pm = ML.MultiPMG(levels, facs, ML.MultiPMGParams(sigma_D=sigA, n=n), coarse_ilu=ilu)
+    rq = levels[0].residual(wl.dq)
+    pm.set_point(wl.dq, rq)
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal(levels[0].shape)
+    X /= np.linalg.norm(X)
+    Y_ref = pm.apply(X)
+    q1 = orc.restrict(wl.dq, 3, 4, 3)
+    fr.ej_factor(0, fr.to_dev(wl.dq), sigS)
+    fr.mbnk_factor(1, fr.to_dev(q1), sigS)
+    fr.pmg_set_point(fr.to_dev(wl.dq), fr.to_dev(rq))
+    Y = fr.pmg_apply(fr.to_dev(X), sigA, n0=2, n1=2, coarse_mode=capi.COARSE_MBNK).cpu().numpy()
+    e = rel(Y, Y_ref)
+    print("3D p{3-2} MBNK-coarse cycle vs the oracle %.2e" % e)
+    assert e <= 1e-6
 
 
 @pytest.mark.parametrize("solver", ["jfnk", "pmg"])
