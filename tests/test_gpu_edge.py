@@ -70,7 +70,7 @@ def test_boundary_rejects_bad_arguments():
     anything, and the context stays usable."""
     require_gpu()
     announce("argument checks")
-    # MBNK needs even element counts >= 4 per axis and blocks of <= 128 unknowns
+    # MBNK needs even element counts >= 4 per axis and blocks of <= 136 unknowns
     wl = W.make_bump_workload(n=(5, 4), p0=2, p1=1, Ma=0.1, seed=3)
     fr = capi.FR.from_workload(wl)
     with pytest.raises(capi.FRError) as ex:
@@ -82,7 +82,7 @@ def test_boundary_rejects_bad_arguments():
     wl = W.make_tgv_workload(n=(4, 4, 4), p0=3, p1=2)
     fr3 = capi.FR.from_workload(wl)
     with pytest.raises(capi.FRError) as ex:
-        fr3.mbnk_factor(1, fr3.to_dev(np.zeros(fr3.shape(1))), 10.0)  # 135 unknowns per block
+        fr3.mbnk_factor(0, fr3.to_dev(np.zeros(fr3.shape(0))), 10.0)  # 320 unknowns per block
     assert ex.value.code == capi.FR_EINVAL
     # degree out of range
     with pytest.raises(capi.FRError):
