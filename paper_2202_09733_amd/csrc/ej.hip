@@ -139,25 +139,35 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_invert(int nb, const double *
 
 // ---------------------------------------------------------------------------
 // Blocked in-place Gauss-Jordan for the larger blocks (100 x 100 in 2D at
-// p = 4; 135 x 135 and 320 x 320 in 3D at p = 2, 3).  Panels of kPanel columns are eliminated in
-// registers (pivot search over the full column, row swaps recorded); the
-// product of the panel's elementary transforms T = (I + W S^T) P (S = the
-// panel's pivot rows) is then applied to every other column at once as a
-// GEMM:
-//     x <- (P x with the pivot rows zeroed) + T_panel (P x)_S,
-// where T_panel = the panel columns just written back.  The row interchanges
-// turn into column interchanges of the result, which are not carried out:
-// the column placement is recorded and the apply gathers r through it.
+// p = 4; 135 x 135 and 320 x 320 in 3D at p = 2, 3).  Sub-panels of kPanel
+// columns are eliminated in registers (pivot search over the full column,
+// row swaps recorded).  The product of a window's elementary transforms is
+// T = (I + W S^T) P (S = the window's pivot rows), and applying it to any
+// other column is one GEMM:
+//     x <- (P x with the pivot rows zeroed) + T_win (P x)_S,
+// where T_win = the window's columns as the elimination left them.  Two
+// sub-panels form one window of kWide columns: the first sub-panel's
+// transform is applied to the second sub-panel's columns only, the second
+// is eliminated, its transform is applied to the first sub-panel's columns
+// only, and the combined transform then updates every other column in one
+// pass -- half the passes over the block set that one update per sub-panel
+// takes, with the same elimination steps.  The row interchanges turn into
+// column interchanges of the result, which are not carried out: the column
+// placement is recorded and the apply gathers r through it.
 // ---------------------------------------------------------------------------
-constexpr int kPanel = 32;
+constexpr int kPanel = 32;                    // columns of one register sub-panel
+constexpr int kWide = 2 * kPanel;             // columns of one update window
+constexpr int kMaxNb = 512;                   // largest block the blocked form takes
+constexpr int kTouch = 2 * kWide;             // S plus at most one moved row per pivot step
+static_assert(kTouchStride == 1 + 2 * kTouch, "touched-row list: count, rows[kTouch], sources[kTouch]");
 
 // The panel kernel also tracks which input row each lane's values came from;
-// at the end it writes the list of touched rows (the panel rows S in order,
+// at the end it writes the list of touched rows (the window rows S in order,
 // then every other row whose content moved, with its source row) that the
 // update kernels use to apply the interchanges to the other columns as a
-// gather.
-constexpr int kTouch = 2 * kPanel;            // S plus at most one moved row per pivot step
-static_assert(kTouchStride == 1 + 2 * kTouch, "touched-row list: count, rows[kTouch], sources[kTouch]");
+// gather.  A row outside S that moved holds the former content of a row of
+// S (contents leave S only by a swap with a later pivot row), so its source
+// lies inside the window's rows.
 
 // Panel factorisation with the panel in registers, two wavefronts per block:
 // lane t of the workgroup owns rows t, t + 128, ... (kPanel values each, RPL
@@ -170,21 +180,24 @@ static_assert(kTouchStride == 1 + 2 * kTouch, "touched-row list: count, rows[kTo
 // from LDS.  The steps are instantiated per panel column so that every
 // register index is a constant (a runtime index would put the rows in scratch
 // memory).  Outputs: the panel columns in place, the pivot rows, the
-// touched-row list and the pivot flags.
+// touched-row lists and the pivot flags.
 constexpr int kPanel2Threads = 128;
 
 struct Panel2Lds {
     double v[2];
     int i[2];
     int cnt[4][2];
-    int porg, corg;
+    int porg, corg, porg2, corg2;
     double pivrow[kPanel];
     double oldc[kPanel];
+    short upos[kMaxNb];  // the first sub-panel's list: slot of row r (-1: untouched)
+    int tsrc[kTouch];
 };
 
 template <int RPL, int CC>
-__device__ __forceinline__ void panel2_step(double (&x)[RPL][kPanel], int (&org)[RPL], Panel2Lds &sh, int t, int nb,
-                                            int c0, int bw, int *__restrict__ perm, int &flags) {
+__device__ __forceinline__ void panel2_step(double (&x)[RPL][kPanel], int (&org)[RPL], int (&org2)[RPL],
+                                            Panel2Lds &sh, int t, int nb, int c0, int bw, int *__restrict__ perm,
+                                            int &flags) {
     if (CC >= bw) return;
     const int c = c0 + CC;
     double best = -1.0;
@@ -218,11 +231,13 @@ __device__ __forceinline__ void panel2_step(double (&x)[RPL][kPanel], int (&org)
 #pragma unroll
             for (int j = 0; j < kPanel; ++j) sh.pivrow[j] = x[s][j];
             sh.porg = org[s];
+            sh.porg2 = org2[s];
         }
         if (s == sc && t == tc && p != c) {
 #pragma unroll
             for (int j = 0; j < kPanel; ++j) sh.oldc[j] = x[s][j];
             sh.corg = org[s];
+            sh.corg2 = org2[s];
         }
     }
     __syncthreads();
@@ -233,8 +248,12 @@ __device__ __forceinline__ void panel2_step(double (&x)[RPL][kPanel], int (&org)
 #pragma unroll
                 for (int j = 0; j < kPanel; ++j) x[s][j] = sh.oldc[j];
                 org[s] = sh.corg;
+                org2[s] = sh.corg2;
             }
-            if (s == sc && t == tc) org[s] = sh.porg;
+            if (s == sc && t == tc) {
+                org[s] = sh.porg;
+                org2[s] = sh.porg2;
+            }
         }
     }
     double d = sh.pivrow[CC];
@@ -273,62 +292,38 @@ __device__ __forceinline__ void panel2_step(double (&x)[RPL][kPanel], int (&org)
 
 template <int RPL, int... CC>
 __device__ __forceinline__ void panel2_steps(std::integer_sequence<int, CC...>, double (&x)[RPL][kPanel],
-                                             int (&org)[RPL], Panel2Lds &sh, int t, int nb, int c0, int bw,
-                                             int *__restrict__ perm, int &flags) {
-    (panel2_step<RPL, CC>(x, org, sh, t, nb, c0, bw, perm, flags), ...);
+                                             int (&org)[RPL], int (&org2)[RPL], Panel2Lds &sh, int t, int nb,
+                                             int c0, int bw, int *__restrict__ perm, int &flags) {
+    (panel2_step<RPL, CC>(x, org, org2, sh, t, nb, c0, bw, perm, flags), ...);
 }
 
+// Write the touched-row list of the window [lo, lo + w) from the lanes' row
+// origins: slot r - lo for the window rows, then the moved rows in row
+// order, ranked by wavefront ballots per slot (rows s*128 + t: slot major,
+// then wavefront, then lane).  Every lane takes part; starts with a barrier.
 template <int RPL>
-__global__ void __launch_bounds__(kPanel2Threads, RPL <= 3 ? 2 : 1)
-k_gj_panel2(int nb, int c0, int bw, double *__restrict__ A,
-                                                             int *__restrict__ perm, int *__restrict__ touch,
-                                                             int *__restrict__ status) {
-    __shared__ Panel2Lds sh;
-    const int t = threadIdx.x;
-    double *Ak = A + (size_t)blockIdx.x * nb * nb;
-    double x[RPL][kPanel];
-    int org[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-        const int r = s * kPanel2Threads + t;
-        org[s] = r;
-#pragma unroll
-        for (int j = 0; j < kPanel; ++j) x[s][j] = (r < nb && j < bw) ? Ak[(size_t)(c0 + j) * nb + r] : 0.0;
-    }
-    int flags = 0;
-    panel2_steps<RPL>(std::make_integer_sequence<int, kPanel>{}, x, org, sh, t, nb, c0, bw, perm, flags);
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-        const int r = s * kPanel2Threads + t;
-        if (r < nb) {
-#pragma unroll
-            for (int j = 0; j < kPanel; ++j)
-                if (j < bw) Ak[(size_t)(c0 + j) * nb + r] = x[s][j];
-        }
-    }
-    // touched-row list: slot r - c0 for the panel rows, then the moved rows in
-    // row order, ranked by wavefront ballots per slot (rows s*128 + t: slot
-    // major, then wavefront, then lane)
-    const int lane = t & 63, w = t >> 6;
+__device__ __forceinline__ void write_touch(const int (&org)[RPL], int lo, int w, int nb, int t, Panel2Lds &sh,
+                                            int *__restrict__ tl) {
+    const int lane = t & 63, wv = t >> 6;
     unsigned long long m[RPL];
+    __syncthreads();  // the previous readers of sh.cnt are done
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const int r = s * kPanel2Threads + t;
-        const bool inS = r >= c0 && r < c0 + bw;
+        const bool inS = r >= lo && r < lo + w;
         m[s] = __ballot(r < nb && !inS && org[s] != r);
-        if (lane == 0) sh.cnt[s][w] = __popcll(m[s]);
+        if (lane == 0) sh.cnt[s][wv] = __popcll(m[s]);
     }
     __syncthreads();
-    int *tl = touch + (size_t)blockIdx.x * kTouchStride;
-    int off = bw;
+    int off = w;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         const int r = s * kPanel2Threads + t;
-        const bool inS = r >= c0 && r < c0 + bw;
-        const int base = off + (w == 1 ? sh.cnt[s][0] : 0);
+        const bool inS = r >= lo && r < lo + w;
+        const int base = off + (wv == 1 ? sh.cnt[s][0] : 0);
         int slot = -1;
         if (inS)
-            slot = r - c0;
+            slot = r - lo;
         else if ((m[s] >> lane) & 1ull)
             slot = base + __popcll(m[s] & ((1ull << lane) - 1ull));
         if (slot >= 0) {
@@ -338,14 +333,65 @@ k_gj_panel2(int nb, int c0, int bw, double *__restrict__ A,
         off += sh.cnt[s][0] + sh.cnt[s][1];
     }
     if (t == 0) tl[0] = off;
+}
+
+// One sub-panel [c0, c0 + bw) of every block.  wlo == c0: a window of its
+// own; its list goes to touch.  wlo < c0: the second sub-panel of the
+// window [wlo, c0 + bw), whose first sub-panel's list is read from touch
+// (before it is overwritten with this sub-panel's own list); the list of the
+// whole window, with the interchanges of both sub-panels composed, goes to
+// touch2.
+template <int RPL>
+__global__ void __launch_bounds__(kPanel2Threads, RPL <= 3 ? 2 : 1)
+k_gj_panel2(int nb, int c0, int bw, int wlo, double *__restrict__ A, int *__restrict__ perm,
+            int *__restrict__ touch, int *__restrict__ touch2, int *__restrict__ status) {
+    __shared__ Panel2Lds sh;
+    const int t = threadIdx.x;
+    const bool second = wlo < c0;
+    double *Ak = A + (size_t)blockIdx.x * nb * nb;
+    int *tl = touch + (size_t)blockIdx.x * kTouchStride;
+    if (second) {
+        for (int r = t; r < nb; r += kPanel2Threads) sh.upos[r] = -1;
+        __syncthreads();
+        const int nu = min(tl[0], kTouch);
+        for (int u = t; u < nu; u += kPanel2Threads) {
+            const int r = tl[1 + u];
+            if (r >= 0 && r < nb) sh.upos[r] = (short)u;
+            sh.tsrc[u] = tl[1 + kTouch + u];
+        }
+        __syncthreads();
+    }
+    double x[RPL][kPanel];
+    int org[RPL], org2[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * kPanel2Threads + t;
+        org[s] = r;
+        const int u = (second && r < nb) ? sh.upos[r] : -1;
+        org2[s] = u >= 0 ? sh.tsrc[u] : r;
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) x[s][j] = (r < nb && j < bw) ? Ak[(size_t)(c0 + j) * nb + r] : 0.0;
+    }
+    int flags = 0;
+    panel2_steps<RPL>(std::make_integer_sequence<int, kPanel>{}, x, org, org2, sh, t, nb, c0, bw, perm, flags);
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * kPanel2Threads + t;
+        if (r < nb) {
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j)
+                if (j < bw) Ak[(size_t)(c0 + j) * nb + r] = x[s][j];
+        }
+    }
+    write_touch<RPL>(org, c0, bw, nb, t, sh, tl);
+    if (second) write_touch<RPL>(org2, wlo, c0 + bw - wlo, nb, t, sh, touch2 + (size_t)blockIdx.x * kTouchStride);
     if (flags && t == 0) atomicOr(status, flags);
 }
 
 constexpr int kUpdCols = 64;  // columns per update workgroup
-constexpr int kUpdRows = 64;  // rows per LDS chunk of T_panel
-constexpr int kMaxNb = 512;   // largest block the update kernels take
+constexpr int kUpdRows = 64;  // rows per chunk
 
-// The panel's touched-row list of one block in LDS: (P x)[rows[u]] =
+// The window's touched-row list of one block in LDS: (P x)[rows[u]] =
 // x[src[u]], upos[r] = slot of row r (-1: untouched, (P x)[r] = x[r]).
 struct TouchLds {
     int rows[kTouch];
@@ -356,7 +402,7 @@ struct TouchLds {
 
 // The columns an update launch transforms: tile column ri < n is block column
 // j = lo + ri, shifted past the excluded window [skip_lo, skip_lo + skip_w)
-// (the panel's own columns).
+// (the window's own columns).
 struct ColMap {
     int lo, n, skip_lo, skip_w;
     __device__ __forceinline__ int col(int ri) const {
@@ -367,7 +413,7 @@ struct ColMap {
 
 // Workgroup -> (block, column tile).  Workgroups are dispatched round-robin
 // over the 8 XCDs; block k goes to XCD k mod 8 and its column tiles run back
-// to back there, so the panel columns they all read stay in that XCD's L2.
+// to back there, so the window columns they all read stay in that XCD's L2.
 __device__ __forceinline__ bool update_tile(int Ne, int ntile, int &k, int &tile) {
     const int g = blockIdx.x, xcd = g & 7, i = g >> 3;
     k = (i / ntile) * 8 + xcd;
@@ -390,26 +436,37 @@ __device__ __forceinline__ void load_touch(TouchLds &t, const int *__restrict__ 
     __syncthreads();
 }
 
-// stg[jj][u] = (P x_j)[rows[u]] = x_j[src[u]] for the tile's columns (0 beyond
-// the block); one column per wavefront per pass.  Read before any write of
-// the tile, so the in-place update cannot overwrite a value still needed.
-__device__ __forceinline__ void stage_touched(const TouchLds &t, double (*stg)[kTouch + 1], const double *Ak,
-                                              int nb, const ColMap &cm, int tile) {
-    for (int i = threadIdx.x; i < kTouch * kUpdCols; i += blockDim.x) {
-        const int u = i % kTouch, jj = i / kTouch;
+// stg[jj][u] = (P x_j)_S[u] = x_j[src[u]] for the window rows u < bw and the
+// tile's columns (0 beyond), the operand of the product.  Read before any
+// write of the tile.
+template <int KP, typename Buf>
+__device__ __forceinline__ void stage_window_rows(const TouchLds &t, double (*stg)[KP + 1], const Buf &B, int nb,
+                                                  const ColMap &cm, int tile, int bw) {
+    for (int i = threadIdx.x; i < KP * kUpdCols; i += blockDim.x) {
+        const int u = i % KP, jj = i / KP;
         const int ri = tile * kUpdCols + jj;
-        double v = 0.0;
-        if (u < t.nu && ri < cm.n) v = Ak[(size_t)cm.col(ri) * nb + t.src[u]];
-        stg[jj][u] = v;
+        const bool ok = u < bw && ri < cm.n;
+        stg[jj][u] = B.ld(Buf::at(cm.col(ri) * nb + t.src[ok ? u : 0], ok));
     }
+}
+
+// Row chunks in the order an update stores them: the chunk that holds the
+// window rows S last (the window starts at a multiple of kPanel and spans at
+// most kWide rows, so S lies in one chunk).  Every moved row outside S reads
+// its source inside S, so up to the last chunk no store overwrites a value
+// still to be read; the last chunk's own reads finish before a barrier that
+// precedes its stores.
+__device__ __forceinline__ int chunk_row(int i, int nch, int cs) {
+    const int c = (i == nch - 1) ? cs : (i < cs ? i : i + 1);
+    return c * kUpdRows;
 }
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// Lane geometry shared by the two update kernels.  Both form the product
-// transposed, out^T = (P x)_S^T T_panel^T, on 16 x 16 MFMA tiles: wave w owns
+// Lane geometry shared by the update kernels.  They form the product
+// transposed, out^T = (P x)_S^T T_win^T, on 16 x 16 MFMA tiles: wave w owns
 // rows wave*16 + r16 of each 64-row chunk, and lane (r16, g) holds the
 // results of that row in 16 columns of the tile: cb*16 + 4g + v for the
 // FP32-output MFMA, cb*16 + g + 4v for the FP64 one (cb, v < 4).  Each store
@@ -417,7 +474,7 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 template <bool F64>
 struct UpdLane {
     int r16, g, wave;
-    int ri0, c0, bw;  // c0, bw: the panel (its columns hold T, its rows are S)
+    int ri0, c0, bw;  // c0, bw: the window (its columns hold T, its rows are S)
     ColMap cm;
     __device__ UpdLane(int tid, int tile, const ColMap &cm_, int c0_, int bw_) {
         const int lane = tid & 63;
@@ -439,93 +496,130 @@ struct UpdLane {
     }
 };
 
+// Block-relative buffer addressing for the update kernels: every read and
+// write is issued unconditionally, and a lane with nothing to read or write
+// passes an offset beyond the block, which the buffer range check turns into
+// a zero read or a dropped write.  With no branches around memory
+// instructions the compiler waits for exactly the reads a use needs.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr unsigned kOutside = 0x80000000u;  // byte offset beyond every block (n_b <= 512: 2 MB)
+constexpr int kBufWord3 = 0x00020000;       // buffer descriptor word 3: 32-bit data format, no swizzle
+struct BlockBuf {
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ BlockBuf(double *Ak, int nb)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(Ak, (short)0, nb * nb * (int)sizeof(double), kBufWord3)) {}
+    __device__ __forceinline__ static unsigned at(int idx, bool ok) {
+        return ok ? (unsigned)idx * (unsigned)sizeof(double) : kOutside;
+    }
+    __device__ __forceinline__ double ld(unsigned off) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    }
+    __device__ __forceinline__ void st(unsigned off, double v) const {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), rs, off, 0, 0);
+    }
+};
+
 // The global reads of one 64-row chunk, issued ahead of their use: the
-// chunk of the panel columns T (eight values per lane, rows fastest; issued
-// before the previous chunk's product) and the lane's untouched x values
-// (touched rows come from the stage; issued right after the previous
-// chunk's stores).  Offsets within a block fit in 32 bits (n_b <= 512).
+// chunk of the window columns T (KP/4 values per lane, rows fastest; issued
+// before the previous chunk's product) and the lane's (P x) values (issued
+// right after the previous chunk's stores; none on the window rows, whose
+// output is the product alone).  Reads outside the window's columns or the
+// block's rows return 0.
+template <int KP>
 struct ChunkLoads {
-    double tpv[8];
+    double tpv[KP / 4];
     double xo[4][4];
     template <bool F64>
-    __device__ void issue_t(const double *Ak, const UpdLane<F64> &L, int nb, int r0) {
+    __device__ void issue_t(const BlockBuf &B, const UpdLane<F64> &L, int nb, int r0) {
         const int tid = threadIdx.x;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < KP / 4; ++i) {
             const int t = tid + 256 * i, cc = t >> 6, rr = t & 63;
-            tpv[i] = (cc < L.bw && r0 + rr < nb) ? Ak[(unsigned)((L.c0 + cc) * nb + r0 + rr)] : 0.0;
+            tpv[i] = B.ld(BlockBuf::at((L.c0 + cc) * nb + r0 + rr, cc < L.bw && r0 + rr < nb));
+        }
+    }
+    // tp[cc][rr] = T[r0 + rr][cc]
+    __device__ void put_t(double (*tp)[kUpdRows]) const {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < KP / 4; ++i) {
+            const int t = tid + 256 * i;
+            tp[t >> 6][t & 63] = tpv[i];
         }
     }
     template <bool F64>
-    __device__ void issue_x(const double *Ak, const TouchLds &tl, const UpdLane<F64> &L, int nb, int r0) {
+    __device__ void issue_x(const BlockBuf &B, const TouchLds &tl, const UpdLane<F64> &L, int nb, int r0) {
         const int r = r0 + L.wave * 16 + L.r16;
-        const bool load = r < nb && tl.upos[r < nb ? r : 0] < 0;
+        const bool row = r < nb && !(r >= L.c0 && r < L.c0 + L.bw);
+        const int u = r < nb ? tl.upos[r] : -1;
+        const int rs = u >= 0 ? tl.src[u] : r;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int j;
                 const bool ok = L.col(cb, v, j);
-                xo[cb][v] = (load && ok) ? Ak[(unsigned)(j * nb + r)] : 0.0;
+                xo[cb][v] = B.ld(BlockBuf::at(j * nb + rs, row && ok));
             }
     }
 };
 
 // Write the lane's results of one chunk: out = (P x, zero on S) + product.
 template <bool F64, typename Acc>
-__device__ __forceinline__ void store_chunk(double *Ak, const TouchLds &tl, const UpdLane<F64> &L,
-                                            const double (*stg)[kTouch + 1], const double (&xo)[4][4],
+__device__ __forceinline__ void store_chunk(const BlockBuf &B, const UpdLane<F64> &L, const double (&xo)[4][4],
                                             const Acc &acc, int nb, int r0) {
     const int r = r0 + L.wave * 16 + L.r16;
-    if (r >= nb) return;
-    const bool inS = (r >= L.c0 && r < L.c0 + L.bw);
-    const int u = tl.upos[r];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             int j;
-            if (!L.col(cb, v, j)) continue;
-            const double base = inS ? 0.0 : (u >= 0 ? stg[L.jj(cb, v)][u] : xo[cb][v]);
-            Ak[(unsigned)(j * nb + r)] = base + acc[cb][v];
+            const bool ok = L.col(cb, v, j);
+            B.st(BlockBuf::at(j * nb + r, ok && r < nb), xo[cb][v] + acc[cb][v]);
         }
 }
 
-// Apply the panel transform to kUpdCols columns (outside the panel) of one
-// block in FP64 on v_mfma_f64_16x16x4f64 (A = stage^T: lane (r16, g) gives
-// column r16, panel column 4ks + g; B = T^T: panel column 4ks + g, row r16).
-// The next chunk's global reads are in flight while a chunk is multiplied.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_gj_update(int Ne, int nb, int c0, int bw, ColMap cm, double *__restrict__ A, const int *__restrict__ touch) {
-    __shared__ double stg[kUpdCols][kTouch + 1];  // (P x) on the touched rows; (P x)_S = slots 0..bw-1
-    __shared__ double tp[kPanel][kUpdRows];       // T_panel chunk, [panel column][row]
-    __shared__ TouchLds tl;
+// Before the last chunk's stores: every lane's reads are complete (the last
+// chunk's moved rows read window rows that the same chunk overwrites).
+__device__ __forceinline__ void reads_done_barrier() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Apply a window's transform (K = KP: one sub-panel, or two as one window)
+// to kUpdCols columns (outside the window) of one block in FP64 on
+// v_mfma_f64_16x16x4f64 (A = stage^T: lane (r16, g) gives column r16, window
+// column 4ks + g; B = T^T: window column 4ks + g, row r16).  The next chunk's
+// global reads are in flight while a chunk is multiplied.
+template <int KP>
+__device__ __forceinline__ void gj_update_f64(int Ne, int nb, int c0, int bw, const ColMap &cm,
+                                              double *__restrict__ A, const int *__restrict__ touch,
+                                              double (*stg)[KP + 1], double (*tp)[kUpdRows], TouchLds &tl) {
     const int ntile = (cm.n + kUpdCols - 1) / kUpdCols;
     int k, tile;
     if (!update_tile(Ne, ntile, k, tile)) return;
     const int tid = threadIdx.x;
-    double *Ak = A + (size_t)k * nb * nb;
+    const BlockBuf B(A + (size_t)k * nb * nb, nb);
     load_touch(tl, touch + (size_t)k * kTouchStride, nb);
-    stage_touched(tl, stg, Ak, nb, cm, tile);
+    stage_window_rows<KP>(tl, stg, B, nb, cm, tile, bw);
     const UpdLane<true> L(tid, tile, cm, c0, bw);
-    ChunkLoads ld;
-    ld.issue_t(Ak, L, nb, 0);
-    ld.issue_x(Ak, tl, L, nb, 0);
-    for (int r0 = 0; r0 < nb; r0 += kUpdRows) {
+    const int nch = (nb + kUpdRows - 1) / kUpdRows, cs = c0 / kUpdRows;
+    ChunkLoads<KP> ld;
+    ld.issue_t(B, L, nb, chunk_row(0, nch, cs));
+    ld.issue_x(B, tl, L, nb, chunk_row(0, nch, cs));
+    for (int i = 0; i < nch; ++i) {
+        const int r0 = chunk_row(i, nch, cs);
         __syncthreads();  // the stage is complete; the previous chunk's tp reads are done
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int t = tid + 256 * i;
-            tp[t >> 6][t & 63] = ld.tpv[i];
-        }
+        ld.put_t(tp);
         __syncthreads();
-        const bool more = r0 + kUpdRows < nb;
-        if (more) ld.issue_t(Ak, L, nb, r0 + kUpdRows);
+        const bool more = i + 1 < nch;
+        const int r1 = more ? chunk_row(i + 1, nch, cs) : 0;
+        if (more) ld.issue_t(B, L, nb, r1);
         f64x4_t acc[4];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) acc[cb] = f64x4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < kPanel / 4; ++ks) {
+        for (int ks = 0; ks < KP / 4; ++ks) {
             const double bv = tp[4 * ks + L.g][L.wave * 16 + L.r16];
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
@@ -533,71 +627,118 @@ k_gj_update(int Ne, int nb, int c0, int bw, ColMap cm, double *__restrict__ A, c
                 acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
             }
         }
-        store_chunk(Ak, tl, L, stg, ld.xo, acc, nb, r0);
-        if (more) ld.issue_x(Ak, tl, L, nb, r0 + kUpdRows);
+        if (!more) reads_done_barrier();
+        store_chunk(B, L, ld.xo, acc, nb, r0);
+        if (more) ld.issue_x(B, tl, L, nb, r1);
     }
 }
 
-// The same panel update on BF16-input MFMA with FP32 accumulation
-// (v_mfma_f32_16x16x32_bf16, K = the 32-column panel): each FP32 operand is
-// split into hi + lo BF16 parts and the product taken as hi*hi + lo*hi +
-// hi*lo (three MFMAs), ~16 mantissa bits.  Operands are staged k-contiguous
-// in LDS.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_gj_update_mfma(int Ne, int nb, int c0, int bw, ColMap cm, double *__restrict__ A, const int *__restrict__ touch) {
-    __shared__ __attribute__((aligned(16))) __bf16 xs_h[kUpdCols][kPanel];
-    __shared__ __attribute__((aligned(16))) __bf16 xs_l[kUpdCols][kPanel];
-    __shared__ __attribute__((aligned(16))) __bf16 tp_h[kUpdRows][kPanel];
-    __shared__ __attribute__((aligned(16))) __bf16 tp_l[kUpdRows][kPanel];
-    __shared__ double stg[kUpdCols][kTouch + 1];
+k_gj_update(int Ne, int nb, int c0, int bw, ColMap cm, double *__restrict__ A, const int *__restrict__ touch) {
+    __shared__ double stg[kUpdCols][kPanel + 1];  // (P x)_S
+    __shared__ double tp[kPanel][kUpdRows];       // T chunk, [window column][row]
     __shared__ TouchLds tl;
+    gj_update_f64<kPanel>(Ne, nb, c0, bw, cm, A, touch, stg, tp, tl);
+}
+
+// The whole-window update (K = kWide); 69 KB of LDS, two workgroups per CU.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_gj_update_wide(int Ne, int nb, int c0, int bw, ColMap cm, double *__restrict__ A, const int *__restrict__ touch) {
+    __shared__ double stg[kUpdCols][kWide + 1];
+    __shared__ double tp[kWide][kUpdRows];
+    __shared__ TouchLds tl;
+    gj_update_f64<kWide>(Ne, nb, c0, bw, cm, A, touch, stg, tp, tl);
+}
+
+// The update on BF16-input MFMA with FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16, K = 32 per instruction: one sub-panel, or two
+// steps for a whole window): each FP32 operand is split into hi + lo BF16
+// parts and the product taken as hi*hi + lo*hi + hi*lo (three MFMAs), ~16
+// mantissa bits.  Operands are staged k-contiguous in LDS (rows padded by 8
+// values to spread the 16-byte reads over the banks).
+template <int KP>
+__device__ __forceinline__ void gj_update_bf16(int Ne, int nb, int c0, int bw, const ColMap &cm,
+                                               double *__restrict__ A, const int *__restrict__ touch,
+                                               __bf16 (*xs_h)[KP + 8], __bf16 (*xs_l)[KP + 8],
+                                               __bf16 (*tp_h)[KP + 8], __bf16 (*tp_l)[KP + 8], TouchLds &tl) {
     const int ntile = (cm.n + kUpdCols - 1) / kUpdCols;
     int k, tile;
     if (!update_tile(Ne, ntile, k, tile)) return;
     const int tid = threadIdx.x;
-    double *Ak = A + (size_t)k * nb * nb;
+    const BlockBuf B(A + (size_t)k * nb * nb, nb);
     load_touch(tl, touch + (size_t)k * kTouchStride, nb);
-    stage_touched(tl, stg, Ak, nb, cm, tile);
-    const UpdLane<false> L(tid, tile, cm, c0, bw);
-    ChunkLoads ld;
-    ld.issue_t(Ak, L, nb, 0);
-    ld.issue_x(Ak, tl, L, nb, 0);
-    __syncthreads();
-    for (int t = tid; t < kPanel * kUpdCols; t += 256) {
-        const int cc = t % kPanel, jj = t / kPanel;
-        const float v = (cc < bw) ? (float)stg[jj][cc] : 0.f;
+    // (P x)_S of the tile's columns, split into hi and lo parts
+    for (int i = tid; i < KP * kUpdCols; i += 256) {
+        const int u = i % KP, jj = i / KP;
+        const int ri = tile * kUpdCols + jj;
+        const bool ok = u < bw && ri < cm.n;
+        const float v = (float)B.ld(BlockBuf::at(cm.col(ri) * nb + tl.src[ok ? u : 0], ok));
         const __bf16 h = (__bf16)v;
-        xs_h[jj][cc] = h;
-        xs_l[jj][cc] = (__bf16)(v - (float)h);
+        xs_h[jj][u] = h;
+        xs_l[jj][u] = (__bf16)(v - (float)h);
     }
-    for (int r0 = 0; r0 < nb; r0 += kUpdRows) {
+    const UpdLane<false> L(tid, tile, cm, c0, bw);
+    const int nch = (nb + kUpdRows - 1) / kUpdRows, cs = c0 / kUpdRows;
+    ChunkLoads<KP> ld;
+    ld.issue_t(B, L, nb, chunk_row(0, nch, cs));
+    ld.issue_x(B, tl, L, nb, chunk_row(0, nch, cs));
+    for (int i = 0; i < nch; ++i) {
+        const int r0 = chunk_row(i, nch, cs);
         __syncthreads();  // xs is complete; the previous chunk's tp reads are done
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int t = tid + 256 * i, cc = t >> 6, rr = t & 63;
-            const float v = (float)ld.tpv[i];
+        for (int q = 0; q < KP / 4; ++q) {
+            const int t = tid + 256 * q, cc = t >> 6, rr = t & 63;
+            const float v = (float)ld.tpv[q];
             const __bf16 h = (__bf16)v;
             tp_h[rr][cc] = h;
             tp_l[rr][cc] = (__bf16)(v - (float)h);
         }
         __syncthreads();
-        const bool more = r0 + kUpdRows < nb;
-        if (more) ld.issue_t(Ak, L, nb, r0 + kUpdRows);
-        const bf16x8_t th = *reinterpret_cast<const bf16x8_t *>(&tp_h[L.wave * 16 + L.r16][8 * L.g]);
-        const bf16x8_t tlo = *reinterpret_cast<const bf16x8_t *>(&tp_l[L.wave * 16 + L.r16][8 * L.g]);
+        const bool more = i + 1 < nch;
+        const int r1 = more ? chunk_row(i + 1, nch, cs) : 0;
+        if (more) ld.issue_t(B, L, nb, r1);
         f32x4_t acc[4];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            const bf16x8_t xh = *reinterpret_cast<const bf16x8_t *>(&xs_h[cb * 16 + L.r16][8 * L.g]);
-            const bf16x8_t xl = *reinterpret_cast<const bf16x8_t *>(&xs_l[cb * 16 + L.r16][8 * L.g]);
-            acc[cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, th, acc[cb], 0, 0, 0);
-            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, th, acc[cb], 0, 0, 0);
-            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, tlo, acc[cb], 0, 0, 0);
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < KP / 32; ++kk) {
+            const int k8 = 32 * kk + 8 * L.g;
+            const bf16x8_t th = *reinterpret_cast<const bf16x8_t *>(&tp_h[L.wave * 16 + L.r16][k8]);
+            const bf16x8_t tlo = *reinterpret_cast<const bf16x8_t *>(&tp_l[L.wave * 16 + L.r16][k8]);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const bf16x8_t xh = *reinterpret_cast<const bf16x8_t *>(&xs_h[cb * 16 + L.r16][k8]);
+                const bf16x8_t xl = *reinterpret_cast<const bf16x8_t *>(&xs_l[cb * 16 + L.r16][k8]);
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, th, acc[cb], 0, 0, 0);
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, th, acc[cb], 0, 0, 0);
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, tlo, acc[cb], 0, 0, 0);
+            }
         }
-        store_chunk(Ak, tl, L, stg, ld.xo, acc, nb, r0);
-        if (more) ld.issue_x(Ak, tl, L, nb, r0 + kUpdRows);
+        if (!more) reads_done_barrier();
+        store_chunk(B, L, ld.xo, acc, nb, r0);
+        if (more) ld.issue_x(B, tl, L, nb, r1);
     }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_gj_update_mfma(int Ne, int nb, int c0, int bw, ColMap cm, double *__restrict__ A, const int *__restrict__ touch) {
+    __shared__ __attribute__((aligned(16))) __bf16 xs_h[kUpdCols][kPanel + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 xs_l[kUpdCols][kPanel + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 tp_h[kUpdRows][kPanel + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 tp_l[kUpdRows][kPanel + 8];
+    __shared__ TouchLds tl;
+    gj_update_bf16<kPanel>(Ne, nb, c0, bw, cm, A, touch, xs_h, xs_l, tp_h, tp_l, tl);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_gj_update_mfma_wide(int Ne, int nb, int c0, int bw, ColMap cm, double *__restrict__ A,
+                      const int *__restrict__ touch) {
+    __shared__ __attribute__((aligned(16))) __bf16 xs_h[kUpdCols][kWide + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 xs_l[kUpdCols][kWide + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 tp_h[kUpdRows][kWide + 8];
+    __shared__ __attribute__((aligned(16))) __bf16 tp_l[kUpdRows][kWide + 8];
+    __shared__ TouchLds tl;
+    gj_update_bf16<kWide>(Ne, nb, c0, bw, cm, A, touch, xs_h, xs_l, tp_h, tp_l, tl);
 }
 
 // The row interchanges of the elimination turn into column interchanges of
@@ -669,31 +810,53 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
         const bool mfma = precision == FR_PREC_FP32_BF16 || precision == FR_PREC_BF16_STORE;
         const int rpl = (nb + kPanel2Threads - 1) / kPanel2Threads;  // rows per lane of the panel kernel
         if (rpl > 4) return hipErrorInvalidValue;
-        auto panel = [&](int c, int bw, int *touch) {
+        auto panel = [&](int c, int bw, int wlo, int *touch, int *touch2) {
             const dim3 gp(Ne), bp(kPanel2Threads);
             if (rpl == 1)
-                hipLaunchKernelGGL(k_gj_panel2<1>, gp, bp, 0, s, nb, c, bw, L.blk64, L.perm, touch, L.dstatus);
+                hipLaunchKernelGGL(k_gj_panel2<1>, gp, bp, 0, s, nb, c, bw, wlo, L.blk64, L.perm, touch, touch2,
+                                   L.dstatus);
             else if (rpl == 2)
-                hipLaunchKernelGGL(k_gj_panel2<2>, gp, bp, 0, s, nb, c, bw, L.blk64, L.perm, touch, L.dstatus);
+                hipLaunchKernelGGL(k_gj_panel2<2>, gp, bp, 0, s, nb, c, bw, wlo, L.blk64, L.perm, touch, touch2,
+                                   L.dstatus);
             else if (rpl == 3)
-                hipLaunchKernelGGL(k_gj_panel2<3>, gp, bp, 0, s, nb, c, bw, L.blk64, L.perm, touch, L.dstatus);
+                hipLaunchKernelGGL(k_gj_panel2<3>, gp, bp, 0, s, nb, c, bw, wlo, L.blk64, L.perm, touch, touch2,
+                                   L.dstatus);
             else
-                hipLaunchKernelGGL(k_gj_panel2<4>, gp, bp, 0, s, nb, c, bw, L.blk64, L.perm, touch, L.dstatus);
+                hipLaunchKernelGGL(k_gj_panel2<4>, gp, bp, 0, s, nb, c, bw, wlo, L.blk64, L.perm, touch, touch2,
+                                   L.dstatus);
         };
-        // one panel's transform applied to the columns cm lists
+        auto grid = [&](const ColMap &cm) {
+            const int ntile = (cm.n + kUpdCols - 1) / kUpdCols;
+            return dim3((unsigned)(((Ne + 7) / 8) * 8 * ntile));
+        };
+        // one sub-panel's transform applied to the columns cm lists
         auto update = [&](int c, int bw, const ColMap &cm, const int *touch) {
             if (cm.n <= 0) return;
-            const int ntile = (cm.n + kUpdCols - 1) / kUpdCols;
-            const dim3 gu((unsigned)(((Ne + 7) / 8) * 8 * ntile));
             if (mfma)
-                hipLaunchKernelGGL(k_gj_update_mfma, gu, dim3(256), 0, s, Ne, nb, c, bw, cm, L.blk64, touch);
+                hipLaunchKernelGGL(k_gj_update_mfma, grid(cm), dim3(256), 0, s, Ne, nb, c, bw, cm, L.blk64, touch);
             else
-                hipLaunchKernelGGL(k_gj_update, gu, dim3(256), 0, s, Ne, nb, c, bw, cm, L.blk64, touch);
+                hipLaunchKernelGGL(k_gj_update, grid(cm), dim3(256), 0, s, Ne, nb, c, bw, cm, L.blk64, touch);
         };
-        for (int c0 = 0; c0 < nb; c0 += kPanel) {
-            const int bw = min(kPanel, nb - c0);
-            panel(c0, bw, L.touch);
-            update(c0, bw, ColMap{0, nb - bw, c0, bw}, L.touch);
+        int *tsub = L.touch, *twin = L.touch + (size_t)Ne * kTouchStride;
+        constexpr int kNever = kMaxNb;  // ColMap without an excluded window
+        for (int c0 = 0; c0 < nb; c0 += kWide) {
+            const int bw1 = min(kPanel, nb - c0), bw2 = min(kPanel, nb - c0 - bw1);
+            panel(c0, bw1, c0, tsub, nullptr);
+            if (bw2 <= 0) {
+                update(c0, bw1, ColMap{0, nb - bw1, c0, bw1}, tsub);
+                continue;
+            }
+            update(c0, bw1, ColMap{c0 + bw1, bw2, kNever, 0}, tsub);  // first transform on the second sub-panel
+            panel(c0 + bw1, bw2, c0, tsub, twin);
+            update(c0 + bw1, bw2, ColMap{c0, bw1, kNever, 0}, tsub);  // second transform on the first sub-panel
+            const int bw = bw1 + bw2;
+            const ColMap cm{0, nb - bw, c0, bw};
+            if (cm.n <= 0) continue;
+            if (mfma)
+                hipLaunchKernelGGL(k_gj_update_mfma_wide, grid(cm), dim3(256), 0, s, Ne, nb, c0, bw, cm, L.blk64,
+                                   twin);
+            else
+                hipLaunchKernelGGL(k_gj_update_wide, grid(cm), dim3(256), 0, s, Ne, nb, c0, bw, cm, L.blk64, twin);
         }
         hipLaunchKernelGGL(k_gj_colperm, dim3(Ne), dim3(64), 0, s, nb, L.perm, L.colperm);
         L.inv_cols = L.colperm;

@@ -213,7 +213,7 @@ void ej_factor_impl(frpmg_ctx *ctx, int level, const double *dq, double sigma, i
         void *p = nullptr;
         HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * L.nb * sizeof(int)));
         L.perm = (int *)p;
-        HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * kTouchStride * sizeof(int)));
+        HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * 2 * kTouchStride * sizeof(int)));
         L.touch = (int *)p;
         HIPCHK(hipMalloc(&p, (size_t)ctx->mesh.Ne * L.nb * sizeof(int)));
         L.colperm = (int *)p;

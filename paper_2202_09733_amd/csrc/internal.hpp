@@ -170,7 +170,7 @@ struct Level {
     int inv_prec = -1;
     int *dstatus = nullptr;   // device pivot flags (kPivZero | kPivNonfinite)
     int *perm = nullptr;      // pivot rows of the blocked inversion [Ne][nb]
-    int *touch = nullptr;     // the panel's touched-row lists [Ne][kTouchStride]
+    int *touch = nullptr;     // touched-row lists of the blocked inversion [2][Ne][kTouchStride]
     int *colperm = nullptr;   // column placement of the blocked inversion [Ne][nb]
     const int *inv_cols = nullptr;  // nullptr: inv holds B^-1; else B^-1[:, inv_cols[j]] = inv[:, j]
     double *r0 = nullptr;     // scratch: R at the EJ linearisation point
@@ -189,9 +189,10 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
-// Blocked Gauss-Jordan: ints per block of one panel's touched-row list (the
-// count, then up to 64 rows and the rows their values come from).
-constexpr int kTouchStride = 129;
+// Blocked Gauss-Jordan: ints per block of one update window's touched-row
+// list (the count, then up to 128 rows and the rows their values come from);
+// each block holds two such lists.
+constexpr int kTouchStride = 257;
 
 // Reduction scratch: partial sums per block and per vector.
 constexpr int kRedBlocks = 2048;     // capacity of the partial-sum buffer per vector
