@@ -572,19 +572,31 @@ struct OutK {
     double dscale;
 };
 
+// Volume kernel.  In 2D every direction's flux is staged at once, so one
+// evaluation takes four barriers (staging; state read; fluxes written; flux
+// jumps formed) instead of three per direction, and the flux jumps of all
+// directions are formed in one pass; the fluxes overlay the staged state and
+// state jumps, which are dead by then (64x64 p = 4 linearised: 11.3 -> 10.1
+// us).  In 3D the staged fluxes would take 46 KB of LDS per workgroup,
+// three workgroups per CU instead of four, and the kernel ran slower (207 ->
+// 232 us at 32^3 p = 3): there it stages one direction at a time
+// (divergence()).  Same arithmetic, in the same order, either way.
 template <int DIM, int P, int MODE, int OUT>
-__global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph,
-                                                             const double *__restrict__ Jp,
-                                                             const double *__restrict__ Fs, OutK o) {
+__global__ void __launch_bounds__((Shape<DIM, P>::NT))
+k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, const double *__restrict__ Jp, const double *__restrict__ Fs,
+         OutK o) {
     using S = Shape<DIM, P>;
     constexpr int EB = S::EB, NV = S::NV, NP = S::NP, NF = S::NF;
     constexpr int NFACE = DIM * NV * NF * EB;
+    constexpr int NSTATE = NV * NP * EB;
+    constexpr bool BATCH = (DIM == 2);
+    constexpr int NA = (BATCH && DIM * NSTATE > NSTATE + NFACE) ? DIM * NSTATE : NSTATE + NFACE;
     __shared__ Ops1D ops;
-    __shared__ double s_u[NV * NP * EB];  // the state, then the flux of one direction
-    __shared__ double s_t[NFACE];         // state jumps q* - q+ on the + faces
-    __shared__ double s_fm[NFACE];        // F* on the - faces, then F* - f^-
-    __shared__ double s_fp[NFACE];        // F* on the + faces, then F* - f^+
+    __shared__ double s_a[NA];      // the state [v][i][slot], the state jumps q* - q+ [a][v][f][slot]; then the fluxes [a][v][i][slot]
+    __shared__ double s_fm[NFACE];  // F* on the - faces, then F* - f^-
+    __shared__ double s_fp[NFACE];  // F* on the + faces, then F* - f^+
     __shared__ double s_ih[DIM * EB];
+    double *s_u = s_a, *s_t = s_a + NSTATE;
     if (threadIdx.x == 0) ops = ops_in;
     const int k0 = xcd_block(blockIdx.x, gridDim.x) * EB;
     const int ne = min(EB, m.Ne - k0);
@@ -608,19 +620,107 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_volume(MeshK m, SrcK sr
     const int e = t % EB, i = t / EB;
     const bool active = (t < NP * EB) && (e < ne);
     double acc[NV];
-    divergence<DIM, P, EB, EB>(ops, ph, s_u, s_t, s_fm, s_fp, s_ih, active, e, i, acc);
-    if (!active) return;
-    const int k = k0 + e;
+    if constexpr (!BATCH) {
+        divergence<DIM, P, EB, EB>(ops, ph, s_u, s_t, s_fm, s_fp, s_ih, active, e, i, acc);
+        if (!active) return;
+    } else {
+        double F[DIM][NV];
+        if (active) {
+            double g[DIM][NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double R = -acc[v];
-        const size_t idx = ((size_t)v * NP + i) * m.Ne + k;
-        if (OUT == OUT_R) {
-            o.r[idx] = R;
-        } else {
-            double val = o.sigma * o.vdir[idx] - (R - o.r0[idx]) / (alpha * o.dscale);
-            if (o.x) val -= o.x[idx];
-            o.r[idx] = val;
+            for (int c = 0; c < DIM; ++c) {
+                int f, ic;
+                S::split(i, c, f, ic);
+                const double ih = s_ih[c * EB + e];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double d = 0.0;
+#pragma unroll
+                    for (int j = 0; j < P; ++j) d += ops.D[ic][j] * s_u[(v * NP + S::line(c, f, j)) * EB + e];
+                    d += s_t[((c * NV + v) * NF + f) * EB + e] * ops.gRd[ic];
+                    g[c][v] = ih * d;
+                }
+            }
+            double q[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[v] = s_u[(v * NP + i) * EB + e];
+            PState<DIM> st;
+            VGrad<DIM> vg;
+            pstate<DIM>(ph, q, st);
+            vgrad<DIM>(st, g, vg);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                double FI[NV], FV[NV];
+                inviscid_dev<DIM>(ph, a, st, FI);
+                viscous_dir<DIM>(ph, a, st, vg, FV);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) F[a][v] = FI[v] - FV[v];
+            }
+        }
+        __syncthreads();  // every read of the state and the jumps is done
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) s_a[((a * NV + v) * NP + i) * EB + e] = F[a][v];
+        }
+        __syncthreads();
+        // flux jumps on both faces normal to every axis
+        for (int t2 = threadIdx.x; t2 < NFACE; t2 += blockDim.x) {
+            const int e2 = t2 % EB;
+            int r = t2 / EB;
+            const int f = r % NF;
+            r /= NF;
+            const int v = r % NV, a = r / NV;
+            const double *x = s_a + (a * NV + v) * NP * EB + e2;
+            double fm = 0.0, fp = 0.0;
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const double xv = x[S::line(a, f, j) * EB];
+                fm += ops.bm[j] * xv;
+                fp += ops.bp[j] * xv;
+            }
+            s_fm[t2] -= fm;
+            s_fp[t2] -= fp;
+        }
+        __syncthreads();
+        if (!active) return;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            int f, ia;
+            S::split(i, a, f, ia);
+            const double ih = s_ih[a * EB + e];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double d = 0.0;
+#pragma unroll
+                for (int j = 0; j < P; ++j) d += ops.D[ia][j] * s_a[((a * NV + v) * NP + S::line(a, f, j)) * EB + e];
+                const int fi = ((a * NV + v) * NF + f) * EB + e;
+                d += s_fm[fi] * ops.gLd[ia] + s_fp[fi] * ops.gRd[ia];
+                acc[v] += ih * d;
+            }
+        }
+    }
+    const int k = k0 + e;
+    // the optional subtrahend x is tested once, outside the unrolled loop (a
+    // test per variable inside it more than doubled the registers)
+    const double *xs = o.x;
+    if (OUT == OUT_R) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) o.r[((size_t)v * NP + i) * m.Ne + k] = -acc[v];
+    } else if (xs) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t idx = ((size_t)v * NP + i) * m.Ne + k;
+            o.r[idx] = o.sigma * o.vdir[idx] - (-acc[v] - o.r0[idx]) / (alpha * o.dscale) - xs[idx];
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t idx = ((size_t)v * NP + i) * m.Ne + k;
+            o.r[idx] = o.sigma * o.vdir[idx] - (-acc[v] - o.r0[idx]) / (alpha * o.dscale);
         }
     }
 }
