@@ -718,13 +718,16 @@ def padapt():
     stage on the ring degree map (degrees 1..4, nested p{4-2} pMG) beside
     the uniform p = 4 stage on the same mesh, field and step; residual launch
     times of both; one adaptation cycle (indicator, degree update, L2
-    projection of the state, new degree map)."""
+    projection of the state, new degree map).  The same pair on a 128 x 128
+    mesh (keys suffixed _128), where the launches are no longer a few
+    workgroups each."""
     import torch
     from paper_2202_09733_amd import capi
     from paper_2202_09733_amd import workloads as W
     out = {}
-    for key, uni in (("p_adaptive", False), ("uniform_p4", True)):
-        wl = W.make_padapt_workload(uniform=uni)
+    for key, uni, n in (("p_adaptive", False, 32), ("uniform_p4", True, 32),
+                        ("p_adaptive_128", False, 128), ("uniform_p4_128", True, 128)):
+        wl = W.make_padapt_workload(n=(n, n), uniform=uni)
         deg = wl.extra["deg"]
         fr = capi.FR.from_padapt(wl, deg, nlevels=2, gap=2) if not uni else capi.FR.from_workload(wl, levels=[4, 2])
         dq = fr.to_dev(wl.dq)
@@ -744,7 +747,7 @@ def padapt():
         out[key] = {"dof": dof, "degrees": np.bincount(deg, minlength=5).tolist(), "stage_s": el,
                     "dof_per_s": dof / el, "gmres_iters": st["gmres_iters"], "true_rel_res": st["true_rel_res"],
                     "t_setup_s": st["t_setup"], "residual_us": t_res * 1e6}
-        if not uni:
+        if not uni and n == 32:
             d_deg = torch.as_tensor(deg, device=fr.device)
 
             def cycle():
@@ -767,10 +770,11 @@ def padapt():
                                        "new_degrees": np.bincount(nd, minlength=5).tolist()}
         fr.close()
         torch.cuda.empty_cache()
-    out["workload"] = ("2D NS FR periodic 32x32, Ma 0.1, Re 1000, vortical field |u'| <= 0.05; degrees in rings "
-                       "(4 at the centre down to 1) vs p = 4 everywhere; first ROW stage at dt = 100 dt_exp, "
+    out["workload"] = ("2D NS FR periodic 32x32 and 128x128, Ma 0.1, Re 1000, vortical field |u'| <= 0.05; degrees "
+                       "in rings (4 at the centre down to 1) vs p = 4 everywhere; first ROW stage at dt = 100 dt_exp, "
                        "FGMRES(30), pMG p{4-2} (nested, order gap 2), EJ smoothers, FP64, recomputed residual 1e-8")
     out["time_ratio_uniform_over_adaptive"] = out["uniform_p4"]["stage_s"] / out["p_adaptive"]["stage_s"]
+    out["time_ratio_uniform_over_adaptive_128"] = out["uniform_p4_128"]["stage_s"] / out["p_adaptive_128"]["stage_s"]
     return out
 
 
