@@ -61,6 +61,8 @@ struct Shape {
     static constexpr int EBF = (DIM == 2) ? (NF >= 32 ? 1 : 32 / NF) : (NF >= 64 ? 1 : 64 / NF);
     static constexpr int LPA = round64(NF * EBF);
     static constexpr int NTF = DIM * LPA;
+    static constexpr bool SPLIT = (DIM == 2);        // face kernel: viscous and Roe parts in separate wavefronts
+    static constexpr int NTF2 = SPLIT ? 2 * NTF : NTF;  // face kernel threads
 
     // local point on the line along axis a through face point f, position j
     __device__ __forceinline__ static int line(int a, int f, int j) {
@@ -429,11 +431,22 @@ __device__ __forceinline__ void face_flux(const MeshK &m, const Ops1D &ops, cons
     for (int v = 0; v < NV; ++v) Fs[((size_t)(A * NV + v) * NF + f) * m.Ne + k] = F[v];
 }
 
-// at most 128 VGPRs (four waves per SIMD): the 3D face flux otherwise takes ~131
+// Face kernel: one lane per (element, + face point), the lanes of each flux
+// direction in whole wavefronts.  In 2D each direction has two wavefronts:
+// one forms the gradient trace and the viscous part of the common flux (and
+// writes the state jumps and saved face data), the other the Roe flux from
+// the two traces; they meet through LDS after one barrier, with
+// common_flux()'s arithmetic in the same order.  Each wavefront's chain of
+// dependent arithmetic is then about half of the whole common flux, which
+// pays on the latency-bound 2D meshes (64x64 p = 4: 8.7 -> 7.7 us, 10.0 ->
+// 9.2 us linearised).  In 3D the kernel is bound by throughput and the split
+// (six wavefronts per workgroup, the pressure point spilling at 128
+// registers) took 178 us against 122: there one lane computes the whole
+// common flux (face_flux()), at most 128 VGPRs (four waves per SIMD; the 3D
+// face flux otherwise takes ~131).
 template <int DIM, int P, int MODE, bool SAVE>
-__global__ void __launch_bounds__((Shape<DIM, P>::NTF)) __attribute__((amdgpu_waves_per_eu(4, 8))) k_faces(MeshK m, SrcK src, Ops1D ops_in, Phys ph,
-                                                             double *__restrict__ Jp,
-                                                             double *__restrict__ Fs, FaceSave sv) {
+__global__ void __launch_bounds__((Shape<DIM, P>::NTF2)) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_faces(MeshK m, SrcK src, Ops1D ops_in, Phys ph, double *__restrict__ Jp, double *__restrict__ Fs, FaceSave sv) {
     using S = Shape<DIM, P>;
     constexpr int EB = S::EBF, NV = S::NV, NP = S::NP, NF = S::NF;
     constexpr int NFACE = DIM * NV * NF * EB;
@@ -441,6 +454,8 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NTF)) __attribute__((amdgpu_wa
     __shared__ double s_u[NV * NP * EB];
     __shared__ double s_t[NFACE];   // q* on the + faces (the + neighbour's minus trace)
     __shared__ double s_qp[NFACE];  // q+ (own plus trace)
+    constexpr bool SPLIT = Shape<DIM, P>::SPLIT;
+    __shared__ double s_x[SPLIT ? NFACE : 1];  // f^V(q+, g) + tau (q* - q+) from the viscous wavefronts
     __shared__ double s_ih[DIM * EB];
     if (threadIdx.x == 0) ops = ops_in;
     const int k0 = xcd_block(blockIdx.x, gridDim.x) * EB;
@@ -460,17 +475,84 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NTF)) __attribute__((amdgpu_wa
         s_qp[t] = s;
     }
     __syncthreads();
-    // one face point per lane; the direction is uniform over each wavefront
-    const int a = __builtin_amdgcn_readfirstlane((int)threadIdx.x / S::LPA);
-    const int rest = threadIdx.x % S::LPA;
-    const int e = rest % EB, f = rest / EB;
-    if (rest >= NF * EB || e >= ne) return;
-    if (a == 0) {
-        face_flux<DIM, P, 0, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
-    } else if (a == 1) {
-        face_flux<DIM, P, 1, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
+    if constexpr (!SPLIT) {
+        // one face point per lane; the direction is uniform over each wavefront
+        const int a = __builtin_amdgcn_readfirstlane((int)threadIdx.x / S::LPA);
+        const int rest = threadIdx.x % S::LPA;
+        const int e = rest % EB, f = rest / EB;
+        if (rest >= NF * EB || e >= ne) return;
+        if (a == 0) {
+            face_flux<DIM, P, 0, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
+        } else if (a == 1) {
+            face_flux<DIM, P, 1, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
+        } else {
+            if constexpr (DIM == 3) face_flux<DIM, P, 2, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
+        }
+        return;
     } else {
-        if constexpr (DIM == 3) face_flux<DIM, P, 2, EB, SAVE>(m, ops, ph, s_u, s_t, s_qp, s_ih, e, f, k0 + e, Fs, Jp, sv);
+        // wavefront pair per direction: 2a viscous, 2a + 1 Roe; one face point per lane
+        const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x / S::LPA);
+        const int a = w >> 1;
+        const bool roe_wave = (w & 1) != 0;
+        const int rest = threadIdx.x % S::LPA;
+        const int e = rest % EB, f = rest / EB;
+        const bool active = rest < NF * EB && e < ne;
+        const int k = k0 + e;
+        double Fr[NV];
+        if (active) {
+            if (!roe_wave) {
+                auto visc = [&](auto Ac) {
+                    constexpr int A = decltype(Ac)::value;
+                    double qL[NV], qR[NV], g[DIM][NV], Sn[NV], Fv[NV];
+                    plus_face_state<DIM, P, A, EB, EB>(ops, s_u, s_t, s_qp, s_ih, e, f, qL, qR, g, Sn);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Jp[((size_t)(A * NV + v) * NF + f) * m.Ne + k] = qR[v] - qL[v];
+                    if (SAVE) {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            const size_t o = ((size_t)(A * NV + v) * NF + f) * m.Ne + k;
+                            sv.Qs[o] = qR[v];
+                            sv.Qp[o] = qL[v];
+                            sv.Sn[o] = Sn[v];
+#pragma unroll
+                            for (int c = 0; c < DIM; ++c) {
+                                if (c == A) continue;
+                                const int cc = c < A ? c : c - 1;
+                                sv.Gt[((size_t)((A * (DIM - 1) + cc) * NV + v) * NF + f) * m.Ne + k] = g[c][v];
+                            }
+                        }
+                    }
+                    PState<DIM> sL;
+                    pstate<DIM>(ph, qL, sL);
+                    VGrad<DIM> vg;
+                    vgrad<DIM>(sL, g, vg);
+                    viscous_dir<DIM>(ph, A, sL, vg, Fv);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) s_x[((A * NV + v) * NF + f) * EB + e] = Fv[v] + ph.tau * (qR[v] - qL[v]);
+                };
+                if (a == 0) visc(std::integral_constant<int, 0>{});
+                else if (a == 1) visc(std::integral_constant<int, 1>{});
+                else if constexpr (DIM == 3) visc(std::integral_constant<int, 2>{});
+            } else {
+                double qL[NV], qR[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const int fb = (a * NV + v) * NF + f;
+                    qL[v] = s_qp[fb * EB + e];
+                    qR[v] = s_t[fb * EB + e];
+                }
+                if (a == 0) roe<DIM>(ph, 0, qL, qR, Fr);
+                else if (a == 1) roe<DIM>(ph, 1, qL, qR, Fr);
+                else roe<DIM>(ph, DIM - 1, qL, qR, Fr);
+            }
+        }
+        __syncthreads();
+        if (!active || !roe_wave) return;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int fb = (a * NV + v) * NF + f;
+            Fs[(size_t)fb * m.Ne + k] = Fr[v] - s_x[fb * EB + e];
+        }
     }
 }
 
@@ -898,10 +980,10 @@ hipError_t run_on(const frpmg_ctx *ctx, const Level &L, const MeshK &m, double *
     SrcK src{a.dq, a.v, a.alpha, S::NP};
     const dim3 g1((m.Ne + S::EBF - 1) / S::EBF);
     if (save) {
-        hipLaunchKernelGGL((k_faces<DIM, P, MODE, true>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, Jp, Fs,
+        hipLaunchKernelGGL((k_faces<DIM, P, MODE, true>), g1, dim3(S::NTF2), 0, s, m, src, L.ops, ctx->phys, Jp, Fs,
                            *save);
     } else {
-        hipLaunchKernelGGL((k_faces<DIM, P, MODE, false>), g1, dim3(S::NTF), 0, s, m, src, L.ops, ctx->phys, Jp,
+        hipLaunchKernelGGL((k_faces<DIM, P, MODE, false>), g1, dim3(S::NTF2), 0, s, m, src, L.ops, ctx->phys, Jp,
                            Fs, FaceSave{nullptr, nullptr, nullptr, nullptr});
     }
     OutK o{a.r, a.r0, a.x, a.v, a.sigma, a.dscale};
