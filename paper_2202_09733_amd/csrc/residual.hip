@@ -52,6 +52,7 @@ struct Shape {
     // (p = 0) takes 64 elements per workgroup to bound the LDS staging
     static constexpr int EB = (P == 1) ? 64 : ((256 / NP) > 0 ? (256 / NP) : 1);
     static constexpr int NT = round64(NP * EB);
+    static constexpr int NTV = (DIM == 2) ? 2 * NT : NT;  // volume kernel threads (2D: two lanes per point)
     // face kernel: one lane per (element, + face point), the lanes of each
     // flux direction in whole wavefronts (LPA per axis), so that no
     // wavefront runs two directions' flux code one after the other.  2D
@@ -655,16 +656,18 @@ struct OutK {
 };
 
 // Volume kernel.  In 2D every direction's flux is staged at once, so one
-// evaluation takes four barriers (staging; state read; fluxes written; flux
-// jumps formed) instead of three per direction, and the flux jumps of all
-// directions are formed in one pass; the fluxes overlay the staged state and
-// state jumps, which are dead by then (64x64 p = 4 linearised: 11.3 -> 10.1
-// us).  In 3D the staged fluxes would take 46 KB of LDS per workgroup,
+// evaluation takes five barriers (staging; state read; fluxes written; flux
+// jumps formed; divergence terms exchanged) instead of three per direction,
+// the flux jumps of all directions are formed in one pass, and two lanes
+// serve each (point, slot), one per direction, each finishing half of the
+// variables; the fluxes overlay the staged state and state jumps, which are
+// dead by then (64x64 p = 4 linearised inside the stage: 11.3 -> 10.3 us,
+// p = 2: 10.6 -> 8.2 us).  In 3D the staged fluxes would take 46 KB of LDS per workgroup,
 // three workgroups per CU instead of four, and the kernel ran slower (207 ->
 // 232 us at 32^3 p = 3): there it stages one direction at a time
 // (divergence()).  Same arithmetic, in the same order, either way.
 template <int DIM, int P, int MODE, int OUT>
-__global__ void __launch_bounds__((Shape<DIM, P>::NT))
+__global__ void __launch_bounds__((Shape<DIM, P>::NTV))
 k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, const double *__restrict__ Jp, const double *__restrict__ Fs,
          OutK o) {
     using S = Shape<DIM, P>;
@@ -678,6 +681,7 @@ k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, const double *__restrict__ Jp
     __shared__ double s_fm[NFACE];  // F* on the - faces, then F* - f^-
     __shared__ double s_fp[NFACE];  // F* on the + faces, then F* - f^+
     __shared__ double s_ih[DIM * EB];
+    __shared__ double s_x[BATCH ? NSTATE : 1];  // 2D: the divergence terms one half hands to the other
     double *s_u = s_a, *s_t = s_a + NSTATE;
     if (threadIdx.x == 0) ops = ops_in;
     const int k0 = xcd_block(blockIdx.x, gridDim.x) * EB;
@@ -698,7 +702,9 @@ k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, const double *__restrict__ Jp
         s_fm[t] = vm;
     }
     __syncthreads();
-    const int t = threadIdx.x;
+    // 2D: two halves of NT lanes, half h taking direction h
+    const int h = BATCH ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / S::NT) : 0;
+    const int t = BATCH ? (int)threadIdx.x - h * S::NT : (int)threadIdx.x;
     const int e = t % EB, i = t / EB;
     const bool active = (t < NP * EB) && (e < ne);
     double acc[NV];
@@ -706,7 +712,10 @@ k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, const double *__restrict__ Jp
         divergence<DIM, P, EB, EB>(ops, ph, s_u, s_t, s_fm, s_fp, s_ih, active, e, i, acc);
         if (!active) return;
     } else {
-        double F[DIM][NV];
+        // two lanes per (point, slot): half h forms direction h's flux and
+        // divergence; the halves meet through LDS, each finishing half of
+        // the variables
+        double F[NV];
         if (active) {
             double g[DIM][NV];
 #pragma unroll
@@ -730,21 +739,21 @@ k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, const double *__restrict__ Jp
             VGrad<DIM> vg;
             pstate<DIM>(ph, q, st);
             vgrad<DIM>(st, g, vg);
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
+            auto flux = [&](auto Ac) {
+                constexpr int A = decltype(Ac)::value;
                 double FI[NV], FV[NV];
-                inviscid_dev<DIM>(ph, a, st, FI);
-                viscous_dir<DIM>(ph, a, st, vg, FV);
+                inviscid_dev<DIM>(ph, A, st, FI);
+                viscous_dir<DIM>(ph, A, st, vg, FV);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) F[a][v] = FI[v] - FV[v];
-            }
+                for (int v = 0; v < NV; ++v) F[v] = FI[v] - FV[v];
+            };
+            if (h == 0) flux(std::integral_constant<int, 0>{});
+            else flux(std::integral_constant<int, 1>{});
         }
         __syncthreads();  // every read of the state and the jumps is done
         if (active) {
 #pragma unroll
-            for (int a = 0; a < DIM; ++a)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) s_a[((a * NV + v) * NP + i) * EB + e] = F[a][v];
+            for (int v = 0; v < NV; ++v) s_a[((h * NV + v) * NP + i) * EB + e] = F[v];
         }
         __syncthreads();
         // flux jumps on both faces normal to every axis
@@ -766,22 +775,35 @@ k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, const double *__restrict__ Jp
             s_fp[t2] -= fp;
         }
         __syncthreads();
-        if (!active) return;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
+        // direction h's divergence term d (before the 2/h factor), for every variable
+        double dd[NV];
+        if (active) {
             int f, ia;
-            S::split(i, a, f, ia);
-            const double ih = s_ih[a * EB + e];
+            S::split(i, h, f, ia);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 double d = 0.0;
 #pragma unroll
-                for (int j = 0; j < P; ++j) d += ops.D[ia][j] * s_a[((a * NV + v) * NP + S::line(a, f, j)) * EB + e];
-                const int fi = ((a * NV + v) * NF + f) * EB + e;
+                for (int j = 0; j < P; ++j) d += ops.D[ia][j] * s_a[((h * NV + v) * NP + S::line(h, f, j)) * EB + e];
+                const int fi = ((h * NV + v) * NF + f) * EB + e;
                 d += s_fm[fi] * ops.gLd[ia] + s_fp[fi] * ops.gRd[ia];
-                acc[v] += ih * d;
+                dd[v] = d;
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if ((v < NV / 2) != (h == 0)) s_x[(v * NP + i) * EB + e] = dd[v];  // the other half finishes v
+        }
+        __syncthreads();
+        if (!active) return;
+        const double ih0 = s_ih[e], ih1 = s_ih[EB + e];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            acc[v] = 0.0;
+            if ((v < NV / 2) == (h == 0)) {
+                const double o = s_x[(v * NP + i) * EB + e];
+                const double d0 = (h == 0) ? dd[v] : o, d1 = (h == 0) ? o : dd[v];
+                acc[v] += ih0 * d0;
+                acc[v] += ih1 * d1;
             }
         }
     }
@@ -789,18 +811,23 @@ k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, const double *__restrict__ Jp
     // the optional subtrahend x is tested once, outside the unrolled loop (a
     // test per variable inside it more than doubled the registers)
     const double *xs = o.x;
+    // the variables this lane finishes (all of them but in the 2D two-lane form)
+    auto mine = [&](int v) { return !BATCH || ((v < NV / 2) == (h == 0)); };
     if (OUT == OUT_R) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) o.r[((size_t)v * NP + i) * m.Ne + k] = -acc[v];
+        for (int v = 0; v < NV; ++v)
+            if (mine(v)) o.r[((size_t)v * NP + i) * m.Ne + k] = -acc[v];
     } else if (xs) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+            if (!mine(v)) continue;
             const size_t idx = ((size_t)v * NP + i) * m.Ne + k;
             o.r[idx] = o.sigma * o.vdir[idx] - (-acc[v] - o.r0[idx]) / (alpha * o.dscale) - xs[idx];
         }
     } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+            if (!mine(v)) continue;
             const size_t idx = ((size_t)v * NP + i) * m.Ne + k;
             o.r[idx] = o.sigma * o.vdir[idx] - (-acc[v] - o.r0[idx]) / (alpha * o.dscale);
         }
@@ -987,7 +1014,7 @@ hipError_t run_on(const frpmg_ctx *ctx, const Level &L, const MeshK &m, double *
                            Fs, FaceSave{nullptr, nullptr, nullptr, nullptr});
     }
     OutK o{a.r, a.r0, a.x, a.v, a.sigma, a.dscale};
-    hipLaunchKernelGGL((k_volume<DIM, P, MODE, OUT>), dim3((m.Ne + S::EB - 1) / S::EB), dim3(S::NT), 0, s, m, src,
+    hipLaunchKernelGGL((k_volume<DIM, P, MODE, OUT>), dim3((m.Ne + S::EB - 1) / S::EB), dim3(S::NTV), 0, s, m, src,
                        L.ops, ctx->phys, Jp, Fs, o);
     return hipGetLastError();
 }
