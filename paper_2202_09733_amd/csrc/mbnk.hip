@@ -111,7 +111,71 @@ __global__ void __launch_bounds__(kThreads) k_mb_gather(MeshK m, int nb, int col
     for (size_t t = threadIdx.x; t < nn; t += blockDim.x) out[c * nn + t] = D[(size_t)k * nn + t];
 }
 
-// U_b = D_b - sum_f O[b][f] (Rinv_r O[r][f^1]), r the red neighbour across face f
+// One nb x nb block (column-major) read through a buffer resource: a read
+// outside the block (row or column >= nb, the padding of the 16 x 16 tiles)
+// returns 0 from the range check, so the operand loads carry no branches.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+struct BlockRd {
+    __amdgpu_buffer_rsrc_t rs;
+    int nb;
+    __device__ BlockRd(const double *p, int nb_)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), (short)0, nb_ * nb_ * (int)sizeof(double),
+                                               0x00020000)),
+          nb(nb_) {}
+    __device__ __forceinline__ double at(int i, int j) const {
+        const unsigned off = (i < nb && j < nb) ? (unsigned)(j * nb + i) * (unsigned)sizeof(double) : 0x80000000u;
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    }
+};
+
+// acc[q] += A[16 it + rows][k] B[k][16 (jt0 + q) + cols] over k < nb on
+// v_mfma_f64_16x16x4f64 (lane (r16, g): A row r16, k = 4 ks + g; B k = 4 ks +
+// g, column r16; result rows g + 4v, column r16), for nq <= 3 column tiles.
+// The operands of the next four k steps are read while the current four
+// are multiplied.
+template <typename LA, typename LB>
+__device__ __forceinline__ void schur_tiles(int nb, int it, int jt0, int nq, const LA &la, const LB &lb,
+                                            f64x4_t (&acc)[3]) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
+    const int i = it * 16 + r16;
+    int jc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) jc[q] = (jt0 + (q < nq ? q : 0)) * 16 + r16;
+    double a[2][4], bb[2][4][3];
+    auto load = [&](int buf, int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + 4 * u + g;
+            a[buf][u] = la(i, k);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) bb[buf][u][q] = lb(k, jc[q]);
+        }
+    };
+    auto mma = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (q < nq) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[buf][u], bb[buf][u][q], acc[q], 0, 0, 0);
+    };
+    const int nk = (nb + 15) / 16;  // blocks of four k steps, two register buffers
+    load(0, 0);
+    for (int kb = 0; kb < nk; kb += 2) {
+        if (kb + 1 < nk) load(1, (kb + 1) * 16);
+        mma(0);
+        if (kb + 1 >= nk) break;
+        if (kb + 2 < nk) load(0, (kb + 2) * 16);
+        mma(1);
+    }
+}
+
+// U_b = D_b - sum_f O[b][f] (Rinv_r O[r][f^1]), r the red neighbour across
+// face f.  One workgroup per black element; per face T = Rinv_r O[r][f^1] is
+// formed in LDS, then O[b][f] T is subtracted from U, both on FP64 MFMA
+// (tiles of 16 x 16, in groups of one row tile and up to three column
+// tiles, dealt out to the wavefronts).  Each lane owns the same U entries
+// for every face, and the first face starts from D_b.
 __global__ void __launch_bounds__(kThreads) k_mb_schur(MeshK m, int nb, int nface, const double *__restrict__ D,
                                                        const double *__restrict__ O,
                                                        const double *__restrict__ Rinv, double *__restrict__ U) {
@@ -119,26 +183,57 @@ __global__ void __launch_bounds__(kThreads) k_mb_schur(MeshK m, int nb, int nfac
     const int c = blockIdx.x;
     const int k = colour_elem(m, c, 1);
     const int nn = nb * nb;
+    const int nt = (nb + 15) / 16, njg = (nt + 2) / 3, ngroup = nt * njg;
+    const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
     double *u = U + (size_t)c * nn;
-    for (int e = threadIdx.x; e < nn; e += blockDim.x) u[e] = D[(size_t)k * nn + e];
+    const BlockRd Db(D + (size_t)k * nn, nb);
     for (int f = 0; f < nface; ++f) {
         const int r = neighbour(m, k, f >> 1, (f & 1) ? 1 : -1);
-        const double *ri = Rinv + (size_t)(r >> 1) * nn;
-        const double *orb = O + ((size_t)r * nface + (f ^ 1)) * nn;
-        const double *obr = O + ((size_t)k * nface + f) * nn;
+        const BlockRd Ri(Rinv + (size_t)(r >> 1) * nn, nb);
+        const BlockRd Orb(O + ((size_t)r * nface + (f ^ 1)) * nn, nb);
+        const BlockRd Obr(O + ((size_t)k * nface + f) * nn, nb);
         __syncthreads();  // the previous face's products have read T
-        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-            const int i = e % nb, jj = e / nb;
-            double acc = 0.0;
-            for (int l = 0; l < nb; ++l) acc += ri[l * nb + i] * orb[jj * nb + l];
-            T[e] = acc;
+        for (int gi = wave; gi < ngroup; gi += nwave) {
+            const int it = gi / njg, jt0 = (gi % njg) * 3, nq = min(3, nt - jt0);
+            f64x4_t acc[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[q] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+            schur_tiles(nb, it, jt0, nq, [&](int i, int kk) { return Ri.at(i, kk); },
+                        [&](int kk, int j) { return Orb.at(kk, j); }, acc);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (q >= nq) continue;
+                const int j = (jt0 + q) * 16 + r16;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = it * 16 + g + 4 * v;
+                    if (i < nb && j < nb) T[j * nb + i] = acc[q][v];
+                }
+            }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-            const int i = e % nb, jj = e / nb;
-            double acc = 0.0;
-            for (int l = 0; l < nb; ++l) acc += obr[l * nb + i] * T[jj * nb + l];
-            u[e] -= acc;
+        for (int gi = wave; gi < ngroup; gi += nwave) {
+            const int it = gi / njg, jt0 = (gi % njg) * 3, nq = min(3, nt - jt0);
+            f64x4_t acc[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[q] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+            // B = T, read at clamped indices: its rows k >= nb meet zero A columns
+            schur_tiles(nb, it, jt0, nq, [&](int i, int kk) { return Obr.at(i, kk); },
+                        [&](int kk, int j) { return T[min(j, nb - 1) * nb + min(kk, nb - 1)]; }, acc);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (q >= nq) continue;
+                const int j = (jt0 + q) * 16 + r16;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = it * 16 + g + 4 * v;
+                    if (i < nb && j < nb) {
+                        const double prev = (f == 0) ? Db.at(i, j) : u[j * nb + i];
+                        u[j * nb + i] = prev - acc[q][v];
+                    }
+                }
+            }
         }
     }
 }
