@@ -770,14 +770,20 @@ __global__ void __launch_bounds__(64) k_gj_colperm(int nb, const int *__restrict
     for (int c = tid; c < nb; c += blockDim.x) sigma[base + pi[c]] = c;
 }
 
-__global__ void k_to_float(size_t n, const double *__restrict__ a, float *__restrict__ b) {
+// Narrow storage of the blocked inversion's result: stored column j of
+// block k is column sigma[k][j] of the inverse, so the conversion writes it
+// there and the narrow apply needs no column gather (64x64 p = 4, BF16:
+// 17.2 -> 16.1 us per fine apply).
+template <typename T>
+__global__ void k_to_narrow_placed(int Ne, int nb, const double *__restrict__ a, const int *__restrict__ sigma,
+                                   T *__restrict__ b) {
+    const size_t nn = (size_t)nb * nb, n = nn * Ne;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
-}
-
-__global__ void k_to_bf16(size_t n, const double *__restrict__ a, __bf16 *__restrict__ b) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (__bf16)(float)a[i];
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const size_t k = t / nn, rem = t - k * nn;
+        const int j = (int)(rem / nb), i = (int)(rem - (size_t)j * nb);
+        b[k * nn + (size_t)sigma[k * nb + j] * nb + i] = (T)(float)a[t];
+    }
 }
 
 }  // namespace
@@ -859,16 +865,19 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
                 hipLaunchKernelGGL(k_gj_update_wide, grid(cm), dim3(256), 0, s, Ne, nb, c0, bw, cm, L.blk64, twin);
         }
         hipLaunchKernelGGL(k_gj_colperm, dim3(Ne), dim3(64), 0, s, nb, L.perm, L.colperm);
-        L.inv_cols = L.colperm;
-        const size_t n = (size_t)Ne * nb * nb;
         if (precision == FR_PREC_FP64) {
             L.inv = L.blk64;
+            L.inv_cols = L.colperm;  // the apply gathers r through the placement
         } else if (precision == FR_PREC_BF16_STORE) {
-            hipLaunchKernelGGL(k_to_bf16, dim3(4096), dim3(256), 0, s, n, L.blk64, L.inv16);
+            hipLaunchKernelGGL(k_to_narrow_placed<__bf16>, dim3(4096), dim3(256), 0, s, Ne, nb, L.blk64, L.colperm,
+                               L.inv16);
             L.inv = L.inv16;
+            L.inv_cols = nullptr;
         } else {
-            hipLaunchKernelGGL(k_to_float, dim3(4096), dim3(256), 0, s, n, L.blk64, L.inv32);
+            hipLaunchKernelGGL(k_to_narrow_placed<float>, dim3(4096), dim3(256), 0, s, Ne, nb, L.blk64, L.colperm,
+                               L.inv32);
             L.inv = L.inv32;
+            L.inv_cols = nullptr;
         }
         L.inv_prec = precision;
         return hipGetLastError();
