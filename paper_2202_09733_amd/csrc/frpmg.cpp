@@ -865,44 +865,69 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int jend = 0;
-        for (int j = 0; j < m; ++j) {
-            // one Arnoldi step: z_j = M v_j, w = A z_j, CGS2 against v_0..v_j,
-            // v_{j+1} = w / ||w|| (the norm stays on the device)
-            const bool timed = !gu && ctx->ph_ev[0];
-            auto step = [&, j](hipStream_t st) {
-                double *vj = V + (size_t)j * ld;
-                double *zj = Z + (size_t)j * ld;
-                if (timed) HIPCHK(hipEventRecord(ctx->ph_ev[0], st));
+        // Arnoldi step j (z_j = M v_j, w = A z_j, CGS2 against v_0..v_j,
+        // v_{j+1} = w / ||w||, the norm kept on the device), then the copy of
+        // its Hessenberg column to pinned buffer j & 1.  Step j + 1 needs only
+        // v_{j+1}, so while the residual estimate is far from the target it
+        // is enqueued before the host waits for step j: the GPU does not idle
+        // for the host's round trip (64x64 p = 4: ~30 us per iteration).  A
+        // step launched ahead of the one that converges is wasted work, so
+        // near the target, and with the learned preconditioner (whose stall
+        // fallback switches preconditioners between steps), steps run one at
+        // a time.
+        const bool timed = !gu && ctx->ph_ev[0];
+        auto launch = [&](int jj) {
+            const int buf = jj & 1;
+            hipEvent_t *ev = ctx->ph_ev + 4 * buf;
+            auto step = [&, jj, ev](hipStream_t st) {
+                double *vj = V + (size_t)jj * ld;
+                double *zj = Z + (size_t)jj * ld;
+                if (timed) HIPCHK(hipEventRecord(ev[0], st));
                 M(vj, zj, st);
-                if (timed) HIPCHK(hipEventRecord(ctx->ph_ev[1], st));
+                if (timed) HIPCHK(hipEventRecord(ev[1], st));
                 A(zj, w, st);
-                if (timed) HIPCHK(hipEventRecord(ctx->ph_ev[2], st));
-                HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H1, st));
-                HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H1, w, st));
-                HIPCHK(vec_mdot(ctx, N, j + 1, V, ld, w, ctx->red_out + RO_H2, st));
-                HIPCHK(vec_gemv_sub(N, j + 1, V, ld, ctx->red_out + RO_H2, w, st));
-                HIPCHK(vec_dot_normalize(ctx, N, w, ctx->red_out + RO_N2, V + (size_t)(j + 1) * ld, st));
-                if (timed) HIPCHK(hipEventRecord(ctx->ph_ev[3], st));
+                if (timed) HIPCHK(hipEventRecord(ev[2], st));
+                HIPCHK(vec_mdot(ctx, N, jj + 1, V, ld, w, ctx->red_out + RO_H1, st));
+                HIPCHK(vec_gemv_sub(N, jj + 1, V, ld, ctx->red_out + RO_H1, w, st));
+                HIPCHK(vec_mdot(ctx, N, jj + 1, V, ld, w, ctx->red_out + RO_H2, st));
+                HIPCHK(vec_gemv_sub(N, jj + 1, V, ld, ctx->red_out + RO_H2, w, st));
+                HIPCHK(vec_dot_normalize(ctx, N, w, ctx->red_out + RO_N2, V + (size_t)(jj + 1) * ld, st));
+                if (timed) HIPCHK(hipEventRecord(ev[3], st));
             };
             if (gu) {
                 std::vector<unsigned long long> key = gu->key;
-                key.push_back((unsigned long long)j);
+                key.push_back((unsigned long long)jj);
                 run_graph(ctx, key, gu->cnt, step, s);
             } else {
                 Range r("arnoldi step");
                 step(s);
             }
-            HIPCHK(hipMemcpyAsync(ctx->host_pinned, ctx->red_out, RO_SIZE * sizeof(double), hipMemcpyDeviceToHost,
-                                  s));
-            HIPCHK(hipStreamSynchronize(s));
+            // the Hessenberg column only (the y staging at RO_Y stays untouched)
+            HIPCHK(hipMemcpyAsync(buf ? ctx->host_pinned2 : ctx->host_pinned, ctx->red_out,
+                                  (RO_N2 + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(ctx->step_ev[buf], s));
+        };
+        int launched = -1;         // the last step enqueued in this cycle
+        double est = beta;         // the residual estimate before step j
+        constexpr double kAhead = 30.0;  // launch ahead while the estimate exceeds kAhead x the target
+        for (int j = 0; j < m; ++j) {
+            if (launched < j) {
+                launch(j);
+                launched = j;
+            }
+            if (!stall && j + 1 < m && est > kAhead * target) {
+                launch(j + 1);
+                launched = j + 1;
+            }
+            HIPCHK(hipEventSynchronize(ctx->step_ev[j & 1]));
             if (timed) {
                 for (int ph = 0; ph < 3; ++ph) {
                     float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, ctx->ph_ev[ph], ctx->ph_ev[ph + 1]));
+                    HIPCHK(hipEventElapsedTime(&ms, ctx->ph_ev[4 * (j & 1) + ph], ctx->ph_ev[4 * (j & 1) + ph + 1]));
                     ctx->ph_acc[ph] += 1e-3 * ms;
                 }
             }
-            const double *hp = ctx->host_pinned;
+            const double *hp = (j & 1) ? ctx->host_pinned2 : ctx->host_pinned;
             for (int i = 0; i <= j; ++i) Hc(i, j) = hp[RO_H1 + i] + hp[RO_H2 + i];
             const double hn = std::sqrt(hp[RO_N2]);
             Hc(j + 1, j) = hn;
@@ -921,6 +946,7 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
             kr.iters++;
             jend = j + 1;
             kr.res_est = std::fabs(g[j + 1]);
+            est = kr.res_est;
             if (!std::isfinite(kr.res_est) || !std::isfinite(hn)) {
                 if (stall && stall->active) {
                     // the learned preconditioner produced a non-finite direction:
@@ -967,6 +993,9 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
             HIPCHK(vec_scale_copy(N, Scal{1.0 / beta, nullptr}, w, V, s));
             continue;
         }
+        // a step launched ahead of the one that ended the cycle finishes
+        // first (it leaves x, and the basis the update uses, untouched)
+        if (launched >= jend) HIPCHK(hipStreamSynchronize(s));
         // back substitution with the triangular Hessenberg factor
         for (int i = jend - 1; i >= 0; --i) {
             double t = g[i];
@@ -1037,6 +1066,8 @@ void ensure_krylov(frpmg_ctx *ctx, int m) {
     if (!ctx->sdx) ctx->sdx = dalloc(ctx, N);
     for (auto &e : ctx->ph_ev)
         if (!e) HIPCHK(hipEventCreate(&e));
+    for (auto &e : ctx->step_ev)
+        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 double now() {
@@ -1747,6 +1778,10 @@ void destroy_all(frpmg_ctx *ctx) {
         if (e) (void)hipEventDestroy(e);
         e = nullptr;
     }
+    for (auto &e : ctx->step_ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     ctx->cap_stream = nullptr;
     lcc_free(ctx);
@@ -1781,6 +1816,7 @@ void destroy_all(frpmg_ctx *ctx) {
     dfree(ctx->red_out);
     dfree(ctx->scal);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+    if (ctx->host_pinned2) (void)hipHostFree(ctx->host_pinned2);
     double *bufs[] = {ctx->q1, ctx->r1, ctx->wY, ctx->wG, ctx->wXs, ctx->cZ0, ctx->cZ, ctx->cS, ctx->cG, ctx->cd,
                       ctx->V, ctx->Zk, ctx->kw, ctx->sq, ctx->srq, ctx->sF, ctx->sb, ctx->sdx,
                       ctx->stv, ctx->stw};
@@ -1872,6 +1908,8 @@ fr_status fr_create(const fr_mesh_desc *d, frpmg_ctx **out) {
         void *hp = nullptr;
         HIPCHK(hipHostMalloc(&hp, RO_SIZE * sizeof(double), hipHostMallocDefault));
         ctx->host_pinned = (double *)hp;
+        HIPCHK(hipHostMalloc(&hp, RO_SIZE * sizeof(double), hipHostMallocDefault));
+        ctx->host_pinned2 = (double *)hp;
         const size_t N0 = ctx->lv[0].N;
         ctx->wY = dalloc(ctx, N0);
         ctx->wG = dalloc(ctx, N0);

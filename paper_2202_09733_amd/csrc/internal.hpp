@@ -247,7 +247,8 @@ struct frpmg_ctx {
     double *red_partial = nullptr;  // [128][kRedBlocks]
     double *red_out = nullptr;      // [64]
     double *scal = nullptr;         // device scalars [16]
-    double *host_pinned = nullptr;  // pinned host staging [64]
+    double *host_pinned = nullptr;   // pinned host staging [RO_SIZE]
+    double *host_pinned2 = nullptr;  // second staging for an Arnoldi step launched ahead [RO_SIZE]
     double *noalloc_scratch = nullptr;  // this device's address of fr_residual_noalloc's array
     // preconditioner workspaces (allocated at creation)
     double *pq = nullptr, *prq = nullptr;    // linearisation point (borrowed pointers)
@@ -270,7 +271,9 @@ struct frpmg_ctx {
     frpmg::Mbnk *mb = nullptr;
     // per-phase timing of host-launched Arnoldi steps (events created at the first stage solve):
     // preconditioner, FD product, orthogonalisation and normalisation, seconds summed over a stage
-    hipEvent_t ph_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // (one set of four per buffer of two Arnoldi steps in flight)
+    hipEvent_t ph_ev[8] = {};
+    hipEvent_t step_ev[2] = {};  // an Arnoldi step's Hessenberg column has reached its pinned staging
     double ph_acc[3] = {0.0, 0.0, 0.0};
     // captured Arnoldi steps, replayed on the caller's stream
     hipStream_t cap_stream = nullptr;
