@@ -316,6 +316,30 @@ def test_row_stage_tiny_matches_oracle(orc, tol, verify):
     assert e <= (1e-7 if not verify else 1e-6)
 
 
+@pytest.mark.parametrize("m", [2, 3, 5])
+def test_row_stage_short_cycles_matches_oracle(orc, m):
+    """FGMRES(m) with m = 2, 3, 5: many restarts, so cycles end both on
+    the basis limit and on convergence right after a step launched ahead of
+    the host's check.  The GPU takes the oracle's restart count and
+    solution."""
+    require_gpu()
+    announce("row stage tiny, m %d" % m)
+    wl = W.make_bump_workload(n=(4, 4), p0=2, p1=1, Ma=0.2, dt_factor=10.0, seed=13, scheme="row", amp=5e-2)
+    fr = capi.FR.from_workload(wl)
+    Y, st = fr.solve_stage(capi.stage_config_for(wl, tol=1e-8, verify=1, m=m, max_restarts=200),
+                           fr.to_dev(wl.dq))
+    L0 = orc.Level(**wl.level_kwargs(wl.p0))
+    L1 = orc.Level(**wl.level_kwargs(wl.p1))
+    Y_ref, so = orc.row_stage(L0, L1, wl.dq, wl.dt, wl.a_ii, m=m, max_restarts=200, tol=1e-8, verify=True)
+    assert st["converged"] == 1 and so.converged
+    assert st["true_rel_res"] <= 1e-8
+    e = rel(Y.cpu().numpy(), Y_ref)
+    print("m %d: GPU %d FGMRES / %d restarts, oracle %d; rel. difference %.2e"
+          % (m, st["gmres_iters"], st["restarts"], so.gmres_iters, e))
+    assert abs(st["gmres_iters"] - so.gmres_iters) <= 1
+    assert e <= 1e-6
+
+
 @pytest.fixture(scope="module")
 def tgv32_oracle_rhs(orc):
     wl = W.tgv_32cubed_p3()
