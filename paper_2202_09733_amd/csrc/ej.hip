@@ -169,24 +169,27 @@ static_assert(kTouchStride == 1 + 2 * kTouch, "touched-row list: count, rows[kTo
 // S (contents leave S only by a swap with a later pivot row), so its source
 // lies inside the window's rows.
 
-// Panel factorisation with the panel in registers, two wavefronts per block:
-// lane t of the workgroup owns rows t, t + 128, ... (kPanel values each, RPL
-// rows), so a pivot step needs two barriers between two wavefronts (one
-// wavefront per 64 rows took three barriers across up to five wavefronts and
-// spent most of its time waiting at them).  Per step: each wavefront's argmax
-// by shuffles (the lowest row wins ties), combined through LDS (barrier); the
-// owners of the pivot row and of row c put them in LDS (barrier); every lane
-// swaps and eliminates its rows against the pivot row, read column by column
-// from LDS.  The steps are instantiated per panel column so that every
-// register index is a constant (a runtime index would put the rows in scratch
-// memory).  Outputs: the panel columns in place, the pivot rows, the
-// touched-row lists and the pivot flags.
-constexpr int kPanel2Threads = 128;
+// Panel factorisation with the panel in registers, NW wavefronts per block
+// (NW = 2..4): lane t of the workgroup owns rows t, t + 64 NW, ... (kPanel
+// values each, RPL rows), so a pivot step needs two barriers whatever NW is.
+// Per step: each wavefront's argmax by shuffles (the lowest row wins ties),
+// combined through LDS (barrier); the owners of the pivot row and of row c
+// put them in LDS (barrier); every lane swaps and eliminates its rows against
+// the pivot row, read column by column from LDS.  The steps are instantiated
+// per panel column so that every register index is a constant (a runtime
+// index would put the rows in scratch memory).  At most two rows per lane
+// (64 doubles) keep the rows in registers without spilling; a block of 320
+// rows takes three wavefronts of two rows per lane (3.2 ms per launch on
+// 32,768 blocks, against 3.5 ms for two wavefronts of three rows, which
+// spill, and 5.0 ms for five wavefronts of one row, whose steps wait longer
+// at the barriers).  Outputs: the panel columns in place, the pivot rows,
+// the touched-row lists and the pivot flags.
+constexpr int kPanel2MaxWaves = 4;
 
 struct Panel2Lds {
-    double v[2];
-    int i[2];
-    int cnt[4][2];
+    double v[kPanel2MaxWaves];
+    int i[kPanel2MaxWaves];
+    int cnt[2][kPanel2MaxWaves];
     int porg, corg, porg2, corg2;
     double pivrow[kPanel];
     double oldc[kPanel];
@@ -194,17 +197,18 @@ struct Panel2Lds {
     int tsrc[kTouch];
 };
 
-template <int RPL, int CC>
+template <int RPL, int NW, int CC>
 __device__ __forceinline__ void panel2_step(double (&x)[RPL][kPanel], int (&org)[RPL], int (&org2)[RPL],
                                             Panel2Lds &sh, int t, int nb, int c0, int bw, int *__restrict__ perm,
                                             int &flags) {
+    constexpr int NT = 64 * NW;
     if (CC >= bw) return;
     const int c = c0 + CC;
     double best = -1.0;
     int bi = 0x7fffffff;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
-        const int r = s * kPanel2Threads + t;
+        const int r = s * NT + t;
         if (r >= c && r < nb) argmax_combine(best, bi, fabs(x[s][CC]), r);
     }
 #pragma unroll
@@ -220,11 +224,12 @@ __device__ __forceinline__ void panel2_step(double (&x)[RPL][kPanel], int (&org)
     __syncthreads();
     double bv = sh.v[0];
     int p = sh.i[0];
-    argmax_combine(bv, p, sh.v[1], sh.i[1]);
+#pragma unroll
+    for (int w = 1; w < NW; ++w) argmax_combine(bv, p, sh.v[w], sh.i[w]);
     if (p < c || p >= nb) p = c;  // a column of NaNs compares false everywhere: keep row c
     if (t == 0) perm[(size_t)blockIdx.x * nb + c] = p;
-    const int sp = p / kPanel2Threads, tp = p - sp * kPanel2Threads;
-    const int sc = c / kPanel2Threads, tc = c - sc * kPanel2Threads;
+    const int sp = p / NT, tp = p - sp * NT;
+    const int sc = c / NT, tc = c - sc * NT;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         if (s == sp && t == tp) {
@@ -290,26 +295,27 @@ __device__ __forceinline__ void panel2_step(double (&x)[RPL][kPanel], int (&org)
     }
 }
 
-template <int RPL, int... CC>
+template <int RPL, int NW, int... CC>
 __device__ __forceinline__ void panel2_steps(std::integer_sequence<int, CC...>, double (&x)[RPL][kPanel],
                                              int (&org)[RPL], int (&org2)[RPL], Panel2Lds &sh, int t, int nb,
                                              int c0, int bw, int *__restrict__ perm, int &flags) {
-    (panel2_step<RPL, CC>(x, org, org2, sh, t, nb, c0, bw, perm, flags), ...);
+    (panel2_step<RPL, NW, CC>(x, org, org2, sh, t, nb, c0, bw, perm, flags), ...);
 }
 
 // Write the touched-row list of the window [lo, lo + w) from the lanes' row
 // origins: slot r - lo for the window rows, then the moved rows in row
-// order, ranked by wavefront ballots per slot (rows s*128 + t: slot major,
+// order, ranked by wavefront ballots per slot (rows s*64NW + t: slot major,
 // then wavefront, then lane).  Every lane takes part; starts with a barrier.
-template <int RPL>
+template <int RPL, int NW>
 __device__ __forceinline__ void write_touch(const int (&org)[RPL], int lo, int w, int nb, int t, Panel2Lds &sh,
                                             int *__restrict__ tl) {
+    constexpr int NT = 64 * NW;
     const int lane = t & 63, wv = t >> 6;
     unsigned long long m[RPL];
     __syncthreads();  // the previous readers of sh.cnt are done
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
-        const int r = s * kPanel2Threads + t;
+        const int r = s * NT + t;
         const bool inS = r >= lo && r < lo + w;
         m[s] = __ballot(r < nb && !inS && org[s] != r);
         if (lane == 0) sh.cnt[s][wv] = __popcll(m[s]);
@@ -318,9 +324,14 @@ __device__ __forceinline__ void write_touch(const int (&org)[RPL], int lo, int w
     int off = w;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
-        const int r = s * kPanel2Threads + t;
+        const int r = s * NT + t;
         const bool inS = r >= lo && r < lo + w;
-        const int base = off + (wv == 1 ? sh.cnt[s][0] : 0);
+        int base = off, all = 0;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            base += u < wv ? sh.cnt[s][u] : 0;
+            all += sh.cnt[s][u];
+        }
         int slot = -1;
         if (inS)
             slot = r - lo;
@@ -330,7 +341,7 @@ __device__ __forceinline__ void write_touch(const int (&org)[RPL], int lo, int w
             tl[1 + slot] = r;
             tl[1 + kTouch + slot] = org[s];
         }
-        off += sh.cnt[s][0] + sh.cnt[s][1];
+        off += all;
     }
     if (t == 0) tl[0] = off;
 }
@@ -341,20 +352,22 @@ __device__ __forceinline__ void write_touch(const int (&org)[RPL], int lo, int w
 // (before it is overwritten with this sub-panel's own list); the list of the
 // whole window, with the interchanges of both sub-panels composed, goes to
 // touch2.
-template <int RPL>
-__global__ void __launch_bounds__(kPanel2Threads, RPL <= 3 ? 2 : 1)
+template <int RPL, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_gj_panel2(int nb, int c0, int bw, int wlo, double *__restrict__ A, int *__restrict__ perm,
             int *__restrict__ touch, int *__restrict__ touch2, int *__restrict__ status) {
+    static_assert(RPL <= 2 && NW >= 2 && NW <= kPanel2MaxWaves, "rows per lane, wavefronts per block");
+    constexpr int NT = 64 * NW;
     __shared__ Panel2Lds sh;
     const int t = threadIdx.x;
     const bool second = wlo < c0;
     double *Ak = A + (size_t)blockIdx.x * nb * nb;
     int *tl = touch + (size_t)blockIdx.x * kTouchStride;
     if (second) {
-        for (int r = t; r < nb; r += kPanel2Threads) sh.upos[r] = -1;
+        for (int r = t; r < nb; r += NT) sh.upos[r] = -1;
         __syncthreads();
         const int nu = min(tl[0], kTouch);
-        for (int u = t; u < nu; u += kPanel2Threads) {
+        for (int u = t; u < nu; u += NT) {
             const int r = tl[1 + u];
             if (r >= 0 && r < nb) sh.upos[r] = (short)u;
             sh.tsrc[u] = tl[1 + kTouch + u];
@@ -365,7 +378,7 @@ k_gj_panel2(int nb, int c0, int bw, int wlo, double *__restrict__ A, int *__rest
     int org[RPL], org2[RPL];
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
-        const int r = s * kPanel2Threads + t;
+        const int r = s * NT + t;
         org[s] = r;
         const int u = (second && r < nb) ? sh.upos[r] : -1;
         org2[s] = u >= 0 ? sh.tsrc[u] : r;
@@ -373,18 +386,18 @@ k_gj_panel2(int nb, int c0, int bw, int wlo, double *__restrict__ A, int *__rest
         for (int j = 0; j < kPanel; ++j) x[s][j] = (r < nb && j < bw) ? Ak[(size_t)(c0 + j) * nb + r] : 0.0;
     }
     int flags = 0;
-    panel2_steps<RPL>(std::make_integer_sequence<int, kPanel>{}, x, org, org2, sh, t, nb, c0, bw, perm, flags);
+    panel2_steps<RPL, NW>(std::make_integer_sequence<int, kPanel>{}, x, org, org2, sh, t, nb, c0, bw, perm, flags);
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
-        const int r = s * kPanel2Threads + t;
+        const int r = s * NT + t;
         if (r < nb) {
 #pragma unroll
             for (int j = 0; j < kPanel; ++j)
                 if (j < bw) Ak[(size_t)(c0 + j) * nb + r] = x[s][j];
         }
     }
-    write_touch<RPL>(org, c0, bw, nb, t, sh, tl);
-    if (second) write_touch<RPL>(org2, wlo, c0 + bw - wlo, nb, t, sh, touch2 + (size_t)blockIdx.x * kTouchStride);
+    write_touch<RPL, NW>(org, c0, bw, nb, t, sh, tl);
+    if (second) write_touch<RPL, NW>(org2, wlo, c0 + bw - wlo, nb, t, sh, touch2 + (size_t)blockIdx.x * kTouchStride);
     if (flags && t == 0) atomicOr(status, flags);
 }
 
@@ -814,22 +827,24 @@ hipError_t ej_invert(frpmg_ctx *ctx, int level, int precision, hipStream_t s) {
     if (ej_blocked(nb, precision)) {
         if (nb > kMaxNb || !L.perm || !L.touch || !L.colperm) return hipErrorInvalidValue;
         const bool mfma = precision == FR_PREC_FP32_BF16 || precision == FR_PREC_BF16_STORE;
-        const int rpl = (nb + kPanel2Threads - 1) / kPanel2Threads;  // rows per lane of the panel kernel
-        if (rpl > 4) return hipErrorInvalidValue;
+        // rows per lane x wavefronts of the panel kernel: one row per lane up
+        // to 256 rows, two above
         auto panel = [&](int c, int bw, int wlo, int *touch, int *touch2) {
-            const dim3 gp(Ne), bp(kPanel2Threads);
-            if (rpl == 1)
-                hipLaunchKernelGGL(k_gj_panel2<1>, gp, bp, 0, s, nb, c, bw, wlo, L.blk64, L.perm, touch, touch2,
-                                   L.dstatus);
-            else if (rpl == 2)
-                hipLaunchKernelGGL(k_gj_panel2<2>, gp, bp, 0, s, nb, c, bw, wlo, L.blk64, L.perm, touch, touch2,
-                                   L.dstatus);
-            else if (rpl == 3)
-                hipLaunchKernelGGL(k_gj_panel2<3>, gp, bp, 0, s, nb, c, bw, wlo, L.blk64, L.perm, touch, touch2,
-                                   L.dstatus);
+            const dim3 gp(Ne);
+#define FR_PANEL2(R, W)                                                                                        \
+    hipLaunchKernelGGL((k_gj_panel2<R, W>), gp, dim3(64 * W), 0, s, nb, c, bw, wlo, L.blk64, L.perm, touch, touch2, \
+                       L.dstatus)
+            if (nb <= 128)
+                FR_PANEL2(1, 2);
+            else if (nb <= 192)
+                FR_PANEL2(1, 3);
+            else if (nb <= 256)
+                FR_PANEL2(1, 4);
+            else if (nb <= 384)
+                FR_PANEL2(2, 3);
             else
-                hipLaunchKernelGGL(k_gj_panel2<4>, gp, bp, 0, s, nb, c, bw, wlo, L.blk64, L.perm, touch, touch2,
-                                   L.dstatus);
+                FR_PANEL2(2, 4);
+#undef FR_PANEL2
         };
         auto grid = [&](const ColMap &cm) {
             const int ntile = (cm.n + kUpdCols - 1) / kUpdCols;
