@@ -846,8 +846,16 @@ k_volume(MeshK m, SrcK src, Ops1D ops_in, Phys ph, const double *__restrict__ Jp
 // + trace, the D part of m's normal gradient and m's tangential gradient
 // components there -- the normal gradient at that face changes with k
 // through q* only.  These are saved by one base evaluation; each workgroup
-// then evaluates R_k for EB columns of one element (the slots), with the same
-// arithmetic as a global evaluation.
+// then evaluates R_k for EB columns of one element (the slots) at a time,
+// with the same arithmetic as a global evaluation.  A workgroup takes
+// `groups` such column groups of one element in turn: the element's state
+// and its neighbours' face data are read once (scattered reads, one cache
+// line per value in the element-fastest layout) and kept in LDS for all of
+// them.
+
+// column groups per workgroup: 32^3 p = 3, 320-column blocks: 64.6 ms with
+// one group per workgroup, 55.3 ms with 4, 52.7 with 16, 52.2 with 80
+constexpr int kFormGroups = 16;
 
 struct FormK {
     const double *dq;  // linearisation point
@@ -856,6 +864,7 @@ struct FormK {
     double *blocks;    // [Ne][nb][nb], column-major per block
     double sigma;
     int nb;
+    int groups;        // column groups of EB per workgroup
 };
 
 template <int DIM, int P>
@@ -864,7 +873,12 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_ej_form(MeshK m, Ops1D 
     constexpr int EB = S::EB, NV = S::NV, NP = S::NP, NF = S::NF;
     constexpr int NFACE = DIM * NV * NF * EB;
     constexpr int NSH = DIM * NV * NF;
+    // a copy of the element's state at the linearisation point, except for
+    // the 3D p = 2 blocks (135 columns), where it would leave LDS for two
+    // workgroups per CU instead of three: those read the state from memory
+    constexpr bool KEEPQ = !(DIM == 3 && P == 3);
     __shared__ Ops1D ops;
+    __shared__ double s_q0[KEEPQ ? NV * NP : 1];
     __shared__ double s_u[NV * NP * EB];   // perturbed states, then the flux of one direction
     __shared__ double s_qp[NFACE];         // own + traces, then the jumps q* - q+
     __shared__ double s_qm[NFACE];         // own - traces (q* on the - faces)
@@ -878,17 +892,12 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_ej_form(MeshK m, Ops1D 
     if (threadIdx.x == 0) ops = ops_in;
     const int nb = fk.nb;
     const int ncb = (nb + EB - 1) / EB;
+    const int nwe = (ncb + fk.groups - 1) / fk.groups;  // workgroups per element
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int k = b / ncb;
-    const int col0 = (b % ncb) * EB;
-    const int ncol = min(EB, nb - col0);
-    for (int t = threadIdx.x; t < NV * NP * EB; t += blockDim.x) {
-        const int e = t % EB, vi = t / EB;
-        const int v = vi / NP;
-        double u = fk.dq[(size_t)vi * m.Ne + k];
-        if (e < ncol && vi == col0 + e) u = u + fd_step(ph.qinf[v], u);
-        s_u[t] = u;
-    }
+    const int k = b / nwe;
+    const int g0 = (b % nwe) * fk.groups, g1 = min(ncb, g0 + fk.groups);
+    if constexpr (KEEPQ)
+        for (int t = threadIdx.x; t < NV * NP; t += blockDim.x) s_q0[t] = fk.dq[(size_t)t * m.Ne + k];
     for (int t = threadIdx.x; t < NSH; t += blockDim.x) {
         const int a = t / (NV * NF);
         const int mm = neighbour(m, k, a, -1);
@@ -907,95 +916,113 @@ __global__ void __launch_bounds__((Shape<DIM, P>::NT)) k_ej_form(MeshK m, Ops1D 
         s_ih[a] = m.inv2h[a][c[a]];
         s_ihm[a] = m.inv2h[a][c[a] > 0 ? c[a] - 1 : m.n[a] - 1];
     }
-    __syncthreads();
-    // own traces of every slot
-    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) {
-        const int e = t % EB;
-        int r = t / EB;
-        const int f = r % NF;
-        r /= NF;
-        const int v = r % NV, a = r / NV;
-        double sp = 0.0, sm = 0.0;
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const double x = s_u[(v * NP + S::line(a, f, j)) * EB + e];
-            sp += ops.bp[j] * x;
-            sm += ops.bm[j] * x;
+    for (int g = g0; g < g1; ++g) {
+        const int col0 = g * EB;
+        const int ncol = min(EB, nb - col0);
+        // the lane index, re-read each group: the index arithmetic of the
+        // loops below is then not hoisted out of this loop, where it would
+        // hold registers for the whole kernel (200 instead of 144 VGPRs)
+        int tid;
+        __asm__ volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+        __syncthreads();  // s_q0 staged; the previous group's reads of s_u are done
+        for (int t = tid; t < NV * NP * EB; t += blockDim.x) {
+            const int e = t % EB, vi = t / EB;
+            const int v = vi / NP;
+            double u = KEEPQ ? s_q0[vi] : fk.dq[(size_t)vi * m.Ne + k];
+            if (e < ncol && vi == col0 + e) u = u + fd_step(ph.qinf[v], u);
+            s_u[t] = u;
         }
-        s_qp[t] = sp;
-        s_qm[t] = sm;
-    }
-    __syncthreads();
-    // common fluxes on the 2 DIM faces of every slot
-    for (int t = threadIdx.x; t < 2 * DIM * NF * EB; t += blockDim.x) {
-        const int e = t % EB;
-        int r = t / EB;
-        const int f = r % NF;
-        r /= NF;
-        const int a = r % DIM, side = r / DIM;
-        double qL[NV], qR[NV], g[DIM][NV], F[NV];
-        auto minus_face = [&](auto Ac) {
-            constexpr int A = decltype(Ac)::value;
+        __syncthreads();
+        // own traces of every slot
+        for (int t = tid; t < NFACE; t += blockDim.x) {
+            const int e = t % EB;
+            int r = t / EB;
+            const int f = r % NF;
+            r /= NF;
+            const int v = r % NV, a = r / NV;
+            double sp = 0.0, sm = 0.0;
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const double x = s_u[(v * NP + S::line(a, f, j)) * EB + e];
+                sp += ops.bp[j] * x;
+                sm += ops.bm[j] * x;
+            }
+            s_qp[t] = sp;
+            s_qm[t] = sm;
+        }
+        __syncthreads();
+        // common fluxes on the 2 DIM faces of every slot
+        for (int t = tid; t < 2 * DIM * NF * EB; t += blockDim.x) {
+            const int e = t % EB;
+            int r = t / EB;
+            const int f = r % NF;
+            r /= NF;
+            const int a = r % DIM, side = r / DIM;
+            double qL[NV], qR[NV], g2[DIM][NV], F[NV];
+            auto minus_face = [&](auto Ac) {
+                constexpr int A = decltype(Ac)::value;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const int fb = (A * NV + v) * NF + f;
+                    qL[v] = s_mq[fb];
+                    qR[v] = s_qm[fb * EB + e];
+                    double d = s_ms[fb];
+                    d += (qR[v] - qL[v]) * ops.cgp;
+                    g2[A][v] = s_ihm[A] * d;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        if (c == A) continue;
+                        const int cc = c < A ? c : c - 1;
+                        g2[c][v] = s_mg[((A * (DIM - 1) + cc) * NV + v) * NF + f];
+                    }
+                }
+                common_flux<DIM, A>(ph, qL, qR, g2, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) s_fm[((A * NV + v) * NF + f) * EB + e] = F[v];
+            };
+            auto plus_face = [&](auto Ac) {
+                constexpr int A = decltype(Ac)::value;
+                double Sn[NV];
+                plus_face_state<DIM, P, A, EB, 0>(ops, s_u, s_tn, s_qp, s_ih, e, f, qL, qR, g2, Sn);
+                common_flux<DIM, A>(ph, qL, qR, g2, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) s_fp[((A * NV + v) * NF + f) * EB + e] = F[v];
+            };
+            using A0 = std::integral_constant<int, 0>;
+            using A1 = std::integral_constant<int, 1>;
+            using A2 = std::integral_constant<int, (DIM == 3 ? 2 : 1)>;
+            if (side == 0) {
+                if (a == 0) plus_face(A0{});
+                else if (a == 1) plus_face(A1{});
+                else if constexpr (DIM == 3) plus_face(A2{});
+            } else {
+                if (a == 0) minus_face(A0{});
+                else if (a == 1) minus_face(A1{});
+                else if constexpr (DIM == 3) minus_face(A2{});
+            }
+        }
+        __syncthreads();
+        // state jumps q* - q+ on the + faces
+        for (int t = tid; t < NFACE; t += blockDim.x) s_qp[t] = s_tn[t / EB] - s_qp[t];
+        __syncthreads();
+        const int t = tid;
+        const int e = t % EB, i = t / EB;
+        const bool active = (t < NP * EB);
+        double acc[NV];
+        divergence<DIM, P, EB, 0>(ops, ph, s_u, s_qp, s_fm, s_fp, s_ih, active, e, i, acc);
+        if (active && e < ncol) {
+            const int col = col0 + e;
+            const double base = KEEPQ ? s_q0[col] : fk.dq[(size_t)col * m.Ne + k];
+            const double hact = (base + fd_step(ph.qinf[col / NP], base)) - base;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const int fb = (A * NV + v) * NF + f;
-                qL[v] = s_mq[fb];
-                qR[v] = s_qm[fb * EB + e];
-                double d = s_ms[fb];
-                d += (qR[v] - qL[v]) * ops.cgp;
-                g[A][v] = s_ihm[A] * d;
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    if (c == A) continue;
-                    const int cc = c < A ? c : c - 1;
-                    g[c][v] = s_mg[((A * (DIM - 1) + cc) * NV + v) * NF + f];
-                }
+                const double R = -acc[v];
+                const int row = v * NP + i;
+                double val = -(R - fk.r0[(size_t)row * m.Ne + k]) / hact;
+                if (row == col) val += fk.sigma;
+                fk.blocks[(size_t)k * nb * nb + (size_t)col * nb + row] = val;
             }
-            common_flux<DIM, A>(ph, qL, qR, g, F);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) s_fm[((A * NV + v) * NF + f) * EB + e] = F[v];
-        };
-        auto plus_face = [&](auto Ac) {
-            constexpr int A = decltype(Ac)::value;
-            double Sn[NV];
-            plus_face_state<DIM, P, A, EB, 0>(ops, s_u, s_tn, s_qp, s_ih, e, f, qL, qR, g, Sn);
-            common_flux<DIM, A>(ph, qL, qR, g, F);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) s_fp[((A * NV + v) * NF + f) * EB + e] = F[v];
-        };
-        using A0 = std::integral_constant<int, 0>;
-        using A1 = std::integral_constant<int, 1>;
-        using A2 = std::integral_constant<int, (DIM == 3 ? 2 : 1)>;
-        if (side == 0) {
-            if (a == 0) plus_face(A0{});
-            else if (a == 1) plus_face(A1{});
-            else if constexpr (DIM == 3) plus_face(A2{});
-        } else {
-            if (a == 0) minus_face(A0{});
-            else if (a == 1) minus_face(A1{});
-            else if constexpr (DIM == 3) minus_face(A2{});
         }
-    }
-    __syncthreads();
-    // state jumps q* - q+ on the + faces
-    for (int t = threadIdx.x; t < NFACE; t += blockDim.x) s_qp[t] = s_tn[t / EB] - s_qp[t];
-    __syncthreads();
-    const int t = threadIdx.x;
-    const int e = t % EB, i = t / EB;
-    const bool active = (t < NP * EB);
-    double acc[NV];
-    divergence<DIM, P, EB, 0>(ops, ph, s_u, s_qp, s_fm, s_fp, s_ih, active, e, i, acc);
-    if (!active || e >= ncol) return;
-    const int col = col0 + e;
-    const double base = fk.dq[(size_t)col * m.Ne + k];
-    const double hact = (base + fd_step(ph.qinf[col / NP], base)) - base;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double R = -acc[v];
-        const int row = v * NP + i;
-        double val = -(R - fk.r0[(size_t)row * m.Ne + k]) / hact;
-        if (row == col) val += fk.sigma;
-        fk.blocks[(size_t)k * nb * nb + (size_t)col * nb + row] = val;
     }
 }
 
@@ -1047,9 +1074,10 @@ hipError_t form(const frpmg_ctx *ctx, const Level &L, const double *dq, double s
     hipError_t err = run<DIM, P, SRC_PLAIN, OUT_R>(ctx, L, a, &sv, s);
     if (err != hipSuccess) return err;
     const int ncb = (L.nb + S::EB - 1) / S::EB;
-    const size_t nblk = (size_t)m.Ne * ncb;
+    const int groups = kFormGroups;
+    const size_t nblk = (size_t)m.Ne * ((ncb + groups - 1) / groups);
     if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-    FormK fk{dq, sv, L.r0, out, sigma, L.nb};
+    FormK fk{dq, sv, L.r0, out, sigma, L.nb, groups};
     hipLaunchKernelGGL((k_ej_form<DIM, P>), dim3((unsigned)nblk), dim3(S::NT), 0, s, m, L.ops, ctx->phys, fk);
     return hipGetLastError();
 }
