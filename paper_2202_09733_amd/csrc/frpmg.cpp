@@ -888,8 +888,7 @@ KrylovResult fgmres(frpmg_ctx *ctx, size_t N, const double *b, double *x, int m,
                 A(zj, w, st);
                 if (timed) HIPCHK(hipEventRecord(ev[2], st));
                 HIPCHK(vec_mdot(ctx, N, jj + 1, V, ld, w, ctx->red_out + RO_H1, st));
-                HIPCHK(vec_gemv_sub(N, jj + 1, V, ld, ctx->red_out + RO_H1, w, st));
-                HIPCHK(vec_mdot(ctx, N, jj + 1, V, ld, w, ctx->red_out + RO_H2, st));
+                HIPCHK(vec_gemv_sub_mdot(ctx, N, jj + 1, V, ld, ctx->red_out + RO_H1, w, ctx->red_out + RO_H2, st));
                 HIPCHK(vec_gemv_sub(N, jj + 1, V, ld, ctx->red_out + RO_H2, w, st));
                 HIPCHK(vec_dot_normalize(ctx, N, w, ctx->red_out + RO_N2, V + (size_t)(jj + 1) * ld, st));
                 if (timed) HIPCHK(hipEventRecord(ev[3], st));

@@ -318,6 +318,10 @@ hipError_t vec_mdot(frpmg_ctx *ctx, size_t n, int nvec, const double *V, size_t 
                     double *dout, hipStream_t s);
 hipError_t vec_gemv_sub(size_t n, int nvec, const double *V, size_t ldv, const double *h, double *w,
                         hipStream_t s);
+// w -= V h, then dout = V^T w (the updated w), in one pass over V; the same
+// bits as vec_gemv_sub followed by vec_mdot
+hipError_t vec_gemv_sub_mdot(frpmg_ctx *ctx, size_t n, int nvec, const double *V, size_t ldv, const double *h,
+                             double *w, double *dout, hipStream_t s);
 // y = a x + b y (a, b host or device scalars); x may be null (then y = b y)
 hipError_t vec_axpby(size_t n, Scal a, const double *x, Scal b, double *y, hipStream_t s);
 // y = a x

@@ -560,8 +560,7 @@ hipError_t mb_sweep(frpmg_ctx *ctx, const Mbnk &mb, const double *G, const doubl
         // w = A z_j with z_j = (L U)^{-1} v_j: the red rows of A z_j are v_j's
         if ((e = launch_rows<MB_MATVEC_BLACK>(ctx, mb, 1, nullptr, zj, vj, mb.w, s)) != hipSuccess) return e;
         if ((e = vec_mdot(ctx, N, j + 1, mb.V, N, mb.w, gm + GM_H1, s)) != hipSuccess) return e;
-        if ((e = vec_gemv_sub(N, j + 1, mb.V, N, gm + GM_H1, mb.w, s)) != hipSuccess) return e;
-        if ((e = vec_mdot(ctx, N, j + 1, mb.V, N, mb.w, gm + GM_H2, s)) != hipSuccess) return e;
+        if ((e = vec_gemv_sub_mdot(ctx, N, j + 1, mb.V, N, gm + GM_H1, mb.w, gm + GM_H2, s)) != hipSuccess) return e;
         if ((e = vec_gemv_sub(N, j + 1, mb.V, N, gm + GM_H2, mb.w, s)) != hipSuccess) return e;
         if ((e = vec_dot_normalize(ctx, N, mb.w, gm + GM_N2, mb.V + (size_t)(j + 1) * N, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_mb_gm_step, dim3(1), dim3(64), 0, s, gm, j, maxit);

@@ -99,6 +99,66 @@ __global__ void __launch_bounds__(kThreads) k_gemv_sub(size_t n, int nvec, const
     }
 }
 
+// w -= sum_v h[v] V_v, then partial[vec * nblk + block] = this block's
+// share of V_vec . w with the updated w: the update of one classical
+// Gram-Schmidt pass and the products of the next in one pass over V (each
+// lane keeps its NV entries of V in registers between the two).  The update
+// takes the terms in k_gemv_sub's order and each product in
+// k_mdot_partial's (same grid, same lane order, same reduction), so the
+// results are bitwise those of the two kernels in turn.
+constexpr int kFuseMax = 32;  // vectors per fused pass
+
+template <int NV>
+__global__ void __launch_bounds__(kThreads) k_gemv_sub_mdot(size_t n, const double *__restrict__ V, size_t ldv,
+                                                            const double *__restrict__ h, double *__restrict__ w,
+                                                            double *__restrict__ partial) {
+    __shared__ double s_part[NV][kThreads / 64];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double hv[NV], acc[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        hv[c] = h[c];
+        acc[c] = 0.0;
+    }
+    for (size_t i = i0; i < n; i += stride) {
+        double vv[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) vv[c] = V[(size_t)c * ldv + i];
+        double wi = w[i];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) wi -= hv[c] * vv[c];
+        w[i] = wi;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) acc[c] += vv[c] * wi;
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double v = acc[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) s_part[c][wid] = v;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < NV; c += blockDim.x) {
+        double tot = 0.0;
+        for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) tot += s_part[c][w2];
+        partial[(size_t)c * gridDim.x + blockIdx.x] = tot;
+    }
+}
+
+template <int NV>
+void launch_gemv_sub_mdot(int nvec, unsigned nb, size_t n, const double *V, size_t ldv, const double *h, double *w,
+                          double *partial, hipStream_t s) {
+    if constexpr (NV <= kFuseMax) {
+        if (nvec == NV)
+            hipLaunchKernelGGL(k_gemv_sub_mdot<NV>, dim3(nb), dim3(kThreads), 0, s, n, V, ldv, h, w, partial);
+        else
+            launch_gemv_sub_mdot<NV + 1>(nvec, nb, n, V, ldv, h, w, partial, s);
+    }
+}
+
 // y = y0 + sum_v c[v] Z_v  (y0 = y on entry)
 __global__ void __launch_bounds__(kThreads) k_combine(size_t n, int nvec, const double *__restrict__ Z,
                                                       size_t ldz, const double *__restrict__ c,
@@ -418,6 +478,18 @@ hipError_t vec_mdot(frpmg_ctx *ctx, size_t n, int nvec, const double *V, size_t 
 hipError_t vec_gemv_sub(size_t n, int nvec, const double *V, size_t ldv, const double *h, double *w,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_gemv_sub, dim3(grid_for(n)), dim3(kThreads), 0, s, n, nvec, V, ldv, h, w);
+    return hipGetLastError();
+}
+
+hipError_t vec_gemv_sub_mdot(frpmg_ctx *ctx, size_t n, int nvec, const double *V, size_t ldv, const double *h,
+                             double *w, double *dout, hipStream_t s) {
+    if (nvec < 1 || nvec > kFuseMax) {
+        hipError_t e = vec_gemv_sub(n, nvec, V, ldv, h, w, s);
+        return e != hipSuccess ? e : vec_mdot(ctx, n, nvec, V, ldv, w, dout, s);
+    }
+    const unsigned nb = red_blocks(n);
+    launch_gemv_sub_mdot<1>(nvec, nb, n, V, ldv, h, w, ctx->red_partial, s);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nvec), dim3(kThreads), 0, s, (int)nb, ctx->red_partial, dout);
     return hipGetLastError();
 }
 
